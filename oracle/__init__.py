@@ -1,0 +1,169 @@
+"""CPU oracle for the Join-Project PI_{x,z}(R(x,y) JOIN_y S(z,y)).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product path never imports this
+package, and this package never imports the product.
+
+Contents
+* ``join_project`` / ``count`` / ``rows`` / ``out_j``: the C++ hash-join plus
+  hash-set deduplication in ``jp_oracle.cpp`` (the paper's classical solution,
+  Sec. 1.1, which reaches the plain definition of Eq. 1).
+* ``brute_force``: nested loops over R x S for tiny inputs (definition of
+  Eq. 1 written out directly), used to pin the C++ oracle.
+* ``split_by_z``: the intersection-free partition of a result by the dense z
+  set (Sec. 2.3): a pair belongs to the dense part iff its z is dense.
+* ``digest_pairs``: order-independent digest (wrapping sum of SplitMix64
+  finalised keys), used where a result is too large to list.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "jp_oracle.cpp")
+_LIB = os.path.join(_HERE, "libjp_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (host code only)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        base = [i32p, i32p, ctypes.c_int64, i32p, i32p, ctypes.c_int64]
+        lib.jpo_out_j.argtypes = base
+        lib.jpo_out_j.restype = ctypes.c_int64
+        lib.jpo_count.argtypes = base + [ctypes.c_int, u64p]
+        lib.jpo_count.restype = ctypes.c_int64
+        lib.jpo_list.argtypes = base + [ctypes.c_int, i32p, i32p, ctypes.c_int64]
+        lib.jpo_list.restype = ctypes.c_int64
+        lib.jpo_rows.argtypes = base + [i32p, ctypes.c_int64, ctypes.c_int, i64p, i32p, ctypes.c_int64]
+        lib.jpo_rows.restype = ctypes.c_int64
+        lib.jpo_digest_pairs.argtypes = [i32p, i32p, ctypes.c_int64]
+        lib.jpo_digest_pairs.restype = ctypes.c_uint64
+        _lib = lib
+    return _lib
+
+
+def _p32(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _cols(rx, ry, sz, sy):
+    cols = [np.ascontiguousarray(np.asarray(c, dtype=np.int32)) for c in (rx, ry, sz, sy)]
+    if cols[0].shape != cols[1].shape or cols[2].shape != cols[3].shape:
+        raise ValueError("column length mismatch")
+    return cols
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def out_j(rx, ry, sz, sy) -> int:
+    rx, ry, sz, sy = _cols(rx, ry, sz, sy)
+    return int(_load().jpo_out_j(_p32(rx), _p32(ry), rx.size, _p32(sz), _p32(sy), sz.size))
+
+
+def count(rx, ry, sz, sy, threads: Optional[int] = None) -> Tuple[int, int]:
+    """(number of distinct pairs, digest) of the whole result."""
+    rx, ry, sz, sy = _cols(rx, ry, sz, sy)
+    d = ctypes.c_uint64(0)
+    c = _load().jpo_count(_p32(rx), _p32(ry), rx.size, _p32(sz), _p32(sy), sz.size,
+                          threads or default_threads(), ctypes.byref(d))
+    return int(c), int(d.value)
+
+
+def join_project(rx, ry, sz, sy, threads: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Sorted (x, z) result as two int32 arrays."""
+    rx, ry, sz, sy = _cols(rx, ry, sz, sy)
+    lib = _load()
+    cap = max(1, out_j(rx, ry, sz, sy))
+    ox = np.empty(cap, dtype=np.int32)
+    oz = np.empty(cap, dtype=np.int32)
+    n = lib.jpo_list(_p32(rx), _p32(ry), rx.size, _p32(sz), _p32(sy), sz.size,
+                     threads or default_threads(), _p32(ox), _p32(oz), cap)
+    assert n <= cap
+    return ox[:n].copy(), oz[:n].copy()
+
+
+def rows(rx, ry, sz, sy, xs: Sequence[int], threads: Optional[int] = None) -> List[np.ndarray]:
+    """Sorted distinct z's of each requested x value (empty if x has no match)."""
+    rx, ry, sz, sy = _cols(rx, ry, sz, sy)
+    xs = np.ascontiguousarray(np.asarray(xs, dtype=np.int32))
+    lib = _load()
+    counts = np.zeros(max(1, xs.size), dtype=np.int64)
+    # first pass sizes the rows, second fills them
+    total = lib.jpo_rows(_p32(rx), _p32(ry), rx.size, _p32(sz), _p32(sy), sz.size, _p32(xs), xs.size,
+                         threads or default_threads(),
+                         counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _p32(np.zeros(1, np.int32)), 0)
+    out = np.empty(max(1, total), dtype=np.int32)
+    lib.jpo_rows(_p32(rx), _p32(ry), rx.size, _p32(sz), _p32(sy), sz.size, _p32(xs), xs.size,
+                 threads or default_threads(), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                 _p32(out), total)
+    res = []
+    pos = 0
+    for i in range(xs.size):
+        c = int(counts[i])
+        res.append(out[pos:pos + c].copy())
+        pos += c
+    return res
+
+
+def digest_pairs(xs: np.ndarray, zs: np.ndarray) -> int:
+    xs = np.ascontiguousarray(np.asarray(xs, dtype=np.int32))
+    zs = np.ascontiguousarray(np.asarray(zs, dtype=np.int32))
+    return int(_load().jpo_digest_pairs(_p32(xs), _p32(zs), xs.size))
+
+
+# ------------------------------------------------------------ pure Python
+
+
+def brute_force(rx: Iterable[int], ry: Iterable[int], sz: Iterable[int], sy: Iterable[int]):
+    """Eq. 1 written out: every (R tuple, S tuple) pair with equal y contributes
+    (x, z); the set removes duplicates.  Returns the sorted list of pairs."""
+    r = list(zip((int(v) for v in rx), (int(v) for v in ry)))
+    s = list(zip((int(v) for v in sz), (int(v) for v in sy)))
+    out = set()
+    for x, y in r:
+        for z, y2 in s:
+            if y == y2:
+                out.add((x, z))
+    return sorted(out)
+
+
+def split_by_z(xs: np.ndarray, zs: np.ndarray, dense_z_values: np.ndarray):
+    """Intersection-free partition of a result (Sec. 2.3): a pair is in the dense
+    part iff its z value is one of the dense z values.  Returns
+    ((dense_x, dense_z), (sparse_x, sparse_z)), each in input order."""
+    mask = np.isin(zs, np.asarray(dense_z_values, dtype=np.int32))
+    return (xs[mask], zs[mask]), (xs[~mask], zs[~mask])
+
+
+def degree_stats(rx, ry, sz, sy):
+    """Per-value degrees the paper's partition and cost functions use (Sec. 2.6):
+    m_x (R tuples per x), m_z (S tuples per z), d_R(y) and d_S(y) (tuples per
+    join key on each side), with repeats counted."""
+    def hist(v):
+        u, c = np.unique(np.asarray(v, dtype=np.int32), return_counts=True)
+        return dict(zip(u.tolist(), c.tolist()))
+    return {"m_x": hist(rx), "m_z": hist(sz), "d_R": hist(ry), "d_S": hist(sy)}

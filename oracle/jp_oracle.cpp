@@ -1,0 +1,228 @@
+// CPU oracle for the Join-Project  PI_{x,z}( R(x,y) JOIN_y S(z,y) ).
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+// benchmark's CPU-baseline leg may load this library.  It shares no code,
+// header or table with the GPU path.
+//
+// What it computes is the plain definition of the operation (Sec. 1, Eq. 1 of
+// the paper): the set of (x, z) such that some y has (x, y) in R and (z, y) in
+// S, with the projection removing duplicates.  It follows the paper's
+// "classical solution" (Sec. 1.1): a hash join with S as the build side,
+// followed by hash-set deduplication of the projected join rows.  The output
+// is ordered lexicographically by (x, z) as signed int32; input tuples may
+// repeat (set semantics).  The bag join size OUT_J counts every matching
+// (R tuple, S tuple) pair, repeats included.
+//
+// The order-independent digest of a pair set is the wrapping 64-bit sum of
+// mix64(key(x, z)), where key flips the sign bit of both values and places x
+// in the high word, and mix64 is the SplitMix64 output finaliser
+// (Steele, Lea, Flood, "Fast splittable pseudorandom number generators",
+// OOPSLA 2014, with the constants published by Vigna for splitmix64).
+//
+// Threads split R by ranges of x value; ranges are disjoint, so their result
+// sets are disjoint and concatenate in order.
+
+#include <algorithm>
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+namespace {
+
+typedef std::unordered_map<int32_t, std::vector<int32_t>> YIndex;
+
+inline uint64_t pair_key(int32_t x, int32_t z) {
+  return (uint64_t(uint32_t(x) ^ 0x80000000u) << 32) | uint64_t(uint32_t(z) ^ 0x80000000u);
+}
+inline int32_t key_x(uint64_t k) { return int32_t(uint32_t(k >> 32) ^ 0x80000000u); }
+inline int32_t key_z(uint64_t k) { return int32_t(uint32_t(k) ^ 0x80000000u); }
+
+inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Step 1 of the classical solution: hash S on the join key y.
+YIndex build_index(const int32_t* sz, const int32_t* sy, int64_t ns) {
+  YIndex h;
+  h.reserve(size_t(ns / 4 + 16));
+  for (int64_t i = 0; i < ns; ++i) h[sy[i]].push_back(sz[i]);
+  return h;
+}
+
+struct Slices {
+  int64_t lo = 0, width = 1;
+  int n = 1;
+  int of(int32_t x) const {
+    int64_t s = (int64_t(x) - lo) / width;
+    return int(s);
+  }
+};
+
+Slices make_slices(const int32_t* rx, int64_t nr, int want) {
+  Slices sl;
+  if (nr == 0) return sl;
+  int32_t mn = rx[0], mx = rx[0];
+  for (int64_t i = 1; i < nr; ++i) {
+    mn = std::min(mn, rx[i]);
+    mx = std::max(mx, rx[i]);
+  }
+  int64_t range = int64_t(mx) - int64_t(mn) + 1;
+  int n = std::max(1, want);
+  if (range < n) n = int(range);
+  sl.lo = mn;
+  sl.width = (range + n - 1) / n;
+  sl.n = int((range + sl.width - 1) / sl.width);
+  return sl;
+}
+
+// R tuple indices grouped by slice.
+std::vector<std::vector<int64_t>> bucket_rows(const int32_t* rx, int64_t nr, const Slices& sl) {
+  std::vector<std::vector<int64_t>> b(sl.n);
+  for (int64_t i = 0; i < nr; ++i) b[sl.of(rx[i])].push_back(i);
+  return b;
+}
+
+// Steps 2-3: probe the index with one slice of R and deduplicate the projected
+// rows in a hash set; returns the slice's keys sorted.
+std::vector<uint64_t> slice_result(const std::vector<int64_t>& rows, const int32_t* rx,
+                                   const int32_t* ry, const YIndex& h) {
+  std::unordered_set<uint64_t> out;
+  for (int64_t i : rows) {
+    auto it = h.find(ry[i]);
+    if (it == h.end()) continue;
+    for (int32_t z : it->second) out.insert(pair_key(rx[i], z));
+  }
+  std::vector<uint64_t> v(out.begin(), out.end());
+  std::sort(v.begin(), v.end());
+  return v;
+}
+
+template <class F>
+void parallel_for(int n, int nthreads, F&& f) {
+  if (nthreads <= 1 || n <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<int> next(0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < std::min(nthreads, n); ++t)
+    th.emplace_back([&]() {
+      for (int i; (i = next.fetch_add(1)) < n;) f(i);
+    });
+  for (auto& t : th) t.join();
+}
+
+}  // namespace
+
+extern "C" {
+
+// Bag join size OUT_J = number of (R tuple, S tuple) pairs with equal y.
+int64_t jpo_out_j(const int32_t* rx, const int32_t* ry, int64_t nr, const int32_t* sz,
+                  const int32_t* sy, int64_t ns) {
+  (void)rx;
+  YIndex h = build_index(sz, sy, ns);
+  int64_t total = 0;
+  for (int64_t i = 0; i < nr; ++i) {
+    auto it = h.find(ry[i]);
+    if (it != h.end()) total += int64_t(it->second.size());
+  }
+  return total;
+}
+
+// Distinct-pair count and digest of the whole result.
+int64_t jpo_count(const int32_t* rx, const int32_t* ry, int64_t nr, const int32_t* sz,
+                  const int32_t* sy, int64_t ns, int nthreads, uint64_t* digest) {
+  YIndex h = build_index(sz, sy, ns);
+  Slices sl = make_slices(rx, nr, std::max(1, nthreads) * 8);
+  auto buckets = bucket_rows(rx, nr, sl);
+  std::vector<int64_t> cnt(sl.n, 0);
+  std::vector<uint64_t> dig(sl.n, 0);
+  parallel_for(sl.n, nthreads, [&](int s) {
+    std::vector<uint64_t> v = slice_result(buckets[s], rx, ry, h);
+    cnt[s] = int64_t(v.size());
+    uint64_t d = 0;
+    for (uint64_t k : v) d += mix64(k);
+    dig[s] = d;
+  });
+  int64_t c = 0;
+  uint64_t d = 0;
+  for (int s = 0; s < sl.n; ++s) {
+    c += cnt[s];
+    d += dig[s];
+  }
+  if (digest) *digest = d;
+  return c;
+}
+
+// Full sorted result.  Writes min(count, cap) pairs; returns the count.
+int64_t jpo_list(const int32_t* rx, const int32_t* ry, int64_t nr, const int32_t* sz,
+                 const int32_t* sy, int64_t ns, int nthreads, int32_t* out_x, int32_t* out_z,
+                 int64_t cap) {
+  YIndex h = build_index(sz, sy, ns);
+  Slices sl = make_slices(rx, nr, std::max(1, nthreads) * 8);
+  auto buckets = bucket_rows(rx, nr, sl);
+  std::vector<std::vector<uint64_t>> res(sl.n);
+  parallel_for(sl.n, nthreads, [&](int s) { res[s] = slice_result(buckets[s], rx, ry, h); });
+  int64_t pos = 0;
+  for (int s = 0; s < sl.n; ++s) {
+    for (uint64_t k : res[s]) {
+      if (pos < cap) {
+        out_x[pos] = key_x(k);
+        out_z[pos] = key_z(k);
+      }
+      ++pos;
+    }
+  }
+  return pos;
+}
+
+// Result rows for selected x values: for each xs[i], the sorted distinct z's
+// reachable from it.  counts[i] receives the row size; the rows are written
+// back to back into out_z (up to cap values).  Returns the total row length.
+int64_t jpo_rows(const int32_t* rx, const int32_t* ry, int64_t nr, const int32_t* sz,
+                 const int32_t* sy, int64_t ns, const int32_t* xs, int64_t nxs, int nthreads,
+                 int64_t* counts, int32_t* out_z, int64_t cap) {
+  YIndex h = build_index(sz, sy, ns);
+  std::unordered_map<int32_t, int64_t> want;
+  for (int64_t i = 0; i < nxs; ++i) want.emplace(xs[i], i);
+  std::vector<std::vector<int32_t>> ys(nxs);
+  for (int64_t i = 0; i < nr; ++i) {
+    auto it = want.find(rx[i]);
+    if (it != want.end()) ys[it->second].push_back(ry[i]);
+  }
+  std::vector<std::vector<int32_t>> rows(nxs);
+  parallel_for(int(nxs), nthreads, [&](int i) {
+    std::unordered_set<int32_t> zs;
+    for (int32_t y : ys[i]) {
+      auto it = h.find(y);
+      if (it == h.end()) continue;
+      for (int32_t z : it->second) zs.insert(z);
+    }
+    rows[i].assign(zs.begin(), zs.end());
+    std::sort(rows[i].begin(), rows[i].end());
+  });
+  int64_t pos = 0;
+  for (int64_t i = 0; i < nxs; ++i) {
+    counts[i] = int64_t(rows[i].size());
+    for (int32_t z : rows[i]) {
+      if (pos < cap) out_z[pos] = z;
+      ++pos;
+    }
+  }
+  return pos;
+}
+
+// Digest of an explicit pair list (used to digest a listed result).
+uint64_t jpo_digest_pairs(const int32_t* xs, const int32_t* zs, int64_t n) {
+  uint64_t d = 0;
+  for (int64_t i = 0; i < n; ++i) d += mix64(pair_key(xs[i], zs[i]));
+  return d;
+}
+
+}  // extern "C"
