@@ -1,0 +1,160 @@
+/*
+ * jp.h -- C ABI of the MI355X (gfx950) Join-Project library.
+ *
+ * Operation (paper Sec. 1, Eq. 1): given R(x, y) and S(z, y), return the set
+ *   PI_{x,z}( R JOIN_y S ) = { (x, z) : some y has (x, y) in R and (z, y) in S }.
+ * The method (paper Sec. 2, Alg. 1): map x, y, z values to dense ids (Sec. 2.2,
+ * with the semi-join on y of optimisation 2), build CSR for R, split S by z into
+ * a sparse and a dense part (intersection-free partition, Sec. 2.3), compute
+ * the sparse part with SparseBMM (Sec. 2.4, Alg. 2) and the dense part with
+ * DenseEC (Sec. 2.5, Alg. 3), and return the disjoint union.
+ *
+ * Conventions for every call:
+ *  - Column arguments are int32 DEVICE pointers (HIP device memory); any int32
+ *    value is allowed, including negatives and INT32_MIN/INT32_MAX.  Input
+ *    tuples may repeat; the result is a set (repeats never change it).
+ *  - Work is enqueued on the caller's stream.  A call synchronises that stream
+ *    only where noted ("syncs").  No call synchronises the device.
+ *  - Every call returns a jp_status and never throws.  On failure
+ *    jp_last_error() returns a message (thread-local, valid until the next call
+ *    on the same thread).  Argument checks happen before any device work.
+ *  - Output pairs are ORIGINAL values, ordered by (x, z) as signed int32, so
+ *    consecutive chunks of a materialised result concatenate to the full list.
+ *  - Counts are int64.  Per plan, each input side holds at most 2^31 - 1 tuples.
+ *  - A plan or batch object is not thread-safe; distinct objects may be used
+ *    concurrently from different threads on different streams.
+ */
+#ifndef JP_H_
+#define JP_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  JP_OK = 0,
+  JP_EINVAL = 1,  /* bad argument (null pointer with n > 0, n < 0, n > 2^31-1, bad option) */
+  JP_ENOMEM = 2,  /* device allocation failed or workspace_limit_bytes exceeded */
+  JP_EHIP = 3,    /* a HIP runtime call failed; jp_last_error() has its text */
+  JP_ESTATE = 4,  /* call out of order (e.g. count before execute) */
+  JP_ERANGE = 5,  /* first > number of pairs in the requested part */
+  JP_EBUSY = 6    /* server queue full or budget exhausted */
+} jp_status;
+
+/* Which part of the result: the union, or one side of the partition by z. */
+typedef enum { JP_PART_ALL = 0, JP_PART_DENSE = 1, JP_PART_SPARSE = 2 } jp_part;
+
+/* How the dense/sparse threshold tau is chosen (Sec. 2.6, function f2). */
+typedef enum {
+  JP_TAU_AUTO = 0,  /* cost model: z is dense iff m_z > tau, tau from f2 with GPU constants */
+  JP_TAU_FIXED = 1  /* use jp_options.dense_threshold */
+} jp_tau_mode;
+
+/* Kernel for the hot (frequent join key) part of DenseEC (Sec. 2.5 / f3). */
+typedef enum {
+  JP_DENSE_AUTO = 0, /* per row block, by the density of hot join keys */
+  JP_DENSE_BITS = 1, /* bit-packed OR of hot key rows */
+  JP_DENSE_MFMA = 2  /* 0/1 product on the INT8 matrix cores, int32 sums thresholded at > 0 */
+} jp_dense_kernel;
+
+/* Options; an all-zero struct (or NULL) selects every default. */
+typedef struct {
+  int32_t tau_mode;              /* jp_tau_mode */
+  int32_t dense_kernel;          /* jp_dense_kernel */
+  int64_t dense_threshold;       /* JP_TAU_FIXED: z dense iff m_z > value (-1: all dense, INT64_MAX: none) */
+  int32_t k_hot_max;             /* cap on hot join keys per instance in DenseEC (0 = 256; max 1024) */
+  int32_t flags;                 /* reserved, must be 0 */
+  int64_t workspace_limit_bytes; /* 0 = no limit; exceeding it returns JP_ENOMEM */
+} jp_options;
+
+typedef struct {
+  int64_t n_x, n_y, n_z;   /* distinct x (after the semi-join), y (of S), z */
+  int64_t n_r_kept;        /* R tuples whose y occurs in S (semi-join, Sec. 2.2 opt. 2) */
+  int64_t out_j;           /* bag join size: sum over y of d_R(y) * d_S(y) */
+  int64_t tau;             /* threshold used: z dense iff m_z > tau */
+  int64_t n_z_dense;       /* number of dense z */
+  int64_t k_hot;           /* hot join keys held as bit rows in DenseEC */
+  int64_t footprint_bytes; /* device memory owned by the object for this instance's share */
+} jp_stats;
+
+typedef struct jp_plan jp_plan;
+typedef struct jp_batch jp_batch;
+
+/* ---------------------------------------------------------------- plan --- */
+
+/* Build the mapped, partitioned plan of one query (Alg. 1 up to the kernels:
+ * mapping, CSR of R, partition of S by z).  r_x/r_y hold n_r tuples of R and
+ * s_z/s_y hold n_s tuples of S, all device pointers that must stay valid until
+ * the work enqueued by this call has completed.  Syncs `stream` (to size the
+ * plan).  On success *out owns all device memory it uses. */
+jp_status jp_plan_create(const int32_t* r_x, const int32_t* r_y, int64_t n_r,
+                         const int32_t* s_z, const int32_t* s_y, int64_t n_s,
+                         const jp_options* opt, hipStream_t stream, jp_plan** out);
+
+/* Count pass of SparseBMM (Alg. 2) and DenseEC (Alg. 3) for every x row, and
+ * the per-row offsets of the result.  Asynchronous. */
+jp_status jp_execute(jp_plan* p, hipStream_t stream);
+
+/* Host copies of the number of pairs in the union, the dense and the sparse
+ * part (each output nullable).  JP_ESTATE before jp_execute.  Syncs. */
+jp_status jp_count(jp_plan* p, int64_t* total, int64_t* dense, int64_t* sparse,
+                   hipStream_t stream);
+
+/* Write pairs [first, first + max_pairs) of the sorted result of `part` into
+ * the device buffers out_x / out_z (caller-owned, >= max_pairs int32 each).
+ * *n_written (host) receives min(max_pairs, count - first).  first == count
+ * writes nothing and returns JP_OK; first > count returns JP_ERANGE.  Syncs. */
+jp_status jp_materialize(jp_plan* p, jp_part part, int64_t first, int64_t max_pairs,
+                         int32_t* out_x, int32_t* out_z, int64_t* n_written,
+                         hipStream_t stream);
+
+/* Host copies of the distinct x values (n_x entries, ascending) and of the
+ * per-row offsets of `part` in the sorted result (n_x + 1 entries); rows can
+ * then be materialised one at a time.  Either output may be NULL.  Syncs. */
+jp_status jp_row_info(jp_plan* p, jp_part part, int32_t* x_values, int64_t* row_offsets,
+                      hipStream_t stream);
+
+/* Host copy of the dense z values (n_z_dense entries, ascending).  Syncs. */
+jp_status jp_dense_z(jp_plan* p, int32_t* z_values, hipStream_t stream);
+
+jp_status jp_plan_stats(const jp_plan* p, jp_stats* s);
+void jp_plan_destroy(jp_plan* p); /* NULL-safe; frees all plan-owned device memory */
+
+const char* jp_last_error(void);
+
+/* --------------------------------------------------------------- batch --- */
+
+/* One query of a batch: device columns as for jp_plan_create. */
+typedef struct {
+  const int32_t* r_x;
+  const int32_t* r_y;
+  const int32_t* s_z;
+  const int32_t* s_y;
+  int64_t n_r;
+  int64_t n_s;
+} jp_instance;
+
+/* Many independent queries planned together: every stage runs as one launch
+ * over all instances (block-diagonal id spaces), with tau and the hot key set
+ * chosen per instance.  The array `inst` is read during the call (host
+ * memory); its device columns must stay valid until the enqueued work has
+ * completed.  The sum of tuples per side must stay below 2^31.  Syncs. */
+jp_status jp_batch_create(const jp_instance* inst, int32_t n_inst, const jp_options* opt,
+                          hipStream_t stream, jp_batch** out);
+jp_status jp_batch_execute(jp_batch* b, hipStream_t stream);
+/* Per-instance pair counts into host array totals[n_inst].  Syncs. */
+jp_status jp_batch_counts(jp_batch* b, int64_t* totals, hipStream_t stream);
+jp_status jp_batch_materialize(jp_batch* b, int32_t inst, jp_part part, int64_t first,
+                               int64_t max_pairs, int32_t* out_x, int32_t* out_z,
+                               int64_t* n_written, hipStream_t stream);
+jp_status jp_batch_stats(const jp_batch* b, int32_t inst, jp_stats* s);
+void jp_batch_destroy(jp_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JP_H_ */

@@ -1,0 +1,119 @@
+"""Small object wrappers over the C ABI (marshalling only)."""
+from __future__ import annotations
+
+from typing import Optional, Sequence, Tuple
+
+from . import binding as B
+
+
+class Plan:
+    """One planned query; frees its device memory on close()."""
+
+    def __init__(self, r_x, r_y, s_z, s_y, opt: Optional[B.jp_options] = None, stream=None):
+        self.stream = stream
+        self.h = B.jp_plan_create(r_x, r_y, s_z, s_y, opt, stream)
+
+    def execute(self):
+        B.jp_execute(self.h, self.stream)
+        return self
+
+    def count(self) -> Tuple[int, int, int]:
+        return B.jp_count(self.h, self.stream)
+
+    def stats(self):
+        return B.jp_plan_stats(self.h)
+
+    def materialize(self, part: int = B.JP_PART_ALL, first: int = 0, max_pairs: Optional[int] = None,
+                    out=None):
+        """Pairs [first, first + max_pairs) of the sorted result as two int32 device tensors."""
+        import torch
+
+        total = self.count()[part]
+        if max_pairs is None:
+            max_pairs = max(0, total - first)
+        if out is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+            out = (torch.empty(max(max_pairs, 1), dtype=torch.int32, device=dev),
+                   torch.empty(max(max_pairs, 1), dtype=torch.int32, device=dev))
+        n = B.jp_materialize(self.h, part, first, max_pairs, out[0], out[1], self.stream)
+        return out[0][:n], out[1][:n]
+
+    def row_info(self, part: int = B.JP_PART_ALL):
+        return B.jp_row_info(self.h, part, self.stream)
+
+    def dense_z(self):
+        return B.jp_dense_z(self.h, self.stream)
+
+    def close(self):
+        if self.h:
+            B.jp_plan_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent queries planned and executed together."""
+
+    def __init__(self, cols: Sequence[Tuple], opt: Optional[B.jp_options] = None, stream=None):
+        self.stream = stream
+        self.n = len(cols)
+        self.h = B.jp_batch_create(cols, opt, stream)
+
+    def execute(self):
+        B.jp_batch_execute(self.h, self.stream)
+        return self
+
+    def counts(self):
+        return B.jp_batch_counts(self.h, self.n, self.stream)
+
+    def stats(self, i: int):
+        return B.jp_batch_stats(self.h, i)
+
+    def materialize(self, i: int, part: int = B.JP_PART_ALL, first: int = 0, max_pairs: Optional[int] = None):
+        import torch
+
+        total = int(self.counts()[i]) if part == B.JP_PART_ALL else None
+        if max_pairs is None:
+            if total is None:
+                raise ValueError("max_pairs is required for a single part of a batch instance")
+            max_pairs = max(0, total - first)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        ox = torch.empty(max(max_pairs, 1), dtype=torch.int32, device=dev)
+        oz = torch.empty(max(max_pairs, 1), dtype=torch.int32, device=dev)
+        n = B.jp_batch_materialize(self.h, i, part, first, max_pairs, ox, oz, self.stream)
+        return ox[:n], oz[:n]
+
+    def close(self):
+        if self.h:
+            B.jp_batch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def join_project(r_x, r_y, s_z, s_y, opt: Optional[B.jp_options] = None, stream=None):
+    """Plan, execute and materialise the whole sorted result (small inputs)."""
+    with Plan(r_x, r_y, s_z, s_y, opt, stream) as p:
+        p.execute()
+        return p.materialize()

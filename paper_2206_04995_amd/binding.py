@@ -1,0 +1,253 @@
+"""ctypes binding of the Join-Project C ABI (include/jp.h).
+
+Argument marshalling only: every step of the Join-Project runs in the HIP
+kernels of libjp.so.  Device columns are int32 torch tensors on a ROCm device;
+streams are torch streams (the current one by default).  If the library is
+missing, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjp.so")
+
+JP_OK, JP_EINVAL, JP_ENOMEM, JP_EHIP, JP_ESTATE, JP_ERANGE, JP_EBUSY = range(7)
+JP_PART_ALL, JP_PART_DENSE, JP_PART_SPARSE = 0, 1, 2
+JP_TAU_AUTO, JP_TAU_FIXED = 0, 1
+JP_DENSE_AUTO, JP_DENSE_BITS, JP_DENSE_MFMA = 0, 1, 2
+INT64_MAX = 2 ** 63 - 1
+
+_STATUS = {0: "JP_OK", 1: "JP_EINVAL", 2: "JP_ENOMEM", 3: "JP_EHIP", 4: "JP_ESTATE", 5: "JP_ERANGE", 6: "JP_EBUSY"}
+
+# every symbol include/jp.h declares
+EXPORTS = [
+    "jp_plan_create", "jp_execute", "jp_count", "jp_materialize", "jp_row_info", "jp_dense_z",
+    "jp_plan_stats", "jp_plan_destroy", "jp_last_error",
+    "jp_batch_create", "jp_batch_execute", "jp_batch_counts", "jp_batch_materialize", "jp_batch_stats",
+    "jp_batch_destroy",
+]
+
+
+class JpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class jp_options(ctypes.Structure):
+    _fields_ = [
+        ("tau_mode", ctypes.c_int32),
+        ("dense_kernel", ctypes.c_int32),
+        ("dense_threshold", ctypes.c_int64),
+        ("k_hot_max", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("workspace_limit_bytes", ctypes.c_int64),
+    ]
+
+
+class jp_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("n_x", "n_y", "n_z", "n_r_kept", "out_j", "tau", "n_z_dense", "k_hot", "footprint_bytes")]
+
+
+class jp_instance(ctypes.Structure):
+    _fields_ = [
+        ("r_x", ctypes.c_void_p), ("r_y", ctypes.c_void_p), ("s_z", ctypes.c_void_p), ("s_y", ctypes.c_void_p),
+        ("n_r", ctypes.c_int64), ("n_s", ctypes.c_int64),
+    ]
+
+
+def _load() -> ctypes.CDLL:
+    # libjp.so must bind to the HIP runtime torch uses (both carry the soname
+    # libamdhip64.so.7); a second runtime mapped into the process sees no device.
+    import torch  # noqa: F401
+
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2206_04995_amd/build.py (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    st = ctypes.c_int
+    sig = {
+        "jp_plan_create": (st, [vp, vp, i64, vp, vp, i64, ctypes.POINTER(jp_options), vp, ctypes.POINTER(vp)]),
+        "jp_execute": (st, [vp, vp]),
+        "jp_count": (st, [vp, i64p, i64p, i64p, vp]),
+        "jp_materialize": (st, [vp, ctypes.c_int, i64, i64, vp, vp, i64p, vp]),
+        "jp_row_info": (st, [vp, ctypes.c_int, i32p, i64p, vp]),
+        "jp_dense_z": (st, [vp, i32p, vp]),
+        "jp_plan_stats": (st, [vp, ctypes.POINTER(jp_stats)]),
+        "jp_plan_destroy": (None, [vp]),
+        "jp_last_error": (ctypes.c_char_p, []),
+        "jp_batch_create": (st, [ctypes.POINTER(jp_instance), i32, ctypes.POINTER(jp_options), vp, ctypes.POINTER(vp)]),
+        "jp_batch_execute": (st, [vp, vp]),
+        "jp_batch_counts": (st, [vp, i64p, vp]),
+        "jp_batch_materialize": (st, [vp, i32, ctypes.c_int, i64, i64, vp, vp, i64p, vp]),
+        "jp_batch_stats": (st, [vp, i32, ctypes.POINTER(jp_stats)]),
+        "jp_batch_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    m = lib.jp_last_error()
+    return m.decode() if m else ""
+
+
+def _check(status: int):
+    if status != JP_OK:
+        raise JpError(status, last_error())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t) -> int:
+    """Device pointer of an int32 tensor (None -> 0)."""
+    if t is None:
+        return 0
+    import torch
+
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("columns must be contiguous int32 tensors on a ROCm device")
+    return t.data_ptr()
+
+
+def make_options(tau_mode: int = JP_TAU_AUTO, dense_threshold: int = 0, dense_kernel: int = JP_DENSE_AUTO,
+                 k_hot_max: int = 0, workspace_limit_bytes: int = 0) -> jp_options:
+    o = jp_options()
+    o.tau_mode = tau_mode
+    o.dense_kernel = dense_kernel
+    o.dense_threshold = dense_threshold
+    o.k_hot_max = k_hot_max
+    o.flags = 0
+    o.workspace_limit_bytes = workspace_limit_bytes
+    return o
+
+
+def _stats_dict(s: jp_stats) -> Dict[str, int]:
+    return {name: int(getattr(s, name)) for name, _ in jp_stats._fields_}
+
+
+# ------------------------------------------------------------------ plan
+
+
+def jp_plan_create(r_x, r_y, s_z, s_y, opt: Optional[jp_options] = None, stream=None) -> int:
+    h = ctypes.c_void_p()
+    n_r = int(r_x.numel()) if r_x is not None else 0
+    n_s = int(s_z.numel()) if s_z is not None else 0
+    _check(lib.jp_plan_create(_ptr(r_x), _ptr(r_y), n_r, _ptr(s_z), _ptr(s_y), n_s,
+                              ctypes.byref(opt) if opt is not None else None, _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def jp_execute(plan: int, stream=None):
+    _check(lib.jp_execute(plan, _stream(stream)))
+
+
+def jp_count(plan: int, stream=None) -> Tuple[int, int, int]:
+    t, d, s = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.jp_count(plan, ctypes.byref(t), ctypes.byref(d), ctypes.byref(s), _stream(stream)))
+    return t.value, d.value, s.value
+
+
+def jp_materialize(plan: int, part: int, first: int, max_pairs: int, out_x, out_z, stream=None) -> int:
+    n = ctypes.c_int64()
+    _check(lib.jp_materialize(plan, part, first, max_pairs, _ptr(out_x), _ptr(out_z), ctypes.byref(n),
+                              _stream(stream)))
+    return n.value
+
+
+def jp_row_info(plan: int, part: int = JP_PART_ALL, stream=None) -> Tuple[np.ndarray, np.ndarray]:
+    st = jp_plan_stats(plan)
+    nx = st["n_x"]
+    xv = np.zeros(max(nx, 1), dtype=np.int32)
+    off = np.zeros(nx + 1, dtype=np.int64)
+    _check(lib.jp_row_info(plan, part, xv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                           off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _stream(stream)))
+    return xv[:nx], off
+
+
+def jp_dense_z(plan: int, stream=None) -> np.ndarray:
+    nd = jp_plan_stats(plan)["n_z_dense"]
+    z = np.zeros(max(nd, 1), dtype=np.int32)
+    _check(lib.jp_dense_z(plan, z.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream(stream)))
+    return z[:nd]
+
+
+def jp_plan_stats(plan: int) -> Dict[str, int]:
+    s = jp_stats()
+    _check(lib.jp_plan_stats(plan, ctypes.byref(s)))
+    return _stats_dict(s)
+
+
+def jp_plan_destroy(plan: int):
+    lib.jp_plan_destroy(plan)
+
+
+# ----------------------------------------------------------------- batch
+
+
+def _instances(cols: Sequence[Tuple]) -> "ctypes.Array":
+    arr = (jp_instance * len(cols))()
+    for i, (rx, ry, sz, sy) in enumerate(cols):
+        arr[i].r_x, arr[i].r_y = _ptr(rx), _ptr(ry)
+        arr[i].s_z, arr[i].s_y = _ptr(sz), _ptr(sy)
+        arr[i].n_r = int(rx.numel())
+        arr[i].n_s = int(sz.numel())
+    return arr
+
+
+def jp_batch_create(cols: Sequence[Tuple], opt: Optional[jp_options] = None, stream=None) -> int:
+    arr = _instances(cols)
+    h = ctypes.c_void_p()
+    _check(lib.jp_batch_create(arr, len(cols), ctypes.byref(opt) if opt is not None else None, _stream(stream),
+                               ctypes.byref(h)))
+    return h.value
+
+
+def jp_batch_execute(batch: int, stream=None):
+    _check(lib.jp_batch_execute(batch, _stream(stream)))
+
+
+def jp_batch_counts(batch: int, n_inst: int, stream=None) -> np.ndarray:
+    out = np.zeros(n_inst, dtype=np.int64)
+    _check(lib.jp_batch_counts(batch, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _stream(stream)))
+    return out
+
+
+def jp_batch_materialize(batch: int, inst: int, part: int, first: int, max_pairs: int, out_x, out_z,
+                         stream=None) -> int:
+    n = ctypes.c_int64()
+    _check(lib.jp_batch_materialize(batch, inst, part, first, max_pairs, _ptr(out_x), _ptr(out_z),
+                                    ctypes.byref(n), _stream(stream)))
+    return n.value
+
+
+def jp_batch_stats(batch: int, inst: int) -> Dict[str, int]:
+    s = jp_stats()
+    _check(lib.jp_batch_stats(batch, inst, ctypes.byref(s)))
+    return _stats_dict(s)
+
+
+def jp_batch_destroy(batch: int):
+    lib.jp_batch_destroy(batch)

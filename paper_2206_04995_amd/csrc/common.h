@@ -1,0 +1,83 @@
+// Internal helpers shared by the HIP sources of the Join-Project library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define JP_WAVE 64
+
+namespace jp {
+
+// ---------------------------------------------------------------- device
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+// inclusive prefix sum across the 64 lanes of a wave
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T u = __shfl_up(v, o, 64);
+    if (l >= o) v += u;
+  }
+  return v;
+}
+
+// index of the instance owning element g: base[] has n_inst + 1 ascending entries
+template <class T>
+__device__ __forceinline__ int find_inst(const T* __restrict__ base, int n_inst, T g) {
+  int lo = 0, hi = n_inst;  // answer in [0, n_inst)
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (base[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// first index in [lo, hi) with a[i] >= v (a ascending)
+template <class T>
+__device__ __forceinline__ int64_t lower_bound_dev(const T* __restrict__ a, int64_t lo, int64_t hi, T v) {
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  // SplitMix64 output finaliser (Steele, Lea, Flood 2014; constants of splitmix64)
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
+
+}  // namespace jp

@@ -1,0 +1,190 @@
+// Mapping of x, y, z values to dense order-preserving ids (paper Sec. 2.2)
+// and the CSR builds of R and S (Sec. 2.4).  Ids come from sorted runs of
+// equal keys, so id order equals value order; the join key y is mapped from
+// S first and R tuples whose y is absent from S are dropped (optimisation 2).
+#include "common.h"
+#include "prim.h"
+#include "stages.h"
+
+namespace jp {
+namespace {
+
+constexpr int NT = 256;
+
+inline int grid(int64_t n, int cap = 1 << 20) {
+  int64_t g = (n + NT - 1) / NT;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return int(g);
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < (n); i += int64_t(gridDim.x) * blockDim.x)
+
+__global__ void k_make_keys(const int32_t* __restrict__ v, int64_t n, const int32_t* __restrict__ ebase,
+                            int n_inst, const int64_t* __restrict__ koff, const int32_t* __restrict__ mn,
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ payload) {
+  GRID_STRIDE(i, n) {
+    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(ebase, n_inst, int32_t(i));
+    keys[i] = uint32_t(koff[inst] + (int64_t(v[i]) - int64_t(mn[inst])));
+    if (payload) payload[i] = uint32_t(i);
+  }
+}
+
+__global__ void k_make_keys_perm(const int32_t* __restrict__ v, const uint32_t* __restrict__ perm, int64_t n,
+                                 const int32_t* __restrict__ ebase, int n_inst, const int64_t* __restrict__ koff,
+                                 const int32_t* __restrict__ mn, const int32_t* __restrict__ E,
+                                 uint32_t* __restrict__ keys, uint32_t* __restrict__ payload) {
+  GRID_STRIDE(p, n) {
+    uint32_t g = perm[p];
+    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(ebase, n_inst, int32_t(g));
+    keys[p] = uint32_t(koff[inst] + (int64_t(v[g]) - int64_t(mn[inst])));
+    payload[p] = uint32_t(E[p + 1] - 1);
+  }
+}
+
+__global__ void k_head_flags(const uint32_t* __restrict__ keys, int64_t n, int32_t* __restrict__ flags) {
+  GRID_STRIDE(p, n) { flags[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1 : 0; }
+}
+
+__global__ void k_assign_ids(const uint32_t* __restrict__ keys, int64_t n, const int32_t* __restrict__ E,
+                             const int64_t* __restrict__ koff, const int32_t* __restrict__ mn, int n_inst,
+                             int32_t* __restrict__ first, int32_t* __restrict__ vals) {
+  GRID_STRIDE(p, n) {
+    int id = E[p];
+    bool head = E[p + 1] != id;
+    if (head) {
+      uint32_t k = keys[p];
+      int inst = n_inst == 1 ? 0 : find_inst<int64_t>(koff, n_inst, int64_t(k));
+      first[id] = int32_t(p);
+      vals[id] = int32_t(int64_t(k) - koff[inst] + int64_t(mn[inst]));
+    }
+    if (p == n - 1) first[E[n]] = int32_t(n);
+  }
+}
+
+__global__ void k_gather_bases(const int32_t* __restrict__ E, const int32_t* __restrict__ ebase, int n_inst,
+                               int32_t* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n_inst) out[i] = E[ebase[i]];
+}
+
+__global__ void k_semijoin(const int32_t* __restrict__ ry, int64_t n, const int32_t* __restrict__ ebase, int n_inst,
+                           const int32_t* __restrict__ vals_y, const int32_t* __restrict__ y_base,
+                           int32_t* __restrict__ keep, int32_t* __restrict__ yid) {
+  GRID_STRIDE(g, n) {
+    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(ebase, n_inst, int32_t(g));
+    int32_t v = ry[g];
+    int64_t lo = y_base[inst], hi = y_base[inst + 1];
+    int64_t pos = lower_bound_dev<int32_t>(vals_y, lo, hi, v);
+    bool ok = pos < hi && vals_y[pos] == v;
+    keep[g] = ok ? 1 : 0;
+    yid[g] = ok ? int32_t(pos) : -1;
+  }
+}
+
+__global__ void k_compact_r(const int32_t* __restrict__ rx, const int32_t* __restrict__ yid,
+                            const int32_t* __restrict__ keep, const int32_t* __restrict__ E, int64_t n,
+                            int32_t* __restrict__ ox, int32_t* __restrict__ oy) {
+  GRID_STRIDE(g, n) {
+    if (keep[g]) {
+      int32_t p = E[g];
+      ox[p] = rx[g];
+      oy[p] = yid[g];
+    }
+  }
+}
+
+__global__ void k_run_lengths(const int32_t* __restrict__ first, int64_t n_id, int32_t* __restrict__ m) {
+  GRID_STRIDE(i, n_id) { m[i] = first[i + 1] - first[i]; }
+}
+
+__global__ void k_histogram(const uint32_t* __restrict__ v, int64_t n, int32_t* __restrict__ h) {
+  GRID_STRIDE(i, n) { atomicAdd(&h[v[i]], 1); }
+}
+
+__global__ void k_out_j(const int32_t* __restrict__ dR, const int32_t* __restrict__ dS, int64_t n_y,
+                        const int32_t* __restrict__ y_base, int n_inst, int64_t* __restrict__ out_j) {
+  GRID_STRIDE(y, n_y) {
+    int64_t prod = int64_t(dR[y]) * int64_t(dS[y]);
+    if (prod) {
+      int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+      atomicAdd((unsigned long long*)&out_j[inst], (unsigned long long)prod);
+    }
+  }
+}
+
+}  // namespace
+
+void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff, const int32_t* mn,
+               uint32_t* keys, uint32_t* payload, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_make_keys, dim3(grid(n)), dim3(NT), 0, s, v, n, ebase, n_inst, koff, mn, keys, payload);
+  JP_LAUNCH_CHECK();
+}
+
+void make_keys_perm(const int32_t* v, const uint32_t* perm, int64_t n, const int32_t* ebase, int n_inst,
+                    const int64_t* koff, const int32_t* mn, const int32_t* E, uint32_t* keys, uint32_t* payload,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_make_keys_perm, dim3(grid(n)), dim3(NT), 0, s, v, perm, n, ebase, n_inst, koff, mn, E, keys,
+                     payload);
+  JP_LAUNCH_CHECK();
+}
+
+void head_flags(const uint32_t* keys, int64_t n, int32_t* flags, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_head_flags, dim3(grid(n)), dim3(NT), 0, s, keys, n, flags);
+  JP_LAUNCH_CHECK();
+}
+
+void assign_ids(const uint32_t* keys, int64_t n, const int32_t* E, const int64_t* koff, const int32_t* mn, int n_inst,
+                int32_t* first, int32_t* vals, hipStream_t s) {
+  if (n <= 0) {
+    fill_i32(first, 1, 0, s);
+    return;
+  }
+  hipLaunchKernelGGL(k_assign_ids, dim3(grid(n)), dim3(NT), 0, s, keys, n, E, koff, mn, n_inst, first, vals);
+  JP_LAUNCH_CHECK();
+}
+
+void gather_bases(const int32_t* E, const int32_t* ebase, int n_inst, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_bases, dim3((n_inst + 1 + NT - 1) / NT), dim3(NT), 0, s, E, ebase, n_inst, out);
+  JP_LAUNCH_CHECK();
+}
+
+void semijoin(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, const int32_t* vals_y,
+              const int32_t* y_base, int32_t* keep, int32_t* yid, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_semijoin, dim3(grid(n)), dim3(NT), 0, s, ry, n, ebase, n_inst, vals_y, y_base, keep, yid);
+  JP_LAUNCH_CHECK();
+}
+
+void compact_r(const int32_t* rx, const int32_t* yid, const int32_t* keep, const int32_t* E, int64_t n, int32_t* ox,
+               int32_t* oy, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_compact_r, dim3(grid(n)), dim3(NT), 0, s, rx, yid, keep, E, n, ox, oy);
+  JP_LAUNCH_CHECK();
+}
+
+void run_lengths(const int32_t* first, int64_t n_id, int32_t* m, hipStream_t s) {
+  if (n_id <= 0) return;
+  hipLaunchKernelGGL(k_run_lengths, dim3(grid(n_id)), dim3(NT), 0, s, first, n_id, m);
+  JP_LAUNCH_CHECK();
+}
+
+void histogram(const uint32_t* v, int64_t n, int32_t* h, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_histogram, dim3(grid(n)), dim3(NT), 0, s, v, n, h);
+  JP_LAUNCH_CHECK();
+}
+
+void out_j_per_inst(const int32_t* dR, const int32_t* dS, int64_t n_y, const int32_t* y_base, int n_inst,
+                    int64_t* out_j, hipStream_t s) {
+  fill_i64(out_j, n_inst, 0, s);
+  if (n_y <= 0) return;
+  hipLaunchKernelGGL(k_out_j, dim3(grid(n_y)), dim3(NT), 0, s, dR, dS, n_y, y_base, n_inst, out_j);
+  JP_LAUNCH_CHECK();
+}
+
+}  // namespace jp

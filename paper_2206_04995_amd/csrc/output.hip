@@ -1,0 +1,140 @@
+// Union of the two parts and output (paper Alg. 1, last step): the dense and
+// sparse results are disjoint by construction of the partition, so per-row
+// counts add and the sorted row lists merge without deduplication.
+#include "common.h"
+#include "prim.h"
+#include "stages.h"
+
+namespace jp {
+namespace {
+
+constexpr int NT = 256;
+
+__global__ void k_add_counts(const int32_t* __restrict__ a, const int32_t* __restrict__ b, int64_t n,
+                             int32_t* __restrict__ out) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = a[i] + b[i];
+}
+
+__global__ void k_inst_totals(const int64_t* __restrict__ oa, const int64_t* __restrict__ od,
+                              const int64_t* __restrict__ os, const int32_t* __restrict__ x_base, int n_inst,
+                              int64_t* __restrict__ tot) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_inst) {
+    int lo = x_base[i], hi = x_base[i + 1];
+    tot[3 * i + 0] = oa[hi] - oa[lo];
+    tot[3 * i + 1] = od[hi] - od[lo];
+    tot[3 * i + 2] = os[hi] - os[lo];
+  }
+}
+
+// out2[0] = row holding pair g0, out2[1] = first row starting at or after g1
+__global__ void k_find_rows(const int64_t* __restrict__ off, int64_t xb, int64_t xe, int64_t g0, int64_t g1,
+                            int64_t* __restrict__ out2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // largest x in [xb, xe) with off[x] <= g0
+  int64_t lo = xb, hi = xe;
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= g0) lo = mid;
+    else hi = mid;
+  }
+  out2[0] = lo;
+  // smallest x in [xb, xe] with off[x] >= g1
+  int64_t a = xb, b = xe;
+  while (a < b) {
+    int64_t mid = (a + b) >> 1;
+    if (off[mid] < g1) a = mid + 1;
+    else b = mid;
+  }
+  out2[1] = a;
+}
+
+__device__ __forceinline__ int64_t row_of(const int64_t* __restrict__ off, int64_t lo, int64_t hi, int64_t e) {
+  // largest x in [lo, hi) with off[x] - off[lo] <= e
+  int64_t base = off[lo];
+  while (hi - lo > 1) {
+    int64_t mid = (lo + hi) >> 1;
+    if (off[mid] - base <= e) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Each element of either list finds its row, then its rank in the other
+// list of the same row (the two lists hold disjoint z sets).
+__global__ void k_merge_write(int64_t x_lo, int64_t x_hi, const int64_t* __restrict__ off_a,
+                              const int64_t* __restrict__ off_b, const int64_t* __restrict__ off_out,
+                              const int32_t* __restrict__ la, const int32_t* __restrict__ lb, int64_t na, int64_t nb,
+                              const int32_t* __restrict__ vals_x, const int32_t* __restrict__ vals_z, int64_t g0,
+                              int64_t g1, int32_t* __restrict__ out_x, int32_t* __restrict__ out_z) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < na + nb; e += int64_t(gridDim.x) * blockDim.x) {
+    const bool in_a = e < na;
+    const int64_t i = in_a ? e : e - na;
+    const int64_t* off_s = in_a ? off_a : off_b;
+    const int64_t* off_o = in_a ? off_b : off_a;
+    const int32_t* ls = in_a ? la : lb;
+    const int32_t* lo_ = in_a ? lb : la;
+    const int64_t x = row_of(off_s, x_lo, x_hi, i);
+    const int64_t rs = off_s[x] - off_s[x_lo];
+    const int32_t z = ls[i];
+    int64_t rank = i - rs;
+    if (lo_) {
+      const int64_t o0 = off_o[x] - off_o[x_lo], o1 = off_o[x + 1] - off_o[x_lo];
+      rank += lower_bound_dev<int32_t>(lo_, o0, o1, z) - o0;
+    }
+    const int64_t g = off_out[x] + rank;
+    if (g >= g0 && g < g1) {
+      out_x[g - g0] = vals_x[x];
+      out_z[g - g0] = vals_z[z];
+    }
+  }
+}
+
+__global__ void k_gather_values(const int32_t* __restrict__ vals, const int32_t* __restrict__ idx, int64_t n,
+                                int32_t* __restrict__ out) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = vals[idx[i]];
+}
+
+}  // namespace
+
+void gather_values(const int32_t* vals, const int32_t* idx, int64_t n, int32_t* out, hipStream_t s) {
+  if (n <= 0) return;
+  int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
+  hipLaunchKernelGGL(k_gather_values, dim3(g), dim3(NT), 0, s, vals, idx, n, out);
+  JP_LAUNCH_CHECK();
+}
+
+void add_counts(const int32_t* a, const int32_t* b, int64_t n, int32_t* out, hipStream_t s) {
+  if (n <= 0) return;
+  int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
+  hipLaunchKernelGGL(k_add_counts, dim3(g), dim3(NT), 0, s, a, b, n, out);
+  JP_LAUNCH_CHECK();
+}
+
+void inst_totals(const int64_t* off_all, const int64_t* off_de, const int64_t* off_sp, const int32_t* x_base, int n_inst,
+                 int64_t* tot, hipStream_t s) {
+  hipLaunchKernelGGL(k_inst_totals, dim3((n_inst + NT - 1) / NT), dim3(NT), 0, s, off_all, off_de, off_sp, x_base,
+                     n_inst, tot);
+  JP_LAUNCH_CHECK();
+}
+
+void find_rows(const int64_t* off, int64_t x_begin, int64_t x_end, int64_t g0, int64_t g1, int64_t* out2,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_find_rows, dim3(1), dim3(64), 0, s, off, x_begin, x_end, g0, g1, out2);
+  JP_LAUNCH_CHECK();
+}
+
+void merge_write_n(int64_t x_lo, int64_t x_hi, const int64_t* off_a, const int64_t* off_b, const int64_t* off_out,
+                   const int32_t* la, const int32_t* lb, int64_t na, int64_t nb, const int32_t* vals_x,
+                   const int32_t* vals_z, int64_t g0, int64_t g1, int32_t* out_x, int32_t* out_z, hipStream_t s) {
+  int64_t n = na + nb;
+  if (n <= 0) return;
+  int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
+  hipLaunchKernelGGL(k_merge_write, dim3(g), dim3(NT), 0, s, x_lo, x_hi, off_a, off_b, off_out, la, lb, na, nb, vals_x,
+                     vals_z, g0, g1, out_x, out_z);
+  JP_LAUNCH_CHECK();
+}
+
+}  // namespace jp

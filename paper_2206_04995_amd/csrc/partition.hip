@@ -1,0 +1,181 @@
+// Intersection-free partition of S by z (paper Sec. 2.3, Alg. 1 line
+// "partition S by S.z"): every S tuple of a z goes to the dense part iff
+// m_z > tau for that z's instance, so the results of the two parts are
+// disjoint.  Also builds the structures of the dense part: the hot join keys
+// (y with many dense S entries) as bit rows over the dense z index, and the
+// remaining dense entries as "cold" CSR rows.
+#include "common.h"
+#include "prim.h"
+#include "stages.h"
+
+namespace jp {
+namespace {
+
+constexpr int NT = 256;
+
+inline int grid(int64_t n, int cap = 1 << 20) {
+  int64_t g = (n + NT - 1) / NT;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return int(g);
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < (n); i += int64_t(gridDim.x) * blockDim.x)
+
+__global__ void k_dense_flags(const int32_t* __restrict__ m_z, int64_t n_z, const int32_t* __restrict__ z_base,
+                              int n_inst, const int64_t* __restrict__ tau, int32_t* __restrict__ flag) {
+  GRID_STRIDE(z, n_z) {
+    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(z_base, n_inst, int32_t(z));
+    flag[z] = int64_t(m_z[z]) > tau[inst] ? 1 : 0;
+  }
+}
+
+__global__ void k_dense_index(const int32_t* __restrict__ flag, const int32_t* __restrict__ Edz, int64_t n_z,
+                              int32_t* __restrict__ dz2z) {
+  GRID_STRIDE(z, n_z) {
+    if (flag[z]) dz2z[Edz[z]] = int32_t(z);
+  }
+}
+
+// one thread per S entry; the row (y id) of entry p is Ey[p + 1] - 1
+__global__ void k_entry_flags(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol, int64_t n,
+                              const int32_t* __restrict__ zflag, const int32_t* __restrict__ hot,
+                              int32_t* __restrict__ sp_flag, int32_t* __restrict__ cold_flag) {
+  GRID_STRIDE(p, n) {
+    int d = zflag[scol[p]];
+    if (sp_flag) sp_flag[p] = d ? 0 : 1;
+    if (cold_flag) {
+      int h = hot[Ey[p + 1] - 1];
+      cold_flag[p] = (d && !h) ? 1 : 0;
+    }
+  }
+}
+
+__global__ void k_remap_rowptr(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ E, int64_t n_y,
+                               int32_t* __restrict__ out) {
+  GRID_STRIDE(y, n_y + 1) { out[y] = E[rowptr[y]]; }
+}
+
+__global__ void k_compact_entries(const int32_t* __restrict__ scol, const int32_t* __restrict__ flag,
+                                  const int32_t* __restrict__ E, int64_t n, const int32_t* __restrict__ Edz,
+                                  const int32_t* __restrict__ z_base, const int32_t* __restrict__ zd_base,
+                                  int n_inst, int to_local_dense, int32_t* __restrict__ out) {
+  GRID_STRIDE(p, n) {
+    if (flag[p]) {
+      int32_t z = scol[p];
+      int32_t v = z;
+      if (to_local_dense) {
+        int inst = n_inst == 1 ? 0 : find_inst<int32_t>(z_base, n_inst, z);
+        v = Edz[z] - zd_base[inst];
+      }
+      out[E[p]] = v;
+    }
+  }
+}
+
+__device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
+
+__global__ void k_hot_histogram(const int32_t* __restrict__ sptr, const int32_t* __restrict__ spptr,
+                                const int32_t* __restrict__ dR, int64_t n_y, const int32_t* __restrict__ y_base,
+                                int n_inst, int32_t* __restrict__ hist) {
+  GRID_STRIDE(y, n_y) {
+    int dd = (sptr[y + 1] - sptr[y]) - (spptr[y + 1] - spptr[y]);
+    if (dd > 0 && dR[y] > 0) {
+      int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+      atomicAdd(&hist[inst * 32 + ilog2(dd)], 1);
+    }
+  }
+}
+
+__global__ void k_hot_flags(const int32_t* __restrict__ sptr, const int32_t* __restrict__ spptr,
+                            const int32_t* __restrict__ dR, int64_t n_y, const int32_t* __restrict__ y_base,
+                            int n_inst, const int64_t* __restrict__ theta, int32_t* __restrict__ hot) {
+  GRID_STRIDE(y, n_y) {
+    int dd = (sptr[y + 1] - sptr[y]) - (spptr[y + 1] - spptr[y]);
+    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+    hot[y] = (dd > 0 && dR[y] > 0 && int64_t(dd) >= theta[inst]) ? 1 : 0;
+  }
+}
+
+// one thread per S entry: set the bit of every dense z of a hot row
+__global__ void k_build_hot_bits(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol, int64_t n,
+                                 const int32_t* __restrict__ hot, const int32_t* __restrict__ Ehot,
+                                 const int32_t* __restrict__ y_base, const int32_t* __restrict__ z_base,
+                                 const int32_t* __restrict__ zd_base, const int32_t* __restrict__ Edz,
+                                 const int32_t* __restrict__ zflag, const int64_t* __restrict__ hb_off,
+                                 const int32_t* __restrict__ row_words, int n_inst, uint32_t* __restrict__ hb) {
+  GRID_STRIDE(p, n) {
+    int32_t y = Ey[p + 1] - 1;
+    int32_t z = scol[p];
+    if (!hot[y] || !zflag[z]) continue;
+    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+    int64_t k = Ehot[y] - Ehot[y_base[inst]];
+    uint32_t* row = hb + hb_off[inst] + k * row_words[inst];
+    int dl = Edz[z] - zd_base[inst];
+    atomicOr(&row[dl >> 5], 1u << (dl & 31));
+  }
+}
+
+}  // namespace
+
+void dense_flags(const int32_t* m_z, int64_t n_z, const int32_t* z_base, int n_inst, const int64_t* tau, int32_t* flag,
+                 hipStream_t s) {
+  if (n_z <= 0) return;
+  hipLaunchKernelGGL(k_dense_flags, dim3(grid(n_z)), dim3(NT), 0, s, m_z, n_z, z_base, n_inst, tau, flag);
+  JP_LAUNCH_CHECK();
+}
+
+void dense_index(const int32_t* flag, const int32_t* Edz, int64_t n_z, int32_t* dz2z, hipStream_t s) {
+  if (n_z <= 0) return;
+  hipLaunchKernelGGL(k_dense_index, dim3(grid(n_z)), dim3(NT), 0, s, flag, Edz, n_z, dz2z);
+  JP_LAUNCH_CHECK();
+}
+
+void entry_flags(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zflag, const int32_t* hot,
+                 int32_t* sp_flag, int32_t* cold_flag, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_entry_flags, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, zflag, hot, sp_flag, cold_flag);
+  JP_LAUNCH_CHECK();
+}
+
+void remap_rowptr(const int32_t* rowptr, const int32_t* E, int64_t n_y, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_remap_rowptr, dim3(grid(n_y + 1)), dim3(NT), 0, s, rowptr, E, n_y, out);
+  JP_LAUNCH_CHECK();
+}
+
+void compact_entries(const int32_t* scol, const int32_t* flag, const int32_t* E, int64_t n, const int32_t* Edz,
+                     const int32_t* z_base, const int32_t* zd_base, int n_inst, bool to_local_dense, int32_t* out,
+                     hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_compact_entries, dim3(grid(n)), dim3(NT), 0, s, scol, flag, E, n, Edz, z_base, zd_base, n_inst,
+                     to_local_dense ? 1 : 0, out);
+  JP_LAUNCH_CHECK();
+}
+
+void hot_histogram(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, const int32_t* y_base,
+                   int n_inst, int32_t* hist, hipStream_t s) {
+  fill_i32(hist, int64_t(n_inst) * 32, 0, s);
+  if (n_y <= 0) return;
+  hipLaunchKernelGGL(k_hot_histogram, dim3(grid(n_y)), dim3(NT), 0, s, sptr, spptr, dR, n_y, y_base, n_inst, hist);
+  JP_LAUNCH_CHECK();
+}
+
+void hot_flags(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, const int32_t* y_base,
+               int n_inst, const int64_t* theta, int32_t* hot, hipStream_t s) {
+  if (n_y <= 0) return;
+  hipLaunchKernelGGL(k_hot_flags, dim3(grid(n_y)), dim3(NT), 0, s, sptr, spptr, dR, n_y, y_base, n_inst, theta, hot);
+  JP_LAUNCH_CHECK();
+}
+
+void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* Ehot,
+                    const int32_t* y_base, const int32_t* z_base, const int32_t* zd_base, const int32_t* Edz,
+                    const int32_t* zflag, const int64_t* hb_off, const int32_t* row_words, int n_inst, uint32_t* hb,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_build_hot_bits, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, hot, Ehot, y_base, z_base,
+                     zd_base, Edz, zflag, hb_off, row_words, n_inst, hb);
+  JP_LAUNCH_CHECK();
+}
+
+}  // namespace jp

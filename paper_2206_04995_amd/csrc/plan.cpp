@@ -1,0 +1,734 @@
+// Host orchestration of the Join-Project path (paper Alg. 1) and the C ABI
+// declared in include/jp.h.  A single query is a batch of one instance: every
+// stage runs as one launch over all instances, whose ids occupy disjoint
+// ranges of the global x, y and z id spaces.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/jp.h"
+#include "common.h"
+#include "plan_impl.h"
+#include "prim.h"
+#include "stages.h"
+
+using namespace jp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+jp_status fail(int st, const std::string& m) {
+  g_last_error = m;
+  return jp_status(st);
+}
+
+template <class F>
+jp_status guarded(F&& f) {
+  try {
+    f();
+    return JP_OK;
+  } catch (const Error& e) {
+    return fail(e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(JP_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(JP_EHIP, e.what());
+  }
+}
+
+template <class T>
+void h2d(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (n) JP_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <class T>
+void d2h(T* dst, const T* src, size_t n, hipStream_t s) {
+  if (n) JP_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, s));
+}
+void sync(hipStream_t s) { JP_HIP(hipStreamSynchronize(s)); }
+
+double env_double(const char* name, double dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::atof(v);
+}
+
+// Per-instance key offsets from per-instance ranges [mn, mx]: instance i's keys
+// are koff[i] + (v - mn[i]).  Returns the number of key bits.
+int key_layout(const std::vector<int32_t>& mn, const std::vector<int32_t>& mx, std::vector<int64_t>& koff) {
+  int n = int(mn.size());
+  koff.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    int64_t rng = mn[i] <= mx[i] ? int64_t(mx[i]) - int64_t(mn[i]) + 1 : 0;
+    koff[i + 1] = koff[i] + rng;
+  }
+  if (koff[n] > (int64_t(1) << 32))
+    throw Error(JP_EINVAL, "the instances' value ranges add up to more than 2^32 keys; split the batch");
+  return bits_for(uint64_t(koff[n]));
+}
+
+// gather of per-instance device columns into one concatenated buffer
+__global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int32_t* __restrict__ base, int n_inst,
+                              int64_t n, int32_t* __restrict__ dst) {
+  for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x) {
+    int inst = find_inst<int32_t>(base, n_inst, int32_t(g));
+    dst[g] = src[inst][g - base[inst]];
+  }
+}
+
+__global__ void k_hotrow(const int32_t* __restrict__ hot, const int32_t* __restrict__ Ehot, int64_t n_y,
+                         const int32_t* __restrict__ y_base, int n_inst, int32_t* __restrict__ hotrow) {
+  for (int64_t y = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; y < n_y; y += int64_t(gridDim.x) * blockDim.x) {
+    if (hot[y]) {
+      int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+      hotrow[y] = Ehot[y] - Ehot[y_base[inst]];
+    } else {
+      hotrow[y] = -1;
+    }
+  }
+}
+
+__global__ void k_slice_info(const int64_t* __restrict__ off_de, const int64_t* __restrict__ off_sp,
+                             const int64_t* __restrict__ rows, int64_t* __restrict__ info) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t lo = rows[0], hi = rows[1];
+    info[0] = lo;
+    info[1] = hi;
+    info[2] = off_de[lo];
+    info[3] = off_de[hi];
+    info[4] = off_sp[lo];
+    info[5] = off_sp[hi];
+  }
+}
+
+inline int grid_of(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1 << 16))); }
+
+}  // namespace
+
+namespace jp {
+
+// Threshold tau of f2 (paper Sec. 2.6): a z is dense iff T_sparseBMM(z) >
+// T_denseEC(z).  With OUT_{J,z} estimated as m_z / |S| * OUT_J (as in the
+// paper), T_sparseBMM(z) = c_fix / |Z| + c_sp * m_z / |S| * OUT_J and
+// T_denseEC(z) = c_de * |X| (one bit decision per x), so f2 grows with m_z and
+// the test is m_z > tau with tau = (c_de |X| - c_fix / |Z|) |S| / (c_sp OUT_J).
+int64_t tau_from_cost(int64_t nx, int64_t nz, int64_t ns, int64_t out_j, double c_de_over_sp, double c_fix_over_sp) {
+  if (out_j <= 0 || nz <= 0 || nx <= 0) return INT64_MAX;
+  double t = (c_de_over_sp * double(nx) - c_fix_over_sp / double(nz)) * double(ns) / double(out_j);
+  if (t < -1.0) return -1;
+  if (t > 9.0e18) return INT64_MAX;
+  return int64_t(std::floor(t));
+}
+
+void Plan::build(const jp_instance* inst, int n, const jp_options* o, hipStream_t s) {
+  n_inst = n;
+  if (o) opt = *o;
+  else std::memset(&opt, 0, sizeof(opt));
+  stream = s;
+  stream_used = true;
+  arena_limit(opt.workspace_limit_bytes);
+  h_rbase.assign(n + 1, 0);
+  h_sbase.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) {
+    h_rbase[i + 1] = h_rbase[i] + int32_t(inst[i].n_r);
+    h_sbase[i + 1] = h_sbase[i] + int32_t(inst[i].n_s);
+  }
+  NR = h_rbase[n];
+  NS = h_sbase[n];
+
+  d_rbase = A.alloc<int32_t>(n + 1, s);
+  d_sbase = A.alloc<int32_t>(n + 1, s);
+  h2d(d_rbase, h_rbase.data(), n + 1, s);
+  h2d(d_sbase, h_sbase.data(), n + 1, s);
+
+  if (n == 1) {
+    rx = inst[0].r_x;
+    ry = inst[0].r_y;
+    sz = inst[0].s_z;
+    sy = inst[0].s_y;
+  } else {
+    std::vector<const int32_t*> ptrs(4 * size_t(n));
+    for (int i = 0; i < n; ++i) {
+      ptrs[i] = inst[i].r_x;
+      ptrs[n + i] = inst[i].r_y;
+      ptrs[2 * n + i] = inst[i].s_z;
+      ptrs[3 * n + i] = inst[i].s_y;
+    }
+    const int32_t** d_ptrs = A.alloc<const int32_t*>(4 * int64_t(n), s);
+    h2d(d_ptrs, ptrs.data(), ptrs.size(), s);
+    int32_t* cat = A.alloc<int32_t>(2 * NR + 2 * NS, s);
+    int32_t *crx = cat, *cry = cat + NR, *csz = cat + 2 * NR, *csy = cat + 2 * NR + NS;
+    if (NR) {
+      hipLaunchKernelGGL(k_gather_cols, dim3(grid_of(NR)), dim3(256), 0, s, d_ptrs, d_rbase, n, NR, crx);
+      hipLaunchKernelGGL(k_gather_cols, dim3(grid_of(NR)), dim3(256), 0, s, d_ptrs + n, d_rbase, n, NR, cry);
+    }
+    if (NS) {
+      hipLaunchKernelGGL(k_gather_cols, dim3(grid_of(NS)), dim3(256), 0, s, d_ptrs + 2 * n, d_sbase, n, NS, csz);
+      hipLaunchKernelGGL(k_gather_cols, dim3(grid_of(NS)), dim3(256), 0, s, d_ptrs + 3 * n, d_sbase, n, NS, csy);
+    }
+    JP_LAUNCH_CHECK();
+    rx = crx;
+    ry = cry;
+    sz = csz;
+    sy = csy;
+  }
+  map(s);
+  partition(s);
+}
+
+// ---------------------------------------------------------------- mapping
+void Plan::map(hipStream_t s) {
+  const int n = n_inst;
+  Arena T;  // temporaries of the mapping stage
+  int32_t* mm = T.alloc<int32_t>(6 * int64_t(n), s);
+  int32_t *zmin = mm, *zmax = mm + n, *ymin = mm + 2 * n, *ymax = mm + 3 * n, *xmin = mm + 4 * n, *xmax = mm + 5 * n;
+  seg_minmax(sz, NS, d_sbase, n, zmin, zmax, s);
+  seg_minmax(sy, NS, d_sbase, n, ymin, ymax, s);
+  std::vector<int32_t> h_mm(4 * size_t(n));
+  d2h(h_mm.data(), mm, 4 * size_t(n), s);
+  sync(s);
+  std::vector<int32_t> hzmin(h_mm.begin(), h_mm.begin() + n), hzmax(h_mm.begin() + n, h_mm.begin() + 2 * n);
+  std::vector<int32_t> hymin(h_mm.begin() + 2 * n, h_mm.begin() + 3 * n), hymax(h_mm.begin() + 3 * n, h_mm.end());
+  std::vector<int64_t> koff_z, koff_y, koff_x;
+  int zbits = key_layout(hzmin, hzmax, koff_z);
+  int ybits = key_layout(hymin, hymax, koff_y);
+  int64_t* d_koff = T.alloc<int64_t>(3 * (int64_t(n) + 1), s);
+  int64_t *dkz = d_koff, *dky = d_koff + (n + 1), *dkx = d_koff + 2 * (n + 1);
+  h2d(dkz, koff_z.data(), n + 1, s);
+  h2d(dky, koff_y.data(), n + 1, s);
+
+  const int64_t NSa = std::max<int64_t>(NS, 1);
+  uint32_t* k1 = T.alloc<uint32_t>(NSa, s);
+  uint32_t* v1 = T.alloc<uint32_t>(NSa, s);
+  uint32_t* k2 = T.alloc<uint32_t>(NSa, s);
+  uint32_t* v2 = T.alloc<uint32_t>(NSa, s);
+  int32_t* flags = T.alloc<int32_t>(std::max<int64_t>(std::max(NS, NR), 1), s);
+
+  // S sorted by (instance, z): z ids, m_z
+  make_keys(sz, NS, d_sbase, n, dkz, zmin, k1, v1, s);
+  bool alt = radix_sort_pairs(k1, v1, k2, v2, NS, zbits, s, T);
+  uint32_t *zk = alt ? k2 : k1, *zp = alt ? v2 : v1;
+  head_flags(zk, NS, flags, s);
+  int32_t* Ez = T.alloc<int32_t>(NS + 1, s);
+  scan_excl_i32(flags, Ez, NS, s, T);
+  zfirst = A.alloc<int32_t>(NS + 1, s);
+  vals_z = A.alloc<int32_t>(NSa, s);
+  assign_ids(zk, NS, Ez, dkz, zmin, n, zfirst, vals_z, s);
+  z_base = A.alloc<int32_t>(n + 1, s);
+  gather_bases(Ez, d_sbase, n, z_base, s);
+
+  // S sorted by (instance, y), z ascending inside each y: CSR of S by y
+  uint32_t *yk = alt ? k1 : k2, *yp = alt ? v1 : v2;  // the free pair
+  make_keys_perm(sy, zp, NS, d_sbase, n, dky, ymin, Ez, yk, yp, s);
+  uint32_t *ok = zk, *op = zp;  // reuse the z-sorted pair as scratch
+  bool alt2 = radix_sort_pairs(yk, yp, ok, op, NS, ybits, s, T);
+  uint32_t *syk = alt2 ? ok : yk, *syp = alt2 ? op : yp;
+  head_flags(syk, NS, flags, s);
+  Ey = A.alloc<int32_t>(NS + 1, s);
+  scan_excl_i32(flags, Ey, NS, s, T);
+  sptr = A.alloc<int32_t>(NS + 1, s);
+  vals_y = A.alloc<int32_t>(NSa, s);
+  assign_ids(syk, NS, Ey, dky, ymin, n, sptr, vals_y, s);
+  y_base = A.alloc<int32_t>(n + 1, s);
+  gather_bases(Ey, d_sbase, n, y_base, s);
+  scol = A.alloc<int32_t>(NSa, s);
+  if (NS) JP_HIP(hipMemcpyAsync(scol, syp, NS * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+
+  // semi-join of R on S.y (Sec. 2.2, optimisation 2), then R' sorted by (instance, x)
+  const int64_t NRa = std::max<int64_t>(NR, 1);
+  int32_t* yid = T.alloc<int32_t>(NRa, s);
+  semijoin(ry, NR, d_rbase, n, vals_y, y_base, flags, yid, s);
+  int32_t* Ek = T.alloc<int32_t>(NR + 1, s);
+  scan_excl_i32(flags, Ek, NR, s, T);
+  int32_t* rpx = T.alloc<int32_t>(NRa, s);
+  uint32_t* rpy = T.alloc<uint32_t>(NRa, s);
+  compact_r(rx, yid, flags, Ek, NR, rpx, reinterpret_cast<int32_t*>(rpy), s);
+  d_rpbase = A.alloc<int32_t>(n + 1, s);
+  gather_bases(Ek, d_rbase, n, d_rpbase, s);
+
+  int32_t counts[3];
+  int32_t* d_counts = T.alloc<int32_t>(3, s);
+  JP_HIP(hipMemcpyAsync(d_counts + 0, Ez + NS, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  JP_HIP(hipMemcpyAsync(d_counts + 1, Ey + NS, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  JP_HIP(hipMemcpyAsync(d_counts + 2, Ek + NR, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  d2h(counts, d_counts, 3, s);
+  h_rpbase.resize(n + 1);
+  d2h(h_rpbase.data(), d_rpbase, n + 1, s);
+  sync(s);
+  NZ = counts[0];
+  NY = counts[1];
+  NRp = counts[2];
+
+  seg_minmax(rpx, NRp, d_rpbase, n, xmin, xmax, s);
+  std::vector<int32_t> hx(2 * size_t(n));
+  d2h(hx.data(), xmin, 2 * size_t(n), s);
+  sync(s);
+  std::vector<int32_t> hxmin(hx.begin(), hx.begin() + n), hxmax(hx.begin() + n, hx.end());
+  int xbits = key_layout(hxmin, hxmax, koff_x);
+  h2d(dkx, koff_x.data(), n + 1, s);
+
+  const int64_t NRpa = std::max<int64_t>(NRp, 1);
+  uint32_t* xk = T.alloc<uint32_t>(NRpa, s);
+  uint32_t* xk2 = T.alloc<uint32_t>(NRpa, s);
+  uint32_t* xp2 = T.alloc<uint32_t>(NRpa, s);
+  make_keys(rpx, NRp, d_rpbase, n, dkx, xmin, xk, nullptr, s);
+  bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, xbits, s, T);
+  uint32_t *sxk = alt3 ? xk2 : xk, *sxp = alt3 ? xp2 : rpy;
+  head_flags(sxk, NRp, flags, s);
+  int32_t* Ex = T.alloc<int32_t>(NRp + 1, s);
+  scan_excl_i32(flags, Ex, NRp, s, T);
+  rptr = A.alloc<int32_t>(NRp + 1, s);
+  vals_x = A.alloc<int32_t>(NRpa, s);
+  assign_ids(sxk, NRp, Ex, dkx, xmin, n, rptr, vals_x, s);
+  x_base = A.alloc<int32_t>(n + 1, s);
+  gather_bases(Ex, d_rpbase, n, x_base, s);
+  rcol = A.alloc<int32_t>(NRpa, s);
+  if (NRp) JP_HIP(hipMemcpyAsync(rcol, sxp, NRp * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+
+  // degree statistics (Sec. 2.6): m_z, d_R(y), d_S(y), OUT_J per instance
+  const int64_t NYa = std::max<int64_t>(NY, 1);
+  m_z = A.alloc<int32_t>(std::max<int64_t>(NZ, 1), s);
+  run_lengths(zfirst, NZ, m_z, s);
+  dR = A.alloc<int32_t>(NYa, s);
+  dS = A.alloc<int32_t>(NYa, s);
+  fill_i32(dR, NY, 0, s);
+  histogram(reinterpret_cast<const uint32_t*>(rcol), NRp, dR, s);
+  run_lengths(sptr, NY, dS, s);
+  d_outj = A.alloc<int64_t>(n, s);
+  out_j_per_inst(dR, dS, NY, y_base, n, d_outj, s);
+
+  h_xbase.resize(n + 1);
+  h_ybase.resize(n + 1);
+  h_zbase.resize(n + 1);
+  h_outj.resize(n);
+  d2h(h_xbase.data(), x_base, n + 1, s);
+  d2h(h_ybase.data(), y_base, n + 1, s);
+  d2h(h_zbase.data(), z_base, n + 1, s);
+  d2h(h_outj.data(), d_outj, n, s);
+  sync(s);
+  NX = h_xbase[n];
+  T.release(s);
+}
+
+// -------------------------------------------------------------- partition
+void Plan::partition(hipStream_t s) {
+  const int n = n_inst;
+  Arena T;
+  const double c_de = env_double("JP_COST_DE_OVER_SP", 0.05);
+  const double c_fix = env_double("JP_COST_FIX_OVER_SP", 0.0);
+  h_tau.resize(n);
+  for (int i = 0; i < n; ++i) {
+    if (opt.tau_mode == JP_TAU_FIXED) {
+      h_tau[i] = opt.dense_threshold;
+    } else {
+      int64_t nx = h_xbase[i + 1] - h_xbase[i], nz = h_zbase[i + 1] - h_zbase[i];
+      int64_t ns = h_sbase[i + 1] - h_sbase[i];
+      h_tau[i] = tau_from_cost(nx, nz, ns, h_outj[i], c_de, c_fix);
+    }
+  }
+  d_tau = A.alloc<int64_t>(n, s);
+  h2d(d_tau, h_tau.data(), n, s);
+
+  const int64_t NZa = std::max<int64_t>(NZ, 1), NSa = std::max<int64_t>(NS, 1), NYa = std::max<int64_t>(NY, 1);
+  zflag = A.alloc<int32_t>(NZa, s);
+  dense_flags(m_z, NZ, z_base, n, d_tau, zflag, s);
+  Edz = A.alloc<int32_t>(NZ + 1, s);
+  scan_excl_i32(zflag, Edz, NZ, s, T);
+  dz2z = A.alloc<int32_t>(NZa, s);
+  dense_index(zflag, Edz, NZ, dz2z, s);
+  zd_base = A.alloc<int32_t>(n + 1, s);
+  gather_bases(Edz, z_base, n, zd_base, s);
+
+  // S_sparse: CSR by y of the entries whose z is sparse
+  int32_t* fl = T.alloc<int32_t>(NSa, s);
+  entry_flags(Ey, scol, NS, zflag, nullptr, fl, nullptr, s);
+  int32_t* Esp = T.alloc<int32_t>(NS + 1, s);
+  scan_excl_i32(fl, Esp, NS, s, T);
+  spptr = A.alloc<int32_t>(NY + 1, s);
+  remap_rowptr(sptr, Esp, NY, spptr, s);
+  int32_t nsp = 0;
+  d2h(&nsp, Esp + NS, 1, s);
+  int32_t* hist = T.alloc<int32_t>(int64_t(n) * 32, s);
+  hot_histogram(sptr, spptr, dR, NY, y_base, n, hist, s);
+  std::vector<int32_t> h_hist(size_t(n) * 32);
+  d2h(h_hist.data(), hist, size_t(n) * 32, s);
+  h_zdbase.resize(n + 1);
+  d2h(h_zdbase.data(), zd_base, n + 1, s);
+  sync(s);
+  NSp = nsp;
+  NZd = h_zdbase[n];
+  spcol = A.alloc<int32_t>(std::max<int64_t>(NSp, 1), s);
+  compact_entries(scol, fl, Esp, NS, Edz, z_base, zd_base, n, false, spcol, s);
+
+  // hot join keys of DenseEC: dense S row covering at least theta of the dense z
+  const int kmax = opt.k_hot_max > 0 ? std::min(opt.k_hot_max, 1024) : 256;
+  const double hot_frac = env_double("JP_HOT_MIN_FRACTION", 1.0 / 128.0);
+  h_theta.assign(n, INT64_MAX);
+  h_K.assign(n, 0);
+  h_roww.assign(n, 0);
+  h_hboff.assign(n, 0);
+  int64_t hb_words = 0;
+  for (int i = 0; i < n; ++i) {
+    int64_t zd = h_zdbase[i + 1] - h_zdbase[i];
+    h_hboff[i] = hb_words;
+    if (zd <= 0) continue;
+    int64_t nwin = (zd + DW_BITS - 1) / DW_BITS;
+    h_roww[i] = int32_t(nwin * DW_WORDS);
+    int64_t th = std::max<int64_t>(2, int64_t(std::ceil(double(zd) * hot_frac)));
+    int b = 0;
+    while ((int64_t(1) << b) < th) ++b;
+    // raise the bucket until at most kmax keys qualify
+    auto count_from = [&](int bb) {
+      int64_t c = 0;
+      for (int q = bb; q < 32; ++q) c += h_hist[size_t(i) * 32 + q];
+      return c;
+    };
+    while (b < 31 && count_from(b) > kmax) ++b;
+    int64_t K = count_from(b);
+    h_theta[i] = int64_t(1) << b;
+    h_K[i] = K;
+    hb_words += K * h_roww[i];
+  }
+  d_theta = A.alloc<int64_t>(n, s);
+  h2d(d_theta, h_theta.data(), n, s);
+  d_hboff = A.alloc<int64_t>(n, s);
+  h2d(d_hboff, h_hboff.data(), n, s);
+  d_roww = A.alloc<int32_t>(n, s);
+  h2d(d_roww, h_roww.data(), n, s);
+  int32_t* hot = T.alloc<int32_t>(NYa, s);
+  hot_flags(sptr, spptr, dR, NY, y_base, n, d_theta, hot, s);
+  Ehot = A.alloc<int32_t>(NY + 1, s);
+  scan_excl_i32(hot, Ehot, NY, s, T);
+  hotrow = A.alloc<int32_t>(NYa, s);
+  if (NY) {
+    hipLaunchKernelGGL(k_hotrow, dim3(grid_of(NY)), dim3(256), 0, s, hot, Ehot, NY, y_base, n, hotrow);
+    JP_LAUNCH_CHECK();
+  }
+  NHb = hb_words;
+  hb = A.alloc<uint32_t>(std::max<int64_t>(hb_words, 4), s);
+  fill_u32(hb, hb_words, 0u, s);
+  build_hot_bits(Ey, scol, NS, hot, Ehot, y_base, z_base, zd_base, Edz, zflag, d_hboff, d_roww, n, hb, s);
+
+  // cold dense entries: CSR by y over the local dense index
+  entry_flags(Ey, scol, NS, zflag, hot, nullptr, fl, s);
+  int32_t* Ec = T.alloc<int32_t>(NS + 1, s);
+  scan_excl_i32(fl, Ec, NS, s, T);
+  cptr = A.alloc<int32_t>(NY + 1, s);
+  remap_rowptr(sptr, Ec, NY, cptr, s);
+  int32_t ncold = 0;
+  d2h(&ncold, Ec + NS, 1, s);
+  sync(s);
+  NCold = ncold;
+  ccol = A.alloc<int32_t>(std::max<int64_t>(NCold, 1), s);
+  compact_entries(scol, fl, Ec, NS, Edz, z_base, zd_base, n, true, ccol, s);
+  T.release(s);
+}
+
+RowCtx Plan::ctx() const {
+  RowCtx c;
+  c.n_inst = n_inst;
+  c.x_base = x_base;
+  c.z_base = z_base;
+  c.zd_base = zd_base;
+  c.rptr = rptr;
+  c.rcol = rcol;
+  c.spptr = spptr;
+  c.spcol = spcol;
+  c.hotrow = hotrow;
+  c.Ehot = Ehot;
+  c.y_base = y_base;
+  c.hb_off = d_hboff;
+  c.row_words = d_roww;
+  c.hb = hb;
+  c.cptr = cptr;
+  c.ccol = ccol;
+  c.dz2z = dz2z;
+  return c;
+}
+
+// ---------------------------------------------------------------- execute
+void Plan::execute(hipStream_t s) {
+  stream = s;
+  stream_used = true;
+  const int64_t NXa = std::max<int64_t>(NX, 1);
+  if (!w) {
+    w = A.alloc<int64_t>(NXa, s);
+    cnt_sp = A.alloc<int32_t>(NXa, s);
+    cnt_de = A.alloc<int32_t>(NXa, s);
+    cnt_all = A.alloc<int32_t>(NXa, s);
+    off_all = A.alloc<int64_t>(NX + 1, s);
+    off_de = A.alloc<int64_t>(NX + 1, s);
+    off_sp = A.alloc<int64_t>(NX + 1, s);
+    tot = A.alloc<int64_t>(3 * int64_t(n_inst), s);
+  }
+  RowCtx c = ctx();
+  sparse_row_work(c, 0, NX, w, s);
+  if (NSp > 0) sparse_bmm(c, 0, NX, w, cnt_sp, nullptr, nullptr, s);
+  else fill_i32(cnt_sp, NX, 0, s);
+  if (NZd > 0) dense_ec(c, 0, NX, cnt_de, nullptr, nullptr, s);
+  else fill_i32(cnt_de, NX, 0, s);
+  add_counts(cnt_sp, cnt_de, NX, cnt_all, s);
+  scan_excl_i32_to_i64(cnt_all, off_all, NX, s, A);
+  scan_excl_i32_to_i64(cnt_de, off_de, NX, s, A);
+  scan_excl_i32_to_i64(cnt_sp, off_sp, NX, s, A);
+  inst_totals(off_all, off_de, off_sp, x_base, n_inst, tot, s);
+  executed = true;
+  h_tot.clear();
+}
+
+void Plan::fetch_totals(hipStream_t s) {
+  if (!executed) throw Error(JP_ESTATE, "count before execute");
+  if (h_tot.empty()) {
+    h_tot.resize(3 * size_t(n_inst));
+    d2h(h_tot.data(), tot, h_tot.size(), s);
+    sync(s);
+  }
+}
+
+// Write pairs [first, first + max) of instance i's sorted `part` result.
+int64_t Plan::materialize(int inst, int part, int64_t first, int64_t maxp, int32_t* ox, int32_t* oz, hipStream_t s) {
+  fetch_totals(s);
+  const int64_t count = h_tot[3 * size_t(inst) + size_t(part)];
+  if (first > count) throw Error(JP_ERANGE, "first beyond the number of pairs");
+  const int64_t nw = std::min(maxp, count - first);
+  if (nw <= 0) return 0;
+  const int64_t xb = h_xbase[inst], xe = h_xbase[inst + 1];
+  const int64_t* off = part == JP_PART_ALL ? off_all : (part == JP_PART_DENSE ? off_de : off_sp);
+  int64_t base = 0;
+  d2h(&base, off + xb, 1, s);
+  sync(s);
+  const int64_t g0 = base + first, g1 = g0 + nw;
+  Arena T;
+  int64_t* rows = T.alloc<int64_t>(2, s);
+  int64_t* info = T.alloc<int64_t>(6, s);
+  find_rows(off, xb, xe, g0, g1, rows, s);
+  hipLaunchKernelGGL(k_slice_info, dim3(1), dim3(64), 0, s, off_de, off_sp, rows, info);
+  JP_LAUNCH_CHECK();
+  int64_t h[6];
+  d2h(h, info, 6, s);
+  sync(s);
+  const int64_t xl = h[0], xh = h[1];
+  const int64_t nde = (part == JP_PART_SPARSE) ? 0 : h[3] - h[2];
+  const int64_t nsp = (part == JP_PART_DENSE) ? 0 : h[5] - h[4];
+  RowCtx c = ctx();
+  int32_t* lde = T.alloc<int32_t>(std::max<int64_t>(nde, 1), s);
+  int32_t* lsp = T.alloc<int32_t>(std::max<int64_t>(nsp, 1), s);
+  if (nde > 0) dense_ec(c, xl, xh, nullptr, off_de, lde, s);
+  if (nsp > 0) sparse_bmm(c, xl, xh, w + xl, nullptr, off_sp, lsp, s);
+  if (part == JP_PART_ALL)
+    merge_write_n(xl, xh, off_de, off_sp, off_all, lde, lsp, nde, nsp, vals_x, vals_z, g0, g1, ox, oz, s);
+  else if (part == JP_PART_DENSE)
+    merge_write_n(xl, xh, off_de, off_de, off_de, lde, nullptr, nde, 0, vals_x, vals_z, g0, g1, ox, oz, s);
+  else
+    merge_write_n(xl, xh, off_sp, off_sp, off_sp, lsp, nullptr, nsp, 0, vals_x, vals_z, g0, g1, ox, oz, s);
+  sync(s);
+  T.release(s);
+  return nw;
+}
+
+void Plan::stats(int i, jp_stats* st) const {
+  st->n_x = h_xbase[i + 1] - h_xbase[i];
+  st->n_y = h_ybase[i + 1] - h_ybase[i];
+  st->n_z = h_zbase[i + 1] - h_zbase[i];
+  st->n_r_kept = h_rpbase[i + 1] - h_rpbase[i];
+  st->out_j = h_outj[i];
+  st->tau = h_tau[i];
+  st->n_z_dense = h_zdbase[i + 1] - h_zdbase[i];
+  st->k_hot = h_K[i];
+  st->footprint_bytes = n_inst == 1 ? A.bytes() : A.bytes() / n_inst;
+}
+
+}  // namespace jp
+
+// ================================================================== C ABI
+
+struct jp_plan {
+  Plan p;
+};
+struct jp_batch {
+  Plan p;
+};
+
+namespace {
+
+jp_status check_cols(const int32_t* a, const int32_t* b, int64_t n, const char* what) {
+  if (n < 0) return fail(JP_EINVAL, std::string(what) + ": negative tuple count");
+  if (n > INT32_MAX) return fail(JP_EINVAL, std::string(what) + ": more than 2^31-1 tuples");
+  if (n > 0 && (!a || !b)) return fail(JP_EINVAL, std::string(what) + ": null column with n > 0");
+  return JP_OK;
+}
+
+jp_status check_opt(const jp_options* o) {
+  if (!o) return JP_OK;
+  if (o->tau_mode != JP_TAU_AUTO && o->tau_mode != JP_TAU_FIXED) return fail(JP_EINVAL, "bad tau_mode");
+  if (o->dense_kernel < 0 || o->dense_kernel > 2) return fail(JP_EINVAL, "bad dense_kernel");
+  if (o->k_hot_max < 0 || o->k_hot_max > 1024) return fail(JP_EINVAL, "k_hot_max must be in [0, 1024]");
+  if (o->flags != 0) return fail(JP_EINVAL, "flags must be 0");
+  if (o->workspace_limit_bytes < 0) return fail(JP_EINVAL, "negative workspace limit");
+  if (o->tau_mode == JP_TAU_FIXED && o->dense_threshold < -1) return fail(JP_EINVAL, "dense_threshold < -1");
+  return JP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* jp_last_error(void) { return g_last_error.c_str(); }
+
+jp_status jp_plan_create(const int32_t* r_x, const int32_t* r_y, int64_t n_r, const int32_t* s_z, const int32_t* s_y,
+                         int64_t n_s, const jp_options* opt, hipStream_t stream, jp_plan** out) {
+  if (!out) return fail(JP_EINVAL, "out is null");
+  *out = nullptr;
+  jp_status st;
+  if ((st = check_cols(r_x, r_y, n_r, "R")) != JP_OK) return st;
+  if ((st = check_cols(s_z, s_y, n_s, "S")) != JP_OK) return st;
+  if ((st = check_opt(opt)) != JP_OK) return st;
+  jp_plan* p = new (std::nothrow) jp_plan();
+  if (!p) return fail(JP_ENOMEM, "host allocation failed");
+  jp_instance in{r_x, r_y, s_z, s_y, n_r, n_s};
+  st = guarded([&] { p->p.build(&in, 1, opt, stream); });
+  if (st != JP_OK) {
+    jp_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return JP_OK;
+}
+
+jp_status jp_execute(jp_plan* p, hipStream_t stream) {
+  if (!p) return fail(JP_EINVAL, "plan is null");
+  return guarded([&] { p->p.execute(stream); });
+}
+
+jp_status jp_count(jp_plan* p, int64_t* total, int64_t* dense, int64_t* sparse, hipStream_t stream) {
+  if (!p) return fail(JP_EINVAL, "plan is null");
+  return guarded([&] {
+    p->p.fetch_totals(stream);
+    if (total) *total = p->p.h_tot[0];
+    if (dense) *dense = p->p.h_tot[1];
+    if (sparse) *sparse = p->p.h_tot[2];
+  });
+}
+
+jp_status jp_materialize(jp_plan* p, jp_part part, int64_t first, int64_t max_pairs, int32_t* out_x, int32_t* out_z,
+                         int64_t* n_written, hipStream_t stream) {
+  if (!p || !n_written) return fail(JP_EINVAL, "plan or n_written is null");
+  if (part < JP_PART_ALL || part > JP_PART_SPARSE) return fail(JP_EINVAL, "bad part");
+  if (first < 0 || max_pairs < 0) return fail(JP_EINVAL, "negative first or max_pairs");
+  if (max_pairs > 0 && (!out_x || !out_z)) return fail(JP_EINVAL, "null output with max_pairs > 0");
+  *n_written = 0;
+  return guarded([&] { *n_written = p->p.materialize(0, int(part), first, max_pairs, out_x, out_z, stream); });
+}
+
+jp_status jp_row_info(jp_plan* p, jp_part part, int32_t* x_values, int64_t* row_offsets, hipStream_t stream) {
+  if (!p) return fail(JP_EINVAL, "plan is null");
+  if (part < JP_PART_ALL || part > JP_PART_SPARSE) return fail(JP_EINVAL, "bad part");
+  return guarded([&] {
+    Plan& q = p->p;
+    if (x_values) d2h(x_values, q.vals_x, size_t(q.NX), stream);
+    if (row_offsets) {
+      if (!q.executed) throw Error(JP_ESTATE, "row offsets before execute");
+      const int64_t* off = part == JP_PART_ALL ? q.off_all : (part == JP_PART_DENSE ? q.off_de : q.off_sp);
+      d2h(row_offsets, off, size_t(q.NX) + 1, stream);
+    }
+    sync(stream);
+  });
+}
+
+jp_status jp_dense_z(jp_plan* p, int32_t* z_values, hipStream_t stream) {
+  if (!p) return fail(JP_EINVAL, "plan is null");
+  return guarded([&] {
+    Plan& q = p->p;
+    if (q.NZd > 0 && z_values) {
+      Arena T;
+      int32_t* tmp = T.alloc<int32_t>(q.NZd, stream);
+      jp::gather_values(q.vals_z, q.dz2z, q.NZd, tmp, stream);
+      d2h(z_values, tmp, size_t(q.NZd), stream);
+      sync(stream);
+      T.release(stream);
+    }
+  });
+}
+
+jp_status jp_plan_stats(const jp_plan* p, jp_stats* s) {
+  if (!p || !s) return fail(JP_EINVAL, "null argument");
+  p->p.stats(0, s);
+  return JP_OK;
+}
+
+void jp_plan_destroy(jp_plan* p) {
+  if (!p) return;
+  if (p->p.stream_used) (void)hipStreamSynchronize(p->p.stream);
+  delete p;
+}
+
+jp_status jp_batch_create(const jp_instance* inst, int32_t n_inst, const jp_options* opt, hipStream_t stream,
+                          jp_batch** out) {
+  if (!out) return fail(JP_EINVAL, "out is null");
+  *out = nullptr;
+  if (n_inst <= 0 || !inst) return fail(JP_EINVAL, "need at least one instance");
+  jp_status st;
+  int64_t sr = 0, ss = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    if ((st = check_cols(inst[i].r_x, inst[i].r_y, inst[i].n_r, "R")) != JP_OK) return st;
+    if ((st = check_cols(inst[i].s_z, inst[i].s_y, inst[i].n_s, "S")) != JP_OK) return st;
+    sr += inst[i].n_r;
+    ss += inst[i].n_s;
+  }
+  if (sr > INT32_MAX || ss > INT32_MAX) return fail(JP_EINVAL, "batch holds more than 2^31-1 tuples per side");
+  if ((st = check_opt(opt)) != JP_OK) return st;
+  jp_batch* b = new (std::nothrow) jp_batch();
+  if (!b) return fail(JP_ENOMEM, "host allocation failed");
+  st = guarded([&] { b->p.build(inst, n_inst, opt, stream); });
+  if (st != JP_OK) {
+    jp_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return JP_OK;
+}
+
+jp_status jp_batch_execute(jp_batch* b, hipStream_t stream) {
+  if (!b) return fail(JP_EINVAL, "batch is null");
+  return guarded([&] { b->p.execute(stream); });
+}
+
+jp_status jp_batch_counts(jp_batch* b, int64_t* totals, hipStream_t stream) {
+  if (!b || !totals) return fail(JP_EINVAL, "null argument");
+  return guarded([&] {
+    b->p.fetch_totals(stream);
+    for (int i = 0; i < b->p.n_inst; ++i) totals[i] = b->p.h_tot[3 * size_t(i)];
+  });
+}
+
+jp_status jp_batch_materialize(jp_batch* b, int32_t inst, jp_part part, int64_t first, int64_t max_pairs,
+                               int32_t* out_x, int32_t* out_z, int64_t* n_written, hipStream_t stream) {
+  if (!b || !n_written) return fail(JP_EINVAL, "batch or n_written is null");
+  if (inst < 0 || inst >= b->p.n_inst) return fail(JP_EINVAL, "instance index out of range");
+  if (part < JP_PART_ALL || part > JP_PART_SPARSE) return fail(JP_EINVAL, "bad part");
+  if (first < 0 || max_pairs < 0) return fail(JP_EINVAL, "negative first or max_pairs");
+  if (max_pairs > 0 && (!out_x || !out_z)) return fail(JP_EINVAL, "null output with max_pairs > 0");
+  *n_written = 0;
+  return guarded([&] { *n_written = b->p.materialize(inst, int(part), first, max_pairs, out_x, out_z, stream); });
+}
+
+jp_status jp_batch_stats(const jp_batch* b, int32_t inst, jp_stats* s) {
+  if (!b || !s) return fail(JP_EINVAL, "null argument");
+  if (inst < 0 || inst >= b->p.n_inst) return fail(JP_EINVAL, "instance index out of range");
+  b->p.stats(inst, s);
+  return JP_OK;
+}
+
+void jp_batch_destroy(jp_batch* b) {
+  if (!b) return;
+  if (b->p.stream_used) (void)hipStreamSynchronize(b->p.stream);
+  delete b;
+}
+
+}  // extern "C"

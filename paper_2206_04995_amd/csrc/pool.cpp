@@ -1,0 +1,116 @@
+// Caching device allocator (see pool.h).
+#include "pool.h"
+
+namespace jp {
+
+Pool& Pool::instance() {
+  static Pool* p = new Pool();  // leaked on purpose: outlives every plan
+  return *p;
+}
+
+void* Pool::alloc(size_t bytes, hipStream_t s) {
+  size_t want = round_alloc(bytes);
+  int dev = 0;
+  JP_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    // best fit among blocks no larger than 1.25x the request
+    auto it = free_.lower_bound(want);
+    while (it != free_.end() && it->first <= want + want / 4) {
+      Block& b = it->second;
+      bool ok = b.device == dev && (b.stream == s || hipEventQuery(b.ev) == hipSuccess);
+      if (ok) {
+        Block blk = b;
+        free_.erase(it);
+        cached_ -= blk.size;
+        used_[blk.p] = blk;
+        return blk.p;
+      }
+      ++it;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // give cached memory back and try once more
+    trim();
+    e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(2, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+  }
+  Block blk{p, want, s, nullptr, dev};
+  JP_HIP(hipEventCreateWithFlags(&blk.ev, hipEventDisableTiming));
+  std::lock_guard<std::mutex> g(mu_);
+  used_[p] = blk;
+  return p;
+}
+
+void Pool::free(void* p, hipStream_t s) {
+  if (!p) return;
+  std::lock_guard<std::mutex> g(mu_);
+  auto it = used_.find(p);
+  if (it == used_.end()) return;
+  Block b = it->second;
+  used_.erase(it);
+  b.stream = s;
+  if (hipEventRecord(b.ev, s) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipDeviceSynchronize();
+  }
+  free_.emplace(b.size, b);
+  cached_ += b.size;
+}
+
+void Pool::trim() {
+  std::vector<Block> drop;
+  {
+    std::lock_guard<std::mutex> g(mu_);
+    for (auto it = free_.begin(); it != free_.end();) {
+      if (hipEventQuery(it->second.ev) == hipSuccess) {
+        drop.push_back(it->second);
+        cached_ -= it->second.size;
+        it = free_.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  for (auto& b : drop) {
+    (void)hipEventDestroy(b.ev);
+    (void)hipFree(b.p);
+  }
+}
+
+void* Arena::raw(size_t bytes, hipStream_t s) {
+  size_t r = round_alloc(bytes);
+  if (limit_ > 0 && bytes_ + int64_t(r) > limit_)
+    throw Error(2, "workspace limit of " + std::to_string(limit_) + " bytes exceeded");
+  void* p = Pool::instance().alloc(bytes, s);
+  recs_.push_back({p, r});
+  bytes_ += int64_t(r);
+  if (bytes_ > peak_) peak_ = bytes_;
+  return p;
+}
+
+void Arena::give_back(void* p, hipStream_t s) {
+  for (size_t i = 0; i < recs_.size(); ++i) {
+    if (recs_[i].p == p) {
+      bytes_ -= int64_t(recs_[i].bytes);
+      Pool::instance().free(p, s);
+      recs_[i] = recs_.back();
+      recs_.pop_back();
+      return;
+    }
+  }
+}
+
+void Arena::release(hipStream_t s) {
+  for (auto& r : recs_) Pool::instance().free(r.p, s);
+  recs_.clear();
+  bytes_ = 0;
+}
+
+}  // namespace jp

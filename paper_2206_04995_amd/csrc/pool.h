@@ -1,0 +1,93 @@
+// Caching device allocator and error plumbing for the Join-Project library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace jp {
+
+// Error carried from a failing step to the C ABI boundary (never crosses it).
+struct Error : std::runtime_error {
+  int status;
+  Error(int st, const std::string& m) : std::runtime_error(m), status(st) {}
+};
+
+#define JP_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::jp::Error(3, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+#define JP_LAUNCH_CHECK() JP_HIP(hipGetLastError())
+
+// Device memory cache.  Blocks freed on a stream are reused at once by the
+// same stream (stream order makes that safe) and by other streams only after
+// an event recorded at the free has completed.  Memory is returned to HIP only
+// by trim() or at process exit.
+class Pool {
+ public:
+  static Pool& instance();
+  void* alloc(size_t bytes, hipStream_t s);
+  void free(void* p, hipStream_t s);
+  void trim();
+  size_t cached_bytes() const { return cached_; }
+
+ private:
+  struct Block {
+    void* p;
+    size_t size;
+    hipStream_t stream;
+    hipEvent_t ev;
+    int device;
+  };
+  std::mutex mu_;
+  std::multimap<size_t, Block> free_;
+  std::map<void*, Block> used_;
+  size_t cached_ = 0;
+};
+
+// Allocation owner for one plan: tracks bytes against an optional limit and
+// returns everything to the pool on release().
+class Arena {
+ public:
+  explicit Arena(int64_t limit = 0) : limit_(limit) {}
+  ~Arena() { release(nullptr); }
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+
+  template <class T>
+  T* alloc(int64_t count, hipStream_t s) {
+    return static_cast<T*>(raw(size_t(count < 1 ? 1 : count) * sizeof(T), s));
+  }
+  void* raw(size_t bytes, hipStream_t s);
+  void give_back(void* p, hipStream_t s);  // return one block early
+  void release(hipStream_t s);
+  void set_limit(int64_t lim) { limit_ = lim; }
+  int64_t bytes() const { return bytes_; }
+  int64_t peak() const { return peak_; }
+
+ private:
+  struct Rec {
+    void* p;
+    size_t bytes;
+  };
+  std::vector<Rec> recs_;
+  int64_t limit_;
+  int64_t bytes_ = 0;
+  int64_t peak_ = 0;
+};
+
+inline size_t round_alloc(size_t b) {
+  if (b <= 4096) return 4096;
+  if (b <= (1u << 20)) return (b + 4095) & ~size_t(4095);
+  return (b + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1);
+}
+
+}  // namespace jp

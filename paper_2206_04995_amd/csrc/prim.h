@@ -1,0 +1,33 @@
+// Device primitives: scans, LSD radix sort, segmented min/max, fills.
+#pragma once
+
+#include "pool.h"
+
+namespace jp {
+
+// out[0..n] = exclusive prefix sums of in[0..n); out[n] = total.
+void scan_excl_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s, Arena& a);
+void scan_excl_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s, Arena& a);
+void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s, Arena& a);
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
+// keys.  The sorted data ends up either in (k, v) or in (kt, vt); the function
+// returns true when it is in (kt, vt).  `v` may be null (keys only).
+bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int64_t n, int bits,
+                      hipStream_t s, Arena& a);
+
+// Per-segment min and max of int32 values; segment i is [base[i], base[i+1]).
+// mn/mx (n_seg entries) are overwritten; empty segments give mn > mx.
+void seg_minmax(const int32_t* v, int64_t n, const int32_t* base, int n_seg, int32_t* mn,
+                int32_t* mx, hipStream_t s);
+
+void fill_i32(int32_t* p, int64_t n, int32_t val, hipStream_t s);
+void fill_i64(int64_t* p, int64_t n, int64_t val, hipStream_t s);
+void fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s);
+
+// Sum of a[0..n) into *out (int64, device).
+void reduce_sum_i32_to_i64(const int32_t* a, int64_t n, int64_t* out, hipStream_t s);
+
+int bits_for(uint64_t range);  // number of bits to hold values in [0, range)
+
+}  // namespace jp

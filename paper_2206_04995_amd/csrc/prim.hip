@@ -1,0 +1,371 @@
+// Device primitives for gfx950: reduce-then-scan, LSD radix sort with
+// wave-ballot ranking and LDS-staged scatter, segmented min/max, fills.
+#include <climits>
+
+#include "common.h"
+#include "prim.h"
+
+namespace jp {
+
+namespace {
+
+constexpr int SCAN_NT = 256;
+constexpr int SCAN_IT = 8;
+constexpr int SCAN_TILE = SCAN_NT * SCAN_IT;
+
+template <class T>
+__device__ T block_excl_scan(T v, T* lds, T& total) {
+  const int lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  T inc = wave_incl_scan(v);
+  if (lane == 63) lds[wid] = inc;
+  __syncthreads();
+  T pre = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    T s = lds[w];
+    if (w < wid) pre += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + inc - v;
+}
+
+template <class Ti, class To>
+__global__ void __launch_bounds__(SCAN_NT) k_scan_reduce(const Ti* __restrict__ in, int64_t n,
+                                                         To* __restrict__ sums) {
+  __shared__ To lds[SCAN_NT / 64];
+  int64_t base = int64_t(blockIdx.x) * SCAN_TILE;
+  To acc = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_IT; ++j) {
+    int64_t i = base + j * SCAN_NT + threadIdx.x;
+    if (i < n) acc += To(in[i]);
+  }
+  To tot;
+  block_excl_scan<To>(acc, lds, tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// exclusive scan of `in` with an added per-block offset; out[n] written by the last block
+template <class Ti, class To>
+__global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const Ti* __restrict__ in, To* __restrict__ out,
+                                                        int64_t n, const To* __restrict__ offs,
+                                                        int single) {
+  __shared__ To lds[SCAN_NT / 64];
+  int64_t base = int64_t(blockIdx.x) * SCAN_TILE + int64_t(threadIdx.x) * SCAN_IT;
+  To v[SCAN_IT];
+  To loc = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_IT; ++j) {
+    int64_t i = base + j;
+    v[j] = i < n ? To(in[i]) : To(0);
+    loc += v[j];
+  }
+  To tot;
+  To pre = block_excl_scan<To>(loc, lds, tot);
+  To off = single ? To(0) : offs[blockIdx.x];
+  To run = off + pre;
+#pragma unroll
+  for (int j = 0; j < SCAN_IT; ++j) {
+    int64_t i = base + j;
+    if (i < n) out[i] = run;
+    run += v[j];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + tot;
+}
+
+template <class Ti, class To>
+void scan_impl(const Ti* in, To* out, int64_t n, hipStream_t s, Arena& a) {
+  if (n <= 0) {
+    hipLaunchKernelGGL((k_scan_apply<Ti, To>), dim3(1), dim3(SCAN_NT), 0, s, in, out, int64_t(0),
+                       (const To*)nullptr, 1);
+    JP_LAUNCH_CHECK();
+    return;
+  }
+  int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (nb == 1) {
+    hipLaunchKernelGGL((k_scan_apply<Ti, To>), dim3(1), dim3(SCAN_NT), 0, s, in, out, n,
+                       (const To*)nullptr, 1);
+    JP_LAUNCH_CHECK();
+    return;
+  }
+  To* sums = a.alloc<To>(nb, s);
+  To* offs = a.alloc<To>(nb + 1, s);
+  hipLaunchKernelGGL((k_scan_reduce<Ti, To>), dim3(nb), dim3(SCAN_NT), 0, s, in, n, sums);
+  JP_LAUNCH_CHECK();
+  scan_impl<To, To>(sums, offs, nb, s, a);
+  hipLaunchKernelGGL((k_scan_apply<Ti, To>), dim3(nb), dim3(SCAN_NT), 0, s, in, out, n,
+                     (const To*)offs, 0);
+  JP_LAUNCH_CHECK();
+  a.give_back(offs, s);
+  a.give_back(sums, s);
+}
+
+// ------------------------------------------------------------ radix sort
+
+constexpr int RS_NT = 256;
+constexpr int RS_IT = 16;
+constexpr int RS_TILE = RS_NT * RS_IT;  // 4096 keys per block
+constexpr int RS_WAVES = RS_NT / 64;
+constexpr int RS_WTILE = RS_TILE / RS_WAVES;  // 1024 keys per wave
+
+__global__ void __launch_bounds__(RS_NT) k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                       int shift, int nbits, int* __restrict__ hist,
+                                                       int nblocks) {
+  __shared__ int cnt[RS_WAVES][256];
+  const int wid = threadIdx.x >> 6;
+  const int nd = 1 << nbits;
+  const uint32_t mask = uint32_t(nd - 1);
+  for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  int64_t base = int64_t(blockIdx.x) * RS_TILE;
+#pragma unroll 4
+  for (int j = 0; j < RS_IT; ++j) {
+    int64_t i = base + j * RS_NT + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[wid][(keys[i] >> shift) & mask], 1);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < nd; d += RS_NT) {
+    int c = 0;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) c += cnt[w][d];
+    hist[int64_t(d) * nblocks + blockIdx.x] = c;
+  }
+}
+
+template <bool HAS_V>
+__global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                          const uint32_t* __restrict__ vin,
+                                                          uint32_t* __restrict__ kout,
+                                                          uint32_t* __restrict__ vout, int64_t n,
+                                                          int shift, int nbits,
+                                                          const int* __restrict__ offs, int nblocks) {
+  __shared__ uint32_t s_k[RS_TILE];
+  __shared__ uint32_t s_v[HAS_V ? RS_TILE : 1];
+  __shared__ int wcnt[RS_WAVES][256];
+  __shared__ int dstart[256];
+  __shared__ int goff[256];
+  __shared__ int scan_lds[RS_NT / 64];
+
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  const int nd = 1 << nbits;
+  const uint32_t mask = uint32_t(nd - 1);
+  const uint64_t ltm = lanemask_lt();
+  for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+
+  const int64_t tbase = int64_t(blockIdx.x) * RS_TILE;
+  const int64_t wbase = tbase + int64_t(wid) * RS_WTILE;
+  uint32_t key[RS_IT], val[RS_IT];
+  int lrank[RS_IT];
+#pragma unroll
+  for (int j = 0; j < RS_IT; ++j) {
+    int64_t i = wbase + j * 64 + lane;
+    bool valid = i < n;
+    uint32_t k = valid ? kin[i] : 0u;
+    uint32_t d = (k >> shift) & mask;
+    key[j] = k;
+    if (HAS_V) val[j] = valid ? vin[i] : 0u;
+    uint64_t m = ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      bool bit = (d >> b) & 1u;
+      uint64_t bb = ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    int r = -1;
+    if (valid) {
+      int rank = __popcll(m & ltm);
+      int leader = __ffsll((unsigned long long)m) - 1;
+      int c = __popcll(m);
+      int before = wcnt[wid][d];
+      if (lane == leader) wcnt[wid][d] = before + c;
+      r = before + rank;
+    }
+    lrank[j] = r;
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // per digit: prefix across waves, block total, block-local start
+  int tot_d = 0;
+  if (threadIdx.x < nd) {
+    int run = 0;
+#pragma unroll
+    for (int w = 0; w < RS_WAVES; ++w) {
+      int c = wcnt[w][threadIdx.x];
+      wcnt[w][threadIdx.x] = run;
+      run += c;
+    }
+    tot_d = run;
+    goff[threadIdx.x] = offs[int64_t(threadIdx.x) * nblocks + blockIdx.x];
+  }
+  int tile_total;
+  int st = block_excl_scan<int>(tot_d, scan_lds, tile_total);
+  if (threadIdx.x < nd) dstart[threadIdx.x] = st;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < RS_IT; ++j) {
+    if (lrank[j] >= 0) {
+      uint32_t d = (key[j] >> shift) & mask;
+      int pos = dstart[d] + wcnt[wid][d] + lrank[j];
+      s_k[pos] = key[j];
+      if (HAS_V) s_v[pos] = val[j];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < tile_total; i += RS_NT) {
+    uint32_t k = s_k[i];
+    uint32_t d = (k >> shift) & mask;
+    int64_t g = int64_t(goff[d]) + (i - dstart[d]);
+    kout[g] = k;
+    if (HAS_V) vout[g] = s_v[i];
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+constexpr int MM_CH = 16;
+
+__global__ void k_seg_minmax(const int32_t* __restrict__ v, int64_t n, const int32_t* __restrict__ base,
+                             int n_seg, int32_t* __restrict__ mn, int32_t* __restrict__ mx) {
+  int64_t start = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * MM_CH;
+  if (start >= n) return;
+  int64_t end = start + MM_CH < n ? start + MM_CH : n;
+  int seg = find_inst<int32_t>(base, n_seg, int32_t(start));
+  int32_t cmn = INT_MAX, cmx = INT_MIN;
+  bool any = false;
+  for (int64_t i = start; i < end; ++i) {
+    while (i >= base[seg + 1]) {
+      if (any) {
+        atomicMin(&mn[seg], cmn);
+        atomicMax(&mx[seg], cmx);
+      }
+      any = false;
+      cmn = INT_MAX;
+      cmx = INT_MIN;
+      ++seg;
+    }
+    int32_t x = v[i];
+    cmn = x < cmn ? x : cmn;
+    cmx = x > cmx ? x : cmx;
+    any = true;
+  }
+  if (any) {
+    atomicMin(&mn[seg], cmn);
+    atomicMax(&mx[seg], cmx);
+  }
+}
+
+__global__ void k_reduce_sum_i32(const int32_t* __restrict__ a, int64_t n, int64_t* out) {
+  int64_t acc = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    acc += a[i];
+  acc = wave_sum(acc);
+  if (lane_id() == 0 && acc) atomicAdd((unsigned long long*)out, (unsigned long long)acc);
+}
+
+int grid_for(int64_t n, int nt = 256, int cap = 65536) {
+  int64_t g = (n + nt - 1) / nt;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return int(g);
+}
+
+}  // namespace
+
+int bits_for(uint64_t range) {
+  int b = 0;
+  while (b < 64 && (uint64_t(1) << b) < range) ++b;
+  return b;
+}
+
+void scan_excl_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s, Arena& a) {
+  scan_impl<int32_t, int32_t>(in, out, n, s, a);
+}
+void scan_excl_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s, Arena& a) {
+  scan_impl<int32_t, int64_t>(in, out, n, s, a);
+}
+void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s, Arena& a) {
+  scan_impl<int64_t, int64_t>(in, out, n, s, a);
+}
+
+bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int64_t n, int bits,
+                      hipStream_t s, Arena& a) {
+  if (n <= 1 || bits <= 0) return false;
+  int passes = (bits + 7) / 8;
+  int width = (bits + passes - 1) / passes;
+  int nblocks = int((n + RS_TILE - 1) / RS_TILE);
+  int64_t hsz = int64_t(1 << width) * nblocks;
+  int* hist = a.alloc<int>(hsz, s);
+  int* offs = a.alloc<int>(hsz + 1, s);
+  uint32_t *ki = k, *vi = v, *ko = kt, *vo = vt;
+  int shift = 0;
+  for (int p = 0; p < passes; ++p) {
+    int w = width;
+    if (shift + w > bits) w = bits - shift;
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(RS_NT), 0, s, (const uint32_t*)ki, n, shift, w, hist,
+                       nblocks);
+    JP_LAUNCH_CHECK();
+    scan_impl<int, int>(hist, offs, int64_t(1 << w) * nblocks, s, a);
+    if (v)
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(nblocks), dim3(RS_NT), 0, s, (const uint32_t*)ki,
+                         (const uint32_t*)vi, ko, vo, n, shift, w, (const int*)offs, nblocks);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblocks), dim3(RS_NT), 0, s, (const uint32_t*)ki,
+                         (const uint32_t*)nullptr, ko, (uint32_t*)nullptr, n, shift, w, (const int*)offs,
+                         nblocks);
+    JP_LAUNCH_CHECK();
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+    shift += w;
+  }
+  a.give_back(offs, s);
+  a.give_back(hist, s);
+  return ki == kt;
+}
+
+void seg_minmax(const int32_t* v, int64_t n, const int32_t* base, int n_seg, int32_t* mn, int32_t* mx,
+                hipStream_t s) {
+  fill_i32(mn, n_seg, INT_MAX, s);
+  fill_i32(mx, n_seg, INT_MIN, s);
+  if (n <= 0) return;
+  int64_t threads = (n + MM_CH - 1) / MM_CH;
+  hipLaunchKernelGGL(k_seg_minmax, dim3(int((threads + 255) / 256)), dim3(256), 0, s, v, n, base, n_seg, mn,
+                     mx);
+  JP_LAUNCH_CHECK();
+}
+
+void fill_i32(int32_t* p, int64_t n, int32_t val, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(256), 0, s, p, n, val);
+  JP_LAUNCH_CHECK();
+}
+void fill_i64(int64_t* p, int64_t n, int64_t val, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n)), dim3(256), 0, s, p, n, val);
+  JP_LAUNCH_CHECK();
+}
+void fill_u32(uint32_t* p, int64_t n, uint32_t val, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, s, p, n, val);
+  JP_LAUNCH_CHECK();
+}
+
+void reduce_sum_i32_to_i64(const int32_t* a, int64_t n, int64_t* out, hipStream_t s) {
+  fill_i64(out, 1, 0, s);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_reduce_sum_i32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, a, n, out);
+  JP_LAUNCH_CHECK();
+}
+
+}  // namespace jp

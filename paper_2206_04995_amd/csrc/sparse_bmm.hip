@@ -1,0 +1,248 @@
+// SparseBMM (paper Sec. 2.4, Alg. 2): for every x row, the union of the
+// sparse S rows S_sparse[y] over the y in R[x], without duplicates.  S_sparse
+// in CSR is a collision-free hash table on y (row pointer = bucket header).
+//
+// The paper deduplicates with one z-vector (SPA) stamped with the current x
+// so it never has to be cleared.  Here x rows run in parallel, so every
+// wavefront owns a small LDS hash set sized to the row's work (cleared per
+// row, cost proportional to the row), and rows whose work exceeds it use a
+// whole workgroup with an LDS bitmap over windows of the z range.
+//
+// Count mode writes the number of distinct z per row; write mode writes the
+// sorted z ids of each row at off[x] - off[x_lo].
+#include "common.h"
+#include "stages.h"
+
+namespace jp {
+namespace {
+
+constexpr int NT = 256;
+constexpr int LIGHT_MAX = 1024;      // rows with at most this much work use a wave hash set
+constexpr int HT_SLOTS = 2048;       // slots of one wave's hash set (load <= 1/2)
+constexpr int32_t EMPTY = 0x7FFFFFFF;
+constexpr int HB_BITS = 1 << 19;     // heavy-row window: 64 KB of LDS
+constexpr int HB_WORDS = HB_BITS / 32;
+
+__device__ __forceinline__ void lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ void k_row_work(const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+                           const int32_t* __restrict__ spptr, int64_t x_lo, int64_t x_hi, int64_t* __restrict__ w) {
+  for (int64_t x = x_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < x_hi;
+       x += int64_t(gridDim.x) * blockDim.x) {
+    int64_t acc = 0;
+    for (int j = rptr[x]; j < rptr[x + 1]; ++j) {
+      int y = rcol[j];
+      acc += spptr[y + 1] - spptr[y];
+    }
+    w[x - x_lo] = acc;
+  }
+}
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t z, int log2t) {
+  return (uint32_t(z) * 0x9E3779B1u) >> (32 - log2t);
+}
+
+// In-place ascending bitonic sort of t (power of two) LDS ints by one wave.
+__device__ void wave_bitonic(int32_t* a, int t) {
+  const int lane = lane_id();
+  for (int k = 2; k <= t; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane; i < t; i += 64) {
+        int ixj = i ^ j;
+        if (ixj > i) {
+          int32_t u = a[i], v = a[ixj];
+          bool up = (i & k) == 0;
+          if ((u > v) == up) {
+            a[i] = v;
+            a[ixj] = u;
+          }
+        }
+      }
+      lds_fence();
+    }
+  }
+}
+
+template <bool WRITE>
+__global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+                                                     const int32_t* __restrict__ spptr,
+                                                     const int32_t* __restrict__ spcol, int64_t x_lo, int64_t x_hi,
+                                                     const int64_t* __restrict__ w, int32_t* __restrict__ cnt,
+                                                     const int64_t* __restrict__ off, int32_t* __restrict__ out) {
+  __shared__ int32_t tab_all[NT / 64][HT_SLOTS];
+  const int lane = lane_id();
+  const int wid = threadIdx.x >> 6;
+  int32_t* tab = tab_all[wid];
+  const int64_t gw = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
+  const int64_t nw = (int64_t(gridDim.x) * NT) >> 6;
+  const int64_t base_off = WRITE ? off[x_lo] : 0;
+
+  for (int64_t x = x_lo + gw; x < x_hi; x += nw) {
+    const int64_t wx = w[x - x_lo];
+    if (wx > LIGHT_MAX) continue;  // heavy row: other kernel
+    if (wx == 0) {
+      if (!WRITE && lane == 0) cnt[x] = 0;
+      continue;
+    }
+    int log2t = 6;
+    while ((1 << log2t) < 2 * wx) ++log2t;
+    const int t = 1 << log2t;
+    for (int i = lane; i < t; i += 64) tab[i] = EMPTY;
+    lds_fence();
+    int fresh = 0;
+    const int a = rptr[x], b = rptr[x + 1];
+    for (int c0 = a; c0 < b; c0 += 64) {
+      int j = c0 + lane;
+      int s0 = 0, len = 0;
+      if (j < b) {
+        int y = rcol[j];
+        s0 = spptr[y];
+        len = spptr[y + 1] - s0;
+      }
+      int incl = wave_incl_scan(len);
+      int excl = incl - len;
+      int total = __shfl(incl, 63, 64);
+      for (int t0 = 0; t0 < total; t0 += 64) {
+        int tt = t0 + lane;
+        int o = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          int e = __shfl(excl, o + step, 64);
+          if (e <= tt) o += step;
+        }
+        int os0 = __shfl(s0, o, 64);
+        int oex = __shfl(excl, o, 64);
+        if (tt < total) {
+          int32_t z = spcol[os0 + (tt - oex)];
+          uint32_t h = hash_slot(z, log2t);
+          while (true) {
+            int32_t old = atomicCAS(&tab[h], EMPTY, z);
+            if (old == EMPTY) {
+              ++fresh;
+              break;
+            }
+            if (old == z) break;
+            h = (h + 1) & uint32_t(t - 1);
+          }
+        }
+      }
+    }
+    int count = wave_sum(fresh);
+    if (!WRITE) {
+      if (lane == 0) cnt[x] = count;
+    } else {
+      lds_fence();
+      wave_bitonic(tab, t);
+      int32_t* dst = out + (off[x] - base_off);
+      for (int i = lane; i < count; i += 64) dst[i] = tab[i];
+    }
+    lds_fence();
+  }
+}
+
+template <bool WRITE>
+__global__ void __launch_bounds__(NT) k_sparse_heavy(const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
+                                                     const int32_t* __restrict__ spptr,
+                                                     const int32_t* __restrict__ spcol, int n_inst,
+                                                     const int32_t* __restrict__ x_base,
+                                                     const int32_t* __restrict__ z_base, int64_t x_lo, int64_t x_hi,
+                                                     const int64_t* __restrict__ w, int32_t* __restrict__ cnt,
+                                                     const int64_t* __restrict__ off, int32_t* __restrict__ out) {
+  __shared__ uint32_t bm[HB_WORDS];
+  __shared__ int red[NT / 64];
+  const int lane = lane_id();
+  const int wid = threadIdx.x >> 6;
+  const int64_t base_off = WRITE ? off[x_lo] : 0;
+
+  for (int64_t x = x_lo + blockIdx.x; x < x_hi; x += gridDim.x) {
+    if (w[x - x_lo] <= LIGHT_MAX) continue;
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(x_base, n_inst, int32_t(x));
+    const int32_t zlo = z_base[inst], zhi = z_base[inst + 1];
+    const int a = rptr[x], b = rptr[x + 1];
+    int64_t row_total = 0;
+    int64_t wpos = WRITE ? off[x] - base_off : 0;
+    for (int32_t wlo = zlo; wlo < zhi; wlo += HB_BITS) {
+      const int32_t whi = (zhi - wlo) > HB_BITS ? wlo + HB_BITS : zhi;
+      for (int i = threadIdx.x; i < HB_WORDS; i += NT) bm[i] = 0u;
+      __syncthreads();
+      for (int j = a + wid; j < b; j += NT / 64) {
+        int y = rcol[j];
+        int s0 = spptr[y], s1 = spptr[y + 1];
+        if (s0 == s1) continue;
+        int lo = int(lower_bound_dev<int32_t>(spcol, s0, s1, wlo));
+        int hi = int(lower_bound_dev<int32_t>(spcol, lo, s1, whi));
+        for (int p = lo + lane; p < hi; p += 64) {
+          int d = spcol[p] - wlo;
+          atomicOr(&bm[d >> 5], 1u << (d & 31));
+        }
+      }
+      __syncthreads();
+      // thread t owns words [t*64, t*64+64): contiguous, so prefix order is z order
+      constexpr int PER = HB_WORDS / NT;
+      int c = 0;
+      for (int k = 0; k < PER; ++k) c += __popc(bm[threadIdx.x * PER + k]);
+      int inc = wave_incl_scan(c);
+      if (lane == 63) red[wid] = inc;
+      __syncthreads();
+      int pre = 0, tot = 0;
+      for (int q = 0; q < NT / 64; ++q) {
+        int v = red[q];
+        if (q < wid) pre += v;
+        tot += v;
+      }
+      if (WRITE) {
+        int64_t pos = wpos + pre + (inc - c);
+        for (int k = 0; k < PER; ++k) {
+          uint32_t word = bm[threadIdx.x * PER + k];
+          while (word) {
+            int bit = __ffs(word) - 1;
+            word &= word - 1;
+            out[pos++] = wlo + (threadIdx.x * PER + k) * 32 + bit;
+          }
+        }
+      }
+      wpos += tot;
+      row_total += tot;
+      __syncthreads();
+    }
+    if (!WRITE && threadIdx.x == 0) cnt[x] = int32_t(row_total);
+  }
+}
+
+}  // namespace
+
+void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t* w, hipStream_t s) {
+  int64_t n = x_hi - x_lo;
+  if (n <= 0) return;
+  int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
+  hipLaunchKernelGGL(k_row_work, dim3(g), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, x_lo, x_hi, w);
+  JP_LAUNCH_CHECK();
+}
+
+void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int32_t* cnt, const int64_t* off,
+                int32_t* out, hipStream_t s) {
+  int64_t n = x_hi - x_lo;
+  if (n <= 0) return;
+  int gl = int(std::min<int64_t>((n + 3) / 4, 1 << 15));
+  int gh = int(std::min<int64_t>(n, 2048));
+  if (out) {
+    hipLaunchKernelGGL(k_sparse_light<true>, dim3(gl), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, x_lo, x_hi, w,
+                       cnt, off, out);
+    JP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sparse_heavy<true>, dim3(gh), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, c.n_inst,
+                       c.x_base, c.z_base, x_lo, x_hi, w, cnt, off, out);
+    JP_LAUNCH_CHECK();
+  } else {
+    hipLaunchKernelGGL(k_sparse_light<false>, dim3(gl), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, x_lo, x_hi,
+                       w, cnt, off, out);
+    JP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sparse_heavy<false>, dim3(gh), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, c.n_inst,
+                       c.x_base, c.z_base, x_lo, x_hi, w, cnt, off, out);
+    JP_LAUNCH_CHECK();
+  }
+}
+
+}  // namespace jp

@@ -1,0 +1,118 @@
+// Launchers of the Join-Project stages (mapping, partition, SparseBMM,
+// DenseEC, output).  All ids are global across the instances of a plan: the
+// ids of instance i occupy [base[i], base[i+1]) of their id space.
+#pragma once
+
+#include "pool.h"
+
+namespace jp {
+
+// Window of the dense-z bitmaps, in bits (DenseEC processes one window of a
+// row at a time).
+constexpr int DW_BITS = 32768;
+constexpr int DW_WORDS = DW_BITS / 32;
+
+// ------------------------------------------------------------ mapping
+// keys[i] = koff[inst(i)] + (v[i] - mn[inst(i)]); payload[i] = i (if non-null)
+void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff,
+               const int32_t* mn, uint32_t* keys, uint32_t* payload, hipStream_t s);
+// keysY[p] = key of sy[perm[p]]; payloadY[p] = E[p + 1] - 1 (id of sorted position p)
+void make_keys_perm(const int32_t* v, const uint32_t* perm, int64_t n, const int32_t* ebase, int n_inst,
+                    const int64_t* koff, const int32_t* mn, const int32_t* E, uint32_t* keys,
+                    uint32_t* payload, hipStream_t s);
+// flags[p] = 1 if sorted position p starts a run of equal keys
+void head_flags(const uint32_t* keys, int64_t n, int32_t* flags, hipStream_t s);
+// for each run head p: first[id] = p, vals[id] = original value of the key; first[n_id] = n
+void assign_ids(const uint32_t* keys, int64_t n, const int32_t* E, const int64_t* koff, const int32_t* mn,
+                int n_inst, int32_t* first, int32_t* vals, hipStream_t s);
+// out[i] = E[ebase[i]] for i in [0, n_inst]
+void gather_bases(const int32_t* E, const int32_t* ebase, int n_inst, int32_t* out, hipStream_t s);
+// semi-join of R on S.y: keep[g] = 1 and yid[g] = id iff ry[g] occurs among the y values of its instance
+void semijoin(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, const int32_t* vals_y,
+              const int32_t* y_base, int32_t* keep, int32_t* yid, hipStream_t s);
+// stable compaction of R to the kept tuples
+void compact_r(const int32_t* rx, const int32_t* yid, const int32_t* keep, const int32_t* E, int64_t n,
+               int32_t* out_x, int32_t* out_y, hipStream_t s);
+// m[i] = first[i + 1] - first[i]
+void run_lengths(const int32_t* first, int64_t n_id, int32_t* m, hipStream_t s);
+void histogram(const uint32_t* v, int64_t n, int32_t* h, hipStream_t s);
+// out_j[inst] += sum over y of dR[y] * dS[y]
+void out_j_per_inst(const int32_t* dR, const int32_t* dS, int64_t n_y, const int32_t* y_base, int n_inst,
+                    int64_t* out_j, hipStream_t s);
+
+// ---------------------------------------------------------- partition
+// flag[z] = m_z[z] > tau[inst(z)]
+void dense_flags(const int32_t* m_z, int64_t n_z, const int32_t* z_base, int n_inst, const int64_t* tau,
+                 int32_t* flag, hipStream_t s);
+// dz2z[Edz[z]] = z for dense z
+void dense_index(const int32_t* flag, const int32_t* Edz, int64_t n_z, int32_t* dz2z, hipStream_t s);
+// per S entry p (row Ey[p+1]-1): sparse flag (z not dense) and cold flag (z dense, y not hot)
+void entry_flags(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zflag,
+                 const int32_t* hot, int32_t* sp_flag, int32_t* cold_flag, hipStream_t s);
+// rowptr_out[y] = E[rowptr[y]] for y in [0, n_y]
+void remap_rowptr(const int32_t* rowptr, const int32_t* E, int64_t n_y, int32_t* out, hipStream_t s);
+// compaction of S entries with flag set; values z (sparse) or local dense index (cold)
+void compact_entries(const int32_t* scol, const int32_t* flag, const int32_t* E, int64_t n, const int32_t* Edz,
+                     const int32_t* z_base, const int32_t* zd_base, int n_inst, bool to_local_dense,
+                     int32_t* out, hipStream_t s);
+// per-instance histogram of floor(log2(d_dense(y))) over y with dR > 0 (32 buckets)
+void hot_histogram(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, const int32_t* y_base,
+                   int n_inst, int32_t* hist, hipStream_t s);
+// hot[y] = 1 iff dR[y] > 0 and d_dense(y) >= theta[inst(y)]
+void hot_flags(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, const int32_t* y_base,
+               int n_inst, const int64_t* theta, int32_t* hot, hipStream_t s);
+// hot row bit sets over the local dense index (one thread per S entry)
+void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* Ehot,
+                    const int32_t* y_base, const int32_t* z_base, const int32_t* zd_base, const int32_t* Edz,
+                    const int32_t* zflag, const int64_t* hb_off, const int32_t* row_words, int n_inst,
+                    uint32_t* hb, hipStream_t s);
+
+// ----------------------------------------------------------- row work
+struct RowCtx {
+  int n_inst;
+  const int32_t* x_base;   // [n_inst+1]
+  const int32_t* z_base;   // [n_inst+1]
+  const int32_t* zd_base;  // [n_inst+1]
+  const int32_t* rptr;     // [n_x+1]
+  const int32_t* rcol;     // y ids
+  // sparse part
+  const int32_t* spptr;    // [n_y+1]
+  const int32_t* spcol;    // z ids, ascending within a row
+  // dense part
+  const int32_t* hotrow;   // [n_y]: global hot row index or -1
+  const int32_t* Ehot;     // [n_y+1] exclusive scan of hot flags
+  const int32_t* y_base;   // [n_inst+1]
+  const int64_t* hb_off;   // [n_inst] word offset of the instance's hot rows
+  const int32_t* row_words;// [n_inst] words per hot row (multiple of DW_WORDS)
+  const uint32_t* hb;      // hot rows
+  const int32_t* cptr;     // [n_y+1] cold rows
+  const int32_t* ccol;     // local dense index, ascending within a row
+  const int32_t* dz2z;     // [n_z_dense] dense index -> z id
+};
+
+// per-row work of the sparse part: w[x] = sum over y in R[x] of |S_sparse[y]|
+void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t* w, hipStream_t s);
+// SparseBMM count (cnt != null) or write (out != null, offsets relative to off[x_lo])
+void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int32_t* cnt,
+                const int64_t* off, int32_t* out, hipStream_t s);
+// DenseEC count or write, bit-packed hot rows
+void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const int64_t* off, int32_t* out,
+              hipStream_t s);
+
+// ------------------------------------------------------------- output
+void add_counts(const int32_t* a, const int32_t* b, int64_t n, int32_t* out, hipStream_t s);
+// tot[3*i + {0,1,2}] = all, dense, sparse pairs of instance i
+void inst_totals(const int64_t* off_all, const int64_t* off_de, const int64_t* off_sp, const int32_t* x_base,
+                 int n_inst, int64_t* tot, hipStream_t s);
+// rows [lo, hi) covering global pair range [g0, g1) of an offset array
+void find_rows(const int64_t* off, int64_t x_begin, int64_t x_end, int64_t g0, int64_t g1, int64_t* out2,
+               hipStream_t s);
+// Merge per-row sorted z lists: la (na entries, row offsets off_a) and lb
+// (nb entries, offsets off_b; null for none) over rows [x_lo, x_hi); the pair
+// of global rank g = off_out[x] + rank-in-row is written to out[g - g0] when
+// g0 <= g < g1, as original values.
+void merge_write_n(int64_t x_lo, int64_t x_hi, const int64_t* off_a, const int64_t* off_b, const int64_t* off_out,
+                   const int32_t* la, const int32_t* lb, int64_t na, int64_t nb, const int32_t* vals_x,
+                   const int32_t* vals_z, int64_t g0, int64_t g1, int32_t* out_x, int32_t* out_z, hipStream_t s);
+
+}  // namespace jp
