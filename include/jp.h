@@ -60,15 +60,33 @@ typedef enum {
   JP_DENSE_MFMA = 2  /* 0/1 product on the INT8 matrix cores, int32 sums thresholded at > 0 */
 } jp_dense_kernel;
 
+/* jp_options.flags bits */
+#define JP_FLAG_TIMING 1 /* record HIP events around the kernels of jp_execute (see jp_plan_timings) */
+
 /* Options; an all-zero struct (or NULL) selects every default. */
 typedef struct {
   int32_t tau_mode;              /* jp_tau_mode */
   int32_t dense_kernel;          /* jp_dense_kernel */
   int64_t dense_threshold;       /* JP_TAU_FIXED: z dense iff m_z > value (-1: all dense, INT64_MAX: none) */
   int32_t k_hot_max;             /* cap on hot join keys per instance in DenseEC (0 = 256; max 1024) */
-  int32_t flags;                 /* reserved, must be 0 */
+  int32_t flags;                 /* JP_FLAG_* bits; others must be 0 */
   int64_t workspace_limit_bytes; /* 0 = no limit; exceeding it returns JP_ENOMEM */
 } jp_options;
+
+/* Kernel times of the last jp_execute (plan built with JP_FLAG_TIMING) and
+ * the algorithmic work those kernels did, for roofline accounting. */
+typedef struct {
+  float sparse_ms;            /* SparseBMM count kernels */
+  float dense_ms;             /* DenseEC count kernel */
+  float execute_ms;           /* all of jp_execute */
+  float pad_;
+  int64_t sparse_join_rows;   /* sum over x of |S_sparse[y]| for y in R[x] (join rows reaching sparse z) */
+  int64_t n_r_kept;           /* R tuples after the semi-join (CSR entries read) */
+  int64_t n_x;                /* x rows */
+  int64_t dense_hot_words;    /* sum over x of (hot keys of x) * (32-bit words of its dense z range) */
+  int64_t dense_row_words;    /* sum over x of the words of its dense z range (one popcount each) */
+  int64_t dense_cold_entries; /* cold dense S entries scattered, summed over x */
+} jp_timings;
 
 typedef struct {
   int64_t n_x, n_y, n_z;   /* distinct x (after the semi-join), y (of S), z */
@@ -121,6 +139,10 @@ jp_status jp_row_info(jp_plan* p, jp_part part, int32_t* x_values, int64_t* row_
 jp_status jp_dense_z(jp_plan* p, int32_t* z_values, hipStream_t stream);
 
 jp_status jp_plan_stats(const jp_plan* p, jp_stats* s);
+
+/* Kernel times and work counters of the last jp_execute; JP_ESTATE unless the
+ * plan was created with JP_FLAG_TIMING and executed.  Syncs. */
+jp_status jp_plan_timings(jp_plan* p, jp_timings* t, hipStream_t stream);
 void jp_plan_destroy(jp_plan* p); /* NULL-safe; frees all plan-owned device memory */
 
 const char* jp_last_error(void);

@@ -9,6 +9,7 @@ from .binding import (  # noqa: F401
     JP_DENSE_AUTO,
     JP_DENSE_BITS,
     JP_DENSE_MFMA,
+    JP_FLAG_TIMING,
     JP_PART_ALL,
     JP_PART_DENSE,
     JP_PART_SPARSE,
@@ -28,6 +29,7 @@ from .binding import (  # noqa: F401
     jp_plan_create,
     jp_plan_destroy,
     jp_plan_stats,
+    jp_plan_timings,
     jp_row_info,
     last_error,
     lib,

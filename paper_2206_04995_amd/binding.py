@@ -20,6 +20,7 @@ JP_OK, JP_EINVAL, JP_ENOMEM, JP_EHIP, JP_ESTATE, JP_ERANGE, JP_EBUSY = range(7)
 JP_PART_ALL, JP_PART_DENSE, JP_PART_SPARSE = 0, 1, 2
 JP_TAU_AUTO, JP_TAU_FIXED = 0, 1
 JP_DENSE_AUTO, JP_DENSE_BITS, JP_DENSE_MFMA = 0, 1, 2
+JP_FLAG_TIMING = 1
 INT64_MAX = 2 ** 63 - 1
 
 _STATUS = {0: "JP_OK", 1: "JP_EINVAL", 2: "JP_ENOMEM", 3: "JP_EHIP", 4: "JP_ESTATE", 5: "JP_ERANGE", 6: "JP_EBUSY"}
@@ -27,7 +28,7 @@ _STATUS = {0: "JP_OK", 1: "JP_EINVAL", 2: "JP_ENOMEM", 3: "JP_EHIP", 4: "JP_ESTA
 # every symbol include/jp.h declares
 EXPORTS = [
     "jp_plan_create", "jp_execute", "jp_count", "jp_materialize", "jp_row_info", "jp_dense_z",
-    "jp_plan_stats", "jp_plan_destroy", "jp_last_error",
+    "jp_plan_stats", "jp_plan_timings", "jp_plan_destroy", "jp_last_error",
     "jp_batch_create", "jp_batch_execute", "jp_batch_counts", "jp_batch_materialize", "jp_batch_stats",
     "jp_batch_destroy",
 ]
@@ -53,6 +54,13 @@ class jp_options(ctypes.Structure):
 class jp_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_x", "n_y", "n_z", "n_r_kept", "out_j", "tau", "n_z_dense", "k_hot", "footprint_bytes")]
+
+
+class jp_timings(ctypes.Structure):
+    _fields_ = [("sparse_ms", ctypes.c_float), ("dense_ms", ctypes.c_float), ("execute_ms", ctypes.c_float),
+                ("pad_", ctypes.c_float)] + [
+        (n, ctypes.c_int64) for n in ("sparse_join_rows", "n_r_kept", "n_x", "dense_hot_words", "dense_row_words",
+                                      "dense_cold_entries")]
 
 
 class jp_instance(ctypes.Structure):
@@ -82,6 +90,7 @@ def _load() -> ctypes.CDLL:
         "jp_row_info": (st, [vp, ctypes.c_int, i32p, i64p, vp]),
         "jp_dense_z": (st, [vp, i32p, vp]),
         "jp_plan_stats": (st, [vp, ctypes.POINTER(jp_stats)]),
+        "jp_plan_timings": (st, [vp, ctypes.POINTER(jp_timings), vp]),
         "jp_plan_destroy": (None, [vp]),
         "jp_last_error": (ctypes.c_char_p, []),
         "jp_batch_create": (st, [ctypes.POINTER(jp_instance), i32, ctypes.POINTER(jp_options), vp, ctypes.POINTER(vp)]),
@@ -133,13 +142,13 @@ def _ptr(t) -> int:
 
 
 def make_options(tau_mode: int = JP_TAU_AUTO, dense_threshold: int = 0, dense_kernel: int = JP_DENSE_AUTO,
-                 k_hot_max: int = 0, workspace_limit_bytes: int = 0) -> jp_options:
+                 k_hot_max: int = 0, workspace_limit_bytes: int = 0, flags: int = 0) -> jp_options:
     o = jp_options()
     o.tau_mode = tau_mode
     o.dense_kernel = dense_kernel
     o.dense_threshold = dense_threshold
     o.k_hot_max = k_hot_max
-    o.flags = 0
+    o.flags = flags
     o.workspace_limit_bytes = workspace_limit_bytes
     return o
 
@@ -198,6 +207,13 @@ def jp_plan_stats(plan: int) -> Dict[str, int]:
     s = jp_stats()
     _check(lib.jp_plan_stats(plan, ctypes.byref(s)))
     return _stats_dict(s)
+
+
+def jp_plan_timings(plan: int, stream=None) -> Dict[str, float]:
+    t = jp_timings()
+    _check(lib.jp_plan_timings(plan, ctypes.byref(t), _stream(stream)))
+    return {name: (float(getattr(t, name)) if name.endswith("_ms") else int(getattr(t, name)))
+            for name, _ in jp_timings._fields_ if name != "pad_"}
 
 
 def jp_plan_destroy(plan: int):

@@ -3,18 +3,21 @@
 //
 // The paper tests one (x, z) pair at a time, either by a SIMD AND of the two
 // |Y|-bit bitmaps or by probing Bitmap_z at each y of x, stopping at the
-// first hit.  Here one wavefront builds a whole window of the x row at once:
+// first hit.  Here one wavefront builds a whole window of an x row at once:
 // the row's "hot" join keys (y with many dense S entries) are kept as bit rows
 // over the dense z index and are ORed word by word (32 z per lane-op), and the
 // remaining "cold" keys are scattered from their z-sorted CSR rows into an
 // LDS copy of the window.  The window is then popcounted (count mode) or
 // written out in z order (write mode).
 //
-// Rows run in blocks of 16 per wavefront; all rows of a block walk the
-// windows in the same order so the hot rows' window slices are reused from
-// the caches, and each (row, cold y) keeps a cursor into its cold row across
-// windows, so a cold entry is read once.
+// A workgroup owns 64 consecutive rows and walks the windows in order.  The
+// window slices of the T_STAGE hot keys shared by the most rows are staged in
+// LDS once per window for all 64 rows; rarer hot keys are read from the
+// caches.  Per-entry codes (hot rank / cold key) avoid dependent lookups, and
+// a per-window table of cold segment bounds lets the 64 lanes of a wave split
+// a row's cold entries evenly.
 #include "common.h"
+#include "prim.h"
 #include "stages.h"
 
 namespace jp {
@@ -23,8 +26,10 @@ namespace {
 constexpr int NT = 256;
 constexpr int WAVES = NT / 64;
 constexpr int RPW = 16;                   // rows per wavefront
-constexpr int WPL = DW_WORDS / 64;        // words of a window per lane (16)
-constexpr int Q = WPL / 4;                // uint4 per lane (4)
+constexpr int RB = WAVES * RPW;           // rows per workgroup
+constexpr int WPL = DW_WORDS / 64;        // words of a window per lane
+constexpr int Q = WPL / 4;                // uint4 per lane
+constexpr int QW = DW_WORDS / 4;          // uint4 per window slice
 
 __device__ __forceinline__ void lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -33,21 +38,37 @@ __device__ __forceinline__ void lds_fence() {
 
 __device__ __forceinline__ int popc4(uint4 v) { return __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w); }
 
+__device__ __forceinline__ void or4(uint4& a, const uint4 b) {
+  a.x |= b.x;
+  a.y |= b.y;
+  a.z |= b.z;
+  a.w |= b.w;
+}
+
 template <bool WRITE>
 __global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64_t x_hi, int32_t* __restrict__ cnt,
                                                    const int64_t* __restrict__ off, int32_t* __restrict__ out) {
-  __shared__ uint4 rowbuf_all[WAVES][DW_WORDS / 4];
-  __shared__ int32_t curs_all[WAVES][RPW][64];
+  __shared__ uint4 stage[T_STAGE][QW];
+  __shared__ uint4 rowbuf_all[WAVES][QW];
+  __shared__ int s_maxwin[WAVES];
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
   uint32_t* rowbuf = reinterpret_cast<uint32_t*>(rowbuf_all[wid]);
   uint4* rowbuf4 = rowbuf_all[wid];
-  int32_t(*curs)[64] = curs_all[wid];
 
-  const int64_t r0 = x_lo + (int64_t(blockIdx.x) * WAVES + wid) * RPW;
-  if (r0 >= x_hi) return;
-  const int nrows = int((x_hi - r0) < RPW ? (x_hi - r0) : RPW);
+  const int64_t rb0 = x_lo + int64_t(blockIdx.x) * RB;
+  const int64_t r0 = rb0 + int64_t(wid) * RPW;
+  const int nrows = r0 >= x_hi ? 0 : int((x_hi - r0) < RPW ? (x_hi - r0) : RPW);
   const int64_t base_off = WRITE ? off[x_lo] : 0;
+
+  // instance of the block's first row: its hottest keys are staged in LDS
+  const int inst0 = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, int32_t(rb0));
+  const int zd0 = c.zd_base[inst0 + 1] - c.zd_base[inst0];
+  const int nwin0 = (zd0 + DW_BITS - 1) / DW_BITS;
+  const int k0 = c.Ehot[c.y_base[inst0 + 1]] - c.Ehot[c.y_base[inst0]];
+  const int t_eff = k0 < T_STAGE ? k0 : T_STAGE;
+  const uint32_t* hb0 = c.hb + c.hb_off[inst0];
+  const int64_t rw0 = c.row_words[inst0];
 
   // lane r < nrows describes row r0 + r
   int my_inst = 0, my_nwin = 0;
@@ -59,32 +80,30 @@ __global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64
     my_nwin = (zd + DW_BITS - 1) / DW_BITS;
     if (WRITE) my_acc = off[x] - base_off;
   }
-  const int maxwin = wave_max(my_nwin);
-  if (maxwin == 0) {
-    if (!WRITE && lane < nrows) cnt[r0 + lane] = 0;
-    return;
-  }
-
-  // cursors of the first 64 join keys of each row into their cold rows
-  for (int r = 0; r < nrows; ++r) {
-    const int64_t x = r0 + r;
-    const int a = c.rptr[x], b = c.rptr[x + 1];
-    int cur = -1;
-    if (a + lane < b) {
-      int y = c.rcol[a + lane];
-      if (c.hotrow[y] < 0 && c.cptr[y + 1] > c.cptr[y]) cur = c.cptr[y];
-    }
-    curs[r][lane] = cur;
-  }
-  lds_fence();
+  const int wmax = wave_max(my_nwin);
+  if (lane == 0) s_maxwin[wid] = wmax;
+  __syncthreads();
+  int maxwin = 0;
+#pragma unroll
+  for (int i = 0; i < WAVES; ++i) maxwin = s_maxwin[i] > maxwin ? s_maxwin[i] : maxwin;
 
   for (int w = 0; w < maxwin; ++w) {
     const int32_t wstart = w * DW_BITS;
     const int32_t wend = wstart + DW_BITS;
+    __syncthreads();
+    if (w < nwin0) {
+      for (int i = threadIdx.x; i < t_eff * QW; i += NT) {
+        const int k = i / QW, q = i - k * QW;
+        stage[k][q] = reinterpret_cast<const uint4*>(hb0 + int64_t(k) * rw0 + int64_t(w) * DW_WORDS)[q];
+      }
+    }
+    __syncthreads();
+
     for (int r = 0; r < nrows; ++r) {
       const int nwin_r = __shfl(my_nwin, r, 64);
       if (w >= nwin_r) continue;
       const int inst = __shfl(my_inst, r, 64);
+      const bool staged = inst == inst0;
       const int64_t x = r0 + r;
       const int a = c.rptr[x], b = c.rptr[x + 1];
       const uint32_t* hbase = c.hb + c.hb_off[inst] + int64_t(w) * DW_WORDS;
@@ -96,27 +115,20 @@ __global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64
       bool any_cold = false;
       for (int c0 = a; c0 < b; c0 += 64) {
         const int j = c0 + lane;
-        int y = -1, hr = -1;
-        bool cold = false;
-        if (j < b) {
-          y = c.rcol[j];
-          hr = c.hotrow[y];
-          cold = hr < 0 && c.cptr[y + 1] > c.cptr[y];
-        }
-        uint64_t hm = ballot(hr >= 0);
-        any_cold |= ballot(cold) != 0;
+        const int code = j < b ? c.rcode[j] : -1;
+        uint64_t hm = ballot(code >= 0);
+        any_cold |= ballot(code <= -2) != 0;
         while (hm) {
           const int l = __ffsll((unsigned long long)hm) - 1;
           hm &= hm - 1;
-          const int k = __shfl(hr, l, 64);
-          const uint4* src = reinterpret_cast<const uint4*>(hbase + int64_t(k) * rw);
+          const int k = __shfl(code, l, 64);
+          if (staged && k < t_eff) {
 #pragma unroll
-          for (int q = 0; q < Q; ++q) {
-            uint4 v = src[q * 64 + lane];
-            acc[q].x |= v.x;
-            acc[q].y |= v.y;
-            acc[q].z |= v.z;
-            acc[q].w |= v.w;
+            for (int q = 0; q < Q; ++q) or4(acc[q], stage[k][q * 64 + lane]);
+          } else {
+            const uint4* src = reinterpret_cast<const uint4*>(hbase + int64_t(k) * rw);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) or4(acc[q], src[q * 64 + lane]);
           }
         }
       }
@@ -124,30 +136,34 @@ __global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64
 #pragma unroll
         for (int q = 0; q < Q; ++q) rowbuf4[q * 64 + lane] = acc[q];
         lds_fence();
-        int ci = 0;
-        for (int c0 = a; c0 < b; c0 += 64, ++ci) {
+        const int yb = c.y_base[inst];
+        const int ny = c.y_base[inst + 1] - yb;
+        const int32_t* cwin = c.cw + c.cw_off[inst] + int64_t(w) * ny;
+        for (int c0 = a; c0 < b; c0 += 64) {
           const int j = c0 + lane;
-          if (j < b) {
-            const int y = c.rcol[j];
-            if (c.hotrow[y] < 0) {
-              const int c1 = c.cptr[y + 1];
-              int cur;
-              if (ci == 0) {
-                cur = curs[r][lane];
-              } else {
-                const int cs = c.cptr[y];
-                cur = cs < c1 ? int(lower_bound_dev<int32_t>(c.ccol, cs, c1, wstart)) : -1;
-              }
-              if (cur >= 0) {
-                while (cur < c1) {
-                  const int32_t d = c.ccol[cur];
-                  if (d >= wend) break;
-                  const int dl = d - wstart;
-                  atomicOr(&rowbuf[dl >> 5], 1u << (dl & 31));
-                  ++cur;
-                }
-                if (ci == 0) curs[r][lane] = cur < c1 ? cur : -1;
-              }
+          const int code = j < b ? c.rcode[j] : -1;
+          int s0 = 0, len = 0;
+          if (code <= -2) {
+            const int yl = (-2 - code) - yb;
+            s0 = cwin[yl];
+            len = cwin[int64_t(ny) + yl] - s0;
+          }
+          const int incl = wave_incl_scan(len);
+          const int excl = incl - len;
+          const int total = __shfl(incl, 63, 64);
+          for (int t0 = 0; t0 < total; t0 += 64) {
+            const int tt = t0 + lane;
+            int o = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+              const int e = __shfl(excl, o + step, 64);
+              if (e <= tt) o += step;
+            }
+            const int os0 = __shfl(s0, o, 64);
+            const int oex = __shfl(excl, o, 64);
+            if (tt < total) {
+              const int dl = c.ccol[os0 + (tt - oex)] - wstart;
+              atomicOr(&rowbuf[dl >> 5], 1u << (dl & 31));
             }
           }
         }
@@ -164,7 +180,7 @@ __global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64
         const int tot = wave_sum(pc);
         if (lane == r) my_acc += tot;
       } else {
-        int64_t pos0 = __shfl(my_acc, r, 64);
+        const int64_t pos0 = __shfl(my_acc, r, 64);
         int64_t qbase = 0;
         const int32_t dzb = c.zd_base[inst];
 #pragma unroll
@@ -193,14 +209,61 @@ __global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64
   if (!WRITE && lane < nrows) cnt[r0 + lane] = int32_t(my_acc);
 }
 
+// Algorithmic work of the count kernels (for roofline accounting):
+// out[0] = sum_x hot(x) * words(x), out[1] = sum_x words(x),
+// out[2] = sum_x cold dense entries of x, out[3] = sum_x w[x]
+__global__ void k_work_stats(RowCtx c, int64_t x_lo, int64_t x_hi, const int64_t* __restrict__ w,
+                             unsigned long long* __restrict__ out) {
+  int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (int64_t b = x_lo + int64_t(blockIdx.x) * blockDim.x; b < x_hi; b += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t x = b + threadIdx.x;
+    if (x < x_hi) {
+      int inst = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, int32_t(x));
+      int zd = c.zd_base[inst + 1] - c.zd_base[inst];
+      int64_t rw = zd > 0 ? int64_t((zd + DW_BITS - 1) / DW_BITS) * DW_WORDS : 0;
+      int64_t h = 0, cold = 0;
+      if (rw > 0) {
+        for (int j = c.rptr[x]; j < c.rptr[x + 1]; ++j) {
+          int code = c.rcode[j];
+          if (code >= 0) ++h;
+          else if (code <= -2) cold += c.cptr[-2 - code + 1] - c.cptr[-2 - code];
+        }
+      }
+      a0 += h * rw;
+      a1 += rw;
+      a2 += cold;
+      a3 += w[x - x_lo];
+    }
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  a3 = wave_sum(a3);
+  if (lane_id() == 0) {
+    atomicAdd(&out[0], (unsigned long long)a0);
+    atomicAdd(&out[1], (unsigned long long)a1);
+    atomicAdd(&out[2], (unsigned long long)a2);
+    atomicAdd(&out[3], (unsigned long long)a3);
+  }
+}
+
 }  // namespace
+
+void work_stats(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int64_t* out4, hipStream_t s) {
+  fill_i64(out4, 4, 0, s);
+  int64_t n = x_hi - x_lo;
+  if (n <= 0) return;
+  int g = int(std::min<int64_t>((n + NT - 1) / NT, 4096));
+  hipLaunchKernelGGL(k_work_stats, dim3(g), dim3(NT), 0, s, c, x_lo, x_hi, w,
+                     reinterpret_cast<unsigned long long*>(out4));
+  JP_LAUNCH_CHECK();
+}
 
 void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const int64_t* off, int32_t* out,
               hipStream_t s) {
   int64_t n = x_hi - x_lo;
   if (n <= 0) return;
-  int64_t rows_per_block = int64_t(WAVES) * RPW;
-  int g = int((n + rows_per_block - 1) / rows_per_block);
+  int g = int((n + RB - 1) / RB);
   if (out)
     hipLaunchKernelGGL(k_dense_bits<true>, dim3(g), dim3(NT), 0, s, c, x_lo, x_hi, cnt, off, out);
   else

@@ -99,16 +99,57 @@ __global__ void k_run_lengths(const int32_t* __restrict__ first, int64_t n_id, i
   GRID_STRIDE(i, n_id) { m[i] = first[i + 1] - first[i]; }
 }
 
-__global__ void k_histogram(const uint32_t* __restrict__ v, int64_t n, int32_t* __restrict__ h) {
-  GRID_STRIDE(i, n) { atomicAdd(&h[v[i]], 1); }
+// Histogram with per-block aggregation in an LDS hash table, so frequent keys
+// (skewed join keys) cost one global atomic per block instead of one per
+// element; keys that do not find a slot go straight to global memory.
+constexpr int HG_SLOTS = 4096;
+constexpr int HG_PER_BLOCK = 1 << 14;
+
+__global__ void __launch_bounds__(NT) k_histogram(const uint32_t* __restrict__ v, int64_t n, int32_t* __restrict__ h) {
+  __shared__ uint32_t key[HG_SLOTS];
+  __shared__ int32_t cnt[HG_SLOTS];
+  for (int i = threadIdx.x; i < HG_SLOTS; i += NT) {
+    key[i] = 0xFFFFFFFFu;
+    cnt[i] = 0;
+  }
+  __syncthreads();
+  const int64_t b0 = int64_t(blockIdx.x) * HG_PER_BLOCK;
+  const int64_t b1 = b0 + HG_PER_BLOCK < n ? b0 + HG_PER_BLOCK : n;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += NT) {
+    const uint32_t k = v[i];
+    uint32_t s = (k * 0x9E3779B1u) >> 20;  // 12-bit slot
+    bool done = false;
+    for (int probe = 0; probe < 8 && !done; ++probe) {
+      uint32_t old = atomicCAS(&key[s], 0xFFFFFFFFu, k);
+      if (old == 0xFFFFFFFFu || old == k) {
+        atomicAdd(&cnt[s], 1);
+        done = true;
+      } else {
+        s = (s + 1) & (HG_SLOTS - 1);
+      }
+    }
+    if (!done) atomicAdd(&h[k], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < HG_SLOTS; i += NT)
+    if (cnt[i]) atomicAdd(&h[key[i]], cnt[i]);
 }
 
 __global__ void k_out_j(const int32_t* __restrict__ dR, const int32_t* __restrict__ dS, int64_t n_y,
                         const int32_t* __restrict__ y_base, int n_inst, int64_t* __restrict__ out_j) {
-  GRID_STRIDE(y, n_y) {
-    int64_t prod = int64_t(dR[y]) * int64_t(dS[y]);
-    if (prod) {
-      int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+  for (int64_t b = int64_t(blockIdx.x) * blockDim.x; b < n_y; b += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t y = b + threadIdx.x;
+    int64_t prod = 0;
+    int inst = 0;
+    if (y < n_y) {
+      prod = int64_t(dR[y]) * int64_t(dS[y]);
+      inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+    }
+    const int i0 = __shfl(inst, 0, 64);
+    if (ballot(y < n_y && inst != i0) == 0) {
+      const int64_t s = wave_sum(prod);
+      if (lane_id() == 0 && s) atomicAdd((unsigned long long*)&out_j[i0], (unsigned long long)s);
+    } else if (prod) {
       atomicAdd((unsigned long long*)&out_j[inst], (unsigned long long)prod);
     }
   }
@@ -175,7 +216,8 @@ void run_lengths(const int32_t* first, int64_t n_id, int32_t* m, hipStream_t s) 
 
 void histogram(const uint32_t* v, int64_t n, int32_t* h, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_histogram, dim3(grid(n)), dim3(NT), 0, s, v, n, h);
+  const int blocks = int((n + HG_PER_BLOCK - 1) / HG_PER_BLOCK);
+  hipLaunchKernelGGL(k_histogram, dim3(blocks), dim3(NT), 0, s, v, n, h);
   JP_LAUNCH_CHECK();
 }
 

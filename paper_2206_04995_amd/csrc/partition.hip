@@ -79,13 +79,22 @@ __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 __global__ void k_hot_histogram(const int32_t* __restrict__ sptr, const int32_t* __restrict__ spptr,
                                 const int32_t* __restrict__ dR, int64_t n_y, const int32_t* __restrict__ y_base,
                                 int n_inst, int32_t* __restrict__ hist) {
+  __shared__ int32_t loc[32];  // one instance: block-local buckets
+  if (threadIdx.x < 32) loc[threadIdx.x] = 0;
+  __syncthreads();
   GRID_STRIDE(y, n_y) {
     int dd = (sptr[y + 1] - sptr[y]) - (spptr[y + 1] - spptr[y]);
     if (dd > 0 && dR[y] > 0) {
-      int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
-      atomicAdd(&hist[inst * 32 + ilog2(dd)], 1);
+      if (n_inst == 1) {
+        atomicAdd(&loc[ilog2(dd)], 1);
+      } else {
+        int inst = find_inst<int32_t>(y_base, n_inst, int32_t(y));
+        atomicAdd(&hist[inst * 32 + ilog2(dd)], 1);
+      }
     }
   }
+  __syncthreads();
+  if (n_inst == 1 && threadIdx.x < 32 && loc[threadIdx.x]) atomicAdd(&hist[threadIdx.x], loc[threadIdx.x]);
 }
 
 __global__ void k_hot_flags(const int32_t* __restrict__ sptr, const int32_t* __restrict__ spptr,
@@ -100,7 +109,7 @@ __global__ void k_hot_flags(const int32_t* __restrict__ sptr, const int32_t* __r
 
 // one thread per S entry: set the bit of every dense z of a hot row
 __global__ void k_build_hot_bits(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol, int64_t n,
-                                 const int32_t* __restrict__ hot, const int32_t* __restrict__ Ehot,
+                                 const int32_t* __restrict__ hot, const int32_t* __restrict__ hotrow,
                                  const int32_t* __restrict__ y_base, const int32_t* __restrict__ z_base,
                                  const int32_t* __restrict__ zd_base, const int32_t* __restrict__ Edz,
                                  const int32_t* __restrict__ zflag, const int64_t* __restrict__ hb_off,
@@ -110,10 +119,86 @@ __global__ void k_build_hot_bits(const int32_t* __restrict__ Ey, const int32_t* 
     int32_t z = scol[p];
     if (!hot[y] || !zflag[z]) continue;
     int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
-    int64_t k = Ehot[y] - Ehot[y_base[inst]];
+    int64_t k = hotrow[y];
     uint32_t* row = hb + hb_off[inst] + k * row_words[inst];
     int dl = Edz[z] - zd_base[inst];
     atomicOr(&row[dl >> 5], 1u << (dl & 31));
+  }
+}
+
+__global__ void k_hot_list(const int32_t* __restrict__ hot, const int32_t* __restrict__ Ehot, int64_t n_y,
+                           int32_t* __restrict__ hotlist) {
+  GRID_STRIDE(y, n_y) {
+    if (hot[y]) hotlist[Ehot[y]] = int32_t(y);
+  }
+}
+
+// rank of each hot y among its instance's hot keys: more rows first, then y order
+__global__ void k_hot_rank(const int32_t* __restrict__ hotlist, int64_t n_hot, const int32_t* __restrict__ Ehot,
+                           const int32_t* __restrict__ y_base, int n_inst, const int32_t* __restrict__ dR,
+                           int32_t* __restrict__ hotrow) {
+  GRID_STRIDE(i, n_hot) {
+    const int32_t y = hotlist[i];
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+    const int lo = Ehot[y_base[inst]], hi = Ehot[y_base[inst + 1]];
+    const int32_t d = dR[y];
+    int rank = 0;
+    for (int j = lo; j < hi; ++j) {
+      const int32_t y2 = hotlist[j];
+      const int32_t d2 = dR[y2];
+      rank += (d2 > d || (d2 == d && y2 < y)) ? 1 : 0;
+    }
+    hotrow[y] = rank;
+  }
+}
+
+__global__ void k_row_codes(const int32_t* __restrict__ rcol, int64_t n, const int32_t* __restrict__ hotrow,
+                            const int32_t* __restrict__ cptr, int32_t* __restrict__ rcode) {
+  GRID_STRIDE(j, n) {
+    const int32_t y = rcol[j];
+    const int32_t h = hotrow[y];
+    rcode[j] = h >= 0 ? h : (cptr[y + 1] > cptr[y] ? -2 - y : -1);
+  }
+}
+
+// every table slot is written exactly once: by the first entry of y at or
+// after the window start (entries), or by the row end (tail)
+__global__ void k_cold_win_entries(const int32_t* __restrict__ cptr, const int32_t* __restrict__ ccol, int64_t n_y,
+                                   int64_t n_cold, const int32_t* __restrict__ y_base, int n_inst,
+                                   const int64_t* __restrict__ cw_off, int32_t* __restrict__ cw) {
+  GRID_STRIDE(p, n_cold) {
+    // row of entry p: largest y with cptr[y] <= p
+    int64_t lo = 0, hi = n_y;
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if (cptr[mid] <= p) lo = mid;
+      else hi = mid;
+    }
+    const int32_t y = int32_t(lo);
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+    const int ny = y_base[inst + 1] - y_base[inst];
+    const int yl = y - y_base[inst];
+    const int wp = ccol[p] / DW_BITS;
+    const int wprev = p == cptr[y] ? -1 : ccol[p - 1] / DW_BITS;
+    int32_t* t = cw + cw_off[inst] + yl;
+    for (int w = wprev + 1; w <= wp; ++w) t[int64_t(w) * ny] = int32_t(p);
+  }
+}
+
+__global__ void k_cold_win_tail(const int32_t* __restrict__ cptr, const int32_t* __restrict__ ccol, int64_t n_y,
+                                const int32_t* __restrict__ y_base, const int32_t* __restrict__ zd_base, int n_inst,
+                                const int64_t* __restrict__ cw_off, int32_t* __restrict__ cw) {
+  GRID_STRIDE(y, n_y) {
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+    const int zd = zd_base[inst + 1] - zd_base[inst];
+    if (zd <= 0) continue;
+    const int nwin = (zd + DW_BITS - 1) / DW_BITS;
+    const int ny = y_base[inst + 1] - y_base[inst];
+    const int yl = int(y) - y_base[inst];
+    const int a = cptr[y], b = cptr[y + 1];
+    const int wlast = b > a ? ccol[b - 1] / DW_BITS : -1;
+    int32_t* t = cw + cw_off[inst] + yl;
+    for (int w = wlast + 1; w <= nwin; ++w) t[int64_t(w) * ny] = b;
   }
 }
 
@@ -168,13 +253,43 @@ void hot_flags(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int
   JP_LAUNCH_CHECK();
 }
 
-void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* Ehot,
+void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* hotrow,
                     const int32_t* y_base, const int32_t* z_base, const int32_t* zd_base, const int32_t* Edz,
                     const int32_t* zflag, const int64_t* hb_off, const int32_t* row_words, int n_inst, uint32_t* hb,
                     hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_build_hot_bits, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, hot, Ehot, y_base, z_base,
+  hipLaunchKernelGGL(k_build_hot_bits, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, hot, hotrow, y_base, z_base,
                      zd_base, Edz, zflag, hb_off, row_words, n_inst, hb);
+  JP_LAUNCH_CHECK();
+}
+
+void hot_rank(const int32_t* hot, const int32_t* Ehot, int64_t n_y, int64_t n_hot, const int32_t* y_base, int n_inst,
+              const int32_t* dR, int32_t* hotlist, int32_t* hotrow, hipStream_t s) {
+  fill_i32(hotrow, n_y, -1, s);
+  if (n_y <= 0 || n_hot <= 0) return;
+  hipLaunchKernelGGL(k_hot_list, dim3(grid(n_y)), dim3(NT), 0, s, hot, Ehot, n_y, hotlist);
+  JP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_hot_rank, dim3(grid(n_hot)), dim3(NT), 0, s, hotlist, n_hot, Ehot, y_base, n_inst, dR, hotrow);
+  JP_LAUNCH_CHECK();
+}
+
+void row_codes(const int32_t* rcol, int64_t n, const int32_t* hotrow, const int32_t* cptr, int32_t* rcode,
+               hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_row_codes, dim3(grid(n)), dim3(NT), 0, s, rcol, n, hotrow, cptr, rcode);
+  JP_LAUNCH_CHECK();
+}
+
+void cold_windows(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t n_cold, const int32_t* y_base,
+                  const int32_t* zd_base, int n_inst, const int64_t* cw_off, int32_t* cw, hipStream_t s) {
+  if (n_y <= 0) return;
+  if (n_cold > 0) {
+    hipLaunchKernelGGL(k_cold_win_entries, dim3(grid(n_cold)), dim3(NT), 0, s, cptr, ccol, n_y, n_cold, y_base, n_inst,
+                       cw_off, cw);
+    JP_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_cold_win_tail, dim3(grid(n_y)), dim3(NT), 0, s, cptr, ccol, n_y, y_base, zd_base, n_inst, cw_off,
+                     cw);
   JP_LAUNCH_CHECK();
 }
 

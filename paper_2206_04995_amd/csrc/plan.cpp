@@ -82,18 +82,6 @@ __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int3
   }
 }
 
-__global__ void k_hotrow(const int32_t* __restrict__ hot, const int32_t* __restrict__ Ehot, int64_t n_y,
-                         const int32_t* __restrict__ y_base, int n_inst, int32_t* __restrict__ hotrow) {
-  for (int64_t y = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; y < n_y; y += int64_t(gridDim.x) * blockDim.x) {
-    if (hot[y]) {
-      int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
-      hotrow[y] = Ehot[y] - Ehot[y_base[inst]];
-    } else {
-      hotrow[y] = -1;
-    }
-  }
-}
-
 __global__ void k_slice_info(const int64_t* __restrict__ off_de, const int64_t* __restrict__ off_sp,
                              const int64_t* __restrict__ rows, int64_t* __restrict__ info) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -406,14 +394,14 @@ void Plan::partition(hipStream_t s) {
   Ehot = A.alloc<int32_t>(NY + 1, s);
   scan_excl_i32(hot, Ehot, NY, s, T);
   hotrow = A.alloc<int32_t>(NYa, s);
-  if (NY) {
-    hipLaunchKernelGGL(k_hotrow, dim3(grid_of(NY)), dim3(256), 0, s, hot, Ehot, NY, y_base, n, hotrow);
-    JP_LAUNCH_CHECK();
-  }
+  int64_t n_hot = 0;
+  for (int i = 0; i < n; ++i) n_hot += h_K[i];
+  int32_t* hotlist = T.alloc<int32_t>(std::max<int64_t>(n_hot, 1), s);
+  hot_rank(hot, Ehot, NY, n_hot, y_base, n, dR, hotlist, hotrow, s);
   NHb = hb_words;
   hb = A.alloc<uint32_t>(std::max<int64_t>(hb_words, 4), s);
   fill_u32(hb, hb_words, 0u, s);
-  build_hot_bits(Ey, scol, NS, hot, Ehot, y_base, z_base, zd_base, Edz, zflag, d_hboff, d_roww, n, hb, s);
+  build_hot_bits(Ey, scol, NS, hot, hotrow, y_base, z_base, zd_base, Edz, zflag, d_hboff, d_roww, n, hb, s);
 
   // cold dense entries: CSR by y over the local dense index
   entry_flags(Ey, scol, NS, zflag, hot, nullptr, fl, s);
@@ -427,6 +415,21 @@ void Plan::partition(hipStream_t s) {
   NCold = ncold;
   ccol = A.alloc<int32_t>(std::max<int64_t>(NCold, 1), s);
   compact_entries(scol, fl, Ec, NS, Edz, z_base, zd_base, n, true, ccol, s);
+
+  // per-window bounds of the cold rows, and per-entry codes of R's CSR
+  h_cwoff.assign(n, 0);
+  int64_t cw_total = 0;
+  for (int i = 0; i < n; ++i) {
+    h_cwoff[i] = cw_total;
+    int64_t zd = h_zdbase[i + 1] - h_zdbase[i];
+    if (zd > 0) cw_total += int64_t(h_ybase[i + 1] - h_ybase[i]) * ((zd + DW_BITS - 1) / DW_BITS + 1);
+  }
+  d_cwoff = A.alloc<int64_t>(n, s);
+  h2d(d_cwoff, h_cwoff.data(), n, s);
+  cw = A.alloc<int32_t>(std::max<int64_t>(cw_total, 1), s);
+  if (cw_total > 0) cold_windows(cptr, ccol, NY, NCold, y_base, zd_base, n, d_cwoff, cw, s);
+  rcode = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
+  row_codes(rcol, NRp, hotrow, cptr, rcode, s);
   T.release(s);
 }
 
@@ -443,6 +446,9 @@ RowCtx Plan::ctx() const {
   c.hotrow = hotrow;
   c.Ehot = Ehot;
   c.y_base = y_base;
+  c.rcode = rcode;
+  c.cw = cw;
+  c.cw_off = d_cwoff;
   c.hb_off = d_hboff;
   c.row_words = d_roww;
   c.hb = hb;
@@ -467,19 +473,48 @@ void Plan::execute(hipStream_t s) {
     off_sp = A.alloc<int64_t>(NX + 1, s);
     tot = A.alloc<int64_t>(3 * int64_t(n_inst), s);
   }
+  const bool timing = (opt.flags & JP_FLAG_TIMING) != 0;
+  if (timing && !ev[0]) {
+    for (auto& e : ev) JP_HIP(hipEventCreate(&e));
+    d_work = A.alloc<int64_t>(4, s);
+  }
   RowCtx c = ctx();
+  if (timing) JP_HIP(hipEventRecord(ev[0], s));
   sparse_row_work(c, 0, NX, w, s);
   if (NSp > 0) sparse_bmm(c, 0, NX, w, cnt_sp, nullptr, nullptr, s);
   else fill_i32(cnt_sp, NX, 0, s);
+  if (timing) JP_HIP(hipEventRecord(ev[1], s));
   if (NZd > 0) dense_ec(c, 0, NX, cnt_de, nullptr, nullptr, s);
   else fill_i32(cnt_de, NX, 0, s);
+  if (timing) JP_HIP(hipEventRecord(ev[2], s));
   add_counts(cnt_sp, cnt_de, NX, cnt_all, s);
   scan_excl_i32_to_i64(cnt_all, off_all, NX, s, A);
   scan_excl_i32_to_i64(cnt_de, off_de, NX, s, A);
   scan_excl_i32_to_i64(cnt_sp, off_sp, NX, s, A);
   inst_totals(off_all, off_de, off_sp, x_base, n_inst, tot, s);
+  if (timing) {
+    JP_HIP(hipEventRecord(ev[3], s));
+    work_stats(c, 0, NX, w, d_work, s);
+  }
   executed = true;
   h_tot.clear();
+}
+
+void Plan::timings(jp_timings* t, hipStream_t s) {
+  if (!executed || !ev[0]) throw Error(JP_ESTATE, "timings need JP_FLAG_TIMING and a jp_execute");
+  int64_t wk[4];
+  d2h(wk, d_work, 4, s);
+  sync(s);
+  JP_HIP(hipEventElapsedTime(&t->sparse_ms, ev[0], ev[1]));
+  JP_HIP(hipEventElapsedTime(&t->dense_ms, ev[1], ev[2]));
+  JP_HIP(hipEventElapsedTime(&t->execute_ms, ev[0], ev[3]));
+  t->pad_ = 0.f;
+  t->sparse_join_rows = wk[3];
+  t->n_r_kept = NRp;
+  t->n_x = NX;
+  t->dense_hot_words = wk[0];
+  t->dense_row_words = wk[1];
+  t->dense_cold_entries = wk[2];
 }
 
 void Plan::fetch_totals(hipStream_t s) {
@@ -569,7 +604,7 @@ jp_status check_opt(const jp_options* o) {
   if (o->tau_mode != JP_TAU_AUTO && o->tau_mode != JP_TAU_FIXED) return fail(JP_EINVAL, "bad tau_mode");
   if (o->dense_kernel < 0 || o->dense_kernel > 2) return fail(JP_EINVAL, "bad dense_kernel");
   if (o->k_hot_max < 0 || o->k_hot_max > 1024) return fail(JP_EINVAL, "k_hot_max must be in [0, 1024]");
-  if (o->flags != 0) return fail(JP_EINVAL, "flags must be 0");
+  if (o->flags & ~JP_FLAG_TIMING) return fail(JP_EINVAL, "unknown flag bits");
   if (o->workspace_limit_bytes < 0) return fail(JP_EINVAL, "negative workspace limit");
   if (o->tau_mode == JP_TAU_FIXED && o->dense_threshold < -1) return fail(JP_EINVAL, "dense_threshold < -1");
   return JP_OK;
@@ -660,6 +695,11 @@ jp_status jp_plan_stats(const jp_plan* p, jp_stats* s) {
   if (!p || !s) return fail(JP_EINVAL, "null argument");
   p->p.stats(0, s);
   return JP_OK;
+}
+
+jp_status jp_plan_timings(jp_plan* p, jp_timings* t, hipStream_t stream) {
+  if (!p || !t) return fail(JP_EINVAL, "null argument");
+  return guarded([&] { p->p.timings(t, stream); });
 }
 
 void jp_plan_destroy(jp_plan* p) {

@@ -39,12 +39,24 @@ struct Plan {
   int32_t *d_roww = nullptr, *zflag = nullptr, *Edz = nullptr, *dz2z = nullptr, *zd_base = nullptr;
   int32_t *spptr = nullptr, *spcol = nullptr, *Ehot = nullptr, *hotrow = nullptr, *cptr = nullptr, *ccol = nullptr;
   uint32_t* hb = nullptr;
+  int32_t *rcode = nullptr, *cw = nullptr;
+  int64_t* d_cwoff = nullptr;
+  std::vector<int64_t> h_cwoff;
   // execute
   int64_t* w = nullptr;
   int32_t *cnt_sp = nullptr, *cnt_de = nullptr, *cnt_all = nullptr;
   int64_t *off_all = nullptr, *off_de = nullptr, *off_sp = nullptr, *tot = nullptr;
 
-  ~Plan() { A.release(stream); }
+  // JP_FLAG_TIMING: events around the execute kernels and work counters
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t* d_work = nullptr;
+
+  ~Plan() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    A.release(stream);
+  }
+  void timings(jp_timings* t, hipStream_t s);
   void arena_limit(int64_t lim) { A.set_limit(lim); }
   void build(const jp_instance* inst, int n, const jp_options* o, hipStream_t s);
   void map(hipStream_t s);

@@ -239,9 +239,9 @@ constexpr int MM_CH = 16;
 __global__ void k_seg_minmax(const int32_t* __restrict__ v, int64_t n, const int32_t* __restrict__ base,
                              int n_seg, int32_t* __restrict__ mn, int32_t* __restrict__ mx) {
   int64_t start = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * MM_CH;
-  if (start >= n) return;
+  if (start >= n) start = n;  // idle lane: empty range, still takes part in the wave reduction
   int64_t end = start + MM_CH < n ? start + MM_CH : n;
-  int seg = find_inst<int32_t>(base, n_seg, int32_t(start));
+  int seg = start < n ? find_inst<int32_t>(base, n_seg, int32_t(start)) : 0;
   int32_t cmn = INT_MAX, cmx = INT_MIN;
   bool any = false;
   for (int64_t i = start; i < end; ++i) {
@@ -260,7 +260,22 @@ __global__ void k_seg_minmax(const int32_t* __restrict__ v, int64_t n, const int
     cmx = x > cmx ? x : cmx;
     any = true;
   }
-  if (any) {
+  // the common case: the whole wave ends in one segment -> one atomic per wave
+  const int s0 = __shfl(seg, 0, 64);
+  const bool same = ballot(seg != s0 && any) == 0;
+  if (same) {
+    int32_t wmn = cmn, wmx = cmx;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      int32_t a = __shfl_xor(wmn, o, 64), b = __shfl_xor(wmx, o, 64);
+      wmn = a < wmn ? a : wmn;
+      wmx = b > wmx ? b : wmx;
+    }
+    if (lane_id() == 0 && wmn <= wmx) {
+      atomicMin(&mn[s0], wmn);
+      atomicMax(&mx[s0], wmx);
+    }
+  } else if (any) {
     atomicMin(&mn[seg], cmn);
     atomicMax(&mx[seg], cmx);
   }

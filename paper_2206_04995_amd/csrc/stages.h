@@ -9,8 +9,10 @@ namespace jp {
 
 // Window of the dense-z bitmaps, in bits (DenseEC processes one window of a
 // row at a time).
-constexpr int DW_BITS = 32768;
+constexpr int DW_BITS = 16384;
 constexpr int DW_WORDS = DW_BITS / 32;
+// hot keys whose window slices a DenseEC workgroup stages in LDS
+constexpr int T_STAGE = 16;
 
 // ------------------------------------------------------------ mapping
 // keys[i] = koff[inst(i)] + (v[i] - mn[inst(i)]); payload[i] = i (if non-null)
@@ -62,7 +64,7 @@ void hot_histogram(const int32_t* sptr, const int32_t* spptr, const int32_t* dR,
 void hot_flags(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, const int32_t* y_base,
                int n_inst, const int64_t* theta, int32_t* hot, hipStream_t s);
 // hot row bit sets over the local dense index (one thread per S entry)
-void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* Ehot,
+void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* hotrow,
                     const int32_t* y_base, const int32_t* z_base, const int32_t* zd_base, const int32_t* Edz,
                     const int32_t* zflag, const int64_t* hb_off, const int32_t* row_words, int n_inst,
                     uint32_t* hb, hipStream_t s);
@@ -88,7 +90,21 @@ struct RowCtx {
   const int32_t* cptr;     // [n_y+1] cold rows
   const int32_t* ccol;     // local dense index, ascending within a row
   const int32_t* dz2z;     // [n_z_dense] dense index -> z id
+  const int32_t* rcode;    // [n_r_kept] per R CSR entry: hot rank (>= 0), -2 - y (cold y), -1 (no dense entry)
+  const int32_t* cw;       // cold segment starts per (instance, window, local y), windows 0..nwin
+  const int64_t* cw_off;   // [n_inst] offset of the instance's table
 };
+
+// hot rank of each hot y within its instance, by decreasing d_R (rows sharing it)
+void hot_rank(const int32_t* hot, const int32_t* Ehot, int64_t n_y, int64_t n_hot, const int32_t* y_base, int n_inst,
+              const int32_t* dR, int32_t* hotlist, int32_t* hotrow, hipStream_t s);
+// per R CSR entry code (see RowCtx::rcode)
+void row_codes(const int32_t* rcol, int64_t n, const int32_t* hotrow, const int32_t* cptr, int32_t* rcode,
+               hipStream_t s);
+// cold segment table: cw[cw_off[i] + w * Y_i + (y - y_base[i])] = first cold entry of y with local dense
+// index >= w * DW_BITS, for w in [0, nwin_i]
+void cold_windows(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t n_cold, const int32_t* y_base,
+                  const int32_t* zd_base, int n_inst, const int64_t* cw_off, int32_t* cw, hipStream_t s);
 
 // per-row work of the sparse part: w[x] = sum over y in R[x] of |S_sparse[y]|
 void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t* w, hipStream_t s);
@@ -98,6 +114,9 @@ void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
 // DenseEC count or write, bit-packed hot rows
 void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const int64_t* off, int32_t* out,
               hipStream_t s);
+
+// algorithmic work of the count kernels over rows [x_lo, x_hi) (see jp_timings)
+void work_stats(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int64_t* out4, hipStream_t s);
 
 // ------------------------------------------------------------- output
 void add_counts(const int32_t* a, const int32_t* b, int64_t n, int32_t* out, hipStream_t s);
