@@ -14,7 +14,7 @@ from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libjp.so")
+LIB_PATH = os.environ.get("JP_LIB_PATH") or os.path.join(_HERE, "libjp.so")
 
 JP_OK, JP_EINVAL, JP_ENOMEM, JP_EHIP, JP_ESTATE, JP_ERANGE, JP_EBUSY = range(7)
 JP_PART_ALL, JP_PART_DENSE, JP_PART_SPARSE = 0, 1, 2

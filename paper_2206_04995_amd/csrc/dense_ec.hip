@@ -10,12 +10,13 @@
 // LDS copy of the window.  The window is then popcounted (count mode) or
 // written out in z order (write mode).
 //
-// A workgroup owns 64 consecutive rows and walks the windows in order.  The
+// A workgroup owns 128 consecutive rows and walks the windows in order.  The
 // window slices of the T_STAGE hot keys shared by the most rows are staged in
-// LDS once per window for all 64 rows; rarer hot keys are read from the
-// caches.  Per-entry codes (hot rank / cold key) avoid dependent lookups, and
-// a per-window table of cold segment bounds lets the 64 lanes of a wave split
-// a row's cold entries evenly.
+// LDS once per window for all 128 rows; rarer hot keys are read from the
+// caches.  Per-entry codes (hot rank / cold key) stay in registers across the
+// windows, and the cold entries are stored window-major with per-(window, key)
+// segment bounds, so the 64 lanes of a wave split a row's cold entries evenly
+// and one window's cold data is a compact, cache-resident range.
 #include "common.h"
 #include "prim.h"
 #include "stages.h"
@@ -23,18 +24,18 @@
 namespace jp {
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 1024;                  // 16 waves share one LDS stage (8 waves per SIMD)
 constexpr int WAVES = NT / 64;
-constexpr int RPW = 16;                   // rows per wavefront
+constexpr int RPW = 8;                    // rows per wavefront
 constexpr int RB = WAVES * RPW;           // rows per workgroup
 constexpr int WPL = DW_WORDS / 64;        // words of a window per lane
 constexpr int Q = WPL / 4;                // uint4 per lane
 constexpr int QW = DW_WORDS / 4;          // uint4 per window slice
 
-__device__ __forceinline__ void lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
+// LDS operations of one wavefront execute in issue order, so ordering the
+// row buffer's stores, atomics and loads across lanes only needs the
+// compiler not to move them past each other.
+__device__ __forceinline__ void lds_fence() { __builtin_amdgcn_wave_barrier(); }
 
 __device__ __forceinline__ int popc4(uint4 v) { return __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w); }
 
@@ -45,8 +46,56 @@ __device__ __forceinline__ void or4(uint4& a, const uint4 b) {
   a.w |= b.w;
 }
 
+// ORs the hot keys among one wave's 64 codes into acc (LDS-staged or cached)
+template <int QN>
+__device__ __forceinline__ void hot_or(uint4 (&acc)[QN], int code, bool staged, int t_eff,
+                                       const uint4 (*stage)[QW], const uint32_t* hbase, int64_t rw) {
+  const int lane = lane_id();
+  uint64_t hm = ballot(code >= 0);
+  // staged keys: LDS reads
+  const uint64_t sm = ballot(code >= 0 && staged && code < t_eff);
+  uint64_t m = sm;
+  while (m) {
+    const int l = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const int k = __builtin_amdgcn_readlane(code, l);
+#pragma unroll
+    for (int q = 0; q < QN; ++q) or4(acc[q], stage[k][q * 64 + lane]);
+  }
+  // other hot keys: cached global reads
+  m = hm & ~sm;
+  while (m) {
+    const int l0 = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const int k0 = __builtin_amdgcn_readlane(code, l0);
+    const uint4* s0 = reinterpret_cast<const uint4*>(hbase + int64_t(k0) * rw);
+#pragma unroll
+    for (int q = 0; q < QN; ++q) or4(acc[q], s0[q * 64 + lane]);
+  }
+}
+
+// scatters the cold entries of one wave's segments (lane = one key) into the
+// LDS window of the row: one segment at a time, its entries spread over the
+// lanes (segment bounds are wave-uniform scalars)
+__device__ __forceinline__ void cold_scatter(int s0, int len, const int32_t* __restrict__ ccol, int32_t wstart,
+                                             uint32_t* rowbuf) {
+  const int lane = lane_id();
+  uint64_t m = ballot(len > 0);
+  while (m) {
+    const int l = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const int ss = __builtin_amdgcn_readlane(s0, l);
+    const int ll = __builtin_amdgcn_readlane(len, l);
+    const int32_t* src = ccol + ss;
+    for (int t = lane; t < ll; t += 64) {
+      const int dl = src[t] - wstart;
+      atomicOr(&rowbuf[dl >> 5], 1u << (dl & 31));
+    }
+  }
+}
+
 template <bool WRITE>
-__global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64_t x_hi, int32_t* __restrict__ cnt,
+__global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, int64_t x_hi, int32_t* __restrict__ cnt,
                                                    const int64_t* __restrict__ off, int32_t* __restrict__ out) {
   __shared__ uint4 stage[T_STAGE][QW];
   __shared__ uint4 rowbuf_all[WAVES][QW];
@@ -71,14 +120,23 @@ __global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64
   const int64_t rw0 = c.row_words[inst0];
 
   // lane r < nrows describes row r0 + r
-  int my_inst = 0, my_nwin = 0;
+  int my_inst = 0, my_nwin = 0, my_a = 0, my_b = 0;
   int64_t my_acc = 0;  // count (count mode) or write position (write mode)
   if (lane < nrows) {
-    int64_t x = r0 + lane;
+    const int64_t x = r0 + lane;
     my_inst = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, int32_t(x));
-    int zd = c.zd_base[my_inst + 1] - c.zd_base[my_inst];
+    const int zd = c.zd_base[my_inst + 1] - c.zd_base[my_inst];
     my_nwin = (zd + DW_BITS - 1) / DW_BITS;
+    my_a = c.rptr[x];
+    my_b = c.rptr[x + 1];
     if (WRITE) my_acc = off[x] - base_off;
+  }
+  // the first 64 codes of every row stay in registers for all windows
+  int code[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int a = __builtin_amdgcn_readlane(my_a, r), b = __builtin_amdgcn_readlane(my_b, r);
+    code[r] = (r < nrows && a + lane < b) ? c.rcode[a + lane] : -1;
   }
   const int wmax = wave_max(my_nwin);
   if (lane == 0) s_maxwin[wid] = wmax;
@@ -89,7 +147,6 @@ __global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64
 
   for (int w = 0; w < maxwin; ++w) {
     const int32_t wstart = w * DW_BITS;
-    const int32_t wend = wstart + DW_BITS;
     __syncthreads();
     if (w < nwin0) {
       for (int i = threadIdx.x; i < t_eff * QW; i += NT) {
@@ -99,73 +156,55 @@ __global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64
     }
     __syncthreads();
 
-    for (int r = 0; r < nrows; ++r) {
-      const int nwin_r = __shfl(my_nwin, r, 64);
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      if (r >= nrows) break;
+      const int nwin_r = __builtin_amdgcn_readlane(my_nwin, r);
       if (w >= nwin_r) continue;
-      const int inst = __shfl(my_inst, r, 64);
+      const int inst = __builtin_amdgcn_readlane(my_inst, r);
+      const int a = __builtin_amdgcn_readlane(my_a, r), b = __builtin_amdgcn_readlane(my_b, r);
       const bool staged = inst == inst0;
-      const int64_t x = r0 + r;
-      const int a = c.rptr[x], b = c.rptr[x + 1];
       const uint32_t* hbase = c.hb + c.hb_off[inst] + int64_t(w) * DW_WORDS;
       const int64_t rw = c.row_words[inst];
+      const int yb = c.y_base[inst];
+      const int ny = c.y_base[inst + 1] - yb;
+      const int32_t* wp = c.wptr + c.cwm_off[inst] + int64_t(w) * ny;
+
+      // bounds of this window's cold segments: issued first, used after the hot ORs
+      const int cd = code[r];
+      int s0 = 0, len = 0;
+      if (cd <= -2) {
+        const int yl = (-2 - cd) - yb;
+        s0 = wp[yl];
+        len = wp[yl + 1] - s0;
+      }
+      bool any_cold = ballot(cd <= -2) != 0;
 
       uint4 acc[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) acc[q] = make_uint4(0, 0, 0, 0);
-      bool any_cold = false;
-      for (int c0 = a; c0 < b; c0 += 64) {
+      hot_or<Q>(acc, cd, staged, t_eff, stage, hbase, rw);
+      for (int c0 = a + 64; c0 < b; c0 += 64) {  // rows with more than 64 join keys
         const int j = c0 + lane;
-        const int code = j < b ? c.rcode[j] : -1;
-        uint64_t hm = ballot(code >= 0);
-        any_cold |= ballot(code <= -2) != 0;
-        while (hm) {
-          const int l = __ffsll((unsigned long long)hm) - 1;
-          hm &= hm - 1;
-          const int k = __shfl(code, l, 64);
-          if (staged && k < t_eff) {
-#pragma unroll
-            for (int q = 0; q < Q; ++q) or4(acc[q], stage[k][q * 64 + lane]);
-          } else {
-            const uint4* src = reinterpret_cast<const uint4*>(hbase + int64_t(k) * rw);
-#pragma unroll
-            for (int q = 0; q < Q; ++q) or4(acc[q], src[q * 64 + lane]);
-          }
-        }
+        const int cx = j < b ? c.rcode[j] : -1;
+        any_cold |= ballot(cx <= -2) != 0;
+        hot_or<Q>(acc, cx, staged, t_eff, stage, hbase, rw);
       }
       if (any_cold) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) rowbuf4[q * 64 + lane] = acc[q];
         lds_fence();
-        const int yb = c.y_base[inst];
-        const int ny = c.y_base[inst + 1] - yb;
-        const int32_t* cwin = c.cw + c.cw_off[inst] + int64_t(w) * ny;
-        for (int c0 = a; c0 < b; c0 += 64) {
+        cold_scatter(s0, len, c.ccol, wstart, rowbuf);
+        for (int c0 = a + 64; c0 < b; c0 += 64) {
           const int j = c0 + lane;
-          const int code = j < b ? c.rcode[j] : -1;
-          int s0 = 0, len = 0;
-          if (code <= -2) {
-            const int yl = (-2 - code) - yb;
-            s0 = cwin[yl];
-            len = cwin[int64_t(ny) + yl] - s0;
+          const int cx = j < b ? c.rcode[j] : -1;
+          int t0 = 0, tl = 0;
+          if (cx <= -2) {
+            const int yl = (-2 - cx) - yb;
+            t0 = wp[yl];
+            tl = wp[yl + 1] - t0;
           }
-          const int incl = wave_incl_scan(len);
-          const int excl = incl - len;
-          const int total = __shfl(incl, 63, 64);
-          for (int t0 = 0; t0 < total; t0 += 64) {
-            const int tt = t0 + lane;
-            int o = 0;
-#pragma unroll
-            for (int step = 32; step > 0; step >>= 1) {
-              const int e = __shfl(excl, o + step, 64);
-              if (e <= tt) o += step;
-            }
-            const int os0 = __shfl(s0, o, 64);
-            const int oex = __shfl(excl, o, 64);
-            if (tt < total) {
-              const int dl = c.ccol[os0 + (tt - oex)] - wstart;
-              atomicOr(&rowbuf[dl >> 5], 1u << (dl & 31));
-            }
-          }
+          cold_scatter(t0, tl, c.ccol, wstart, rowbuf);
         }
         lds_fence();
 #pragma unroll
@@ -177,7 +216,7 @@ __global__ void __launch_bounds__(NT) k_dense_bits(RowCtx c, int64_t x_lo, int64
         int pc = 0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) pc += popc4(acc[q]);
-        const int tot = wave_sum(pc);
+        const int tot = wave_sum_dpp(pc);
         if (lane == r) my_acc += tot;
       } else {
         const int64_t pos0 = __shfl(my_acc, r, 64);

@@ -202,7 +202,64 @@ __global__ void k_cold_win_tail(const int32_t* __restrict__ cptr, const int32_t*
   }
 }
 
+// window-major layout of the cold entries: segment counts per (window, y)
+__global__ void k_cold_win_counts(const int32_t* __restrict__ cw, const int64_t* __restrict__ cw_off,
+                                  const int64_t* __restrict__ cwm_off, const int32_t* __restrict__ y_base,
+                                  const int32_t* __restrict__ zd_base, int n_inst, int64_t n_y,
+                                  int32_t* __restrict__ cnt) {
+  GRID_STRIDE(y, n_y) {
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+    const int zd = zd_base[inst + 1] - zd_base[inst];
+    if (zd <= 0) continue;
+    const int nwin = (zd + DW_BITS - 1) / DW_BITS;
+    const int ny = y_base[inst + 1] - y_base[inst];
+    const int yl = int(y) - y_base[inst];
+    const int32_t* t = cw + cw_off[inst] + yl;
+    int32_t* o = cnt + cwm_off[inst] + yl;
+    for (int w = 0; w < nwin; ++w) o[int64_t(w) * ny] = t[int64_t(w + 1) * ny] - t[int64_t(w) * ny];
+  }
+}
+
+__global__ void k_cold_win_scatter(const int32_t* __restrict__ cptr, const int32_t* __restrict__ ccol, int64_t n_y,
+                                   int64_t n_cold, const int32_t* __restrict__ y_base, int n_inst,
+                                   const int32_t* __restrict__ cw, const int64_t* __restrict__ cw_off,
+                                   const int32_t* __restrict__ wptr, const int64_t* __restrict__ cwm_off,
+                                   int32_t* __restrict__ ccol_w) {
+  GRID_STRIDE(p, n_cold) {
+    int64_t lo = 0, hi = n_y;
+    while (hi - lo > 1) {
+      int64_t mid = (lo + hi) >> 1;
+      if (cptr[mid] <= p) lo = mid;
+      else hi = mid;
+    }
+    const int32_t y = int32_t(lo);
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+    const int ny = y_base[inst + 1] - y_base[inst];
+    const int yl = y - y_base[inst];
+    const int32_t d = ccol[p];
+    const int64_t slot = int64_t(d / DW_BITS) * ny + yl;
+    ccol_w[wptr[cwm_off[inst] + slot] + (p - cw[cw_off[inst] + slot])] = d;
+  }
+}
+
 }  // namespace
+
+void cold_window_major(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t n_cold, const int32_t* y_base,
+                       const int32_t* zd_base, int n_inst, const int32_t* cw, const int64_t* cw_off,
+                       const int64_t* cwm_off, int64_t cwm_total, int32_t* wptr, int32_t* ccol_w, hipStream_t s,
+                       Arena& a) {
+  int32_t* cnt = a.alloc<int32_t>(std::max<int64_t>(cwm_total, 1), s);
+  if (n_y > 0)
+    hipLaunchKernelGGL(k_cold_win_counts, dim3(grid(n_y)), dim3(NT), 0, s, cw, cw_off, cwm_off, y_base, zd_base, n_inst,
+                       n_y, cnt);
+  JP_LAUNCH_CHECK();
+  scan_excl_i32(cnt, wptr, cwm_total, s, a);
+  if (n_cold > 0)
+    hipLaunchKernelGGL(k_cold_win_scatter, dim3(grid(n_cold)), dim3(NT), 0, s, cptr, ccol, n_y, n_cold, y_base, n_inst,
+                       cw, cw_off, wptr, cwm_off, ccol_w);
+  JP_LAUNCH_CHECK();
+  a.give_back(cnt, s);
+}
 
 void dense_flags(const int32_t* m_z, int64_t n_z, const int32_t* z_base, int n_inst, const int64_t* tau, int32_t* flag,
                  hipStream_t s) {

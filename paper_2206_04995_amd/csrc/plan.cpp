@@ -413,21 +413,37 @@ void Plan::partition(hipStream_t s) {
   d2h(&ncold, Ec + NS, 1, s);
   sync(s);
   NCold = ncold;
-  ccol = A.alloc<int32_t>(std::max<int64_t>(NCold, 1), s);
-  compact_entries(scol, fl, Ec, NS, Edz, z_base, zd_base, n, true, ccol, s);
+  int32_t* ccol_y = T.alloc<int32_t>(std::max<int64_t>(NCold, 1), s);
+  compact_entries(scol, fl, Ec, NS, Edz, z_base, zd_base, n, true, ccol_y, s);
 
-  // per-window bounds of the cold rows, and per-entry codes of R's CSR
-  h_cwoff.assign(n, 0);
-  int64_t cw_total = 0;
+  // cold entries in window-major order with per-(window, key) segment bounds,
+  // and per-entry codes of R's CSR
+  std::vector<int64_t> h_cwoff(n, 0), h_cwmoff(n, 0);
+  int64_t cw_total = 0, cwm_total = 0;
   for (int i = 0; i < n; ++i) {
     h_cwoff[i] = cw_total;
+    h_cwmoff[i] = cwm_total;
     int64_t zd = h_zdbase[i + 1] - h_zdbase[i];
-    if (zd > 0) cw_total += int64_t(h_ybase[i + 1] - h_ybase[i]) * ((zd + DW_BITS - 1) / DW_BITS + 1);
+    if (zd > 0) {
+      int64_t ny = h_ybase[i + 1] - h_ybase[i], nwin = (zd + DW_BITS - 1) / DW_BITS;
+      cw_total += ny * (nwin + 1);
+      cwm_total += ny * nwin;
+    }
   }
-  d_cwoff = A.alloc<int64_t>(n, s);
-  h2d(d_cwoff, h_cwoff.data(), n, s);
-  cw = A.alloc<int32_t>(std::max<int64_t>(cw_total, 1), s);
-  if (cw_total > 0) cold_windows(cptr, ccol, NY, NCold, y_base, zd_base, n, d_cwoff, cw, s);
+  if (cwm_total >= INT32_MAX) throw Error(JP_ENOMEM, "cold segment table too large");
+  int64_t* d_offs = T.alloc<int64_t>(2 * int64_t(n), s);
+  h2d(d_offs, h_cwoff.data(), n, s);
+  d_cwmoff = A.alloc<int64_t>(n, s);
+  h2d(d_cwmoff, h_cwmoff.data(), n, s);
+  int32_t* cw = T.alloc<int32_t>(std::max<int64_t>(cw_total, 1), s);
+  wptr = A.alloc<int32_t>(cwm_total + 1, s);
+  ccol = A.alloc<int32_t>(std::max<int64_t>(NCold, 1), s);
+  if (cw_total > 0) {
+    cold_windows(cptr, ccol_y, NY, NCold, y_base, zd_base, n, d_offs, cw, s);
+    cold_window_major(cptr, ccol_y, NY, NCold, y_base, zd_base, n, cw, d_offs, d_cwmoff, cwm_total, wptr, ccol, s, T);
+  } else {
+    fill_i32(wptr, 1, 0, s);
+  }
   rcode = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
   row_codes(rcol, NRp, hotrow, cptr, rcode, s);
   T.release(s);
@@ -447,8 +463,8 @@ RowCtx Plan::ctx() const {
   c.Ehot = Ehot;
   c.y_base = y_base;
   c.rcode = rcode;
-  c.cw = cw;
-  c.cw_off = d_cwoff;
+  c.wptr = wptr;
+  c.cwm_off = d_cwmoff;
   c.hb_off = d_hboff;
   c.row_words = d_roww;
   c.hb = hb;

@@ -39,9 +39,8 @@ struct Plan {
   int32_t *d_roww = nullptr, *zflag = nullptr, *Edz = nullptr, *dz2z = nullptr, *zd_base = nullptr;
   int32_t *spptr = nullptr, *spcol = nullptr, *Ehot = nullptr, *hotrow = nullptr, *cptr = nullptr, *ccol = nullptr;
   uint32_t* hb = nullptr;
-  int32_t *rcode = nullptr, *cw = nullptr;
-  int64_t* d_cwoff = nullptr;
-  std::vector<int64_t> h_cwoff;
+  int32_t *rcode = nullptr, *wptr = nullptr;
+  int64_t* d_cwmoff = nullptr;
   // execute
   int64_t* w = nullptr;
   int32_t *cnt_sp = nullptr, *cnt_de = nullptr, *cnt_all = nullptr;

@@ -87,12 +87,12 @@ struct RowCtx {
   const int64_t* hb_off;   // [n_inst] word offset of the instance's hot rows
   const int32_t* row_words;// [n_inst] words per hot row (multiple of DW_WORDS)
   const uint32_t* hb;      // hot rows
-  const int32_t* cptr;     // [n_y+1] cold rows
-  const int32_t* ccol;     // local dense index, ascending within a row
+  const int32_t* cptr;     // [n_y+1] number of cold entries per y (cptr[y+1] - cptr[y])
+  const int32_t* ccol;     // cold entries (local dense index), window-major: by window, then y, then z
   const int32_t* dz2z;     // [n_z_dense] dense index -> z id
   const int32_t* rcode;    // [n_r_kept] per R CSR entry: hot rank (>= 0), -2 - y (cold y), -1 (no dense entry)
-  const int32_t* cw;       // cold segment starts per (instance, window, local y), windows 0..nwin
-  const int64_t* cw_off;   // [n_inst] offset of the instance's table
+  const int32_t* wptr;     // segment of (window w, y): ccol[wptr[k], wptr[k+1]), k = cwm_off[i] + w*Y_i + y - y_base[i]
+  const int64_t* cwm_off;  // [n_inst] offset of the instance's segment table
 };
 
 // hot rank of each hot y within its instance, by decreasing d_R (rows sharing it)
@@ -105,6 +105,13 @@ void row_codes(const int32_t* rcol, int64_t n, const int32_t* hotrow, const int3
 // index >= w * DW_BITS, for w in [0, nwin_i]
 void cold_windows(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t n_cold, const int32_t* y_base,
                   const int32_t* zd_base, int n_inst, const int64_t* cw_off, int32_t* cw, hipStream_t s);
+// Window-major copy of the cold entries: the entries of (window w, key y) of
+// instance i are ccol_w[wptr[k], wptr[k + 1]) with k = cwm_off[i] + w * Y_i + (y - y_base[i]);
+// wptr has cwm_total + 1 entries.
+void cold_window_major(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t n_cold, const int32_t* y_base,
+                       const int32_t* zd_base, int n_inst, const int32_t* cw, const int64_t* cw_off,
+                       const int64_t* cwm_off, int64_t cwm_total, int32_t* wptr, int32_t* ccol_w, hipStream_t s,
+                       Arena& a);
 
 // per-row work of the sparse part: w[x] = sum over y in R[x] of |S_sparse[y]|
 void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t* w, hipStream_t s);
