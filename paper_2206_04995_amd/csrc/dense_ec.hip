@@ -260,18 +260,24 @@ __global__ void k_work_stats(RowCtx c, int64_t x_lo, int64_t x_hi, const int64_t
       int inst = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, int32_t(x));
       int zd = c.zd_base[inst + 1] - c.zd_base[inst];
       int64_t rw = zd > 0 ? int64_t((zd + DW_BITS - 1) / DW_BITS) * DW_WORDS : 0;
-      int64_t h = 0, cold = 0;
-      if (rw > 0) {
-        for (int j = c.rptr[x]; j < c.rptr[x + 1]; ++j) {
-          int code = c.rcode[j];
-          if (code >= 0) ++h;
-          else if (code <= -2) cold += c.cptr[-2 - code + 1] - c.cptr[-2 - code];
-        }
-      }
-      a0 += h * rw;
       a1 += rw;
-      a2 += cold;
       a3 += w[x - x_lo];
+    }
+  }
+  // per CSR entry (one thread each, so long rows do not serialise)
+  const int64_t j_lo = c.rptr[x_lo], j_hi = c.rptr[x_hi];
+  for (int64_t b = j_lo + int64_t(blockIdx.x) * blockDim.x; b < j_hi; b += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = b + threadIdx.x;
+    if (j < j_hi) {
+      const int code = c.rcode[j];
+      if (code >= 0) {
+        const int y = c.rcol[j];
+        const int inst = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.y_base, c.n_inst, y);
+        const int zd = c.zd_base[inst + 1] - c.zd_base[inst];
+        a0 += int64_t((zd + DW_BITS - 1) / DW_BITS) * DW_WORDS;
+      } else if (code <= -2) {
+        a2 += c.cptr[-2 - code + 1] - c.cptr[-2 - code];
+      }
     }
   }
   a0 = wave_sum(a0);

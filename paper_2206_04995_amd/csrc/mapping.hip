@@ -83,6 +83,29 @@ __global__ void k_semijoin(const int32_t* __restrict__ ry, int64_t n, const int3
   }
 }
 
+// direct-address table of the y keys (used when the key space is small, as
+// for naturally dense domains): table[key] = id for every run head
+__global__ void k_fill_direct(const uint32_t* __restrict__ keys, int64_t n, const int32_t* __restrict__ E,
+                              int32_t* __restrict__ table) {
+  GRID_STRIDE(p, n) {
+    if (E[p + 1] != E[p]) table[keys[p]] = E[p];
+  }
+}
+
+__global__ void k_semijoin_direct(const int32_t* __restrict__ ry, int64_t n, const int32_t* __restrict__ ebase,
+                                  int n_inst, const int64_t* __restrict__ koff, const int32_t* __restrict__ mn,
+                                  const int32_t* __restrict__ table, int32_t* __restrict__ keep,
+                                  int32_t* __restrict__ yid) {
+  GRID_STRIDE(g, n) {
+    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(ebase, n_inst, int32_t(g));
+    const int64_t rel = int64_t(ry[g]) - int64_t(mn[inst]);
+    const int64_t range = koff[inst + 1] - koff[inst];
+    const int32_t id = (rel >= 0 && rel < range) ? table[koff[inst] + rel] : -1;
+    keep[g] = id >= 0 ? 1 : 0;
+    yid[g] = id;
+  }
+}
+
 __global__ void k_compact_r(const int32_t* __restrict__ rx, const int32_t* __restrict__ yid,
                             const int32_t* __restrict__ keep, const int32_t* __restrict__ E, int64_t n,
                             int32_t* __restrict__ ox, int32_t* __restrict__ oy) {
@@ -198,6 +221,20 @@ void semijoin(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, co
               const int32_t* y_base, int32_t* keep, int32_t* yid, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_semijoin, dim3(grid(n)), dim3(NT), 0, s, ry, n, ebase, n_inst, vals_y, y_base, keep, yid);
+  JP_LAUNCH_CHECK();
+}
+
+void semijoin_direct(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, const uint32_t* ykeys, int64_t ns,
+                     const int32_t* Ey, const int64_t* koff, int64_t key_space, const int32_t* mn, int32_t* table,
+                     int32_t* keep, int32_t* yid, hipStream_t s) {
+  fill_i32(table, key_space, -1, s);
+  if (ns > 0) {
+    hipLaunchKernelGGL(k_fill_direct, dim3(grid(ns)), dim3(NT), 0, s, ykeys, ns, Ey, table);
+    JP_LAUNCH_CHECK();
+  }
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_semijoin_direct, dim3(grid(n)), dim3(NT), 0, s, ry, n, ebase, n_inst, koff, mn, table, keep,
+                     yid);
   JP_LAUNCH_CHECK();
 }
 

@@ -231,7 +231,14 @@ void Plan::map(hipStream_t s) {
   // semi-join of R on S.y (Sec. 2.2, optimisation 2), then R' sorted by (instance, x)
   const int64_t NRa = std::max<int64_t>(NR, 1);
   int32_t* yid = T.alloc<int32_t>(NRa, s);
-  semijoin(ry, NR, d_rbase, n, vals_y, y_base, flags, yid, s);
+  const int64_t y_keys = koff_y[n];
+  if (y_keys <= 2 * NS + 65536) {
+    // dense key domain: one table lookup per R tuple instead of a binary search
+    int32_t* table = T.alloc<int32_t>(std::max<int64_t>(y_keys, 1), s);
+    semijoin_direct(ry, NR, d_rbase, n, syk, NS, Ey, dky, y_keys, ymin, table, flags, yid, s);
+  } else {
+    semijoin(ry, NR, d_rbase, n, vals_y, y_base, flags, yid, s);
+  }
   int32_t* Ek = T.alloc<int32_t>(NR + 1, s);
   scan_excl_i32(flags, Ek, NR, s, T);
   int32_t* rpx = T.alloc<int32_t>(NRa, s);
@@ -452,6 +459,8 @@ void Plan::partition(hipStream_t s) {
 RowCtx Plan::ctx() const {
   RowCtx c;
   c.n_inst = n_inst;
+  c.max_z_range = 0;
+  for (int i = 0; i < n_inst; ++i) c.max_z_range = std::max<int64_t>(c.max_z_range, h_zbase[i + 1] - h_zbase[i]);
   c.x_base = x_base;
   c.z_base = z_base;
   c.zd_base = zd_base;
@@ -496,7 +505,7 @@ void Plan::execute(hipStream_t s) {
   }
   RowCtx c = ctx();
   if (timing) JP_HIP(hipEventRecord(ev[0], s));
-  sparse_row_work(c, 0, NX, w, s);
+  sparse_row_work(c, 0, NX, 0, NRp, w, s, A);
   if (NSp > 0) sparse_bmm(c, 0, NX, w, cnt_sp, nullptr, nullptr, s);
   else fill_i32(cnt_sp, NX, 0, s);
   if (timing) JP_HIP(hipEventRecord(ev[1], s));

@@ -5,12 +5,14 @@
 // The paper deduplicates with one z-vector (SPA) stamped with the current x
 // so it never has to be cleared.  Here x rows run in parallel, so every
 // wavefront owns a small LDS hash set sized to the row's work (cleared per
-// row, cost proportional to the row), and rows whose work exceeds it use a
-// whole workgroup with an LDS bitmap over windows of the z range.
+// row, cost proportional to the row), and rows whose work exceeds it use
+// workgroups with an LDS bitmap over windows of the z range; in count mode
+// the windows of one heavy row run as separate workgroups.
 //
 // Count mode writes the number of distinct z per row; write mode writes the
 // sorted z ids of each row at off[x] - off[x_lo].
 #include "common.h"
+#include "prim.h"
 #include "stages.h"
 
 namespace jp {
@@ -28,17 +30,22 @@ __device__ __forceinline__ void lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-__global__ void k_row_work(const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
-                           const int32_t* __restrict__ spptr, int64_t x_lo, int64_t x_hi, int64_t* __restrict__ w) {
-  for (int64_t x = x_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < x_hi;
-       x += int64_t(gridDim.x) * blockDim.x) {
-    int64_t acc = 0;
-    for (int j = rptr[x]; j < rptr[x + 1]; ++j) {
-      int y = rcol[j];
-      acc += spptr[y + 1] - spptr[y];
-    }
-    w[x - x_lo] = acc;
+// per R CSR entry: length of the sparse S row of its join key
+__global__ void k_entry_len(const int32_t* __restrict__ rcol, const int32_t* __restrict__ spptr, int64_t j_lo,
+                            int64_t j_hi, int32_t* __restrict__ len) {
+  for (int64_t j = j_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < j_hi;
+       j += int64_t(gridDim.x) * blockDim.x) {
+    const int y = rcol[j];
+    len[j - j_lo] = spptr[y + 1] - spptr[y];
   }
+}
+
+// w[x] = sum of the entry lengths of row x (difference of the entries' prefix sums)
+__global__ void k_row_diff(const int32_t* __restrict__ rptr, const int64_t* __restrict__ E, int64_t j_lo, int64_t x_lo,
+                           int64_t x_hi, int64_t* __restrict__ w) {
+  for (int64_t x = x_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < x_hi;
+       x += int64_t(gridDim.x) * blockDim.x)
+    w[x - x_lo] = E[rptr[x + 1] - j_lo] - E[rptr[x] - j_lo];
 }
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t z, int log2t) {
@@ -66,6 +73,52 @@ __device__ void wave_bitonic(int32_t* a, int t) {
   }
 }
 
+// Lanes hold segments [s0, s0 + len) of a z-sorted array; every entry lands
+// on one lane (owner found by a search over the wave's prefix sums) and its
+// bit is set in the LDS bitmap of window [wlo, wlo + HB_BITS).
+__device__ __forceinline__ void wave_flat_scatter(int s0, int len, const int32_t* __restrict__ col, int32_t wlo,
+                                                  uint32_t* bm) {
+  const int lane = lane_id();
+  const int incl = wave_incl_scan(len);
+  const int excl = incl - len;
+  const int total = __shfl(incl, 63, 64);
+  for (int t0 = 0; t0 < total; t0 += 64) {
+    const int tt = t0 + lane;
+    int o = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+      const int e = __shfl(excl, o + step, 64);
+      if (e <= tt) o += step;
+    }
+    const int os0 = __shfl(s0, o, 64);
+    const int oex = __shfl(excl, o, 64);
+    if (tt < total) {
+      const int d = col[os0 + (tt - oex)] - wlo;
+      atomicOr(&bm[d >> 5], 1u << (d & 31));
+    }
+  }
+}
+
+// every thread takes join keys of the row, finds the part of its sparse S row
+// inside the window by binary search, and its wave scatters the entries
+__device__ __forceinline__ void heavy_window(const int32_t* __restrict__ rcol, const int32_t* __restrict__ spptr,
+                                             const int32_t* __restrict__ spcol, int a, int b, int32_t wlo,
+                                             int32_t whi, uint32_t* bm) {
+  for (int c0 = a; c0 < b; c0 += NT) {
+    const int j = c0 + int(threadIdx.x);
+    int lo = 0, len = 0;
+    if (j < b) {
+      const int y = rcol[j];
+      const int s0 = spptr[y], s1 = spptr[y + 1];
+      if (s1 > s0) {
+        lo = int(lower_bound_dev<int32_t>(spcol, s0, s1, wlo));
+        len = int(lower_bound_dev<int32_t>(spcol, lo, s1, whi)) - lo;
+      }
+    }
+    wave_flat_scatter(lo, len, spcol, wlo, bm);
+  }
+}
+
 template <bool WRITE>
 __global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
                                                      const int32_t* __restrict__ spptr,
@@ -82,8 +135,8 @@ __global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__
 
   for (int64_t x = x_lo + gw; x < x_hi; x += nw) {
     const int64_t wx = w[x - x_lo];
-    if (wx > LIGHT_MAX) continue;  // heavy row: other kernel
-    if (wx == 0) {
+    if (wx > LIGHT_MAX || wx == 0) {
+      // heavy rows are counted by the windowed kernel, which adds to cnt[x]
       if (!WRITE && lane == 0) cnt[x] = 0;
       continue;
     }
@@ -143,44 +196,74 @@ __global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__
   }
 }
 
-template <bool WRITE>
-__global__ void __launch_bounds__(NT) k_sparse_heavy(const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
-                                                     const int32_t* __restrict__ spptr,
-                                                     const int32_t* __restrict__ spcol, int n_inst,
-                                                     const int32_t* __restrict__ x_base,
-                                                     const int32_t* __restrict__ z_base, int64_t x_lo, int64_t x_hi,
-                                                     const int64_t* __restrict__ w, int32_t* __restrict__ cnt,
-                                                     const int64_t* __restrict__ off, int32_t* __restrict__ out) {
+// count mode: one workgroup per (heavy row, window blockIdx.y)
+__global__ void __launch_bounds__(NT) k_sparse_heavy_count(const int32_t* __restrict__ rptr,
+                                                           const int32_t* __restrict__ rcol,
+                                                           const int32_t* __restrict__ spptr,
+                                                           const int32_t* __restrict__ spcol, int n_inst,
+                                                           const int32_t* __restrict__ x_base,
+                                                           const int32_t* __restrict__ z_base, int64_t x_lo,
+                                                           int64_t x_hi, const int64_t* __restrict__ w,
+                                                           int32_t* __restrict__ cnt) {
   __shared__ uint32_t bm[HB_WORDS];
   __shared__ int red[NT / 64];
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
-  const int64_t base_off = WRITE ? off[x_lo] : 0;
+  for (int64_t x = x_lo + blockIdx.x; x < x_hi; x += gridDim.x) {
+    if (w[x - x_lo] <= LIGHT_MAX) continue;
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(x_base, n_inst, int32_t(x));
+    const int32_t zlo = z_base[inst], zhi = z_base[inst + 1];
+    const int64_t wlo64 = int64_t(zlo) + int64_t(blockIdx.y) * HB_BITS;
+    if (wlo64 >= zhi) continue;
+    const int32_t wlo = int32_t(wlo64);
+    const int32_t whi = (zhi - wlo) > HB_BITS ? wlo + HB_BITS : zhi;
+    for (int i = threadIdx.x; i < HB_WORDS; i += NT) bm[i] = 0u;
+    __syncthreads();
+    heavy_window(rcol, spptr, spcol, rptr[x], rptr[x + 1], wlo, whi, bm);
+    __syncthreads();
+    constexpr int PER = HB_WORDS / NT;
+    int c = 0;
+    for (int k = 0; k < PER; ++k) c += __popc(bm[threadIdx.x * PER + k]);
+    c = wave_sum(c);
+    if (lane == 0) red[wid] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int q = 0; q < NT / 64; ++q) tot += red[q];
+      if (tot) atomicAdd(&cnt[x], tot);
+    }
+    __syncthreads();
+  }
+}
+
+// write mode: one workgroup per heavy row, windows in z order
+__global__ void __launch_bounds__(NT) k_sparse_heavy_write(const int32_t* __restrict__ rptr,
+                                                           const int32_t* __restrict__ rcol,
+                                                           const int32_t* __restrict__ spptr,
+                                                           const int32_t* __restrict__ spcol, int n_inst,
+                                                           const int32_t* __restrict__ x_base,
+                                                           const int32_t* __restrict__ z_base, int64_t x_lo,
+                                                           int64_t x_hi, const int64_t* __restrict__ w,
+                                                           const int64_t* __restrict__ off, int32_t* __restrict__ out) {
+  __shared__ uint32_t bm[HB_WORDS];
+  __shared__ int red[NT / 64];
+  const int lane = lane_id();
+  const int wid = threadIdx.x >> 6;
+  const int64_t base_off = off[x_lo];
 
   for (int64_t x = x_lo + blockIdx.x; x < x_hi; x += gridDim.x) {
     if (w[x - x_lo] <= LIGHT_MAX) continue;
     const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(x_base, n_inst, int32_t(x));
     const int32_t zlo = z_base[inst], zhi = z_base[inst + 1];
-    const int a = rptr[x], b = rptr[x + 1];
-    int64_t row_total = 0;
-    int64_t wpos = WRITE ? off[x] - base_off : 0;
-    for (int32_t wlo = zlo; wlo < zhi; wlo += HB_BITS) {
+    int64_t wpos = off[x] - base_off;
+    for (int64_t wlo64 = zlo; wlo64 < zhi; wlo64 += HB_BITS) {
+      const int32_t wlo = int32_t(wlo64);
       const int32_t whi = (zhi - wlo) > HB_BITS ? wlo + HB_BITS : zhi;
       for (int i = threadIdx.x; i < HB_WORDS; i += NT) bm[i] = 0u;
       __syncthreads();
-      for (int j = a + wid; j < b; j += NT / 64) {
-        int y = rcol[j];
-        int s0 = spptr[y], s1 = spptr[y + 1];
-        if (s0 == s1) continue;
-        int lo = int(lower_bound_dev<int32_t>(spcol, s0, s1, wlo));
-        int hi = int(lower_bound_dev<int32_t>(spcol, lo, s1, whi));
-        for (int p = lo + lane; p < hi; p += 64) {
-          int d = spcol[p] - wlo;
-          atomicOr(&bm[d >> 5], 1u << (d & 31));
-        }
-      }
+      heavy_window(rcol, spptr, spcol, rptr[x], rptr[x + 1], wlo, whi, bm);
       __syncthreads();
-      // thread t owns words [t*64, t*64+64): contiguous, so prefix order is z order
+      // thread t owns words [t*PER, (t+1)*PER): contiguous, so prefix order is z order
       constexpr int PER = HB_WORDS / NT;
       int c = 0;
       for (int k = 0; k < PER; ++k) c += __popc(bm[threadIdx.x * PER + k]);
@@ -193,33 +276,41 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy(const int32_t* __restrict__
         if (q < wid) pre += v;
         tot += v;
       }
-      if (WRITE) {
-        int64_t pos = wpos + pre + (inc - c);
-        for (int k = 0; k < PER; ++k) {
-          uint32_t word = bm[threadIdx.x * PER + k];
-          while (word) {
-            int bit = __ffs(word) - 1;
-            word &= word - 1;
-            out[pos++] = wlo + (threadIdx.x * PER + k) * 32 + bit;
-          }
+      int64_t pos = wpos + pre + (inc - c);
+      for (int k = 0; k < PER; ++k) {
+        uint32_t word = bm[threadIdx.x * PER + k];
+        while (word) {
+          int bit = __ffs(word) - 1;
+          word &= word - 1;
+          out[pos++] = wlo + (threadIdx.x * PER + k) * 32 + bit;
         }
       }
       wpos += tot;
-      row_total += tot;
       __syncthreads();
     }
-    if (!WRITE && threadIdx.x == 0) cnt[x] = int32_t(row_total);
   }
 }
 
 }  // namespace
 
-void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t* w, hipStream_t s) {
+void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, int64_t j_hi, int64_t* w,
+                     hipStream_t s, Arena& a) {
   int64_t n = x_hi - x_lo;
   if (n <= 0) return;
+  const int64_t ne = j_hi - j_lo;
+  int32_t* len = a.alloc<int32_t>(std::max<int64_t>(ne, 1), s);
+  int64_t* E = a.alloc<int64_t>(ne + 1, s);
+  if (ne > 0) {
+    int g = int(std::min<int64_t>((ne + NT - 1) / NT, 1 << 16));
+    hipLaunchKernelGGL(k_entry_len, dim3(g), dim3(NT), 0, s, c.rcol, c.spptr, j_lo, j_hi, len);
+    JP_LAUNCH_CHECK();
+  }
+  scan_excl_i32_to_i64(len, E, ne, s, a);
   int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
-  hipLaunchKernelGGL(k_row_work, dim3(g), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, x_lo, x_hi, w);
+  hipLaunchKernelGGL(k_row_diff, dim3(g), dim3(NT), 0, s, c.rptr, E, j_lo, x_lo, x_hi, w);
   JP_LAUNCH_CHECK();
+  a.give_back(E, s);
+  a.give_back(len, s);
 }
 
 void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int32_t* cnt, const int64_t* off,
@@ -227,20 +318,21 @@ void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
   int64_t n = x_hi - x_lo;
   if (n <= 0) return;
   int gl = int(std::min<int64_t>((n + 3) / 4, 1 << 15));
-  int gh = int(std::min<int64_t>(n, 2048));
+  int gh = int(std::min<int64_t>(n, 1024));
   if (out) {
     hipLaunchKernelGGL(k_sparse_light<true>, dim3(gl), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, x_lo, x_hi, w,
                        cnt, off, out);
     JP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sparse_heavy<true>, dim3(gh), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, c.n_inst,
-                       c.x_base, c.z_base, x_lo, x_hi, w, cnt, off, out);
+    hipLaunchKernelGGL(k_sparse_heavy_write, dim3(gh), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, c.n_inst,
+                       c.x_base, c.z_base, x_lo, x_hi, w, off, out);
     JP_LAUNCH_CHECK();
   } else {
     hipLaunchKernelGGL(k_sparse_light<false>, dim3(gl), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, x_lo, x_hi,
                        w, cnt, off, out);
     JP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sparse_heavy<false>, dim3(gh), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, c.n_inst,
-                       c.x_base, c.z_base, x_lo, x_hi, w, cnt, off, out);
+    const int wins = int(std::max<int64_t>(1, (c.max_z_range + HB_BITS - 1) / HB_BITS));
+    hipLaunchKernelGGL(k_sparse_heavy_count, dim3(gh, wins), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol,
+                       c.n_inst, c.x_base, c.z_base, x_lo, x_hi, w, cnt);
     JP_LAUNCH_CHECK();
   }
 }

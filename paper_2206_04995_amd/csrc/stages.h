@@ -32,6 +32,11 @@ void gather_bases(const int32_t* E, const int32_t* ebase, int n_inst, int32_t* o
 // semi-join of R on S.y: keep[g] = 1 and yid[g] = id iff ry[g] occurs among the y values of its instance
 void semijoin(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, const int32_t* vals_y,
               const int32_t* y_base, int32_t* keep, int32_t* yid, hipStream_t s);
+// same result through a direct-address table over the key space of S.y
+// (table has key_space entries; ykeys/Ey are the y-sorted S keys and their scan)
+void semijoin_direct(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, const uint32_t* ykeys, int64_t ns,
+                     const int32_t* Ey, const int64_t* koff, int64_t key_space, const int32_t* mn, int32_t* table,
+                     int32_t* keep, int32_t* yid, hipStream_t s);
 // stable compaction of R to the kept tuples
 void compact_r(const int32_t* rx, const int32_t* yid, const int32_t* keep, const int32_t* E, int64_t n,
                int32_t* out_x, int32_t* out_y, hipStream_t s);
@@ -72,6 +77,7 @@ void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int
 // ----------------------------------------------------------- row work
 struct RowCtx {
   int n_inst;
+  int64_t max_z_range;     // largest number of z ids of one instance
   const int32_t* x_base;   // [n_inst+1]
   const int32_t* z_base;   // [n_inst+1]
   const int32_t* zd_base;  // [n_inst+1]
@@ -113,8 +119,10 @@ void cold_window_major(const int32_t* cptr, const int32_t* ccol, int64_t n_y, in
                        const int64_t* cwm_off, int64_t cwm_total, int32_t* wptr, int32_t* ccol_w, hipStream_t s,
                        Arena& a);
 
-// per-row work of the sparse part: w[x] = sum over y in R[x] of |S_sparse[y]|
-void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t* w, hipStream_t s);
+// per-row work of the sparse part: w[x] = sum over y in R[x] of |S_sparse[y]|,
+// for rows [x_lo, x_hi) whose CSR entries are [j_lo, j_hi)
+void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, int64_t j_hi, int64_t* w,
+                     hipStream_t s, Arena& a);
 // SparseBMM count (cnt != null) or write (out != null, offsets relative to off[x_lo])
 void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int32_t* cnt,
                 const int64_t* off, int32_t* out, hipStream_t s);
