@@ -95,19 +95,24 @@ def main():
         opt = P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=args.tau, flags=P.JP_FLAG_TIMING)
     stream = torch.cuda.current_stream()
 
-    def step():
+    def step(want_work=False):
         h = P.jp_plan_create(*cols, opt=opt, stream=stream)
         try:
             P.jp_execute(h, stream)
             cnt = P.jp_count(h, stream)
             tm = P.jp_plan_timings(h, stream)
             st = P.jp_plan_stats(h)
+            if want_work:
+                tm.update(P.jp_plan_work(h, stream))
         finally:
             P.jp_plan_destroy(h)
         return cnt, tm, st
 
+    work = None
     for i in range(args.warmup):
-        cnt, tm, st = step()
+        cnt, tm, st = step(want_work=(i == 0))
+        if i == 0:
+            work = tm
         print(f"[bench] warmup {i}: pairs={cnt[0]} dense={cnt[1]} sparse={cnt[2]} tau={st['tau']} "
               f"z_dense={st['n_z_dense']} k_hot={st['k_hot']} exec={tm['execute_ms']:.2f} ms", file=sys.stderr,
               flush=True)
@@ -131,7 +136,9 @@ def main():
     sp_ms = float(np.mean([t["sparse_ms"] for t in tms]))
     de_ms = float(np.mean([t["dense_ms"] for t in tms]))
     ex_ms = float(np.mean([t["execute_ms"] for t in tms]))
-    t = tms[-1]
+    if work is None:  # no warmup step: take the counters from one extra, untimed step
+        work = step(want_work=True)[1]
+    t = work
     if de_ms >= sp_ms:
         ops = t["dense_hot_words"] + t["dense_row_words"] + t["dense_cold_entries"]
         achieved = ops / (de_ms * 1e-3) / 1e12

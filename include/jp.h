@@ -73,8 +73,9 @@ typedef struct {
   int64_t workspace_limit_bytes; /* 0 = no limit; exceeding it returns JP_ENOMEM */
 } jp_options;
 
-/* Kernel times of the last jp_execute (plan built with JP_FLAG_TIMING) and
- * the algorithmic work those kernels did, for roofline accounting. */
+/* Kernel times of the last jp_execute (filled by jp_plan_timings for a plan
+ * built with JP_FLAG_TIMING) and the algorithmic work of those kernels (filled
+ * by jp_plan_work), for roofline accounting. */
 typedef struct {
   float sparse_ms;            /* SparseBMM count kernels */
   float dense_ms;             /* DenseEC count kernel */
@@ -140,9 +141,14 @@ jp_status jp_dense_z(jp_plan* p, int32_t* z_values, hipStream_t stream);
 
 jp_status jp_plan_stats(const jp_plan* p, jp_stats* s);
 
-/* Kernel times and work counters of the last jp_execute; JP_ESTATE unless the
- * plan was created with JP_FLAG_TIMING and executed.  Syncs. */
+/* Kernel times of the last jp_execute into the *_ms fields (others zeroed);
+ * JP_ESTATE unless the plan was created with JP_FLAG_TIMING and executed.  Syncs. */
 jp_status jp_plan_timings(jp_plan* p, jp_timings* t, hipStream_t stream);
+
+/* Algorithmic work counters of the execute kernels into the integer fields of
+ * *t (the *_ms fields are left as they are); JP_ESTATE before jp_execute.
+ * Runs one small kernel.  Syncs. */
+jp_status jp_plan_work(jp_plan* p, jp_timings* t, hipStream_t stream);
 void jp_plan_destroy(jp_plan* p); /* NULL-safe; frees all plan-owned device memory */
 
 const char* jp_last_error(void);

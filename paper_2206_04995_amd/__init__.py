@@ -30,6 +30,7 @@ from .binding import (  # noqa: F401
     jp_plan_destroy,
     jp_plan_stats,
     jp_plan_timings,
+    jp_plan_work,
     jp_row_info,
     last_error,
     lib,

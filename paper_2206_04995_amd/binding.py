@@ -28,7 +28,7 @@ _STATUS = {0: "JP_OK", 1: "JP_EINVAL", 2: "JP_ENOMEM", 3: "JP_EHIP", 4: "JP_ESTA
 # every symbol include/jp.h declares
 EXPORTS = [
     "jp_plan_create", "jp_execute", "jp_count", "jp_materialize", "jp_row_info", "jp_dense_z",
-    "jp_plan_stats", "jp_plan_timings", "jp_plan_destroy", "jp_last_error",
+    "jp_plan_stats", "jp_plan_timings", "jp_plan_work", "jp_plan_destroy", "jp_last_error",
     "jp_batch_create", "jp_batch_execute", "jp_batch_counts", "jp_batch_materialize", "jp_batch_stats",
     "jp_batch_destroy",
 ]
@@ -91,6 +91,7 @@ def _load() -> ctypes.CDLL:
         "jp_dense_z": (st, [vp, i32p, vp]),
         "jp_plan_stats": (st, [vp, ctypes.POINTER(jp_stats)]),
         "jp_plan_timings": (st, [vp, ctypes.POINTER(jp_timings), vp]),
+        "jp_plan_work": (st, [vp, ctypes.POINTER(jp_timings), vp]),
         "jp_plan_destroy": (None, [vp]),
         "jp_last_error": (ctypes.c_char_p, []),
         "jp_batch_create": (st, [ctypes.POINTER(jp_instance), i32, ctypes.POINTER(jp_options), vp, ctypes.POINTER(vp)]),
@@ -210,10 +211,18 @@ def jp_plan_stats(plan: int) -> Dict[str, int]:
 
 
 def jp_plan_timings(plan: int, stream=None) -> Dict[str, float]:
+    """Kernel times (ms) of the last jp_execute of a plan built with JP_FLAG_TIMING."""
     t = jp_timings()
     _check(lib.jp_plan_timings(plan, ctypes.byref(t), _stream(stream)))
-    return {name: (float(getattr(t, name)) if name.endswith("_ms") else int(getattr(t, name)))
-            for name, _ in jp_timings._fields_ if name != "pad_"}
+    return {name: float(getattr(t, name)) for name, _ in jp_timings._fields_ if name.endswith("_ms")}
+
+
+def jp_plan_work(plan: int, stream=None) -> Dict[str, int]:
+    """Algorithmic work counters of the execute kernels."""
+    t = jp_timings()
+    _check(lib.jp_plan_work(plan, ctypes.byref(t), _stream(stream)))
+    return {name: int(getattr(t, name)) for name, _ in jp_timings._fields_
+            if not name.endswith("_ms") and name != "pad_"}
 
 
 def jp_plan_destroy(plan: int):

@@ -497,16 +497,16 @@ void Plan::execute(hipStream_t s) {
     off_de = A.alloc<int64_t>(NX + 1, s);
     off_sp = A.alloc<int64_t>(NX + 1, s);
     tot = A.alloc<int64_t>(3 * int64_t(n_inst), s);
+    heavy_list = A.alloc<int32_t>(NX + 1, s);
   }
   const bool timing = (opt.flags & JP_FLAG_TIMING) != 0;
   if (timing && !ev[0]) {
     for (auto& e : ev) JP_HIP(hipEventCreate(&e));
-    d_work = A.alloc<int64_t>(4, s);
   }
   RowCtx c = ctx();
   if (timing) JP_HIP(hipEventRecord(ev[0], s));
   sparse_row_work(c, 0, NX, 0, NRp, w, s, A);
-  if (NSp > 0) sparse_bmm(c, 0, NX, w, cnt_sp, nullptr, nullptr, s);
+  if (NSp > 0) sparse_bmm(c, 0, NX, w, cnt_sp, nullptr, nullptr, heavy_list, s);
   else fill_i32(cnt_sp, NX, 0, s);
   if (timing) JP_HIP(hipEventRecord(ev[1], s));
   if (NZd > 0) dense_ec(c, 0, NX, cnt_de, nullptr, nullptr, s);
@@ -517,23 +517,28 @@ void Plan::execute(hipStream_t s) {
   scan_excl_i32_to_i64(cnt_de, off_de, NX, s, A);
   scan_excl_i32_to_i64(cnt_sp, off_sp, NX, s, A);
   inst_totals(off_all, off_de, off_sp, x_base, n_inst, tot, s);
-  if (timing) {
-    JP_HIP(hipEventRecord(ev[3], s));
-    work_stats(c, 0, NX, w, d_work, s);
-  }
+  if (timing) JP_HIP(hipEventRecord(ev[3], s));
   executed = true;
   h_tot.clear();
 }
 
 void Plan::timings(jp_timings* t, hipStream_t s) {
   if (!executed || !ev[0]) throw Error(JP_ESTATE, "timings need JP_FLAG_TIMING and a jp_execute");
-  int64_t wk[4];
-  d2h(wk, d_work, 4, s);
   sync(s);
+  std::memset(t, 0, sizeof(*t));
   JP_HIP(hipEventElapsedTime(&t->sparse_ms, ev[0], ev[1]));
   JP_HIP(hipEventElapsedTime(&t->dense_ms, ev[1], ev[2]));
   JP_HIP(hipEventElapsedTime(&t->execute_ms, ev[0], ev[3]));
-  t->pad_ = 0.f;
+}
+
+void Plan::work(jp_timings* t, hipStream_t s) {
+  if (!executed) throw Error(JP_ESTATE, "work counters need a jp_execute");
+  int64_t* d = A.alloc<int64_t>(4, s);
+  work_stats(ctx(), 0, NX, w, d, s);
+  int64_t wk[4];
+  d2h(wk, d, 4, s);
+  sync(s);
+  A.give_back(d, s);
   t->sparse_join_rows = wk[3];
   t->n_r_kept = NRp;
   t->n_x = NX;
@@ -580,7 +585,7 @@ int64_t Plan::materialize(int inst, int part, int64_t first, int64_t maxp, int32
   int32_t* lde = T.alloc<int32_t>(std::max<int64_t>(nde, 1), s);
   int32_t* lsp = T.alloc<int32_t>(std::max<int64_t>(nsp, 1), s);
   if (nde > 0) dense_ec(c, xl, xh, nullptr, off_de, lde, s);
-  if (nsp > 0) sparse_bmm(c, xl, xh, w + xl, nullptr, off_sp, lsp, s);
+  if (nsp > 0) sparse_bmm(c, xl, xh, w + xl, nullptr, off_sp, lsp, T.alloc<int32_t>(xh - xl + 1, s), s);
   if (part == JP_PART_ALL)
     merge_write_n(xl, xh, off_de, off_sp, off_all, lde, lsp, nde, nsp, vals_x, vals_z, g0, g1, ox, oz, s);
   else if (part == JP_PART_DENSE)
@@ -725,6 +730,11 @@ jp_status jp_plan_stats(const jp_plan* p, jp_stats* s) {
 jp_status jp_plan_timings(jp_plan* p, jp_timings* t, hipStream_t stream) {
   if (!p || !t) return fail(JP_EINVAL, "null argument");
   return guarded([&] { p->p.timings(t, stream); });
+}
+
+jp_status jp_plan_work(jp_plan* p, jp_timings* t, hipStream_t stream) {
+  if (!p || !t) return fail(JP_EINVAL, "null argument");
+  return guarded([&] { p->p.work(t, stream); });
 }
 
 void jp_plan_destroy(jp_plan* p) {

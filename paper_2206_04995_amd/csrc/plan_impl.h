@@ -48,7 +48,8 @@ struct Plan {
 
   // JP_FLAG_TIMING: events around the execute kernels and work counters
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  int64_t* d_work = nullptr;
+  int32_t* heavy_list = nullptr;
+  void work(jp_timings* t, hipStream_t s);
 
   ~Plan() {
     for (auto& e : ev)

@@ -196,21 +196,31 @@ __global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__
   }
 }
 
+// list of the heavy rows (order irrelevant: every row owns its output range)
+__global__ void k_collect_heavy(int64_t x_lo, int64_t x_hi, const int64_t* __restrict__ w, int32_t* __restrict__ list,
+                                int32_t* __restrict__ n_list) {
+  for (int64_t x = x_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < x_hi;
+       x += int64_t(gridDim.x) * blockDim.x)
+    if (w[x - x_lo] > LIGHT_MAX) list[atomicAdd(n_list, 1)] = int32_t(x);
+}
+
 // count mode: one workgroup per (heavy row, window blockIdx.y)
 __global__ void __launch_bounds__(NT) k_sparse_heavy_count(const int32_t* __restrict__ rptr,
                                                            const int32_t* __restrict__ rcol,
                                                            const int32_t* __restrict__ spptr,
                                                            const int32_t* __restrict__ spcol, int n_inst,
                                                            const int32_t* __restrict__ x_base,
-                                                           const int32_t* __restrict__ z_base, int64_t x_lo,
-                                                           int64_t x_hi, const int64_t* __restrict__ w,
+                                                           const int32_t* __restrict__ z_base,
+                                                           const int32_t* __restrict__ list,
+                                                           const int32_t* __restrict__ n_list,
                                                            int32_t* __restrict__ cnt) {
   __shared__ uint32_t bm[HB_WORDS];
   __shared__ int red[NT / 64];
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
-  for (int64_t x = x_lo + blockIdx.x; x < x_hi; x += gridDim.x) {
-    if (w[x - x_lo] <= LIGHT_MAX) continue;
+  const int nh = *n_list;
+  for (int i = blockIdx.x; i < nh; i += gridDim.x) {
+    const int64_t x = list[i];
     const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(x_base, n_inst, int32_t(x));
     const int32_t zlo = z_base[inst], zhi = z_base[inst + 1];
     const int64_t wlo64 = int64_t(zlo) + int64_t(blockIdx.y) * HB_BITS;
@@ -243,16 +253,18 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_write(const int32_t* __rest
                                                            const int32_t* __restrict__ spcol, int n_inst,
                                                            const int32_t* __restrict__ x_base,
                                                            const int32_t* __restrict__ z_base, int64_t x_lo,
-                                                           int64_t x_hi, const int64_t* __restrict__ w,
+                                                           const int32_t* __restrict__ list,
+                                                           const int32_t* __restrict__ n_list,
                                                            const int64_t* __restrict__ off, int32_t* __restrict__ out) {
   __shared__ uint32_t bm[HB_WORDS];
   __shared__ int red[NT / 64];
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
   const int64_t base_off = off[x_lo];
+  const int nh = *n_list;
 
-  for (int64_t x = x_lo + blockIdx.x; x < x_hi; x += gridDim.x) {
-    if (w[x - x_lo] <= LIGHT_MAX) continue;
+  for (int i = blockIdx.x; i < nh; i += gridDim.x) {
+    const int64_t x = list[i];
     const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(x_base, n_inst, int32_t(x));
     const int32_t zlo = z_base[inst], zhi = z_base[inst + 1];
     int64_t wpos = off[x] - base_off;
@@ -314,17 +326,24 @@ void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, 
 }
 
 void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int32_t* cnt, const int64_t* off,
-                int32_t* out, hipStream_t s) {
+                int32_t* out, int32_t* heavy_list, hipStream_t s) {
   int64_t n = x_hi - x_lo;
   if (n <= 0) return;
   int gl = int(std::min<int64_t>((n + 3) / 4, 1 << 15));
   int gh = int(std::min<int64_t>(n, 1024));
+  // heavy_list holds n + 1 ints: the count, then the rows
+  int32_t* n_list = heavy_list;
+  int32_t* list = heavy_list + 1;
+  fill_i32(n_list, 1, 0, s);
+  hipLaunchKernelGGL(k_collect_heavy, dim3(int(std::min<int64_t>((n + NT - 1) / NT, 4096))), dim3(NT), 0, s, x_lo, x_hi,
+                     w, list, n_list);
+  JP_LAUNCH_CHECK();
   if (out) {
     hipLaunchKernelGGL(k_sparse_light<true>, dim3(gl), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, x_lo, x_hi, w,
                        cnt, off, out);
     JP_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sparse_heavy_write, dim3(gh), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, c.n_inst,
-                       c.x_base, c.z_base, x_lo, x_hi, w, off, out);
+                       c.x_base, c.z_base, x_lo, list, n_list, off, out);
     JP_LAUNCH_CHECK();
   } else {
     hipLaunchKernelGGL(k_sparse_light<false>, dim3(gl), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, x_lo, x_hi,
@@ -332,7 +351,7 @@ void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
     JP_LAUNCH_CHECK();
     const int wins = int(std::max<int64_t>(1, (c.max_z_range + HB_BITS - 1) / HB_BITS));
     hipLaunchKernelGGL(k_sparse_heavy_count, dim3(gh, wins), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol,
-                       c.n_inst, c.x_base, c.z_base, x_lo, x_hi, w, cnt);
+                       c.n_inst, c.x_base, c.z_base, list, n_list, cnt);
     JP_LAUNCH_CHECK();
   }
 }
