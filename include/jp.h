@@ -181,6 +181,54 @@ jp_status jp_batch_materialize(jp_batch* b, int32_t inst, jp_part part, int64_t 
 jp_status jp_batch_stats(const jp_batch* b, int32_t inst, jp_stats* s);
 void jp_batch_destroy(jp_batch* b);
 
+/* -------------------------------------------------------------- server --- */
+
+/* A query server: a host thread that admits submitted queries while their
+ * estimated device footprint fits an HBM budget, plans every admitted group
+ * as one batch (continuous batching: queries that arrive while a batch runs
+ * join the next one) and overlaps the planning of one batch with the
+ * execution of the previous one on a second stream.  Results are counts. */
+typedef struct jp_server jp_server;
+
+typedef struct {
+  int32_t device;           /* HIP device the server runs on */
+  int32_t max_batch;        /* most queries per batch (0 = 4096) */
+  int64_t hbm_budget_bytes; /* device memory the in-flight batches may hold (0 = 64 GiB) */
+  jp_options opt;           /* options of every batch */
+} jp_server_config;
+
+typedef struct {
+  int64_t total, dense, sparse; /* pair counts */
+  int32_t status;               /* jp_status of the query */
+  int32_t batch_size;           /* queries in the batch that carried it */
+  double submit_us, admit_us, done_us; /* host clock, microseconds since the server started */
+} jp_query_result;
+
+typedef struct {
+  int64_t submitted, completed, failed, batches;
+  int64_t pairs;           /* pairs over completed queries */
+  int64_t peak_bytes;      /* largest device footprint of the in-flight batches */
+  double p50_us, p99_us, mean_us; /* latency submit -> done over completed queries */
+} jp_server_summary;
+
+/* Starts the server thread.  Syncs nothing on the caller's streams. */
+jp_status jp_server_create(const jp_server_config* cfg, jp_server** out);
+
+/* Queues one query.  q holds device columns as in jp_plan_create; they must
+ * stay valid until the query is done.  JP_EBUSY if the server is stopping. */
+jp_status jp_server_submit(jp_server* s, const jp_instance* q, uint64_t* ticket);
+
+/* *done = 1 and *r filled once the query has finished; non-blocking. */
+jp_status jp_server_poll(jp_server* s, uint64_t ticket, int* done, jp_query_result* r);
+
+/* Blocks until the query has finished, then fills *r. */
+jp_status jp_server_wait(jp_server* s, uint64_t ticket, jp_query_result* r);
+
+jp_status jp_server_stats(jp_server* s, jp_server_summary* st);
+
+/* Finishes the queued queries, stops the thread, frees everything (NULL-safe). */
+void jp_server_destroy(jp_server* s);
+
 #ifdef __cplusplus
 }
 #endif

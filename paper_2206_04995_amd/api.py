@@ -117,3 +117,49 @@ def join_project(r_x, r_y, s_z, s_y, opt: Optional[B.jp_options] = None, stream=
     with Plan(r_x, r_y, s_z, s_y, opt, stream) as p:
         p.execute()
         return p.materialize()
+
+
+class Server:
+    """Continuous-batching query server (counts), see jp_server_* in include/jp.h."""
+
+    def __init__(self, device: int = 0, max_batch: int = 0, hbm_budget_bytes: int = 0,
+                 opt: Optional[B.jp_options] = None):
+        self.h = B.jp_server_create(device, max_batch, hbm_budget_bytes, opt)
+        self._keep = {}
+
+    def submit(self, r_x, r_y, s_z, s_y) -> int:
+        t = B.jp_server_submit(self.h, r_x, r_y, s_z, s_y)
+        self._keep[t] = (r_x, r_y, s_z, s_y)  # device columns stay alive until the query is done
+        return t
+
+    def poll(self, ticket: int):
+        r = B.jp_server_poll(self.h, ticket)
+        if r is not None:
+            self._keep.pop(ticket, None)
+        return r
+
+    def wait(self, ticket: int):
+        r = B.jp_server_wait(self.h, ticket)
+        self._keep.pop(ticket, None)
+        return r
+
+    def stats(self):
+        return B.jp_server_stats(self.h)
+
+    def close(self):
+        if self.h:
+            B.jp_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -31,6 +31,7 @@ EXPORTS = [
     "jp_plan_stats", "jp_plan_timings", "jp_plan_work", "jp_plan_destroy", "jp_last_error",
     "jp_batch_create", "jp_batch_execute", "jp_batch_counts", "jp_batch_materialize", "jp_batch_stats",
     "jp_batch_destroy",
+    "jp_server_create", "jp_server_submit", "jp_server_poll", "jp_server_wait", "jp_server_stats", "jp_server_destroy",
 ]
 
 
@@ -70,6 +71,22 @@ class jp_instance(ctypes.Structure):
     ]
 
 
+class jp_server_config(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
+                ("opt", jp_options)]
+
+
+class jp_query_result(ctypes.Structure):
+    _fields_ = [("total", ctypes.c_int64), ("dense", ctypes.c_int64), ("sparse", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("submit_us", ctypes.c_double),
+                ("admit_us", ctypes.c_double), ("done_us", ctypes.c_double)]
+
+
+class jp_server_summary(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "batches", "pairs", "peak_bytes")] + [
+        (n, ctypes.c_double) for n in ("p50_us", "p99_us", "mean_us")]
+
+
 def _load() -> ctypes.CDLL:
     # libjp.so must bind to the HIP runtime torch uses (both carry the soname
     # libamdhip64.so.7); a second runtime mapped into the process sees no device.
@@ -100,6 +117,12 @@ def _load() -> ctypes.CDLL:
         "jp_batch_materialize": (st, [vp, i32, ctypes.c_int, i64, i64, vp, vp, i64p, vp]),
         "jp_batch_stats": (st, [vp, i32, ctypes.POINTER(jp_stats)]),
         "jp_batch_destroy": (None, [vp]),
+        "jp_server_create": (st, [ctypes.POINTER(jp_server_config), ctypes.POINTER(vp)]),
+        "jp_server_submit": (st, [vp, ctypes.POINTER(jp_instance), ctypes.POINTER(ctypes.c_uint64)]),
+        "jp_server_poll": (st, [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(jp_query_result)]),
+        "jp_server_wait": (st, [vp, ctypes.c_uint64, ctypes.POINTER(jp_query_result)]),
+        "jp_server_stats": (st, [vp, ctypes.POINTER(jp_server_summary)]),
+        "jp_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -276,3 +299,52 @@ def jp_batch_stats(batch: int, inst: int) -> Dict[str, int]:
 
 def jp_batch_destroy(batch: int):
     lib.jp_batch_destroy(batch)
+
+
+# ---------------------------------------------------------------- server
+
+
+def _result_dict(r: jp_query_result) -> Dict[str, float]:
+    return {name: getattr(r, name) for name, _ in jp_query_result._fields_}
+
+
+def jp_server_create(device: int = 0, max_batch: int = 0, hbm_budget_bytes: int = 0,
+                     opt: Optional[jp_options] = None) -> int:
+    cfg = jp_server_config()
+    cfg.device = device
+    cfg.max_batch = max_batch
+    cfg.hbm_budget_bytes = hbm_budget_bytes
+    cfg.opt = opt if opt is not None else make_options()
+    h = ctypes.c_void_p()
+    _check(lib.jp_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h.value
+
+
+def jp_server_submit(server: int, r_x, r_y, s_z, s_y) -> int:
+    arr = _instances([(r_x, r_y, s_z, s_y)])
+    t = ctypes.c_uint64()
+    _check(lib.jp_server_submit(server, arr, ctypes.byref(t)))
+    return t.value
+
+
+def jp_server_poll(server: int, ticket: int):
+    done = ctypes.c_int()
+    r = jp_query_result()
+    _check(lib.jp_server_poll(server, ticket, ctypes.byref(done), ctypes.byref(r)))
+    return (_result_dict(r) if done.value else None)
+
+
+def jp_server_wait(server: int, ticket: int) -> Dict[str, float]:
+    r = jp_query_result()
+    _check(lib.jp_server_wait(server, ticket, ctypes.byref(r)))
+    return _result_dict(r)
+
+
+def jp_server_stats(server: int) -> Dict[str, float]:
+    s = jp_server_summary()
+    _check(lib.jp_server_stats(server, ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in jp_server_summary._fields_}
+
+
+def jp_server_destroy(server: int):
+    lib.jp_server_destroy(server)

@@ -21,6 +21,7 @@ SOURCES = [
     "dense_ec.hip",
     "output.hip",
     "plan.cpp",
+    "server.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

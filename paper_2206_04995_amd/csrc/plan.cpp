@@ -101,6 +101,8 @@ inline int grid_of(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t
 
 namespace jp {
 
+void set_last_error(const std::string& m) { g_last_error = m; }
+
 // Threshold tau of f2 (paper Sec. 2.6): a z is dense iff T_sparseBMM(z) >
 // T_denseEC(z).  With OUT_{J,z} estimated as m_z / |S| * OUT_J (as in the
 // paper), T_sparseBMM(z) = c_fix / |Z| + c_sp * m_z / |S| * OUT_J and

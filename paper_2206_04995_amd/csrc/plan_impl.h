@@ -2,6 +2,7 @@
 // Join-Project instances after mapping and partition, plus execute results.
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "../../include/jp.h"
@@ -11,6 +12,7 @@
 namespace jp {
 
 void gather_values(const int32_t* vals, const int32_t* idx, int64_t n, int32_t* out, hipStream_t s);
+void set_last_error(const std::string& m);  // message returned by jp_last_error() on this thread
 
 struct Plan {
   Arena A;
