@@ -62,6 +62,9 @@ typedef enum {
 
 /* jp_options.flags bits */
 #define JP_FLAG_TIMING 1 /* record HIP events around the kernels of jp_execute (see jp_plan_timings) */
+#define JP_FLAG_GRAPH 2  /* record the count pass of the second jp_execute into a HIP graph and
+                            replay it on later calls: no allocation and one launch per call after
+                            the first; results are identical; JP_FLAG_TIMING is ignored with it */
 
 /* Options; an all-zero struct (or NULL) selects every default. */
 typedef struct {

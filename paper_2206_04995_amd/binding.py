@@ -21,6 +21,7 @@ JP_PART_ALL, JP_PART_DENSE, JP_PART_SPARSE = 0, 1, 2
 JP_TAU_AUTO, JP_TAU_FIXED = 0, 1
 JP_DENSE_AUTO, JP_DENSE_BITS, JP_DENSE_MFMA = 0, 1, 2
 JP_FLAG_TIMING = 1
+JP_FLAG_GRAPH = 2
 INT64_MAX = 2 ** 63 - 1
 
 _STATUS = {0: "JP_OK", 1: "JP_EINVAL", 2: "JP_ENOMEM", 3: "JP_EHIP", 4: "JP_ESTATE", 5: "JP_ERANGE", 6: "JP_EBUSY"}

@@ -500,14 +500,45 @@ void Plan::execute(hipStream_t s) {
     off_sp = A.alloc<int64_t>(NX + 1, s);
     tot = A.alloc<int64_t>(3 * int64_t(n_inst), s);
     heavy_list = A.alloc<int32_t>(NX + 1, s);
+    XA.set_replay(true);
   }
-  const bool timing = (opt.flags & JP_FLAG_TIMING) != 0;
+  const bool graph = (opt.flags & JP_FLAG_GRAPH) != 0;
+  const bool timing = (opt.flags & JP_FLAG_TIMING) != 0 && !graph;
   if (timing && !ev[0]) {
     for (auto& e : ev) JP_HIP(hipEventCreate(&e));
   }
+  if (graph && graph_exec) {
+    JP_HIP(hipGraphLaunch(graph_exec, s));
+  } else if (graph && warm) {
+    // Second run: every temporary is a replayed block, so the pass records
+    // without allocating.  It is recorded on a private stream (the caller's may
+    // be the null stream, which cannot capture) and launched on the caller's.
+    if (!cap_stream) JP_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+    JP_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      run_count_pass(cap_stream, false);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    JP_HIP(hipStreamEndCapture(cap_stream, &graph_));
+    JP_HIP(hipGraphInstantiate(&graph_exec, graph_, nullptr, nullptr, 0));
+    JP_HIP(hipGraphLaunch(graph_exec, s));
+  } else {
+    run_count_pass(s, timing);
+  }
+  warm = true;
+  executed = true;
+  h_tot.clear();
+}
+
+void Plan::run_count_pass(hipStream_t s, bool timing) {
+  XA.rewind();
   RowCtx c = ctx();
   if (timing) JP_HIP(hipEventRecord(ev[0], s));
-  sparse_row_work(c, 0, NX, 0, NRp, w, s, A);
+  sparse_row_work(c, 0, NX, 0, NRp, w, s, XA);
   if (NSp > 0) sparse_bmm(c, 0, NX, w, cnt_sp, nullptr, nullptr, heavy_list, s);
   else fill_i32(cnt_sp, NX, 0, s);
   if (timing) JP_HIP(hipEventRecord(ev[1], s));
@@ -515,13 +546,11 @@ void Plan::execute(hipStream_t s) {
   else fill_i32(cnt_de, NX, 0, s);
   if (timing) JP_HIP(hipEventRecord(ev[2], s));
   add_counts(cnt_sp, cnt_de, NX, cnt_all, s);
-  scan_excl_i32_to_i64(cnt_all, off_all, NX, s, A);
-  scan_excl_i32_to_i64(cnt_de, off_de, NX, s, A);
-  scan_excl_i32_to_i64(cnt_sp, off_sp, NX, s, A);
+  scan_excl_i32_to_i64(cnt_all, off_all, NX, s, XA);
+  scan_excl_i32_to_i64(cnt_de, off_de, NX, s, XA);
+  scan_excl_i32_to_i64(cnt_sp, off_sp, NX, s, XA);
   inst_totals(off_all, off_de, off_sp, x_base, n_inst, tot, s);
   if (timing) JP_HIP(hipEventRecord(ev[3], s));
-  executed = true;
-  h_tot.clear();
 }
 
 void Plan::timings(jp_timings* t, hipStream_t s) {
@@ -636,7 +665,7 @@ jp_status check_opt(const jp_options* o) {
   if (o->tau_mode != JP_TAU_AUTO && o->tau_mode != JP_TAU_FIXED) return fail(JP_EINVAL, "bad tau_mode");
   if (o->dense_kernel < 0 || o->dense_kernel > 2) return fail(JP_EINVAL, "bad dense_kernel");
   if (o->k_hot_max < 0 || o->k_hot_max > 1024) return fail(JP_EINVAL, "k_hot_max must be in [0, 1024]");
-  if (o->flags & ~JP_FLAG_TIMING) return fail(JP_EINVAL, "unknown flag bits");
+  if (o->flags & ~(JP_FLAG_TIMING | JP_FLAG_GRAPH)) return fail(JP_EINVAL, "unknown flag bits");
   if (o->workspace_limit_bytes < 0) return fail(JP_EINVAL, "negative workspace limit");
   if (o->tau_mode == JP_TAU_FIXED && o->dense_threshold < -1) return fail(JP_EINVAL, "dense_threshold < -1");
   return JP_OK;

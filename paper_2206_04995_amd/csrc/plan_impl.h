@@ -53,13 +53,28 @@ struct Plan {
   int32_t* heavy_list = nullptr;
   void work(jp_timings* t, hipStream_t s);
 
+  // temporaries of the count pass, replayed on every execute (see Arena)
+  Arena XA;
+  bool warm = false;
+  hipGraph_t graph_ = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  void run_count_pass(hipStream_t s, bool timing);
+
   ~Plan() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    XA.release(stream);
     A.release(stream);
   }
   void timings(jp_timings* t, hipStream_t s);
-  void arena_limit(int64_t lim) { A.set_limit(lim); }
+  void arena_limit(int64_t lim) {
+    A.set_limit(lim);
+    XA.set_limit(lim);
+  }
   void build(const jp_instance* inst, int n, const jp_options* o, hipStream_t s);
   void map(hipStream_t s);
   void partition(hipStream_t s);

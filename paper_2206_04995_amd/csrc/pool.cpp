@@ -86,16 +86,24 @@ void Pool::trim() {
 
 void* Arena::raw(size_t bytes, hipStream_t s) {
   size_t r = round_alloc(bytes);
+  if (replay_ && cursor_ < recs_.size()) {
+    Rec& rec = recs_[cursor_];
+    if (rec.bytes < r) throw Error(4, "replayed allocation sequence changed");
+    ++cursor_;
+    return rec.p;
+  }
   if (limit_ > 0 && bytes_ + int64_t(r) > limit_)
     throw Error(2, "workspace limit of " + std::to_string(limit_) + " bytes exceeded");
   void* p = Pool::instance().alloc(bytes, s);
   recs_.push_back({p, r});
+  if (replay_) cursor_ = recs_.size();
   bytes_ += int64_t(r);
   if (bytes_ > peak_) peak_ = bytes_;
   return p;
 }
 
 void Arena::give_back(void* p, hipStream_t s) {
+  if (replay_) return;  // kept for the next pass
   for (size_t i = 0; i < recs_.size(); ++i) {
     if (recs_[i].p == p) {
       bytes_ -= int64_t(recs_[i].bytes);
@@ -111,6 +119,7 @@ void Arena::release(hipStream_t s) {
   for (auto& r : recs_) Pool::instance().free(r.p, s);
   recs_.clear();
   bytes_ = 0;
+  cursor_ = 0;
 }
 
 }  // namespace jp

@@ -73,6 +73,13 @@ class Arena {
   int64_t bytes() const { return bytes_; }
   int64_t peak() const { return peak_; }
 
+  // Replay mode: the first pass records its allocations and keeps them
+  // (give_back does nothing); every later pass, started by rewind(), gets the
+  // same blocks in the same order without touching the allocator, so the
+  // pass can be captured into a graph or run where allocation is not allowed.
+  void set_replay(bool on) { replay_ = on; }
+  void rewind() { cursor_ = 0; }
+
  private:
   struct Rec {
     void* p;
@@ -82,6 +89,8 @@ class Arena {
   int64_t limit_;
   int64_t bytes_ = 0;
   int64_t peak_ = 0;
+  bool replay_ = false;
+  size_t cursor_ = 0;
 };
 
 inline size_t round_alloc(size_t b) {

@@ -51,7 +51,7 @@ def test_invalid_arguments_rejected_before_device_work():
             setattr(o, k, v)
         assert lib.jp_plan_create(one, one, 1, one, one, 1, ctypes.byref(o), None, ctypes.byref(h)) == B.JP_EINVAL
     o = P.make_options()
-    o.flags = 2  # not a defined JP_FLAG_* bit
+    o.flags = 4  # not a defined JP_FLAG_* bit
     assert lib.jp_plan_create(one, one, 1, one, one, 1, ctypes.byref(o), None, ctypes.byref(h)) == B.JP_EINVAL
     # null plan everywhere
     n = ctypes.c_int64()
