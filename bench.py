@@ -262,6 +262,8 @@ def main():
     ap.add_argument("--cpu-sample-mod", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tau", type=int, default=None, help="fixed dense threshold (default: cost model)")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="first run one plain elementwise copy over this many MiB (a reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -284,6 +286,16 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     cols = [torch.from_numpy(c).to(dev) for c in (inst.rx, inst.ry, inst.sz, inst.sy)]
+    if args.copy_ref_mib > 0:
+        # one kernel that reads and writes exactly copy_ref_mib MiB each
+        src = torch.ones(args.copy_ref_mib << 18, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.bitwise_not(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] copy reference: {args.copy_ref_mib} MiB read + written by one bitwise_not kernel",
+              file=sys.stderr, flush=True)
     if args.tau is None:
         opt = P.make_options(flags=P.JP_FLAG_TIMING)
     else:

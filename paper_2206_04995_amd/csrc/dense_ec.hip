@@ -10,13 +10,18 @@
 // LDS copy of the window.  The window is then popcounted (count mode) or
 // written out in z order (write mode).
 //
-// A workgroup owns 128 consecutive rows and walks the windows in order.  The
+// A workgroup owns 128 consecutive rows and a group of consecutive windows;
+// the grid is ordered window-group-major, so the workgroups resident at one
+// time all read the same few windows of the hot rows and of the cold table,
+// which then stay in each XCD's L2 instead of streaming from HBM.  The
 // window slices of the T_STAGE hot keys shared by the most rows are staged in
 // LDS once per window for all 128 rows; rarer hot keys are read from the
 // caches.  Per-entry codes (hot rank / cold key) stay in registers across the
 // windows, and the cold entries are stored window-major with per-(window, key)
 // segment bounds, so the 64 lanes of a wave split a row's cold entries evenly
 // and one window's cold data is a compact, cache-resident range.
+#include <cstdlib>
+
 #include "common.h"
 #include "prim.h"
 #include "stages.h"
@@ -95,8 +100,9 @@ __device__ __forceinline__ void cold_scatter(int s0, int len, const int32_t* __r
 }
 
 template <bool WRITE>
-__global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, int64_t x_hi, int32_t* __restrict__ cnt,
-                                                   const int64_t* __restrict__ off, int32_t* __restrict__ out) {
+__global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, int64_t x_hi, int wgroup,
+                                                   int32_t* __restrict__ cnt, const int64_t* __restrict__ off,
+                                                   int32_t* __restrict__ out) {
   __shared__ uint4 stage[T_STAGE][QW];
   __shared__ uint4 rowbuf_all[WAVES][QW];
   __shared__ int s_maxwin[WAVES];
@@ -145,7 +151,9 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
 #pragma unroll
   for (int i = 0; i < WAVES; ++i) maxwin = s_maxwin[i] > maxwin ? s_maxwin[i] : maxwin;
 
-  for (int w = 0; w < maxwin; ++w) {
+  const int w_lo = int(blockIdx.y) * wgroup;
+  const int w_hi = maxwin < w_lo + wgroup ? maxwin : w_lo + wgroup;
+  for (int w = w_lo; w < w_hi; ++w) {
     const int32_t wstart = w * DW_BITS;
     __syncthreads();
     if (w < nwin0) {
@@ -245,7 +253,10 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
       }
     }
   }
-  if (!WRITE && lane < nrows) cnt[r0 + lane] = int32_t(my_acc);
+  if (!WRITE && lane < nrows) {
+    if (gridDim.y == 1) cnt[r0 + lane] = int32_t(my_acc);
+    else if (my_acc) atomicAdd(&cnt[r0 + lane], int32_t(my_acc));
+  }
 }
 
 // Algorithmic work of the count kernels (for roofline accounting):
@@ -294,6 +305,20 @@ __global__ void k_work_stats(RowCtx c, int64_t x_lo, int64_t x_hi, const int64_t
 
 }  // namespace
 
+// Windows per workgroup of the count kernel: as many as keep the hot-row
+// slices of the windows in flight within about 512 KiB of an XCD's 4 MiB L2
+// (each hot key holds DW_WORDS words per window).
+int dense_window_group(int64_t max_hot, int nwin) {
+  static const int env = [] {
+    const char* e = std::getenv("JP_DENSE_WINDOW_GROUP");
+    return e ? std::atoi(e) : 0;
+  }();
+  int64_t g = env > 0 ? env : (int64_t(1) << 19) / ((max_hot > 0 ? max_hot : 1) * DW_WORDS * 4);
+  if (g < 1) g = 1;
+  if (g > nwin) g = nwin > 0 ? nwin : 1;
+  return int(g);
+}
+
 void work_stats(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int64_t* out4, hipStream_t s) {
   fill_i64(out4, 4, 0, s);
   int64_t n = x_hi - x_lo;
@@ -309,10 +334,16 @@ void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const i
   int64_t n = x_hi - x_lo;
   if (n <= 0) return;
   int g = int((n + RB - 1) / RB);
-  if (out)
-    hipLaunchKernelGGL(k_dense_bits<true>, dim3(g), dim3(NT), 0, s, c, x_lo, x_hi, cnt, off, out);
-  else
-    hipLaunchKernelGGL(k_dense_bits<false>, dim3(g), dim3(NT), 0, s, c, x_lo, x_hi, cnt, off, out);
+  if (out) {  // write mode emits each row's windows in order: one group
+    hipLaunchKernelGGL(k_dense_bits<true>, dim3(g), dim3(NT), 0, s, c, x_lo, x_hi, INT32_MAX, cnt, off, out);
+  } else {
+    const int nwin = int((c.max_zd_range + DW_BITS - 1) / DW_BITS);
+    const int wg = dense_window_group(c.max_hot, nwin);
+    const int ng = (nwin + wg - 1) / wg;
+    if (ng > 1) fill_i32(cnt + x_lo, n, 0, s);
+    hipLaunchKernelGGL(k_dense_bits<false>, dim3(g, ng > 0 ? ng : 1), dim3(NT), 0, s, c, x_lo, x_hi, wg, cnt, off,
+                       out);
+  }
   JP_LAUNCH_CHECK();
 }
 

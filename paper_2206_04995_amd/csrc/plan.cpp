@@ -462,7 +462,13 @@ RowCtx Plan::ctx() const {
   RowCtx c;
   c.n_inst = n_inst;
   c.max_z_range = 0;
-  for (int i = 0; i < n_inst; ++i) c.max_z_range = std::max<int64_t>(c.max_z_range, h_zbase[i + 1] - h_zbase[i]);
+  c.max_zd_range = 0;
+  c.max_hot = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    c.max_z_range = std::max<int64_t>(c.max_z_range, h_zbase[i + 1] - h_zbase[i]);
+    c.max_zd_range = std::max<int64_t>(c.max_zd_range, h_zdbase[i + 1] - h_zdbase[i]);
+    c.max_hot = std::max<int64_t>(c.max_hot, h_K[i]);
+  }
   c.x_base = x_base;
   c.z_base = z_base;
   c.zd_base = zd_base;

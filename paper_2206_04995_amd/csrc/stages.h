@@ -78,6 +78,8 @@ void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int
 struct RowCtx {
   int n_inst;
   int64_t max_z_range;     // largest number of z ids of one instance
+  int64_t max_zd_range;    // largest number of dense z ids of one instance
+  int64_t max_hot;         // largest number of hot keys of one instance
   const int32_t* x_base;   // [n_inst+1]
   const int32_t* z_base;   // [n_inst+1]
   const int32_t* zd_base;  // [n_inst+1]
@@ -130,6 +132,8 @@ void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
 // DenseEC count or write, bit-packed hot rows
 void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const int64_t* off, int32_t* out,
               hipStream_t s);
+// windows per workgroup of the DenseEC count kernel (JP_DENSE_WINDOW_GROUP overrides)
+int dense_window_group(int64_t max_hot, int nwin);
 
 // algorithmic work of the count kernels over rows [x_lo, x_hi) (see jp_timings)
 void work_stats(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int64_t* out4, hipStream_t s);
