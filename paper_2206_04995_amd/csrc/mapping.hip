@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(NT) k_histogram(const uint32_t* __restrict__ v
     const uint32_t k = v[i];
     uint32_t s = (k * 0x9E3779B1u) >> 20;  // 12-bit slot
     bool done = false;
-    for (int probe = 0; probe < 8 && !done; ++probe) {
+    for (int probe = 0; probe < 2 && !done; ++probe) {
       uint32_t old = atomicCAS(&key[s], 0xFFFFFFFFu, k);
       if (old == 0xFFFFFFFFu || old == k) {
         atomicAdd(&cnt[s], 1);
@@ -160,6 +160,21 @@ __global__ void __launch_bounds__(NT) k_histogram(const uint32_t* __restrict__ v
 
 __global__ void k_out_j(const int32_t* __restrict__ dR, const int32_t* __restrict__ dS, int64_t n_y,
                         const int32_t* __restrict__ y_base, int n_inst, int64_t* __restrict__ out_j) {
+  if (n_inst == 1) {  // grid-stride sum, one atomic per block
+    __shared__ int64_t s_part[NT / 64];
+    int64_t acc = 0;
+    for (int64_t y = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; y < n_y; y += int64_t(gridDim.x) * blockDim.x)
+      acc += int64_t(dR[y]) * int64_t(dS[y]);
+    acc = wave_sum(acc);
+    if (lane_id() == 0) s_part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t t = 0;
+      for (int w = 0; w < NT / 64; ++w) t += s_part[w];
+      if (t) atomicAdd((unsigned long long*)&out_j[0], (unsigned long long)t);
+    }
+    return;
+  }
   for (int64_t b = int64_t(blockIdx.x) * blockDim.x; b < n_y; b += int64_t(gridDim.x) * blockDim.x) {
     const int64_t y = b + threadIdx.x;
     int64_t prod = 0;
@@ -262,7 +277,8 @@ void out_j_per_inst(const int32_t* dR, const int32_t* dS, int64_t n_y, const int
                     int64_t* out_j, hipStream_t s) {
   fill_i64(out_j, n_inst, 0, s);
   if (n_y <= 0) return;
-  hipLaunchKernelGGL(k_out_j, dim3(grid(n_y)), dim3(NT), 0, s, dR, dS, n_y, y_base, n_inst, out_j);
+  hipLaunchKernelGGL(k_out_j, dim3(n_inst == 1 ? grid(n_y, 1024) : grid(n_y)), dim3(NT), 0, s, dR, dS, n_y, y_base,
+                     n_inst, out_j);
   JP_LAUNCH_CHECK();
 }
 

@@ -152,13 +152,18 @@ __global__ void k_hot_rank(const int32_t* __restrict__ hotlist, int64_t n_hot, c
   }
 }
 
-__global__ void k_row_codes(const int32_t* __restrict__ rcol, int64_t n, const int32_t* __restrict__ hotrow,
-                            const int32_t* __restrict__ cptr, int32_t* __restrict__ rcode) {
-  GRID_STRIDE(j, n) {
-    const int32_t y = rcol[j];
+// code of each join key (coalesced over y), then one gather per R entry
+__global__ void k_key_codes(const int32_t* __restrict__ hotrow, const int32_t* __restrict__ cptr, int64_t n_y,
+                            int32_t* __restrict__ ycode) {
+  GRID_STRIDE(y, n_y) {
     const int32_t h = hotrow[y];
-    rcode[j] = h >= 0 ? h : (cptr[y + 1] > cptr[y] ? -2 - y : -1);
+    ycode[y] = h >= 0 ? h : (cptr[y + 1] > cptr[y] ? int32_t(-2 - y) : -1);
   }
+}
+
+__global__ void k_row_codes(const int32_t* __restrict__ rcol, int64_t n, const int32_t* __restrict__ ycode,
+                            int32_t* __restrict__ rcode) {
+  GRID_STRIDE(j, n) rcode[j] = ycode[rcol[j]];
 }
 
 // every table slot is written exactly once: by the first entry of y at or
@@ -330,10 +335,12 @@ void hot_rank(const int32_t* hot, const int32_t* Ehot, int64_t n_y, int64_t n_ho
   JP_LAUNCH_CHECK();
 }
 
-void row_codes(const int32_t* rcol, int64_t n, const int32_t* hotrow, const int32_t* cptr, int32_t* rcode,
-               hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_row_codes, dim3(grid(n)), dim3(NT), 0, s, rcol, n, hotrow, cptr, rcode);
+void row_codes(const int32_t* rcol, int64_t n, const int32_t* hotrow, const int32_t* cptr, int64_t n_y,
+               int32_t* ycode, int32_t* rcode, hipStream_t s) {
+  if (n <= 0 || n_y <= 0) return;
+  hipLaunchKernelGGL(k_key_codes, dim3(grid(n_y)), dim3(NT), 0, s, hotrow, cptr, n_y, ycode);
+  JP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_row_codes, dim3(grid(n)), dim3(NT), 0, s, rcol, n, ycode, rcode);
   JP_LAUNCH_CHECK();
 }
 

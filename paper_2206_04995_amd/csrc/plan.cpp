@@ -363,6 +363,40 @@ void Plan::partition(hipStream_t s) {
   spcol = A.alloc<int32_t>(std::max<int64_t>(NSp, 1), s);
   compact_entries(scol, fl, Esp, NS, Edz, z_base, zd_base, n, false, spcol, s);
 
+  if (NZd == 0) {
+    // no dense z in any instance: DenseEC has no work, its tables stay empty
+    h_theta.assign(n, INT64_MAX);
+    h_K.assign(n, 0);
+    h_roww.assign(n, 0);
+    h_hboff.assign(n, 0);
+    d_theta = A.alloc<int64_t>(n, s);
+    fill_i64(d_theta, n, INT64_MAX, s);
+    d_hboff = A.alloc<int64_t>(n, s);
+    fill_i64(d_hboff, n, 0, s);
+    d_roww = A.alloc<int32_t>(n, s);
+    fill_i32(d_roww, n, 0, s);
+    d_cwmoff = A.alloc<int64_t>(n, s);
+    fill_i64(d_cwmoff, n, 0, s);
+    Ehot = A.alloc<int32_t>(NY + 1, s);
+    fill_i32(Ehot, NY + 1, 0, s);
+    hotrow = A.alloc<int32_t>(NYa, s);
+    fill_i32(hotrow, NYa, -1, s);
+    cptr = A.alloc<int32_t>(NY + 1, s);
+    fill_i32(cptr, NY + 1, 0, s);
+    NHb = 0;
+    hb = A.alloc<uint32_t>(4, s);
+    fill_u32(hb, 4, 0u, s);
+    NCold = 0;
+    ccol = A.alloc<int32_t>(1, s);
+    fill_i32(ccol, 1, 0, s);
+    wptr = A.alloc<int32_t>(1, s);
+    fill_i32(wptr, 1, 0, s);
+    rcode = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
+    fill_i32(rcode, std::max<int64_t>(NRp, 1), -1, s);
+    T.release(s);
+    return;
+  }
+
   // hot join keys of DenseEC: dense S row covering at least theta of the dense z
   const int kmax = opt.k_hot_max > 0 ? std::min(opt.k_hot_max, 1024) : 256;
   const double hot_frac = env_double("JP_HOT_MIN_FRACTION", 1.0 / 128.0);
@@ -454,7 +488,8 @@ void Plan::partition(hipStream_t s) {
     fill_i32(wptr, 1, 0, s);
   }
   rcode = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
-  row_codes(rcol, NRp, hotrow, cptr, rcode, s);
+  int32_t* ycode = T.alloc<int32_t>(NYa, s);
+  row_codes(rcol, NRp, hotrow, cptr, NY, ycode, rcode, s);
   T.release(s);
 }
 

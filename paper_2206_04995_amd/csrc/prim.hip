@@ -234,17 +234,53 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     p[i] = v;
 }
 
-constexpr int MM_CH = 16;
+// Per-segment min and max.  A block owns a contiguous chunk of MM_CHUNK
+// elements read with coalesced, strided loads.  When the chunk lies in one
+// segment (the common case: few, large segments) the block reduces through
+// LDS and issues one atomic pair; otherwise each thread tracks the segment of
+// its (increasing) elements and flushes at every change.
+constexpr int MM_NT = 256;
+constexpr int MM_CHUNK = MM_NT * 64;
 
-__global__ void k_seg_minmax(const int32_t* __restrict__ v, int64_t n, const int32_t* __restrict__ base,
-                             int n_seg, int32_t* __restrict__ mn, int32_t* __restrict__ mx) {
-  int64_t start = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * MM_CH;
-  if (start >= n) start = n;  // idle lane: empty range, still takes part in the wave reduction
-  int64_t end = start + MM_CH < n ? start + MM_CH : n;
-  int seg = start < n ? find_inst<int32_t>(base, n_seg, int32_t(start)) : 0;
+__global__ void __launch_bounds__(MM_NT) k_seg_minmax(const int32_t* __restrict__ v, int64_t n,
+                                                      const int32_t* __restrict__ base, int n_seg,
+                                                      int32_t* __restrict__ mn, int32_t* __restrict__ mx) {
+  __shared__ int32_t s_mn[MM_NT / 64], s_mx[MM_NT / 64];
+  const int64_t c0 = int64_t(blockIdx.x) * MM_CHUNK;
+  const int64_t c1 = c0 + MM_CHUNK < n ? c0 + MM_CHUNK : n;
+  const int seg0 = n_seg == 1 ? 0 : find_inst<int32_t>(base, n_seg, int32_t(c0));
+  const int seg1 = n_seg == 1 ? 0 : find_inst<int32_t>(base, n_seg, int32_t(c1 - 1));
   int32_t cmn = INT_MAX, cmx = INT_MIN;
+  if (seg0 == seg1) {
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += MM_NT) {
+      const int32_t x = v[i];
+      cmn = x < cmn ? x : cmn;
+      cmx = x > cmx ? x : cmx;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int32_t a = __shfl_xor(cmn, o, 64), b = __shfl_xor(cmx, o, 64);
+      cmn = a < cmn ? a : cmn;
+      cmx = b > cmx ? b : cmx;
+    }
+    if (lane_id() == 0) {
+      s_mn[threadIdx.x >> 6] = cmn;
+      s_mx[threadIdx.x >> 6] = cmx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < MM_NT / 64; ++w) {
+        cmn = s_mn[w] < cmn ? s_mn[w] : cmn;
+        cmx = s_mx[w] > cmx ? s_mx[w] : cmx;
+      }
+      atomicMin(&mn[seg0], cmn);
+      atomicMax(&mx[seg0], cmx);
+    }
+    return;
+  }
+  int seg = seg0;
   bool any = false;
-  for (int64_t i = start; i < end; ++i) {
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += MM_NT) {
     while (i >= base[seg + 1]) {
       if (any) {
         atomicMin(&mn[seg], cmn);
@@ -255,27 +291,12 @@ __global__ void k_seg_minmax(const int32_t* __restrict__ v, int64_t n, const int
       cmx = INT_MIN;
       ++seg;
     }
-    int32_t x = v[i];
+    const int32_t x = v[i];
     cmn = x < cmn ? x : cmn;
     cmx = x > cmx ? x : cmx;
     any = true;
   }
-  // the common case: the whole wave ends in one segment -> one atomic per wave
-  const int s0 = __shfl(seg, 0, 64);
-  const bool same = ballot(seg != s0 && any) == 0;
-  if (same) {
-    int32_t wmn = cmn, wmx = cmx;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      int32_t a = __shfl_xor(wmn, o, 64), b = __shfl_xor(wmx, o, 64);
-      wmn = a < wmn ? a : wmn;
-      wmx = b > wmx ? b : wmx;
-    }
-    if (lane_id() == 0 && wmn <= wmx) {
-      atomicMin(&mn[s0], wmn);
-      atomicMax(&mx[s0], wmx);
-    }
-  } else if (any) {
+  if (any) {
     atomicMin(&mn[seg], cmn);
     atomicMax(&mx[seg], cmx);
   }
@@ -354,9 +375,8 @@ void seg_minmax(const int32_t* v, int64_t n, const int32_t* base, int n_seg, int
   fill_i32(mn, n_seg, INT_MAX, s);
   fill_i32(mx, n_seg, INT_MIN, s);
   if (n <= 0) return;
-  int64_t threads = (n + MM_CH - 1) / MM_CH;
-  hipLaunchKernelGGL(k_seg_minmax, dim3(int((threads + 255) / 256)), dim3(256), 0, s, v, n, base, n_seg, mn,
-                     mx);
+  hipLaunchKernelGGL(k_seg_minmax, dim3(int((n + MM_CHUNK - 1) / MM_CHUNK)), dim3(MM_NT), 0, s, v, n, base, n_seg,
+                     mn, mx);
   JP_LAUNCH_CHECK();
 }
 

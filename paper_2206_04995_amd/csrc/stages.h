@@ -107,8 +107,8 @@ struct RowCtx {
 void hot_rank(const int32_t* hot, const int32_t* Ehot, int64_t n_y, int64_t n_hot, const int32_t* y_base, int n_inst,
               const int32_t* dR, int32_t* hotlist, int32_t* hotrow, hipStream_t s);
 // per R CSR entry code (see RowCtx::rcode)
-void row_codes(const int32_t* rcol, int64_t n, const int32_t* hotrow, const int32_t* cptr, int32_t* rcode,
-               hipStream_t s);
+void row_codes(const int32_t* rcol, int64_t n, const int32_t* hotrow, const int32_t* cptr, int64_t n_y,
+               int32_t* ycode, int32_t* rcode, hipStream_t s);
 // cold segment table: cw[cw_off[i] + w * Y_i + (y - y_base[i])] = first cold entry of y with local dense
 // index >= w * DW_BITS, for w in [0, nwin_i]
 void cold_windows(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t n_cold, const int32_t* y_base,
