@@ -100,6 +100,8 @@ typedef struct {
   int64_t n_z_dense;       /* number of dense z */
   int64_t k_hot;           /* hot join keys held as bit rows in DenseEC */
   int64_t footprint_bytes; /* device memory owned by the object for this instance's share */
+  int64_t pivot_cover;     /* dense z in the S row of the pivot key whose rows DenseEC counts outside
+                              that row (0: no pivot split for this instance) */
 } jp_stats;
 
 typedef struct jp_plan jp_plan;

@@ -55,7 +55,8 @@ class jp_options(ctypes.Structure):
 
 class jp_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
-                ("n_x", "n_y", "n_z", "n_r_kept", "out_j", "tau", "n_z_dense", "k_hot", "footprint_bytes")]
+                ("n_x", "n_y", "n_z", "n_r_kept", "out_j", "tau", "n_z_dense", "k_hot", "footprint_bytes",
+                 "pivot_cover")]
 
 
 class jp_timings(ctypes.Structure):

@@ -99,10 +99,16 @@ __device__ __forceinline__ void cold_scatter(int s0, int len, const int32_t* __r
   }
 }
 
+// Rows are slots [0, n_rows): slot i is row rows[i] (a list, count mode) or
+// x_lo + i.  In count mode the row's count starts at base_cnt[instance] (the
+// pivot row's size when the rows are evaluated outside the pivot's z) and is
+// stored, or added when the grid has several window groups or `accumulate`.
 template <bool WRITE>
-__global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, int64_t x_hi, int wgroup,
+__global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, int64_t n_rows,
+                                                   const int32_t* __restrict__ rows,
+                                                   const int32_t* __restrict__ base_cnt, int accumulate, int wgroup,
                                                    int32_t* __restrict__ cnt, const int64_t* __restrict__ off,
-                                                   int32_t* __restrict__ out) {
+                                                   int32_t* __restrict__ out, int64_t out_n) {
   __shared__ uint4 stage[T_STAGE][QW];
   __shared__ uint4 rowbuf_all[WAVES][QW];
   __shared__ int s_maxwin[WAVES];
@@ -111,13 +117,14 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
   uint32_t* rowbuf = reinterpret_cast<uint32_t*>(rowbuf_all[wid]);
   uint4* rowbuf4 = rowbuf_all[wid];
 
-  const int64_t rb0 = x_lo + int64_t(blockIdx.x) * RB;
+  const int64_t rb0 = int64_t(blockIdx.x) * RB;  // first slot of the block
   const int64_t r0 = rb0 + int64_t(wid) * RPW;
-  const int nrows = r0 >= x_hi ? 0 : int((x_hi - r0) < RPW ? (x_hi - r0) : RPW);
+  const int nrows = r0 >= n_rows ? 0 : int((n_rows - r0) < RPW ? (n_rows - r0) : RPW);
   const int64_t base_off = WRITE ? off[x_lo] : 0;
 
   // instance of the block's first row: its hottest keys are staged in LDS
-  const int inst0 = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, int32_t(rb0));
+  const int64_t xb0 = rows ? int64_t(rows[rb0]) : x_lo + rb0;
+  const int inst0 = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, int32_t(xb0));
   const int zd0 = c.zd_base[inst0 + 1] - c.zd_base[inst0];
   const int nwin0 = (zd0 + DW_BITS - 1) / DW_BITS;
   const int k0 = c.Ehot[c.y_base[inst0 + 1]] - c.Ehot[c.y_base[inst0]];
@@ -127,15 +134,18 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
 
   // lane r < nrows describes row r0 + r
   int my_inst = 0, my_nwin = 0, my_a = 0, my_b = 0;
+  int64_t my_x = 0;
   int64_t my_acc = 0;  // count (count mode) or write position (write mode)
   if (lane < nrows) {
-    const int64_t x = r0 + lane;
+    const int64_t x = rows ? int64_t(rows[r0 + lane]) : x_lo + r0 + lane;
+    my_x = x;
     my_inst = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, int32_t(x));
     const int zd = c.zd_base[my_inst + 1] - c.zd_base[my_inst];
     my_nwin = (zd + DW_BITS - 1) / DW_BITS;
     my_a = c.rptr[x];
     my_b = c.rptr[x + 1];
     if (WRITE) my_acc = off[x] - base_off;
+    else if (base_cnt && blockIdx.y == 0) my_acc = base_cnt[my_inst];
   }
   // the first 64 codes of every row stay in registers for all windows
   int code[RPW];
@@ -244,7 +254,8 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
             while (word) {
               const int bit = __ffs(word) - 1;
               word &= word - 1;
-              out[pos++] = c.dz2z[dzb + wbase + bit];
+              if (pos < out_n) out[pos] = c.dz2z[dzb + wbase + bit];  // out_n bounds a stale count
+              ++pos;
             }
           }
           qbase += tq;
@@ -254,8 +265,8 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
     }
   }
   if (!WRITE && lane < nrows) {
-    if (gridDim.y == 1) cnt[r0 + lane] = int32_t(my_acc);
-    else if (my_acc) atomicAdd(&cnt[r0 + lane], int32_t(my_acc));
+    if (gridDim.y == 1 && !accumulate) cnt[my_x] = int32_t(my_acc);
+    else if (my_acc) atomicAdd(&cnt[my_x], int32_t(my_acc));
   }
 }
 
@@ -303,7 +314,44 @@ __global__ void k_work_stats(RowCtx c, int64_t x_lo, int64_t x_hi, const int64_t
   }
 }
 
+// The same four sums over a list of rows (one thread per row), added to out.
+__global__ void k_work_rows(RowCtx c, const int32_t* __restrict__ rows, int64_t n_rows,
+                            const int64_t* __restrict__ w, unsigned long long* __restrict__ out) {
+  int64_t a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n_rows; i += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t x = rows[i];
+    const int inst = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, x);
+    const int zd = c.zd_base[inst + 1] - c.zd_base[inst];
+    const int64_t words = zd > 0 ? int64_t((zd + DW_BITS - 1) / DW_BITS) * DW_WORDS : 0;
+    a1 += words;
+    if (w) a3 += w[x];
+    for (int j = c.rptr[x]; j < c.rptr[x + 1]; ++j) {
+      const int code = c.rcode[j];
+      if (code >= 0) a0 += words;
+      else if (code <= -2) a2 += c.cptr[-2 - code + 1] - c.cptr[-2 - code];
+    }
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  a3 = wave_sum(a3);
+  if (lane_id() == 0) {
+    atomicAdd(&out[0], (unsigned long long)a0);
+    atomicAdd(&out[1], (unsigned long long)a1);
+    atomicAdd(&out[2], (unsigned long long)a2);
+    atomicAdd(&out[3], (unsigned long long)a3);
+  }
+}
+
 }  // namespace
+
+void work_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const int64_t* w, int64_t* out4, hipStream_t s) {
+  if (n_rows <= 0) return;
+  int g = int(std::min<int64_t>((n_rows + NT - 1) / NT, 4096));
+  hipLaunchKernelGGL(k_work_rows, dim3(g), dim3(NT), 0, s, c, rows, n_rows, w,
+                     reinterpret_cast<unsigned long long*>(out4));
+  JP_LAUNCH_CHECK();
+}
 
 // Windows per workgroup of the count kernel: as many as keep the hot-row
 // slices of the windows in flight within about 512 KiB of an XCD's 4 MiB L2
@@ -330,20 +378,33 @@ void work_stats(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
 }
 
 void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const int64_t* off, int32_t* out,
-              hipStream_t s) {
+              int64_t out_n, hipStream_t s) {
   int64_t n = x_hi - x_lo;
   if (n <= 0) return;
   int g = int((n + RB - 1) / RB);
   if (out) {  // write mode emits each row's windows in order: one group
-    hipLaunchKernelGGL(k_dense_bits<true>, dim3(g), dim3(NT), 0, s, c, x_lo, x_hi, INT32_MAX, cnt, off, out);
+    hipLaunchKernelGGL(k_dense_bits<true>, dim3(g), dim3(NT), 0, s, c, x_lo, n, nullptr, nullptr, 0, INT32_MAX, cnt,
+                       off, out, out_n);
   } else {
     const int nwin = int((c.max_zd_range + DW_BITS - 1) / DW_BITS);
     const int wg = dense_window_group(c.max_hot, nwin);
     const int ng = (nwin + wg - 1) / wg;
     if (ng > 1) fill_i32(cnt + x_lo, n, 0, s);
-    hipLaunchKernelGGL(k_dense_bits<false>, dim3(g, ng > 0 ? ng : 1), dim3(NT), 0, s, c, x_lo, x_hi, wg, cnt, off,
-                       out);
+    hipLaunchKernelGGL(k_dense_bits<false>, dim3(g, ng > 0 ? ng : 1), dim3(NT), 0, s, c, x_lo, n, nullptr, nullptr, 0,
+                       wg, cnt, off, out, int64_t(0));
   }
+  JP_LAUNCH_CHECK();
+}
+
+void dense_ec_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const int32_t* base_cnt, int32_t* cnt,
+                   hipStream_t s) {
+  if (n_rows <= 0) return;
+  const int g = int((n_rows + RB - 1) / RB);
+  const int nwin = int((c.max_zd_range + DW_BITS - 1) / DW_BITS);
+  const int wg = dense_window_group(c.max_hot, nwin);
+  const int ng = (nwin + wg - 1) / wg;
+  hipLaunchKernelGGL(k_dense_bits<false>, dim3(g, ng > 0 ? ng : 1), dim3(NT), 0, s, c, int64_t(0), n_rows, rows,
+                     base_cnt, 1, wg, cnt, nullptr, nullptr, int64_t(0));
   JP_LAUNCH_CHECK();
 }
 

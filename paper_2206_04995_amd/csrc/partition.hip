@@ -76,14 +76,19 @@ __global__ void k_compact_entries(const int32_t* __restrict__ scol, const int32_
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
-__global__ void k_hot_histogram(const int32_t* __restrict__ sptr, const int32_t* __restrict__ spptr,
+// entries of key y in the space: a[y+1] - a[y] - (b ? b[y+1] - b[y] : 0)
+__device__ __forceinline__ int space_count(const int32_t* __restrict__ a, const int32_t* __restrict__ b, int64_t y) {
+  return (a[y + 1] - a[y]) - (b ? b[y + 1] - b[y] : 0);
+}
+
+__global__ void k_hot_histogram(const int32_t* __restrict__ cnt_a, const int32_t* __restrict__ cnt_b,
                                 const int32_t* __restrict__ dR, int64_t n_y, const int32_t* __restrict__ y_base,
                                 int n_inst, int32_t* __restrict__ hist) {
   __shared__ int32_t loc[32];  // one instance: block-local buckets
   if (threadIdx.x < 32) loc[threadIdx.x] = 0;
   __syncthreads();
   GRID_STRIDE(y, n_y) {
-    int dd = (sptr[y + 1] - sptr[y]) - (spptr[y + 1] - spptr[y]);
+    const int dd = space_count(cnt_a, cnt_b, y);
     if (dd > 0 && dR[y] > 0) {
       if (n_inst == 1) {
         atomicAdd(&loc[ilog2(dd)], 1);
@@ -97,32 +102,152 @@ __global__ void k_hot_histogram(const int32_t* __restrict__ sptr, const int32_t*
   if (n_inst == 1 && threadIdx.x < 32 && loc[threadIdx.x]) atomicAdd(&hist[threadIdx.x], loc[threadIdx.x]);
 }
 
-__global__ void k_hot_flags(const int32_t* __restrict__ sptr, const int32_t* __restrict__ spptr,
+__global__ void k_hot_flags(const int32_t* __restrict__ cnt_a, const int32_t* __restrict__ cnt_b,
                             const int32_t* __restrict__ dR, int64_t n_y, const int32_t* __restrict__ y_base,
                             int n_inst, const int64_t* __restrict__ theta, int32_t* __restrict__ hot) {
   GRID_STRIDE(y, n_y) {
-    int dd = (sptr[y + 1] - sptr[y]) - (spptr[y + 1] - spptr[y]);
+    const int dd = space_count(cnt_a, cnt_b, y);
     int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
     hot[y] = (dd > 0 && dR[y] > 0 && int64_t(dd) >= theta[inst]) ? 1 : 0;
   }
 }
 
-// one thread per S entry: set the bit of every dense z of a hot row
+// one thread per S entry: set the bit of every z of a hot row that lies in
+// the space (zmap[z] = local index in the space, or -1)
 __global__ void k_build_hot_bits(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol, int64_t n,
                                  const int32_t* __restrict__ hot, const int32_t* __restrict__ hotrow,
-                                 const int32_t* __restrict__ y_base, const int32_t* __restrict__ z_base,
-                                 const int32_t* __restrict__ zd_base, const int32_t* __restrict__ Edz,
-                                 const int32_t* __restrict__ zflag, const int64_t* __restrict__ hb_off,
-                                 const int32_t* __restrict__ row_words, int n_inst, uint32_t* __restrict__ hb) {
+                                 const int32_t* __restrict__ y_base, const int32_t* __restrict__ zmap,
+                                 const int64_t* __restrict__ hb_off, const int32_t* __restrict__ row_words,
+                                 int n_inst, uint32_t* __restrict__ hb) {
   GRID_STRIDE(p, n) {
-    int32_t y = Ey[p + 1] - 1;
-    int32_t z = scol[p];
-    if (!hot[y] || !zflag[z]) continue;
-    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
-    int64_t k = hotrow[y];
+    const int32_t y = Ey[p + 1] - 1;
+    if (!hot[y]) continue;
+    const int32_t dl = zmap[scol[p]];
+    if (dl < 0) continue;
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+    const int64_t k = hotrow[y];
     uint32_t* row = hb + hb_off[inst] + k * row_words[inst];
-    int dl = Edz[z] - zd_base[inst];
     atomicOr(&row[dl >> 5], 1u << (dl & 31));
+  }
+}
+
+// per S entry: 1 iff its z lies in the space and its key is not hot (cold entry)
+__global__ void k_cold_flags(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol, int64_t n,
+                             const int32_t* __restrict__ zmap, const int32_t* __restrict__ hot,
+                             int32_t* __restrict__ flag) {
+  GRID_STRIDE(p, n) flag[p] = (zmap[scol[p]] >= 0 && !hot[Ey[p + 1] - 1]) ? 1 : 0;
+}
+
+// per S entry: 1 iff its z lies in the space
+__global__ void k_space_flags(const int32_t* __restrict__ scol, int64_t n, const int32_t* __restrict__ zmap,
+                              int32_t* __restrict__ flag) {
+  GRID_STRIDE(p, n) flag[p] = zmap[scol[p]] >= 0 ? 1 : 0;
+}
+
+// compaction of flagged S entries to their local index in the space
+__global__ void k_compact_mapped(const int32_t* __restrict__ scol, const int32_t* __restrict__ flag,
+                                 const int32_t* __restrict__ E, int64_t n, const int32_t* __restrict__ zmap,
+                                 int32_t* __restrict__ out) {
+  GRID_STRIDE(p, n) {
+    if (flag[p]) out[E[p]] = zmap[scol[p]];
+  }
+}
+
+// space 0: the dense z, local index = dense index - first dense index of the instance
+__global__ void k_zmap_dense(const int32_t* __restrict__ zflag, const int32_t* __restrict__ Edz, int64_t n_z,
+                             const int32_t* __restrict__ z_base, const int32_t* __restrict__ zd_base, int n_inst,
+                             int32_t* __restrict__ zmap) {
+  GRID_STRIDE(z, n_z) {
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(z_base, n_inst, int32_t(z));
+    zmap[z] = zflag[z] ? Edz[z] - zd_base[inst] : -1;
+  }
+}
+
+// space 1: the dense z outside the pivot row of instances with a pivot
+// (rflag over the dense index, Erd its exclusive scan)
+__global__ void k_zmap_resid(const int32_t* __restrict__ zflag, const int32_t* __restrict__ Edz,
+                             const int32_t* __restrict__ rflag, const int32_t* __restrict__ Erd, int64_t n_z,
+                             const int32_t* __restrict__ z_base, const int32_t* __restrict__ zc_base, int n_inst,
+                             int32_t* __restrict__ zmap) {
+  GRID_STRIDE(z, n_z) {
+    int32_t v = -1;
+    if (zflag[z]) {
+      const int d = Edz[z];
+      if (rflag[d]) {
+        const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(z_base, n_inst, int32_t(z));
+        v = Erd[d] - zc_base[inst];
+      }
+    }
+    zmap[z] = v;
+  }
+}
+
+// pivot candidate of each instance: its hot key of rank 0 (most R rows)
+__global__ void k_pivot_pick(const int32_t* __restrict__ hotrow, int64_t n_y, const int32_t* __restrict__ y_base,
+                             int n_inst, int32_t* __restrict__ piv) {
+  GRID_STRIDE(y, n_y) {
+    if (hotrow[y] == 0) piv[n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y))] = int32_t(y);
+  }
+}
+
+// info[3i..3i+2] = (pivot, d_R(pivot), dense entries of the pivot) for instance i (pivot -1: none)
+__global__ void k_pivot_info(const int32_t* __restrict__ piv, int n_inst, const int32_t* __restrict__ dR,
+                             const int32_t* __restrict__ cnt_a, const int32_t* __restrict__ cnt_b,
+                             int32_t* __restrict__ info) {
+  GRID_STRIDE(i, n_inst) {
+    const int32_t p = piv[i];
+    info[3 * i] = p;
+    info[3 * i + 1] = p >= 0 ? dR[p] : 0;
+    info[3 * i + 2] = p >= 0 ? space_count(cnt_a, cnt_b, p) : 0;
+  }
+}
+
+// inP[dense index] = 1 for every dense z of the instance's pivot row
+__global__ void k_mark_pivot(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol, int64_t n,
+                             const int32_t* __restrict__ y_base, int n_inst, const int32_t* __restrict__ piv,
+                             const int32_t* __restrict__ zflag, const int32_t* __restrict__ Edz,
+                             int32_t* __restrict__ inP) {
+  GRID_STRIDE(p, n) {
+    const int32_t y = Ey[p + 1] - 1;
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+    const int32_t z = scol[p];
+    if (piv[inst] == y && zflag[z]) inP[Edz[z]] = 1;
+  }
+}
+
+// out[d] = 1 iff dense index d belongs to an instance with a pivot and is outside the pivot row
+__global__ void k_resid_flags(const int32_t* __restrict__ inP, int64_t n, const int32_t* __restrict__ zd_base,
+                              int n_inst, const int32_t* __restrict__ piv, int32_t* __restrict__ out) {
+  GRID_STRIDE(d, n) {
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(zd_base, n_inst, int32_t(d));
+    out[d] = (piv[inst] >= 0 && !inP[d]) ? 1 : 0;
+  }
+}
+
+// flag[x] = 1 iff row x holds its instance's pivot key (one wavefront per row)
+__global__ void k_row_pivot(const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol, int64_t n_x,
+                            const int32_t* __restrict__ x_base, int n_inst, const int32_t* __restrict__ piv,
+                            int32_t* __restrict__ flag) {
+  const int lane = lane_id();
+  const int64_t waves = int64_t(gridDim.x) * (blockDim.x >> 6);
+  for (int64_t x = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); x < n_x; x += waves) {
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(x_base, n_inst, int32_t(x));
+    const int32_t p = piv[inst];
+    bool hit = false;
+    if (p >= 0) {
+      for (int j = rptr[x] + lane; j < rptr[x + 1] && !hit; j += 64) hit = rcol[j] == p;
+    }
+    const bool any = ballot(hit) != 0;
+    if (lane == 0) flag[x] = any ? 1 : 0;
+  }
+}
+
+// rows with flag 1 to rows_p, the others to rows_n, both in x order
+__global__ void k_split_rows(const int32_t* __restrict__ flag, const int32_t* __restrict__ E, int64_t n,
+                             int32_t* __restrict__ rows_p, int32_t* __restrict__ rows_n) {
+  GRID_STRIDE(x, n) {
+    if (flag[x]) rows_p[E[x]] = int32_t(x);
+    else rows_n[x - E[x]] = int32_t(x);
   }
 }
 
@@ -300,28 +425,101 @@ void compact_entries(const int32_t* scol, const int32_t* flag, const int32_t* E,
   JP_LAUNCH_CHECK();
 }
 
-void hot_histogram(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, const int32_t* y_base,
-                   int n_inst, int32_t* hist, hipStream_t s) {
+void hot_histogram(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR, int64_t n_y,
+                   const int32_t* y_base, int n_inst, int32_t* hist, hipStream_t s) {
   fill_i32(hist, int64_t(n_inst) * 32, 0, s);
   if (n_y <= 0) return;
-  hipLaunchKernelGGL(k_hot_histogram, dim3(grid(n_y)), dim3(NT), 0, s, sptr, spptr, dR, n_y, y_base, n_inst, hist);
+  hipLaunchKernelGGL(k_hot_histogram, dim3(grid(n_y)), dim3(NT), 0, s, cnt_a, cnt_b, dR, n_y, y_base, n_inst, hist);
   JP_LAUNCH_CHECK();
 }
 
-void hot_flags(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, const int32_t* y_base,
+void hot_flags(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR, int64_t n_y, const int32_t* y_base,
                int n_inst, const int64_t* theta, int32_t* hot, hipStream_t s) {
   if (n_y <= 0) return;
-  hipLaunchKernelGGL(k_hot_flags, dim3(grid(n_y)), dim3(NT), 0, s, sptr, spptr, dR, n_y, y_base, n_inst, theta, hot);
+  hipLaunchKernelGGL(k_hot_flags, dim3(grid(n_y)), dim3(NT), 0, s, cnt_a, cnt_b, dR, n_y, y_base, n_inst, theta, hot);
   JP_LAUNCH_CHECK();
 }
 
 void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* hotrow,
-                    const int32_t* y_base, const int32_t* z_base, const int32_t* zd_base, const int32_t* Edz,
-                    const int32_t* zflag, const int64_t* hb_off, const int32_t* row_words, int n_inst, uint32_t* hb,
-                    hipStream_t s) {
+                    const int32_t* y_base, const int32_t* zmap, const int64_t* hb_off, const int32_t* row_words,
+                    int n_inst, uint32_t* hb, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_build_hot_bits, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, hot, hotrow, y_base, z_base,
-                     zd_base, Edz, zflag, hb_off, row_words, n_inst, hb);
+  hipLaunchKernelGGL(k_build_hot_bits, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, hot, hotrow, y_base, zmap, hb_off,
+                     row_words, n_inst, hb);
+  JP_LAUNCH_CHECK();
+}
+
+void cold_flags(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zmap, const int32_t* hot,
+                int32_t* flag, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_cold_flags, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, zmap, hot, flag);
+  JP_LAUNCH_CHECK();
+}
+
+void space_flags(const int32_t* scol, int64_t n, const int32_t* zmap, int32_t* flag, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_space_flags, dim3(grid(n)), dim3(NT), 0, s, scol, n, zmap, flag);
+  JP_LAUNCH_CHECK();
+}
+
+void compact_mapped(const int32_t* scol, const int32_t* flag, const int32_t* E, int64_t n, const int32_t* zmap,
+                    int32_t* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_compact_mapped, dim3(grid(n)), dim3(NT), 0, s, scol, flag, E, n, zmap, out);
+  JP_LAUNCH_CHECK();
+}
+
+void zmap_dense(const int32_t* zflag, const int32_t* Edz, int64_t n_z, const int32_t* z_base, const int32_t* zd_base,
+                int n_inst, int32_t* zmap, hipStream_t s) {
+  if (n_z <= 0) return;
+  hipLaunchKernelGGL(k_zmap_dense, dim3(grid(n_z)), dim3(NT), 0, s, zflag, Edz, n_z, z_base, zd_base, n_inst, zmap);
+  JP_LAUNCH_CHECK();
+}
+
+void zmap_resid(const int32_t* zflag, const int32_t* Edz, const int32_t* rflag, const int32_t* Erd, int64_t n_z,
+                const int32_t* z_base, const int32_t* zc_base, int n_inst, int32_t* zmap, hipStream_t s) {
+  if (n_z <= 0) return;
+  hipLaunchKernelGGL(k_zmap_resid, dim3(grid(n_z)), dim3(NT), 0, s, zflag, Edz, rflag, Erd, n_z, z_base, zc_base,
+                     n_inst, zmap);
+  JP_LAUNCH_CHECK();
+}
+
+void pivot_info(const int32_t* hotrow, int64_t n_y, const int32_t* y_base, int n_inst, const int32_t* dR,
+                const int32_t* cnt_a, const int32_t* cnt_b, int32_t* piv, int32_t* info, hipStream_t s) {
+  fill_i32(piv, n_inst, -1, s);
+  if (n_y > 0) {
+    hipLaunchKernelGGL(k_pivot_pick, dim3(grid(n_y)), dim3(NT), 0, s, hotrow, n_y, y_base, n_inst, piv);
+    JP_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_pivot_info, dim3(grid(n_inst)), dim3(NT), 0, s, piv, n_inst, dR, cnt_a, cnt_b, info);
+  JP_LAUNCH_CHECK();
+}
+
+void mark_pivot(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* y_base, int n_inst,
+                const int32_t* piv, const int32_t* zflag, const int32_t* Edz, int32_t* inP, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mark_pivot, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, y_base, n_inst, piv, zflag, Edz, inP);
+  JP_LAUNCH_CHECK();
+}
+
+void resid_flags(const int32_t* inP, int64_t n, const int32_t* zd_base, int n_inst, const int32_t* piv, int32_t* out,
+                 hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_resid_flags, dim3(grid(n)), dim3(NT), 0, s, inP, n, zd_base, n_inst, piv, out);
+  JP_LAUNCH_CHECK();
+}
+
+void row_pivot_flags(const int32_t* rptr, const int32_t* rcol, int64_t n_x, const int32_t* x_base, int n_inst,
+                     const int32_t* piv, int32_t* flag, hipStream_t s) {
+  if (n_x <= 0) return;
+  hipLaunchKernelGGL(k_row_pivot, dim3(grid(n_x * 64, 1 << 16)), dim3(NT), 0, s, rptr, rcol, n_x, x_base, n_inst, piv,
+                     flag);
+  JP_LAUNCH_CHECK();
+}
+
+void split_rows(const int32_t* flag, const int32_t* E, int64_t n, int32_t* rows_p, int32_t* rows_n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_split_rows, dim3(grid(n)), dim3(NT), 0, s, flag, E, n, rows_p, rows_n);
   JP_LAUNCH_CHECK();
 }
 

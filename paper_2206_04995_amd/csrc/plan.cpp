@@ -363,54 +363,91 @@ void Plan::partition(hipStream_t s) {
   spcol = A.alloc<int32_t>(std::max<int64_t>(NSp, 1), s);
   compact_entries(scol, fl, Esp, NS, Edz, z_base, zd_base, n, false, spcol, s);
 
+  DenseSpace& d0 = ds[0];
+  d0.h_base = h_zdbase;
+  d0.base = zd_base;
   if (NZd == 0) {
     // no dense z in any instance: DenseEC has no work, its tables stay empty
-    h_theta.assign(n, INT64_MAX);
-    h_K.assign(n, 0);
-    h_roww.assign(n, 0);
-    h_hboff.assign(n, 0);
-    d_theta = A.alloc<int64_t>(n, s);
-    fill_i64(d_theta, n, INT64_MAX, s);
-    d_hboff = A.alloc<int64_t>(n, s);
-    fill_i64(d_hboff, n, 0, s);
-    d_roww = A.alloc<int32_t>(n, s);
-    fill_i32(d_roww, n, 0, s);
-    d_cwmoff = A.alloc<int64_t>(n, s);
-    fill_i64(d_cwmoff, n, 0, s);
-    Ehot = A.alloc<int32_t>(NY + 1, s);
-    fill_i32(Ehot, NY + 1, 0, s);
-    hotrow = A.alloc<int32_t>(NYa, s);
-    fill_i32(hotrow, NYa, -1, s);
-    cptr = A.alloc<int32_t>(NY + 1, s);
-    fill_i32(cptr, NY + 1, 0, s);
-    NHb = 0;
-    hb = A.alloc<uint32_t>(4, s);
-    fill_u32(hb, 4, 0u, s);
-    NCold = 0;
-    ccol = A.alloc<int32_t>(1, s);
-    fill_i32(ccol, 1, 0, s);
-    wptr = A.alloc<int32_t>(1, s);
-    fill_i32(wptr, 1, 0, s);
-    rcode = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
-    fill_i32(rcode, std::max<int64_t>(NRp, 1), -1, s);
+    empty_space(d0, s);
     T.release(s);
     return;
   }
+  int32_t* zmap = T.alloc<int32_t>(NZa, s);
+  zmap_dense(zflag, Edz, NZ, z_base, zd_base, n, zmap, s);
+  build_space(d0, zmap, sptr, spptr, &h_hist, T, s);
+  pivot_split(T, s);
+  T.release(s);
+}
 
-  // hot join keys of DenseEC: dense S row covering at least theta of the dense z
+// Tables of DenseEC over empty spaces (no instance has a dense z).
+void Plan::empty_space(DenseSpace& d, hipStream_t s) {
+  const int n = n_inst;
+  const int64_t NYa = std::max<int64_t>(NY, 1);
+  d.h_theta.assign(n, INT64_MAX);
+  d.h_K.assign(n, 0);
+  d.h_roww.assign(n, 0);
+  d.h_hboff.assign(n, 0);
+  d.d_theta = A.alloc<int64_t>(n, s);
+  fill_i64(d.d_theta, n, INT64_MAX, s);
+  d.d_hboff = A.alloc<int64_t>(n, s);
+  fill_i64(d.d_hboff, n, 0, s);
+  d.d_roww = A.alloc<int32_t>(n, s);
+  fill_i32(d.d_roww, n, 0, s);
+  d.d_cwmoff = A.alloc<int64_t>(n, s);
+  fill_i64(d.d_cwmoff, n, 0, s);
+  d.Ehot = A.alloc<int32_t>(NY + 1, s);
+  fill_i32(d.Ehot, NY + 1, 0, s);
+  d.hotrow = A.alloc<int32_t>(NYa, s);
+  fill_i32(d.hotrow, NYa, -1, s);
+  d.cptr = A.alloc<int32_t>(NY + 1, s);
+  fill_i32(d.cptr, NY + 1, 0, s);
+  d.NHb = 0;
+  d.hb = A.alloc<uint32_t>(4, s);
+  fill_u32(d.hb, 4, 0u, s);
+  d.NCold = 0;
+  d.ccol = A.alloc<int32_t>(1, s);
+  fill_i32(d.ccol, 1, 0, s);
+  d.wptr = A.alloc<int32_t>(1, s);
+  fill_i32(d.wptr, 1, 0, s);
+  d.rcode = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
+  fill_i32(d.rcode, std::max<int64_t>(NRp, 1), -1, s);
+}
+
+// Tables of DenseEC over one z space: hot keys as bit rows over the space's
+// local index, cold entries window-major, per-entry codes of R's CSR.
+void Plan::build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a, const int32_t* cnt_b,
+                       const std::vector<int32_t>* hist_pre, Arena& T, hipStream_t s) {
+  const int n = n_inst;
+  const int64_t NSa = std::max<int64_t>(NS, 1), NYa = std::max<int64_t>(NY, 1);
+  std::vector<int32_t> h_hist;
+  if (hist_pre) {
+    h_hist = *hist_pre;
+  } else {
+    int32_t* hist = T.alloc<int32_t>(int64_t(n) * 32, s);
+    hot_histogram(cnt_a, cnt_b, dR, NY, y_base, n, hist, s);
+    h_hist.resize(size_t(n) * 32);
+    d2h(h_hist.data(), hist, size_t(n) * 32, s);
+    if (d.h_base.empty()) {
+      d.h_base.resize(n + 1);
+      d2h(d.h_base.data(), d.base, n + 1, s);
+    }
+    sync(s);
+  }
+
+  // hot join keys: S row covering at least theta of the space
   const int kmax = opt.k_hot_max > 0 ? std::min(opt.k_hot_max, 1024) : 256;
   const double hot_frac = env_double("JP_HOT_MIN_FRACTION", 1.0 / 128.0);
-  h_theta.assign(n, INT64_MAX);
-  h_K.assign(n, 0);
-  h_roww.assign(n, 0);
-  h_hboff.assign(n, 0);
+  d.h_theta.assign(n, INT64_MAX);
+  d.h_K.assign(n, 0);
+  d.h_roww.assign(n, 0);
+  d.h_hboff.assign(n, 0);
   int64_t hb_words = 0;
   for (int i = 0; i < n; ++i) {
-    int64_t zd = h_zdbase[i + 1] - h_zdbase[i];
-    h_hboff[i] = hb_words;
+    int64_t zd = d.h_base[i + 1] - d.h_base[i];
+    d.h_hboff[i] = hb_words;
     if (zd <= 0) continue;
     int64_t nwin = (zd + DW_BITS - 1) / DW_BITS;
-    h_roww[i] = int32_t(nwin * DW_WORDS);
+    d.h_roww[i] = int32_t(nwin * DW_WORDS);
     int64_t th = std::max<int64_t>(2, int64_t(std::ceil(double(zd) * hot_frac)));
     int b = 0;
     while ((int64_t(1) << b) < th) ++b;
@@ -422,51 +459,51 @@ void Plan::partition(hipStream_t s) {
     };
     while (b < 31 && count_from(b) > kmax) ++b;
     int64_t K = count_from(b);
-    h_theta[i] = int64_t(1) << b;
-    h_K[i] = K;
-    hb_words += K * h_roww[i];
+    d.h_theta[i] = int64_t(1) << b;
+    d.h_K[i] = K;
+    hb_words += K * d.h_roww[i];
   }
-  d_theta = A.alloc<int64_t>(n, s);
-  h2d(d_theta, h_theta.data(), n, s);
-  d_hboff = A.alloc<int64_t>(n, s);
-  h2d(d_hboff, h_hboff.data(), n, s);
-  d_roww = A.alloc<int32_t>(n, s);
-  h2d(d_roww, h_roww.data(), n, s);
+  d.d_theta = A.alloc<int64_t>(n, s);
+  h2d(d.d_theta, d.h_theta.data(), n, s);
+  d.d_hboff = A.alloc<int64_t>(n, s);
+  h2d(d.d_hboff, d.h_hboff.data(), n, s);
+  d.d_roww = A.alloc<int32_t>(n, s);
+  h2d(d.d_roww, d.h_roww.data(), n, s);
   int32_t* hot = T.alloc<int32_t>(NYa, s);
-  hot_flags(sptr, spptr, dR, NY, y_base, n, d_theta, hot, s);
-  Ehot = A.alloc<int32_t>(NY + 1, s);
-  scan_excl_i32(hot, Ehot, NY, s, T);
-  hotrow = A.alloc<int32_t>(NYa, s);
+  hot_flags(cnt_a, cnt_b, dR, NY, y_base, n, d.d_theta, hot, s);
+  d.Ehot = A.alloc<int32_t>(NY + 1, s);
+  scan_excl_i32(hot, d.Ehot, NY, s, T);
+  d.hotrow = A.alloc<int32_t>(NYa, s);
   int64_t n_hot = 0;
-  for (int i = 0; i < n; ++i) n_hot += h_K[i];
+  for (int i = 0; i < n; ++i) n_hot += d.h_K[i];
   int32_t* hotlist = T.alloc<int32_t>(std::max<int64_t>(n_hot, 1), s);
-  hot_rank(hot, Ehot, NY, n_hot, y_base, n, dR, hotlist, hotrow, s);
-  NHb = hb_words;
-  hb = A.alloc<uint32_t>(std::max<int64_t>(hb_words, 4), s);
-  fill_u32(hb, hb_words, 0u, s);
-  build_hot_bits(Ey, scol, NS, hot, hotrow, y_base, z_base, zd_base, Edz, zflag, d_hboff, d_roww, n, hb, s);
+  hot_rank(hot, d.Ehot, NY, n_hot, y_base, n, dR, hotlist, d.hotrow, s);
+  d.NHb = hb_words;
+  d.hb = A.alloc<uint32_t>(std::max<int64_t>(hb_words, 4), s);
+  fill_u32(d.hb, hb_words, 0u, s);
+  build_hot_bits(Ey, scol, NS, hot, d.hotrow, y_base, zmap, d.d_hboff, d.d_roww, n, d.hb, s);
 
-  // cold dense entries: CSR by y over the local dense index
-  entry_flags(Ey, scol, NS, zflag, hot, nullptr, fl, s);
+  // cold entries: CSR by y over the space's local index (ascending in each row)
+  int32_t* fl = T.alloc<int32_t>(NSa, s);
+  cold_flags(Ey, scol, NS, zmap, hot, fl, s);
   int32_t* Ec = T.alloc<int32_t>(NS + 1, s);
   scan_excl_i32(fl, Ec, NS, s, T);
-  cptr = A.alloc<int32_t>(NY + 1, s);
-  remap_rowptr(sptr, Ec, NY, cptr, s);
+  d.cptr = A.alloc<int32_t>(NY + 1, s);
+  remap_rowptr(sptr, Ec, NY, d.cptr, s);
   int32_t ncold = 0;
   d2h(&ncold, Ec + NS, 1, s);
   sync(s);
-  NCold = ncold;
-  int32_t* ccol_y = T.alloc<int32_t>(std::max<int64_t>(NCold, 1), s);
-  compact_entries(scol, fl, Ec, NS, Edz, z_base, zd_base, n, true, ccol_y, s);
+  d.NCold = ncold;
+  int32_t* ccol_y = T.alloc<int32_t>(std::max<int64_t>(d.NCold, 1), s);
+  compact_mapped(scol, fl, Ec, NS, zmap, ccol_y, s);
 
-  // cold entries in window-major order with per-(window, key) segment bounds,
-  // and per-entry codes of R's CSR
+  // cold entries in window-major order with per-(window, key) segment bounds
   std::vector<int64_t> h_cwoff(n, 0), h_cwmoff(n, 0);
   int64_t cw_total = 0, cwm_total = 0;
   for (int i = 0; i < n; ++i) {
     h_cwoff[i] = cw_total;
     h_cwmoff[i] = cwm_total;
-    int64_t zd = h_zdbase[i + 1] - h_zdbase[i];
+    int64_t zd = d.h_base[i + 1] - d.h_base[i];
     if (zd > 0) {
       int64_t ny = h_ybase[i + 1] - h_ybase[i], nwin = (zd + DW_BITS - 1) / DW_BITS;
       cw_total += ny * (nwin + 1);
@@ -476,24 +513,97 @@ void Plan::partition(hipStream_t s) {
   if (cwm_total >= INT32_MAX) throw Error(JP_ENOMEM, "cold segment table too large");
   int64_t* d_offs = T.alloc<int64_t>(2 * int64_t(n), s);
   h2d(d_offs, h_cwoff.data(), n, s);
-  d_cwmoff = A.alloc<int64_t>(n, s);
-  h2d(d_cwmoff, h_cwmoff.data(), n, s);
+  d.d_cwmoff = A.alloc<int64_t>(n, s);
+  h2d(d.d_cwmoff, h_cwmoff.data(), n, s);
   int32_t* cw = T.alloc<int32_t>(std::max<int64_t>(cw_total, 1), s);
-  wptr = A.alloc<int32_t>(cwm_total + 1, s);
-  ccol = A.alloc<int32_t>(std::max<int64_t>(NCold, 1), s);
+  d.wptr = A.alloc<int32_t>(cwm_total + 1, s);
+  d.ccol = A.alloc<int32_t>(std::max<int64_t>(d.NCold, 1), s);
   if (cw_total > 0) {
-    cold_windows(cptr, ccol_y, NY, NCold, y_base, zd_base, n, d_offs, cw, s);
-    cold_window_major(cptr, ccol_y, NY, NCold, y_base, zd_base, n, cw, d_offs, d_cwmoff, cwm_total, wptr, ccol, s, T);
+    cold_windows(d.cptr, ccol_y, NY, d.NCold, y_base, d.base, n, d_offs, cw, s);
+    cold_window_major(d.cptr, ccol_y, NY, d.NCold, y_base, d.base, n, cw, d_offs, d.d_cwmoff, cwm_total, d.wptr, d.ccol,
+                      s, T);
   } else {
-    fill_i32(wptr, 1, 0, s);
+    fill_i32(d.wptr, 1, 0, s);
   }
-  rcode = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
+  d.rcode = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
   int32_t* ycode = T.alloc<int32_t>(NYa, s);
-  row_codes(rcol, NRp, hotrow, cptr, NY, ycode, rcode, s);
-  T.release(s);
+  row_codes(rcol, NRp, d.hotrow, d.cptr, NY, ycode, d.rcode, s);
 }
 
-RowCtx Plan::ctx() const {
+// Pivot split of the DenseEC rows.  For an instance whose most shared hot key
+// p (rank 0) lies in at least a quarter of its rows and covers at least half
+// of its dense z, a row x holding p has
+//   C[x] = S_dense[p]  disjoint-union  (OR over its other keys of S_dense[y] minus S_dense[p]),
+// so its count is |S_dense[p]| plus a count over the dense z outside
+// S_dense[p] (space 1), which is at most half as wide.  Rows without p keep
+// space 0.  Exact for every row; only the count pass uses it.
+void Plan::pivot_split(Arena& T, hipStream_t s) {
+  const int n = n_inst;
+  n_piv = 0;
+  // JP_PIVOT: 0 disables the split, 2 takes every rank-0 hot key as a pivot (tests)
+  const double mode = env_double("JP_PIVOT", 1.0);
+  if (mode == 0.0) return;
+  DenseSpace& d0 = ds[0];
+  int32_t* info = T.alloc<int32_t>(3 * int64_t(n), s);
+  d_piv = A.alloc<int32_t>(n, s);
+  pivot_info(d0.hotrow, NY, y_base, n, dR, sptr, spptr, d_piv, info, s);
+  std::vector<int32_t> h_info(3 * size_t(n));
+  d2h(h_info.data(), info, 3 * size_t(n), s);
+  sync(s);
+  h_piv.assign(n, -1);
+  for (int i = 0; i < n; ++i) {
+    const int32_t p = h_info[3 * i], dr = h_info[3 * i + 1], cnt = h_info[3 * i + 2];
+    const int64_t nx = h_xbase[i + 1] - h_xbase[i], zd = h_zdbase[i + 1] - h_zdbase[i];
+    if (p >= 0 && (mode == 2.0 || (zd > DW_BITS && 4 * int64_t(dr) >= nx && 2 * int64_t(cnt) >= zd))) {
+      h_piv[i] = p;
+      ++n_piv;
+    }
+  }
+  if (n_piv == 0) return;
+  h2d(d_piv, h_piv.data(), n, s);
+  const int64_t NZda = std::max<int64_t>(NZd, 1), NSa = std::max<int64_t>(NS, 1), NXa = std::max<int64_t>(NX, 1);
+  int32_t* inP = T.alloc<int32_t>(NZda, s);
+  fill_i32(inP, NZd, 0, s);
+  mark_pivot(Ey, scol, NS, y_base, n, d_piv, zflag, Edz, inP, s);
+  int32_t* rflag = T.alloc<int32_t>(NZda, s);
+  resid_flags(inP, NZd, zd_base, n, d_piv, rflag, s);
+  int32_t* Erd = T.alloc<int32_t>(NZd + 1, s);
+  scan_excl_i32(rflag, Erd, NZd, s, T);
+  DenseSpace& d1 = ds[1];
+  d1.base = A.alloc<int32_t>(n + 1, s);
+  gather_bases(Erd, zd_base, n, d1.base, s);
+  int32_t* zmap1 = T.alloc<int32_t>(std::max<int64_t>(NZ, 1), s);
+  zmap_resid(zflag, Edz, rflag, Erd, NZ, z_base, d1.base, n, zmap1, s);
+  int32_t* f1 = T.alloc<int32_t>(NSa, s);
+  space_flags(scol, NS, zmap1, f1, s);
+  int32_t* E1 = T.alloc<int32_t>(NS + 1, s);
+  scan_excl_i32(f1, E1, NS, s, T);
+  int32_t* cnt1 = T.alloc<int32_t>(NY + 1, s);
+  remap_rowptr(sptr, E1, NY, cnt1, s);
+  build_space(d1, zmap1, cnt1, nullptr, nullptr, T, s);
+
+  // rows holding their pivot, and the base count |S_dense[p]| = (dense z) - (space-1 z)
+  int32_t* rf = T.alloc<int32_t>(NXa, s);
+  row_pivot_flags(rptr, rcol, NX, x_base, n, d_piv, rf, s);
+  int32_t* Er = T.alloc<int32_t>(NX + 1, s);
+  scan_excl_i32(rf, Er, NX, s, T);
+  int32_t np = 0;
+  d2h(&np, Er + NX, 1, s);
+  sync(s);
+  NRowsP = np;
+  NRowsN = NX - np;
+  rows_p = A.alloc<int32_t>(std::max<int64_t>(NRowsP, 1), s);
+  rows_n = A.alloc<int32_t>(std::max<int64_t>(NRowsN, 1), s);
+  split_rows(rf, Er, NX, rows_p, rows_n, s);
+  std::vector<int32_t> h_pc(n, 0);
+  for (int i = 0; i < n; ++i)
+    if (h_piv[i] >= 0) h_pc[i] = (h_zdbase[i + 1] - h_zdbase[i]) - (d1.h_base[i + 1] - d1.h_base[i]);
+  d_pivcnt = A.alloc<int32_t>(n, s);
+  h2d(d_pivcnt, h_pc.data(), n, s);
+}
+
+RowCtx Plan::ctx(int space) const {
+  const DenseSpace& d = ds[space];
   RowCtx c;
   c.n_inst = n_inst;
   c.max_z_range = 0;
@@ -501,27 +611,27 @@ RowCtx Plan::ctx() const {
   c.max_hot = 0;
   for (int i = 0; i < n_inst; ++i) {
     c.max_z_range = std::max<int64_t>(c.max_z_range, h_zbase[i + 1] - h_zbase[i]);
-    c.max_zd_range = std::max<int64_t>(c.max_zd_range, h_zdbase[i + 1] - h_zdbase[i]);
-    c.max_hot = std::max<int64_t>(c.max_hot, h_K[i]);
+    if (!d.h_base.empty()) c.max_zd_range = std::max<int64_t>(c.max_zd_range, d.h_base[i + 1] - d.h_base[i]);
+    if (!d.h_K.empty()) c.max_hot = std::max<int64_t>(c.max_hot, d.h_K[i]);
   }
   c.x_base = x_base;
   c.z_base = z_base;
-  c.zd_base = zd_base;
+  c.zd_base = d.base;
   c.rptr = rptr;
   c.rcol = rcol;
   c.spptr = spptr;
   c.spcol = spcol;
-  c.hotrow = hotrow;
-  c.Ehot = Ehot;
+  c.hotrow = d.hotrow;
+  c.Ehot = d.Ehot;
   c.y_base = y_base;
-  c.rcode = rcode;
-  c.wptr = wptr;
-  c.cwm_off = d_cwmoff;
-  c.hb_off = d_hboff;
-  c.row_words = d_roww;
-  c.hb = hb;
-  c.cptr = cptr;
-  c.ccol = ccol;
+  c.rcode = d.rcode;
+  c.wptr = d.wptr;
+  c.cwm_off = d.d_cwmoff;
+  c.hb_off = d.d_hboff;
+  c.row_words = d.d_roww;
+  c.hb = d.hb;
+  c.cptr = d.cptr;
+  c.ccol = d.ccol;
   c.dz2z = dz2z;
   return c;
 }
@@ -583,8 +693,15 @@ void Plan::run_count_pass(hipStream_t s, bool timing) {
   if (NSp > 0) sparse_bmm(c, 0, NX, w, cnt_sp, nullptr, nullptr, heavy_list, s);
   else fill_i32(cnt_sp, NX, 0, s);
   if (timing) JP_HIP(hipEventRecord(ev[1], s));
-  if (NZd > 0) dense_ec(c, 0, NX, cnt_de, nullptr, nullptr, s);
-  else fill_i32(cnt_de, NX, 0, s);
+  if (NZd > 0 && n_piv > 0) {
+    fill_i32(cnt_de, NX, 0, s);
+    dense_ec_rows(c, rows_n, NRowsN, nullptr, cnt_de, s);
+    dense_ec_rows(ctx(1), rows_p, NRowsP, d_pivcnt, cnt_de, s);
+  } else if (NZd > 0) {
+    dense_ec(c, 0, NX, cnt_de, nullptr, nullptr, 0, s);
+  } else {
+    fill_i32(cnt_de, NX, 0, s);
+  }
   if (timing) JP_HIP(hipEventRecord(ev[2], s));
   add_counts(cnt_sp, cnt_de, NX, cnt_all, s);
   scan_excl_i32_to_i64(cnt_all, off_all, NX, s, XA);
@@ -606,7 +723,13 @@ void Plan::timings(jp_timings* t, hipStream_t s) {
 void Plan::work(jp_timings* t, hipStream_t s) {
   if (!executed) throw Error(JP_ESTATE, "work counters need a jp_execute");
   int64_t* d = A.alloc<int64_t>(4, s);
-  work_stats(ctx(), 0, NX, w, d, s);
+  if (n_piv > 0) {
+    fill_i64(d, 4, 0, s);
+    work_rows(ctx(0), rows_n, NRowsN, w, d, s);
+    work_rows(ctx(1), rows_p, NRowsP, w, d, s);
+  } else {
+    work_stats(ctx(), 0, NX, w, d, s);
+  }
   int64_t wk[4];
   d2h(wk, d, 4, s);
   sync(s);
@@ -656,7 +779,7 @@ int64_t Plan::materialize(int inst, int part, int64_t first, int64_t maxp, int32
   RowCtx c = ctx();
   int32_t* lde = T.alloc<int32_t>(std::max<int64_t>(nde, 1), s);
   int32_t* lsp = T.alloc<int32_t>(std::max<int64_t>(nsp, 1), s);
-  if (nde > 0) dense_ec(c, xl, xh, nullptr, off_de, lde, s);
+  if (nde > 0) dense_ec(c, xl, xh, nullptr, off_de, lde, nde, s);
   if (nsp > 0) sparse_bmm(c, xl, xh, w + xl, nullptr, off_sp, lsp, T.alloc<int32_t>(xh - xl + 1, s), s);
   if (part == JP_PART_ALL)
     merge_write_n(xl, xh, off_de, off_sp, off_all, lde, lsp, nde, nsp, vals_x, vals_z, g0, g1, ox, oz, s);
@@ -677,8 +800,11 @@ void Plan::stats(int i, jp_stats* st) const {
   st->out_j = h_outj[i];
   st->tau = h_tau[i];
   st->n_z_dense = h_zdbase[i + 1] - h_zdbase[i];
-  st->k_hot = h_K[i];
+  st->k_hot = ds[0].h_K.empty() ? 0 : ds[0].h_K[i];
   st->footprint_bytes = n_inst == 1 ? A.bytes() : A.bytes() / n_inst;
+  st->pivot_cover = (n_piv > 0 && h_piv[i] >= 0) ? int64_t(h_zdbase[i + 1] - h_zdbase[i]) -
+                                                       int64_t(ds[1].h_base[i + 1] - ds[1].h_base[i])
+                                                 : 0;
 }
 
 }  // namespace jp

@@ -14,6 +14,21 @@ namespace jp {
 void gather_values(const int32_t* vals, const int32_t* idx, int64_t n, int32_t* out, hipStream_t s);
 void set_last_error(const std::string& m);  // message returned by jp_last_error() on this thread
 
+// The tables of DenseEC over one z space (see stages.h): space 0 holds every
+// dense z; space 1 holds, per instance with a pivot key, the dense z outside
+// the pivot's S row, and serves the rows that contain the pivot.
+struct DenseSpace {
+  std::vector<int32_t> h_base;  // [n_inst+1] prefix of the instances' space sizes
+  std::vector<int64_t> h_theta, h_K, h_hboff;
+  std::vector<int32_t> h_roww;
+  int32_t* base = nullptr;      // device copy of h_base
+  int64_t *d_theta = nullptr, *d_hboff = nullptr, *d_cwmoff = nullptr;
+  int32_t *d_roww = nullptr, *Ehot = nullptr, *hotrow = nullptr, *cptr = nullptr, *ccol = nullptr;
+  int32_t *wptr = nullptr, *rcode = nullptr;
+  uint32_t* hb = nullptr;
+  int64_t NHb = 0, NCold = 0;
+};
+
 struct Plan {
   Arena A;
   int n_inst = 0;
@@ -22,10 +37,9 @@ struct Plan {
   bool stream_used = false;
   bool executed = false;
 
-  int64_t NR = 0, NS = 0, NRp = 0, NX = 0, NY = 0, NZ = 0, NZd = 0, NSp = 0, NCold = 0, NHb = 0;
+  int64_t NR = 0, NS = 0, NRp = 0, NX = 0, NY = 0, NZ = 0, NZd = 0, NSp = 0;
   std::vector<int32_t> h_rbase, h_sbase, h_rpbase, h_xbase, h_ybase, h_zbase, h_zdbase;
-  std::vector<int64_t> h_outj, h_tau, h_theta, h_K, h_hboff, h_tot;
-  std::vector<int32_t> h_roww;
+  std::vector<int64_t> h_outj, h_tau, h_tot;
 
   // inputs (concatenated over instances)
   const int32_t *rx = nullptr, *ry = nullptr, *sz = nullptr, *sy = nullptr;
@@ -37,12 +51,19 @@ struct Plan {
   int32_t *m_z = nullptr, *dR = nullptr, *dS = nullptr;
   int64_t* d_outj = nullptr;
   // partition
-  int64_t *d_tau = nullptr, *d_theta = nullptr, *d_hboff = nullptr;
-  int32_t *d_roww = nullptr, *zflag = nullptr, *Edz = nullptr, *dz2z = nullptr, *zd_base = nullptr;
-  int32_t *spptr = nullptr, *spcol = nullptr, *Ehot = nullptr, *hotrow = nullptr, *cptr = nullptr, *ccol = nullptr;
-  uint32_t* hb = nullptr;
-  int32_t *rcode = nullptr, *wptr = nullptr;
-  int64_t* d_cwmoff = nullptr;
+  int64_t* d_tau = nullptr;
+  int32_t *zflag = nullptr, *Edz = nullptr, *dz2z = nullptr, *zd_base = nullptr;
+  int32_t *spptr = nullptr, *spcol = nullptr;
+  DenseSpace ds[2];
+  // pivot split of the DenseEC rows (space 1 in use iff n_piv > 0)
+  int n_piv = 0;
+  std::vector<int32_t> h_piv;
+  int32_t *d_piv = nullptr, *d_pivcnt = nullptr, *rows_p = nullptr, *rows_n = nullptr;
+  int64_t NRowsP = 0, NRowsN = 0;
+  void build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a, const int32_t* cnt_b,
+                   const std::vector<int32_t>* hist_pre, Arena& T, hipStream_t s);
+  void empty_space(DenseSpace& d, hipStream_t s);
+  void pivot_split(Arena& T, hipStream_t s);
   // execute
   int64_t* w = nullptr;
   int32_t *cnt_sp = nullptr, *cnt_de = nullptr, *cnt_all = nullptr;
@@ -78,7 +99,7 @@ struct Plan {
   void build(const jp_instance* inst, int n, const jp_options* o, hipStream_t s);
   void map(hipStream_t s);
   void partition(hipStream_t s);
-  RowCtx ctx() const;
+  RowCtx ctx(int space = 0) const;
   void execute(hipStream_t s);
   void fetch_totals(hipStream_t s);
   int64_t materialize(int inst, int part, int64_t first, int64_t maxp, int32_t* ox, int32_t* oz, hipStream_t s);

@@ -62,17 +62,48 @@ void remap_rowptr(const int32_t* rowptr, const int32_t* E, int64_t n_y, int32_t*
 void compact_entries(const int32_t* scol, const int32_t* flag, const int32_t* E, int64_t n, const int32_t* Edz,
                      const int32_t* z_base, const int32_t* zd_base, int n_inst, bool to_local_dense,
                      int32_t* out, hipStream_t s);
-// per-instance histogram of floor(log2(d_dense(y))) over y with dR > 0 (32 buckets)
-void hot_histogram(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, const int32_t* y_base,
+// The tables of DenseEC are built over a "space" of z: a map zmap[z] = local
+// index of z in its instance's part of the space, or -1 if z is not in it.
+// The count of key y in the space is cnt_a[y+1] - cnt_a[y] - (cnt_b ? cnt_b[y+1] - cnt_b[y] : 0).
+//
+// per-instance histogram of floor(log2(count in the space)) over y with dR > 0 (32 buckets)
+void hot_histogram(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR, int64_t n_y, const int32_t* y_base,
                    int n_inst, int32_t* hist, hipStream_t s);
-// hot[y] = 1 iff dR[y] > 0 and d_dense(y) >= theta[inst(y)]
-void hot_flags(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, const int32_t* y_base,
+// hot[y] = 1 iff dR[y] > 0 and the count of y in the space >= theta[inst(y)]
+void hot_flags(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR, int64_t n_y, const int32_t* y_base,
                int n_inst, const int64_t* theta, int32_t* hot, hipStream_t s);
-// hot row bit sets over the local dense index (one thread per S entry)
+// hot row bit sets over the space's local index (one thread per S entry)
 void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* hotrow,
-                    const int32_t* y_base, const int32_t* z_base, const int32_t* zd_base, const int32_t* Edz,
-                    const int32_t* zflag, const int64_t* hb_off, const int32_t* row_words, int n_inst,
-                    uint32_t* hb, hipStream_t s);
+                    const int32_t* y_base, const int32_t* zmap, const int64_t* hb_off, const int32_t* row_words,
+                    int n_inst, uint32_t* hb, hipStream_t s);
+// per S entry: in the space and not of a hot key
+void cold_flags(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zmap, const int32_t* hot,
+                int32_t* flag, hipStream_t s);
+// per S entry: in the space
+void space_flags(const int32_t* scol, int64_t n, const int32_t* zmap, int32_t* flag, hipStream_t s);
+// out[E[p]] = zmap[scol[p]] for flagged entries
+void compact_mapped(const int32_t* scol, const int32_t* flag, const int32_t* E, int64_t n, const int32_t* zmap,
+                    int32_t* out, hipStream_t s);
+// space 0: all dense z
+void zmap_dense(const int32_t* zflag, const int32_t* Edz, int64_t n_z, const int32_t* z_base, const int32_t* zd_base,
+                int n_inst, int32_t* zmap, hipStream_t s);
+// space 1: the dense z with rflag[dense index] set (Erd: exclusive scan of rflag)
+void zmap_resid(const int32_t* zflag, const int32_t* Edz, const int32_t* rflag, const int32_t* Erd, int64_t n_z,
+                const int32_t* z_base, const int32_t* zc_base, int n_inst, int32_t* zmap, hipStream_t s);
+// piv[i] = hot key of rank 0 of instance i (or -1); info[3i..] = (piv, dR(piv), count of piv in the space)
+void pivot_info(const int32_t* hotrow, int64_t n_y, const int32_t* y_base, int n_inst, const int32_t* dR,
+                const int32_t* cnt_a, const int32_t* cnt_b, int32_t* piv, int32_t* info, hipStream_t s);
+// inP[Edz[z]] = 1 for the dense z of each instance's pivot row
+void mark_pivot(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* y_base, int n_inst,
+                const int32_t* piv, const int32_t* zflag, const int32_t* Edz, int32_t* inP, hipStream_t s);
+// rflag[d] = 1 iff dense index d is of an instance with a pivot (piv >= 0) and not in its pivot row
+void resid_flags(const int32_t* inP, int64_t n, const int32_t* zd_base, int n_inst, const int32_t* piv, int32_t* out,
+                 hipStream_t s);
+// flag[x] = 1 iff R row x holds the pivot of its instance
+void row_pivot_flags(const int32_t* rptr, const int32_t* rcol, int64_t n_x, const int32_t* x_base, int n_inst,
+                     const int32_t* piv, int32_t* flag, hipStream_t s);
+// flagged rows to rows_p, the others to rows_n (E = exclusive scan of flag)
+void split_rows(const int32_t* flag, const int32_t* E, int64_t n, int32_t* rows_p, int32_t* rows_n, hipStream_t s);
 
 // ----------------------------------------------------------- row work
 struct RowCtx {
@@ -130,13 +161,20 @@ void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, 
 void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int32_t* cnt,
                 const int64_t* off, int32_t* out, int32_t* heavy_list, hipStream_t s);
 // DenseEC count or write, bit-packed hot rows
+// (write mode: out holds out_n values; writes past it are dropped)
 void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const int64_t* off, int32_t* out,
-              hipStream_t s);
+              int64_t out_n, hipStream_t s);
+// DenseEC count over a list of rows, adding to cnt (zeroed by the caller);
+// every row's count starts at base_cnt[instance] when base_cnt is given
+void dense_ec_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const int32_t* base_cnt, int32_t* cnt,
+                   hipStream_t s);
 // windows per workgroup of the DenseEC count kernel (JP_DENSE_WINDOW_GROUP overrides)
 int dense_window_group(int64_t max_hot, int nwin);
 
 // algorithmic work of the count kernels over rows [x_lo, x_hi) (see jp_timings)
 void work_stats(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int64_t* out4, hipStream_t s);
+// the same sums over a list of rows, added to out4 (w indexed by x; nullable)
+void work_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const int64_t* w, int64_t* out4, hipStream_t s);
 
 // ------------------------------------------------------------- output
 void add_counts(const int32_t* a, const int32_t* b, int64_t n, int32_t* out, hipStream_t s);
