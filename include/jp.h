@@ -53,11 +53,14 @@ typedef enum {
   JP_TAU_FIXED = 1  /* use jp_options.dense_threshold */
 } jp_tau_mode;
 
-/* Kernel for the hot (frequent join key) part of DenseEC (Sec. 2.5 / f3). */
+/* Kernel of the DenseEC count pass (Sec. 2.5).  The write pass of
+ * jp_materialize always uses the bit path; both are exact. */
 typedef enum {
-  JP_DENSE_AUTO = 0, /* per row block, by the density of hot join keys */
-  JP_DENSE_BITS = 1, /* bit-packed OR of hot key rows */
-  JP_DENSE_MFMA = 2  /* 0/1 product on the INT8 matrix cores, int32 sums thresholded at > 0 */
+  JP_DENSE_AUTO = 0, /* the INT8-MFMA product for a single-query plan whose (x, dense key) panel has at
+                        least 1/32 of its cells set and fits (2 GiB per panel); the bit path otherwise */
+  JP_DENSE_BITS = 1, /* bit rows of the hot join keys ORed per window, cold keys scattered */
+  JP_DENSE_MFMA = 2  /* 0/1 product on the INT8 matrix cores with int32 sums tested > 0, whenever the
+                        plan is a single query and the panels fit; the bit path otherwise */
 } jp_dense_kernel;
 
 /* jp_options.flags bits */
@@ -90,6 +93,7 @@ typedef struct {
   int64_t dense_hot_words;    /* sum over x of (hot keys of x) * (32-bit words of its dense z range) */
   int64_t dense_row_words;    /* sum over x of the words of its dense z range (one popcount each) */
   int64_t dense_cold_entries; /* cold dense S entries scattered, summed over x */
+  int64_t dense_mfma_ops;     /* 2 * |X| * (dense keys) * |Z_dense| when the INT8-MFMA product ran, else 0 */
 } jp_timings;
 
 typedef struct {
@@ -102,6 +106,7 @@ typedef struct {
   int64_t footprint_bytes; /* device memory owned by the object for this instance's share */
   int64_t pivot_cover;     /* dense z in the S row of the pivot key whose rows DenseEC counts outside
                               that row (0: no pivot split for this instance) */
+  int64_t dense_mfma;      /* 1 if the dense part is counted by the INT8-MFMA product, else 0 */
 } jp_stats;
 
 typedef struct jp_plan jp_plan;

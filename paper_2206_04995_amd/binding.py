@@ -56,14 +56,14 @@ class jp_options(ctypes.Structure):
 class jp_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_x", "n_y", "n_z", "n_r_kept", "out_j", "tau", "n_z_dense", "k_hot", "footprint_bytes",
-                 "pivot_cover")]
+                 "pivot_cover", "dense_mfma")]
 
 
 class jp_timings(ctypes.Structure):
     _fields_ = [("sparse_ms", ctypes.c_float), ("dense_ms", ctypes.c_float), ("execute_ms", ctypes.c_float),
                 ("pad_", ctypes.c_float)] + [
         (n, ctypes.c_int64) for n in ("sparse_join_rows", "n_r_kept", "n_x", "dense_hot_words", "dense_row_words",
-                                      "dense_cold_entries")]
+                                      "dense_cold_entries", "dense_mfma_ops")]
 
 
 class jp_instance(ctypes.Structure):

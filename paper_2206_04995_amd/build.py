@@ -19,6 +19,7 @@ SOURCES = [
     "partition.hip",
     "sparse_bmm.hip",
     "dense_ec.hip",
+    "dense_mfma.hip",
     "output.hip",
     "plan.cpp",
     "server.cpp",

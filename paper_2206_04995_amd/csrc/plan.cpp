@@ -375,8 +375,36 @@ void Plan::partition(hipStream_t s) {
   int32_t* zmap = T.alloc<int32_t>(NZa, s);
   zmap_dense(zflag, Edz, NZ, z_base, zd_base, n, zmap, s);
   build_space(d0, zmap, sptr, spptr, &h_hist, T, s);
-  pivot_split(T, s);
+  choose_dense_kernel(T, s);
+  if (!use_mfma) pivot_split(T, s);
   T.release(s);
+}
+
+// The count pass of the dense part runs on the INT8 matrix cores when the
+// panel of (x, dense key) cells is dense: the product does 2 ops per cell and
+// dense z whether or not the cell is set, the bit path one 32-z word per set
+// cell (plus its cold scatters), so the product wins when a good share of the
+// cells is set.  Single-instance plans only; JP_DENSE_MFMA asks for it
+// whenever the panels fit, JP_DENSE_BITS never uses it.
+void Plan::choose_dense_kernel(Arena& T, hipStream_t s) {
+  use_mfma = false;
+  if (n_inst != 1 || opt.dense_kernel == JP_DENSE_BITS || NZd <= 0 || NX <= 0) return;
+  const int64_t NYa = std::max<int64_t>(NY, 1);
+  int32_t* kmap = T.alloc<int32_t>(NYa, s);
+  K_panel = panel_key_count(sptr, spptr, NY, kmap, T, s);
+  if (K_panel <= 0) return;
+  k_pad = (K_panel + 63) / 64 * 64;
+  nx_pad = (NX + 127) / 128 * 128;
+  nz_pad = (NZd + 127) / 128 * 128;
+  const int64_t lim = int64_t(1) << 31;
+  if (nx_pad * k_pad > lim || nz_pad * k_pad > lim) return;
+  const double density = double(NRp) / (double(NX) * double(K_panel));
+  const double min_density = env_double("JP_MFMA_MIN_DENSITY", 1.0 / 32.0);
+  if (opt.dense_kernel != JP_DENSE_MFMA && density < min_density) return;
+  use_mfma = true;
+  pA = A.alloc<int8_t>(nx_pad * k_pad, s);
+  pBt = A.alloc<int8_t>(nz_pad * k_pad, s);
+  build_panels(rptr, rcol, NX, Ey, scol, NS, zflag, Edz, kmap, k_pad, nx_pad, nz_pad, pA, pBt, s);
 }
 
 // Tables of DenseEC over empty spaces (no instance has a dense z).
@@ -693,7 +721,9 @@ void Plan::run_count_pass(hipStream_t s, bool timing) {
   if (NSp > 0) sparse_bmm(c, 0, NX, w, cnt_sp, nullptr, nullptr, heavy_list, s);
   else fill_i32(cnt_sp, NX, 0, s);
   if (timing) JP_HIP(hipEventRecord(ev[1], s));
-  if (NZd > 0 && n_piv > 0) {
+  if (NZd > 0 && use_mfma) {
+    dense_mfma_count(pA, pBt, k_pad, NX, nx_pad, nz_pad, cnt_de, s);
+  } else if (NZd > 0 && n_piv > 0) {
     fill_i32(cnt_de, NX, 0, s);
     dense_ec_rows(c, rows_n, NRowsN, nullptr, cnt_de, s);
     dense_ec_rows(ctx(1), rows_p, NRowsP, d_pivcnt, cnt_de, s);
@@ -740,6 +770,8 @@ void Plan::work(jp_timings* t, hipStream_t s) {
   t->dense_hot_words = wk[0];
   t->dense_row_words = wk[1];
   t->dense_cold_entries = wk[2];
+  t->dense_mfma_ops = use_mfma ? 2 * NX * K_panel * NZd : 0;
+  if (use_mfma) t->dense_hot_words = t->dense_row_words = t->dense_cold_entries = 0;
 }
 
 void Plan::fetch_totals(hipStream_t s) {
@@ -802,6 +834,7 @@ void Plan::stats(int i, jp_stats* st) const {
   st->n_z_dense = h_zdbase[i + 1] - h_zdbase[i];
   st->k_hot = ds[0].h_K.empty() ? 0 : ds[0].h_K[i];
   st->footprint_bytes = n_inst == 1 ? A.bytes() : A.bytes() / n_inst;
+  st->dense_mfma = use_mfma ? 1 : 0;
   st->pivot_cover = (n_piv > 0 && h_piv[i] >= 0) ? int64_t(h_zdbase[i + 1] - h_zdbase[i]) -
                                                        int64_t(ds[1].h_base[i + 1] - ds[1].h_base[i])
                                                  : 0;

@@ -60,6 +60,11 @@ struct Plan {
   std::vector<int32_t> h_piv;
   int32_t *d_piv = nullptr, *d_pivcnt = nullptr, *rows_p = nullptr, *rows_n = nullptr;
   int64_t NRowsP = 0, NRowsN = 0;
+  // INT8-MFMA count of the dense part (single-instance plans with a dense panel)
+  bool use_mfma = false;
+  int8_t *pA = nullptr, *pBt = nullptr;
+  int64_t K_panel = 0, k_pad = 0, nx_pad = 0, nz_pad = 0;
+  void choose_dense_kernel(Arena& T, hipStream_t s);
   void build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a, const int32_t* cnt_b,
                    const std::vector<int32_t>* hist_pre, Arena& T, hipStream_t s);
   void empty_space(DenseSpace& d, hipStream_t s);

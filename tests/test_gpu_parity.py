@@ -22,8 +22,10 @@ def _opts(kind):
 
     if kind == "auto":
         return None
-    if kind == "all_dense":
-        return P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=-1)
+    if kind == "all_dense":  # bit path
+        return P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=-1, dense_kernel=P.JP_DENSE_BITS)
+    if kind == "all_dense_mfma":
+        return P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=-1, dense_kernel=P.JP_DENSE_MFMA)
     if kind == "all_sparse":
         return P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=BIG)
     return P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=int(kind))
@@ -37,14 +39,14 @@ def test_hand_examples():
         s = np.array(case["S"], dtype=np.int64).reshape(-1, 2)
         inst = synth.Instance(r[:, 0].astype(np.int32), r[:, 1].astype(np.int32), s[:, 0].astype(np.int32),
                               s[:, 1].astype(np.int32), case["name"])
-        for kind in ("auto", "all_dense", "all_sparse"):
+        for kind in ("auto", "all_dense", "all_dense_mfma", "all_sparse"):
             print(f"[case] hand {case['name']} {kind}", flush=True)
             st, _ = assert_parity(inst, _opts(kind))
             assert st["out_j"] == case["out_j"]
 
 
 @pytest.mark.parametrize("seed", range(8))
-@pytest.mark.parametrize("kind", ["auto", "all_dense", "all_sparse", "3"])
+@pytest.mark.parametrize("kind", ["auto", "all_dense", "all_dense_mfma", "all_sparse", "3"])
 def test_small_random(seed, kind):
     inst = synth.small_random(seed, 300 + 97 * seed, 250 + 61 * seed, dom_x=40 + 5 * seed, dom_y=30 + 3 * seed,
                               dom_z=50 + 7 * seed, offset=(-2 ** 31 if seed == 3 else -20 * seed),
@@ -70,14 +72,14 @@ def test_edge_cases():
                        np.arange(100, dtype=np.int32), np.arange(100, dtype=np.int32) + 5000, "no-match"),
     ]
     for inst in cases:
-        for kind in ("auto", "all_dense", "all_sparse"):
+        for kind in ("auto", "all_dense", "all_dense_mfma", "all_sparse"):
             print(f"[case] edge {inst.name} {kind}", flush=True)
             assert_parity(inst, _opts(kind))
 
 
 def test_config1_exact():
     inst = synth.config1()
-    for kind in ("auto", "all_dense", "all_sparse"):
+    for kind in ("auto", "all_dense", "all_dense_mfma", "all_sparse"):
         print(f"[case] config1 {kind}", flush=True)
         st, _ = assert_parity(inst, _opts(kind), chunk=700_001)
         assert st["n_x"] == np.unique(inst.rx[np.isin(inst.ry, inst.sy)]).size

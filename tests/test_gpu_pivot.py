@@ -25,9 +25,10 @@ def pivot_env():
 
 
 def _all_dense():
+    # the bit path (these small panels are dense enough for the MFMA product otherwise)
     import paper_2206_04995_amd as P
 
-    return P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=-1)
+    return P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=-1, dense_kernel=P.JP_DENSE_BITS)
 
 
 @pytest.mark.parametrize("seed", range(6))
