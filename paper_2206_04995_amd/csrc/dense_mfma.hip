@@ -6,12 +6,14 @@
 //
 // A is stored x-major and B transposed (z-major), both with the key index
 // contiguous, so one 16-byte load gives a lane its 16 k-values of an MFMA
-// operand.  A workgroup computes a 128 x 128 tile of C with four waves of
-// 64 x 64 (4 x 4 blocks of v_mfma_i32_16x16x64_i8), staging 64 keys of both
-// panels per step in LDS.  Lane l of a 16x16x64 operand holds row (or column)
-// l % 16 and keys 16 * (l / 16) .. + 15; its accumulator element r is
-// C[4 * (l / 16) + r][l % 16].  The epilogue counts C > 0 per row with
-// ballots and adds one partial count per row and tile.
+// operand.  A workgroup of WR x WC waves computes a tile of C, each wave a
+// (16 TI) x (16 TJ) block of v_mfma_i32_16x16x64_i8.  Every step stages 64
+// keys of both panels in LDS, double buffered: the next step's loads are in flight while the current step
+// multiplies.  LDS rows are padded to 80 bytes so the 16-byte operand reads of
+// 16 consecutive rows fall in distinct banks.  Lane l of a 16x16x64 operand
+// holds row (or column) l % 16 and keys 16 * (l / 16) .. + 15; its accumulator
+// element r is C[4 * (l / 16) + r][l % 16].  The epilogue counts C > 0 per row
+// with ballots and adds one partial count per row and tile.
 #include "common.h"
 #include "prim.h"
 #include "stages.h"
@@ -21,57 +23,103 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int MT = 128;  // x rows per workgroup tile
-constexpr int ZT = 128;  // dense z per workgroup tile
-constexpr int KT = 64;   // keys per step
-constexpr int BT = 256;  // 4 waves: 2 x 2 quadrants of 64 x 64
+// wave tile (16 * TI) x (16 * TJ), WR x WC waves per workgroup
+constexpr int TI = 4, TJ = 8, WR = 4, WC = 2;
+constexpr int MT = WR * 16 * TI;  // x rows per workgroup tile
+constexpr int ZT = WC * 16 * TJ;  // dense z per workgroup tile
+constexpr int KS = 2;             // 64-key MFMA steps per staged step
+constexpr int KT = 64 * KS;       // keys per staged step
+constexpr int CPR = KT / 16;      // 16-byte chunks per panel row and step
+constexpr int BT = 64 * WR * WC;  // threads per workgroup
+constexpr int RP = CPR + 1;       // 16-byte chunks per LDS row (one of padding)
+constexpr int SA = MT * CPR / BT;  // 16-byte staging loads per thread and step, panel A
+constexpr int SB = ZT * CPR / BT;  // the same for panel B
+static_assert(SA >= 1 && SB >= 1 && MT * CPR % BT == 0 && ZT * CPR % BT == 0, "staging split");
 
-__global__ void __launch_bounds__(BT) k_dense_mfma(const int8_t* __restrict__ A, const int8_t* __restrict__ Bt,
-                                                   int64_t k_pad, int64_t nx, int32_t* __restrict__ cnt) {
-  __shared__ v4i As[MT][KT / 16];
-  __shared__ v4i Bs[ZT][KT / 16];
+__global__ void __launch_bounds__(BT, 1) k_dense_mfma(const int8_t* __restrict__ A, const int8_t* __restrict__ Bt,
+                                                      int64_t k_pad, int64_t nx, int32_t* __restrict__ cnt) {
+  __shared__ v4i As[2][MT * RP];
+  __shared__ v4i Bs[2][ZT * RP];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
+  const int wr = wid / WC, wc = wid % WC;
   const int64_t x0 = int64_t(blockIdx.y) * MT, z0 = int64_t(blockIdx.x) * ZT;
-  v4i acc[4][4];
+  v4i acc[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4i{0, 0, 0, 0};
+    for (int j = 0; j < TJ; ++j) acc[i][j] = v4i{0, 0, 0, 0};
 
-  for (int64_t k0 = 0; k0 < k_pad; k0 += KT) {
+  // staging chunk c of a panel: row c / 4, 16-byte column c % 4
+  v4i pa[SA], pb[SB];
 #pragma unroll
-    for (int c = tid; c < MT * (KT / 16); c += BT) {
-      const int r = c >> 2, q = c & 3;
-      As[r][q] = *reinterpret_cast<const v4i*>(A + (x0 + r) * k_pad + k0 + q * 16);
-      Bs[r][q] = *reinterpret_cast<const v4i*>(Bt + (z0 + r) * k_pad + k0 + q * 16);
+  for (int s = 0; s < SA; ++s) {
+    const int c = tid + s * BT;
+    pa[s] = *reinterpret_cast<const v4i*>(A + (x0 + (c / CPR)) * k_pad + (c % CPR) * 16);
+    As[0][(c / CPR) * RP + (c % CPR)] = pa[s];
+  }
+#pragma unroll
+  for (int s = 0; s < SB; ++s) {
+    const int c = tid + s * BT;
+    pb[s] = *reinterpret_cast<const v4i*>(Bt + (z0 + (c / CPR)) * k_pad + (c % CPR) * 16);
+    Bs[0][(c / CPR) * RP + (c % CPR)] = pb[s];
+  }
+  __syncthreads();
+  const int nk = int(k_pad / KT);
+  for (int ks = 0; ks < nk; ++ks) {
+    const int cur = ks & 1;
+    if (ks + 1 < nk) {
+      const int64_t kk = int64_t(ks + 1) * KT;
+#pragma unroll
+      for (int s = 0; s < SA; ++s) {
+        const int c = tid + s * BT;
+        pa[s] = *reinterpret_cast<const v4i*>(A + (x0 + (c / CPR)) * k_pad + kk + (c % CPR) * 16);
+      }
+#pragma unroll
+      for (int s = 0; s < SB; ++s) {
+        const int c = tid + s * BT;
+        pb[s] = *reinterpret_cast<const v4i*>(Bt + (z0 + (c / CPR)) * k_pad + kk + (c % CPR) * 16);
+      }
     }
-    __syncthreads();
-    v4i a[4], b[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      a[t] = As[wr * 64 + t * 16 + (lane & 15)][lane >> 4];
-      b[t] = Bs[wc * 64 + t * 16 + (lane & 15)][lane >> 4];
+    for (int kq = 0; kq < KS; ++kq) {
+      v4i a[TI], b[TJ];
+#pragma unroll
+      for (int t = 0; t < TI; ++t) a[t] = As[cur][(wr * 16 * TI + t * 16 + (lane & 15)) * RP + 4 * kq + (lane >> 4)];
+#pragma unroll
+      for (int t = 0; t < TJ; ++t) b[t] = Bs[cur][(wc * 16 * TJ + t * 16 + (lane & 15)) * RP + 4 * kq + (lane >> 4)];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (ks + 1 < nk) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int s = 0; s < SA; ++s) {
+        const int c = tid + s * BT;
+        As[cur ^ 1][(c / CPR) * RP + (c % CPR)] = pa[s];
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int s = 0; s < SB; ++s) {
+        const int c = tid + s * BT;
+        Bs[cur ^ 1][(c / CPR) * RP + (c % CPR)] = pb[s];
+      }
+    }
     __syncthreads();
   }
 
   const int g = lane >> 4;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < TI; ++i) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int c = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < TJ; ++j) {
         const uint64_t m = ballot(acc[i][j][r] > 0);
         c += __popcll((m >> (16 * g)) & 0xFFFFull);
       }
-      const int64_t x = x0 + wr * 64 + i * 16 + 4 * g + r;
+      const int64_t x = x0 + wr * 16 * TI + i * 16 + 4 * g + r;
       if ((lane & 15) == 0 && x < nx && c) atomicAdd(&cnt[x], c);
     }
   }
@@ -152,11 +200,15 @@ void build_panels(const int32_t* rptr, const int32_t* rcol, int64_t n_x, const i
   }
 }
 
+int64_t mfma_pad_rows(int64_t n) { return (n + MT - 1) / MT * MT; }
+int64_t mfma_pad_keys(int64_t n) { return (n + KT - 1) / KT * KT; }
+int64_t mfma_pad_cols(int64_t n) { return (n + ZT - 1) / ZT * ZT; }
+
 void dense_mfma_count(const int8_t* A, const int8_t* Bt, int64_t k_pad, int64_t nx, int64_t nx_pad, int64_t nz_pad,
                       int32_t* cnt, hipStream_t s) {
   fill_i32(cnt, nx, 0, s);
   if (nx <= 0 || nz_pad <= 0 || k_pad <= 0) return;
-  dim3 grid(unsigned(nz_pad / ZT), unsigned(nx_pad / MT));
+  dim3 grid(unsigned(nz_pad / ZT), unsigned(nx_pad / MT));  // padded by mfma_pad_rows / mfma_pad_cols
   hipLaunchKernelGGL(k_dense_mfma, grid, dim3(BT), 0, s, A, Bt, k_pad, nx, cnt);
   JP_LAUNCH_CHECK();
 }

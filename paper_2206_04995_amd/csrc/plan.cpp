@@ -393,9 +393,9 @@ void Plan::choose_dense_kernel(Arena& T, hipStream_t s) {
   int32_t* kmap = T.alloc<int32_t>(NYa, s);
   K_panel = panel_key_count(sptr, spptr, NY, kmap, T, s);
   if (K_panel <= 0) return;
-  k_pad = (K_panel + 63) / 64 * 64;
-  nx_pad = (NX + 127) / 128 * 128;
-  nz_pad = (NZd + 127) / 128 * 128;
+  k_pad = mfma_pad_keys(K_panel);
+  nx_pad = mfma_pad_rows(NX);
+  nz_pad = mfma_pad_cols(NZd);
   const int64_t lim = int64_t(1) << 31;
   if (nx_pad * k_pad > lim || nz_pad * k_pad > lim) return;
   const double density = double(NRp) / (double(NX) * double(K_panel));

@@ -176,6 +176,10 @@ int64_t panel_key_count(const int32_t* sptr, const int32_t* spptr, int64_t n_y, 
 void build_panels(const int32_t* rptr, const int32_t* rcol, int64_t n_x, const int32_t* Ey, const int32_t* scol,
                   int64_t n_s, const int32_t* zflag, const int32_t* Edz, const int32_t* kmap, int64_t k_pad,
                   int64_t nx_pad, int64_t nz_pad, int8_t* A, int8_t* Bt, hipStream_t s);
+// panel rows (x) and columns (dense z) padded to the product's tiles
+int64_t mfma_pad_rows(int64_t n);
+int64_t mfma_pad_cols(int64_t n);
+int64_t mfma_pad_keys(int64_t n);
 void dense_mfma_count(const int8_t* A, const int8_t* Bt, int64_t k_pad, int64_t nx, int64_t nx_pad, int64_t nz_pad,
                       int32_t* cnt, hipStream_t s);
 // windows per workgroup of the DenseEC count kernel (JP_DENSE_WINDOW_GROUP overrides)
