@@ -7,13 +7,14 @@
 // A is stored x-major and B transposed (z-major), both with the key index
 // contiguous, so one 16-byte load gives a lane its 16 k-values of an MFMA
 // operand.  A workgroup of WR x WC waves computes a tile of C, each wave a
-// (16 TI) x (16 TJ) block of v_mfma_i32_16x16x64_i8.  Every step stages 64
-// keys of both panels in LDS, double buffered: the next step's loads are in flight while the current step
-// multiplies.  LDS rows are padded to 80 bytes so the 16-byte operand reads of
-// 16 consecutive rows fall in distinct banks.  Lane l of a 16x16x64 operand
-// holds row (or column) l % 16 and keys 16 * (l / 16) .. + 15; its accumulator
-// element r is C[4 * (l / 16) + r][l % 16].  The epilogue counts C > 0 per row
-// with ballots and adds one partial count per row and tile.
+// (16 TI) x (16 TJ) block of v_mfma_i32_16x16x64_i8.  Every step stages KT
+// keys of both panels in LDS, double buffered: the next step's loads are in
+// flight while the current step multiplies.  LDS rows carry one 16-byte chunk
+// of padding so the 16-byte operand reads of 16 consecutive rows fall in
+// distinct banks.  Lane l of a 16x16x64 operand holds row (or column) l % 16
+// and keys 16 * (l / 16) .. + 15; its accumulator element r is
+// C[4 * (l / 16) + r][l % 16].  The epilogue counts C > 0 per row with ballots
+// and adds one partial count per row and tile.
 #include "common.h"
 #include "prim.h"
 #include "stages.h"
