@@ -191,6 +191,33 @@ jp_status jp_batch_materialize(jp_batch* b, int32_t inst, jp_part part, int64_t 
 jp_status jp_batch_stats(const jp_batch* b, int32_t inst, jp_stats* s);
 void jp_batch_destroy(jp_batch* b);
 
+/* ------------------------------------------------------------ autotuner --- */
+
+/* The dense/sparse threshold of Sec. 2.6 is tau = (c_de / c_sp) |X| |S| / OUT_J;
+ * jp_tune times the plan + count pass of one query (device columns as for
+ * jp_plan_create) for a set of thresholds (all dense, all sparse, the model's
+ * tau scaled by 1/16 .. 16, quantiles of m_z), checks that all give the same
+ * counts (the partition is intersection-free, Sec. 2.3), and stores the cost
+ * ratio of the fastest under the query's shape signature (log2 buckets of
+ * |X|, |Z|, |S| and OUT_J / |S|).  Later plans and batch instances with
+ * JP_TAU_AUTO and that signature take tau from the stored ratio.  The store is
+ * process-wide and thread-safe.  jp_tune syncs the stream; it returns
+ * JP_ESTATE if two thresholds disagree. */
+typedef struct {
+  int64_t tau;         /* fastest threshold (dense iff m_z > tau; INT64_MAX: all sparse) */
+  int64_t model_tau;   /* the untuned cost model's threshold */
+  double cost_ratio;   /* c_de / c_sp stored for the signature */
+  double best_ms;      /* plan + count pass at tau (best of 2) */
+  double model_ms;     /* the same at model_tau */
+  int32_t candidates;  /* thresholds timed besides model_tau */
+  int32_t pad_;
+  uint64_t signature;  /* shape signature the ratio is stored under */
+} jp_tune_result;
+
+jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r, const int32_t* s_z, const int32_t* s_y,
+                  int64_t n_s, const jp_options* opt, hipStream_t stream, jp_tune_result* out);
+jp_status jp_tune_clear(void); /* forgets every stored ratio */
+
 /* -------------------------------------------------------------- server --- */
 
 /* A query server: a host thread that admits submitted queries while their

@@ -33,6 +33,7 @@ EXPORTS = [
     "jp_batch_create", "jp_batch_execute", "jp_batch_counts", "jp_batch_materialize", "jp_batch_stats",
     "jp_batch_destroy",
     "jp_server_create", "jp_server_submit", "jp_server_poll", "jp_server_wait", "jp_server_stats", "jp_server_destroy",
+    "jp_tune", "jp_tune_clear",
 ]
 
 
@@ -64,6 +65,12 @@ class jp_timings(ctypes.Structure):
                 ("pad_", ctypes.c_float)] + [
         (n, ctypes.c_int64) for n in ("sparse_join_rows", "n_r_kept", "n_x", "dense_hot_words", "dense_row_words",
                                       "dense_cold_entries", "dense_mfma_ops")]
+
+
+class jp_tune_result(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_int64), ("model_tau", ctypes.c_int64), ("cost_ratio", ctypes.c_double),
+                ("best_ms", ctypes.c_double), ("model_ms", ctypes.c_double), ("candidates", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("signature", ctypes.c_uint64)]
 
 
 class jp_instance(ctypes.Structure):
@@ -125,6 +132,8 @@ def _load() -> ctypes.CDLL:
         "jp_server_wait": (st, [vp, ctypes.c_uint64, ctypes.POINTER(jp_query_result)]),
         "jp_server_stats": (st, [vp, ctypes.POINTER(jp_server_summary)]),
         "jp_server_destroy": (None, [vp]),
+        "jp_tune": (st, [vp, vp, i64, vp, vp, i64, ctypes.POINTER(jp_options), vp, ctypes.POINTER(jp_tune_result)]),
+        "jp_tune_clear": (st, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -193,6 +202,20 @@ def jp_plan_create(r_x, r_y, s_z, s_y, opt: Optional[jp_options] = None, stream=
     _check(lib.jp_plan_create(_ptr(r_x), _ptr(r_y), n_r, _ptr(s_z), _ptr(s_y), n_s,
                               ctypes.byref(opt) if opt is not None else None, _stream(stream), ctypes.byref(h)))
     return h.value
+
+
+def jp_tune(r_x, r_y, s_z, s_y, opt: Optional[jp_options] = None, stream=None) -> Dict[str, float]:
+    """Time the candidate thresholds on this query and store the fastest one's cost ratio."""
+    r = jp_tune_result()
+    n_r = int(r_x.numel()) if r_x is not None else 0
+    n_s = int(s_z.numel()) if s_z is not None else 0
+    _check(lib.jp_tune(_ptr(r_x), _ptr(r_y), n_r, _ptr(s_z), _ptr(s_y), n_s,
+                       ctypes.byref(opt) if opt is not None else None, _stream(stream), ctypes.byref(r)))
+    return {name: getattr(r, name) for name, _ in jp_tune_result._fields_ if name != "pad_"}
+
+
+def jp_tune_clear():
+    _check(lib.jp_tune_clear())
 
 
 def jp_execute(plan: int, stream=None):

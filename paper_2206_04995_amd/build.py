@@ -23,6 +23,7 @@ SOURCES = [
     "output.hip",
     "plan.cpp",
     "server.cpp",
+    "tune.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -326,7 +326,12 @@ void Plan::partition(hipStream_t s) {
     } else {
       int64_t nx = h_xbase[i + 1] - h_xbase[i], nz = h_zbase[i + 1] - h_zbase[i];
       int64_t ns = h_sbase[i + 1] - h_sbase[i];
-      h_tau[i] = tau_from_cost(nx, nz, ns, h_outj[i], c_de, c_fix);
+      double c = c_de, cf = c_fix, tuned = 0.0;
+      if (tuned_ratio(shape_signature(nx, nz, ns, h_outj[i]), &tuned)) {  // set by jp_tune
+        c = tuned;
+        cf = 0.0;
+      }
+      h_tau[i] = tau_from_cost(nx, nz, ns, h_outj[i], c, cf);
     }
   }
   d_tau = A.alloc<int64_t>(n, s);

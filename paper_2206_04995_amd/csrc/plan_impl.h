@@ -112,5 +112,8 @@ struct Plan {
 };
 
 int64_t tau_from_cost(int64_t nx, int64_t nz, int64_t ns, int64_t out_j, double c_de_over_sp, double c_fix_over_sp);
+// shape signature of one instance, and the cost ratio c_de / c_sp stored for it by jp_tune
+uint64_t shape_signature(int64_t nx, int64_t nz, int64_t ns, int64_t out_j);
+bool tuned_ratio(uint64_t sig, double* ratio);
 
 }  // namespace jp

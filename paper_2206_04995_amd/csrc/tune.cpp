@@ -1,0 +1,175 @@
+// Autotuner of the dense/sparse threshold (paper Sec. 2.6, f2).
+//
+// The cost model puts z in the dense part iff m_z > tau with
+// tau = (c_de / c_sp) * |X| * |S| / OUT_J (c_fix = 0): the only free number is
+// the cost ratio of one DenseEC bit decision to one SparseBMM join row, which
+// depends on the kernels and the shape of the data.  jp_tune measures the whole
+// plan + count pass of a query for a set of thresholds (all dense, all sparse,
+// the model's tau scaled by powers of 4, and quantiles of m_z), checks that
+// every threshold gives the same counts (the partition is intersection-free,
+// Sec. 2.3, so it must), and stores the ratio implied by the fastest threshold
+// under the query's shape signature.  Plans with JP_TAU_AUTO then take tau from
+// the stored ratio of their (instance's) signature.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/jp.h"
+#include "plan_impl.h"
+
+namespace jp {
+namespace {
+
+std::mutex g_mu;
+std::map<uint64_t, double> g_ratio;  // signature -> c_de / c_sp
+
+int log2_bucket(double v) { return v < 1.0 ? 0 : std::min(63, int(std::floor(std::log2(v))) + 1); }
+
+}  // namespace
+
+uint64_t shape_signature(int64_t nx, int64_t nz, int64_t ns, int64_t out_j) {
+  const uint64_t a = uint64_t(log2_bucket(double(nx))), b = uint64_t(log2_bucket(double(nz)));
+  const uint64_t c = uint64_t(log2_bucket(double(ns)));
+  const uint64_t d = uint64_t(log2_bucket(ns > 0 ? double(out_j) / double(ns) : 0.0));
+  return (a << 24) | (b << 16) | (c << 8) | d;
+}
+
+bool tuned_ratio(uint64_t sig, double* ratio) {
+  std::lock_guard<std::mutex> g(g_mu);
+  auto it = g_ratio.find(sig);
+  if (it == g_ratio.end()) return false;
+  *ratio = it->second;
+  return true;
+}
+
+}  // namespace jp
+
+using namespace jp;
+
+namespace {
+
+struct Trial {
+  int64_t tau;
+  double ms;
+  int64_t counts[3];
+};
+
+// wall time of plan + count pass + count read-back for one threshold
+Trial run_trial(const jp_instance& in, const jp_options& base, int64_t tau, hipStream_t s, int reps) {
+  Trial t{tau, 1e300, {0, 0, 0}};
+  jp_options o = base;
+  o.tau_mode = JP_TAU_FIXED;
+  o.dense_threshold = tau;
+  o.flags = 0;
+  for (int r = 0; r < reps; ++r) {
+    JP_HIP(hipStreamSynchronize(s));
+    const auto t0 = std::chrono::steady_clock::now();
+    Plan p;
+    p.build(&in, 1, &o, s);
+    p.execute(s);
+    p.fetch_totals(s);
+    const auto t1 = std::chrono::steady_clock::now();
+    t.ms = std::min(t.ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+    for (int k = 0; k < 3; ++k) t.counts[k] = p.h_tot[k];
+    p.A.release(s);
+  }
+  return t;
+}
+
+}  // namespace
+
+extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r, const int32_t* s_z,
+                             const int32_t* s_y, int64_t n_s, const jp_options* opt, hipStream_t stream,
+                             jp_tune_result* out) {
+  if (!out) {
+    set_last_error("out is null");
+    return JP_EINVAL;
+  }
+  if (n_r < 0 || n_s < 0 || n_r > INT32_MAX || n_s > INT32_MAX || (n_r > 0 && (!r_x || !r_y)) ||
+      (n_s > 0 && (!s_z || !s_y))) {
+    set_last_error("bad columns");
+    return JP_EINVAL;
+  }
+  if (opt && (opt->flags & ~(JP_FLAG_TIMING | JP_FLAG_GRAPH))) {
+    set_last_error("unknown flag bits");
+    return JP_EINVAL;
+  }
+  try {
+    jp_options base{};
+    if (opt) base = *opt;
+    base.tau_mode = JP_TAU_AUTO;
+    const jp_instance in{r_x, r_y, s_z, s_y, n_r, n_s};
+    // the untuned model's plan: shape, OUT_J and m_z
+    Plan p0;
+    jp_options o0 = base;
+    o0.flags = 0;
+    p0.build(&in, 1, &o0, stream);
+    const int64_t nx = p0.NX, nz = p0.NZ, ns = p0.NS, out_j = p0.h_outj.empty() ? 0 : p0.h_outj[0];
+    std::vector<int32_t> mz(size_t(std::max<int64_t>(nz, 0)));
+    if (nz > 0) JP_HIP(hipMemcpyAsync(mz.data(), p0.m_z, size_t(nz) * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    JP_HIP(hipStreamSynchronize(stream));
+    const int64_t tau_model = p0.h_tau.empty() ? 0 : p0.h_tau[0];
+    p0.A.release(stream);
+
+    std::vector<int64_t> cand = {-1, INT64_MAX};
+    if (out_j > 0 && nx > 0 && ns > 0) {
+      const double unit = double(nx) * double(ns) / double(out_j);  // tau per unit of c_de / c_sp
+      const double c0 = tau_model >= 0 && unit > 0 ? double(tau_model) / unit : 0.05;
+      for (double f : {1.0 / 16, 1.0 / 4, 1.0, 4.0, 16.0}) {
+        const double t = std::floor(c0 * f * unit);
+        cand.push_back(t > 9.0e18 ? INT64_MAX : int64_t(t));
+      }
+    }
+    if (!mz.empty()) {
+      std::sort(mz.begin(), mz.end());
+      for (double q : {0.25, 0.5, 0.75, 0.9, 0.99}) cand.push_back(mz[size_t(q * double(mz.size() - 1))]);
+    }
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+
+    const Trial model = run_trial(in, base, tau_model, stream, 2);
+    Trial best = model;
+    for (int64_t tau : cand) {
+      const Trial t = run_trial(in, base, tau, stream, 2);
+      if (t.counts[0] != model.counts[0])
+        throw Error(JP_ESTATE, "thresholds gave different counts: " + std::to_string(t.counts[0]) + " vs " +
+                                   std::to_string(model.counts[0]));
+      if (t.ms < best.ms) best = t;
+    }
+    double ratio;
+    if (best.tau == INT64_MAX) ratio = 1e300;
+    else if (best.tau < 0 || out_j <= 0 || nx <= 0 || ns <= 0) ratio = 0.0;
+    else ratio = (double(best.tau) + 0.5) * double(out_j) / (double(nx) * double(ns));
+    const uint64_t sig = shape_signature(nx, nz, ns, out_j);
+    {
+      std::lock_guard<std::mutex> g(g_mu);
+      g_ratio[sig] = ratio;
+    }
+    out->tau = best.tau;
+    out->cost_ratio = ratio;
+    out->best_ms = best.ms;
+    out->model_ms = model.ms;
+    out->model_tau = tau_model;
+    out->candidates = int32_t(cand.size());
+    out->pad_ = 0;
+    out->signature = sig;
+    return JP_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return jp_status(e.status);
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return JP_EHIP;
+  }
+}
+
+extern "C" jp_status jp_tune_clear(void) {
+  std::lock_guard<std::mutex> g(g_mu);
+  g_ratio.clear();
+  return JP_OK;
+}
