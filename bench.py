@@ -124,6 +124,17 @@ def batched(args):
     print(f"[bench] {args.instances} instances, {n_tuples} tuples, generated in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
+    tuned = []
+    if not args.no_tune:
+        # one representative per shape signature among the first instances (both paths use the result)
+        P.jp_tune_clear()
+        seen = set()
+        for c in cols[:args.tune_sample]:
+            r = P.jp_tune(*c, stream=stream)
+            if r["signature"] not in seen:
+                seen.add(r["signature"])
+                tuned.append({"tau": r["tau"], "model_tau": r["model_tau"], "signature": r["signature"]})
+        print(f"[bench] tuned {len(seen)} shape signatures", file=sys.stderr, flush=True)
 
     def plain():
         out = []
@@ -172,7 +183,7 @@ def batched(args):
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic (seeded generator, inputs resident in HBM)",
-        "config": {"workload": "batched instances", "instances": args.instances,
+        "config": {"workload": "batched instances", "instances": args.instances, "tuned_signatures": len(tuned),
                    "tuples_per_side": f"log-uniform [1e3, {args.batch_hi:.0e}]", "key_domain": "10% of tuples",
                    "y": "uniform (even) / Zipf 1.2 (odd)", "pairs": pairs, "tuples": n_tuples,
                    "plain_ms": res["plain"][0], "plain_pairs_per_s": pairs / (res["plain"][0] * 1e-3),
@@ -216,6 +227,11 @@ def served(args):
             return P.jp_count(h, stream)[0]
         finally:
             P.jp_plan_destroy(h)
+
+    if not args.no_tune:  # thresholds for the shapes of the first queries and of the large tables
+        P.jp_tune_clear()
+        for c in small_cols[:args.tune_sample] + large_cols[:1]:
+            P.jp_tune(*c, stream=stream)
 
     # calibration: service time of the serial path with every query present at once
     for c in queries[: min(8, len(queries))]:
@@ -304,7 +320,9 @@ def main():
     ap.add_argument("--batch-hi", type=float, default=1e6, help="batched workload: largest tuples per side")
     ap.add_argument("--cpu-sample-mod", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tau", type=int, default=None, help="fixed dense threshold (default: cost model)")
+    ap.add_argument("--tau", type=int, default=None, help="fixed dense threshold (default: tuned cost model)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the threshold autotuner (untimed, before warmup)")
+    ap.add_argument("--tune-sample", type=int, default=16, help="batched workload: instances the tuner times")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain elementwise copy over this many MiB (a reference for HBM counters)")
     args = ap.parse_args()
@@ -344,6 +362,12 @@ def main():
     else:
         opt = P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=args.tau, flags=P.JP_FLAG_TIMING)
     stream = torch.cuda.current_stream()
+    tune = None
+    if not args.no_tune and args.tau is None:
+        P.jp_tune_clear()
+        tune = P.jp_tune(*cols, stream=stream)
+        print(f"[bench] tuned tau {tune['tau']} (model {tune['model_tau']}): {tune['best_ms']:.2f} ms vs "
+              f"{tune['model_ms']:.2f} ms", file=sys.stderr, flush=True)
 
     def step(want_work=False):
         h = P.jp_plan_create(*cols, opt=opt, stream=stream)
@@ -428,7 +452,8 @@ def main():
         "config": dict(desc, pairs=total, dense_pairs=dense, sparse_pairs=sparse, tau=st["tau"],
                        n_z_dense=st["n_z_dense"], k_hot=st["k_hot"], out_j=st["out_j"],
                        input_tuples_per_s=(inst.n_r + inst.n_s) / (ms * 1e-3),
-                       kernel_ms={"sparse": sp_ms, "dense": de_ms, "execute": ex_ms}),
+                       kernel_ms={"sparse": sp_ms, "dense": de_ms, "execute": ex_ms},
+                       tau_tuned=None if tune is None else {"tau": tune["tau"], "model_tau": tune["model_tau"]}),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

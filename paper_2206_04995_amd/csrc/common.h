@@ -72,6 +72,38 @@ __device__ __forceinline__ int find_inst(const T* __restrict__ base, int n_inst,
   return lo;
 }
 
+// Segment index of increasing positions: the first call searches, later calls
+// step forward (or search again after a long gap).  Loops over contiguous
+// chunks (CHUNK_LOOP) keep the steps short, so most lookups cost one load.
+template <class T>
+struct SegCursor {
+  const T* base;
+  int n;
+  int cur = -1;
+  __device__ SegCursor(const T* b, int n_) : base(b), n(n_) {}
+  __device__ int operator()(T g) {
+    if (n == 1) return 0;
+    if (cur < 0 || g < base[cur]) return cur = find_inst<T>(base, n, g);
+    for (int steps = 0; g >= base[cur + 1]; ++steps) {
+      if (steps == 8) return cur = find_inst<T>(base, n, g);
+      ++cur;
+    }
+    return cur;
+  }
+};
+
+// Block b covers elements [b * ch, (b + 1) * ch) of [0, n); its threads stride
+// by blockDim inside the chunk, so each thread's positions grow in small steps.
+#define CHUNK_LOOP(i, n, ch)                                                                     \
+  for (int64_t i = int64_t(blockIdx.x) * (ch) + threadIdx.x,                                      \
+               i##_end = (int64_t(blockIdx.x) + 1) * (ch) < int64_t(n) ? (int64_t(blockIdx.x) + 1) * (ch) \
+                                                                   : int64_t(n);                   \
+       i < i##_end; i += blockDim.x)
+
+constexpr int JP_CHUNK = 4096;  // elements per block of CHUNK_LOOP kernels (256 threads x 16)
+
+inline int chunk_grid(int64_t n, int ch = JP_CHUNK) { return int(n <= 0 ? 1 : (n + ch - 1) / ch); }
+
 // first index in [lo, hi) with a[i] >= v (a ascending)
 template <class T>
 __device__ __forceinline__ int64_t lower_bound_dev(const T* __restrict__ a, int64_t lo, int64_t hi, T v) {

@@ -127,18 +127,20 @@ __global__ void __launch_bounds__(BT, 1) k_dense_mfma(const int8_t* __restrict__
 }
 
 // key index of every join key with a dense S entry (-1 otherwise)
+// key index of every join key with a dense S entry and an R row (-1 otherwise)
 __global__ void k_panel_keys(const int32_t* __restrict__ sptr, const int32_t* __restrict__ spptr,
-                             const int32_t* __restrict__ E, int64_t n_y, int32_t* __restrict__ kmap) {
+                             const int32_t* __restrict__ dR, const int32_t* __restrict__ E, int64_t n_y,
+                             int32_t* __restrict__ kmap) {
   for (int64_t y = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; y < n_y; y += int64_t(gridDim.x) * blockDim.x) {
     const int dd = (sptr[y + 1] - sptr[y]) - (spptr[y + 1] - spptr[y]);
-    kmap[y] = dd > 0 ? E[y] : -1;
+    kmap[y] = (dd > 0 && dR[y] > 0) ? E[y] : -1;
   }
 }
 
-__global__ void k_panel_key_flags(const int32_t* __restrict__ sptr, const int32_t* __restrict__ spptr, int64_t n_y,
-                                  int32_t* __restrict__ flag) {
+__global__ void k_panel_key_flags(const int32_t* __restrict__ sptr, const int32_t* __restrict__ spptr,
+                                  const int32_t* __restrict__ dR, int64_t n_y, int32_t* __restrict__ flag) {
   for (int64_t y = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; y < n_y; y += int64_t(gridDim.x) * blockDim.x)
-    flag[y] = ((sptr[y + 1] - sptr[y]) - (spptr[y + 1] - spptr[y])) > 0 ? 1 : 0;
+    flag[y] = (((sptr[y + 1] - sptr[y]) - (spptr[y + 1] - spptr[y])) > 0 && dR[y] > 0) ? 1 : 0;
 }
 
 // A[x][kmap[y]] = 1 for every R entry (one wavefront per row)
@@ -170,15 +172,15 @@ inline int grid256(int64_t n) { return int(std::max<int64_t>(1, std::min<int64_t
 
 }  // namespace
 
-int64_t panel_key_count(const int32_t* sptr, const int32_t* spptr, int64_t n_y, int32_t* kmap, Arena& T,
-                        hipStream_t s) {
+int64_t panel_key_count(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, int32_t* kmap,
+                        Arena& T, hipStream_t s) {
   if (n_y <= 0) return 0;
   int32_t* flag = T.alloc<int32_t>(n_y, s);
-  hipLaunchKernelGGL(k_panel_key_flags, dim3(grid256(n_y)), dim3(256), 0, s, sptr, spptr, n_y, flag);
+  hipLaunchKernelGGL(k_panel_key_flags, dim3(grid256(n_y)), dim3(256), 0, s, sptr, spptr, dR, n_y, flag);
   JP_LAUNCH_CHECK();
   int32_t* E = T.alloc<int32_t>(n_y + 1, s);
   scan_excl_i32(flag, E, n_y, s, T);
-  hipLaunchKernelGGL(k_panel_keys, dim3(grid256(n_y)), dim3(256), 0, s, sptr, spptr, E, n_y, kmap);
+  hipLaunchKernelGGL(k_panel_keys, dim3(grid256(n_y)), dim3(256), 0, s, sptr, spptr, dR, E, n_y, kmap);
   JP_LAUNCH_CHECK();
   int32_t k = 0;
   JP_HIP(hipMemcpyAsync(&k, E + n_y, sizeof(int32_t), hipMemcpyDeviceToHost, s));

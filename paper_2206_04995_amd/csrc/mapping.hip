@@ -24,8 +24,9 @@ inline int grid(int64_t n, int cap = 1 << 20) {
 __global__ void k_make_keys(const int32_t* __restrict__ v, int64_t n, const int32_t* __restrict__ ebase,
                             int n_inst, const int64_t* __restrict__ koff, const int32_t* __restrict__ mn,
                             uint32_t* __restrict__ keys, uint32_t* __restrict__ payload) {
-  GRID_STRIDE(i, n) {
-    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(ebase, n_inst, int32_t(i));
+  SegCursor<int32_t> cur(ebase, n_inst);
+  CHUNK_LOOP(i, n, JP_CHUNK) {
+    const int inst = cur(int32_t(i));
     keys[i] = uint32_t(koff[inst] + (int64_t(v[i]) - int64_t(mn[inst])));
     if (payload) payload[i] = uint32_t(i);
   }
@@ -35,9 +36,10 @@ __global__ void k_make_keys_perm(const int32_t* __restrict__ v, const uint32_t* 
                                  const int32_t* __restrict__ ebase, int n_inst, const int64_t* __restrict__ koff,
                                  const int32_t* __restrict__ mn, const int32_t* __restrict__ E,
                                  uint32_t* __restrict__ keys, uint32_t* __restrict__ payload) {
-  GRID_STRIDE(p, n) {
+  SegCursor<int32_t> cur(ebase, n_inst);
+  CHUNK_LOOP(p, n, JP_CHUNK) {
     uint32_t g = perm[p];
-    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(ebase, n_inst, int32_t(g));
+    const int inst = cur(int32_t(p));  // sorted by instance first: same instance as g
     keys[p] = uint32_t(koff[inst] + (int64_t(v[g]) - int64_t(mn[inst])));
     payload[p] = uint32_t(E[p + 1] - 1);
   }
@@ -50,12 +52,13 @@ __global__ void k_head_flags(const uint32_t* __restrict__ keys, int64_t n, int32
 __global__ void k_assign_ids(const uint32_t* __restrict__ keys, int64_t n, const int32_t* __restrict__ E,
                              const int64_t* __restrict__ koff, const int32_t* __restrict__ mn, int n_inst,
                              int32_t* __restrict__ first, int32_t* __restrict__ vals) {
-  GRID_STRIDE(p, n) {
+  SegCursor<int64_t> kcur(koff, n_inst);
+  CHUNK_LOOP(p, n, JP_CHUNK) {
     int id = E[p];
     bool head = E[p + 1] != id;
     if (head) {
       uint32_t k = keys[p];
-      int inst = n_inst == 1 ? 0 : find_inst<int64_t>(koff, n_inst, int64_t(k));
+      const int inst = kcur(int64_t(k));
       first[id] = int32_t(p);
       vals[id] = int32_t(int64_t(k) - koff[inst] + int64_t(mn[inst]));
     }
@@ -72,8 +75,9 @@ __global__ void k_gather_bases(const int32_t* __restrict__ E, const int32_t* __r
 __global__ void k_semijoin(const int32_t* __restrict__ ry, int64_t n, const int32_t* __restrict__ ebase, int n_inst,
                            const int32_t* __restrict__ vals_y, const int32_t* __restrict__ y_base,
                            int32_t* __restrict__ keep, int32_t* __restrict__ yid) {
-  GRID_STRIDE(g, n) {
-    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(ebase, n_inst, int32_t(g));
+  SegCursor<int32_t> cur(ebase, n_inst);
+  CHUNK_LOOP(g, n, JP_CHUNK) {
+    const int inst = cur(int32_t(g));
     int32_t v = ry[g];
     int64_t lo = y_base[inst], hi = y_base[inst + 1];
     int64_t pos = lower_bound_dev<int32_t>(vals_y, lo, hi, v);
@@ -96,8 +100,9 @@ __global__ void k_semijoin_direct(const int32_t* __restrict__ ry, int64_t n, con
                                   int n_inst, const int64_t* __restrict__ koff, const int32_t* __restrict__ mn,
                                   const int32_t* __restrict__ table, int32_t* __restrict__ keep,
                                   int32_t* __restrict__ yid) {
-  GRID_STRIDE(g, n) {
-    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(ebase, n_inst, int32_t(g));
+  SegCursor<int32_t> cur(ebase, n_inst);
+  CHUNK_LOOP(g, n, JP_CHUNK) {
+    const int inst = cur(int32_t(g));
     const int64_t rel = int64_t(ry[g]) - int64_t(mn[inst]);
     const int64_t range = koff[inst + 1] - koff[inst];
     const int32_t id = (rel >= 0 && rel < range) ? table[koff[inst] + rel] : -1;
@@ -198,7 +203,7 @@ __global__ void k_out_j(const int32_t* __restrict__ dR, const int32_t* __restric
 void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff, const int32_t* mn,
                uint32_t* keys, uint32_t* payload, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_make_keys, dim3(grid(n)), dim3(NT), 0, s, v, n, ebase, n_inst, koff, mn, keys, payload);
+  hipLaunchKernelGGL(k_make_keys, dim3(chunk_grid(n)), dim3(NT), 0, s, v, n, ebase, n_inst, koff, mn, keys, payload);
   JP_LAUNCH_CHECK();
 }
 
@@ -206,7 +211,7 @@ void make_keys_perm(const int32_t* v, const uint32_t* perm, int64_t n, const int
                     const int64_t* koff, const int32_t* mn, const int32_t* E, uint32_t* keys, uint32_t* payload,
                     hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_make_keys_perm, dim3(grid(n)), dim3(NT), 0, s, v, perm, n, ebase, n_inst, koff, mn, E, keys,
+  hipLaunchKernelGGL(k_make_keys_perm, dim3(chunk_grid(n)), dim3(NT), 0, s, v, perm, n, ebase, n_inst, koff, mn, E, keys,
                      payload);
   JP_LAUNCH_CHECK();
 }
@@ -223,7 +228,7 @@ void assign_ids(const uint32_t* keys, int64_t n, const int32_t* E, const int64_t
     fill_i32(first, 1, 0, s);
     return;
   }
-  hipLaunchKernelGGL(k_assign_ids, dim3(grid(n)), dim3(NT), 0, s, keys, n, E, koff, mn, n_inst, first, vals);
+  hipLaunchKernelGGL(k_assign_ids, dim3(chunk_grid(n)), dim3(NT), 0, s, keys, n, E, koff, mn, n_inst, first, vals);
   JP_LAUNCH_CHECK();
 }
 
@@ -235,7 +240,7 @@ void gather_bases(const int32_t* E, const int32_t* ebase, int n_inst, int32_t* o
 void semijoin(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, const int32_t* vals_y,
               const int32_t* y_base, int32_t* keep, int32_t* yid, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_semijoin, dim3(grid(n)), dim3(NT), 0, s, ry, n, ebase, n_inst, vals_y, y_base, keep, yid);
+  hipLaunchKernelGGL(k_semijoin, dim3(chunk_grid(n)), dim3(NT), 0, s, ry, n, ebase, n_inst, vals_y, y_base, keep, yid);
   JP_LAUNCH_CHECK();
 }
 
@@ -248,7 +253,7 @@ void semijoin_direct(const int32_t* ry, int64_t n, const int32_t* ebase, int n_i
     JP_LAUNCH_CHECK();
   }
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_semijoin_direct, dim3(grid(n)), dim3(NT), 0, s, ry, n, ebase, n_inst, koff, mn, table, keep,
+  hipLaunchKernelGGL(k_semijoin_direct, dim3(chunk_grid(n)), dim3(NT), 0, s, ry, n, ebase, n_inst, koff, mn, table, keep,
                      yid);
   JP_LAUNCH_CHECK();
 }

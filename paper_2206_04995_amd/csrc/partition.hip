@@ -25,8 +25,9 @@ inline int grid(int64_t n, int cap = 1 << 20) {
 
 __global__ void k_dense_flags(const int32_t* __restrict__ m_z, int64_t n_z, const int32_t* __restrict__ z_base,
                               int n_inst, const int64_t* __restrict__ tau, int32_t* __restrict__ flag) {
-  GRID_STRIDE(z, n_z) {
-    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(z_base, n_inst, int32_t(z));
+  SegCursor<int32_t> zcur(z_base, n_inst);
+  CHUNK_LOOP(z, n_z, JP_CHUNK) {
+    const int inst = zcur(int32_t(z));
     flag[z] = int64_t(m_z[z]) > tau[inst] ? 1 : 0;
   }
 }
@@ -105,9 +106,10 @@ __global__ void k_hot_histogram(const int32_t* __restrict__ cnt_a, const int32_t
 __global__ void k_hot_flags(const int32_t* __restrict__ cnt_a, const int32_t* __restrict__ cnt_b,
                             const int32_t* __restrict__ dR, int64_t n_y, const int32_t* __restrict__ y_base,
                             int n_inst, const int64_t* __restrict__ theta, int32_t* __restrict__ hot) {
-  GRID_STRIDE(y, n_y) {
+  SegCursor<int32_t> ycur(y_base, n_inst);
+  CHUNK_LOOP(y, n_y, JP_CHUNK) {
     const int dd = space_count(cnt_a, cnt_b, y);
-    int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+    const int inst = ycur(int32_t(y));
     hot[y] = (dd > 0 && dR[y] > 0 && int64_t(dd) >= theta[inst]) ? 1 : 0;
   }
 }
@@ -119,12 +121,13 @@ __global__ void k_build_hot_bits(const int32_t* __restrict__ Ey, const int32_t* 
                                  const int32_t* __restrict__ y_base, const int32_t* __restrict__ zmap,
                                  const int64_t* __restrict__ hb_off, const int32_t* __restrict__ row_words,
                                  int n_inst, uint32_t* __restrict__ hb) {
-  GRID_STRIDE(p, n) {
+  SegCursor<int32_t> ycur(y_base, n_inst);
+  CHUNK_LOOP(p, n, JP_CHUNK) {
     const int32_t y = Ey[p + 1] - 1;
     if (!hot[y]) continue;
     const int32_t dl = zmap[scol[p]];
     if (dl < 0) continue;
-    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+    const int inst = ycur(y);
     const int64_t k = hotrow[y];
     uint32_t* row = hb + hb_off[inst] + k * row_words[inst];
     atomicOr(&row[dl >> 5], 1u << (dl & 31));
@@ -157,8 +160,9 @@ __global__ void k_compact_mapped(const int32_t* __restrict__ scol, const int32_t
 __global__ void k_zmap_dense(const int32_t* __restrict__ zflag, const int32_t* __restrict__ Edz, int64_t n_z,
                              const int32_t* __restrict__ z_base, const int32_t* __restrict__ zd_base, int n_inst,
                              int32_t* __restrict__ zmap) {
-  GRID_STRIDE(z, n_z) {
-    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(z_base, n_inst, int32_t(z));
+  SegCursor<int32_t> zcur(z_base, n_inst);
+  CHUNK_LOOP(z, n_z, JP_CHUNK) {
+    const int inst = zcur(int32_t(z));
     zmap[z] = zflag[z] ? Edz[z] - zd_base[inst] : -1;
   }
 }
@@ -169,12 +173,13 @@ __global__ void k_zmap_resid(const int32_t* __restrict__ zflag, const int32_t* _
                              const int32_t* __restrict__ rflag, const int32_t* __restrict__ Erd, int64_t n_z,
                              const int32_t* __restrict__ z_base, const int32_t* __restrict__ zc_base, int n_inst,
                              int32_t* __restrict__ zmap) {
-  GRID_STRIDE(z, n_z) {
+  SegCursor<int32_t> zcur(z_base, n_inst);
+  CHUNK_LOOP(z, n_z, JP_CHUNK) {
     int32_t v = -1;
     if (zflag[z]) {
       const int d = Edz[z];
       if (rflag[d]) {
-        const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(z_base, n_inst, int32_t(z));
+        const int inst = zcur(int32_t(z));
         v = Erd[d] - zc_base[inst];
       }
     }
@@ -207,9 +212,10 @@ __global__ void k_mark_pivot(const int32_t* __restrict__ Ey, const int32_t* __re
                              const int32_t* __restrict__ y_base, int n_inst, const int32_t* __restrict__ piv,
                              const int32_t* __restrict__ zflag, const int32_t* __restrict__ Edz,
                              int32_t* __restrict__ inP) {
-  GRID_STRIDE(p, n) {
+  SegCursor<int32_t> ycur(y_base, n_inst);
+  CHUNK_LOOP(p, n, JP_CHUNK) {
     const int32_t y = Ey[p + 1] - 1;
-    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+    const int inst = ycur(y);
     const int32_t z = scol[p];
     if (piv[inst] == y && zflag[z]) inP[Edz[z]] = 1;
   }
@@ -218,8 +224,9 @@ __global__ void k_mark_pivot(const int32_t* __restrict__ Ey, const int32_t* __re
 // out[d] = 1 iff dense index d belongs to an instance with a pivot and is outside the pivot row
 __global__ void k_resid_flags(const int32_t* __restrict__ inP, int64_t n, const int32_t* __restrict__ zd_base,
                               int n_inst, const int32_t* __restrict__ piv, int32_t* __restrict__ out) {
-  GRID_STRIDE(d, n) {
-    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(zd_base, n_inst, int32_t(d));
+  SegCursor<int32_t> dcur(zd_base, n_inst);
+  CHUNK_LOOP(d, n, JP_CHUNK) {
+    const int inst = dcur(int32_t(d));
     out[d] = (piv[inst] >= 0 && !inP[d]) ? 1 : 0;
   }
 }
@@ -296,16 +303,11 @@ __global__ void k_row_codes(const int32_t* __restrict__ rcol, int64_t n, const i
 __global__ void k_cold_win_entries(const int32_t* __restrict__ cptr, const int32_t* __restrict__ ccol, int64_t n_y,
                                    int64_t n_cold, const int32_t* __restrict__ y_base, int n_inst,
                                    const int64_t* __restrict__ cw_off, int32_t* __restrict__ cw) {
-  GRID_STRIDE(p, n_cold) {
-    // row of entry p: largest y with cptr[y] <= p
-    int64_t lo = 0, hi = n_y;
-    while (hi - lo > 1) {
-      int64_t mid = (lo + hi) >> 1;
-      if (cptr[mid] <= p) lo = mid;
-      else hi = mid;
-    }
-    const int32_t y = int32_t(lo);
-    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+  // row of entry p: largest y with cptr[y] <= p
+  SegCursor<int32_t> rowcur(cptr, int(n_y)), ycur(y_base, n_inst);
+  CHUNK_LOOP(p, n_cold, JP_CHUNK) {
+    const int32_t y = rowcur(int32_t(p));
+    const int inst = ycur(y);
     const int ny = y_base[inst + 1] - y_base[inst];
     const int yl = y - y_base[inst];
     const int wp = ccol[p] / DW_BITS;
@@ -355,15 +357,10 @@ __global__ void k_cold_win_scatter(const int32_t* __restrict__ cptr, const int32
                                    const int32_t* __restrict__ cw, const int64_t* __restrict__ cw_off,
                                    const int32_t* __restrict__ wptr, const int64_t* __restrict__ cwm_off,
                                    int32_t* __restrict__ ccol_w) {
-  GRID_STRIDE(p, n_cold) {
-    int64_t lo = 0, hi = n_y;
-    while (hi - lo > 1) {
-      int64_t mid = (lo + hi) >> 1;
-      if (cptr[mid] <= p) lo = mid;
-      else hi = mid;
-    }
-    const int32_t y = int32_t(lo);
-    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+  SegCursor<int32_t> rowcur(cptr, int(n_y)), ycur(y_base, n_inst);
+  CHUNK_LOOP(p, n_cold, JP_CHUNK) {
+    const int32_t y = rowcur(int32_t(p));
+    const int inst = ycur(y);
     const int ny = y_base[inst + 1] - y_base[inst];
     const int yl = y - y_base[inst];
     const int32_t d = ccol[p];
@@ -385,7 +382,7 @@ void cold_window_major(const int32_t* cptr, const int32_t* ccol, int64_t n_y, in
   JP_LAUNCH_CHECK();
   scan_excl_i32(cnt, wptr, cwm_total, s, a);
   if (n_cold > 0)
-    hipLaunchKernelGGL(k_cold_win_scatter, dim3(grid(n_cold)), dim3(NT), 0, s, cptr, ccol, n_y, n_cold, y_base, n_inst,
+    hipLaunchKernelGGL(k_cold_win_scatter, dim3(chunk_grid(n_cold)), dim3(NT), 0, s, cptr, ccol, n_y, n_cold, y_base, n_inst,
                        cw, cw_off, wptr, cwm_off, ccol_w);
   JP_LAUNCH_CHECK();
   a.give_back(cnt, s);
@@ -394,7 +391,7 @@ void cold_window_major(const int32_t* cptr, const int32_t* ccol, int64_t n_y, in
 void dense_flags(const int32_t* m_z, int64_t n_z, const int32_t* z_base, int n_inst, const int64_t* tau, int32_t* flag,
                  hipStream_t s) {
   if (n_z <= 0) return;
-  hipLaunchKernelGGL(k_dense_flags, dim3(grid(n_z)), dim3(NT), 0, s, m_z, n_z, z_base, n_inst, tau, flag);
+  hipLaunchKernelGGL(k_dense_flags, dim3(chunk_grid(n_z)), dim3(NT), 0, s, m_z, n_z, z_base, n_inst, tau, flag);
   JP_LAUNCH_CHECK();
 }
 
@@ -436,7 +433,7 @@ void hot_histogram(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR
 void hot_flags(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR, int64_t n_y, const int32_t* y_base,
                int n_inst, const int64_t* theta, int32_t* hot, hipStream_t s) {
   if (n_y <= 0) return;
-  hipLaunchKernelGGL(k_hot_flags, dim3(grid(n_y)), dim3(NT), 0, s, cnt_a, cnt_b, dR, n_y, y_base, n_inst, theta, hot);
+  hipLaunchKernelGGL(k_hot_flags, dim3(chunk_grid(n_y)), dim3(NT), 0, s, cnt_a, cnt_b, dR, n_y, y_base, n_inst, theta, hot);
   JP_LAUNCH_CHECK();
 }
 
@@ -444,7 +441,7 @@ void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int
                     const int32_t* y_base, const int32_t* zmap, const int64_t* hb_off, const int32_t* row_words,
                     int n_inst, uint32_t* hb, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_build_hot_bits, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, hot, hotrow, y_base, zmap, hb_off,
+  hipLaunchKernelGGL(k_build_hot_bits, dim3(chunk_grid(n)), dim3(NT), 0, s, Ey, scol, n, hot, hotrow, y_base, zmap, hb_off,
                      row_words, n_inst, hb);
   JP_LAUNCH_CHECK();
 }
@@ -472,14 +469,14 @@ void compact_mapped(const int32_t* scol, const int32_t* flag, const int32_t* E, 
 void zmap_dense(const int32_t* zflag, const int32_t* Edz, int64_t n_z, const int32_t* z_base, const int32_t* zd_base,
                 int n_inst, int32_t* zmap, hipStream_t s) {
   if (n_z <= 0) return;
-  hipLaunchKernelGGL(k_zmap_dense, dim3(grid(n_z)), dim3(NT), 0, s, zflag, Edz, n_z, z_base, zd_base, n_inst, zmap);
+  hipLaunchKernelGGL(k_zmap_dense, dim3(chunk_grid(n_z)), dim3(NT), 0, s, zflag, Edz, n_z, z_base, zd_base, n_inst, zmap);
   JP_LAUNCH_CHECK();
 }
 
 void zmap_resid(const int32_t* zflag, const int32_t* Edz, const int32_t* rflag, const int32_t* Erd, int64_t n_z,
                 const int32_t* z_base, const int32_t* zc_base, int n_inst, int32_t* zmap, hipStream_t s) {
   if (n_z <= 0) return;
-  hipLaunchKernelGGL(k_zmap_resid, dim3(grid(n_z)), dim3(NT), 0, s, zflag, Edz, rflag, Erd, n_z, z_base, zc_base,
+  hipLaunchKernelGGL(k_zmap_resid, dim3(chunk_grid(n_z)), dim3(NT), 0, s, zflag, Edz, rflag, Erd, n_z, z_base, zc_base,
                      n_inst, zmap);
   JP_LAUNCH_CHECK();
 }
@@ -498,14 +495,14 @@ void pivot_info(const int32_t* hotrow, int64_t n_y, const int32_t* y_base, int n
 void mark_pivot(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* y_base, int n_inst,
                 const int32_t* piv, const int32_t* zflag, const int32_t* Edz, int32_t* inP, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_mark_pivot, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, y_base, n_inst, piv, zflag, Edz, inP);
+  hipLaunchKernelGGL(k_mark_pivot, dim3(chunk_grid(n)), dim3(NT), 0, s, Ey, scol, n, y_base, n_inst, piv, zflag, Edz, inP);
   JP_LAUNCH_CHECK();
 }
 
 void resid_flags(const int32_t* inP, int64_t n, const int32_t* zd_base, int n_inst, const int32_t* piv, int32_t* out,
                  hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_resid_flags, dim3(grid(n)), dim3(NT), 0, s, inP, n, zd_base, n_inst, piv, out);
+  hipLaunchKernelGGL(k_resid_flags, dim3(chunk_grid(n)), dim3(NT), 0, s, inP, n, zd_base, n_inst, piv, out);
   JP_LAUNCH_CHECK();
 }
 
@@ -546,7 +543,7 @@ void cold_windows(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t
                   const int32_t* zd_base, int n_inst, const int64_t* cw_off, int32_t* cw, hipStream_t s) {
   if (n_y <= 0) return;
   if (n_cold > 0) {
-    hipLaunchKernelGGL(k_cold_win_entries, dim3(grid(n_cold)), dim3(NT), 0, s, cptr, ccol, n_y, n_cold, y_base, n_inst,
+    hipLaunchKernelGGL(k_cold_win_entries, dim3(chunk_grid(n_cold)), dim3(NT), 0, s, cptr, ccol, n_y, n_cold, y_base, n_inst,
                        cw_off, cw);
     JP_LAUNCH_CHECK();
   }

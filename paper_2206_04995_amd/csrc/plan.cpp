@@ -76,8 +76,9 @@ int key_layout(const std::vector<int32_t>& mn, const std::vector<int32_t>& mx, s
 // gather of per-instance device columns into one concatenated buffer
 __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int32_t* __restrict__ base, int n_inst,
                               int64_t n, int32_t* __restrict__ dst) {
-  for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x) {
-    int inst = find_inst<int32_t>(base, n_inst, int32_t(g));
+  SegCursor<int32_t> cur(base, n_inst);
+  CHUNK_LOOP(g, n, JP_CHUNK) {
+    const int inst = cur(int32_t(g));
     dst[g] = src[inst][g - base[inst]];
   }
 }
@@ -155,12 +156,12 @@ void Plan::build(const jp_instance* inst, int n, const jp_options* o, hipStream_
     int32_t* cat = A.alloc<int32_t>(2 * NR + 2 * NS, s);
     int32_t *crx = cat, *cry = cat + NR, *csz = cat + 2 * NR, *csy = cat + 2 * NR + NS;
     if (NR) {
-      hipLaunchKernelGGL(k_gather_cols, dim3(grid_of(NR)), dim3(256), 0, s, d_ptrs, d_rbase, n, NR, crx);
-      hipLaunchKernelGGL(k_gather_cols, dim3(grid_of(NR)), dim3(256), 0, s, d_ptrs + n, d_rbase, n, NR, cry);
+      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NR)), dim3(256), 0, s, d_ptrs, d_rbase, n, NR, crx);
+      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NR)), dim3(256), 0, s, d_ptrs + n, d_rbase, n, NR, cry);
     }
     if (NS) {
-      hipLaunchKernelGGL(k_gather_cols, dim3(grid_of(NS)), dim3(256), 0, s, d_ptrs + 2 * n, d_sbase, n, NS, csz);
-      hipLaunchKernelGGL(k_gather_cols, dim3(grid_of(NS)), dim3(256), 0, s, d_ptrs + 3 * n, d_sbase, n, NS, csy);
+      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NS)), dim3(256), 0, s, d_ptrs + 2 * n, d_sbase, n, NS, csz);
+      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NS)), dim3(256), 0, s, d_ptrs + 3 * n, d_sbase, n, NS, csy);
     }
     JP_LAUNCH_CHECK();
     rx = crx;
@@ -380,6 +381,8 @@ void Plan::partition(hipStream_t s) {
   int32_t* zmap = T.alloc<int32_t>(NZa, s);
   zmap_dense(zflag, Edz, NZ, z_base, zd_base, n, zmap, s);
   build_space(d0, zmap, sptr, spptr, &h_hist, T, s);
+  dense_keys0 = 0;  // keys with a dense S entry and an R row (the hot histogram covers them all)
+  for (int q = 0; q < 32; ++q) dense_keys0 += h_hist[q];
   choose_dense_kernel(T, s);
   if (!use_mfma) pivot_split(T, s);
   T.release(s);
@@ -393,19 +396,19 @@ void Plan::partition(hipStream_t s) {
 // whenever the panels fit, JP_DENSE_BITS never uses it.
 void Plan::choose_dense_kernel(Arena& T, hipStream_t s) {
   use_mfma = false;
-  if (n_inst != 1 || opt.dense_kernel == JP_DENSE_BITS || NZd <= 0 || NX <= 0) return;
+  if (n_inst != 1 || opt.dense_kernel == JP_DENSE_BITS || NZd <= 0 || NX <= 0 || dense_keys0 <= 0) return;
+  const double min_density = env_double("JP_MFMA_MIN_DENSITY", 1.0 / 32.0);
+  if (opt.dense_kernel != JP_DENSE_MFMA && double(NRp) / (double(NX) * double(dense_keys0)) < min_density) return;
   const int64_t NYa = std::max<int64_t>(NY, 1);
   int32_t* kmap = T.alloc<int32_t>(NYa, s);
-  K_panel = panel_key_count(sptr, spptr, NY, kmap, T, s);
+  K_panel = panel_key_count(sptr, spptr, dR, NY, kmap, T, s);
   if (K_panel <= 0) return;
   k_pad = mfma_pad_keys(K_panel);
   nx_pad = mfma_pad_rows(NX);
   nz_pad = mfma_pad_cols(NZd);
   const int64_t lim = int64_t(1) << 31;
   if (nx_pad * k_pad > lim || nz_pad * k_pad > lim) return;
-  const double density = double(NRp) / (double(NX) * double(K_panel));
-  const double min_density = env_double("JP_MFMA_MIN_DENSITY", 1.0 / 32.0);
-  if (opt.dense_kernel != JP_DENSE_MFMA && density < min_density) return;
+
   use_mfma = true;
   pA = A.alloc<int8_t>(nx_pad * k_pad, s);
   pBt = A.alloc<int8_t>(nz_pad * k_pad, s);
@@ -577,6 +580,19 @@ void Plan::pivot_split(Arena& T, hipStream_t s) {
   const double mode = env_double("JP_PIVOT", 1.0);
   if (mode == 0.0) return;
   DenseSpace& d0 = ds[0];
+  // The split pays only for an instance with dense z beyond one window and
+  // many (x, dense z) cells (its second set of tables costs plan time in
+  // proportion to its tuples): candidates are decided from host-known sizes
+  // before any device work.
+  const double min_cells = env_double("JP_PIVOT_MIN_CELLS", 1e11);
+  std::vector<char> cand(n, 0);
+  bool any = false;
+  for (int i = 0; i < n; ++i) {
+    const int64_t nx = h_xbase[i + 1] - h_xbase[i], zd = h_zdbase[i + 1] - h_zdbase[i];
+    cand[i] = d0.h_K[i] > 0 && (mode == 2.0 || (zd > DW_BITS && double(nx) * double(zd) >= min_cells));
+    any = any || cand[i];
+  }
+  if (!any) return;
   int32_t* info = T.alloc<int32_t>(3 * int64_t(n), s);
   d_piv = A.alloc<int32_t>(n, s);
   pivot_info(d0.hotrow, NY, y_base, n, dR, sptr, spptr, d_piv, info, s);
@@ -587,7 +603,7 @@ void Plan::pivot_split(Arena& T, hipStream_t s) {
   for (int i = 0; i < n; ++i) {
     const int32_t p = h_info[3 * i], dr = h_info[3 * i + 1], cnt = h_info[3 * i + 2];
     const int64_t nx = h_xbase[i + 1] - h_xbase[i], zd = h_zdbase[i + 1] - h_zdbase[i];
-    if (p >= 0 && (mode == 2.0 || (zd > DW_BITS && 4 * int64_t(dr) >= nx && 2 * int64_t(cnt) >= zd))) {
+    if (p >= 0 && cand[i] && (mode == 2.0 || (4 * int64_t(dr) >= nx && 2 * int64_t(cnt) >= zd))) {
       h_piv[i] = p;
       ++n_piv;
     }

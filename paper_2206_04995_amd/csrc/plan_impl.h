@@ -63,7 +63,7 @@ struct Plan {
   // INT8-MFMA count of the dense part (single-instance plans with a dense panel)
   bool use_mfma = false;
   int8_t *pA = nullptr, *pBt = nullptr;
-  int64_t K_panel = 0, k_pad = 0, nx_pad = 0, nz_pad = 0;
+  int64_t K_panel = 0, k_pad = 0, nx_pad = 0, nz_pad = 0, dense_keys0 = 0;
   void choose_dense_kernel(Arena& T, hipStream_t s);
   void build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a, const int32_t* cnt_b,
                    const std::vector<int32_t>* hist_pre, Arena& T, hipStream_t s);

@@ -169,10 +169,10 @@ void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const i
 void dense_ec_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const int32_t* base_cnt, int32_t* cnt,
                    hipStream_t s);
 // INT8-MFMA DenseEC for one instance with a dense panel: kmap[y] = panel key of y
-// (or -1), returns the number of panel keys (syncs s); panels A [nx_pad][k_pad]
+// (a dense S entry and an R row; else -1), returns the number of panel keys (syncs s); panels A [nx_pad][k_pad]
 // and Bt [nz_pad][k_pad] of 0/1 bytes; count pass writes cnt[0, nx)
-int64_t panel_key_count(const int32_t* sptr, const int32_t* spptr, int64_t n_y, int32_t* kmap, Arena& T,
-                        hipStream_t s);
+int64_t panel_key_count(const int32_t* sptr, const int32_t* spptr, const int32_t* dR, int64_t n_y, int32_t* kmap,
+                        Arena& T, hipStream_t s);
 void build_panels(const int32_t* rptr, const int32_t* rcol, int64_t n_x, const int32_t* Ey, const int32_t* scol,
                   int64_t n_s, const int32_t* zflag, const int32_t* Edz, const int32_t* kmap, int64_t k_pad,
                   int64_t nx_pad, int64_t nz_pad, int8_t* A, int8_t* Bt, hipStream_t s);

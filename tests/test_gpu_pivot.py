@@ -80,11 +80,14 @@ def test_pivot_batch_matches_single(pivot_env):
             assert np.array_equal(mx.cpu().numpy(), ox) and np.array_equal(mz.cpu().numpy(), oz)
 
 
-def test_auto_pivot_medium_skewed(pivot_env):
-    """Skewed query large enough for the automatic split (dense z > one window,
-    the top key in a quarter of the rows and half of the z): counts equal the
-    oracle's and the run without the split; sampled rows are exact."""
+def test_auto_pivot_medium_skewed(pivot_env, monkeypatch):
+    """Skewed query that meets the automatic split's conditions (dense z > one
+    window, the top key in a quarter of the rows and half of the z; the size
+    gate is lowered to this query's cells): counts equal the oracle's and the
+    run without the split; sampled rows are exact."""
     import paper_2206_04995_amd as P
+
+    monkeypatch.setenv("JP_PIVOT_MIN_CELLS", "1e6")
 
     inst = synth.config2(3, n=150_000, dom_xz=20_000, dom_y=2_000)
     print("[case] auto pivot medium skewed", flush=True)
