@@ -77,6 +77,8 @@ typedef struct {
   int32_t k_hot_max;             /* cap on hot join keys per instance in DenseEC (0 = 256; max 1024) */
   int32_t flags;                 /* JP_FLAG_* bits; others must be 0 */
   int64_t workspace_limit_bytes; /* 0 = no limit; exceeding it returns JP_ENOMEM */
+  int32_t window_group;          /* z windows per workgroup of the bit-path DenseEC count (0 = automatic, max 64) */
+  int32_t reserved;              /* must be 0 */
 } jp_options;
 
 /* Kernel times of the last jp_execute (filled by jp_plan_timings for a plan
@@ -197,21 +199,26 @@ void jp_batch_destroy(jp_batch* b);
  * jp_tune times the plan + count pass of one query (device columns as for
  * jp_plan_create) for a set of thresholds (all dense, all sparse, the model's
  * tau scaled by 1/16 .. 16, quantiles of m_z), checks that all give the same
- * counts (the partition is intersection-free, Sec. 2.3), and stores the cost
- * ratio of the fastest under the query's shape signature (log2 buckets of
- * |X|, |Z|, |S| and OUT_J / |S|).  Later plans and batch instances with
- * JP_TAU_AUTO and that signature take tau from the stored ratio.  The store is
- * process-wide and thread-safe.  jp_tune syncs the stream; it returns
- * JP_ESTATE if two thresholds disagree. */
+ * counts (the partition is intersection-free, Sec. 2.3), then, at the fastest
+ * threshold, searches the DenseEC count kernel (bit path or INT8 MFMA), the
+ * hot-key cap and the windows per workgroup one after the other.  The cost
+ * ratio and these choices are stored under the query's shape signature (log2
+ * buckets of |X|, |Z|, |S| and OUT_J / |S|); later plans and batch instances
+ * of that signature use them for every option left automatic (tau_mode
+ * JP_TAU_AUTO, dense_kernel JP_DENSE_AUTO, k_hot_max 0, window_group 0).  The
+ * store is process-wide and thread-safe.  jp_tune syncs the stream; it returns
+ * JP_ESTATE if two settings disagree on the counts. */
 typedef struct {
   int64_t tau;         /* fastest threshold (dense iff m_z > tau; INT64_MAX: all sparse) */
   int64_t model_tau;   /* the untuned cost model's threshold */
   double cost_ratio;   /* c_de / c_sp stored for the signature */
   double best_ms;      /* plan + count pass at tau (best of 2) */
   double model_ms;     /* the same at model_tau */
-  int32_t candidates;  /* thresholds timed besides model_tau */
-  int32_t pad_;
-  uint64_t signature;  /* shape signature the ratio is stored under */
+  int32_t candidates;  /* settings timed besides the model's */
+  int32_t dense_kernel;  /* chosen jp_dense_kernel */
+  int32_t k_hot_max;     /* chosen hot-key cap */
+  int32_t window_group;  /* chosen windows per workgroup */
+  uint64_t signature;  /* shape signature the choices are stored under */
 } jp_tune_result;
 
 jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r, const int32_t* s_z, const int32_t* s_y,

@@ -51,6 +51,8 @@ class jp_options(ctypes.Structure):
         ("k_hot_max", ctypes.c_int32),
         ("flags", ctypes.c_int32),
         ("workspace_limit_bytes", ctypes.c_int64),
+        ("window_group", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -70,7 +72,8 @@ class jp_timings(ctypes.Structure):
 class jp_tune_result(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_int64), ("model_tau", ctypes.c_int64), ("cost_ratio", ctypes.c_double),
                 ("best_ms", ctypes.c_double), ("model_ms", ctypes.c_double), ("candidates", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("signature", ctypes.c_uint64)]
+                ("dense_kernel", ctypes.c_int32), ("k_hot_max", ctypes.c_int32), ("window_group", ctypes.c_int32),
+                ("signature", ctypes.c_uint64)]
 
 
 class jp_instance(ctypes.Structure):
@@ -177,8 +180,10 @@ def _ptr(t) -> int:
 
 
 def make_options(tau_mode: int = JP_TAU_AUTO, dense_threshold: int = 0, dense_kernel: int = JP_DENSE_AUTO,
-                 k_hot_max: int = 0, workspace_limit_bytes: int = 0, flags: int = 0) -> jp_options:
+                 k_hot_max: int = 0, workspace_limit_bytes: int = 0, flags: int = 0,
+                 window_group: int = 0) -> jp_options:
     o = jp_options()
+    o.window_group = window_group
     o.tau_mode = tau_mode
     o.dense_kernel = dense_kernel
     o.dense_threshold = dense_threshold
@@ -211,7 +216,7 @@ def jp_tune(r_x, r_y, s_z, s_y, opt: Optional[jp_options] = None, stream=None) -
     n_s = int(s_z.numel()) if s_z is not None else 0
     _check(lib.jp_tune(_ptr(r_x), _ptr(r_y), n_r, _ptr(s_z), _ptr(s_y), n_s,
                        ctypes.byref(opt) if opt is not None else None, _stream(stream), ctypes.byref(r)))
-    return {name: getattr(r, name) for name, _ in jp_tune_result._fields_ if name != "pad_"}
+    return {name: getattr(r, name) for name, _ in jp_tune_result._fields_}
 
 
 def jp_tune_clear():

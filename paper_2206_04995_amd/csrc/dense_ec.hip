@@ -387,7 +387,7 @@ void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const i
                        off, out, out_n);
   } else {
     const int nwin = int((c.max_zd_range + DW_BITS - 1) / DW_BITS);
-    const int wg = dense_window_group(c.max_hot, nwin);
+    const int wg = c.wgroup > 0 ? std::max(1, std::min(c.wgroup, nwin)) : dense_window_group(c.max_hot, nwin);
     const int ng = (nwin + wg - 1) / wg;
     if (ng > 1) fill_i32(cnt + x_lo, n, 0, s);
     hipLaunchKernelGGL(k_dense_bits<false>, dim3(g, ng > 0 ? ng : 1), dim3(NT), 0, s, c, x_lo, n, nullptr, nullptr, 0,
@@ -401,7 +401,7 @@ void dense_ec_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const i
   if (n_rows <= 0) return;
   const int g = int((n_rows + RB - 1) / RB);
   const int nwin = int((c.max_zd_range + DW_BITS - 1) / DW_BITS);
-  const int wg = dense_window_group(c.max_hot, nwin);
+  const int wg = c.wgroup > 0 ? std::max(1, std::min(c.wgroup, nwin)) : dense_window_group(c.max_hot, nwin);
   const int ng = (nwin + wg - 1) / wg;
   hipLaunchKernelGGL(k_dense_bits<false>, dim3(g, ng > 0 ? ng : 1), dim3(NT), 0, s, c, int64_t(0), n_rows, rows,
                      base_cnt, 1, wg, cnt, nullptr, nullptr, int64_t(0));

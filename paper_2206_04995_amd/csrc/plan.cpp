@@ -321,18 +321,17 @@ void Plan::partition(hipStream_t s) {
   const double c_de = env_double("JP_COST_DE_OVER_SP", 0.05);
   const double c_fix = env_double("JP_COST_FIX_OVER_SP", 0.0);
   h_tau.resize(n);
+  h_rec.assign(n, TuneRec{});
   for (int i = 0; i < n; ++i) {
+    int64_t nx = h_xbase[i + 1] - h_xbase[i], nz = h_zbase[i + 1] - h_zbase[i];
+    int64_t ns = h_sbase[i + 1] - h_sbase[i];
+    tuned_record(shape_signature(nx, nz, ns, h_outj[i]), &h_rec[i]);  // stored by jp_tune, if any
     if (opt.tau_mode == JP_TAU_FIXED) {
       h_tau[i] = opt.dense_threshold;
+    } else if (h_rec[i].valid) {
+      h_tau[i] = tau_from_cost(nx, nz, ns, h_outj[i], h_rec[i].ratio, 0.0);
     } else {
-      int64_t nx = h_xbase[i + 1] - h_xbase[i], nz = h_zbase[i + 1] - h_zbase[i];
-      int64_t ns = h_sbase[i + 1] - h_sbase[i];
-      double c = c_de, cf = c_fix, tuned = 0.0;
-      if (tuned_ratio(shape_signature(nx, nz, ns, h_outj[i]), &tuned)) {  // set by jp_tune
-        c = tuned;
-        cf = 0.0;
-      }
-      h_tau[i] = tau_from_cost(nx, nz, ns, h_outj[i], c, cf);
+      h_tau[i] = tau_from_cost(nx, nz, ns, h_outj[i], c_de, c_fix);
     }
   }
   d_tau = A.alloc<int64_t>(n, s);
@@ -396,9 +395,11 @@ void Plan::partition(hipStream_t s) {
 // whenever the panels fit, JP_DENSE_BITS never uses it.
 void Plan::choose_dense_kernel(Arena& T, hipStream_t s) {
   use_mfma = false;
-  if (n_inst != 1 || opt.dense_kernel == JP_DENSE_BITS || NZd <= 0 || NX <= 0 || dense_keys0 <= 0) return;
+  int kernel = opt.dense_kernel;
+  if (kernel == JP_DENSE_AUTO && !h_rec.empty() && h_rec[0].valid) kernel = h_rec[0].dense_kernel;  // tuned
+  if (n_inst != 1 || kernel == JP_DENSE_BITS || NZd <= 0 || NX <= 0 || dense_keys0 <= 0) return;
   const double min_density = env_double("JP_MFMA_MIN_DENSITY", 1.0 / 32.0);
-  if (opt.dense_kernel != JP_DENSE_MFMA && double(NRp) / (double(NX) * double(dense_keys0)) < min_density) return;
+  if (kernel != JP_DENSE_MFMA && double(NRp) / (double(NX) * double(dense_keys0)) < min_density) return;
   const int64_t NYa = std::max<int64_t>(NY, 1);
   int32_t* kmap = T.alloc<int32_t>(NYa, s);
   K_panel = panel_key_count(sptr, spptr, dR, NY, kmap, T, s);
@@ -471,7 +472,6 @@ void Plan::build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a,
   }
 
   // hot join keys: S row covering at least theta of the space
-  const int kmax = opt.k_hot_max > 0 ? std::min(opt.k_hot_max, 1024) : 256;
   const double hot_frac = env_double("JP_HOT_MIN_FRACTION", 1.0 / 128.0);
   d.h_theta.assign(n, INT64_MAX);
   d.h_K.assign(n, 0);
@@ -493,6 +493,8 @@ void Plan::build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a,
       for (int q = bb; q < 32; ++q) c += h_hist[size_t(i) * 32 + q];
       return c;
     };
+    const int kmax = opt.k_hot_max > 0 ? std::min(opt.k_hot_max, 1024)
+                                        : (h_rec[i].valid && h_rec[i].k_hot_max > 0 ? h_rec[i].k_hot_max : 256);
     while (b < 31 && count_from(b) > kmax) ++b;
     int64_t K = count_from(b);
     d.h_theta[i] = int64_t(1) << b;
@@ -682,6 +684,8 @@ RowCtx Plan::ctx(int space) const {
   c.cptr = d.cptr;
   c.ccol = d.ccol;
   c.dz2z = dz2z;
+  c.wgroup = opt.window_group;
+  if (c.wgroup == 0 && !h_rec.empty() && h_rec[0].valid) c.wgroup = h_rec[0].window_group;  // tuned
   return c;
 }
 
@@ -889,6 +893,8 @@ jp_status check_opt(const jp_options* o) {
   if (o->flags & ~(JP_FLAG_TIMING | JP_FLAG_GRAPH)) return fail(JP_EINVAL, "unknown flag bits");
   if (o->workspace_limit_bytes < 0) return fail(JP_EINVAL, "negative workspace limit");
   if (o->tau_mode == JP_TAU_FIXED && o->dense_threshold < -1) return fail(JP_EINVAL, "dense_threshold < -1");
+  if (o->window_group < 0 || o->window_group > 64) return fail(JP_EINVAL, "window_group must be in [0, 64]");
+  if (o->reserved != 0) return fail(JP_EINVAL, "reserved option field must be 0");
   return JP_OK;
 }
 

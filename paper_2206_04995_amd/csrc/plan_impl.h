@@ -29,6 +29,15 @@ struct DenseSpace {
   int64_t NHb = 0, NCold = 0;
 };
 
+// Choices jp_tune stored for one shape signature (valid = false: none).
+struct TuneRec {
+  bool valid = false;
+  double ratio = 0.0;  // c_de / c_sp of the threshold
+  int32_t dense_kernel = JP_DENSE_AUTO;
+  int32_t k_hot_max = 0;
+  int32_t window_group = 0;
+};
+
 struct Plan {
   Arena A;
   int n_inst = 0;
@@ -40,6 +49,7 @@ struct Plan {
   int64_t NR = 0, NS = 0, NRp = 0, NX = 0, NY = 0, NZ = 0, NZd = 0, NSp = 0;
   std::vector<int32_t> h_rbase, h_sbase, h_rpbase, h_xbase, h_ybase, h_zbase, h_zdbase;
   std::vector<int64_t> h_outj, h_tau, h_tot;
+  std::vector<TuneRec> h_rec;  // per instance
 
   // inputs (concatenated over instances)
   const int32_t *rx = nullptr, *ry = nullptr, *sz = nullptr, *sy = nullptr;
@@ -114,6 +124,6 @@ struct Plan {
 int64_t tau_from_cost(int64_t nx, int64_t nz, int64_t ns, int64_t out_j, double c_de_over_sp, double c_fix_over_sp);
 // shape signature of one instance, and the cost ratio c_de / c_sp stored for it by jp_tune
 uint64_t shape_signature(int64_t nx, int64_t nz, int64_t ns, int64_t out_j);
-bool tuned_ratio(uint64_t sig, double* ratio);
+bool tuned_record(uint64_t sig, TuneRec* rec);
 
 }  // namespace jp

@@ -132,6 +132,7 @@ struct RowCtx {
   const int32_t* rcode;    // [n_r_kept] per R CSR entry: hot rank (>= 0), -2 - y (cold y), -1 (no dense entry)
   const int32_t* wptr;     // segment of (window w, y): ccol[wptr[k], wptr[k+1]), k = cwm_off[i] + w*Y_i + y - y_base[i]
   const int64_t* cwm_off;  // [n_inst] offset of the instance's segment table
+  int wgroup;              // windows per workgroup of the count kernel (0: from dense_window_group)
 };
 
 // hot rank of each hot y within its instance, by decreasing d_R (rows sharing it)

@@ -5,16 +5,19 @@
 // the cost ratio of one DenseEC bit decision to one SparseBMM join row, which
 // depends on the kernels and the shape of the data.  jp_tune measures the whole
 // plan + count pass of a query for a set of thresholds (all dense, all sparse,
-// the model's tau scaled by powers of 4, and quantiles of m_z), checks that
-// every threshold gives the same counts (the partition is intersection-free,
-// Sec. 2.3, so it must), and stores the ratio implied by the fastest threshold
-// under the query's shape signature.  Plans with JP_TAU_AUTO then take tau from
-// the stored ratio of their (instance's) signature.
+// the model's tau scaled by powers of 4, and quantiles of m_z), then at the
+// fastest threshold the DenseEC count kernel, the hot-key cap and the windows
+// per workgroup (a coordinate search), checks that every setting gives the
+// same counts (the partition is intersection-free, Sec. 2.3, so it must), and
+// stores the ratio implied by the fastest threshold with the other choices
+// under the query's shape signature.  Plans take them for every option left
+// automatic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -26,7 +29,7 @@ namespace jp {
 namespace {
 
 std::mutex g_mu;
-std::map<uint64_t, double> g_ratio;  // signature -> c_de / c_sp
+std::map<uint64_t, TuneRec> g_rec;  // signature -> stored choices
 
 int log2_bucket(double v) { return v < 1.0 ? 0 : std::min(63, int(std::floor(std::log2(v))) + 1); }
 
@@ -39,11 +42,11 @@ uint64_t shape_signature(int64_t nx, int64_t nz, int64_t ns, int64_t out_j) {
   return (a << 24) | (b << 16) | (c << 8) | d;
 }
 
-bool tuned_ratio(uint64_t sig, double* ratio) {
+bool tuned_record(uint64_t sig, TuneRec* rec) {
   std::lock_guard<std::mutex> g(g_mu);
-  auto it = g_ratio.find(sig);
-  if (it == g_ratio.end()) return false;
-  *ratio = it->second;
+  auto it = g_rec.find(sig);
+  if (it == g_rec.end()) return false;
+  *rec = it->second;
   return true;
 }
 
@@ -54,18 +57,15 @@ using namespace jp;
 namespace {
 
 struct Trial {
-  int64_t tau;
+  jp_options o;
   double ms;
   int64_t counts[3];
+  bool mfma;
 };
 
-// wall time of plan + count pass + count read-back for one threshold
-Trial run_trial(const jp_instance& in, const jp_options& base, int64_t tau, hipStream_t s, int reps) {
-  Trial t{tau, 1e300, {0, 0, 0}};
-  jp_options o = base;
-  o.tau_mode = JP_TAU_FIXED;
-  o.dense_threshold = tau;
-  o.flags = 0;
+// wall time of plan + count pass + count read-back for one setting
+Trial run_trial(const jp_instance& in, const jp_options& o, hipStream_t s, int reps) {
+  Trial t{o, 1e300, {0, 0, 0}, false};
   for (int r = 0; r < reps; ++r) {
     JP_HIP(hipStreamSynchronize(s));
     const auto t0 = std::chrono::steady_clock::now();
@@ -76,6 +76,7 @@ Trial run_trial(const jp_instance& in, const jp_options& base, int64_t tau, hipS
     const auto t1 = std::chrono::steady_clock::now();
     t.ms = std::min(t.ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
     for (int k = 0; k < 3; ++k) t.counts[k] = p.h_tot[k];
+    t.mfma = p.use_mfma;
     p.A.release(s);
   }
   return t;
@@ -99,6 +100,11 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
     set_last_error("unknown flag bits");
     return JP_EINVAL;
   }
+  if (opt && (opt->window_group < 0 || opt->window_group > 64 || opt->k_hot_max < 0 || opt->k_hot_max > 1024 ||
+              opt->dense_kernel < 0 || opt->dense_kernel > 2 || opt->reserved != 0)) {
+    set_last_error("bad options");
+    return JP_EINVAL;
+  }
   try {
     jp_options base{};
     if (opt) base = *opt;
@@ -113,8 +119,17 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
     std::vector<int32_t> mz(size_t(std::max<int64_t>(nz, 0)));
     if (nz > 0) JP_HIP(hipMemcpyAsync(mz.data(), p0.m_z, size_t(nz) * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     JP_HIP(hipStreamSynchronize(stream));
-    const int64_t tau_model = p0.h_tau.empty() ? 0 : p0.h_tau[0];
     p0.A.release(stream);
+    // trials must not see an earlier choice for this shape; the model's tau uses the default constants
+    const uint64_t sig = shape_signature(nx, nz, ns, out_j);
+    {
+      std::lock_guard<std::mutex> g(g_mu);
+      g_rec.erase(sig);
+    }
+    const char* ce = std::getenv("JP_COST_DE_OVER_SP");
+    const char* cf = std::getenv("JP_COST_FIX_OVER_SP");
+    const int64_t tau_model =
+        tau_from_cost(nx, nz, ns, out_j, ce && *ce ? std::atof(ce) : 0.05, cf && *cf ? std::atof(cf) : 0.0);
 
     std::vector<int64_t> cand = {-1, INT64_MAX};
     if (out_j > 0 && nx > 0 && ns > 0) {
@@ -132,31 +147,72 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
     std::sort(cand.begin(), cand.end());
     cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
 
-    const Trial model = run_trial(in, base, tau_model, stream, 2);
+    auto fixed = [&](int64_t tau) {
+      jp_options o = base;
+      o.tau_mode = JP_TAU_FIXED;
+      o.dense_threshold = tau;
+      o.flags = 0;
+      return o;
+    };
+    const Trial model = run_trial(in, fixed(tau_model), stream, 2);
     Trial best = model;
-    for (int64_t tau : cand) {
-      const Trial t = run_trial(in, base, tau, stream, 2);
+    int tried = 0;
+    auto consider = [&](const jp_options& o) {
+      const Trial t = run_trial(in, o, stream, 2);
+      ++tried;
       if (t.counts[0] != model.counts[0])
-        throw Error(JP_ESTATE, "thresholds gave different counts: " + std::to_string(t.counts[0]) + " vs " +
+        throw Error(JP_ESTATE, "settings gave different counts: " + std::to_string(t.counts[0]) + " vs " +
                                    std::to_string(model.counts[0]));
       if (t.ms < best.ms) best = t;
+    };
+    for (int64_t tau : cand) consider(fixed(tau));
+    // at the chosen threshold: the dense count kernel, then the hot-key cap and
+    // the windows per workgroup of the bit path, one after the other
+    if (best.o.dense_threshold != INT64_MAX) {
+      for (int k : {int(JP_DENSE_BITS), int(JP_DENSE_MFMA)}) {
+        jp_options o = best.o;
+        o.dense_kernel = k;
+        consider(o);
+      }
+      if (!best.mfma) {
+        const jp_options at = best.o;
+        for (int kh : {64, 128, 256, 512, 1024}) {
+          jp_options o = at;
+          o.k_hot_max = kh;
+          consider(o);
+        }
+        const jp_options at2 = best.o;
+        for (int wg : {1, 2, 4, 8}) {
+          jp_options o = at2;
+          o.window_group = wg;
+          consider(o);
+        }
+      }
     }
+    const int64_t btau = best.o.dense_threshold;
     double ratio;
-    if (best.tau == INT64_MAX) ratio = 1e300;
-    else if (best.tau < 0 || out_j <= 0 || nx <= 0 || ns <= 0) ratio = 0.0;
-    else ratio = (double(best.tau) + 0.5) * double(out_j) / (double(nx) * double(ns));
-    const uint64_t sig = shape_signature(nx, nz, ns, out_j);
+    if (btau == INT64_MAX) ratio = 1e300;
+    else if (btau < 0 || out_j <= 0 || nx <= 0 || ns <= 0) ratio = 0.0;
+    else ratio = (double(btau) + 0.5) * double(out_j) / (double(nx) * double(ns));
+    TuneRec rec;
+    rec.valid = true;
+    rec.ratio = ratio;
+    rec.dense_kernel = best.mfma ? JP_DENSE_MFMA : JP_DENSE_BITS;
+    rec.k_hot_max = best.o.k_hot_max;
+    rec.window_group = best.o.window_group;
     {
       std::lock_guard<std::mutex> g(g_mu);
-      g_ratio[sig] = ratio;
+      g_rec[sig] = rec;
     }
-    out->tau = best.tau;
+    out->tau = btau;
     out->cost_ratio = ratio;
     out->best_ms = best.ms;
     out->model_ms = model.ms;
     out->model_tau = tau_model;
-    out->candidates = int32_t(cand.size());
-    out->pad_ = 0;
+    out->candidates = tried;
+    out->dense_kernel = rec.dense_kernel;
+    out->k_hot_max = rec.k_hot_max;
+    out->window_group = rec.window_group;
     out->signature = sig;
     return JP_OK;
   } catch (const Error& e) {
@@ -170,6 +226,6 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
 
 extern "C" jp_status jp_tune_clear(void) {
   std::lock_guard<std::mutex> g(g_mu);
-  g_ratio.clear();
+  g_rec.clear();
   return JP_OK;
 }
