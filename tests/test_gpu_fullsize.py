@@ -1,0 +1,121 @@
+"""Parity at the full workload sizes the benchmark times, through the same
+entry points and launch configuration (one plan, jp_execute, jp_count, then
+chunked jp_materialize):
+
+* skewed query, 1e7 tuples per side: sampled rows (random and the heaviest)
+  equal the oracle's rows; the union equals dense + sparse; the count is the
+  same with the pivot split off, with the bit path forced and with another
+  hot-key cap (the paths compute it differently);
+* graph self-join, 2e7 edges: count and order-independent digest of all pairs,
+  streamed in 64M-pair chunks, equal the oracle's (stored by
+  tests/golden/make_fullsize.py);
+* dense uniform query, 1e7 tuples over a 1e4 domain: the INT8-MFMA count
+  equals the bit path's and |X| * |Z|, and sampled rows equal the oracle's.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from jp_helpers import dev
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "fullsize.json")
+
+
+def _sample_rows(p, inst, xs, offs, n_random, n_heavy, seed):
+    import paper_2206_04995_amd as P
+
+    rng = np.random.default_rng(seed)
+    lens = np.diff(offs)
+    pick = np.unique(np.concatenate([rng.choice(xs.size, n_random, replace=False), np.argsort(lens)[-n_heavy:]]))
+    want = oracle.rows(inst.rx, inst.ry, inst.sz, inst.sy, xs[pick])
+    for k, i in enumerate(pick):
+        assert want[k].size == lens[i], (int(xs[i]), want[k].size, int(lens[i]))
+        if lens[i] == 0:
+            continue
+        mx, mz = p.materialize(P.JP_PART_ALL, int(offs[i]), int(lens[i]))
+        assert np.all(mx.cpu().numpy() == xs[i])
+        assert np.array_equal(mz.cpu().numpy(), want[k]), int(xs[i])
+
+
+def test_skewed_1e7_sampled_rows_and_paths(monkeypatch):
+    import paper_2206_04995_amd as P
+
+    print("[case] skewed 1e7", flush=True)
+    inst = synth.config2()
+    cols = [dev(c) for c in (inst.rx, inst.ry, inst.sz, inst.sy)]
+    with P.Plan(*cols) as p:
+        p.execute()
+        total, dense, sparse = p.count()
+        st = p.stats()
+        assert total == dense + sparse and st["out_j"] == oracle.out_j(inst.rx, inst.ry, inst.sz, inst.sy)
+        xs, offs = p.row_info(P.JP_PART_ALL)
+        assert offs[-1] == total and xs.size == st["n_x"]
+        _sample_rows(p, inst, xs, offs, 24, 6, 11)
+    variants = [({"JP_PIVOT": "0"}, None),
+                ({}, P.make_options(dense_kernel=P.JP_DENSE_BITS, k_hot_max=512)),
+                ({}, P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=12))]
+    for env, opt in variants:
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        with P.Plan(*cols, opt=opt) as q:
+            q.execute()
+            got = q.count()
+        for k in env:
+            monkeypatch.delenv(k)
+        print("[case] skewed variant", env, got, flush=True)
+        assert got[0] == total
+
+
+def test_graph_2e7_count_and_digest():
+    import paper_2206_04995_amd as P
+
+    with open(GOLD) as f:
+        want = json.load(f)["graph_2e6_2e7"]
+    print("[case] graph 2e7", flush=True)
+    g = synth.config3()
+    cols = [dev(c) for c in (g.rx, g.ry, g.sz, g.sy)]
+    with P.Plan(*cols) as p:
+        p.execute()
+        total, dense, sparse = p.count()
+        assert total == want["pairs"] == dense + sparse
+        assert p.stats()["out_j"] == want["out_j"]
+        chunk = 1 << 26
+        digest = 0
+        first = 0
+        prev = None
+        while first < total:
+            n = min(chunk, total - first)
+            mx, mz = p.materialize(P.JP_PART_ALL, first, n)
+            x, z = mx.cpu().numpy(), mz.cpu().numpy()
+            key = (x.astype(np.int64) << 32) | (z.astype(np.int64) & 0xFFFFFFFF)
+            assert np.all(np.diff(key) > 0) and (prev is None or key[0] > prev)  # sorted, distinct, across chunks
+            prev = key[-1]
+            digest = (digest + oracle.digest_pairs(x, z)) % (1 << 64)
+            first += n
+        assert str(digest) == want["digest"]
+
+
+def test_dense_1e7_mfma_equals_bits_and_rows():
+    import paper_2206_04995_amd as P
+
+    print("[case] dense 1e7", flush=True)
+    inst = synth.uniform_paper_default(n_tuples=10_000_000, n_domain=10_000)
+    cols = [dev(c) for c in (inst.rx, inst.ry, inst.sz, inst.sy)]
+    with P.Plan(*cols) as p:
+        p.execute()
+        total = p.count()
+        st = p.stats()
+        assert st["dense_mfma"] == 1
+        assert total[0] == st["n_x"] * st["n_z"]  # every pair: each x reaches every z through ~1000 keys
+        xs, offs = p.row_info(P.JP_PART_ALL)
+        _sample_rows(p, inst, xs, offs, 12, 2, 5)
+    with P.Plan(*cols, opt=P.make_options(dense_kernel=P.JP_DENSE_BITS)) as q:
+        q.execute()
+        assert q.stats()["dense_mfma"] == 0
+        assert q.count() == total
