@@ -48,6 +48,22 @@ __device__ __forceinline__ int wave_sum_dpp(int v) {
          __builtin_amdgcn_readlane(v, 48);
 }
 
+// Inclusive prefix sum over the 64 lanes in DPP, without LDS: three row shifts
+// of the input give sums of 4 inside each 16-lane row, shifts by 4 and 8 (on
+// the upper banks) complete the rows, and the row broadcasts of lanes 15 and 31
+// carry row totals into the rows above.  Lanes a DPP step does not write take
+// 0.  Needs all 64 lanes active.
+__device__ __forceinline__ int wave_scan_add_dpp(int x) {
+  int v = x + __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, x, 0x113, 0xF, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xE, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xC, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
+  return v;
+}
+
 // inclusive prefix sum across the 64 lanes of a wave
 template <class T>
 __device__ __forceinline__ T wave_incl_scan(T v) {

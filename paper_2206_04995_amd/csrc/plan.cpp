@@ -684,6 +684,8 @@ RowCtx Plan::ctx(int space) const {
   c.cptr = d.cptr;
   c.ccol = d.ccol;
   c.dz2z = dz2z;
+  c.seg0 = seg0;
+  c.seglen = seglen;
   c.wgroup = opt.window_group;
   if (c.wgroup == 0 && !h_rec.empty() && h_rec[0].valid) c.wgroup = h_rec[0].window_group;  // tuned
   return c;
@@ -704,6 +706,8 @@ void Plan::execute(hipStream_t s) {
     off_sp = A.alloc<int64_t>(NX + 1, s);
     tot = A.alloc<int64_t>(3 * int64_t(n_inst), s);
     heavy_list = A.alloc<int32_t>(NX + 1, s);
+    seg0 = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
+    seglen = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
     XA.set_replay(true);
   }
   const bool graph = (opt.flags & JP_FLAG_GRAPH) != 0;
@@ -742,7 +746,7 @@ void Plan::run_count_pass(hipStream_t s, bool timing) {
   XA.rewind();
   RowCtx c = ctx();
   if (timing) JP_HIP(hipEventRecord(ev[0], s));
-  sparse_row_work(c, 0, NX, 0, NRp, w, s, XA);
+  sparse_row_work(c, 0, NX, 0, NRp, w, seg0, seglen, s, XA);
   if (NSp > 0) sparse_bmm(c, 0, NX, w, cnt_sp, nullptr, nullptr, heavy_list, s);
   else fill_i32(cnt_sp, NX, 0, s);
   if (timing) JP_HIP(hipEventRecord(ev[1], s));

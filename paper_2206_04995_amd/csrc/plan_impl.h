@@ -81,6 +81,7 @@ struct Plan {
   void pivot_split(Arena& T, hipStream_t s);
   // execute
   int64_t* w = nullptr;
+  int32_t *seg0 = nullptr, *seglen = nullptr;  // per R entry: sparse S row of its key
   int32_t *cnt_sp = nullptr, *cnt_de = nullptr, *cnt_all = nullptr;
   int64_t *off_all = nullptr, *off_de = nullptr, *off_sp = nullptr, *tot = nullptr;
 

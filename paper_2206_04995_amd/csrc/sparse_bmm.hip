@@ -30,13 +30,15 @@ __device__ __forceinline__ void lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// per R CSR entry: length of the sparse S row of its join key
-__global__ void k_entry_len(const int32_t* __restrict__ rcol, const int32_t* __restrict__ spptr, int64_t j_lo,
-                            int64_t j_hi, int32_t* __restrict__ len) {
+// per R CSR entry j: the sparse S row of its join key, as (start, length)
+__global__ void k_entry_seg(const int32_t* __restrict__ rcol, const int32_t* __restrict__ spptr, int64_t j_lo,
+                            int64_t j_hi, int32_t* __restrict__ seg0, int32_t* __restrict__ len) {
   for (int64_t j = j_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < j_hi;
        j += int64_t(gridDim.x) * blockDim.x) {
     const int y = rcol[j];
-    len[j - j_lo] = spptr[y + 1] - spptr[y];
+    const int a = spptr[y];
+    seg0[j] = a;
+    len[j] = spptr[y + 1] - a;
   }
 }
 
@@ -79,7 +81,7 @@ __device__ void wave_bitonic(int32_t* a, int t) {
 __device__ __forceinline__ void wave_flat_scatter(int s0, int len, const int32_t* __restrict__ col, int32_t wlo,
                                                   uint32_t* bm) {
   const int lane = lane_id();
-  const int incl = wave_incl_scan(len);
+  const int incl = wave_scan_add_dpp(len);
   const int excl = incl - len;
   const int total = __shfl(incl, 63, 64);
   for (int t0 = 0; t0 < total; t0 += 64) {
@@ -101,15 +103,14 @@ __device__ __forceinline__ void wave_flat_scatter(int s0, int len, const int32_t
 
 // every thread takes join keys of the row, finds the part of its sparse S row
 // inside the window by binary search, and its wave scatters the entries
-__device__ __forceinline__ void heavy_window(const int32_t* __restrict__ rcol, const int32_t* __restrict__ spptr,
+__device__ __forceinline__ void heavy_window(const int32_t* __restrict__ seg0, const int32_t* __restrict__ seglen,
                                              const int32_t* __restrict__ spcol, int a, int b, int32_t wlo,
                                              int32_t whi, uint32_t* bm) {
   for (int c0 = a; c0 < b; c0 += NT) {
     const int j = c0 + int(threadIdx.x);
     int lo = 0, len = 0;
     if (j < b) {
-      const int y = rcol[j];
-      const int s0 = spptr[y], s1 = spptr[y + 1];
+      const int s0 = seg0[j], s1 = s0 + seglen[j];
       if (s1 > s0) {
         lo = int(lower_bound_dev<int32_t>(spcol, s0, s1, wlo));
         len = int(lower_bound_dev<int32_t>(spcol, lo, s1, whi)) - lo;
@@ -120,8 +121,8 @@ __device__ __forceinline__ void heavy_window(const int32_t* __restrict__ rcol, c
 }
 
 template <bool WRITE>
-__global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__ rptr, const int32_t* __restrict__ rcol,
-                                                     const int32_t* __restrict__ spptr,
+__global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__ rptr, const int32_t* __restrict__ seg0,
+                                                     const int32_t* __restrict__ seglen,
                                                      const int32_t* __restrict__ spcol, int64_t x_lo, int64_t x_hi,
                                                      const int64_t* __restrict__ w, int32_t* __restrict__ cnt,
                                                      const int64_t* __restrict__ off, int32_t* __restrict__ out) {
@@ -151,11 +152,10 @@ __global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__
       int j = c0 + lane;
       int s0 = 0, len = 0;
       if (j < b) {
-        int y = rcol[j];
-        s0 = spptr[y];
-        len = spptr[y + 1] - s0;
+        s0 = seg0[j];
+        len = seglen[j];
       }
-      int incl = wave_incl_scan(len);
+      int incl = wave_scan_add_dpp(len);
       int excl = incl - len;
       int total = __shfl(incl, 63, 64);
       for (int t0 = 0; t0 < total; t0 += 64) {
@@ -206,8 +206,8 @@ __global__ void k_collect_heavy(int64_t x_lo, int64_t x_hi, const int64_t* __res
 
 // count mode: one workgroup per (heavy row, window blockIdx.y)
 __global__ void __launch_bounds__(NT) k_sparse_heavy_count(const int32_t* __restrict__ rptr,
-                                                           const int32_t* __restrict__ rcol,
-                                                           const int32_t* __restrict__ spptr,
+                                                           const int32_t* __restrict__ seg0,
+                                                           const int32_t* __restrict__ seglen,
                                                            const int32_t* __restrict__ spcol, int n_inst,
                                                            const int32_t* __restrict__ x_base,
                                                            const int32_t* __restrict__ z_base,
@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_count(const int32_t* __rest
     const int32_t whi = (zhi - wlo) > HB_BITS ? wlo + HB_BITS : zhi;
     for (int i = threadIdx.x; i < HB_WORDS; i += NT) bm[i] = 0u;
     __syncthreads();
-    heavy_window(rcol, spptr, spcol, rptr[x], rptr[x + 1], wlo, whi, bm);
+    heavy_window(seg0, seglen, spcol, rptr[x], rptr[x + 1], wlo, whi, bm);
     __syncthreads();
     constexpr int PER = HB_WORDS / NT;
     int c = 0;
@@ -248,8 +248,8 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_count(const int32_t* __rest
 
 // write mode: one workgroup per heavy row, windows in z order
 __global__ void __launch_bounds__(NT) k_sparse_heavy_write(const int32_t* __restrict__ rptr,
-                                                           const int32_t* __restrict__ rcol,
-                                                           const int32_t* __restrict__ spptr,
+                                                           const int32_t* __restrict__ seg0,
+                                                           const int32_t* __restrict__ seglen,
                                                            const int32_t* __restrict__ spcol, int n_inst,
                                                            const int32_t* __restrict__ x_base,
                                                            const int32_t* __restrict__ z_base, int64_t x_lo,
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_write(const int32_t* __rest
       const int32_t whi = (zhi - wlo) > HB_BITS ? wlo + HB_BITS : zhi;
       for (int i = threadIdx.x; i < HB_WORDS; i += NT) bm[i] = 0u;
       __syncthreads();
-      heavy_window(rcol, spptr, spcol, rptr[x], rptr[x + 1], wlo, whi, bm);
+      heavy_window(seg0, seglen, spcol, rptr[x], rptr[x + 1], wlo, whi, bm);
       __syncthreads();
       // thread t owns words [t*PER, (t+1)*PER): contiguous, so prefix order is z order
       constexpr int PER = HB_WORDS / NT;
@@ -306,23 +306,21 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_write(const int32_t* __rest
 }  // namespace
 
 void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, int64_t j_hi, int64_t* w,
-                     hipStream_t s, Arena& a) {
+                     int32_t* seg0, int32_t* seglen, hipStream_t s, Arena& a) {
   int64_t n = x_hi - x_lo;
   if (n <= 0) return;
   const int64_t ne = j_hi - j_lo;
-  int32_t* len = a.alloc<int32_t>(std::max<int64_t>(ne, 1), s);
   int64_t* E = a.alloc<int64_t>(ne + 1, s);
   if (ne > 0) {
     int g = int(std::min<int64_t>((ne + NT - 1) / NT, 1 << 16));
-    hipLaunchKernelGGL(k_entry_len, dim3(g), dim3(NT), 0, s, c.rcol, c.spptr, j_lo, j_hi, len);
+    hipLaunchKernelGGL(k_entry_seg, dim3(g), dim3(NT), 0, s, c.rcol, c.spptr, j_lo, j_hi, seg0, seglen);
     JP_LAUNCH_CHECK();
   }
-  scan_excl_i32_to_i64(len, E, ne, s, a);
+  scan_excl_i32_to_i64(seglen + j_lo, E, ne, s, a);
   int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
   hipLaunchKernelGGL(k_row_diff, dim3(g), dim3(NT), 0, s, c.rptr, E, j_lo, x_lo, x_hi, w);
   JP_LAUNCH_CHECK();
   a.give_back(E, s);
-  a.give_back(len, s);
 }
 
 void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int32_t* cnt, const int64_t* off,
@@ -339,18 +337,18 @@ void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
                      w, list, n_list);
   JP_LAUNCH_CHECK();
   if (out) {
-    hipLaunchKernelGGL(k_sparse_light<true>, dim3(gl), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, x_lo, x_hi, w,
+    hipLaunchKernelGGL(k_sparse_light<true>, dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen, c.spcol, x_lo, x_hi, w,
                        cnt, off, out);
     JP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sparse_heavy_write, dim3(gh), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, c.n_inst,
+    hipLaunchKernelGGL(k_sparse_heavy_write, dim3(gh), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen, c.spcol, c.n_inst,
                        c.x_base, c.z_base, x_lo, list, n_list, off, out);
     JP_LAUNCH_CHECK();
   } else {
-    hipLaunchKernelGGL(k_sparse_light<false>, dim3(gl), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol, x_lo, x_hi,
+    hipLaunchKernelGGL(k_sparse_light<false>, dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen, c.spcol, x_lo, x_hi,
                        w, cnt, off, out);
     JP_LAUNCH_CHECK();
     const int wins = int(std::max<int64_t>(1, (c.max_z_range + HB_BITS - 1) / HB_BITS));
-    hipLaunchKernelGGL(k_sparse_heavy_count, dim3(gh, wins), dim3(NT), 0, s, c.rptr, c.rcol, c.spptr, c.spcol,
+    hipLaunchKernelGGL(k_sparse_heavy_count, dim3(gh, wins), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen, c.spcol,
                        c.n_inst, c.x_base, c.z_base, list, n_list, cnt);
     JP_LAUNCH_CHECK();
   }

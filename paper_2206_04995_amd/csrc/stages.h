@@ -133,6 +133,9 @@ struct RowCtx {
   const int32_t* wptr;     // segment of (window w, y): ccol[wptr[k], wptr[k+1]), k = cwm_off[i] + w*Y_i + y - y_base[i]
   const int64_t* cwm_off;  // [n_inst] offset of the instance's segment table
   int wgroup;              // windows per workgroup of the count kernel (0: from dense_window_group)
+  // per R CSR entry j (filled by sparse_row_work): the sparse S row of its key
+  const int32_t* seg0;     // first entry in spcol
+  const int32_t* seglen;   // number of entries
 };
 
 // hot rank of each hot y within its instance, by decreasing d_R (rows sharing it)
@@ -156,7 +159,7 @@ void cold_window_major(const int32_t* cptr, const int32_t* ccol, int64_t n_y, in
 // per-row work of the sparse part: w[x] = sum over y in R[x] of |S_sparse[y]|,
 // for rows [x_lo, x_hi) whose CSR entries are [j_lo, j_hi)
 void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, int64_t j_hi, int64_t* w,
-                     hipStream_t s, Arena& a);
+                     int32_t* seg0, int32_t* seglen, hipStream_t s, Arena& a);
 // SparseBMM count (cnt != null) or write (out != null, offsets relative to off[x_lo]);
 // heavy_list is scratch of x_hi - x_lo + 1 ints
 void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int32_t* cnt,
