@@ -21,6 +21,7 @@ namespace {
 constexpr int NT = 256;
 constexpr int LIGHT_MAX = 1024;      // rows with at most this much work use a wave hash set
 constexpr int HT_SLOTS = 2048;       // slots of one wave's hash set (load <= 1/2)
+constexpr int SMALL_SLOTS = 512;     // the table of rows with w <= 256: more waves fit in LDS
 constexpr int32_t EMPTY = 0x7FFFFFFF;
 constexpr int HB_BITS = 1 << 19;     // heavy-row window: 64 KB of LDS
 constexpr int HB_WORDS = HB_BITS / 32;
@@ -120,13 +121,17 @@ __device__ __forceinline__ void heavy_window(const int32_t* __restrict__ seg0, c
   }
 }
 
-template <bool WRITE>
+// Rows with w in (W_LO, SLOTS / 2] (a table of SLOTS slots stays at most half
+// full).  The launch with W_LO = 0 also writes the zero counts of empty and
+// heavy rows (count mode), so every row's count is set before the heavy
+// kernels add to it.
+template <bool WRITE, int SLOTS, int W_LO>
 __global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__ rptr, const int32_t* __restrict__ seg0,
                                                      const int32_t* __restrict__ seglen,
                                                      const int32_t* __restrict__ spcol, int64_t x_lo, int64_t x_hi,
                                                      const int64_t* __restrict__ w, int32_t* __restrict__ cnt,
                                                      const int64_t* __restrict__ off, int32_t* __restrict__ out) {
-  __shared__ int32_t tab_all[NT / 64][HT_SLOTS];
+  __shared__ int32_t tab_all[NT / 64][SLOTS];
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
   int32_t* tab = tab_all[wid];
@@ -138,9 +143,10 @@ __global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__
     const int64_t wx = w[x - x_lo];
     if (wx > LIGHT_MAX || wx == 0) {
       // heavy rows are counted by the windowed kernel, which adds to cnt[x]
-      if (!WRITE && lane == 0) cnt[x] = 0;
+      if (!WRITE && W_LO == 0 && lane == 0) cnt[x] = 0;
       continue;
     }
+    if (wx <= W_LO || wx > SLOTS / 2) continue;  // the other table size's rows
     int log2t = 6;
     while ((1 << log2t) < 2 * wx) ++log2t;
     const int t = 1 << log2t;
@@ -337,15 +343,21 @@ void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
                      w, list, n_list);
   JP_LAUNCH_CHECK();
   if (out) {
-    hipLaunchKernelGGL(k_sparse_light<true>, dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen, c.spcol, x_lo, x_hi, w,
-                       cnt, off, out);
+    hipLaunchKernelGGL((k_sparse_light<true, SMALL_SLOTS, 0>), dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen,
+                       c.spcol, x_lo, x_hi, w, cnt, off, out);
+    JP_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_sparse_light<true, HT_SLOTS, SMALL_SLOTS / 2>), dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0,
+                       c.seglen, c.spcol, x_lo, x_hi, w, cnt, off, out);
     JP_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sparse_heavy_write, dim3(gh), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen, c.spcol, c.n_inst,
                        c.x_base, c.z_base, x_lo, list, n_list, off, out);
     JP_LAUNCH_CHECK();
   } else {
-    hipLaunchKernelGGL(k_sparse_light<false>, dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen, c.spcol, x_lo, x_hi,
-                       w, cnt, off, out);
+    hipLaunchKernelGGL((k_sparse_light<false, SMALL_SLOTS, 0>), dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen,
+                       c.spcol, x_lo, x_hi, w, cnt, off, out);
+    JP_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_sparse_light<false, HT_SLOTS, SMALL_SLOTS / 2>), dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0,
+                       c.seglen, c.spcol, x_lo, x_hi, w, cnt, off, out);
     JP_LAUNCH_CHECK();
     const int wins = int(std::max<int64_t>(1, (c.max_z_range + HB_BITS - 1) / HB_BITS));
     hipLaunchKernelGGL(k_sparse_heavy_count, dim3(gh, wins), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen, c.spcol,
