@@ -40,20 +40,25 @@ MFMA_I8_PEAK_TOPS = 5000.0
 FETCH_FACTOR = 1048576 / 524308.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
-    "skewed": {"kernels": "k_dense_bits<false>", "fetch_kib": 944179.8, "write_kib": 121090.8,
-               "sources": {"dense_ec.hip": "a08db9227690e3bcbe3de00643ae5ebec19f97bf666260e692d4be3121034e2c",
-                           "stages.h": "554f18b0e75f417b87c57be0648c6956b98e3e6701ea1137cd3728821a5f37a9",
-                           "common.h": "36901928bfe6e97c4a250204c3dc4afd5ca71267867d00fb477e81ea3653e732"}},
-    "graph": {"kernels": "k_sparse_light<false> + k_sparse_heavy_count", "fetch_kib": 2649626.9 + 424962.5,
-              "write_kib": 20910.1 + 596.4,
-              "sources": {"sparse_bmm.hip": "72dff182c318020adef6deb37bfde98e7e41623df2bb2ebabd1250fda03b2ff3",
-                          "stages.h": "554f18b0e75f417b87c57be0648c6956b98e3e6701ea1137cd3728821a5f37a9",
-                          "common.h": "36901928bfe6e97c4a250204c3dc4afd5ca71267867d00fb477e81ea3653e732"}},
+    # two count launches per step: rows without and with the pivot key
+    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 886072.6 + 398541.0, "write_kib": 155407.4 + 73847.1,
+               "sources": {"dense_ec.hip": "4b6ada38f0bd3a5f4bf3869fc5a1e5c815d6d0f9e5b71d7e2d60821afed43dce",
+                           "stages.h": "d3ef8a70362acf75a5759b26df505dda3672d8d864ec93e53337039aa89075af",
+                           "common.h": "fc0ab1073844693a810a6c96bccaf3980fb07c7dcfbabb749f508575f5f09373"}},
+    "graph": {"kernels": "k_sparse_light<false> x 2 + k_sparse_heavy_count",
+              "fetch_kib": 1463260.3 + 295829.8 + 254204.3, "write_kib": 21095.1 + 2435.2 + 596.4,
+              "sources": {"sparse_bmm.hip": "e159496729db7df054ada0ce0ced3e9623b306883c00d2b591c02f212b0074e2",
+                          "stages.h": "d3ef8a70362acf75a5759b26df505dda3672d8d864ec93e53337039aa89075af",
+                          "common.h": "fc0ab1073844693a810a6c96bccaf3980fb07c7dcfbabb749f508575f5f09373"}},
+    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 809094.8, "write_kib": 12343.8,
+              "sources": {"dense_mfma.hip": "c4103f00b68fb47500e9e25f66d0e6c7b0317e25200728f600fa7ef5ed3c3ed4",
+                          "stages.h": "d3ef8a70362acf75a5759b26df505dda3672d8d864ec93e53337039aa89075af",
+                          "common.h": "fc0ab1073844693a810a6c96bccaf3980fb07c7dcfbabb749f508575f5f09373"}},
 }
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per launch from the committed counter runs, or None if stale."""
+    """HBM bytes per step of the dominant kernel(s) from the committed counter runs, or None if stale."""
     import hashlib
 
     m = MEASURED_TRAFFIC.get(workload)
