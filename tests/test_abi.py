@@ -45,7 +45,9 @@ def test_invalid_arguments_rejected_before_device_work():
     # more than 2^31 - 1 tuples
     assert lib.jp_plan_create(one, one, 2 ** 31, one, one, 1, None, None, ctypes.byref(h)) == B.JP_EINVAL
     # bad options
-    for kw in ({"tau_mode": 7}, {"dense_kernel": 9}, {"k_hot_max": 5000}, {"workspace_limit_bytes": -1}):
+    for kw in ({"tau_mode": 7}, {"dense_kernel": 9}, {"k_hot_max": 5000}, {"workspace_limit_bytes": -1},
+               {"window_group": 65}, {"window_group": -1}, {"reserved": 1},
+               {"tau_mode": 1, "dense_threshold": -2}):
         o = P.make_options()
         for k, v in kw.items():
             setattr(o, k, v)
@@ -67,6 +69,14 @@ def test_invalid_arguments_rejected_before_device_work():
     assert lib.jp_batch_create(arr, 1, None, None, ctypes.byref(h)) == B.JP_EINVAL
     assert lib.jp_batch_execute(None, None) == B.JP_EINVAL
     lib.jp_batch_destroy(None)
+    # the tuner
+    r = B.jp_tune_result()
+    assert lib.jp_tune(one, one, 1, one, one, 1, None, None, None) == B.JP_EINVAL
+    assert lib.jp_tune(one, one, -1, one, one, 1, None, None, ctypes.byref(r)) == B.JP_EINVAL
+    assert lib.jp_tune(None, None, 3, one, one, 1, None, None, ctypes.byref(r)) == B.JP_EINVAL
+    o = P.make_options(window_group=99)
+    assert lib.jp_tune(one, one, 1, one, one, 1, ctypes.byref(o), None, ctypes.byref(r)) == B.JP_EINVAL
+    assert lib.jp_tune_clear() == B.JP_OK
 
 
 def test_binding_refuses_cpu_tensors():
