@@ -36,6 +36,21 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
+// Inclusive prefix maximum over the 64 lanes in DPP, with the shifts and row
+// broadcasts of wave_scan_add_dpp (a maximum may see a lane twice).  Lanes a
+// DPP step does not write take INT32_MIN.  Needs all 64 lanes active.
+__device__ __forceinline__ int wave_scan_max_dpp(int x) {
+  const int lo = INT32_MIN;
+  int v = max(x, __builtin_amdgcn_update_dpp(lo, x, 0x111, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, x, 0x112, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, x, 0x113, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x114, 0xF, 0xE, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x118, 0xF, 0xC, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x142, 0xA, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(lo, v, 0x143, 0xC, 0xF, false));
+  return v;
+}
+
 // Sum over the 64 lanes without LDS traffic: DPP permutations reduce each
 // 16-lane row (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
 // row_mirror), then the four row sums are read as scalars.  Wave-uniform result.
@@ -88,6 +103,27 @@ __device__ __forceinline__ int find_inst(const T* __restrict__ base, int n_inst,
   return lo;
 }
 
+// find_inst by the whole wave (all 64 lanes, uniform control flow): a 64-ary
+// search with one load per lane and level (two levels up to 4096 segments)
+// instead of a chain of dependent loads.  Wave-uniform result.
+template <class T>
+__device__ __forceinline__ int wave_find_inst(const T* __restrict__ base, int n_inst, T g) {
+  if (n_inst <= 1) return 0;
+  const int lane = lane_id();
+  int lo = 0, span = n_inst;  // the answer is in [lo, lo + span)
+  while (span > 1) {
+    const int step = (span + 63) >> 6;
+    const int idx = lo + lane * step;
+    const uint64_t m = __ballot(idx < lo + span && base[idx] <= g);
+    if (m == 0) break;  // g below base[0]
+    const int k = 63 - __builtin_clzll((unsigned long long)m);
+    const int nlo = lo + k * step;
+    span = min(step, lo + span - nlo);
+    lo = nlo;
+  }
+  return lo;
+}
+
 // Segment index of increasing positions: the first call searches, later calls
 // step forward (or search again after a long gap).  Loops over contiguous
 // chunks (CHUNK_LOOP) keep the steps short, so most lookups cost one load.
@@ -97,6 +133,10 @@ struct SegCursor {
   int n;
   int cur = -1;
   __device__ SegCursor(const T* b, int n_) : base(b), n(n_) {}
+  // Wave-cooperative start (all 64 lanes, uniform control flow) at the
+  // segment of g0; g0 should not exceed the wave's later queries (a wrong
+  // seed costs a search later, not a wrong answer).
+  __device__ void seed(T g0) { cur = wave_find_inst<T>(base, n, g0); }
   __device__ int operator()(T g) {
     if (n == 1) return 0;
     if (cur < 0 || g < base[cur]) return cur = find_inst<T>(base, n, g);
@@ -117,6 +157,9 @@ struct SegCursor {
        i < i##_end; i += blockDim.x)
 
 constexpr int JP_CHUNK = 4096;  // elements per block of CHUNK_LOOP kernels (256 threads x 16)
+
+// first element of this block's CHUNK_LOOP chunk
+__device__ __forceinline__ int64_t chunk_first() { return int64_t(blockIdx.x) * JP_CHUNK; }
 
 inline int chunk_grid(int64_t n, int ch = JP_CHUNK) { return int(n <= 0 ? 1 : (n + ch - 1) / ch); }
 

@@ -25,6 +25,7 @@ __global__ void k_make_keys(const int32_t* __restrict__ v, int64_t n, const int3
                             int n_inst, const int64_t* __restrict__ koff, const int32_t* __restrict__ mn,
                             uint32_t* __restrict__ keys, uint32_t* __restrict__ payload) {
   SegCursor<int32_t> cur(ebase, n_inst);
+  cur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(i, n, JP_CHUNK) {
     const int inst = cur(int32_t(i));
     keys[i] = uint32_t(koff[inst] + (int64_t(v[i]) - int64_t(mn[inst])));
@@ -37,6 +38,7 @@ __global__ void k_make_keys_perm(const int32_t* __restrict__ v, const uint32_t* 
                                  const int32_t* __restrict__ mn, const int32_t* __restrict__ E,
                                  uint32_t* __restrict__ keys, uint32_t* __restrict__ payload) {
   SegCursor<int32_t> cur(ebase, n_inst);
+  cur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(p, n, JP_CHUNK) {
     uint32_t g = perm[p];
     const int inst = cur(int32_t(p));  // sorted by instance first: same instance as g
@@ -53,6 +55,7 @@ __global__ void k_assign_ids(const uint32_t* __restrict__ keys, int64_t n, const
                              const int64_t* __restrict__ koff, const int32_t* __restrict__ mn, int n_inst,
                              int32_t* __restrict__ first, int32_t* __restrict__ vals) {
   SegCursor<int64_t> kcur(koff, n_inst);
+  if (chunk_first() < n) kcur.seed(int64_t(keys[chunk_first()]));
   CHUNK_LOOP(p, n, JP_CHUNK) {
     int id = E[p];
     bool head = E[p + 1] != id;
@@ -76,6 +79,7 @@ __global__ void k_semijoin(const int32_t* __restrict__ ry, int64_t n, const int3
                            const int32_t* __restrict__ vals_y, const int32_t* __restrict__ y_base,
                            int32_t* __restrict__ keep, int32_t* __restrict__ yid) {
   SegCursor<int32_t> cur(ebase, n_inst);
+  cur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(g, n, JP_CHUNK) {
     const int inst = cur(int32_t(g));
     int32_t v = ry[g];
@@ -101,6 +105,7 @@ __global__ void k_semijoin_direct(const int32_t* __restrict__ ry, int64_t n, con
                                   const int32_t* __restrict__ table, int32_t* __restrict__ keep,
                                   int32_t* __restrict__ yid) {
   SegCursor<int32_t> cur(ebase, n_inst);
+  cur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(g, n, JP_CHUNK) {
     const int inst = cur(int32_t(g));
     const int64_t rel = int64_t(ry[g]) - int64_t(mn[inst]);

@@ -26,6 +26,7 @@ inline int grid(int64_t n, int cap = 1 << 20) {
 __global__ void k_dense_flags(const int32_t* __restrict__ m_z, int64_t n_z, const int32_t* __restrict__ z_base,
                               int n_inst, const int64_t* __restrict__ tau, int32_t* __restrict__ flag) {
   SegCursor<int32_t> zcur(z_base, n_inst);
+  zcur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(z, n_z, JP_CHUNK) {
     const int inst = zcur(int32_t(z));
     flag[z] = int64_t(m_z[z]) > tau[inst] ? 1 : 0;
@@ -107,6 +108,7 @@ __global__ void k_hot_flags(const int32_t* __restrict__ cnt_a, const int32_t* __
                             const int32_t* __restrict__ dR, int64_t n_y, const int32_t* __restrict__ y_base,
                             int n_inst, const int64_t* __restrict__ theta, int32_t* __restrict__ hot) {
   SegCursor<int32_t> ycur(y_base, n_inst);
+  ycur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(y, n_y, JP_CHUNK) {
     const int dd = space_count(cnt_a, cnt_b, y);
     const int inst = ycur(int32_t(y));
@@ -122,6 +124,7 @@ __global__ void k_build_hot_bits(const int32_t* __restrict__ Ey, const int32_t* 
                                  const int64_t* __restrict__ hb_off, const int32_t* __restrict__ row_words,
                                  int n_inst, uint32_t* __restrict__ hb) {
   SegCursor<int32_t> ycur(y_base, n_inst);
+  if (chunk_first() < n) ycur.seed(Ey[chunk_first() + 1] - 1);
   CHUNK_LOOP(p, n, JP_CHUNK) {
     const int32_t y = Ey[p + 1] - 1;
     if (!hot[y]) continue;
@@ -161,6 +164,7 @@ __global__ void k_zmap_dense(const int32_t* __restrict__ zflag, const int32_t* _
                              const int32_t* __restrict__ z_base, const int32_t* __restrict__ zd_base, int n_inst,
                              int32_t* __restrict__ zmap) {
   SegCursor<int32_t> zcur(z_base, n_inst);
+  zcur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(z, n_z, JP_CHUNK) {
     const int inst = zcur(int32_t(z));
     zmap[z] = zflag[z] ? Edz[z] - zd_base[inst] : -1;
@@ -174,6 +178,7 @@ __global__ void k_zmap_resid(const int32_t* __restrict__ zflag, const int32_t* _
                              const int32_t* __restrict__ z_base, const int32_t* __restrict__ zc_base, int n_inst,
                              int32_t* __restrict__ zmap) {
   SegCursor<int32_t> zcur(z_base, n_inst);
+  zcur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(z, n_z, JP_CHUNK) {
     int32_t v = -1;
     if (zflag[z]) {
@@ -213,6 +218,7 @@ __global__ void k_mark_pivot(const int32_t* __restrict__ Ey, const int32_t* __re
                              const int32_t* __restrict__ zflag, const int32_t* __restrict__ Edz,
                              int32_t* __restrict__ inP) {
   SegCursor<int32_t> ycur(y_base, n_inst);
+  if (chunk_first() < n) ycur.seed(Ey[chunk_first() + 1] - 1);
   CHUNK_LOOP(p, n, JP_CHUNK) {
     const int32_t y = Ey[p + 1] - 1;
     const int inst = ycur(y);
@@ -225,6 +231,7 @@ __global__ void k_mark_pivot(const int32_t* __restrict__ Ey, const int32_t* __re
 __global__ void k_resid_flags(const int32_t* __restrict__ inP, int64_t n, const int32_t* __restrict__ zd_base,
                               int n_inst, const int32_t* __restrict__ piv, int32_t* __restrict__ out) {
   SegCursor<int32_t> dcur(zd_base, n_inst);
+  dcur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(d, n, JP_CHUNK) {
     const int inst = dcur(int32_t(d));
     out[d] = (piv[inst] >= 0 && !inP[d]) ? 1 : 0;
@@ -305,6 +312,8 @@ __global__ void k_cold_win_entries(const int32_t* __restrict__ cptr, const int32
                                    const int64_t* __restrict__ cw_off, int32_t* __restrict__ cw) {
   // row of entry p: largest y with cptr[y] <= p
   SegCursor<int32_t> rowcur(cptr, int(n_y)), ycur(y_base, n_inst);
+  rowcur.seed(int32_t(chunk_first()));
+  ycur.seed(int32_t(rowcur.cur));
   CHUNK_LOOP(p, n_cold, JP_CHUNK) {
     const int32_t y = rowcur(int32_t(p));
     const int inst = ycur(y);
@@ -358,6 +367,8 @@ __global__ void k_cold_win_scatter(const int32_t* __restrict__ cptr, const int32
                                    const int32_t* __restrict__ wptr, const int64_t* __restrict__ cwm_off,
                                    int32_t* __restrict__ ccol_w) {
   SegCursor<int32_t> rowcur(cptr, int(n_y)), ycur(y_base, n_inst);
+  rowcur.seed(int32_t(chunk_first()));
+  ycur.seed(int32_t(rowcur.cur));
   CHUNK_LOOP(p, n_cold, JP_CHUNK) {
     const int32_t y = rowcur(int32_t(p));
     const int inst = ycur(y);

@@ -77,6 +77,7 @@ int key_layout(const std::vector<int32_t>& mn, const std::vector<int32_t>& mx, s
 __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int32_t* __restrict__ base, int n_inst,
                               int64_t n, int32_t* __restrict__ dst) {
   SegCursor<int32_t> cur(base, n_inst);
+  cur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(g, n, JP_CHUNK) {
     const int inst = cur(int32_t(g));
     dst[g] = src[inst][g - base[inst]];
@@ -705,7 +706,7 @@ void Plan::execute(hipStream_t s) {
     off_de = A.alloc<int64_t>(NX + 1, s);
     off_sp = A.alloc<int64_t>(NX + 1, s);
     tot = A.alloc<int64_t>(3 * int64_t(n_inst), s);
-    heavy_list = A.alloc<int32_t>(NX + 1, s);
+    heavy_list = A.alloc<int32_t>(sparse_list_ints(NX), s);
     seg0 = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
     seglen = A.alloc<int32_t>(std::max<int64_t>(NRp, 1), s);
     XA.set_replay(true);
@@ -841,7 +842,7 @@ int64_t Plan::materialize(int inst, int part, int64_t first, int64_t maxp, int32
   int32_t* lde = T.alloc<int32_t>(std::max<int64_t>(nde, 1), s);
   int32_t* lsp = T.alloc<int32_t>(std::max<int64_t>(nsp, 1), s);
   if (nde > 0) dense_ec(c, xl, xh, nullptr, off_de, lde, nde, s);
-  if (nsp > 0) sparse_bmm(c, xl, xh, w + xl, nullptr, off_sp, lsp, T.alloc<int32_t>(xh - xl + 1, s), s);
+  if (nsp > 0) sparse_bmm(c, xl, xh, w + xl, nullptr, off_sp, lsp, T.alloc<int32_t>(sparse_list_ints(xh - xl), s), s);
   if (part == JP_PART_ALL)
     merge_write_n(xl, xh, off_de, off_sp, off_all, lde, lsp, nde, nsp, vals_x, vals_z, g0, g1, ox, oz, s);
   else if (part == JP_PART_DENSE)

@@ -248,8 +248,8 @@ __global__ void __launch_bounds__(MM_NT) k_seg_minmax(const int32_t* __restrict_
   __shared__ int32_t s_mn[MM_NT / 64], s_mx[MM_NT / 64];
   const int64_t c0 = int64_t(blockIdx.x) * MM_CHUNK;
   const int64_t c1 = c0 + MM_CHUNK < n ? c0 + MM_CHUNK : n;
-  const int seg0 = n_seg == 1 ? 0 : find_inst<int32_t>(base, n_seg, int32_t(c0));
-  const int seg1 = n_seg == 1 ? 0 : find_inst<int32_t>(base, n_seg, int32_t(c1 - 1));
+  const int seg0 = wave_find_inst<int32_t>(base, n_seg, int32_t(c0));
+  const int seg1 = wave_find_inst<int32_t>(base, n_seg, int32_t(c1 - 1));
   int32_t cmn = INT_MAX, cmx = INT_MIN;
   if (seg0 == seg1) {
     for (int64_t i = c0 + threadIdx.x; i < c1; i += MM_NT) {

@@ -23,6 +23,7 @@ constexpr int LIGHT_MAX = 1024;      // rows with at most this much work use a w
 constexpr int HT_SLOTS = 2048;       // slots of one wave's hash set (load <= 1/2)
 constexpr int SMALL_SLOTS = 512;     // the table of rows with w <= 256: more waves fit in LDS
 constexpr int32_t EMPTY = 0x7FFFFFFF;
+constexpr int MED_MAX = 8192;       // count mode: rows up to this much work use a workgroup hash set
 constexpr int HB_BITS = 1 << 19;     // heavy-row window: 64 KB of LDS
 constexpr int HB_WORDS = HB_BITS / 32;
 
@@ -121,93 +122,284 @@ __device__ __forceinline__ void heavy_window(const int32_t* __restrict__ seg0, c
   }
 }
 
-// Rows with w in (W_LO, SLOTS / 2] (a table of SLOTS slots stays at most half
-// full).  The launch with W_LO = 0 also writes the zero counts of empty and
-// heavy rows (count mode), so every row's count is set before the heavy
-// kernels add to it.
-template <bool WRITE, int SLOTS, int W_LO>
-__global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__ rptr, const int32_t* __restrict__ seg0,
-                                                     const int32_t* __restrict__ seglen,
-                                                     const int32_t* __restrict__ spcol, int64_t x_lo, int64_t x_hi,
+// Sorts the rows of [x_lo, x_hi) by their work w into four lists:
+//   class 1: w in [1, SMALL_SLOTS / 2]     hdr[0], upwards from A
+//   class 2: w up to LIGHT_MAX             hdr[1], downwards from A + n
+//   class 3: w up to med_max               hdr[2], upwards from B
+//   class 4: heavier rows                  hdr[3], downwards from B + n
+// (write mode passes med_max = LIGHT_MAX: no class 3).  A block takes
+// CLS_ROWS consecutive rows (CLS_PER per thread), ranks them with one block
+// scan and reserves its places with one atomic per class, so few atomics meet
+// on the four counters.  In count mode the rows no wave or workgroup hash set
+// writes (empty and heavy ones) get count 0 here, before the heavy kernel adds
+// to it.
+constexpr int CLS_PER = 16;
+constexpr int CLS_ROWS = NT * CLS_PER;
+
+__global__ void __launch_bounds__(NT) k_classify_rows(int64_t x_lo, int64_t x_hi, const int64_t* __restrict__ w,
+                                                      int64_t med_max, int32_t* __restrict__ cnt,
+                                                      int32_t* __restrict__ hdr, int32_t* __restrict__ A,
+                                                      int32_t* __restrict__ B) {
+  __shared__ int64_t wtot[NT / 64];
+  __shared__ int32_t bases[4];
+  const int lane = lane_id();
+  const int wid = threadIdx.x >> 6;
+  const int64_t n = x_hi - x_lo;
+  const int64_t r0 = int64_t(blockIdx.x) * CLS_ROWS + int64_t(threadIdx.x) * CLS_PER;
+  // classes packed 3 bits per row; per-class counts packed 16 bits each (at most CLS_ROWS)
+  uint64_t cls = 0;
+  int64_t packed = 0;
+#pragma unroll
+  for (int k = 0; k < CLS_PER; ++k) {
+    const int64_t i = r0 + k;
+    int c = 0;
+    if (i < n) {
+      const int64_t wx = w[i];
+      c = wx == 0 ? 0 : wx <= SMALL_SLOTS / 2 ? 1 : wx <= LIGHT_MAX ? 2 : wx <= med_max ? 3 : 4;
+      if (cnt && (c == 0 || c == 4)) cnt[x_lo + i] = 0;
+    }
+    cls |= uint64_t(c) << (3 * k);
+    if (c) packed += int64_t(1) << (16 * (c - 1));
+  }
+  const int64_t incl = wave_incl_scan(packed);
+  if (lane == 63) wtot[wid] = incl;
+  __syncthreads();
+  int64_t pre = 0, all = 0;
+  for (int q = 0; q < NT / 64; ++q) {
+    const int64_t v = wtot[q];
+    if (q < wid) pre += v;
+    all += v;
+  }
+  if (threadIdx.x < 4) {
+    const int m = int((all >> (16 * threadIdx.x)) & 0xFFFF);
+    bases[threadIdx.x] = m ? atomicAdd(&hdr[threadIdx.x], m) : 0;
+  }
+  __syncthreads();
+  const int64_t excl = pre + incl - packed;
+  int64_t pos[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) pos[c] = bases[c] + ((excl >> (16 * c)) & 0xFFFF);
+#pragma unroll
+  for (int k = 0; k < CLS_PER; ++k) {
+    const int c = int((cls >> (3 * k)) & 7u);
+    const int32_t x = int32_t(x_lo + r0 + k);
+    if (c == 1) A[pos[0]++] = x;
+    else if (c == 2) A[n - 1 - pos[1]++] = x;
+    else if (c == 3) B[pos[2]++] = x;
+    else if (c == 4) B[n - 1 - pos[3]++] = x;
+  }
+}
+
+// The wave's lanes hold up to 64 S segments [s0, s0 + len) (one per join
+// key); every z id in them is inserted into the LDS hash set tab of 2^log2t
+// slots.  The ids are taken 64 at a time in the order of the segments; lane
+// i takes id w0 + i.  Its segment is found without a search: the lanes whose
+// (non-empty) segment starts inside the window [w0, w0 + 64) write their lane
+// number into the wave's 64-entry LDS array head at that offset, a prefix
+// maximum over head carries each owner forward, and a ballot gives the
+// segment that covers w0 itself.  head holds -1 on entry and on return.  G
+// windows are gathered before inserting.  Returns the number of ids this lane
+// inserted first.
+template <int G>
+__device__ __forceinline__ int hash_insert_segments(int s0, int len, const int32_t* __restrict__ spcol, int32_t* tab,
+                                                    int log2t, int32_t* head) {
+  const int lane = lane_id();
+  const uint32_t tmask = (1u << log2t) - 1u;
+  const int incl = wave_scan_add_dpp(len);
+  const int excl = incl - len;
+  const int total = __builtin_amdgcn_readlane(incl, 63);
+  const bool nz = len > 0;
+  int fresh = 0;
+  for (int t0 = 0; t0 < total; t0 += 64 * G) {
+    int32_t zz[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      zz[g] = EMPTY;
+      const int w0 = t0 + g * 64;
+      if (w0 < total) {
+        // w0 < total lies in a non-empty segment starting at or before it
+        const uint64_t cov = ballot(nz && excl <= w0);
+        const int start = 63 - __builtin_clzll(cov);
+        if (nz && excl > w0 && excl < w0 + 64) head[excl - w0] = lane;
+        lds_fence();
+        int o = head[lane];
+        head[lane] = -1;
+        o = max(wave_scan_max_dpp(o), start);
+        const int os0 = __shfl(s0, o, 64);
+        const int oex = __shfl(excl, o, 64);
+        const int tt = w0 + lane;
+        if (tt < total) zz[g] = spcol[os0 + (tt - oex)];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int32_t z = zz[g];
+      if (z == EMPTY) continue;
+      uint32_t h = hash_slot(z, log2t);
+      while (true) {
+        const int32_t old = atomicCAS(&tab[h], EMPTY, z);
+        if (old == EMPTY) {
+          ++fresh;
+          break;
+        }
+        if (old == z) break;
+        h = (h + 1) & tmask;
+      }
+    }
+  }
+  return fresh;
+}
+
+// One wavefront per listed row with an LDS hash set of SLOTS slots (at most
+// half full: the list holds rows with w <= SLOTS / 2).  A row costs a chain of
+// dependent loads (its list entry, row bounds and work, the S segments of its
+// join keys, the z ids), so each wave runs a software pipeline over its rows
+// r, r + nw, r + 2 nw, ...: while it gathers row r's z ids, the segments of
+// row r + nw, the bounds of row r + 2 nw and the list entry of row r + 3 nw are
+// in flight.
+template <bool WRITE, int SLOTS, int G>
+__global__ void __launch_bounds__(NT) k_sparse_light(const int32_t* __restrict__ lst_at, const int32_t* __restrict__ n_ptr,
+                                                     int from_end, const int32_t* __restrict__ rptr,
+                                                     const int32_t* __restrict__ seg0, const int32_t* __restrict__ seglen,
+                                                     const int32_t* __restrict__ spcol, int64_t x_lo,
                                                      const int64_t* __restrict__ w, int32_t* __restrict__ cnt,
                                                      const int64_t* __restrict__ off, int32_t* __restrict__ out) {
   __shared__ int32_t tab_all[NT / 64][SLOTS];
+  __shared__ int32_t head_all[NT / 64][64];
   const int lane = lane_id();
-  const int wid = threadIdx.x >> 6;
-  int32_t* tab = tab_all[wid];
-  const int64_t gw = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
+  int32_t* tab = tab_all[threadIdx.x >> 6];
+  int32_t* head = head_all[threadIdx.x >> 6];
+  head[lane] = -1;
+  const int64_t n = *n_ptr;
+  const int32_t* lst = from_end ? lst_at - n : lst_at;
   const int64_t nw = (int64_t(gridDim.x) * NT) >> 6;
+  int64_t r = (int64_t(blockIdx.x) * NT + threadIdx.x) >> 6;
   const int64_t base_off = WRITE ? off[x_lo] : 0;
 
-  for (int64_t x = x_lo + gw; x < x_hi; x += nw) {
-    const int64_t wx = w[x - x_lo];
-    if (wx > LIGHT_MAX || wx == 0) {
-      // heavy rows are counted by the windowed kernel, which adds to cnt[x]
-      if (!WRITE && W_LO == 0 && lane == 0) cnt[x] = 0;
-      continue;
+  // pipeline registers: c = row r, 1 = row r + nw, 2 = row r + 2 nw
+  int xc = r < n ? lst[r] : -1;
+  int x1 = r + nw < n ? lst[r + nw] : -1;
+  int x2 = r + 2 * nw < n ? lst[r + 2 * nw] : -1;
+  int ac = 0, bc = 0, wc = 0;
+  if (xc >= 0) {
+    ac = rptr[xc];
+    bc = rptr[xc + 1];
+    wc = int(w[xc - x_lo]);
+  }
+  int a1 = 0, b1 = 0, w1 = 0;
+  if (x1 >= 0) {
+    a1 = rptr[x1];
+    b1 = rptr[x1 + 1];
+    w1 = int(w[x1 - x_lo]);
+  }
+  int s0c = 0, lc = 0;
+  if (ac + lane < bc) {
+    s0c = seg0[ac + lane];
+    lc = seglen[ac + lane];
+  }
+  while (xc >= 0) {
+    // loads for the rows ahead
+    const int x3 = r + 3 * nw < n ? lst[r + 3 * nw] : -1;
+    int s01 = 0, l1 = 0;
+    if (a1 + lane < b1) {
+      s01 = seg0[a1 + lane];
+      l1 = seglen[a1 + lane];
     }
-    if (wx <= W_LO || wx > SLOTS / 2) continue;  // the other table size's rows
+    int a2 = 0, b2 = 0, w2 = 0;
+    if (x2 >= 0) {
+      a2 = rptr[x2];
+      b2 = rptr[x2 + 1];
+      w2 = int(w[x2 - x_lo]);
+    }
+
+    // row r
     int log2t = 6;
-    while ((1 << log2t) < 2 * wx) ++log2t;
+    while ((1 << log2t) < 2 * wc) ++log2t;
     const int t = 1 << log2t;
     for (int i = lane; i < t; i += 64) tab[i] = EMPTY;
     lds_fence();
-    int fresh = 0;
+    int fresh = hash_insert_segments<G>(s0c, lc, spcol, tab, log2t, head);
+    for (int c0 = ac + 64; c0 < bc; c0 += 64) {
+      const int j = c0 + lane;
+      int s0 = 0, len = 0;
+      if (j < bc) {
+        s0 = seg0[j];
+        len = seglen[j];
+      }
+      fresh += hash_insert_segments<G>(s0, len, spcol, tab, log2t, head);
+    }
+    const int count = wave_sum(fresh);
+    if (!WRITE) {
+      if (lane == 0) cnt[xc] = count;
+    } else {
+      lds_fence();
+      wave_bitonic(tab, t);
+      int32_t* dst = out + (off[xc] - base_off);
+      for (int i = lane; i < count; i += 64) dst[i] = tab[i];
+    }
+    lds_fence();
+
+    r += nw;
+    xc = x1;
+    ac = a1;
+    bc = b1;
+    wc = w1;
+    s0c = s01;
+    lc = l1;
+    x1 = x2;
+    a1 = a2;
+    b1 = b2;
+    w1 = w2;
+    x2 = x3;
+  }
+}
+
+// count mode, rows with LIGHT_MAX < w <= MED_MAX: one workgroup per row and
+// one LDS hash set of the row's z ids (at most half full) shared by its waves;
+// each wave takes 64 join keys of the row at a time
+__global__ void __launch_bounds__(NT) k_sparse_medium_count(const int32_t* __restrict__ lst, const int32_t* __restrict__ n_ptr,
+                                                            const int32_t* __restrict__ rptr,
+                                                            const int32_t* __restrict__ seg0,
+                                                            const int32_t* __restrict__ seglen,
+                                                            const int32_t* __restrict__ spcol, int64_t x_lo,
+                                                            const int64_t* __restrict__ w, int32_t* __restrict__ cnt) {
+  __shared__ int32_t tab[2 * MED_MAX];
+  __shared__ int32_t head_all[NT / 64][64];
+  __shared__ int red[NT / 64];
+  const int lane = lane_id();
+  const int wid = threadIdx.x >> 6;
+  int32_t* head = head_all[wid];
+  head[lane] = -1;
+  const int n = *n_ptr;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int x = lst[i];
+    const int wx = int(w[x - x_lo]);
     const int a = rptr[x], b = rptr[x + 1];
-    for (int c0 = a; c0 < b; c0 += 64) {
-      int j = c0 + lane;
+    int log2t = 6;
+    while ((1 << log2t) < 2 * wx) ++log2t;
+    const int t = 1 << log2t;
+    for (int k = threadIdx.x; k < t; k += NT) tab[k] = EMPTY;
+    __syncthreads();
+    int fresh = 0;
+    for (int c0 = a + wid * 64; c0 < b; c0 += NT) {
+      const int j = c0 + lane;
       int s0 = 0, len = 0;
       if (j < b) {
         s0 = seg0[j];
         len = seglen[j];
       }
-      int incl = wave_scan_add_dpp(len);
-      int excl = incl - len;
-      int total = __shfl(incl, 63, 64);
-      for (int t0 = 0; t0 < total; t0 += 64) {
-        int tt = t0 + lane;
-        int o = 0;
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1) {
-          int e = __shfl(excl, o + step, 64);
-          if (e <= tt) o += step;
-        }
-        int os0 = __shfl(s0, o, 64);
-        int oex = __shfl(excl, o, 64);
-        if (tt < total) {
-          int32_t z = spcol[os0 + (tt - oex)];
-          uint32_t h = hash_slot(z, log2t);
-          while (true) {
-            int32_t old = atomicCAS(&tab[h], EMPTY, z);
-            if (old == EMPTY) {
-              ++fresh;
-              break;
-            }
-            if (old == z) break;
-            h = (h + 1) & uint32_t(t - 1);
-          }
-        }
-      }
+      fresh += hash_insert_segments<4>(s0, len, spcol, tab, log2t, head);
     }
-    int count = wave_sum(fresh);
-    if (!WRITE) {
-      if (lane == 0) cnt[x] = count;
-    } else {
-      lds_fence();
-      wave_bitonic(tab, t);
-      int32_t* dst = out + (off[x] - base_off);
-      for (int i = lane; i < count; i += 64) dst[i] = tab[i];
+    const int c = wave_sum(fresh);
+    if (lane == 0) red[wid] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int q = 0; q < NT / 64; ++q) tot += red[q];
+      cnt[x] = tot;
     }
-    lds_fence();
+    __syncthreads();
   }
-}
-
-// list of the heavy rows (order irrelevant: every row owns its output range)
-__global__ void k_collect_heavy(int64_t x_lo, int64_t x_hi, const int64_t* __restrict__ w, int32_t* __restrict__ list,
-                                int32_t* __restrict__ n_list) {
-  for (int64_t x = x_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < x_hi;
-       x += int64_t(gridDim.x) * blockDim.x)
-    if (w[x - x_lo] > LIGHT_MAX) list[atomicAdd(n_list, 1)] = int32_t(x);
 }
 
 // count mode: one workgroup per (heavy row, window blockIdx.y)
@@ -217,7 +409,7 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_count(const int32_t* __rest
                                                            const int32_t* __restrict__ spcol, int n_inst,
                                                            const int32_t* __restrict__ x_base,
                                                            const int32_t* __restrict__ z_base,
-                                                           const int32_t* __restrict__ list,
+                                                           const int32_t* __restrict__ lst_end,
                                                            const int32_t* __restrict__ n_list,
                                                            int32_t* __restrict__ cnt) {
   __shared__ uint32_t bm[HB_WORDS];
@@ -225,6 +417,7 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_count(const int32_t* __rest
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
   const int nh = *n_list;
+  const int32_t* list = lst_end - nh;
   for (int i = blockIdx.x; i < nh; i += gridDim.x) {
     const int64_t x = list[i];
     const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(x_base, n_inst, int32_t(x));
@@ -259,7 +452,7 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_write(const int32_t* __rest
                                                            const int32_t* __restrict__ spcol, int n_inst,
                                                            const int32_t* __restrict__ x_base,
                                                            const int32_t* __restrict__ z_base, int64_t x_lo,
-                                                           const int32_t* __restrict__ list,
+                                                           const int32_t* __restrict__ lst_end,
                                                            const int32_t* __restrict__ n_list,
                                                            const int64_t* __restrict__ off, int32_t* __restrict__ out) {
   __shared__ uint32_t bm[HB_WORDS];
@@ -268,6 +461,7 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_write(const int32_t* __rest
   const int wid = threadIdx.x >> 6;
   const int64_t base_off = off[x_lo];
   const int nh = *n_list;
+  const int32_t* list = lst_end - nh;
 
   for (int i = blockIdx.x; i < nh; i += gridDim.x) {
     const int64_t x = list[i];
@@ -329,39 +523,50 @@ void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, 
   a.give_back(E, s);
 }
 
+int64_t sparse_list_ints(int64_t n_rows) { return 2 * n_rows + 4; }
+
 void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int32_t* cnt, const int64_t* off,
-                int32_t* out, int32_t* heavy_list, hipStream_t s) {
+                int32_t* out, int32_t* lists, hipStream_t s) {
   int64_t n = x_hi - x_lo;
   if (n <= 0) return;
-  int gl = int(std::min<int64_t>((n + 3) / 4, 1 << 15));
-  int gh = int(std::min<int64_t>(n, 1024));
-  // heavy_list holds n + 1 ints: the count, then the rows
-  int32_t* n_list = heavy_list;
-  int32_t* list = heavy_list + 1;
-  fill_i32(n_list, 1, 0, s);
-  hipLaunchKernelGGL(k_collect_heavy, dim3(int(std::min<int64_t>((n + NT - 1) / NT, 4096))), dim3(NT), 0, s, x_lo, x_hi,
-                     w, list, n_list);
+  // lists: 4 header ints (the list lengths), then regions A (light rows) and
+  // B (medium and heavy rows) of n ints, each holding two lists from both ends
+  int32_t* hdr = lists;
+  int32_t* A = lists + 4;
+  int32_t* B = A + n;
+  fill_i32(hdr, 4, 0, s);
+  const int64_t med_max = out ? LIGHT_MAX : MED_MAX;
+  hipLaunchKernelGGL(k_classify_rows, dim3(int((n + CLS_ROWS - 1) / CLS_ROWS)), dim3(NT), 0, s, x_lo, x_hi, w, med_max,
+                     cnt, hdr, A, B);
   JP_LAUNCH_CHECK();
+  // light rows: four times as many waves as stay resident (8 blocks of 4 waves
+  // per CU with 512-slot tables, 5 with 2048), each pipelining over its rows
+  const int gs = int(std::min<int64_t>((n + 3) / 4, 8192));
+  const int gb = int(std::min<int64_t>((n + 3) / 4, 5120));
+  const int gh = int(std::min<int64_t>(n, 1024));
   if (out) {
-    hipLaunchKernelGGL((k_sparse_light<true, SMALL_SLOTS, 0>), dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen,
-                       c.spcol, x_lo, x_hi, w, cnt, off, out);
+    hipLaunchKernelGGL((k_sparse_light<true, SMALL_SLOTS, 4>), dim3(gs), dim3(NT), 0, s, A, hdr + 0, 0, c.rptr, c.seg0,
+                       c.seglen, c.spcol, x_lo, w, cnt, off, out);
     JP_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_sparse_light<true, HT_SLOTS, SMALL_SLOTS / 2>), dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0,
-                       c.seglen, c.spcol, x_lo, x_hi, w, cnt, off, out);
+    hipLaunchKernelGGL((k_sparse_light<true, HT_SLOTS, 4>), dim3(gb), dim3(NT), 0, s, A + n, hdr + 1, 1, c.rptr, c.seg0,
+                       c.seglen, c.spcol, x_lo, w, cnt, off, out);
     JP_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sparse_heavy_write, dim3(gh), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen, c.spcol, c.n_inst,
-                       c.x_base, c.z_base, x_lo, list, n_list, off, out);
+                       c.x_base, c.z_base, x_lo, B + n, hdr + 3, off, out);
     JP_LAUNCH_CHECK();
   } else {
-    hipLaunchKernelGGL((k_sparse_light<false, SMALL_SLOTS, 0>), dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen,
-                       c.spcol, x_lo, x_hi, w, cnt, off, out);
+    hipLaunchKernelGGL((k_sparse_light<false, SMALL_SLOTS, 4>), dim3(gs), dim3(NT), 0, s, A, hdr + 0, 0, c.rptr, c.seg0,
+                       c.seglen, c.spcol, x_lo, w, cnt, off, out);
     JP_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_sparse_light<false, HT_SLOTS, SMALL_SLOTS / 2>), dim3(gl), dim3(NT), 0, s, c.rptr, c.seg0,
-                       c.seglen, c.spcol, x_lo, x_hi, w, cnt, off, out);
+    hipLaunchKernelGGL((k_sparse_light<false, HT_SLOTS, 4>), dim3(gb), dim3(NT), 0, s, A + n, hdr + 1, 1, c.rptr,
+                       c.seg0, c.seglen, c.spcol, x_lo, w, cnt, off, out);
+    JP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sparse_medium_count, dim3(gh), dim3(NT), 0, s, B, hdr + 2, c.rptr, c.seg0, c.seglen, c.spcol,
+                       x_lo, w, cnt);
     JP_LAUNCH_CHECK();
     const int wins = int(std::max<int64_t>(1, (c.max_z_range + HB_BITS - 1) / HB_BITS));
     hipLaunchKernelGGL(k_sparse_heavy_count, dim3(gh, wins), dim3(NT), 0, s, c.rptr, c.seg0, c.seglen, c.spcol,
-                       c.n_inst, c.x_base, c.z_base, list, n_list, cnt);
+                       c.n_inst, c.x_base, c.z_base, B + n, hdr + 3, cnt);
     JP_LAUNCH_CHECK();
   }
 }

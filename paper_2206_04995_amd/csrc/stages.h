@@ -161,9 +161,10 @@ void cold_window_major(const int32_t* cptr, const int32_t* ccol, int64_t n_y, in
 void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, int64_t j_hi, int64_t* w,
                      int32_t* seg0, int32_t* seglen, hipStream_t s, Arena& a);
 // SparseBMM count (cnt != null) or write (out != null, offsets relative to off[x_lo]);
-// heavy_list is scratch of x_hi - x_lo + 1 ints
+// lists is scratch of sparse_list_ints(x_hi - x_lo) ints (the rows sorted by work)
+int64_t sparse_list_ints(int64_t n_rows);
 void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, int32_t* cnt,
-                const int64_t* off, int32_t* out, int32_t* heavy_list, hipStream_t s);
+                const int64_t* off, int32_t* out, int32_t* lists, hipStream_t s);
 // DenseEC count or write, bit-packed hot rows
 // (write mode: out holds out_n values; writes past it are dropped)
 void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const int64_t* off, int32_t* out,
