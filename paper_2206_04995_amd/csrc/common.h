@@ -132,18 +132,43 @@ struct SegCursor {
   const T* base;
   int n;
   int cur = -1;
+  T lo = 0, hi = 0;  // base[cur], base[cur + 1]: a query inside costs no load
   __device__ SegCursor(const T* b, int n_) : base(b), n(n_) {}
+  __device__ void set(int c) {
+    cur = c;
+    lo = base[c];
+    hi = base[c + 1];
+  }
   // Wave-cooperative start (all 64 lanes, uniform control flow) at the
   // segment of g0; g0 should not exceed the wave's later queries (a wrong
   // seed costs a search later, not a wrong answer).
-  __device__ void seed(T g0) { cur = wave_find_inst<T>(base, n, g0); }
-  __device__ int operator()(T g) {
-    if (n == 1) return 0;
-    if (cur < 0 || g < base[cur]) return cur = find_inst<T>(base, n, g);
-    for (int steps = 0; g >= base[cur + 1]; ++steps) {
-      if (steps == 8) return cur = find_inst<T>(base, n, g);
-      ++cur;
+  __device__ void seed(T g0) {
+    if (n <= 1) {
+      if (n == 1) set(0);
+      else cur = 0;
+      return;
     }
+    set(wave_find_inst<T>(base, n, g0));
+  }
+  __device__ int operator()(T g) {
+    if (n == 1) {
+      if (cur < 0) set(0);
+      return 0;
+    }
+    if (cur >= 0 && g >= lo && g < hi) return cur;
+    if (cur < 0 || g < lo) {
+      set(find_inst<T>(base, n, g));
+      return cur;
+    }
+    int c = cur;
+    for (int steps = 0; g >= base[c + 1]; ++steps) {
+      if (steps == 8) {
+        set(find_inst<T>(base, n, g));
+        return cur;
+      }
+      ++c;
+    }
+    set(c);
     return cur;
   }
 };

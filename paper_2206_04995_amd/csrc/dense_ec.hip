@@ -25,6 +25,7 @@
 #include "common.h"
 #include "prim.h"
 #include "stages.h"
+#include "../../include/jp.h"
 
 namespace jp {
 namespace {
@@ -99,16 +100,20 @@ __device__ __forceinline__ void cold_scatter(int s0, int len, const int32_t* __r
   }
 }
 
-// Rows are slots [0, n_rows): slot i is row rows[i] (a list, count mode) or
-// x_lo + i.  In count mode the row's count starts at base_cnt[instance] (the
+// Rows are slots [0, n_rows): slot i is row rows[i] (a list, count mode), the
+// i-th row of the instances listed by seg_base / seg_x0 (first x of each,
+// running row count), or x_lo + i.  In count mode the row's count starts at base_cnt[instance] (the
 // pivot row's size when the rows are evaluated outside the pivot's z) and is
 // stored, or added when the grid has several window groups or `accumulate`.
 template <bool WRITE>
 __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, int64_t n_rows,
                                                    const int32_t* __restrict__ rows,
+                                                   const int32_t* __restrict__ seg_base,
+                                                   const int32_t* __restrict__ seg_x0, int seg_m,
                                                    const int32_t* __restrict__ base_cnt, int accumulate, int wgroup,
-                                                   int32_t* __restrict__ cnt, const int64_t* __restrict__ off,
-                                                   int32_t* __restrict__ out, int64_t out_n) {
+                                                   int skip_narrow, int32_t* __restrict__ cnt,
+                                                   const int64_t* __restrict__ off, int32_t* __restrict__ out,
+                                                   int64_t out_n) {
   __shared__ uint4 stage[T_STAGE][QW];
   __shared__ uint4 rowbuf_all[WAVES][QW];
   __shared__ int s_maxwin[WAVES];
@@ -122,11 +127,25 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
   const int nrows = r0 >= n_rows ? 0 : int((n_rows - r0) < RPW ? (n_rows - r0) : RPW);
   const int64_t base_off = WRITE ? off[x_lo] : 0;
 
+  // slot -> row (slots ascend with rows inside a block)
+  SegCursor<int32_t> scur(seg_base, seg_m);
+  if (seg_base) scur.seed(int32_t(rb0));
+  auto row_of = [&](int64_t slot) -> int64_t {
+    if (rows) return rows[slot];
+    if (seg_base) {
+      const int sg = scur(int32_t(slot));
+      return int64_t(seg_x0[sg]) + (slot - scur.lo);
+    }
+    return x_lo + slot;
+  };
   // instance of the block's first row: its hottest keys are staged in LDS
-  const int64_t xb0 = rows ? int64_t(rows[rb0]) : x_lo + rb0;
-  const int inst0 = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, int32_t(xb0));
+  const int64_t xb0 = row_of(rb0);
+  SegCursor<int32_t> icur(c.x_base, c.n_inst);
+  icur.seed(int32_t(xb0));
+  const int inst0 = icur.cur;
   const int zd0 = c.zd_base[inst0 + 1] - c.zd_base[inst0];
-  const int nwin0 = (zd0 + DW_BITS - 1) / DW_BITS;
+  // rows of instances with at most NARROW_MAX dense z are left to k_dense_narrow
+  const int nwin0 = (skip_narrow && zd0 <= NARROW_MAX) ? 0 : (zd0 + DW_BITS - 1) / DW_BITS;
   const int k0 = c.Ehot[c.y_base[inst0 + 1]] - c.Ehot[c.y_base[inst0]];
   const int t_eff = k0 < T_STAGE ? k0 : T_STAGE;
   const uint32_t* hb0 = c.hb + c.hb_off[inst0];
@@ -137,11 +156,11 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
   int64_t my_x = 0;
   int64_t my_acc = 0;  // count (count mode) or write position (write mode)
   if (lane < nrows) {
-    const int64_t x = rows ? int64_t(rows[r0 + lane]) : x_lo + r0 + lane;
+    const int64_t x = row_of(r0 + lane);
     my_x = x;
-    my_inst = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, int32_t(x));
+    my_inst = icur(int32_t(x));
     const int zd = c.zd_base[my_inst + 1] - c.zd_base[my_inst];
-    my_nwin = (zd + DW_BITS - 1) / DW_BITS;
+    my_nwin = (skip_narrow && zd <= NARROW_MAX) ? 0 : (zd + DW_BITS - 1) / DW_BITS;
     my_a = c.rptr[x];
     my_b = c.rptr[x + 1];
     if (WRITE) my_acc = off[x] - base_off;
@@ -270,6 +289,107 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
   }
 }
 
+// Count mode for rows of instances with few dense z (0 < Z_d <= 32 * LANES):
+// the whole dense range is one short bit row, so a group of LANES lanes owns
+// a row, one 32-z word per lane, and a wave counts 64 / LANES rows at once
+// (the window kernel would spend a 16384-z window, 512 words, on each).  The
+// groups walk their rows' join keys LANES at a time: hot keys are ORed one
+// per group per step (each group loads its own key's words), cold keys are
+// scattered into the group's LDS words.  Slot i is row rows[i] (a list: rows
+// of other instances are skipped), or the i-th row of the class's narrow
+// instances (c.nar_x0 / c.nar_base of class CLS).
+template <int LANES>
+__global__ void __launch_bounds__(256) k_dense_narrow(RowCtx c, int64_t n_slots, const int32_t* __restrict__ rows,
+                                                   int accumulate, int32_t* __restrict__ cnt) {
+  constexpr int CLS = LANES == 16 ? 0 : 1;
+  constexpr int GROUPS = 64 / LANES;
+  constexpr int ZMAX = 32 * LANES;
+  constexpr int ZMIN = LANES == 16 ? 1 : NARROW_SMALL + 1;
+  __shared__ uint32_t buf_all[4][64];
+  const int lane = lane_id();
+  const int wid = threadIdx.x >> 6;
+  const int grp = lane / LANES, gl = lane % LANES;
+  uint32_t* buf = &buf_all[wid][grp * LANES];
+  buf[gl] = 0u;
+  lds_fence();
+
+  const int64_t slot0 = (int64_t(blockIdx.x) * 4 + wid) * GROUPS;
+  const int64_t slot = slot0 + grp;
+  const bool valid = slot < n_slots;
+  int64_t x = 0;
+  int32_t x_first = 0;  // the wave's first row (rows ascend with the slots): seeds the instance cursor
+  if (rows) {
+    x = valid ? int64_t(rows[slot]) : 0;
+    x_first = slot0 < n_slots ? rows[slot0] : 0;
+  } else {
+    SegCursor<int32_t> scur(c.nar_base[CLS], c.nar_m[CLS]);
+    scur.seed(int32_t(slot0 < n_slots ? slot0 : 0));
+    if (valid) {
+      const int sg = scur(int32_t(slot));
+      x = int64_t(c.nar_x0[CLS][sg]) + (slot - scur.lo);
+    }
+    x_first = __shfl(int32_t(x), 0, 64);
+  }
+  SegCursor<int32_t> icur(c.x_base, c.n_inst);
+  icur.seed(x_first);
+  const int inst = valid ? icur(int32_t(x)) : 0;
+  const int zd = c.zd_base[inst + 1] - c.zd_base[inst];
+  const bool active = valid && zd >= ZMIN && zd <= ZMAX;
+  if (!__ballot(active)) return;
+  const int nwords = (zd + 31) >> 5;
+  int a = 0, b = 0;
+  if (active) {
+    a = c.rptr[x];
+    b = c.rptr[x + 1];
+  }
+  const uint32_t* hrow = c.hb + c.hb_off[inst];
+  const int64_t rw = c.row_words[inst];
+  const int yb = c.y_base[inst];
+  const int32_t* wp = c.wptr + c.cwm_off[inst];  // window 0 of the instance
+
+  uint32_t acc = 0u;
+  const int len = b - a;
+  const int maxlen = wave_max(len);
+  for (int c0 = 0; c0 < maxlen; c0 += LANES) {
+    const int j = a + c0 + gl;
+    const int code = (c0 + gl < len) ? c.rcode[j] : -1;
+    // hot keys: one per group per step
+    const uint64_t hm = __ballot(code >= 0);
+    uint64_t gm = LANES == 64 ? hm : (hm >> (grp * LANES)) & (~uint64_t(0) >> (64 - LANES));
+    while (__ballot(gm != 0)) {
+      const int l = gm ? __ffsll((unsigned long long)gm) - 1 : 0;
+      const int k = __shfl(code, grp * LANES + l, 64);
+      if (gm && gl < nwords) acc |= hrow[int64_t(k) * rw + gl];
+      gm &= gm - 1;
+    }
+    // cold keys: the group scatters each key's window-0 entries
+    const uint64_t cm = __ballot(code <= -2);
+    uint64_t gc = LANES == 64 ? cm : (cm >> (grp * LANES)) & (~uint64_t(0) >> (64 - LANES));
+    while (__ballot(gc != 0)) {
+      const int l = gc ? __ffsll((unsigned long long)gc) - 1 : 0;
+      const int cd = __shfl(code, grp * LANES + l, 64);
+      if (gc) {
+        const int yl = (-2 - cd) - yb;
+        const int s0 = wp[yl], s1 = wp[yl + 1];
+        for (int t = s0 + gl; t < s1; t += LANES) {
+          const int dl = c.ccol[t];
+          atomicOr(&buf[dl >> 5], 1u << (dl & 31));
+        }
+      }
+      gc &= gc - 1;
+    }
+  }
+  lds_fence();
+  if (gl < nwords) acc |= buf[gl];
+  int pc = active ? __popc(acc) : 0;
+#pragma unroll
+  for (int o = LANES / 2; o > 0; o >>= 1) pc += __shfl_xor(pc, o, 64);
+  if (active && gl == 0) {
+    if (accumulate) atomicAdd(&cnt[x], pc);
+    else cnt[x] = pc;
+  }
+}
+
 // Algorithmic work of the count kernels (for roofline accounting):
 // out[0] = sum_x hot(x) * words(x), out[1] = sum_x words(x),
 // out[2] = sum_x cold dense entries of x, out[3] = sum_x w[x]
@@ -377,23 +497,55 @@ void work_stats(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
   JP_LAUNCH_CHECK();
 }
 
+// count of the rows of narrow instances (RowCtx::narrow), after the window
+// kernel: all of them (rows == nullptr), or those in a list of n_rows rows
+static void dense_narrow(const RowCtx& c, int64_t n_rows, const int32_t* rows, int accumulate, int32_t* cnt,
+                         hipStream_t s) {
+  if (c.narrow & 1) {
+    const int64_t n = rows ? n_rows : c.nar_rows[0];
+    hipLaunchKernelGGL(k_dense_narrow<16>, dim3(int((n + 15) / 16)), dim3(256), 0, s, c, n, rows, accumulate, cnt);
+    JP_LAUNCH_CHECK();
+  }
+  if (c.narrow & 2) {
+    const int64_t n = rows ? n_rows : c.nar_rows[1];
+    hipLaunchKernelGGL(k_dense_narrow<64>, dim3(int((n + 3) / 4)), dim3(256), 0, s, c, n, rows, accumulate, cnt);
+    JP_LAUNCH_CHECK();
+  }
+}
+
 void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const int64_t* off, int32_t* out,
               int64_t out_n, hipStream_t s) {
   int64_t n = x_hi - x_lo;
   if (n <= 0) return;
   int g = int((n + RB - 1) / RB);
   if (out) {  // write mode emits each row's windows in order: one group
-    hipLaunchKernelGGL(k_dense_bits<true>, dim3(g), dim3(NT), 0, s, c, x_lo, n, nullptr, nullptr, 0, INT32_MAX, cnt,
-                       off, out, out_n);
+    hipLaunchKernelGGL(k_dense_bits<true>, dim3(g), dim3(NT), 0, s, c, x_lo, n, nullptr, nullptr, nullptr, 0, nullptr,
+                       0, INT32_MAX, 0, cnt, off, out, out_n);
+    JP_LAUNCH_CHECK();
   } else {
     const int nwin = int((c.max_zd_range + DW_BITS - 1) / DW_BITS);
     const int wg = c.wgroup > 0 ? std::max(1, std::min(c.wgroup, nwin)) : dense_window_group(c.max_hot, nwin);
     const int ng = (nwin + wg - 1) / wg;
-    if (ng > 1) fill_i32(cnt + x_lo, n, 0, s);
-    hipLaunchKernelGGL(k_dense_bits<false>, dim3(g, ng > 0 ? ng : 1), dim3(NT), 0, s, c, x_lo, n, nullptr, nullptr, 0,
-                       wg, cnt, off, out, int64_t(0));
+    if (c.by_width) {
+      // rows of instances without dense z keep 0; the window kernel counts the
+      // rows of wide instances, the narrow kernels the others
+      if (x_lo != 0 || x_hi != c.n_x) throw Error(JP_ESTATE, "rows listed by width are counted over the whole range");
+      fill_i32(cnt, n, 0, s);
+      const int64_t nw = c.nar_rows[2];
+      if (nw > 0) {
+        hipLaunchKernelGGL(k_dense_bits<false>, dim3(int((nw + RB - 1) / RB), ng > 0 ? ng : 1), dim3(NT), 0, s, c,
+                           int64_t(0), nw, nullptr, c.nar_base[2], c.nar_x0[2], c.nar_m[2], nullptr, 0, wg, 0, cnt,
+                           off, out, int64_t(0));
+        JP_LAUNCH_CHECK();
+      }
+      dense_narrow(c, 0, nullptr, 0, cnt, s);
+    } else {
+      if (ng > 1) fill_i32(cnt + x_lo, n, 0, s);
+      hipLaunchKernelGGL(k_dense_bits<false>, dim3(g, ng > 0 ? ng : 1), dim3(NT), 0, s, c, x_lo, n, nullptr, nullptr,
+                         nullptr, 0, nullptr, 0, wg, 0, cnt, off, out, int64_t(0));
+      JP_LAUNCH_CHECK();
+    }
   }
-  JP_LAUNCH_CHECK();
 }
 
 void dense_ec_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const int32_t* base_cnt, int32_t* cnt,
@@ -403,9 +555,12 @@ void dense_ec_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const i
   const int nwin = int((c.max_zd_range + DW_BITS - 1) / DW_BITS);
   const int wg = c.wgroup > 0 ? std::max(1, std::min(c.wgroup, nwin)) : dense_window_group(c.max_hot, nwin);
   const int ng = (nwin + wg - 1) / wg;
+  // with a base count (rows outside a pivot) every row stays in the window kernel
+  const int skip = (c.narrow && !base_cnt) ? 1 : 0;
   hipLaunchKernelGGL(k_dense_bits<false>, dim3(g, ng > 0 ? ng : 1), dim3(NT), 0, s, c, int64_t(0), n_rows, rows,
-                     base_cnt, 1, wg, cnt, nullptr, nullptr, int64_t(0));
+                     nullptr, nullptr, 0, base_cnt, 1, wg, skip, cnt, nullptr, nullptr, int64_t(0));
   JP_LAUNCH_CHECK();
+  if (skip) dense_narrow(c, n_rows, rows, 1, cnt, s);
 }
 
 }  // namespace jp

@@ -23,26 +23,26 @@ inline int grid(int64_t n, int cap = 1 << 20) {
 
 __global__ void k_make_keys(const int32_t* __restrict__ v, int64_t n, const int32_t* __restrict__ ebase,
                             int n_inst, const int64_t* __restrict__ koff, const int32_t* __restrict__ mn,
-                            uint32_t* __restrict__ keys, uint32_t* __restrict__ payload) {
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ payload,
+                            const int32_t* __restrict__ pay_src) {
   SegCursor<int32_t> cur(ebase, n_inst);
   cur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(i, n, JP_CHUNK) {
     const int inst = cur(int32_t(i));
     keys[i] = uint32_t(koff[inst] + (int64_t(v[i]) - int64_t(mn[inst])));
-    if (payload) payload[i] = uint32_t(i);
+    if (payload) payload[i] = pay_src ? uint32_t(pay_src[i]) : uint32_t(i);
   }
 }
 
-__global__ void k_make_keys_perm(const int32_t* __restrict__ v, const uint32_t* __restrict__ perm, int64_t n,
-                                 const int32_t* __restrict__ ebase, int n_inst, const int64_t* __restrict__ koff,
-                                 const int32_t* __restrict__ mn, const int32_t* __restrict__ E,
-                                 uint32_t* __restrict__ keys, uint32_t* __restrict__ payload) {
+__global__ void k_make_keys_carried(const uint32_t* __restrict__ v, int64_t n, const int32_t* __restrict__ ebase,
+                                    int n_inst, const int64_t* __restrict__ koff, const int32_t* __restrict__ mn,
+                                    const int32_t* __restrict__ E, uint32_t* __restrict__ keys,
+                                    uint32_t* __restrict__ payload) {
   SegCursor<int32_t> cur(ebase, n_inst);
   cur.seed(int32_t(chunk_first()));
   CHUNK_LOOP(p, n, JP_CHUNK) {
-    uint32_t g = perm[p];
-    const int inst = cur(int32_t(p));  // sorted by instance first: same instance as g
-    keys[p] = uint32_t(koff[inst] + (int64_t(v[g]) - int64_t(mn[inst])));
+    const int inst = cur(int32_t(p));  // sorted by instance first: the instance of position p
+    keys[p] = uint32_t(koff[inst] + (int64_t(int32_t(v[p])) - int64_t(mn[inst])));
     payload[p] = uint32_t(E[p + 1] - 1);
   }
 }
@@ -206,17 +206,17 @@ __global__ void k_out_j(const int32_t* __restrict__ dR, const int32_t* __restric
 }  // namespace
 
 void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff, const int32_t* mn,
-               uint32_t* keys, uint32_t* payload, hipStream_t s) {
+               uint32_t* keys, uint32_t* payload, const int32_t* pay_src, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_make_keys, dim3(chunk_grid(n)), dim3(NT), 0, s, v, n, ebase, n_inst, koff, mn, keys, payload);
+  hipLaunchKernelGGL(k_make_keys, dim3(chunk_grid(n)), dim3(NT), 0, s, v, n, ebase, n_inst, koff, mn, keys, payload,
+                     pay_src);
   JP_LAUNCH_CHECK();
 }
 
-void make_keys_perm(const int32_t* v, const uint32_t* perm, int64_t n, const int32_t* ebase, int n_inst,
-                    const int64_t* koff, const int32_t* mn, const int32_t* E, uint32_t* keys, uint32_t* payload,
-                    hipStream_t s) {
+void make_keys_carried(const uint32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff,
+                       const int32_t* mn, const int32_t* E, uint32_t* keys, uint32_t* payload, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_make_keys_perm, dim3(chunk_grid(n)), dim3(NT), 0, s, v, perm, n, ebase, n_inst, koff, mn, E, keys,
+  hipLaunchKernelGGL(k_make_keys_carried, dim3(chunk_grid(n)), dim3(NT), 0, s, v, n, ebase, n_inst, koff, mn, E, keys,
                      payload);
   JP_LAUNCH_CHECK();
 }

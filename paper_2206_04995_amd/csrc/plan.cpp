@@ -78,9 +78,15 @@ __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int3
                               int64_t n, int32_t* __restrict__ dst) {
   SegCursor<int32_t> cur(base, n_inst);
   cur.seed(int32_t(chunk_first()));
+  const int32_t* col = nullptr;
+  int last = -1;
   CHUNK_LOOP(g, n, JP_CHUNK) {
     const int inst = cur(int32_t(g));
-    dst[g] = src[inst][g - base[inst]];
+    if (inst != last) {
+      last = inst;
+      col = src[inst];
+    }
+    dst[g] = col[g - cur.lo];
   }
 }
 
@@ -203,7 +209,7 @@ void Plan::map(hipStream_t s) {
   int32_t* flags = T.alloc<int32_t>(std::max<int64_t>(std::max(NS, NR), 1), s);
 
   // S sorted by (instance, z): z ids, m_z
-  make_keys(sz, NS, d_sbase, n, dkz, zmin, k1, v1, s);
+  make_keys(sz, NS, d_sbase, n, dkz, zmin, k1, v1, sy, s);  // S.y rides along
   bool alt = radix_sort_pairs(k1, v1, k2, v2, NS, zbits, s, T);
   uint32_t *zk = alt ? k2 : k1, *zp = alt ? v2 : v1;
   head_flags(zk, NS, flags, s);
@@ -217,7 +223,7 @@ void Plan::map(hipStream_t s) {
 
   // S sorted by (instance, y), z ascending inside each y: CSR of S by y
   uint32_t *yk = alt ? k1 : k2, *yp = alt ? v1 : v2;  // the free pair
-  make_keys_perm(sy, zp, NS, d_sbase, n, dky, ymin, Ez, yk, yp, s);
+  make_keys_carried(zp, NS, d_sbase, n, dky, ymin, Ez, yk, yp, s);
   uint32_t *ok = zk, *op = zp;  // reuse the z-sorted pair as scratch
   bool alt2 = radix_sort_pairs(yk, yp, ok, op, NS, ybits, s, T);
   uint32_t *syk = alt2 ? ok : yk, *syp = alt2 ? op : yp;
@@ -276,7 +282,7 @@ void Plan::map(hipStream_t s) {
   uint32_t* xk = T.alloc<uint32_t>(NRpa, s);
   uint32_t* xk2 = T.alloc<uint32_t>(NRpa, s);
   uint32_t* xp2 = T.alloc<uint32_t>(NRpa, s);
-  make_keys(rpx, NRp, d_rpbase, n, dkx, xmin, xk, nullptr, s);
+  make_keys(rpx, NRp, d_rpbase, n, dkx, xmin, xk, nullptr, nullptr, s);
   bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, xbits, s, T);
   uint32_t *sxk = alt3 ? xk2 : xk, *sxp = alt3 ? xp2 : rpy;
   head_flags(sxk, NRp, flags, s);
@@ -384,8 +390,38 @@ void Plan::partition(hipStream_t s) {
   dense_keys0 = 0;  // keys with a dense S entry and an R row (the hot histogram covers them all)
   for (int q = 0; q < 32; ++q) dense_keys0 += h_hist[q];
   choose_dense_kernel(T, s);
-  if (!use_mfma) pivot_split(T, s);
+  if (!use_mfma) {
+    pivot_split(T, s);
+    narrow_segments(s);
+  }
   T.release(s);
+}
+
+void Plan::narrow_segments(hipStream_t s) {
+  const DenseSpace& d0 = ds[0];
+  for (int k = 0; k < 3; ++k) {
+    const int64_t lo = k == 0 ? 1 : k == 1 ? NARROW_SMALL + 1 : NARROW_MAX + 1;
+    const int64_t hi = k == 0 ? NARROW_SMALL : k == 1 ? NARROW_MAX : INT64_MAX;
+    std::vector<int32_t>& x0 = h_nar_x0[k];
+    std::vector<int32_t>& base = h_nar_base[k];
+    x0.clear();
+    base.assign(1, 0);
+    for (int i = 0; i < n_inst; ++i) {
+      const int64_t zd = d0.h_base[i + 1] - d0.h_base[i], nx = h_xbase[i + 1] - h_xbase[i];
+      if (zd >= lo && zd <= hi && nx > 0) {
+        x0.push_back(h_xbase[i]);
+        base.push_back(base.back() + int32_t(nx));
+      }
+    }
+    nar_m[k] = int(x0.size());
+    nar_rows[k] = base.back();
+    if (nar_m[k] == 0) continue;
+    nar_x0[k] = A.alloc<int32_t>(nar_m[k], s);
+    nar_base[k] = A.alloc<int32_t>(nar_m[k] + 1, s);
+    h2d(nar_x0[k], x0.data(), x0.size(), s);
+    h2d(nar_base[k], base.data(), base.size(), s);
+  }
+  nar_listed = true;
 }
 
 // The count pass of the dense part runs on the INT8 matrix cores when the
@@ -658,9 +694,19 @@ RowCtx Plan::ctx(int space) const {
   const DenseSpace& d = ds[space];
   RowCtx c;
   c.n_inst = n_inst;
+  c.n_x = NX;
   c.max_z_range = 0;
   c.max_zd_range = 0;
   c.max_hot = 0;
+  c.narrow = 0;
+  c.by_width = space == 0 && nar_listed;
+  for (int k = 0; k < 3; ++k) {  // listed for space 0 only
+    c.nar_x0[k] = c.by_width ? nar_x0[k] : nullptr;
+    c.nar_base[k] = c.by_width ? nar_base[k] : nullptr;
+    c.nar_m[k] = c.by_width ? nar_m[k] : 0;
+    c.nar_rows[k] = c.by_width ? nar_rows[k] : 0;
+    if (k < 2 && c.nar_m[k] > 0) c.narrow |= 1 << k;
+  }
   for (int i = 0; i < n_inst; ++i) {
     c.max_z_range = std::max<int64_t>(c.max_z_range, h_zbase[i + 1] - h_zbase[i]);
     if (!d.h_base.empty()) c.max_zd_range = std::max<int64_t>(c.max_zd_range, d.h_base[i + 1] - d.h_base[i]);

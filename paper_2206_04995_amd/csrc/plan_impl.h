@@ -74,6 +74,16 @@ struct Plan {
   bool use_mfma = false;
   int8_t *pA = nullptr, *pBt = nullptr;
   int64_t K_panel = 0, k_pad = 0, nx_pad = 0, nz_pad = 0, dense_keys0 = 0;
+  // rows of the instances by dense width (class 0: at most NARROW_SMALL dense
+  // z, 1: at most NARROW_MAX, 2: more): per class, the first x of each such
+  // instance and the running row count
+  int32_t* nar_x0[3] = {nullptr, nullptr, nullptr};
+  int32_t* nar_base[3] = {nullptr, nullptr, nullptr};
+  int nar_m[3] = {0, 0, 0};
+  int64_t nar_rows[3] = {0, 0, 0};
+  std::vector<int32_t> h_nar_x0[3], h_nar_base[3];  // host copies (sources of the uploads)
+  bool nar_listed = false;
+  void narrow_segments(hipStream_t s);
   void choose_dense_kernel(Arena& T, hipStream_t s);
   void build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a, const int32_t* cnt_b,
                    const std::vector<int32_t>* hist_pre, Arena& T, hipStream_t s);

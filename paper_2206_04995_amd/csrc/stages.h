@@ -11,17 +11,22 @@ namespace jp {
 // row at a time).
 constexpr int DW_BITS = 16384;
 constexpr int DW_WORDS = DW_BITS / 32;
+// count mode: rows of instances with at most this many dense z are counted
+// with a quarter wave (NARROW_SMALL) or a whole wave (NARROW_MAX) per row
+constexpr int NARROW_SMALL = 512;
+constexpr int NARROW_MAX = 2048;
 // hot keys whose window slices a DenseEC workgroup stages in LDS
 constexpr int T_STAGE = 16;
 
 // ------------------------------------------------------------ mapping
-// keys[i] = koff[inst(i)] + (v[i] - mn[inst(i)]); payload[i] = i (if non-null)
+// keys[i] = koff[inst(i)] + (v[i] - mn[inst(i)]); if payload is non-null,
+// payload[i] = pay_src[i] (a column carried through the sort) or i
 void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff,
-               const int32_t* mn, uint32_t* keys, uint32_t* payload, hipStream_t s);
-// keysY[p] = key of sy[perm[p]]; payloadY[p] = E[p + 1] - 1 (id of sorted position p)
-void make_keys_perm(const int32_t* v, const uint32_t* perm, int64_t n, const int32_t* ebase, int n_inst,
-                    const int64_t* koff, const int32_t* mn, const int32_t* E, uint32_t* keys,
-                    uint32_t* payload, hipStream_t s);
+               const int32_t* mn, uint32_t* keys, uint32_t* payload, const int32_t* pay_src, hipStream_t s);
+// keys[p] = key of the value v[p] carried through an earlier sort (position p
+// keeps its instance); payload[p] = E[p + 1] - 1 (the id of sorted position p)
+void make_keys_carried(const uint32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff,
+                       const int32_t* mn, const int32_t* E, uint32_t* keys, uint32_t* payload, hipStream_t s);
 // flags[p] = 1 if sorted position p starts a run of equal keys
 void head_flags(const uint32_t* keys, int64_t n, int32_t* flags, hipStream_t s);
 // for each run head p: first[id] = p, vals[id] = original value of the key; first[n_id] = n
@@ -108,6 +113,7 @@ void split_rows(const int32_t* flag, const int32_t* E, int64_t n, int32_t* rows_
 // ----------------------------------------------------------- row work
 struct RowCtx {
   int n_inst;
+  int64_t n_x;             // rows of all instances
   int64_t max_z_range;     // largest number of z ids of one instance
   int64_t max_zd_range;    // largest number of dense z ids of one instance
   int64_t max_hot;         // largest number of hot keys of one instance
@@ -133,6 +139,14 @@ struct RowCtx {
   const int32_t* wptr;     // segment of (window w, y): ccol[wptr[k], wptr[k+1]), k = cwm_off[i] + w*Y_i + y - y_base[i]
   const int64_t* cwm_off;  // [n_inst] offset of the instance's segment table
   int wgroup;              // windows per workgroup of the count kernel (0: from dense_window_group)
+  // rows by the dense width of their instance, class 0: 0 < dense z <= NARROW_SMALL,
+  // 1: up to NARROW_MAX, 2: more (space 0 only; set when the partition listed them)
+  int narrow;                  // bit k: class k has rows (k = 0, 1)
+  bool by_width;               // the three classes are listed
+  const int32_t* nar_x0[3];    // per class: first x of each instance of the class
+  const int32_t* nar_base[3];  // per class: running count of their rows [nar_m + 1]
+  int nar_m[3];
+  int64_t nar_rows[3];
   // per R CSR entry j (filled by sparse_row_work): the sparse S row of its key
   const int32_t* seg0;     // first entry in spcol
   const int32_t* seglen;   // number of entries
