@@ -73,6 +73,13 @@ int key_layout(const std::vector<int32_t>& mn, const std::vector<int32_t>& mx, s
   return bits_for(uint64_t(koff[n]));
 }
 
+// key bits of the widest instance range (a segmented sort sorts only these)
+int local_bits(const std::vector<int64_t>& koff) {
+  int64_t w = 0;
+  for (size_t i = 0; i + 1 < koff.size(); ++i) w = std::max<int64_t>(w, koff[i + 1] - koff[i]);
+  return bits_for(uint64_t(w));
+}
+
 // gather of per-instance device columns into one concatenated buffer
 __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int32_t* __restrict__ base, int n_inst,
                               int64_t n, int32_t* __restrict__ dst) {
@@ -210,7 +217,8 @@ void Plan::map(hipStream_t s) {
 
   // S sorted by (instance, z): z ids, m_z
   make_keys(sz, NS, d_sbase, n, dkz, zmin, k1, v1, sy, s);  // S.y rides along
-  bool alt = radix_sort_pairs(k1, v1, k2, v2, NS, zbits, s, T);
+  const SortSegments sseg_z{n, d_sbase, dkz, h_sbase};
+  bool alt = radix_sort_pairs(k1, v1, k2, v2, NS, n > 1 ? local_bits(koff_z) : zbits, s, T, &sseg_z);
   uint32_t *zk = alt ? k2 : k1, *zp = alt ? v2 : v1;
   head_flags(zk, NS, flags, s);
   int32_t* Ez = T.alloc<int32_t>(NS + 1, s);
@@ -225,7 +233,8 @@ void Plan::map(hipStream_t s) {
   uint32_t *yk = alt ? k1 : k2, *yp = alt ? v1 : v2;  // the free pair
   make_keys_carried(zp, NS, d_sbase, n, dky, ymin, Ez, yk, yp, s);
   uint32_t *ok = zk, *op = zp;  // reuse the z-sorted pair as scratch
-  bool alt2 = radix_sort_pairs(yk, yp, ok, op, NS, ybits, s, T);
+  const SortSegments sseg_y{n, d_sbase, dky, h_sbase};
+  bool alt2 = radix_sort_pairs(yk, yp, ok, op, NS, n > 1 ? local_bits(koff_y) : ybits, s, T, &sseg_y);
   uint32_t *syk = alt2 ? ok : yk, *syp = alt2 ? op : yp;
   head_flags(syk, NS, flags, s);
   Ey = A.alloc<int32_t>(NS + 1, s);
@@ -283,7 +292,8 @@ void Plan::map(hipStream_t s) {
   uint32_t* xk2 = T.alloc<uint32_t>(NRpa, s);
   uint32_t* xp2 = T.alloc<uint32_t>(NRpa, s);
   make_keys(rpx, NRp, d_rpbase, n, dkx, xmin, xk, nullptr, nullptr, s);
-  bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, xbits, s, T);
+  const SortSegments sseg_x{n, d_rpbase, dkx, h_rpbase};
+  bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, n > 1 ? local_bits(koff_x) : xbits, s, T, &sseg_x);
   uint32_t *sxk = alt3 ? xk2 : xk, *sxp = alt3 ? xp2 : rpy;
   head_flags(sxk, NRp, flags, s);
   int32_t* Ex = T.alloc<int32_t>(NRp + 1, s);

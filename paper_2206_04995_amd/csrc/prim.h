@@ -10,11 +10,24 @@ void scan_excl_i32(const int32_t* in, int32_t* out, int64_t n, hipStream_t s, Ar
 void scan_excl_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, hipStream_t s, Arena& a);
 void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s, Arena& a);
 
+// Input already grouped by segment: segment i holds elements [ebase[i],
+// ebase[i+1]) (device and host copies) and its keys lie in [koff[i],
+// koff[i] + 2^bits).
+struct SortSegments {
+  int n_seg;
+  const int32_t* d_ebase;             // [n_seg + 1]
+  const int64_t* d_koff;              // [n_seg]
+  const std::vector<int32_t>& h_ebase;  // [n_seg + 1]
+};
+
 // Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the
-// keys.  The sorted data ends up either in (k, v) or in (kt, vt); the function
-// returns true when it is in (kt, vt).  `v` may be null (keys only).
+// keys, or, with segments, of every segment in place on the low `bits` bits of
+// key - koff[i] (passes then depend on the widest segment's key range, not on
+// the stacked ranges).  The sorted data ends up either in (k, v) or in
+// (kt, vt); the function returns true when it is in (kt, vt).  `v` may be null
+// (keys only).
 bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int64_t n, int bits,
-                      hipStream_t s, Arena& a);
+                      hipStream_t s, Arena& a, const SortSegments* seg = nullptr);
 
 // Per-segment min and max of int32 values; segment i is [base[i], base[i+1]).
 // mn/mx (n_seg entries) are overwritten; empty segments give mn > mx.

@@ -109,28 +109,81 @@ constexpr int RS_TILE = RS_NT * RS_IT;  // 4096 keys per block
 constexpr int RS_WAVES = RS_NT / 64;
 constexpr int RS_WTILE = RS_TILE / RS_WAVES;  // 1024 keys per wave
 
+// Tiles of a segmented sort: segment i (elements [ebase[i], ebase[i+1]), keys
+// in [koff[i], koff[i] + 2^bits)) owns tiles [toff[i], toff[i+1]), so no tile
+// spans two segments.  The histogram of tile t of segment i, digit d, sits at
+// toff[i] * nd + d * T_i + (t - toff[i]) (T_i tiles): a flat scan then orders
+// the output by segment, digit, tile, which keeps every segment in place.  A
+// plain sort is one segment with koff 0.
+struct TileMap {
+  const int32_t* toff;   // [n_seg + 1]
+  const int32_t* ebase;  // [n_seg + 1]
+  const int64_t* koff;   // [n_seg] (null: 0)
+  int n_seg;             // 0: one segment [0, n)
+};
+
+struct Tile {
+  int64_t lo, hi;   // elements
+  int64_t hbase;    // histogram index of digit 0
+  int stride;       // histogram distance of consecutive digits (tiles of the segment)
+  int64_t koff;     // subtracted from the keys
+};
+
+// whole wave, uniform control flow
+__device__ __forceinline__ Tile tile_of(const TileMap& m, int64_t n, int nd) {
+  Tile t;
+  const int b = blockIdx.x;
+  if (m.n_seg == 0) {
+    t.lo = int64_t(b) * RS_TILE;
+    t.hi = t.lo + RS_TILE < n ? t.lo + RS_TILE : n;
+    t.hbase = b;
+    t.stride = int(gridDim.x);
+    t.koff = 0;
+    return t;
+  }
+  const int sg = wave_find_inst<int32_t>(m.toff, m.n_seg, b);
+  const int t0 = m.toff[sg], nt = m.toff[sg + 1] - t0;
+  const int64_t e1 = m.ebase[sg + 1];
+  t.lo = int64_t(m.ebase[sg]) + int64_t(b - t0) * RS_TILE;
+  t.hi = t.lo + RS_TILE < e1 ? t.lo + RS_TILE : e1;
+  t.hbase = int64_t(t0) * nd + (b - t0);
+  t.stride = nt;
+  t.koff = m.koff ? m.koff[sg] : 0;
+  return t;
+}
+
+__device__ __forceinline__ uint32_t digit_of(uint32_t k, const Tile& t, int shift, uint32_t mask) {
+  return (uint32_t(int64_t(k) - t.koff) >> shift) & mask;
+}
+
 __global__ void __launch_bounds__(RS_NT) k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
                                                        int shift, int nbits, int* __restrict__ hist,
-                                                       int nblocks) {
+                                                       TileMap m) {
   __shared__ int cnt[RS_WAVES][256];
   const int wid = threadIdx.x >> 6;
   const int nd = 1 << nbits;
   const uint32_t mask = uint32_t(nd - 1);
+  const Tile tl = tile_of(m, n, nd);
   for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&cnt[0][0])[i] = 0;
   __syncthreads();
-  int64_t base = int64_t(blockIdx.x) * RS_TILE;
 #pragma unroll 4
   for (int j = 0; j < RS_IT; ++j) {
-    int64_t i = base + j * RS_NT + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[wid][(keys[i] >> shift) & mask], 1);
+    int64_t i = tl.lo + j * RS_NT + threadIdx.x;
+    if (i < tl.hi) atomicAdd(&cnt[wid][digit_of(keys[i], tl, shift, mask)], 1);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < nd; d += RS_NT) {
     int c = 0;
 #pragma unroll
     for (int w = 0; w < RS_WAVES; ++w) c += cnt[w][d];
-    hist[int64_t(d) * nblocks + blockIdx.x] = c;
+    hist[tl.hbase + int64_t(d) * tl.stride] = c;
   }
+}
+
+// T_i = tiles of segment i
+__global__ void k_tile_counts(const int32_t* __restrict__ ebase, int n_seg, int32_t* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_seg) cnt[i] = int32_t((int64_t(ebase[i + 1]) - ebase[i] + RS_TILE - 1) / RS_TILE);
 }
 
 template <bool HAS_V>
@@ -139,7 +192,7 @@ __global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restr
                                                           uint32_t* __restrict__ kout,
                                                           uint32_t* __restrict__ vout, int64_t n,
                                                           int shift, int nbits,
-                                                          const int* __restrict__ offs, int nblocks) {
+                                                          const int* __restrict__ offs, TileMap m) {
   __shared__ uint32_t s_k[RS_TILE];
   __shared__ uint32_t s_v[HAS_V ? RS_TILE : 1];
   __shared__ int wcnt[RS_WAVES][256];
@@ -151,19 +204,19 @@ __global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restr
   const int nd = 1 << nbits;
   const uint32_t mask = uint32_t(nd - 1);
   const uint64_t ltm = lanemask_lt();
+  const Tile tl = tile_of(m, n, nd);
   for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
   __syncthreads();
 
-  const int64_t tbase = int64_t(blockIdx.x) * RS_TILE;
-  const int64_t wbase = tbase + int64_t(wid) * RS_WTILE;
+  const int64_t wbase = tl.lo + int64_t(wid) * RS_WTILE;
   uint32_t key[RS_IT], val[RS_IT];
   int lrank[RS_IT];
 #pragma unroll
   for (int j = 0; j < RS_IT; ++j) {
     int64_t i = wbase + j * 64 + lane;
-    bool valid = i < n;
+    bool valid = i < tl.hi;
     uint32_t k = valid ? kin[i] : 0u;
-    uint32_t d = (k >> shift) & mask;
+    uint32_t d = digit_of(k, tl, shift, mask);
     key[j] = k;
     if (HAS_V) val[j] = valid ? vin[i] : 0u;
     uint64_t m = ballot(valid);
@@ -196,7 +249,7 @@ __global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restr
       run += c;
     }
     tot_d = run;
-    goff[threadIdx.x] = offs[int64_t(threadIdx.x) * nblocks + blockIdx.x];
+    goff[threadIdx.x] = offs[tl.hbase + int64_t(threadIdx.x) * tl.stride];
   }
   int tile_total;
   int st = block_excl_scan<int>(tot_d, scan_lds, tile_total);
@@ -205,7 +258,7 @@ __global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restr
 #pragma unroll
   for (int j = 0; j < RS_IT; ++j) {
     if (lrank[j] >= 0) {
-      uint32_t d = (key[j] >> shift) & mask;
+      uint32_t d = digit_of(key[j], tl, shift, mask);
       int pos = dstart[d] + wcnt[wid][d] + lrank[j];
       s_k[pos] = key[j];
       if (HAS_V) s_v[pos] = val[j];
@@ -214,7 +267,7 @@ __global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restr
   __syncthreads();
   for (int i = threadIdx.x; i < tile_total; i += RS_NT) {
     uint32_t k = s_k[i];
-    uint32_t d = (k >> shift) & mask;
+    uint32_t d = digit_of(k, tl, shift, mask);
     int64_t g = int64_t(goff[d]) + (i - dstart[d]);
     kout[g] = k;
     if (HAS_V) vout[g] = s_v[i];
@@ -336,11 +389,27 @@ void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s, Ar
 }
 
 bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int64_t n, int bits,
-                      hipStream_t s, Arena& a) {
+                      hipStream_t s, Arena& a, const SortSegments* seg) {
   if (n <= 1 || bits <= 0) return false;
   int passes = (bits + 7) / 8;
   int width = (bits + passes - 1) / passes;
+  TileMap m{nullptr, nullptr, nullptr, 0};
   int nblocks = int((n + RS_TILE - 1) / RS_TILE);
+  int32_t* toff = nullptr;
+  if (seg && seg->n_seg > 1) {
+    const int ns = seg->n_seg;
+    int64_t nb = 0;
+    for (int i = 0; i < ns; ++i) nb += (seg->h_ebase[i + 1] - seg->h_ebase[i] + RS_TILE - 1) / RS_TILE;
+    nblocks = int(nb);
+    int32_t* tc = a.alloc<int32_t>(ns, s);
+    toff = a.alloc<int32_t>(ns + 1, s);
+    hipLaunchKernelGGL(k_tile_counts, dim3((ns + 255) / 256), dim3(256), 0, s, seg->d_ebase, ns, tc);
+    JP_LAUNCH_CHECK();
+    scan_excl_i32(tc, toff, ns, s, a);
+    a.give_back(tc, s);
+    m = TileMap{toff, seg->d_ebase, seg->d_koff, ns};
+  }
+  if (nblocks == 0) return false;
   int64_t hsz = int64_t(1 << width) * nblocks;
   int* hist = a.alloc<int>(hsz, s);
   int* offs = a.alloc<int>(hsz + 1, s);
@@ -349,17 +418,15 @@ bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int6
   for (int p = 0; p < passes; ++p) {
     int w = width;
     if (shift + w > bits) w = bits - shift;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(RS_NT), 0, s, (const uint32_t*)ki, n, shift, w, hist,
-                       nblocks);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(RS_NT), 0, s, (const uint32_t*)ki, n, shift, w, hist, m);
     JP_LAUNCH_CHECK();
     scan_impl<int, int>(hist, offs, int64_t(1 << w) * nblocks, s, a);
     if (v)
       hipLaunchKernelGGL(k_radix_scatter<true>, dim3(nblocks), dim3(RS_NT), 0, s, (const uint32_t*)ki,
-                         (const uint32_t*)vi, ko, vo, n, shift, w, (const int*)offs, nblocks);
+                         (const uint32_t*)vi, ko, vo, n, shift, w, (const int*)offs, m);
     else
       hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblocks), dim3(RS_NT), 0, s, (const uint32_t*)ki,
-                         (const uint32_t*)nullptr, ko, (uint32_t*)nullptr, n, shift, w, (const int*)offs,
-                         nblocks);
+                         (const uint32_t*)nullptr, ko, (uint32_t*)nullptr, n, shift, w, (const int*)offs, m);
     JP_LAUNCH_CHECK();
     std::swap(ki, ko);
     std::swap(vi, vo);
@@ -367,6 +434,7 @@ bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int6
   }
   a.give_back(offs, s);
   a.give_back(hist, s);
+  if (toff) a.give_back(toff, s);
   return ki == kt;
 }
 
