@@ -193,9 +193,16 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
     }
     __syncthreads();
 
+    // the rows' first codes shift through cr, so the row loop stays rolled
+    // (unrolled, its scalar state spills)
+    int cr[RPW];
 #pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-      if (r >= nrows) break;
+    for (int k = 0; k < RPW; ++k) cr[k] = code[k];
+#pragma unroll 1
+    for (int r = 0; r < nrows; ++r) {
+      const int cd_r = cr[0];
+#pragma unroll
+      for (int k = 0; k + 1 < RPW; ++k) cr[k] = cr[k + 1];
       const int nwin_r = __builtin_amdgcn_readlane(my_nwin, r);
       if (w >= nwin_r) continue;
       const int inst = __builtin_amdgcn_readlane(my_inst, r);
@@ -208,7 +215,7 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
       const int32_t* wp = c.wptr + c.cwm_off[inst] + int64_t(w) * ny;
 
       // bounds of this window's cold segments: issued first, used after the hot ORs
-      const int cd = code[r];
+      const int cd = cd_r;
       int s0 = 0, len = 0;
       if (cd <= -2) {
         const int yl = (-2 - cd) - yb;
@@ -292,7 +299,7 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
 // Count mode for rows of instances with few dense z (0 < Z_d <= 32 * LANES):
 // the whole dense range is one short bit row, so a group of LANES lanes owns
 // a row, one 32-z word per lane, and a wave counts 64 / LANES rows at once
-// (the window kernel would spend a 16384-z window, 512 words, on each).  The
+// (the window kernel would spend a 32768-z window, 1024 words, on each).  The
 // groups walk their rows' join keys LANES at a time: hot keys are ORed one
 // per group per step (each group loads its own key's words), cold keys are
 // scattered into the group's LDS words.  Slot i is row rows[i] (a list: rows

@@ -622,6 +622,9 @@ void Plan::build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a,
 // so its count is |S_dense[p]| plus a count over the dense z outside
 // S_dense[p] (space 1), which is at most half as wide.  Rows without p keep
 // space 0.  Exact for every row; only the count pass uses it.
+// the automatic split needs rows of more than this many dense z (and enough cells)
+constexpr int64_t PIVOT_MIN_DENSE_Z = 16384;
+
 void Plan::pivot_split(Arena& T, hipStream_t s) {
   const int n = n_inst;
   n_piv = 0;
@@ -638,7 +641,7 @@ void Plan::pivot_split(Arena& T, hipStream_t s) {
   bool any = false;
   for (int i = 0; i < n; ++i) {
     const int64_t nx = h_xbase[i + 1] - h_xbase[i], zd = h_zdbase[i + 1] - h_zdbase[i];
-    cand[i] = d0.h_K[i] > 0 && (mode == 2.0 || (zd > DW_BITS && double(nx) * double(zd) >= min_cells));
+    cand[i] = d0.h_K[i] > 0 && (mode == 2.0 || (zd > PIVOT_MIN_DENSE_Z && double(nx) * double(zd) >= min_cells));
     any = any || cand[i];
   }
   if (!any) return;

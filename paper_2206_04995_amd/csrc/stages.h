@@ -9,14 +9,14 @@ namespace jp {
 
 // Window of the dense-z bitmaps, in bits (DenseEC processes one window of a
 // row at a time).
-constexpr int DW_BITS = 16384;
+constexpr int DW_BITS = 32768;
 constexpr int DW_WORDS = DW_BITS / 32;
 // count mode: rows of instances with at most this many dense z are counted
 // with a quarter wave (NARROW_SMALL) or a whole wave (NARROW_MAX) per row
 constexpr int NARROW_SMALL = 512;
 constexpr int NARROW_MAX = 2048;
 // hot keys whose window slices a DenseEC workgroup stages in LDS
-constexpr int T_STAGE = 16;
+constexpr int T_STAGE = 3;
 
 // ------------------------------------------------------------ mapping
 // keys[i] = koff[inst(i)] + (v[i] - mn[inst(i)]); if payload is non-null,

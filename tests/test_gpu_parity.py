@@ -99,7 +99,7 @@ def test_heavy_sparse_rows_many_windows():
 
 
 def test_dense_many_windows_and_long_rows():
-    # > 32768 dense z (several DenseEC windows), hot keys, cold keys, and x rows
+    # > 65536 dense z (three DenseEC windows), hot keys, cold keys, and x rows
     # with more than 64 join keys (cursor chunk 0 plus binary-searched chunks)
     rng = np.random.default_rng(2)
     n = 200_000
@@ -110,7 +110,7 @@ def test_dense_many_windows_and_long_rows():
     inst = synth.Instance(rx, ry, sz, sy, "dense-windows")
     print("[case] dense windows", flush=True)
     st, _ = assert_parity(inst, _opts("all_dense"), chunk=3_000_000)
-    assert st["n_z_dense"] > 32768 and st["k_hot"] > 0
+    assert st["n_z_dense"] > 65536 and st["k_hot"] > 0
 
 
 def test_tau_invariance():
