@@ -40,20 +40,23 @@ MFMA_I8_PEAK_TOPS = 5000.0
 FETCH_FACTOR = 1048576 / 524308.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
-    # two count launches per step: rows without and with the pivot key
-    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 886072.6 + 398541.0, "write_kib": 155407.4 + 73847.1,
-               "sources": {"dense_ec.hip": "4b6ada38f0bd3a5f4bf3869fc5a1e5c815d6d0f9e5b71d7e2d60821afed43dce",
-                           "stages.h": "d3ef8a70362acf75a5759b26df505dda3672d8d864ec93e53337039aa89075af",
-                           "common.h": "fc0ab1073844693a810a6c96bccaf3980fb07c7dcfbabb749f508575f5f09373"}},
-    "graph": {"kernels": "k_sparse_light<false> x 2 + k_sparse_heavy_count",
-              "fetch_kib": 1463260.3 + 295829.8 + 254204.3, "write_kib": 21095.1 + 2435.2 + 596.4,
-              "sources": {"sparse_bmm.hip": "e159496729db7df054ada0ce0ced3e9623b306883c00d2b591c02f212b0074e2",
-                          "stages.h": "d3ef8a70362acf75a5759b26df505dda3672d8d864ec93e53337039aa89075af",
-                          "common.h": "fc0ab1073844693a810a6c96bccaf3980fb07c7dcfbabb749f508575f5f09373"}},
-    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 809094.8, "write_kib": 12343.8,
+    # two count launches per step: rows without and with the pivot key (2 windows per workgroup, as tuned)
+    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 663708.1 + 276139.1, "write_kib": 80210.6 + 39764.1,
+               "sources": {"dense_ec.hip": "fd636cac880b437f22e4750dd8f0fabb89d8a429d114c6a495c1a0523702ee2c",
+                           "stages.h": "fe8559586cc810df2e3461f9abdbc3fd0266a8a07c78503c5535ded4ae5efe60",
+                           "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
+    # the whole timed SparseBMM count region: per-entry segments and their scan,
+    # row work, row lists, the light/medium/heavy count kernels
+    "graph": {"kernels": "SparseBMM count pass (k_entry_seg ... k_sparse_heavy_count)",
+              "fetch_kib": 2755696.9, "write_kib": 372813.3,
+              "sources": {"sparse_bmm.hip": "a7071e86a80e7333cb7c7c4bf363e9576b9471ef95d373dc26577cd658cf6df3",
+                          "prim.hip": "00bccd1cf8ca5f9a3b869d52992551b66e3be81df0233f26cc46969d5d115881",
+                          "stages.h": "fe8559586cc810df2e3461f9abdbc3fd0266a8a07c78503c5535ded4ae5efe60",
+                          "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
+    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 809038.0, "write_kib": 12343.8,
               "sources": {"dense_mfma.hip": "c4103f00b68fb47500e9e25f66d0e6c7b0317e25200728f600fa7ef5ed3c3ed4",
-                          "stages.h": "d3ef8a70362acf75a5759b26df505dda3672d8d864ec93e53337039aa89075af",
-                          "common.h": "fc0ab1073844693a810a6c96bccaf3980fb07c7dcfbabb749f508575f5f09373"}},
+                          "stages.h": "fe8559586cc810df2e3461f9abdbc3fd0266a8a07c78503c5535ded4ae5efe60",
+                          "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
 }
 
 
@@ -327,6 +330,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tau", type=int, default=None, help="fixed dense threshold (default: tuned cost model)")
     ap.add_argument("--no-tune", action="store_true", help="skip the threshold autotuner (untimed, before warmup)")
+    ap.add_argument("--window-group", type=int, default=None,
+                    help="DenseEC windows per workgroup (default: tuned or automatic; counter runs pin the tuned value)")
+    ap.add_argument("--k-hot-max", type=int, default=None, help="cap on hot keys per instance (default: tuned or automatic)")
     ap.add_argument("--tune-sample", type=int, default=16, help="batched workload: instances the tuner times")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain elementwise copy over this many MiB (a reference for HBM counters)")
@@ -362,10 +368,15 @@ def main():
         del src, dst
         print(f"[bench] copy reference: {args.copy_ref_mib} MiB read + written by one bitwise_not kernel",
               file=sys.stderr, flush=True)
+    fixed = {}
+    if args.window_group is not None:
+        fixed["window_group"] = args.window_group
+    if args.k_hot_max is not None:
+        fixed["k_hot_max"] = args.k_hot_max
     if args.tau is None:
-        opt = P.make_options(flags=P.JP_FLAG_TIMING)
+        opt = P.make_options(flags=P.JP_FLAG_TIMING, **fixed)
     else:
-        opt = P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=args.tau, flags=P.JP_FLAG_TIMING)
+        opt = P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=args.tau, flags=P.JP_FLAG_TIMING, **fixed)
     stream = torch.cuda.current_stream()
     tune = None
     if not args.no_tune and args.tau is None:
@@ -458,7 +469,10 @@ def main():
                        n_z_dense=st["n_z_dense"], k_hot=st["k_hot"], out_j=st["out_j"],
                        input_tuples_per_s=(inst.n_r + inst.n_s) / (ms * 1e-3),
                        kernel_ms={"sparse": sp_ms, "dense": de_ms, "execute": ex_ms},
-                       tau_tuned=None if tune is None else {"tau": tune["tau"], "model_tau": tune["model_tau"]}),
+                       tau_tuned=None if tune is None else {"tau": tune["tau"], "model_tau": tune["model_tau"],
+                                                            "dense_kernel": tune["dense_kernel"],
+                                                            "k_hot_max": tune["k_hot_max"],
+                                                            "window_group": tune["window_group"]}),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

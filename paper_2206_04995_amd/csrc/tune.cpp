@@ -5,7 +5,8 @@
 // the cost ratio of one DenseEC bit decision to one SparseBMM join row, which
 // depends on the kernels and the shape of the data.  jp_tune measures the whole
 // plan + count pass of a query for a set of thresholds (all dense, all sparse,
-// the model's tau scaled by powers of 4, and quantiles of m_z), then at the
+// the model's tau scaled by powers of 4, and quantiles of m_z; in increasing
+// order, stopping once a threshold above the best is 3x slower), then at the
 // fastest threshold the DenseEC count kernel, the hot-key cap and the windows
 // per workgroup (a coordinate search), checks that every setting gives the
 // same counts (the partition is intersection-free, Sec. 2.3, so it must), and
@@ -63,10 +64,11 @@ struct Trial {
   bool mfma;
 };
 
-// wall time of plan + count pass + count read-back for one setting
-Trial run_trial(const jp_instance& in, const jp_options& o, hipStream_t s, int reps) {
+// wall time of plan + count pass + count read-back for one setting (the best
+// of `reps` runs; no repeat once a run exceeds cutoff_ms)
+Trial run_trial(const jp_instance& in, const jp_options& o, hipStream_t s, int reps, double cutoff_ms = 1e300) {
   Trial t{o, 1e300, {0, 0, 0}, false};
-  for (int r = 0; r < reps; ++r) {
+  for (int r = 0; r < reps && !(r > 0 && t.ms > cutoff_ms); ++r) {
     JP_HIP(hipStreamSynchronize(s));
     const auto t0 = std::chrono::steady_clock::now();
     Plan p;
@@ -158,14 +160,21 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
     Trial best = model;
     int tried = 0;
     auto consider = [&](const jp_options& o) {
-      const Trial t = run_trial(in, o, stream, 2);
+      const Trial t = run_trial(in, o, stream, 2, 3.0 * best.ms);
       ++tried;
       if (t.counts[0] != model.counts[0])
         throw Error(JP_ESTATE, "settings gave different counts: " + std::to_string(t.counts[0]) + " vs " +
                                    std::to_string(model.counts[0]));
-      if (t.ms < best.ms) best = t;
+      if (t.ms < 0.98 * best.ms) best = t;  // within 2% the earlier (default-side) setting stays: stable choices
+      return t.ms;
     };
-    for (int64_t tau : cand) consider(fixed(tau));
+    // thresholds in increasing order: a higher threshold moves more z to the
+    // sparse side, so once a threshold above the best one is 3x slower than
+    // it the higher ones are not tried (on a skewed query they cost seconds)
+    for (int64_t tau : cand) {
+      const double ms = consider(fixed(tau));
+      if (tau > best.o.dense_threshold && ms > 3.0 * best.ms) break;
+    }
     // at the chosen threshold: the dense count kernel, then the hot-key cap and
     // the windows per workgroup of the bit path, one after the other
     if (best.o.dense_threshold != INT64_MAX) {
