@@ -298,26 +298,29 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
 
 // Count mode for rows of instances with few dense z (0 < Z_d <= 32 * LANES):
 // the whole dense range is one short bit row, so a group of LANES lanes owns
-// a row, one 32-z word per lane, and a wave counts 64 / LANES rows at once
+// a row, WPL 32-z words per lane, and a wave counts 64 / LANES rows at once
 // (the window kernel would spend a 32768-z window, 1024 words, on each).  The
 // groups walk their rows' join keys LANES at a time: hot keys are ORed one
 // per group per step (each group loads its own key's words), cold keys are
 // scattered into the group's LDS words.  Slot i is row rows[i] (a list: rows
 // of other instances are skipped), or the i-th row of the class's narrow
 // instances (c.nar_x0 / c.nar_base of class CLS).
-template <int LANES>
+template <int LANES, int WPL>
 __global__ void __launch_bounds__(256) k_dense_narrow(RowCtx c, int64_t n_slots, const int32_t* __restrict__ rows,
                                                    int accumulate, int32_t* __restrict__ cnt) {
-  constexpr int CLS = LANES == 16 ? 0 : 1;
+  static_assert(WPL == 1 || WPL == 4, "one word or one uint4 per lane");
+  constexpr int CLS = LANES == 16 ? 0 : WPL == 1 ? 1 : 2;
   constexpr int GROUPS = 64 / LANES;
-  constexpr int ZMAX = 32 * LANES;
-  constexpr int ZMIN = LANES == 16 ? 1 : NARROW_SMALL + 1;
-  __shared__ uint32_t buf_all[4][64];
+  constexpr int ZMAX = 32 * LANES * WPL;
+  constexpr int ZMIN = CLS == 0 ? 1 : CLS == 1 ? NARROW_SMALL + 1 : NARROW_MID + 1;
+  static_assert(ZMAX == (CLS == 0 ? NARROW_SMALL : CLS == 1 ? NARROW_MID : NARROW_MAX), "class bounds");
+  __shared__ uint32_t buf_all[4][64 * WPL];
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
   const int grp = lane / LANES, gl = lane % LANES;
-  uint32_t* buf = &buf_all[wid][grp * LANES];
-  buf[gl] = 0u;
+  uint32_t* buf = &buf_all[wid][grp * LANES * WPL];
+#pragma unroll
+  for (int e = 0; e < WPL; ++e) buf[gl * WPL + e] = 0u;
   lds_fence();
 
   const int64_t slot0 = (int64_t(blockIdx.x) * 4 + wid) * GROUPS;
@@ -354,41 +357,80 @@ __global__ void __launch_bounds__(256) k_dense_narrow(RowCtx c, int64_t n_slots,
   const int yb = c.y_base[inst];
   const int32_t* wp = c.wptr + c.cwm_off[inst];  // window 0 of the instance
 
-  uint32_t acc = 0u;
+  uint32_t acc[WPL];
+#pragma unroll
+  for (int e = 0; e < WPL; ++e) acc[e] = 0u;
+  const bool mine = gl * WPL < nwords;  // this lane's words hold dense z of the row
   const int len = b - a;
   const int maxlen = wave_max(len);
   for (int c0 = 0; c0 < maxlen; c0 += LANES) {
     const int j = a + c0 + gl;
     const int code = (c0 + gl < len) ? c.rcode[j] : -1;
-    // hot keys: one per group per step
+    // hot keys: one per group per step, four steps' loads in flight before the ORs
     const uint64_t hm = __ballot(code >= 0);
     uint64_t gm = LANES == 64 ? hm : (hm >> (grp * LANES)) & (~uint64_t(0) >> (64 - LANES));
     while (__ballot(gm != 0)) {
-      const int l = gm ? __ffsll((unsigned long long)gm) - 1 : 0;
-      const int k = __shfl(code, grp * LANES + l, 64);
-      if (gm && gl < nwords) acc |= hrow[int64_t(k) * rw + gl];
-      gm &= gm - 1;
+      uint32_t v[4][WPL];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool has = gm != 0;
+        const int l = has ? __ffsll((unsigned long long)gm) - 1 : 0;
+        const int k = __shfl(code, grp * LANES + l, 64);
+#pragma unroll
+        for (int e = 0; e < WPL; ++e) v[u][e] = 0u;
+        if (has && mine) {
+          const uint32_t* src = hrow + int64_t(k) * rw + gl * WPL;  // rows are whole windows: WPL words in bounds
+          if (WPL == 4) {
+            const uint4 q = *reinterpret_cast<const uint4*>(src);
+            v[u][0] = q.x;
+            v[u][WPL > 1 ? 1 : 0] = q.y;
+            v[u][WPL > 2 ? 2 : 0] = q.z;
+            v[u][WPL > 3 ? 3 : 0] = q.w;
+          } else {
+            v[u][0] = src[0];
+          }
+        }
+        gm &= gm - 1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < WPL; ++e) acc[e] |= v[u][e];
     }
-    // cold keys: the group scatters each key's window-0 entries
+    // cold keys: the group scatters each key's window-0 entries (segment
+    // bounds of four keys loaded together)
     const uint64_t cm = __ballot(code <= -2);
     uint64_t gc = LANES == 64 ? cm : (cm >> (grp * LANES)) & (~uint64_t(0) >> (64 - LANES));
     while (__ballot(gc != 0)) {
-      const int l = gc ? __ffsll((unsigned long long)gc) - 1 : 0;
-      const int cd = __shfl(code, grp * LANES + l, 64);
-      if (gc) {
-        const int yl = (-2 - cd) - yb;
-        const int s0 = wp[yl], s1 = wp[yl + 1];
-        for (int t = s0 + gl; t < s1; t += LANES) {
+      int s0[4], s1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool has = gc != 0;
+        const int l = has ? __ffsll((unsigned long long)gc) - 1 : 0;
+        const int cd = __shfl(code, grp * LANES + l, 64);
+        s0[u] = 0;
+        s1[u] = 0;
+        if (has) {
+          const int yl = (-2 - cd) - yb;
+          s0[u] = wp[yl];
+          s1[u] = wp[yl + 1];
+        }
+        gc &= gc - 1;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        for (int t = s0[u] + gl; t < s1[u]; t += LANES) {
           const int dl = c.ccol[t];
           atomicOr(&buf[dl >> 5], 1u << (dl & 31));
         }
       }
-      gc &= gc - 1;
     }
   }
   lds_fence();
-  if (gl < nwords) acc |= buf[gl];
-  int pc = active ? __popc(acc) : 0;
+  int pc = 0;
+#pragma unroll
+  for (int e = 0; e < WPL; ++e) pc += __popc(acc[e] | buf[gl * WPL + e]);
+  if (!active) pc = 0;
 #pragma unroll
   for (int o = LANES / 2; o > 0; o >>= 1) pc += __shfl_xor(pc, o, 64);
   if (active && gl == 0) {
@@ -510,12 +552,18 @@ static void dense_narrow(const RowCtx& c, int64_t n_rows, const int32_t* rows, i
                          hipStream_t s) {
   if (c.narrow & 1) {
     const int64_t n = rows ? n_rows : c.nar_rows[0];
-    hipLaunchKernelGGL(k_dense_narrow<16>, dim3(int((n + 15) / 16)), dim3(256), 0, s, c, n, rows, accumulate, cnt);
+    hipLaunchKernelGGL((k_dense_narrow<16, 1>), dim3(int((n + 15) / 16)), dim3(256), 0, s, c, n, rows, accumulate,
+                       cnt);
     JP_LAUNCH_CHECK();
   }
   if (c.narrow & 2) {
     const int64_t n = rows ? n_rows : c.nar_rows[1];
-    hipLaunchKernelGGL(k_dense_narrow<64>, dim3(int((n + 3) / 4)), dim3(256), 0, s, c, n, rows, accumulate, cnt);
+    hipLaunchKernelGGL((k_dense_narrow<64, 1>), dim3(int((n + 3) / 4)), dim3(256), 0, s, c, n, rows, accumulate, cnt);
+    JP_LAUNCH_CHECK();
+  }
+  if (c.narrow & 4) {
+    const int64_t n = rows ? n_rows : c.nar_rows[2];
+    hipLaunchKernelGGL((k_dense_narrow<64, 4>), dim3(int((n + 3) / 4)), dim3(256), 0, s, c, n, rows, accumulate, cnt);
     JP_LAUNCH_CHECK();
   }
 }
@@ -538,10 +586,11 @@ void dense_ec(const RowCtx& c, int64_t x_lo, int64_t x_hi, int32_t* cnt, const i
       // rows of wide instances, the narrow kernels the others
       if (x_lo != 0 || x_hi != c.n_x) throw Error(JP_ESTATE, "rows listed by width are counted over the whole range");
       fill_i32(cnt, n, 0, s);
-      const int64_t nw = c.nar_rows[2];
+      const int64_t nw = c.nar_rows[N_WIDTH_CLASSES - 1];
       if (nw > 0) {
         hipLaunchKernelGGL(k_dense_bits<false>, dim3(int((nw + RB - 1) / RB), ng > 0 ? ng : 1), dim3(NT), 0, s, c,
-                           int64_t(0), nw, nullptr, c.nar_base[2], c.nar_x0[2], c.nar_m[2], nullptr, 0, wg, 0, cnt,
+                           int64_t(0), nw, nullptr, c.nar_base[N_WIDTH_CLASSES - 1], c.nar_x0[N_WIDTH_CLASSES - 1],
+                           c.nar_m[N_WIDTH_CLASSES - 1], nullptr, 0, wg, 0, cnt,
                            off, out, int64_t(0));
         JP_LAUNCH_CHECK();
       }

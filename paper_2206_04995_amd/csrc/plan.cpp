@@ -409,9 +409,9 @@ void Plan::partition(hipStream_t s) {
 
 void Plan::narrow_segments(hipStream_t s) {
   const DenseSpace& d0 = ds[0];
-  for (int k = 0; k < 3; ++k) {
-    const int64_t lo = k == 0 ? 1 : k == 1 ? NARROW_SMALL + 1 : NARROW_MAX + 1;
-    const int64_t hi = k == 0 ? NARROW_SMALL : k == 1 ? NARROW_MAX : INT64_MAX;
+  const int64_t bound[N_WIDTH_CLASSES + 1] = {0, NARROW_SMALL, NARROW_MID, NARROW_MAX, INT64_MAX};
+  for (int k = 0; k < N_WIDTH_CLASSES; ++k) {
+    const int64_t lo = bound[k] + 1, hi = bound[k + 1];
     std::vector<int32_t>& x0 = h_nar_x0[k];
     std::vector<int32_t>& base = h_nar_base[k];
     x0.clear();
@@ -713,12 +713,12 @@ RowCtx Plan::ctx(int space) const {
   c.max_hot = 0;
   c.narrow = 0;
   c.by_width = space == 0 && nar_listed;
-  for (int k = 0; k < 3; ++k) {  // listed for space 0 only
+  for (int k = 0; k < N_WIDTH_CLASSES; ++k) {  // listed for space 0 only
     c.nar_x0[k] = c.by_width ? nar_x0[k] : nullptr;
     c.nar_base[k] = c.by_width ? nar_base[k] : nullptr;
     c.nar_m[k] = c.by_width ? nar_m[k] : 0;
     c.nar_rows[k] = c.by_width ? nar_rows[k] : 0;
-    if (k < 2 && c.nar_m[k] > 0) c.narrow |= 1 << k;
+    if (k < N_WIDTH_CLASSES - 1 && c.nar_m[k] > 0) c.narrow |= 1 << k;
   }
   for (int i = 0; i < n_inst; ++i) {
     c.max_z_range = std::max<int64_t>(c.max_z_range, h_zbase[i + 1] - h_zbase[i]);

@@ -75,13 +75,13 @@ struct Plan {
   int8_t *pA = nullptr, *pBt = nullptr;
   int64_t K_panel = 0, k_pad = 0, nx_pad = 0, nz_pad = 0, dense_keys0 = 0;
   // rows of the instances by dense width (class 0: at most NARROW_SMALL dense
-  // z, 1: at most NARROW_MAX, 2: more): per class, the first x of each such
-  // instance and the running row count
-  int32_t* nar_x0[3] = {nullptr, nullptr, nullptr};
-  int32_t* nar_base[3] = {nullptr, nullptr, nullptr};
-  int nar_m[3] = {0, 0, 0};
-  int64_t nar_rows[3] = {0, 0, 0};
-  std::vector<int32_t> h_nar_x0[3], h_nar_base[3];  // host copies (sources of the uploads)
+  // z, 1: NARROW_MID, 2: NARROW_MAX, 3: more): per class, the first x of each
+  // such instance and the running row count
+  int32_t* nar_x0[N_WIDTH_CLASSES] = {};
+  int32_t* nar_base[N_WIDTH_CLASSES] = {};
+  int nar_m[N_WIDTH_CLASSES] = {};
+  int64_t nar_rows[N_WIDTH_CLASSES] = {};
+  std::vector<int32_t> h_nar_x0[N_WIDTH_CLASSES], h_nar_base[N_WIDTH_CLASSES];  // host copies (upload sources)
   bool nar_listed = false;
   void narrow_segments(hipStream_t s);
   void choose_dense_kernel(Arena& T, hipStream_t s);

@@ -12,9 +12,12 @@ namespace jp {
 constexpr int DW_BITS = 32768;
 constexpr int DW_WORDS = DW_BITS / 32;
 // count mode: rows of instances with at most this many dense z are counted
-// with a quarter wave (NARROW_SMALL) or a whole wave (NARROW_MAX) per row
+// with a quarter wave (NARROW_SMALL), a whole wave with one word per lane
+// (NARROW_MID) or four words per lane (NARROW_MAX) per row
 constexpr int NARROW_SMALL = 512;
-constexpr int NARROW_MAX = 2048;
+constexpr int NARROW_MID = 2048;
+constexpr int NARROW_MAX = 8192;
+constexpr int N_WIDTH_CLASSES = 4;  // the three narrow classes and the window kernel's
 // hot keys whose window slices a DenseEC workgroup stages in LDS
 constexpr int T_STAGE = 3;
 
@@ -140,13 +143,14 @@ struct RowCtx {
   const int64_t* cwm_off;  // [n_inst] offset of the instance's segment table
   int wgroup;              // windows per workgroup of the count kernel (0: from dense_window_group)
   // rows by the dense width of their instance, class 0: 0 < dense z <= NARROW_SMALL,
-  // 1: up to NARROW_MAX, 2: more (space 0 only; set when the partition listed them)
-  int narrow;                  // bit k: class k has rows (k = 0, 1)
-  bool by_width;               // the three classes are listed
-  const int32_t* nar_x0[3];    // per class: first x of each instance of the class
-  const int32_t* nar_base[3];  // per class: running count of their rows [nar_m + 1]
-  int nar_m[3];
-  int64_t nar_rows[3];
+  // 1: up to NARROW_MID, 2: up to NARROW_MAX, 3: more (space 0 only; set when the
+  // partition listed them)
+  int narrow;                  // bit k: class k has rows (k = 0, 1, 2)
+  bool by_width;               // the classes are listed
+  const int32_t* nar_x0[N_WIDTH_CLASSES];    // per class: first x of each instance of the class
+  const int32_t* nar_base[N_WIDTH_CLASSES];  // per class: running count of their rows [nar_m + 1]
+  int nar_m[N_WIDTH_CLASSES];
+  int64_t nar_rows[N_WIDTH_CLASSES];
   // per R CSR entry j (filled by sparse_row_work): the sparse S row of its key
   const int32_t* seg0;     // first entry in spcol
   const int32_t* seglen;   // number of entries

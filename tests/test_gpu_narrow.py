@@ -1,9 +1,9 @@
-"""DenseEC count of narrow instances (at most 2048 dense z): a quarter wave per
-row up to 512 dense z, a whole wave per row up to 2048, the window kernel
-above.  Counts and the lists written by the window kernel (whose row offsets
-come from these counts) must equal the oracle's, at the boundaries of the
-three widths, for rows longer than one group of keys, and in a batch that
-mixes the widths with a pivot split."""
+"""DenseEC count of narrow instances (at most 8192 dense z): a quarter wave per
+row up to 512 dense z, a whole wave per row up to 2048 (one word per lane) and
+8192 (four words per lane), the window kernel above.  Counts and the lists
+written by the window kernel (whose row offsets come from these counts) must
+equal the oracle's, at the boundaries of the four widths, for rows longer than
+one group of keys, and in a batch that mixes the widths with a pivot split."""
 import os
 
 import numpy as np
@@ -23,7 +23,8 @@ def _all_dense_bits():
 
 
 @pytest.mark.parametrize("dom_z,zipf_y,n_s", [(37, 0.0, 1_500), (512, 0.0, 18_432), (513, 0.5, 20_000),
-                                               (1_500, 0.0, 100_000), (2_048, 0.3, 80_000), (2_049, 0.0, 100_000)])
+                                               (1_500, 0.0, 100_000), (2_048, 0.3, 80_000), (2_049, 0.0, 100_000),
+                                               (4_096, 0.0, 250_000), (8_192, 0.0, 500_000), (8_193, 0.2, 500_000)])
 def test_narrow_widths_single_query(dom_z, zipf_y, n_s):
     # every z value occurs, so the dense range is exactly dom_z; a row holds
     # about 100 join keys (several groups of 16 and of 64) and reaches 50-80%
@@ -48,7 +49,7 @@ def test_narrow_batch_mixed_widths_with_pivot(monkeypatch):
     # the large instance gets an automatic pivot split, so its rows and the
     # narrow instances' rows are counted from row lists
     monkeypatch.setenv("JP_PIVOT_MIN_CELLS", "1e6")
-    specs = [(60, 0.0), (512, 1.0), (513, 0.0), (1_800, 1.2), (2_049, 1.0), (100, 1.2), (20_000, 1.3)]
+    specs = [(60, 0.0), (512, 1.0), (513, 0.0), (1_800, 1.2), (2_049, 1.0), (100, 1.2), (6_000, 0.0), (20_000, 1.3)]
     insts = [synth.small_random(300 + i, 8_000 + 1_000 * i, 60_000 if dz == 20_000 else max(3_000, 12 * dz),
                                 dom_x=150 + 40 * i, dom_y=1_500 + 100 * i, dom_z=dz, offset=-11 * i, zipf_y=zy)
              for i, (dz, zy) in enumerate(specs)]
