@@ -116,24 +116,48 @@ __global__ void k_hot_flags(const int32_t* __restrict__ cnt_a, const int32_t* __
   }
 }
 
-// one thread per S entry: set the bit of every z of a hot row that lies in
-// the space (zmap[z] = local index in the space, or -1)
+// one lane per S entry: set the bit of every z of a hot row that lies in the
+// space (zmap[z] = local index in the space, or -1).  A hot row's entries
+// ascend in z, so neighbouring lanes often target the same word: the wave ORs
+// the bits of lanes with equal word addresses (shuffle-down doubling; every
+// bit a lane takes belongs to its own address) and only the first lane of each
+// run issues the atomic.  The wave walks its chunk in uniform steps so the
+// shuffles never read an inactive lane.
 __global__ void k_build_hot_bits(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol, int64_t n,
                                  const int32_t* __restrict__ hot, const int32_t* __restrict__ hotrow,
                                  const int32_t* __restrict__ y_base, const int32_t* __restrict__ zmap,
                                  const int64_t* __restrict__ hb_off, const int32_t* __restrict__ row_words,
                                  int n_inst, uint32_t* __restrict__ hb) {
+  const int lane = lane_id();
   SegCursor<int32_t> ycur(y_base, n_inst);
-  if (chunk_first() < n) ycur.seed(Ey[chunk_first() + 1] - 1);
-  CHUNK_LOOP(p, n, JP_CHUNK) {
-    const int32_t y = Ey[p + 1] - 1;
-    if (!hot[y]) continue;
-    const int32_t dl = zmap[scol[p]];
-    if (dl < 0) continue;
-    const int inst = ycur(y);
-    const int64_t k = hotrow[y];
-    uint32_t* row = hb + hb_off[inst] + k * row_words[inst];
-    atomicOr(&row[dl >> 5], 1u << (dl & 31));
+  const int64_t c0 = chunk_first();
+  if (c0 >= n) return;  // whole block
+  ycur.seed(Ey[c0 + 1] - 1);
+  const int64_t c1 = c0 + JP_CHUNK < n ? c0 + JP_CHUNK : n;
+  constexpr uint64_t NONE = ~uint64_t(0);
+  for (int64_t base = c0 + (threadIdx.x & ~63); base < c1; base += blockDim.x) {
+    const int64_t p = base + lane;
+    uint64_t addr = NONE;
+    uint32_t bits = 0u;
+    if (p < c1) {
+      const int32_t y = Ey[p + 1] - 1;
+      if (hot[y]) {
+        const int32_t dl = zmap[scol[p]];
+        if (dl >= 0) {
+          const int inst = ycur(y);
+          addr = uint64_t(hb_off[inst] + int64_t(hotrow[y]) * row_words[inst] + (dl >> 5));
+          bits = 1u << (dl & 31);
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t a2 = __shfl_down(addr, o, 64);
+      const uint32_t b2 = __shfl_down(bits, o, 64);
+      if (lane + o < 64 && a2 == addr) bits |= b2;
+    }
+    const uint64_t ap = __shfl_up(addr, 1, 64);
+    if (addr != NONE && (lane == 0 || ap != addr)) atomicOr(&hb[addr], bits);
   }
 }
 
