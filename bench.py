@@ -41,21 +41,21 @@ FETCH_FACTOR = 1048576 / 524308.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
     # two count launches per step: rows without and with the pivot key (2 windows per workgroup, as tuned)
-    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 663708.1 + 276139.1, "write_kib": 80210.6 + 39764.1,
-               "sources": {"dense_ec.hip": "fd636cac880b437f22e4750dd8f0fabb89d8a429d114c6a495c1a0523702ee2c",
-                           "stages.h": "fe8559586cc810df2e3461f9abdbc3fd0266a8a07c78503c5535ded4ae5efe60",
+    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 663350.6 + 276007.0, "write_kib": 80210.6 + 39764.1,
+               "sources": {"dense_ec.hip": "111caeb87b8fff3c2b7d76cf9dd318885ab8d800b1e135ab9a90f9392802e7c7",
+                           "stages.h": "61a98e3e858a556aa26452dad0578d661920385a14e93a954af6e1b1f09a98b0",
                            "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
     # the whole timed SparseBMM count region: per-entry segments and their scan,
     # row work, row lists, the light/medium/heavy count kernels
     "graph": {"kernels": "SparseBMM count pass (k_entry_seg ... k_sparse_heavy_count)",
-              "fetch_kib": 2755696.9, "write_kib": 372813.3,
+              "fetch_kib": 2756808.5, "write_kib": 372866.3,
               "sources": {"sparse_bmm.hip": "a7071e86a80e7333cb7c7c4bf363e9576b9471ef95d373dc26577cd658cf6df3",
                           "prim.hip": "00bccd1cf8ca5f9a3b869d52992551b66e3be81df0233f26cc46969d5d115881",
-                          "stages.h": "fe8559586cc810df2e3461f9abdbc3fd0266a8a07c78503c5535ded4ae5efe60",
+                          "stages.h": "61a98e3e858a556aa26452dad0578d661920385a14e93a954af6e1b1f09a98b0",
                           "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
-    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 809038.0, "write_kib": 12343.8,
+    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 809039.1, "write_kib": 12343.8,
               "sources": {"dense_mfma.hip": "c4103f00b68fb47500e9e25f66d0e6c7b0317e25200728f600fa7ef5ed3c3ed4",
-                          "stages.h": "fe8559586cc810df2e3461f9abdbc3fd0266a8a07c78503c5535ded4ae5efe60",
+                          "stages.h": "61a98e3e858a556aa26452dad0578d661920385a14e93a954af6e1b1f09a98b0",
                           "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
 }
 
