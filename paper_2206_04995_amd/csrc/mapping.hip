@@ -168,13 +168,6 @@ __global__ void __launch_bounds__(NT) k_histogram(const uint32_t* __restrict__ v
     if (cnt[i]) atomicAdd(&h[key[i]], cnt[i]);
 }
 
-// many distinct values (no block sees a value twice in its share): one
-// global atomic per element, without the LDS table
-__global__ void k_histogram_direct(const uint32_t* __restrict__ v, int64_t n, int32_t* __restrict__ h) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    atomicAdd(&h[v[i]], 1);
-}
-
 __global__ void k_out_j(const int32_t* __restrict__ dR, const int32_t* __restrict__ dS, int64_t n_y,
                         const int32_t* __restrict__ y_base, int n_inst, int64_t* __restrict__ out_j) {
   if (n_inst == 1) {  // grid-stride sum, one atomic per block
@@ -283,14 +276,10 @@ void run_lengths(const int32_t* first, int64_t n_id, int32_t* m, hipStream_t s) 
   JP_LAUNCH_CHECK();
 }
 
-void histogram(const uint32_t* v, int64_t n, int32_t* h, int64_t n_bins, hipStream_t s) {
+void histogram(const uint32_t* v, int64_t n, int32_t* h, hipStream_t s) {
   if (n <= 0) return;
-  if (n_bins * 8 > n) {  // on average fewer than 8 elements per value: the LDS table would mostly miss
-    hipLaunchKernelGGL(k_histogram_direct, dim3(grid(n)), dim3(NT), 0, s, v, n, h);
-  } else {
-    const int blocks = int((n + HG_PER_BLOCK - 1) / HG_PER_BLOCK);
-    hipLaunchKernelGGL(k_histogram, dim3(blocks), dim3(NT), 0, s, v, n, h);
-  }
+  const int blocks = int((n + HG_PER_BLOCK - 1) / HG_PER_BLOCK);
+  hipLaunchKernelGGL(k_histogram, dim3(blocks), dim3(NT), 0, s, v, n, h);
   JP_LAUNCH_CHECK();
 }
 

@@ -313,7 +313,7 @@ void Plan::map(hipStream_t s) {
   dR = A.alloc<int32_t>(NYa, s);
   dS = A.alloc<int32_t>(NYa, s);
   fill_i32(dR, NY, 0, s);
-  histogram(reinterpret_cast<const uint32_t*>(rcol), NRp, dR, NY, s);
+  histogram(reinterpret_cast<const uint32_t*>(rcol), NRp, dR, s);
   run_lengths(sptr, NY, dS, s);
   d_outj = A.alloc<int64_t>(n, s);
   out_j_per_inst(dR, dS, NY, y_base, n, d_outj, s);

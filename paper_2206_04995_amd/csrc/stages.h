@@ -50,8 +50,7 @@ void compact_r(const int32_t* rx, const int32_t* yid, const int32_t* keep, const
                int32_t* out_x, int32_t* out_y, hipStream_t s);
 // m[i] = first[i + 1] - first[i]
 void run_lengths(const int32_t* first, int64_t n_id, int32_t* m, hipStream_t s);
-// h[v[i]] += 1 over i < n (values below n_bins; h zeroed by the caller)
-void histogram(const uint32_t* v, int64_t n, int32_t* h, int64_t n_bins, hipStream_t s);
+void histogram(const uint32_t* v, int64_t n, int32_t* h, hipStream_t s);
 // out_j[inst] += sum over y of dR[y] * dS[y]
 void out_j_per_inst(const int32_t* dR, const int32_t* dS, int64_t n_y, const int32_t* y_base, int n_inst,
                     int64_t* out_j, hipStream_t s);
