@@ -49,7 +49,7 @@ MEASURED_TRAFFIC = {
     # row work, row lists, the light/medium/heavy count kernels
     "graph": {"kernels": "SparseBMM count pass (k_entry_seg ... k_sparse_heavy_count)",
               "fetch_kib": 2756808.5, "write_kib": 372866.3,
-              "sources": {"sparse_bmm.hip": "a7071e86a80e7333cb7c7c4bf363e9576b9471ef95d373dc26577cd658cf6df3",
+              "sources": {"sparse_bmm.hip": "0563945fb2abfe85c00b9423b0102642ee95735227e00dc29ac7eb30a2a15044",
                           "prim.hip": "00bccd1cf8ca5f9a3b869d52992551b66e3be81df0233f26cc46969d5d115881",
                           "stages.h": "db4e2e91fb756daf670618167ba02229b76f8d1a892b53baf9ce2b210137b55b",
                           "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},

@@ -3,11 +3,14 @@
 // in CSR is a collision-free hash table on y (row pointer = bucket header).
 //
 // The paper deduplicates with one z-vector (SPA) stamped with the current x
-// so it never has to be cleared.  Here x rows run in parallel, so every
-// wavefront owns a small LDS hash set sized to the row's work (cleared per
-// row, cost proportional to the row), and rows whose work exceeds it use
-// workgroups with an LDS bitmap over windows of the z range; in count mode
-// the windows of one heavy row run as separate workgroups.
+// so it never has to be cleared.  Here x rows run in parallel, each with its
+// own LDS set, chosen by the row's work w (join rows reaching sparse z): rows
+// are first sorted into lists by w, then light rows (w <= 1024) run one per
+// wavefront with a hash set sized to the row (cleared per row, cost
+// proportional to the row), medium rows (count mode, w <= 8192) one per
+// workgroup with a shared hash set, and heavy rows as workgroups with an LDS
+// bitmap over windows of the z range (in count mode the windows of one row run
+// as separate workgroups).
 //
 // Count mode writes the number of distinct z per row; write mode writes the
 // sorted z ids of each row at off[x] - off[x_lo].
