@@ -69,3 +69,45 @@ def test_graph_and_eager_plans_agree_on_same_input():
             assert g.count() == ref
             gx = _all_pairs(g, ref[0])
             assert np.array_equal(gx[0], ex[0]) and np.array_equal(gx[1], ex[1])
+
+
+def test_graph_replays_batch_of_every_width():
+    """A batch whose count pass holds every kernel class, recorded once and
+    replayed, each replay checked against the oracle with eager work between
+    the replays.  With tau = 4 (z dense iff m_z > 4) the instances cover the
+    quarter-wave, whole-wave and four-word narrow DenseEC kernels and the
+    window kernel (300, 1500, 4040 and 9474 dense z), and SparseBMM rows of
+    every work class (w <= 256, <= 1024, <= 8192 and heavier)."""
+    import torch
+    import paper_2206_04995_amd as P
+
+    specs = [  # (seed, n_r, n_s, dom_x, dom_y, dom_z, zipf_y)
+        (500, 20_000, 30_000, 200, 1_000, 300, 0.0),
+        (501, 23_000, 32_000, 250, 1_200, 1_500, 1.0),
+        (502, 26_000, 34_000, 300, 1_400, 6_000, 0.0),
+        (503, 29_000, 80_000, 350, 1_600, 12_000, 0.0),
+        (504, 32_000, 38_000, 400, 1_800, 40_000, 1.2),
+        (600, 20_000, 40_000, 200, 2_000, 50_000, 0.0),
+        (601, 6_000, 30_000, 600, 3_000, 50_000, 0.0),
+    ]
+    insts = [synth.small_random(sd, nr, ns, dom_x=dx, dom_y=dy, dom_z=dz, offset=-3 * k, zipf_y=zy)
+             for k, (sd, nr, ns, dx, dy, dz, zy) in enumerate(specs)]
+    want = [oracle.count(a.rx, a.ry, a.sz, a.sy)[0] for a in insts]
+    cols = [tuple(dev(c) for c in (a.rx, a.ry, a.sz, a.sy)) for a in insts]
+    opt = P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=4, dense_kernel=P.JP_DENSE_BITS,
+                         flags=P.JP_FLAG_GRAPH)
+    print("[case] graph batch", flush=True)
+    with P.Batch(cols, opt=opt) as b:
+        for rep in range(4):
+            b.execute()
+            got = [int(v) for v in b.counts()]
+            assert got == want, (rep, got, want)
+            junk = torch.arange(1 << 20, device="cuda", dtype=torch.int32) + rep
+            assert int(junk[0].item()) == rep
+            torch.cuda.synchronize()
+        # the lists stay exact after the replays (sampled instances)
+        for i in (0, 2, 5):
+            a = insts[i]
+            ox, oz = oracle.join_project(a.rx, a.ry, a.sz, a.sy)
+            mx, mz = b.materialize(i)
+            assert np.array_equal(mx.cpu().numpy(), ox) and np.array_equal(mz.cpu().numpy(), oz)
