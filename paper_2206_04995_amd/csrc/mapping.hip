@@ -47,25 +47,83 @@ __global__ void k_make_keys_carried(const uint32_t* __restrict__ v, int64_t n, c
   }
 }
 
-__global__ void k_head_flags(const uint32_t* __restrict__ keys, int64_t n, int32_t* __restrict__ flags) {
-  GRID_STRIDE(p, n) { flags[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1 : 0; }
+// Run ids of sorted keys in two passes over the keys (a head starts a run of
+// equal keys): k_run_heads counts the heads of each tile, and k_run_ids scans
+// the head flags of its tile (offset by the scanned tile counts), writes
+// E[i] = heads before i, and for every head its position first[id] and its
+// original value vals[id] = key - koff[inst] + mn[inst].
+constexpr int RUN_NT = 256;
+constexpr int RUN_IT = 8;
+constexpr int RUN_TILE = RUN_NT * RUN_IT;
+
+__global__ void __launch_bounds__(RUN_NT) k_run_heads(const uint32_t* __restrict__ keys, int64_t n,
+                                                      int32_t* __restrict__ sums) {
+  __shared__ int32_t part[RUN_NT / 64];
+  const int64_t b0 = int64_t(blockIdx.x) * RUN_TILE;
+  int c = 0;
+#pragma unroll
+  for (int j = 0; j < RUN_IT; ++j) {
+    const int64_t i = b0 + j * RUN_NT + threadIdx.x;
+    if (i < n) c += (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+  }
+  c = wave_sum(c);
+  if (lane_id() == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < RUN_NT / 64; ++w) t += part[w];
+    sums[blockIdx.x] = t;
+  }
 }
 
-__global__ void k_assign_ids(const uint32_t* __restrict__ keys, int64_t n, const int32_t* __restrict__ E,
-                             const int64_t* __restrict__ koff, const int32_t* __restrict__ mn, int n_inst,
-                             int32_t* __restrict__ first, int32_t* __restrict__ vals) {
+__global__ void __launch_bounds__(RUN_NT) k_run_ids(const uint32_t* __restrict__ keys, int64_t n,
+                                                    const int32_t* __restrict__ offs, const int64_t* __restrict__ koff,
+                                                    const int32_t* __restrict__ mn, int n_inst, int32_t* __restrict__ E,
+                                                    int32_t* __restrict__ first, int32_t* __restrict__ vals) {
+  __shared__ int32_t part[RUN_NT / 64];
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  const int64_t b0 = int64_t(blockIdx.x) * RUN_TILE;  // < n: the grid covers n
+  const int64_t base = b0 + int64_t(threadIdx.x) * RUN_IT;
   SegCursor<int64_t> kcur(koff, n_inst);
-  if (chunk_first() < n) kcur.seed(int64_t(keys[chunk_first()]));
-  CHUNK_LOOP(p, n, JP_CHUNK) {
-    int id = E[p];
-    bool head = E[p + 1] != id;
-    if (head) {
-      uint32_t k = keys[p];
-      const int inst = kcur(int64_t(k));
-      first[id] = int32_t(p);
-      vals[id] = int32_t(int64_t(k) - koff[inst] + int64_t(mn[inst]));
+  kcur.seed(int64_t(keys[b0]));  // the tile's smallest key
+  uint32_t k[RUN_IT];
+  int h[RUN_IT];
+  int loc = 0;
+#pragma unroll
+  for (int j = 0; j < RUN_IT; ++j) {
+    const int64_t i = base + j;
+    k[j] = 0u;
+    h[j] = 0;
+    if (i < n) {
+      k[j] = keys[i];
+      const bool head = i == 0 || (j > 0 ? k[j - 1] : keys[i - 1]) != k[j];
+      h[j] = head ? 1 : 0;
     }
-    if (p == n - 1) first[E[n]] = int32_t(n);
+    loc += h[j];
+  }
+  const int inc = wave_incl_scan(loc);
+  if (lane == 63) part[wid] = inc;
+  __syncthreads();
+  int pre = 0;
+  for (int w = 0; w < wid; ++w) pre += part[w];
+  int run = (offs ? offs[blockIdx.x] : 0) + pre + inc - loc;
+#pragma unroll
+  for (int j = 0; j < RUN_IT; ++j) {
+    const int64_t i = base + j;
+    if (i < n) {
+      E[i] = run;
+      if (h[j]) {
+        const int inst = kcur(int64_t(k[j]));
+        first[run] = int32_t(i);
+        vals[run] = int32_t(int64_t(k[j]) - koff[inst] + int64_t(mn[inst]));
+      }
+    }
+    run += h[j];
+  }
+  // the last thread of the grid holds the total: E[n] and first[total] = n
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == RUN_NT - 1) {
+    E[n] = run;
+    first[run] = int32_t(n);
   }
 }
 
@@ -221,20 +279,30 @@ void make_keys_carried(const uint32_t* v, int64_t n, const int32_t* ebase, int n
   JP_LAUNCH_CHECK();
 }
 
-void head_flags(const uint32_t* keys, int64_t n, int32_t* flags, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_head_flags, dim3(grid(n)), dim3(NT), 0, s, keys, n, flags);
-  JP_LAUNCH_CHECK();
-}
-
-void assign_ids(const uint32_t* keys, int64_t n, const int32_t* E, const int64_t* koff, const int32_t* mn, int n_inst,
-                int32_t* first, int32_t* vals, hipStream_t s) {
+void run_ids(const uint32_t* keys, int64_t n, const int64_t* koff, const int32_t* mn, int n_inst, int32_t* E,
+             int32_t* first, int32_t* vals, hipStream_t s, Arena& a) {
   if (n <= 0) {
+    fill_i32(E, 1, 0, s);
     fill_i32(first, 1, 0, s);
     return;
   }
-  hipLaunchKernelGGL(k_assign_ids, dim3(chunk_grid(n)), dim3(NT), 0, s, keys, n, E, koff, mn, n_inst, first, vals);
+  const int64_t nb = (n + RUN_TILE - 1) / RUN_TILE;
+  int32_t* offs = nullptr;
+  int32_t* sums = nullptr;
+  if (nb > 1) {
+    sums = a.alloc<int32_t>(nb, s);
+    offs = a.alloc<int32_t>(nb + 1, s);
+    hipLaunchKernelGGL(k_run_heads, dim3(int(nb)), dim3(RUN_NT), 0, s, keys, n, sums);
+    JP_LAUNCH_CHECK();
+    scan_excl_i32(sums, offs, nb, s, a);
+  }
+  hipLaunchKernelGGL(k_run_ids, dim3(int(nb)), dim3(RUN_NT), 0, s, keys, n, (const int32_t*)offs, koff, mn, n_inst, E,
+                     first, vals);
   JP_LAUNCH_CHECK();
+  if (nb > 1) {
+    a.give_back(offs, s);
+    a.give_back(sums, s);
+  }
 }
 
 void gather_bases(const int32_t* E, const int32_t* ebase, int n_inst, int32_t* out, hipStream_t s) {

@@ -220,12 +220,10 @@ void Plan::map(hipStream_t s) {
   const SortSegments sseg_z{n, d_sbase, dkz, h_sbase};
   bool alt = radix_sort_pairs(k1, v1, k2, v2, NS, n > 1 ? local_bits(koff_z) : zbits, s, T, &sseg_z);
   uint32_t *zk = alt ? k2 : k1, *zp = alt ? v2 : v1;
-  head_flags(zk, NS, flags, s);
   int32_t* Ez = T.alloc<int32_t>(NS + 1, s);
-  scan_excl_i32(flags, Ez, NS, s, T);
   zfirst = A.alloc<int32_t>(NS + 1, s);
   vals_z = A.alloc<int32_t>(NSa, s);
-  assign_ids(zk, NS, Ez, dkz, zmin, n, zfirst, vals_z, s);
+  run_ids(zk, NS, dkz, zmin, n, Ez, zfirst, vals_z, s, T);
   z_base = A.alloc<int32_t>(n + 1, s);
   gather_bases(Ez, d_sbase, n, z_base, s);
 
@@ -236,12 +234,10 @@ void Plan::map(hipStream_t s) {
   const SortSegments sseg_y{n, d_sbase, dky, h_sbase};
   bool alt2 = radix_sort_pairs(yk, yp, ok, op, NS, n > 1 ? local_bits(koff_y) : ybits, s, T, &sseg_y);
   uint32_t *syk = alt2 ? ok : yk, *syp = alt2 ? op : yp;
-  head_flags(syk, NS, flags, s);
   Ey = A.alloc<int32_t>(NS + 1, s);
-  scan_excl_i32(flags, Ey, NS, s, T);
   sptr = A.alloc<int32_t>(NS + 1, s);
   vals_y = A.alloc<int32_t>(NSa, s);
-  assign_ids(syk, NS, Ey, dky, ymin, n, sptr, vals_y, s);
+  run_ids(syk, NS, dky, ymin, n, Ey, sptr, vals_y, s, T);
   y_base = A.alloc<int32_t>(n + 1, s);
   gather_bases(Ey, d_sbase, n, y_base, s);
   scol = A.alloc<int32_t>(NSa, s);
@@ -295,12 +291,10 @@ void Plan::map(hipStream_t s) {
   const SortSegments sseg_x{n, d_rpbase, dkx, h_rpbase};
   bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, n > 1 ? local_bits(koff_x) : xbits, s, T, &sseg_x);
   uint32_t *sxk = alt3 ? xk2 : xk, *sxp = alt3 ? xp2 : rpy;
-  head_flags(sxk, NRp, flags, s);
   int32_t* Ex = T.alloc<int32_t>(NRp + 1, s);
-  scan_excl_i32(flags, Ex, NRp, s, T);
   rptr = A.alloc<int32_t>(NRp + 1, s);
   vals_x = A.alloc<int32_t>(NRpa, s);
-  assign_ids(sxk, NRp, Ex, dkx, xmin, n, rptr, vals_x, s);
+  run_ids(sxk, NRp, dkx, xmin, n, Ex, rptr, vals_x, s, T);
   x_base = A.alloc<int32_t>(n + 1, s);
   gather_bases(Ex, d_rpbase, n, x_base, s);
   rcol = A.alloc<int32_t>(NRpa, s);

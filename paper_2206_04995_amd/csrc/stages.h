@@ -30,11 +30,11 @@ void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, co
 // keeps its instance); payload[p] = E[p + 1] - 1 (the id of sorted position p)
 void make_keys_carried(const uint32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff,
                        const int32_t* mn, const int32_t* E, uint32_t* keys, uint32_t* payload, hipStream_t s);
-// flags[p] = 1 if sorted position p starts a run of equal keys
-void head_flags(const uint32_t* keys, int64_t n, int32_t* flags, hipStream_t s);
-// for each run head p: first[id] = p, vals[id] = original value of the key; first[n_id] = n
-void assign_ids(const uint32_t* keys, int64_t n, const int32_t* E, const int64_t* koff, const int32_t* mn,
-                int n_inst, int32_t* first, int32_t* vals, hipStream_t s);
+// ids of the runs of equal sorted keys: E[p] = runs started before position p
+// (E[n] = number of runs), and for each run id: first[id] = its first position,
+// vals[id] = the original value of its key; first[E[n]] = n
+void run_ids(const uint32_t* keys, int64_t n, const int64_t* koff, const int32_t* mn, int n_inst, int32_t* E,
+             int32_t* first, int32_t* vals, hipStream_t s, Arena& a);
 // out[i] = E[ebase[i]] for i in [0, n_inst]
 void gather_bases(const int32_t* E, const int32_t* ebase, int n_inst, int32_t* out, hipStream_t s);
 // semi-join of R on S.y: keep[g] = 1 and yid[g] = id iff ry[g] occurs among the y values of its instance
