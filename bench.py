@@ -339,8 +339,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path is single-GPU; "
-              f"see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the path runs on a single GPU "
+              f"(rows shard by x across GPUs with S broadcast, which this benchmark does not exercise)",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batched":
