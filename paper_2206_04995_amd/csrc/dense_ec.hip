@@ -450,7 +450,7 @@ __global__ void k_work_stats(RowCtx c, int64_t x_lo, int64_t x_hi, const int64_t
     if (x < x_hi) {
       int inst = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, int32_t(x));
       int zd = c.zd_base[inst + 1] - c.zd_base[inst];
-      int64_t rw = zd > 0 ? int64_t((zd + DW_BITS - 1) / DW_BITS) * DW_WORDS : 0;
+      int64_t rw = int64_t((zd + 31) / 32);  // words of the dense range (window padding excluded)
       a1 += rw;
       a3 += w[x - x_lo];
     }
@@ -465,7 +465,7 @@ __global__ void k_work_stats(RowCtx c, int64_t x_lo, int64_t x_hi, const int64_t
         const int y = c.rcol[j];
         const int inst = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.y_base, c.n_inst, y);
         const int zd = c.zd_base[inst + 1] - c.zd_base[inst];
-        a0 += int64_t((zd + DW_BITS - 1) / DW_BITS) * DW_WORDS;
+        a0 += int64_t((zd + 31) / 32);
       } else if (code <= -2) {
         a2 += c.cptr[-2 - code + 1] - c.cptr[-2 - code];
       }
@@ -491,7 +491,7 @@ __global__ void k_work_rows(RowCtx c, const int32_t* __restrict__ rows, int64_t 
     const int32_t x = rows[i];
     const int inst = c.n_inst == 1 ? 0 : find_inst<int32_t>(c.x_base, c.n_inst, x);
     const int zd = c.zd_base[inst + 1] - c.zd_base[inst];
-    const int64_t words = zd > 0 ? int64_t((zd + DW_BITS - 1) / DW_BITS) * DW_WORDS : 0;
+    const int64_t words = int64_t((zd + 31) / 32);  // window padding excluded
     a1 += words;
     if (w) a3 += w[x];
     for (int j = c.rptr[x]; j < c.rptr[x + 1]; ++j) {
