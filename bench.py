@@ -164,7 +164,8 @@ def batched(args):
             P.jp_batch_destroy(b)
 
     res = {}
-    for name, fn in (("plain", plain), ("batched", batch)):
+    paths = (("batched", batch),) if args.batched_only else (("plain", plain), ("batched", batch))
+    for name, fn in paths:
         for _ in range(args.warmup):
             fn()
         torch.cuda.synchronize()
@@ -174,8 +175,9 @@ def batched(args):
         torch.cuda.synchronize()
         res[name] = ((time.perf_counter() - t0) * 1000.0 / args.steps, counts)
         print(f"[bench] {name}: {res[name][0]:.2f} ms per pass", file=sys.stderr, flush=True)
-    if not np.array_equal(res["plain"][1], res["batched"][1]):
+    if "plain" in res and not np.array_equal(res["plain"][1], res["batched"][1]):
         raise SystemExit("batched and plain per-instance counts differ")
+    plain_ms = res["plain"][0] if "plain" in res else None
     pairs = int(res["batched"][1].sum())
     ms = res["batched"][0]
     out = {
@@ -194,8 +196,8 @@ def batched(args):
         "config": {"workload": "batched instances", "instances": args.instances, "tuned_signatures": len(tuned),
                    "tuples_per_side": f"log-uniform [1e3, {args.batch_hi:.0e}]", "key_domain": "10% of tuples",
                    "y": "uniform (even) / Zipf 1.2 (odd)", "pairs": pairs, "tuples": n_tuples,
-                   "plain_ms": res["plain"][0], "plain_pairs_per_s": pairs / (res["plain"][0] * 1e-3),
-                   "batched_over_plain": res["plain"][0] / ms},
+                   "plain_ms": plain_ms, "plain_pairs_per_s": None if plain_ms is None else pairs / (plain_ms * 1e-3),
+                   "batched_over_plain": None if plain_ms is None else plain_ms / ms},
     }
     print(json.dumps(out), flush=True)
 
@@ -334,6 +336,8 @@ def main():
                     help="DenseEC windows per workgroup (default: tuned or automatic; counter runs pin the tuned value)")
     ap.add_argument("--k-hot-max", type=int, default=None, help="cap on hot keys per instance (default: tuned or automatic)")
     ap.add_argument("--tune-sample", type=int, default=16, help="batched workload: instances the tuner times")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="batched workload: skip the plain one-plan-per-instance loop (for kernel traces)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain elementwise copy over this many MiB (a reference for HBM counters)")
     args = ap.parse_args()
