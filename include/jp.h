@@ -198,10 +198,13 @@ void jp_batch_destroy(jp_batch* b);
 /* The dense/sparse threshold of Sec. 2.6 is tau = (c_de / c_sp) |X| |S| / OUT_J;
  * jp_tune times the plan + count pass of one query (device columns as for
  * jp_plan_create) for a set of thresholds (all dense, all sparse, the model's
- * tau scaled by 1/16 .. 16, quantiles of m_z), checks that all give the same
- * counts (the partition is intersection-free, Sec. 2.3), then, at the fastest
+ * tau scaled by 1/16 .. 16, quantiles of m_z) in increasing order, skipping
+ * the higher ones once a threshold above the best is 3x slower than it, checks
+ * that all give the same counts (the partition is intersection-free, Sec.
+ * 2.3), then, at the fastest
  * threshold, searches the DenseEC count kernel (bit path or INT8 MFMA), the
- * hot-key cap and the windows per workgroup one after the other.  The cost
+ * hot-key cap and the windows per workgroup one after the other (a setting
+ * replaces the current best only when at least 2% faster).  The cost
  * ratio and these choices are stored under the query's shape signature (log2
  * buckets of |X|, |Z|, |S| and OUT_J / |S|); later plans and batch instances
  * of that signature use them for every option left automatic (tau_mode
