@@ -305,6 +305,7 @@ __global__ void __launch_bounds__(MM_NT) k_seg_minmax(const int32_t* __restrict_
   const int seg1 = wave_find_inst<int32_t>(base, n_seg, int32_t(c1 - 1));
   int32_t cmn = INT_MAX, cmx = INT_MIN;
   if (seg0 == seg1) {
+#pragma unroll 8  // independent loads in flight: one at a time leaves each thread waiting on memory
     for (int64_t i = c0 + threadIdx.x; i < c1; i += MM_NT) {
       const int32_t x = v[i];
       cmn = x < cmn ? x : cmn;
