@@ -41,19 +41,19 @@ FETCH_FACTOR = 1048576 / 524308.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
     # two count launches per step: rows without and with the pivot key (2 windows per workgroup, as tuned)
-    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 664304.8 + 274578.1, "write_kib": 80210.6 + 39764.1,
+    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 663647.8 + 275965.1, "write_kib": 80210.6 + 39764.1,
                "sources": {"dense_ec.hip": "9abaf47b14713dc235ed9bb4d25b280a95c0f2e143ff38b509303eb9123bc0ad",
                            "stages.h": "19c030a1670b519a14c35bf3e9f052e634aca0be7ac1bd4d72947b679aac04fc",
                            "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
     # the whole timed SparseBMM count region: per-entry segments and their scan,
     # row work, row lists, the light/medium/heavy count kernels
     "graph": {"kernels": "SparseBMM count pass (k_entry_seg ... k_sparse_heavy_count)",
-              "fetch_kib": 2756595.0, "write_kib": 372846.6,
+              "fetch_kib": 2757289.5, "write_kib": 372779.5,
               "sources": {"sparse_bmm.hip": "0563945fb2abfe85c00b9423b0102642ee95735227e00dc29ac7eb30a2a15044",
-                          "prim.hip": "00bccd1cf8ca5f9a3b869d52992551b66e3be81df0233f26cc46969d5d115881",
+                          "prim.hip": "357a597bf671428e992d90c55058e3ad4a1e381eb3669035c44e9d121fbb67c6",
                           "stages.h": "19c030a1670b519a14c35bf3e9f052e634aca0be7ac1bd4d72947b679aac04fc",
                           "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
-    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 809038.0, "write_kib": 12343.8,
+    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 809038.4, "write_kib": 12343.8,
               "sources": {"dense_mfma.hip": "c4103f00b68fb47500e9e25f66d0e6c7b0317e25200728f600fa7ef5ed3c3ed4",
                           "stages.h": "19c030a1670b519a14c35bf3e9f052e634aca0be7ac1bd4d72947b679aac04fc",
                           "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
