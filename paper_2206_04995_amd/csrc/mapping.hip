@@ -21,16 +21,42 @@ inline int grid(int64_t n, int cap = 1 << 20) {
 #define GRID_STRIDE(i, n) \
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < (n); i += int64_t(gridDim.x) * blockDim.x)
 
+// k_make_keys takes four elements per thread and step (positions i0 +
+// u * blockDim.x, u < 4, increasing) and issues their loads before using them:
+// one load at a time, consumed at once, would leave each thread waiting on
+// memory.  (The same form made the carried-key and direct semi-join kernels
+// slower, so they keep one element per step.)
+constexpr int UNR = 4;
+
+__device__ __forceinline__ int64_t chunk_end(int64_t n) {
+  const int64_t c1 = chunk_first() + JP_CHUNK;
+  return c1 < n ? c1 : n;
+}
+
 __global__ void k_make_keys(const int32_t* __restrict__ v, int64_t n, const int32_t* __restrict__ ebase,
                             int n_inst, const int64_t* __restrict__ koff, const int32_t* __restrict__ mn,
                             uint32_t* __restrict__ keys, uint32_t* __restrict__ payload,
                             const int32_t* __restrict__ pay_src) {
   SegCursor<int32_t> cur(ebase, n_inst);
   cur.seed(int32_t(chunk_first()));
-  CHUNK_LOOP(i, n, JP_CHUNK) {
-    const int inst = cur(int32_t(i));
-    keys[i] = uint32_t(koff[inst] + (int64_t(v[i]) - int64_t(mn[inst])));
-    if (payload) payload[i] = pay_src ? uint32_t(pay_src[i]) : uint32_t(i);
+  const int64_t c1 = chunk_end(n);
+  const int64_t step = blockDim.x;
+  for (int64_t i0 = chunk_first() + threadIdx.x; i0 < c1; i0 += UNR * step) {
+    int32_t vv[UNR], pp[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int64_t i = i0 + u * step;
+      vv[u] = i < c1 ? v[i] : 0;
+      pp[u] = (pay_src && i < c1) ? pay_src[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int64_t i = i0 + u * step;
+      if (i >= c1) break;
+      const int inst = cur(int32_t(i));
+      keys[i] = uint32_t(koff[inst] + (int64_t(vv[u]) - int64_t(mn[inst])));
+      if (payload) payload[i] = pay_src ? uint32_t(pp[u]) : uint32_t(i);
+    }
   }
 }
 

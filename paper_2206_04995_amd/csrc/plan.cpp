@@ -85,15 +85,33 @@ __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int3
                               int64_t n, int32_t* __restrict__ dst) {
   SegCursor<int32_t> cur(base, n_inst);
   cur.seed(int32_t(chunk_first()));
+  const int64_t c1 = chunk_first() + JP_CHUNK < n ? chunk_first() + JP_CHUNK : n;
+  const int64_t step = blockDim.x;
   const int32_t* col = nullptr;
   int last = -1;
-  CHUNK_LOOP(g, n, JP_CHUNK) {
-    const int inst = cur(int32_t(g));
-    if (inst != last) {
-      last = inst;
-      col = src[inst];
+  // four elements per thread and step: their source addresses first, then the
+  // four loads in flight together, then the stores
+  for (int64_t g0 = chunk_first() + threadIdx.x; g0 < c1; g0 += 4 * step) {
+    const int32_t* at[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t g = g0 + u * step;
+      at[u] = nullptr;
+      if (g < c1) {
+        const int inst = cur(int32_t(g));
+        if (inst != last) {
+          last = inst;
+          col = src[inst];
+        }
+        at[u] = col + (g - cur.lo);
+      }
     }
-    dst[g] = col[g - cur.lo];
+    int32_t vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) vv[u] = at[u] ? *at[u] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (g0 + u * step < c1) dst[g0 + u * step] = vv[u];
   }
 }
 
