@@ -8,6 +8,9 @@ Contents
 * ``join_project`` / ``count`` / ``rows`` / ``out_j``: the C++ hash-join plus
   hash-set deduplication in ``jp_oracle.cpp`` (the paper's classical solution,
   Sec. 1.1, which reaches the plain definition of Eq. 1).
+* ``row_counts``: per-row counts and digests from the matrix form of Sec. 1.1
+  (row x of the Boolean product as a bit vector over z, one x at a time), for
+  results too large to hold as a set or a list.
 * ``brute_force``: nested loops over R x S for tiny inputs (definition of
   Eq. 1 written out directly), used to pin the C++ oracle.
 * ``split_by_z``: the intersection-free partition of a result by the dense z
@@ -58,6 +61,8 @@ def _load():
         lib.jpo_list.restype = ctypes.c_int64
         lib.jpo_rows.argtypes = base + [i32p, ctypes.c_int64, ctypes.c_int, i64p, i32p, ctypes.c_int64]
         lib.jpo_rows.restype = ctypes.c_int64
+        lib.jpo_row_counts.argtypes = base + [ctypes.c_int, i32p, i64p, u64p, i64p, u64p]
+        lib.jpo_row_counts.restype = ctypes.c_int64
         lib.jpo_digest_pairs.argtypes = [i32p, i32p, ctypes.c_int64]
         lib.jpo_digest_pairs.restype = ctypes.c_uint64
         _lib = lib
@@ -129,6 +134,28 @@ def rows(rx, ry, sz, sy, xs: Sequence[int], threads: Optional[int] = None) -> Li
     return res
 
 
+def row_counts(rx, ry, sz, sy, threads: Optional[int] = None):
+    """Per-row counts and digests by the matrix form (bit vector over z per x row).
+
+    Returns (xs, counts, digests, total, digest): the distinct x values of R
+    ascending, each row's number of pairs and digest (uint64), and the totals
+    over the whole result.  Memory stays at |Z| bits per thread, so it scales
+    to results far too large to list."""
+    rx, ry, sz, sy = _cols(rx, ry, sz, sy)
+    n = max(1, rx.size)
+    xs = np.empty(n, dtype=np.int32)
+    cnt = np.empty(n, dtype=np.int64)
+    dig = np.empty(n, dtype=np.uint64)
+    tot = ctypes.c_int64(0)
+    d = ctypes.c_uint64(0)
+    nx = _load().jpo_row_counts(_p32(rx), _p32(ry), rx.size, _p32(sz), _p32(sy), sz.size,
+                                threads or default_threads(), _p32(xs),
+                                cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                dig.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                ctypes.byref(tot), ctypes.byref(d))
+    return xs[:nx].copy(), cnt[:nx].copy(), dig[:nx].copy(), int(tot.value), int(d.value)
+
+
 def digest_pairs(xs: np.ndarray, zs: np.ndarray) -> int:
     xs = np.ascontiguousarray(np.asarray(xs, dtype=np.int32))
     zs = np.ascontiguousarray(np.asarray(zs, dtype=np.int32))
@@ -157,13 +184,3 @@ def split_by_z(xs: np.ndarray, zs: np.ndarray, dense_z_values: np.ndarray):
     ((dense_x, dense_z), (sparse_x, sparse_z)), each in input order."""
     mask = np.isin(zs, np.asarray(dense_z_values, dtype=np.int32))
     return (xs[mask], zs[mask]), (xs[~mask], zs[~mask])
-
-
-def degree_stats(rx, ry, sz, sy):
-    """Per-value degrees the paper's partition and cost functions use (Sec. 2.6):
-    m_x (R tuples per x), m_z (S tuples per z), d_R(y) and d_S(y) (tuples per
-    join key on each side), with repeats counted."""
-    def hist(v):
-        u, c = np.unique(np.asarray(v, dtype=np.int32), return_counts=True)
-        return dict(zip(u.tolist(), c.tolist()))
-    return {"m_x": hist(rx), "m_z": hist(sz), "d_R": hist(ry), "d_S": hist(sy)}

@@ -21,6 +21,12 @@
 //
 // Threads split R by ranges of x value; ranges are disjoint, so their result
 // sets are disjoint and concatenate in order.
+//
+// jpo_row_counts reaches the same set through the matrix form of Sec. 1.1
+// ((x, z) is in the result iff row x of the Boolean product R S has a 1 at z),
+// one x row at a time as a bit vector over the distinct z values.  It keeps
+// memory at |Z| bits per thread, so it counts and digests results that are
+// far too large to hold in a hash set.
 
 #include <algorithm>
 #include <atomic>
@@ -216,6 +222,83 @@ int64_t jpo_rows(const int32_t* rx, const int32_t* ry, int64_t nr, const int32_t
     }
   }
   return pos;
+}
+
+// Per-row counts and digests by the matrix form of the definition (Sec. 1.1):
+// row x of the Boolean product C = R S is the OR, over the join keys y of x,
+// of the 0/1 rows S[y] over the distinct z values.  Each x row is built as a
+// bit vector over the sorted distinct z values, one x at a time, so memory
+// stays at |Z| bits per thread whatever the result size; a pair is counted
+// (and its mix64 added to the row's digest) when its bit goes from 0 to 1.
+// Rows are the distinct x values of R in ascending order, including those
+// with no match (count 0).  xs_out, cnt_out and dig_out must hold nr entries
+// (nullable); *digest receives the digest of the whole result.  Returns the
+// number of distinct x values; *total receives the number of pairs.
+int64_t jpo_row_counts(const int32_t* rx, const int32_t* ry, int64_t nr, const int32_t* sz,
+                       const int32_t* sy, int64_t ns, int nthreads, int32_t* xs_out, int64_t* cnt_out,
+                       uint64_t* dig_out, int64_t* total, uint64_t* digest) {
+  // distinct z values, ascending, and each S tuple's index among them
+  std::vector<int32_t> zs(sz, sz + ns);
+  std::sort(zs.begin(), zs.end());
+  zs.erase(std::unique(zs.begin(), zs.end()), zs.end());
+  std::unordered_map<int32_t, std::vector<int32_t>> h;  // y -> z indices (S is the build side)
+  h.reserve(size_t(ns / 4 + 16));
+  for (int64_t j = 0; j < ns; ++j) {
+    const int32_t zi = int32_t(std::lower_bound(zs.begin(), zs.end(), sz[j]) - zs.begin());
+    h[sy[j]].push_back(zi);
+  }
+  // R grouped by x (ascending)
+  std::vector<std::pair<int32_t, int32_t>> r(static_cast<size_t>(nr));
+  for (int64_t i = 0; i < nr; ++i) r[size_t(i)] = {rx[i], ry[i]};
+  std::sort(r.begin(), r.end());
+  std::vector<int64_t> start;  // first tuple of each distinct x
+  for (int64_t i = 0; i < nr; ++i)
+    if (i == 0 || r[size_t(i)].first != r[size_t(i - 1)].first) start.push_back(i);
+  const int64_t nx = int64_t(start.size());
+  start.push_back(nr);
+  std::vector<int64_t> cnt(size_t(nx), 0);
+  std::vector<uint64_t> dig(size_t(nx), 0);
+  const int64_t words = int64_t(zs.size() / 64 + 1);
+  const int64_t per_task = 64;
+  const int n_tasks = int((nx + per_task - 1) / per_task);
+  parallel_for(n_tasks, nthreads, [&](int t) {
+    std::vector<uint64_t> bits(size_t(words), 0);
+    std::vector<int64_t> touched;
+    for (int64_t k = int64_t(t) * per_task; k < std::min(nx, int64_t(t + 1) * per_task); ++k) {
+      const int32_t x = r[size_t(start[size_t(k)])].first;
+      int64_t c = 0;
+      uint64_t d = 0;
+      for (int64_t i = start[size_t(k)]; i < start[size_t(k + 1)]; ++i) {
+        auto it = h.find(r[size_t(i)].second);
+        if (it == h.end()) continue;
+        for (int32_t zi : it->second) {
+          uint64_t& w = bits[size_t(zi >> 6)];
+          const uint64_t b = uint64_t(1) << (zi & 63);
+          if (w & b) continue;
+          if (w == 0) touched.push_back(zi >> 6);
+          w |= b;
+          ++c;
+          d += mix64(pair_key(x, zs[size_t(zi)]));
+        }
+      }
+      for (int64_t wi : touched) bits[size_t(wi)] = 0;
+      touched.clear();
+      cnt[size_t(k)] = c;
+      dig[size_t(k)] = d;
+    }
+  });
+  int64_t tc = 0;
+  uint64_t td = 0;
+  for (int64_t k = 0; k < nx; ++k) {
+    if (xs_out) xs_out[k] = r[size_t(start[size_t(k)])].first;
+    if (cnt_out) cnt_out[k] = cnt[size_t(k)];
+    if (dig_out) dig_out[k] = dig[size_t(k)];
+    tc += cnt[size_t(k)];
+    td += dig[size_t(k)];
+  }
+  if (total) *total = tc;
+  if (digest) *digest = td;
+  return nx;
 }
 
 // Digest of an explicit pair list (used to digest a listed result).

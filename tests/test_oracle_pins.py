@@ -45,6 +45,25 @@ def test_hand_examples(oracle_mod, case):
     assert c == len(expect)
     assert oracle_mod.out_j(rx, ry, sz, sy) == case["out_j"]
     assert d == oracle_mod.digest_pairs(ox, oz)
+    _check_row_counts(oracle_mod, rx, ry, sz, sy, expect)
+
+
+def _check_row_counts(oracle_mod, rx, ry, sz, sy, expect, threads=None):
+    """row_counts against an explicit pair list: one row per distinct x of R
+    (ascending), its count and digest, and the totals."""
+    xs, cnt, dig, total, digest = oracle_mod.row_counts(rx, ry, sz, sy, threads=threads)
+    assert xs.tolist() == sorted(set(np.asarray(rx).tolist()))
+    by_x = {}
+    for x, z in expect:
+        by_x.setdefault(x, []).append(z)
+    for x, c, d in zip(xs.tolist(), cnt.tolist(), dig.tolist()):
+        zs = by_x.get(x, [])
+        assert c == len(zs)
+        assert d == oracle_mod.digest_pairs(np.full(len(zs), x, np.int32), np.array(zs, np.int32))
+    assert total == len(expect)
+    ex = np.array([p[0] for p in expect], np.int32)
+    ez = np.array([p[1] for p in expect], np.int32)
+    assert digest == oracle_mod.digest_pairs(ex, ez)
 
 
 def test_splitmix64_vector(oracle_mod):
@@ -79,6 +98,7 @@ def test_oracle_equals_brute_force(oracle_mod, r, s, self_join):
     assert list(zip(ox.tolist(), oz.tolist())) == expect
     c, d = oracle_mod.count(rx, ry, sz, sy, threads=2)
     assert c == len(expect)
+    _check_row_counts(oracle_mod, rx, ry, sz, sy, expect, threads=3)
     bag = sum(1 for _, y in r for _, y2 in s if y == y2)
     assert oracle_mod.out_j(rx, ry, sz, sy) == bag
 
@@ -105,6 +125,10 @@ def test_oracle_matches_matrix_form(oracle_mod, seed):
     mx, mz = _matrix_form(inst.rx, inst.ry, inst.sz, inst.sy)
     ox, oz = oracle_mod.join_project(inst.rx, inst.ry, inst.sz, inst.sy)
     assert np.array_equal(ox, mx) and np.array_equal(oz, mz)
+    xs, cnt, _, total, digest = oracle_mod.row_counts(inst.rx, inst.ry, inst.sz, inst.sy, threads=4)
+    assert total == mx.size and digest == oracle_mod.digest_pairs(mx, mz)
+    u, c = np.unique(mx, return_counts=True)
+    assert np.array_equal(cnt[np.isin(xs, u)], c) and not cnt[~np.isin(xs, u)].any()
 
 
 def test_closed_forms(oracle_mod):
@@ -118,6 +142,8 @@ def test_closed_forms(oracle_mod):
     c, _ = oracle_mod.count(rx, ry, sz, sy)
     assert c == X.size * Z.size
     assert oracle_mod.out_j(rx, ry, sz, sy) == X.size * Y.size * Z.size
+    xs, cnt, _, total, _ = oracle_mod.row_counts(rx, ry, sz, sy)
+    assert np.array_equal(xs, X) and (cnt == Z.size).all() and total == X.size * Z.size
     # one shared key: |X_y| * |Z_y|
     rx = rng.integers(0, 50, 300).astype(np.int32)
     ry = np.where(rng.random(300) < 0.3, 7, rng.integers(10, 20, 300)).astype(np.int32)
@@ -125,9 +151,17 @@ def test_closed_forms(oracle_mod):
     sy = np.where(rng.random(200) < 0.4, 7, rng.integers(30, 40, 200)).astype(np.int32)
     c, _ = oracle_mod.count(rx, ry, sz, sy)
     assert c == np.unique(rx[ry == 7]).size * np.unique(sz[sy == 7]).size
+    assert oracle_mod.row_counts(rx, ry, sz, sy)[3] == c
     # disjoint key domains: empty
     c, _ = oracle_mod.count(rx, ry + 1000, sz, sy)
     assert c == 0
+    xs, cnt, dig, total, digest = oracle_mod.row_counts(rx, ry + 1000, sz, sy)
+    assert total == 0 and digest == 0 and not cnt.any() and not dig.any()
+    # empty sides
+    e = np.zeros(0, np.int32)
+    assert oracle_mod.row_counts(e, e, sz, sy)[0].size == 0
+    xs, cnt, _, total, _ = oracle_mod.row_counts(rx, ry, e, e)
+    assert total == 0 and xs.size == np.unique(rx).size
 
 
 @pytest.mark.parametrize("seed", range(3))
