@@ -76,7 +76,8 @@ typedef struct {
   int64_t dense_threshold;       /* JP_TAU_FIXED: z dense iff m_z > value (-1: all dense, INT64_MAX: none) */
   int32_t k_hot_max;             /* cap on hot join keys per instance in DenseEC (0 = 256; max 1024) */
   int32_t flags;                 /* JP_FLAG_* bits; others must be 0 */
-  int64_t workspace_limit_bytes; /* 0 = no limit; exceeding it returns JP_ENOMEM */
+  int64_t workspace_limit_bytes; /* 0 = no limit; else the most device memory the plan or batch may hold
+                                    at once, temporaries included: exceeding it returns JP_ENOMEM */
   int32_t window_group;          /* z windows per workgroup of the bit-path DenseEC count (0 = automatic, max 64) */
   int32_t reserved;              /* must be 0 */
 } jp_options;
@@ -96,6 +97,8 @@ typedef struct {
   int64_t dense_row_words;    /* sum over x of the words of its dense z range (one popcount each) */
   int64_t dense_cold_entries; /* cold dense S entries scattered, summed over x */
   int64_t dense_mfma_ops;     /* 2 * |X| * (dense keys) * |Z_dense| when the INT8-MFMA product ran, else 0 */
+  float map_ms;               /* plan: input gather and mapping to ids with the CSR builds (Sec. 2.2) */
+  float partition_ms;         /* plan: partition by z and the DenseEC tables (Sec. 2.3) */
 } jp_timings;
 
 typedef struct {
@@ -109,6 +112,8 @@ typedef struct {
   int64_t pivot_cover;     /* dense z in the S row of the pivot key whose rows DenseEC counts outside
                               that row (0: no pivot split for this instance) */
   int64_t dense_mfma;      /* 1 if the dense part is counted by the INT8-MFMA product, else 0 */
+  int64_t peak_bytes;      /* most device memory the object held at once so far, temporaries included
+                              (all instances of a batch; the quantity workspace_limit_bytes bounds) */
 } jp_stats;
 
 typedef struct jp_plan jp_plan;
@@ -153,8 +158,9 @@ jp_status jp_dense_z(jp_plan* p, int32_t* z_values, hipStream_t stream);
 
 jp_status jp_plan_stats(const jp_plan* p, jp_stats* s);
 
-/* Kernel times of the last jp_execute into the *_ms fields (others zeroed);
- * JP_ESTATE unless the plan was created with JP_FLAG_TIMING and executed.  Syncs. */
+/* Kernel times of the last jp_execute, and of the mapping and partition
+ * stages of the plan, into the *_ms fields (others zeroed); JP_ESTATE unless
+ * the plan was created with JP_FLAG_TIMING and executed.  Syncs. */
 jp_status jp_plan_timings(jp_plan* p, jp_timings* t, hipStream_t stream);
 
 /* Algorithmic work counters of the execute kernels into the integer fields of
@@ -191,6 +197,9 @@ jp_status jp_batch_materialize(jp_batch* b, int32_t inst, jp_part part, int64_t 
                                int64_t max_pairs, int32_t* out_x, int32_t* out_z,
                                int64_t* n_written, hipStream_t stream);
 jp_status jp_batch_stats(const jp_batch* b, int32_t inst, jp_stats* s);
+/* As jp_plan_timings and jp_plan_work, over all instances of the batch. */
+jp_status jp_batch_timings(jp_batch* b, jp_timings* t, hipStream_t stream);
+jp_status jp_batch_work(jp_batch* b, jp_timings* t, hipStream_t stream);
 void jp_batch_destroy(jp_batch* b);
 
 /* ------------------------------------------------------------ autotuner --- */
@@ -234,31 +243,64 @@ jp_status jp_tune_clear(void); /* forgets every stored ratio */
  * estimated device footprint fits an HBM budget, plans every admitted group
  * as one batch (continuous batching: queries that arrive while a batch runs
  * join the next one) and overlaps the planning of one batch with the
- * execution of the previous one on a second stream.  Results are counts. */
+ * execution of the previous one on a second stream.  The paper runs one query
+ * at a time (Sec. 5); the server only groups independent queries, so each
+ * result is exactly that of the query alone.
+ *
+ * Admission.  A query's estimated footprint is a fixed number of bytes per
+ * input tuple (its plan, temporaries included) plus, with JP_SERVER_DIGEST or
+ * JP_SERVER_KEEP, one chunk of output of min(n_r * n_s, chunk_pairs) pairs.
+ * A group is admitted while the sum of the estimates of everything in flight
+ * or kept stays within hbm_budget_bytes and each side of the group holds at
+ * most 2^31 - 1 tuples; the group's plan is then limited to its summed
+ * estimate (every device byte it holds at once), so the server never holds
+ * more than the budget (the caching allocator may keep freed blocks).  A
+ * query whose estimate exceeds the budget fails with JP_ENOMEM.  A group
+ * whose plan fails is split in halves and planned again, so a failure stays
+ * with the query that causes it: a query above its estimate is retried once
+ * alone with all the budget left, and fails with JP_ENOMEM if that is no
+ * more.  Results: counts, the order-independent digest (JP_SERVER_DIGEST:
+ * the wrapping sum of SplitMix64(key(x, z)) over the pairs, key = the two
+ * sign-flipped values with x in the high word, computed on the device from
+ * materialised chunks) and, with JP_SERVER_KEEP, the pairs themselves until
+ * the query is released. */
 typedef struct jp_server jp_server;
+
+#define JP_SERVER_DIGEST 1 /* compute each query's digest on the device before it is done */
+#define JP_SERVER_KEEP 2   /* keep each query's plan until jp_server_release: jp_server_materialize */
 
 typedef struct {
   int32_t device;           /* HIP device the server runs on */
   int32_t max_batch;        /* most queries per batch (0 = 4096) */
-  int64_t hbm_budget_bytes; /* device memory the in-flight batches may hold (0 = 64 GiB) */
-  jp_options opt;           /* options of every batch */
+  int64_t hbm_budget_bytes; /* device memory the in-flight and kept batches may hold (0 = 64 GiB) */
+  jp_options opt;           /* options of every batch (no JP_FLAG_TIMING / JP_FLAG_GRAPH) */
+  int32_t flags;            /* JP_SERVER_* bits */
+  int32_t reserved;         /* must be 0 */
+  int64_t chunk_pairs;      /* pairs per output chunk of the digest pass and the estimate (0 = 2^24) */
 } jp_server_config;
 
 typedef struct {
   int64_t total, dense, sparse; /* pair counts */
+  uint64_t digest;              /* digest of the pairs when has_digest */
   int32_t status;               /* jp_status of the query */
   int32_t batch_size;           /* queries in the batch that carried it */
+  int32_t has_digest;           /* 1 if digest is set (JP_SERVER_DIGEST) */
+  int32_t kept;                 /* 1 while the pairs can be materialised (JP_SERVER_KEEP, not released) */
   double submit_us, admit_us, done_us; /* host clock, microseconds since the server started */
 } jp_query_result;
 
 typedef struct {
   int64_t submitted, completed, failed, batches;
+  int64_t splits;          /* failed groups split in halves and planned again */
   int64_t pairs;           /* pairs over completed queries */
-  int64_t peak_bytes;      /* largest device footprint of the in-flight batches */
+  int64_t peak_bytes;      /* largest sum of the live batches' peak device bytes (<= budget_bytes) */
+  int64_t budget_bytes;    /* the HBM budget */
+  int64_t charged_bytes;   /* estimates of the batches live now (in flight or kept) */
   double p50_us, p99_us, mean_us; /* latency submit -> done over completed queries */
 } jp_server_summary;
 
-/* Starts the server thread.  Syncs nothing on the caller's streams. */
+/* Starts the server thread.  Syncs nothing on the caller's streams.
+ * JP_EINVAL for a bad device, negative limits, unknown flags or options. */
 jp_status jp_server_create(const jp_server_config* cfg, jp_server** out);
 
 /* Queues one query.  q holds device columns as in jp_plan_create; they must
@@ -271,10 +313,33 @@ jp_status jp_server_poll(jp_server* s, uint64_t ticket, int* done, jp_query_resu
 /* Blocks until the query has finished, then fills *r. */
 jp_status jp_server_wait(jp_server* s, uint64_t ticket, jp_query_result* r);
 
+/* As jp_materialize, for a finished query of a JP_SERVER_KEEP server that has
+ * not been released (else JP_ESTATE).  Requests of up to chunk_pairs pairs fit
+ * the query's admission estimate; larger ones may return JP_ENOMEM.  Runs on
+ * the caller's stream; syncs it. */
+jp_status jp_server_materialize(jp_server* s, uint64_t ticket, jp_part part, int64_t first,
+                                int64_t max_pairs, int32_t* out_x, int32_t* out_z,
+                                int64_t* n_written, hipStream_t stream);
+
+/* Drops a finished query's kept result; its batch's memory and budget charge
+ * go once every kept query of the batch is released.  JP_ESTATE if not done. */
+jp_status jp_server_release(jp_server* s, uint64_t ticket);
+
 jp_status jp_server_stats(jp_server* s, jp_server_summary* st);
 
-/* Finishes the queued queries, stops the thread, frees everything (NULL-safe). */
+/* Finishes the queued queries, stops the thread, frees everything, kept
+ * results included (NULL-safe). */
 void jp_server_destroy(jp_server* s);
+
+/* -------------------------------------------------------------- digest --- */
+
+/* *digest (one uint64 in DEVICE memory) += the order-independent digest of the
+ * n pairs (x[i], z[i]) (device columns): the wrapping sum of SplitMix64
+ * (Steele, Lea and Flood, OOPSLA 2014) of key(x, z), the sign-flipped values
+ * with x in the high word.  Adding the digests of the chunks of a result gives
+ * the digest of the result.  Asynchronous. */
+jp_status jp_digest_pairs(const int32_t* x, const int32_t* z, int64_t n, uint64_t* digest,
+                          hipStream_t stream);
 
 #ifdef __cplusplus
 }

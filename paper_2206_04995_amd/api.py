@@ -120,11 +120,11 @@ def join_project(r_x, r_y, s_z, s_y, opt: Optional[B.jp_options] = None, stream=
 
 
 class Server:
-    """Continuous-batching query server (counts), see jp_server_* in include/jp.h."""
+    """Continuous-batching query server, see jp_server_* in include/jp.h."""
 
     def __init__(self, device: int = 0, max_batch: int = 0, hbm_budget_bytes: int = 0,
-                 opt: Optional[B.jp_options] = None):
-        self.h = B.jp_server_create(device, max_batch, hbm_budget_bytes, opt)
+                 opt: Optional[B.jp_options] = None, flags: int = 0, chunk_pairs: int = 0):
+        self.h = B.jp_server_create(device, max_batch, hbm_budget_bytes, opt, flags, chunk_pairs)
         self._keep = {}
 
     def submit(self, r_x, r_y, s_z, s_y) -> int:
@@ -142,6 +142,20 @@ class Server:
         r = B.jp_server_wait(self.h, ticket)
         self._keep.pop(ticket, None)
         return r
+
+    def materialize(self, ticket: int, total: int, part: int = B.JP_PART_ALL, first: int = 0,
+                    max_pairs: Optional[int] = None):
+        """Pairs [first, first + max_pairs) of a kept result as two device tensors."""
+        import torch
+
+        n = total - first if max_pairs is None else min(max_pairs, max(total - first, 0))
+        ox = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        oz = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        w = B.jp_server_materialize(self.h, ticket, part, first, n, ox, oz)
+        return ox[:w], oz[:w]
+
+    def release(self, ticket: int):
+        B.jp_server_release(self.h, ticket)
 
     def stats(self):
         return B.jp_server_stats(self.h)

@@ -22,6 +22,8 @@ JP_TAU_AUTO, JP_TAU_FIXED = 0, 1
 JP_DENSE_AUTO, JP_DENSE_BITS, JP_DENSE_MFMA = 0, 1, 2
 JP_FLAG_TIMING = 1
 JP_FLAG_GRAPH = 2
+JP_SERVER_DIGEST = 1
+JP_SERVER_KEEP = 2
 INT64_MAX = 2 ** 63 - 1
 
 _STATUS = {0: "JP_OK", 1: "JP_EINVAL", 2: "JP_ENOMEM", 3: "JP_EHIP", 4: "JP_ESTATE", 5: "JP_ERANGE", 6: "JP_EBUSY"}
@@ -31,8 +33,9 @@ EXPORTS = [
     "jp_plan_create", "jp_execute", "jp_count", "jp_materialize", "jp_row_info", "jp_dense_z",
     "jp_plan_stats", "jp_plan_timings", "jp_plan_work", "jp_plan_destroy", "jp_last_error",
     "jp_batch_create", "jp_batch_execute", "jp_batch_counts", "jp_batch_materialize", "jp_batch_stats",
-    "jp_batch_destroy",
+    "jp_batch_destroy", "jp_batch_timings", "jp_batch_work",
     "jp_server_create", "jp_server_submit", "jp_server_poll", "jp_server_wait", "jp_server_stats", "jp_server_destroy",
+    "jp_server_materialize", "jp_server_release", "jp_digest_pairs",
     "jp_tune", "jp_tune_clear",
 ]
 
@@ -59,14 +62,15 @@ class jp_options(ctypes.Structure):
 class jp_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_x", "n_y", "n_z", "n_r_kept", "out_j", "tau", "n_z_dense", "k_hot", "footprint_bytes",
-                 "pivot_cover", "dense_mfma")]
+                 "pivot_cover", "dense_mfma", "peak_bytes")]
 
 
 class jp_timings(ctypes.Structure):
     _fields_ = [("sparse_ms", ctypes.c_float), ("dense_ms", ctypes.c_float), ("execute_ms", ctypes.c_float),
                 ("pad_", ctypes.c_float)] + [
         (n, ctypes.c_int64) for n in ("sparse_join_rows", "n_r_kept", "n_x", "dense_hot_words", "dense_row_words",
-                                      "dense_cold_entries", "dense_mfma_ops")]
+                                      "dense_cold_entries", "dense_mfma_ops")] + [
+        ("map_ms", ctypes.c_float), ("partition_ms", ctypes.c_float)]
 
 
 class jp_tune_result(ctypes.Structure):
@@ -85,17 +89,20 @@ class jp_instance(ctypes.Structure):
 
 class jp_server_config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64),
-                ("opt", jp_options)]
+                ("opt", jp_options), ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("chunk_pairs", ctypes.c_int64)]
 
 
 class jp_query_result(ctypes.Structure):
     _fields_ = [("total", ctypes.c_int64), ("dense", ctypes.c_int64), ("sparse", ctypes.c_int64),
-                ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("submit_us", ctypes.c_double),
+                ("digest", ctypes.c_uint64), ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("has_digest", ctypes.c_int32), ("kept", ctypes.c_int32), ("submit_us", ctypes.c_double),
                 ("admit_us", ctypes.c_double), ("done_us", ctypes.c_double)]
 
 
 class jp_server_summary(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "batches", "pairs", "peak_bytes")] + [
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "batches", "splits", "pairs",
+                                              "peak_bytes", "budget_bytes", "charged_bytes")] + [
         (n, ctypes.c_double) for n in ("p50_us", "p99_us", "mean_us")]
 
 
@@ -129,12 +136,17 @@ def _load() -> ctypes.CDLL:
         "jp_batch_materialize": (st, [vp, i32, ctypes.c_int, i64, i64, vp, vp, i64p, vp]),
         "jp_batch_stats": (st, [vp, i32, ctypes.POINTER(jp_stats)]),
         "jp_batch_destroy": (None, [vp]),
+        "jp_batch_timings": (st, [vp, ctypes.POINTER(jp_timings), vp]),
+        "jp_batch_work": (st, [vp, ctypes.POINTER(jp_timings), vp]),
         "jp_server_create": (st, [ctypes.POINTER(jp_server_config), ctypes.POINTER(vp)]),
         "jp_server_submit": (st, [vp, ctypes.POINTER(jp_instance), ctypes.POINTER(ctypes.c_uint64)]),
         "jp_server_poll": (st, [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(jp_query_result)]),
         "jp_server_wait": (st, [vp, ctypes.c_uint64, ctypes.POINTER(jp_query_result)]),
         "jp_server_stats": (st, [vp, ctypes.POINTER(jp_server_summary)]),
         "jp_server_destroy": (None, [vp]),
+        "jp_server_materialize": (st, [vp, ctypes.c_uint64, ctypes.c_int, i64, i64, vp, vp, i64p, vp]),
+        "jp_server_release": (st, [vp, ctypes.c_uint64]),
+        "jp_digest_pairs": (st, [vp, vp, i64, vp, vp]),
         "jp_tune": (st, [vp, vp, i64, vp, vp, i64, ctypes.POINTER(jp_options), vp, ctypes.POINTER(jp_tune_result)]),
         "jp_tune_clear": (st, []),
     }
@@ -327,6 +339,20 @@ def jp_batch_stats(batch: int, inst: int) -> Dict[str, int]:
     return _stats_dict(s)
 
 
+def jp_batch_timings(batch: int, stream=None) -> Dict[str, float]:
+    """Stage times (ms) of the plan and the last execute of a batch built with JP_FLAG_TIMING."""
+    t = jp_timings()
+    _check(lib.jp_batch_timings(batch, ctypes.byref(t), _stream(stream)))
+    return {name: float(getattr(t, name)) for name, _ in jp_timings._fields_ if name.endswith("_ms")}
+
+
+def jp_batch_work(batch: int, stream=None) -> Dict[str, int]:
+    t = jp_timings()
+    _check(lib.jp_batch_work(batch, ctypes.byref(t), _stream(stream)))
+    return {name: int(getattr(t, name)) for name, _ in jp_timings._fields_
+            if not name.endswith("_ms") and name != "pad_"}
+
+
 def jp_batch_destroy(batch: int):
     lib.jp_batch_destroy(batch)
 
@@ -339,12 +365,14 @@ def _result_dict(r: jp_query_result) -> Dict[str, float]:
 
 
 def jp_server_create(device: int = 0, max_batch: int = 0, hbm_budget_bytes: int = 0,
-                     opt: Optional[jp_options] = None) -> int:
+                     opt: Optional[jp_options] = None, flags: int = 0, chunk_pairs: int = 0) -> int:
     cfg = jp_server_config()
     cfg.device = device
     cfg.max_batch = max_batch
     cfg.hbm_budget_bytes = hbm_budget_bytes
     cfg.opt = opt if opt is not None else make_options()
+    cfg.flags = flags
+    cfg.chunk_pairs = chunk_pairs
     h = ctypes.c_void_p()
     _check(lib.jp_server_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h.value
@@ -376,5 +404,29 @@ def jp_server_stats(server: int) -> Dict[str, float]:
     return {name: getattr(s, name) for name, _ in jp_server_summary._fields_}
 
 
+def jp_server_materialize(server: int, ticket: int, part: int, first: int, max_pairs: int, out_x, out_z,
+                          stream=None) -> int:
+    n = ctypes.c_int64()
+    _check(lib.jp_server_materialize(server, ticket, part, first, max_pairs, _ptr(out_x), _ptr(out_z),
+                                     ctypes.byref(n), _stream(stream)))
+    return n.value
+
+
+def jp_server_release(server: int, ticket: int):
+    _check(lib.jp_server_release(server, ticket))
+
+
 def jp_server_destroy(server: int):
     lib.jp_server_destroy(server)
+
+
+# ---------------------------------------------------------------- digest
+
+
+def jp_digest_pairs(out_x, out_z, n: int, acc, stream=None):
+    """acc (a one-element int64 device tensor, read as uint64) += digest of the first n pairs."""
+    import torch
+
+    if not isinstance(acc, torch.Tensor) or acc.dtype != torch.int64 or not acc.is_cuda or acc.numel() < 1:
+        raise TypeError("acc must be an int64 tensor on a ROCm device")
+    _check(lib.jp_digest_pairs(_ptr(out_x), _ptr(out_z), n, acc.data_ptr(), _stream(stream)))

@@ -97,7 +97,31 @@ __global__ void k_gather_values(const int32_t* __restrict__ vals, const int32_t*
     out[i] = vals[idx[i]];
 }
 
+// digest term of a pair: mix64 of its order-preserving key (both values
+// sign-flipped, x in the high word)
+__device__ __forceinline__ uint64_t pair_mix(int32_t x, int32_t z) {
+  return mix64((uint64_t(uint32_t(x) ^ 0x80000000u) << 32) | uint64_t(uint32_t(z) ^ 0x80000000u));
+}
+
+// acc += sum of pair_mix over the n pairs (wrapping): one 64-bit atomic per wave
+__global__ void k_digest_pairs(const int32_t* __restrict__ x, const int32_t* __restrict__ z, int64_t n,
+                               unsigned long long* __restrict__ acc) {
+  uint64_t d = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    d += pair_mix(x[i], z[i]);
+  d = wave_sum(d);
+  if (lane_id() == 0 && d != 0) atomicAdd(acc, (unsigned long long)d);
+}
+
 }  // namespace
+
+void digest_pairs(const int32_t* x, const int32_t* z, int64_t n, uint64_t* acc, hipStream_t s) {
+  if (n <= 0) return;
+  const int grid = int(std::min<int64_t>((n + NT * 8 - 1) / (NT * 8), 4096));
+  hipLaunchKernelGGL(k_digest_pairs, dim3(grid), dim3(NT), 0, s, x, z, n,
+                     reinterpret_cast<unsigned long long*>(acc));
+  JP_LAUNCH_CHECK();
+}
 
 void gather_values(const int32_t* vals, const int32_t* idx, int64_t n, int32_t* out, hipStream_t s) {
   if (n <= 0) return;

@@ -156,6 +156,11 @@ void Plan::build(const jp_instance* inst, int n, const jp_options* o, hipStream_
   stream = s;
   stream_used = true;
   arena_limit(opt.workspace_limit_bytes);
+  const bool timing = (opt.flags & JP_FLAG_TIMING) != 0;
+  if (timing) {
+    for (auto& e : evp) JP_HIP(hipEventCreate(&e));
+    JP_HIP(hipEventRecord(evp[0], s));
+  }
   h_rbase.assign(n + 1, 0);
   h_sbase.assign(n + 1, 0);
   for (int i = 0; i < n; ++i) {
@@ -202,13 +207,15 @@ void Plan::build(const jp_instance* inst, int n, const jp_options* o, hipStream_
     sy = csy;
   }
   map(s);
+  if (timing) JP_HIP(hipEventRecord(evp[1], s));
   partition(s);
+  if (timing) JP_HIP(hipEventRecord(evp[2], s));
 }
 
 // ---------------------------------------------------------------- mapping
 void Plan::map(hipStream_t s) {
   const int n = n_inst;
-  Arena T;  // temporaries of the mapping stage
+  Arena T(&B);  // temporaries of the mapping stage
   int32_t* mm = T.alloc<int32_t>(6 * int64_t(n), s);
   int32_t *zmin = mm, *zmax = mm + n, *ymin = mm + 2 * n, *ymax = mm + 3 * n, *xmin = mm + 4 * n, *xmax = mm + 5 * n;
   seg_minmax(sz, NS, d_sbase, n, zmin, zmax, s);
@@ -346,7 +353,7 @@ void Plan::map(hipStream_t s) {
 // -------------------------------------------------------------- partition
 void Plan::partition(hipStream_t s) {
   const int n = n_inst;
-  Arena T;
+  Arena T(&B);
   const double c_de = env_double("JP_COST_DE_OVER_SP", 0.05);
   const double c_fix = env_double("JP_COST_FIX_OVER_SP", 0.0);
   h_tau.resize(n);
@@ -849,6 +856,10 @@ void Plan::timings(jp_timings* t, hipStream_t s) {
   JP_HIP(hipEventElapsedTime(&t->sparse_ms, ev[0], ev[1]));
   JP_HIP(hipEventElapsedTime(&t->dense_ms, ev[1], ev[2]));
   JP_HIP(hipEventElapsedTime(&t->execute_ms, ev[0], ev[3]));
+  if (evp[0]) {
+    JP_HIP(hipEventElapsedTime(&t->map_ms, evp[0], evp[1]));
+    JP_HIP(hipEventElapsedTime(&t->partition_ms, evp[1], evp[2]));
+  }
 }
 
 void Plan::work(jp_timings* t, hipStream_t s) {
@@ -897,7 +908,7 @@ int64_t Plan::materialize(int inst, int part, int64_t first, int64_t maxp, int32
   d2h(&base, off + xb, 1, s);
   sync(s);
   const int64_t g0 = base + first, g1 = g0 + nw;
-  Arena T;
+  Arena T(&B);
   int64_t* rows = T.alloc<int64_t>(2, s);
   int64_t* info = T.alloc<int64_t>(6, s);
   find_rows(off, xb, xe, g0, g1, rows, s);
@@ -936,6 +947,7 @@ void Plan::stats(int i, jp_stats* st) const {
   st->k_hot = ds[0].h_K.empty() ? 0 : ds[0].h_K[i];
   st->footprint_bytes = n_inst == 1 ? A.bytes() : A.bytes() / n_inst;
   st->dense_mfma = use_mfma ? 1 : 0;
+  st->peak_bytes = B.peak;
   st->pivot_cover = (n_piv > 0 && h_piv[i] >= 0) ? int64_t(h_zdbase[i + 1] - h_zdbase[i]) -
                                                        int64_t(ds[1].h_base[i + 1] - ds[1].h_base[i])
                                                  : 0;
@@ -973,6 +985,12 @@ jp_status check_opt(const jp_options* o) {
   if (o->reserved != 0) return fail(JP_EINVAL, "reserved option field must be 0");
   return JP_OK;
 }
+
+}  // namespace
+
+jp_status jp::check_options(const jp_options* o) { return check_opt(o); }
+
+namespace {
 
 }  // namespace
 
@@ -1045,7 +1063,7 @@ jp_status jp_dense_z(jp_plan* p, int32_t* z_values, hipStream_t stream) {
   return guarded([&] {
     Plan& q = p->p;
     if (q.NZd > 0 && z_values) {
-      Arena T;
+      Arena T(&q.B);
       int32_t* tmp = T.alloc<int32_t>(q.NZd, stream);
       jp::gather_values(q.vals_z, q.dz2z, q.NZd, tmp, stream);
       d2h(z_values, tmp, size_t(q.NZd), stream);
@@ -1127,11 +1145,27 @@ jp_status jp_batch_materialize(jp_batch* b, int32_t inst, jp_part part, int64_t 
   return guarded([&] { *n_written = b->p.materialize(inst, int(part), first, max_pairs, out_x, out_z, stream); });
 }
 
+jp_status jp_batch_timings(jp_batch* b, jp_timings* t, hipStream_t stream) {
+  if (!b || !t) return fail(JP_EINVAL, "null argument");
+  return guarded([&] { b->p.timings(t, stream); });
+}
+
+jp_status jp_batch_work(jp_batch* b, jp_timings* t, hipStream_t stream) {
+  if (!b || !t) return fail(JP_EINVAL, "null argument");
+  return guarded([&] { b->p.work(t, stream); });
+}
+
 jp_status jp_batch_stats(const jp_batch* b, int32_t inst, jp_stats* s) {
   if (!b || !s) return fail(JP_EINVAL, "null argument");
   if (inst < 0 || inst >= b->p.n_inst) return fail(JP_EINVAL, "instance index out of range");
   b->p.stats(inst, s);
   return JP_OK;
+}
+
+jp_status jp_digest_pairs(const int32_t* x, const int32_t* z, int64_t n, uint64_t* digest, hipStream_t stream) {
+  if (n < 0) return fail(JP_EINVAL, "negative pair count");
+  if (!digest || (n > 0 && (!x || !z))) return fail(JP_EINVAL, "null argument");
+  return guarded([&] { digest_pairs(x, z, n, digest, stream); });
 }
 
 void jp_batch_destroy(jp_batch* b) {

@@ -39,7 +39,8 @@ struct TuneRec {
 };
 
 struct Plan {
-  Arena A;
+  Budget B;       // device bytes held at once by the arenas below and the stages' temporaries
+  Arena A{&B};    // persistent state
   int n_inst = 0;
   jp_options opt{};
   hipStream_t stream = nullptr;
@@ -97,11 +98,12 @@ struct Plan {
 
   // JP_FLAG_TIMING: events around the execute kernels and work counters
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t evp[3] = {nullptr, nullptr, nullptr};  // start of the plan, after mapping, after partition
   int32_t* heavy_list = nullptr;
   void work(jp_timings* t, hipStream_t s);
 
   // temporaries of the count pass, replayed on every execute (see Arena)
-  Arena XA;
+  Arena XA{&B};
   bool warm = false;
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -114,14 +116,13 @@ struct Plan {
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    for (auto& e : evp)
+      if (e) (void)hipEventDestroy(e);
     XA.release(stream);
     A.release(stream);
   }
   void timings(jp_timings* t, hipStream_t s);
-  void arena_limit(int64_t lim) {
-    A.set_limit(lim);
-    XA.set_limit(lim);
-  }
+  void arena_limit(int64_t lim) { B.limit = lim; }
   void build(const jp_instance* inst, int n, const jp_options* o, hipStream_t s);
   void map(hipStream_t s);
   void partition(hipStream_t s);
@@ -131,6 +132,9 @@ struct Plan {
   int64_t materialize(int inst, int part, int64_t first, int64_t maxp, int32_t* ox, int32_t* oz, hipStream_t s);
   void stats(int i, jp_stats* st) const;
 };
+
+// argument checks of jp_options shared by every entry point (JP_OK or JP_EINVAL with the message set)
+jp_status check_options(const jp_options* o);
 
 int64_t tau_from_cost(int64_t nx, int64_t nz, int64_t ns, int64_t out_j, double c_de_over_sp, double c_fix_over_sp);
 // shape signature of one instance, and the cost ratio c_de / c_sp stored for it by jp_tune

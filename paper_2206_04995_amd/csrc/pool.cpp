@@ -84,6 +84,16 @@ void Pool::trim() {
   }
 }
 
+void Arena::charge(int64_t b) {
+  if (budget_) {
+    if (budget_->limit > 0 && budget_->used + b > budget_->limit)
+      throw Error(2, "workspace limit of " + std::to_string(budget_->limit) + " bytes exceeded");
+    budget_->used += b;
+    if (budget_->used > budget_->peak) budget_->peak = budget_->used;
+  }
+  bytes_ += b;
+}
+
 void* Arena::raw(size_t bytes, hipStream_t s) {
   size_t r = round_alloc(bytes);
   if (replay_ && cursor_ < recs_.size()) {
@@ -92,13 +102,17 @@ void* Arena::raw(size_t bytes, hipStream_t s) {
     ++cursor_;
     return rec.p;
   }
-  if (limit_ > 0 && bytes_ + int64_t(r) > limit_)
-    throw Error(2, "workspace limit of " + std::to_string(limit_) + " bytes exceeded");
-  void* p = Pool::instance().alloc(bytes, s);
+  charge(int64_t(r));
+  void* p = nullptr;
+  try {
+    p = Pool::instance().alloc(bytes, s);
+  } catch (...) {
+    bytes_ -= int64_t(r);
+    if (budget_) budget_->used -= int64_t(r);
+    throw;
+  }
   recs_.push_back({p, r});
   if (replay_) cursor_ = recs_.size();
-  bytes_ += int64_t(r);
-  if (bytes_ > peak_) peak_ = bytes_;
   return p;
 }
 
@@ -107,6 +121,7 @@ void Arena::give_back(void* p, hipStream_t s) {
   for (size_t i = 0; i < recs_.size(); ++i) {
     if (recs_[i].p == p) {
       bytes_ -= int64_t(recs_[i].bytes);
+      if (budget_) budget_->used -= int64_t(recs_[i].bytes);
       Pool::instance().free(p, s);
       recs_[i] = recs_.back();
       recs_.pop_back();
@@ -118,6 +133,7 @@ void Arena::give_back(void* p, hipStream_t s) {
 void Arena::release(hipStream_t s) {
   for (auto& r : recs_) Pool::instance().free(r.p, s);
   recs_.clear();
+  if (budget_) budget_->used -= bytes_;
   bytes_ = 0;
   cursor_ = 0;
 }

@@ -53,11 +53,20 @@ class Pool {
   size_t cached_ = 0;
 };
 
-// Allocation owner for one plan: tracks bytes against an optional limit and
-// returns everything to the pool on release().
+// Device bytes held at once by every arena of one owner (a plan: its
+// persistent state and its temporaries), checked against an optional limit.
+struct Budget {
+  int64_t limit = 0;  // 0: none
+  int64_t used = 0;
+  int64_t peak = 0;
+};
+
+// Allocation owner: returns everything to the pool on release().  Every block
+// is charged to the owner's budget (if any); a block that would take the
+// budget past its limit throws JP_ENOMEM before anything is allocated.
 class Arena {
  public:
-  explicit Arena(int64_t limit = 0) : limit_(limit) {}
+  explicit Arena(Budget* b = nullptr) : budget_(b) {}
   ~Arena() { release(nullptr); }
   Arena(const Arena&) = delete;
   Arena& operator=(const Arena&) = delete;
@@ -69,9 +78,7 @@ class Arena {
   void* raw(size_t bytes, hipStream_t s);
   void give_back(void* p, hipStream_t s);  // return one block early
   void release(hipStream_t s);
-  void set_limit(int64_t lim) { limit_ = lim; }
   int64_t bytes() const { return bytes_; }
-  int64_t peak() const { return peak_; }
 
   // Replay mode: the first pass records its allocations and keeps them
   // (give_back does nothing); every later pass, started by rewind(), gets the
@@ -85,10 +92,10 @@ class Arena {
     void* p;
     size_t bytes;
   };
+  void charge(int64_t b);
   std::vector<Rec> recs_;
-  int64_t limit_;
+  Budget* budget_;
   int64_t bytes_ = 0;
-  int64_t peak_ = 0;
   bool replay_ = false;
   size_t cursor_ = 0;
 };

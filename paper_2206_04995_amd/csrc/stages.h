@@ -214,6 +214,9 @@ void work_stats(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
 void work_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const int64_t* w, int64_t* out4, hipStream_t s);
 
 // ------------------------------------------------------------- output
+// *acc (device) += sum over the n pairs of SplitMix64(key(x, z)), wrapping:
+// the order-independent digest of a pair list
+void digest_pairs(const int32_t* x, const int32_t* z, int64_t n, uint64_t* acc, hipStream_t s);
 void add_counts(const int32_t* a, const int32_t* b, int64_t n, int32_t* out, hipStream_t s);
 // tot[3*i + {0,1,2}] = all, dense, sparse pairs of instance i
 void inst_totals(const int64_t* off_all, const int64_t* off_de, const int64_t* off_sp, const int32_t* x_base,
