@@ -171,6 +171,30 @@ void jp_plan_destroy(jp_plan* p); /* NULL-safe; frees all plan-owned device memo
 
 const char* jp_last_error(void);
 
+/* ------------------------------------------------- no device allocation --- */
+
+/* Size of the static device scratch of jp_count_static, and the most tuples
+ * (n_r + n_s) it accepts. */
+#define JP_STATIC_SCRATCH_MIB 256
+#define JP_STATIC_MAX_TUPLES (1 << 20)
+
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the same result as jp_plan_create +
+ * jp_execute + jp_count on one query, computed entirely inside a fixed
+ * device array of JP_STATIC_SCRATCH_MIB MiB that the library holds per GPU
+ * until the process ends; the call allocates and frees no device memory.
+ * Columns as for jp_plan_create; counts go to host outputs (each nullable).
+ * JP_EINVAL (before any device work) if n_r + n_s > JP_STATIC_MAX_TUPLES or
+ * the options ask for JP_FLAG_TIMING or JP_FLAG_GRAPH; JP_ENOMEM if the
+ * query's plan does not fit the scratch (very wide value domains).  Syncs.
+ * Calls from threads of one process are serialised per GPU (the array is the
+ * process's own); work of an earlier call never overlaps a later one, and
+ * every call initialises the parts of the array it reads. */
+jp_status jp_count_static(const int32_t* r_x, const int32_t* r_y, int64_t n_r,
+                          const int32_t* s_z, const int32_t* s_y, int64_t n_s,
+                          const jp_options* opt, hipStream_t stream,
+                          int64_t* total, int64_t* dense, int64_t* sparse);
+
 /* --------------------------------------------------------------- batch --- */
 
 /* One query of a batch: device columns as for jp_plan_create. */

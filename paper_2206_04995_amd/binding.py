@@ -36,7 +36,7 @@ EXPORTS = [
     "jp_batch_destroy", "jp_batch_timings", "jp_batch_work",
     "jp_server_create", "jp_server_submit", "jp_server_poll", "jp_server_wait", "jp_server_stats", "jp_server_destroy",
     "jp_server_materialize", "jp_server_release", "jp_digest_pairs",
-    "jp_tune", "jp_tune_clear",
+    "jp_tune", "jp_tune_clear", "jp_count_static",
 ]
 
 
@@ -149,6 +149,7 @@ def _load() -> ctypes.CDLL:
         "jp_digest_pairs": (st, [vp, vp, i64, vp, vp]),
         "jp_tune": (st, [vp, vp, i64, vp, vp, i64, ctypes.POINTER(jp_options), vp, ctypes.POINTER(jp_tune_result)]),
         "jp_tune_clear": (st, []),
+        "jp_count_static": (st, [vp, vp, i64, vp, vp, i64, ctypes.POINTER(jp_options), vp, i64p, i64p, i64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -219,6 +220,17 @@ def jp_plan_create(r_x, r_y, s_z, s_y, opt: Optional[jp_options] = None, stream=
     _check(lib.jp_plan_create(_ptr(r_x), _ptr(r_y), n_r, _ptr(s_z), _ptr(s_y), n_s,
                               ctypes.byref(opt) if opt is not None else None, _stream(stream), ctypes.byref(h)))
     return h.value
+
+
+def jp_count_static(r_x, r_y, s_z, s_y, opt: Optional[jp_options] = None, stream=None) -> Tuple[int, int, int]:
+    """(total, dense, sparse) of one query computed in the library's static device scratch (no allocation)."""
+    n_r = int(r_x.numel()) if r_x is not None else 0
+    n_s = int(s_z.numel()) if s_z is not None else 0
+    t, d, s = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.jp_count_static(_ptr(r_x), _ptr(r_y), n_r, _ptr(s_z), _ptr(s_y), n_s,
+                               ctypes.byref(opt) if opt is not None else None, _stream(stream),
+                               ctypes.byref(t), ctypes.byref(d), ctypes.byref(s)))
+    return t.value, d.value, s.value
 
 
 def jp_tune(r_x, r_y, s_z, s_y, opt: Optional[jp_options] = None, stream=None) -> Dict[str, float]:

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -992,11 +993,72 @@ jp_status jp::check_options(const jp_options* o) { return check_opt(o); }
 
 namespace {
 
+// Device scratch of jp_count_static: one copy per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the device
+// copy: the device address comes from hipGetSymbolAddress (per device, in
+// static_scratch()) and only that address is handed to kernels.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(JP_STATIC_SCRATCH_MIB) << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_static_mu[MAX_DEVICES];  // one call at a time per device and process
+void* g_static_ptr[MAX_DEVICES] = {};  // device address of scratch, per device (set under g_static_mu)
+
+// Device address of this device's scratch (looked up once per device).
+void* static_scratch(int dev) {
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    JP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(JP_EHIP, "hipGetSymbolAddress returned a null address for the static scratch");
+    g_static_ptr[dev] = p;
+  }
+  return g_static_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* jp_last_error(void) { return g_last_error.c_str(); }
+
+jp_status jp_count_static(const int32_t* r_x, const int32_t* r_y, int64_t n_r, const int32_t* s_z,
+                          const int32_t* s_y, int64_t n_s, const jp_options* opt, hipStream_t stream,
+                          int64_t* total, int64_t* dense, int64_t* sparse) {
+  jp_status st;
+  if ((st = check_cols(r_x, r_y, n_r, "R")) != JP_OK) return st;
+  if ((st = check_cols(s_z, s_y, n_s, "S")) != JP_OK) return st;
+  if (n_r + n_s > JP_STATIC_MAX_TUPLES)
+    return fail(JP_EINVAL, "jp_count_static takes at most " + std::to_string(JP_STATIC_MAX_TUPLES) +
+                               " tuples (n_r + n_s); use jp_plan_create for larger queries");
+  if ((st = check_opt(opt)) != JP_OK) return st;
+  if (opt && (opt->flags & (JP_FLAG_TIMING | JP_FLAG_GRAPH)))
+    return fail(JP_EINVAL, "jp_count_static takes neither JP_FLAG_TIMING nor JP_FLAG_GRAPH");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+    (void)hipGetLastError();
+    return fail(JP_EHIP, "no usable current HIP device");
+  }
+  std::lock_guard<std::mutex> lock(g_static_mu[dev]);
+  return guarded([&] {
+    Region region;
+    region.base = static_cast<char*>(static_scratch(dev));
+    region.size = STATIC_SCRATCH_BYTES;
+    RegionScope scope(&region);  // every arena below carves from the scratch
+    Plan p;
+    jp_instance in{r_x, r_y, s_z, s_y, n_r, n_s};
+    try {
+      p.build(&in, 1, opt, stream);
+      p.execute(stream);
+      p.fetch_totals(stream);  // syncs: the scratch is free again when this returns
+    } catch (...) {
+      (void)hipStreamSynchronize(stream);  // no work of this call may still use the scratch
+      throw;
+    }
+    if (total) *total = p.h_tot[0];
+    if (dense) *dense = p.h_tot[1];
+    if (sparse) *sparse = p.h_tot[2];
+  });
+}
 
 jp_status jp_plan_create(const int32_t* r_x, const int32_t* r_y, int64_t n_r, const int32_t* s_z, const int32_t* s_y,
                          int64_t n_s, const jp_options* opt, hipStream_t stream, jp_plan** out) {

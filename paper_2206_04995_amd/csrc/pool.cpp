@@ -84,6 +84,14 @@ void Pool::trim() {
   }
 }
 
+namespace {
+thread_local Region* t_region = nullptr;
+}
+
+Region* active_region() { return t_region; }
+RegionScope::RegionScope(Region* r) : prev_(t_region) { t_region = r; }
+RegionScope::~RegionScope() { t_region = prev_; }
+
 void Arena::charge(int64_t b) {
   if (budget_) {
     if (budget_->limit > 0 && budget_->used + b > budget_->limit)
@@ -95,6 +103,16 @@ void Arena::charge(int64_t b) {
 }
 
 void* Arena::raw(size_t bytes, hipStream_t s) {
+  if (Region* g = t_region) {
+    // carved from the caller's fixed region: never recorded, never freed
+    const size_t r = bytes == 0 ? 256 : (bytes + 255) & ~size_t(255);
+    if (r > g->size - g->used)
+      throw Error(2, "the query needs more than the " + std::to_string(g->size) + " bytes of the static scratch");
+    charge(int64_t(r));
+    void* p = g->base + g->used;
+    g->used += r;
+    return p;
+  }
   size_t r = round_alloc(bytes);
   if (replay_ && cursor_ < recs_.size()) {
     Rec& rec = recs_[cursor_];

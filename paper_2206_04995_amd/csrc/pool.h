@@ -53,6 +53,28 @@ class Pool {
   size_t cached_ = 0;
 };
 
+// A fixed device region that arenas carve their blocks from, instead of the
+// pool, while a RegionScope is active on the calling thread: blocks are taken
+// in order (256-byte aligned) and none is returned before the scope ends, so
+// the region must hold everything the work of the scope allocates.  Running
+// out throws JP_ENOMEM.
+struct Region {
+  char* base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+};
+Region* active_region();  // of the calling thread; null outside any scope
+class RegionScope {
+ public:
+  explicit RegionScope(Region* r);
+  ~RegionScope();
+  RegionScope(const RegionScope&) = delete;
+  RegionScope& operator=(const RegionScope&) = delete;
+
+ private:
+  Region* prev_;
+};
+
 // Device bytes held at once by every arena of one owner (a plan: its
 // persistent state and its temporaries), checked against an optional limit.
 struct Budget {
