@@ -17,6 +17,10 @@ Contents
   set (Sec. 2.3): a pair belongs to the dense part iff its z is dense.
 * ``digest_pairs``: order-independent digest (wrapping sum of SplitMix64
   finalised keys), used where a result is too large to list.
+* ``aggregate`` / ``brute_force_aggregate``: Join-Aggregate (Sec. 4.1), per
+  group (x, z) the number of join rows and the sum of R.v * S.u.
+* ``join_project_composite`` / ``brute_force_composite``: multi-attribute
+  keys (Sec. 2.2, wider range of operations).
 """
 from __future__ import annotations
 
@@ -63,6 +67,9 @@ def _load():
         lib.jpo_rows.restype = ctypes.c_int64
         lib.jpo_row_counts.argtypes = base + [ctypes.c_int, i32p, i64p, u64p, i64p, u64p]
         lib.jpo_row_counts.restype = ctypes.c_int64
+        lib.jpo_aggregate.argtypes = [i32p, i32p, i32p, ctypes.c_int64, i32p, i32p, i32p, ctypes.c_int64, ctypes.c_int,
+                                      i32p, i32p, i64p, i64p, ctypes.c_int64]
+        lib.jpo_aggregate.restype = ctypes.c_int64
         lib.jpo_digest_pairs.argtypes = [i32p, i32p, ctypes.c_int64]
         lib.jpo_digest_pairs.restype = ctypes.c_uint64
         _lib = lib
@@ -184,3 +191,89 @@ def split_by_z(xs: np.ndarray, zs: np.ndarray, dense_z_values: np.ndarray):
     ((dense_x, dense_z), (sparse_x, sparse_z)), each in input order."""
     mask = np.isin(zs, np.asarray(dense_z_values, dtype=np.int32))
     return (xs[mask], zs[mask]), (xs[~mask], zs[~mask])
+
+
+# ------------------------------------------------------- composite keys
+
+
+def _ranks(*cols_groups):
+    """Lexicographic ranks of the row tuples of several column groups encoded
+    together (np.unique over rows), one rank array per group, plus the sorted
+    distinct tuples."""
+    mats = [np.stack([np.asarray(c, dtype=np.int32) for c in g], axis=1) if len(g[0]) else
+            np.zeros((0, len(g)), dtype=np.int32) for g in cols_groups]
+    allm = np.concatenate(mats, axis=0)
+    uniq, inv = np.unique(allm, axis=0, return_inverse=True)
+    inv = inv.reshape(-1).astype(np.int32)
+    out, at = [], 0
+    for m in mats:
+        out.append(inv[at:at + m.shape[0]])
+        at += m.shape[0]
+    return out, uniq
+
+
+def join_project_composite(r_x, r_y, s_z, s_y):
+    """Join-Project over multi-attribute keys (Sec. 2.2, wider range of
+    operations): r_x, r_y, s_z, s_y are lists of int32 columns; x is the tuple of
+    R's r_x columns, y the tuple of the join columns (equal arity on both sides),
+    z the tuple of S's s_z columns.  Each tuple kind is replaced by its rank among
+    the distinct tuples in lexicographic order (np.unique over rows; R.y and S.y
+    ranked together), the single-column oracle runs on the ranks, and the ranks
+    are mapped back.  Returns (x columns, z columns) of the distinct result
+    pairs, sorted lexicographically by (x tuple, z tuple)."""
+    (xr,), ux = _ranks(r_x)
+    (yr, ys), _ = _ranks(r_y, s_y)
+    (zr,), uz = _ranks(s_z)
+    ox, oz = join_project(xr, yr, zr, ys)
+    return [ux[ox, c].copy() for c in range(ux.shape[1])], [uz[oz, c].copy() for c in range(uz.shape[1])]
+
+
+def brute_force_composite(r_x, r_y, s_z, s_y):
+    """Eq. 1 over tuples, written out with nested loops (tiny inputs only):
+    sorted list of distinct (x tuple, z tuple) pairs."""
+    R = [(tuple(int(c[i]) for c in r_x), tuple(int(c[i]) for c in r_y)) for i in range(len(r_x[0]))]
+    S = [(tuple(int(c[i]) for c in s_z), tuple(int(c[i]) for c in s_y)) for i in range(len(s_z[0]))]
+    out = set()
+    for x, y in R:
+        for z, y2 in S:
+            if y == y2:
+                out.add((x, z))
+    return sorted(out)
+
+
+# ------------------------------------------------------- Join-Aggregate
+
+
+def aggregate(rx, ry, rv, sz, sy, su, threads: Optional[int] = None):
+    """Join-Aggregate (Sec. 4.1): groups (x, z) of R(x, y, v) JOIN_y S(z, y, u)
+    with COUNT(*) and SUM(v * u) (int64, wrapping), sorted by (x, z).  Returns
+    (x, z, count, sum) arrays."""
+    rx, ry, sz, sy = _cols(rx, ry, sz, sy)
+    rv = np.ascontiguousarray(np.asarray(rv, dtype=np.int32))
+    su = np.ascontiguousarray(np.asarray(su, dtype=np.int32))
+    if rv.shape != rx.shape or su.shape != sz.shape:
+        raise ValueError("value column length mismatch")
+    lib = _load()
+    cap = max(1, out_j(rx, ry, sz, sy))
+    ox = np.empty(cap, np.int32)
+    oz = np.empty(cap, np.int32)
+    oc = np.empty(cap, np.int64)
+    osum = np.empty(cap, np.int64)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    n = lib.jpo_aggregate(_p32(rx), _p32(ry), _p32(rv), rx.size, _p32(sz), _p32(sy), _p32(su), sz.size,
+                          threads or default_threads(), _p32(ox), _p32(oz), oc.ctypes.data_as(i64p),
+                          osum.ctypes.data_as(i64p), cap)
+    assert n <= cap
+    return ox[:n].copy(), oz[:n].copy(), oc[:n].copy(), osum[:n].copy()
+
+
+def brute_force_aggregate(rx, ry, rv, sz, sy, su):
+    """Sec. 4.1's Join-Aggregate written out with nested loops (tiny inputs):
+    sorted list of (x, z, count, sum of v * u)."""
+    acc = {}
+    for x, y, v in zip(rx, ry, rv):
+        for z, y2, u in zip(sz, sy, su):
+            if int(y) == int(y2):
+                c, s = acc.get((int(x), int(z)), (0, 0))
+                acc[(int(x), int(z))] = (c + 1, s + int(v) * int(u))
+    return [(x, z, c, s) for (x, z), (c, s) in sorted(acc.items())]

@@ -301,6 +301,55 @@ int64_t jpo_row_counts(const int32_t* rx, const int32_t* ry, int64_t nr, const i
   return nx;
 }
 
+// Join-Aggregate (Sec. 4.1, group-by attributes from both tables): for every
+// group (x, z) of the join rows of R(x, y, v) and S(z, y, u), the number of
+// join rows and the sum of v * u (int64, wrapping).  The same hash join as the
+// classical solution, with the hash set replaced by a hash map from the pair
+// key to its (count, sum).  Groups sorted by (x, z) as signed int32; writes
+// min(groups, cap) of them and returns the number of groups.
+int64_t jpo_aggregate(const int32_t* rx, const int32_t* ry, const int32_t* rv, int64_t nr, const int32_t* sz,
+                      const int32_t* sy, const int32_t* su, int64_t ns, int nthreads, int32_t* out_x,
+                      int32_t* out_z, int64_t* out_cnt, int64_t* out_sum, int64_t cap) {
+  std::unordered_map<int32_t, std::vector<std::pair<int32_t, int32_t>>> h;  // y -> (z, u)
+  h.reserve(size_t(ns / 4 + 16));
+  for (int64_t j = 0; j < ns; ++j) h[sy[j]].push_back({sz[j], su[j]});
+  Slices sl = make_slices(rx, nr, std::max(1, nthreads) * 8);
+  auto buckets = bucket_rows(rx, nr, sl);
+  struct Agg {
+    int64_t cnt = 0;
+    uint64_t sum = 0;
+  };
+  std::vector<std::vector<std::pair<uint64_t, Agg>>> res(sl.n);
+  parallel_for(sl.n, nthreads, [&](int s) {
+    std::unordered_map<uint64_t, Agg> m;
+    for (int64_t i : buckets[s]) {
+      auto it = h.find(ry[i]);
+      if (it == h.end()) continue;
+      for (const auto& zu : it->second) {
+        Agg& a = m[pair_key(rx[i], zu.first)];
+        a.cnt += 1;
+        a.sum += uint64_t(int64_t(rv[i]) * int64_t(zu.second));
+      }
+    }
+    res[s].assign(m.begin(), m.end());
+    std::sort(res[s].begin(), res[s].end(),
+              [](const std::pair<uint64_t, Agg>& a, const std::pair<uint64_t, Agg>& b) { return a.first < b.first; });
+  });
+  int64_t pos = 0;
+  for (int s = 0; s < sl.n; ++s) {
+    for (const auto& e : res[s]) {
+      if (pos < cap) {
+        out_x[pos] = key_x(e.first);
+        out_z[pos] = key_z(e.first);
+        out_cnt[pos] = e.second.cnt;
+        out_sum[pos] = int64_t(e.second.sum);
+      }
+      ++pos;
+    }
+  }
+  return pos;
+}
+
 // Digest of an explicit pair list (used to digest a listed result).
 uint64_t jpo_digest_pairs(const int32_t* xs, const int32_t* zs, int64_t n) {
   uint64_t d = 0;

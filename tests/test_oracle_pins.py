@@ -234,3 +234,80 @@ def test_split_by_z_is_a_partition(oracle_mod):
     b = set(zip(sx.tolist(), sz_.tolist()))
     assert not (a & b)
     assert a | b == set(zip(ox.tolist(), oz.tolist()))
+
+
+# ------------------------------------------------------- composite keys
+
+
+def _composite_case(seed, n_r, n_s, kx, ky, kz, dom, offset=0):
+    rng = np.random.default_rng(seed)
+
+    def cols(k, n):
+        return [(rng.integers(0, dom, n) + offset).astype(np.int32) for _ in range(k)]
+
+    return cols(kx, n_r), cols(ky, n_r), cols(kz, n_s), cols(ky, n_s)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_composite_oracle_equals_brute_force(oracle_mod, seed):
+    """The rank-encoded composite oracle equals nested loops over tuples."""
+    kx, ky, kz = 1 + seed % 3, 1 + (seed // 3) % 3, 1 + (seed // 2) % 2
+    r_x, r_y, s_z, s_y = _composite_case(seed, 40 + seed, 35 + 2 * seed, kx, ky, kz, 3 + seed % 3,
+                                         offset=-(seed % 2) * 2 ** 31)
+    gx, gz = oracle_mod.join_project_composite(r_x, r_y, s_z, s_y)
+    got = [(tuple(int(c[i]) for c in gx), tuple(int(c[i]) for c in gz)) for i in range(gx[0].size)]
+    assert got == oracle_mod.brute_force_composite(r_x, r_y, s_z, s_y)
+
+
+def test_composite_single_columns_reduce_to_plain_oracle(oracle_mod):
+    """One column per key kind is the plain Join-Project."""
+    r_x, r_y, s_z, s_y = _composite_case(99, 3000, 2500, 1, 1, 1, 60, offset=-30)
+    gx, gz = oracle_mod.join_project_composite(r_x, r_y, s_z, s_y)
+    ox, oz = oracle_mod.join_project(r_x[0], r_y[0], s_z[0], s_y[0])
+    assert np.array_equal(gx[0], ox) and np.array_equal(gz[0], oz)
+
+
+def test_composite_join_key_is_the_whole_tuple(oracle_mod):
+    """Tuples that agree on one join column but not the other do not join."""
+    r_x = [np.array([1, 2], np.int32)]
+    r_y = [np.array([5, 5], np.int32), np.array([0, 1], np.int32)]
+    s_z = [np.array([7, 8], np.int32), np.array([-1, -2], np.int32)]
+    s_y = [np.array([5, 5], np.int32), np.array([1, 2], np.int32)]
+    gx, gz = oracle_mod.join_project_composite(r_x, r_y, s_z, s_y)
+    assert gx[0].tolist() == [2] and gz[0].tolist() == [7] and gz[1].tolist() == [-1]
+
+
+# ------------------------------------------------------- Join-Aggregate
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_aggregate_oracle_equals_brute_force(oracle_mod, seed):
+    rng = np.random.default_rng(50 + seed)
+    n_r, n_s, dom = 30 + 7 * seed, 25 + 5 * seed, 4 + seed % 4
+    off = -(seed % 3) * 2 ** 30
+    rx, ry = (rng.integers(0, dom, n_r) + off).astype(np.int32), rng.integers(0, dom, n_r).astype(np.int32)
+    sz, sy = (rng.integers(0, dom, n_s) - off).astype(np.int32), rng.integers(0, dom, n_s).astype(np.int32)
+    rv = rng.integers(-1000, 1000, n_r).astype(np.int32)
+    su = rng.integers(-1000, 1000, n_s).astype(np.int32)
+    got = oracle_mod.aggregate(rx, ry, rv, sz, sy, su)
+    want = oracle_mod.brute_force_aggregate(rx, ry, rv, sz, sy, su)
+    assert list(zip(*(a.tolist() for a in got))) == want
+
+
+def test_aggregate_invariants(oracle_mod):
+    """Groups are the Join-Project result; counts add up to OUT_J; with unit
+    values the sum is the count; one shared key gives sum = (sum of v)(sum of u)
+    for distinct x and z."""
+    inst = synth.small_random(77, 4000, 3000, dom_x=200, dom_y=90, dom_z=150)
+    ones_r, ones_s = np.ones(inst.n_r, np.int32), np.ones(inst.n_s, np.int32)
+    x, z, c, s = oracle_mod.aggregate(inst.rx, inst.ry, ones_r, inst.sz, inst.sy, ones_s)
+    ox, oz = oracle_mod.join_project(inst.rx, inst.ry, inst.sz, inst.sy)
+    assert np.array_equal(x, ox) and np.array_equal(z, oz)
+    assert int(c.sum()) == oracle_mod.out_j(inst.rx, inst.ry, inst.sz, inst.sy)
+    assert np.array_equal(c, s)
+    rv = np.arange(1, 51, dtype=np.int32)
+    su = np.arange(-20, 0, dtype=np.int32)
+    x, z, c, s = oracle_mod.aggregate(np.zeros(50, np.int32), np.full(50, 9, np.int32), rv,
+                                      np.zeros(20, np.int32), np.full(20, 9, np.int32), su)
+    assert x.tolist() == [0] and z.tolist() == [0] and c.tolist() == [1000]
+    assert s.tolist() == [int(rv.sum()) * int(su.sum())]
