@@ -1,15 +1,25 @@
 """Benchmark of the Join-Project hot path on one MI355X.
 
-One step = the whole path for one query over inputs already resident in HBM:
-jp_plan_create (mapping, CSR, partition by z) + jp_execute (SparseBMM and
-DenseEC count kernels, per-row offsets) + jp_count (host read of the counts),
-which is the paper's count-only mode.  The default workload is the skewed
-single query: R and S with 1e7 distinct tuples each, x and z uniform in
-[0, 1e6), y Zipf(1.0) over [0, 1e5).
+Default workload (the headline): 4096 independent instances, tuple counts
+log-uniform in [1e3, 1e6] per side, key domains 10% of the tuples, y uniform
+(even instances) or Zipf(1.2) (odd).  One step is one batched pass over all of
+them with inputs resident in HBM: jp_batch_create (mapping, CSR builds and
+partition of every instance, one launch per stage) + jp_batch_execute (the
+SparseBMM and DenseEC count kernels) + jp_batch_counts, the paper's count-only
+mode.  Beside it: the plain loop (one plan per instance) on the same inputs,
+with identical per-instance counts required (and equal to the oracle's
+per-instance counts when they are on file), and a served query stream (the
+continuous-batching server against the serial path on one Poisson trace) with
+p50/p99 latency.
 
-Prints one JSON line with the metric, a roofline object for the dominant
-kernel (times from HIP events on the stream the kernel runs on) and a CPU
-baseline (the oracle timed on the host over a bounded sample).
+Other workloads (--workload): the skewed single query (1e7 distinct tuples per
+side, x and z uniform in [0, 1e6), y Zipf(1.0) over [0, 1e5)), the plain 1e5
+query, a dense uniform query, the power-law graph self-join, and the served
+stream alone.
+
+Prints one JSON line with the metric, a roofline object for the dominant stage
+or kernel (times from HIP events on the stream it runs on) and a CPU baseline
+(the oracle timed on the host over a bounded sample).
 """
 from __future__ import annotations
 
@@ -75,6 +85,21 @@ def measured_traffic(workload: str):
     return (m["fetch_kib"] * FETCH_FACTOR + m["write_kib"] * WRITE_FACTOR) * 1024.0
 
 
+def copy_reference(mib: int, dev):
+    """One plain elementwise kernel that reads and writes exactly `mib` MiB (a reference for HBM counters)."""
+    if mib <= 0:
+        return
+    import torch
+
+    src = torch.ones(mib << 18, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.bitwise_not(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    print(f"[bench] copy reference: {mib} MiB read + written by one bitwise_not kernel", file=sys.stderr, flush=True)
+
+
 def make_workload(name: str):
     import synth
 
@@ -115,21 +140,52 @@ def cpu_baseline(inst, sample_mod: int):
                       f"{pairs} distinct pairs in {dt:.2f} s"}
 
 
+def _gen_instances(n, hi, batch_seed=0, threads=8):
+    """Seeded batched-mix instances, built by a thread pool (each instance has its own seed path)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import synth
+
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        return list(ex.map(lambda i: synth.config4_instance(i, hi=hi, batch_seed=batch_seed), range(n)))
+
+
+def _golden_batched():
+    """Per-instance oracle pair counts of the 4096-instance batch, written by tests/golden/make_fullsize.py."""
+    path = os.path.join(ROOT, "tests", "golden", "batched_4096.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return np.array([r["pairs"] for r in json.load(f)["instances"]], dtype=np.int64)
+
+
+def map_bytes(stats_list, n_r, n_s):
+    """Algorithmic bytes of the mapping and CSR builds of one instance set:
+    8 (|R| + |S|) column bytes read, 4 (|R'| + |S|) CSR column bytes and
+    4 (|X| + |Y| + |Z| + 3) row-pointer bytes written, 4 (|X| + |Z|) id -> value bytes written."""
+    b = 8 * (n_r + n_s)
+    for st in stats_list:
+        b += 4 * (st["n_r_kept"]) + 4 * (st["n_x"] + st["n_y"] + st["n_z"] + 3) + 4 * (st["n_x"] + st["n_z"])
+    return b + 4 * n_s
+
+
 def batched(args):
     """Many independent instances: one batched plan (every stage one launch over
     all instances) against the plain loop of one plan per instance, same GPU,
-    same inputs, identical per-instance counts required."""
+    same inputs, identical per-instance counts required (and equal to the
+    oracle's, when its per-instance counts are on file)."""
     import torch
     import paper_2206_04995_amd as P
-    import synth
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    copy_reference(args.copy_ref_mib, dev)
     t0 = time.perf_counter()
-    insts = [synth.config4_instance(i, hi=args.batch_hi) for i in range(args.instances)]
+    insts = _gen_instances(args.instances, args.batch_hi, threads=args.gen_threads)
+    n_r = sum(a.n_r for a in insts)
+    n_s = sum(a.n_s for a in insts)
     cols = [tuple(torch.from_numpy(c).to(dev) for c in (a.rx, a.ry, a.sz, a.sy)) for a in insts]
-    n_tuples = sum(a.n_r + a.n_s for a in insts)
-    print(f"[bench] {args.instances} instances, {n_tuples} tuples, generated in {time.perf_counter() - t0:.1f} s",
+    print(f"[bench] {args.instances} instances, {n_r + n_s} tuples, generated in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
     tuned = []
@@ -144,10 +200,10 @@ def batched(args):
                 tuned.append({"tau": r["tau"], "model_tau": r["model_tau"], "signature": r["signature"]})
         print(f"[bench] tuned {len(seen)} shape signatures", file=sys.stderr, flush=True)
 
-    def plain():
+    def plain(cs):
         out = []
-        for c in cols:
-            h = P.jp_plan_create(*c, stream=stream)
+        for c in cs:
+            h = P.jp_plan_create(*c, opt=plain_opt, stream=stream)
             try:
                 P.jp_execute(h, stream)
                 out.append(P.jp_count(h, stream)[0])
@@ -155,33 +211,104 @@ def batched(args):
                 P.jp_plan_destroy(h)
         return np.array(out, dtype=np.int64)
 
-    def batch():
-        b = P.jp_batch_create(cols, stream=stream)
+    base_flags = P.JP_FLAG_DIRECT_IDS if args.direct_ids else 0
+    plain_opt = P.make_options(flags=base_flags)
+    timing_opt = P.make_options(flags=P.JP_FLAG_TIMING | base_flags)
+
+    def batch(timing=False, want_work=False):
+        b = P.jp_batch_create(cols, opt=timing_opt if timing else plain_opt, stream=stream)
         try:
             P.jp_batch_execute(b, stream)
-            return P.jp_batch_counts(b, len(cols), stream)
+            counts = P.jp_batch_counts(b, len(cols), stream)
+            extra = {}
+            if timing:
+                extra["tm"] = P.jp_batch_timings(b, stream)
+            if want_work:
+                extra["work"] = P.jp_batch_work(b, stream)
+                extra["stats"] = [P.jp_batch_stats(b, i) for i in range(len(cols))]
+            return counts, extra
         finally:
             P.jp_batch_destroy(b)
 
-    res = {}
-    paths = (("batched", batch),) if args.batched_only else (("plain", plain), ("batched", batch))
-    for name, fn in paths:
-        for _ in range(args.warmup):
-            fn()
+    # batched: warmup, then exactly `steps` timed passes
+    for _ in range(args.warmup):
+        batch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        counts, _ = batch()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    print(f"[bench] batched: {ms:.2f} ms per pass", file=sys.stderr, flush=True)
+
+    # stage split from HIP events on the stream the stages run on (separate passes, not timed above)
+    stage = []
+    for _ in range(args.stage_passes):
+        c2, ex = batch(timing=True)
+        if not np.array_equal(c2, counts):
+            raise SystemExit("batched counts differ between passes")
+        stage.append(ex["tm"])
+    _, ex = batch(want_work=True)
+    work, stats = ex["work"], ex["stats"]
+    st_ms = {k: float(np.mean([s[k] for s in stage])) for k in ("map_ms", "partition_ms", "sparse_ms", "dense_ms",
+                                                                  "execute_ms")}
+
+    # plain: one plan per instance in a loop, identical inputs
+    plain_ms = None
+    if args.plain_passes > 0:
+        plain(cols[:64])  # warm the allocator and code objects
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            counts = fn()
+        for _ in range(args.plain_passes):
+            pc = plain(cols)
         torch.cuda.synchronize()
-        res[name] = ((time.perf_counter() - t0) * 1000.0 / args.steps, counts)
-        print(f"[bench] {name}: {res[name][0]:.2f} ms per pass", file=sys.stderr, flush=True)
-    if "plain" in res and not np.array_equal(res["plain"][1], res["batched"][1]):
-        raise SystemExit("batched and plain per-instance counts differ")
-    plain_ms = res["plain"][0] if "plain" in res else None
-    pairs = int(res["batched"][1].sum())
-    ms = res["batched"][0]
+        plain_ms = (time.perf_counter() - t0) * 1000.0 / args.plain_passes
+        print(f"[bench] plain: {plain_ms:.2f} ms per pass", file=sys.stderr, flush=True)
+        if not np.array_equal(pc, counts):
+            raise SystemExit("batched and plain per-instance counts differ")
+    gold = _golden_batched() if (args.instances == 4096 and args.batch_hi == 1e6) else None
+    oracle_match = None
+    if gold is not None:
+        oracle_match = bool(np.array_equal(gold, counts))
+        if not oracle_match:
+            raise SystemExit("batched per-instance counts differ from the oracle's")
+
+    pairs = int(counts.sum())
+    # roofline of the dominant stage of the pass
+    groups = {"map": st_ms["map_ms"], "partition": st_ms["partition_ms"], "sparse": st_ms["sparse_ms"],
+              "dense": st_ms["dense_ms"]}
+    dom = max(groups, key=groups.get)
+    if dom == "map":
+        nbytes = map_bytes(stats, n_r, n_s)
+        ach = nbytes / (st_ms["map_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "mapping and CSR builds (all kernels of the stage)", "achieved": ach,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": measured_traffic("batched_map"), "kernel_ms": st_ms["map_ms"],
+                "work": {"bytes": nbytes, "note": "8(|R|+|S|) + 4(|R'|+|S|) + 4(|X|+|Y|+|Z|+3) + 4(|X|+|Z|) summed "
+                                                  "over instances"}}
+    elif dom == "dense":
+        ops = work["dense_hot_words"] + work["dense_row_words"] + work["dense_cold_entries"]
+        ach = ops / (st_ms["dense_ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": "DenseEC count (k_dense_bits, k_dense_narrow)", "achieved": ach,
+                "peak": VALU_I32_PEAK_TOPS, "unit": "TOP/s", "frac": ach / VALU_I32_PEAK_TOPS,
+                "traffic": measured_traffic("batched_dense"), "kernel_ms": st_ms["dense_ms"],
+                "work": {"int32_ops": ops}}
+    elif dom == "sparse":
+        nbytes = 12 * work["n_r_kept"] + 8 * work["n_x"] + 4 * work["sparse_join_rows"]
+        ach = nbytes / (st_ms["sparse_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "SparseBMM count", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("batched_sparse"),
+                "kernel_ms": st_ms["sparse_ms"], "work": {"bytes": nbytes}}
+    else:
+        nbytes = 16 * n_s + 8 * work["n_r_kept"]
+        ach = nbytes / (st_ms["partition_ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "partition by z and DenseEC tables (all kernels of the stage)",
+                "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": measured_traffic("batched_partition"), "kernel_ms": st_ms["partition_ms"],
+                "work": {"bytes": nbytes, "note": "16 B per S entry, 8 B per kept R entry"}}
+
     out = {
-        "metric": "distinct (x,z) pairs/sec",
+        "metric": "distinct (x,z) pairs/sec on 1 MI355X, batched vs plain; p50/p99 query latency",
         "value": pairs / (ms * 1e-3),
         "unit": "pairs/s",
         "n_gpus": 1,
@@ -195,14 +322,39 @@ def batched(args):
         "data": "synthetic (seeded generator, inputs resident in HBM)",
         "config": {"workload": "batched instances", "instances": args.instances, "tuned_signatures": len(tuned),
                    "tuples_per_side": f"log-uniform [1e3, {args.batch_hi:.0e}]", "key_domain": "10% of tuples",
-                   "y": "uniform (even) / Zipf 1.2 (odd)", "pairs": pairs, "tuples": n_tuples,
+                   "y": "uniform (even) / Zipf 1.2 (odd)", "pairs": pairs, "tuples": n_r + n_s,
+                   "input_tuples_per_s": (n_r + n_s) / (ms * 1e-3), "oracle_counts_match": oracle_match,
+                   "stage_ms": st_ms,
                    "plain_ms": plain_ms, "plain_pairs_per_s": None if plain_ms is None else pairs / (plain_ms * 1e-3),
                    "batched_over_plain": None if plain_ms is None else plain_ms / ms},
+        "roofline": roof,
     }
+    if args.served_queries > 0:
+        out["config"]["served"] = served(args, emit=False)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline_batched(insts, args.cpu_sample_stride)
     print(json.dumps(out), flush=True)
 
 
-def served(args):
+def cpu_baseline_batched(insts, stride: int):
+    """The oracle as it stands over every stride-th instance of the batch."""
+    import oracle
+
+    oracle.build(force=False)
+    threads = oracle.default_threads()
+    sample = insts[::stride]
+    t0 = time.perf_counter()
+    pairs = 0
+    for a in sample:
+        pairs += oracle.count(a.rx, a.ry, a.sz, a.sy, threads=threads)[0]
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th batched instance ({len(sample)} instances, "
+                      f"{sum(a.n_r + a.n_s for a in sample)} tuples); {pairs} distinct pairs in {dt:.2f} s"}
+
+
+def served(args, emit=True):
     """Poisson arrivals of a mix of queries: the continuous-batching server
     against the plain serial path (one query at a time, in arrival order) on the
     same trace, same device-resident tables; identical counts required."""
@@ -215,9 +367,10 @@ def served(args):
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    trace = synth.config5_trace(n_queries=args.queries, rate_per_s=1.0, p_large=args.p_large)
+    n_queries = args.queries if emit else args.served_queries
+    trace = synth.config5_trace(n_queries=n_queries, rate_per_s=1.0, p_large=args.p_large)
     n_small = sum(1 for _, k, _ in trace if k == 0)
-    small = [synth.config4_instance(i, hi=args.batch_hi, batch_seed=1000) for i in range(n_small)]
+    small = _gen_instances(n_small, args.batch_hi, batch_seed=1000, threads=args.gen_threads)
     large = [synth.config2(seed_index=1 + j) for j in range(args.large_distinct)]
 
     def cols_of(a):
@@ -251,9 +404,8 @@ def served(args):
     ref = [one(c) for c in queries]
     serial_busy = time.perf_counter() - tc
     rate = args.rate if args.rate > 0 else len(queries) / serial_busy
-    arrivals = np.array([t for t, _, _ in trace]) / trace[-1][0] * (len(queries) / rate)
 
-    def serial_run():
+    def serial_run(arrivals):
         lat = []
         start = time.perf_counter()
         for a, c in zip(arrivals, queries):
@@ -264,7 +416,7 @@ def served(args):
             lat.append(time.perf_counter() - start - a)
         return time.perf_counter() - start, np.array(lat)
 
-    def served_run():
+    def served_run(arrivals):
         with P.Server(max_batch=args.max_batch) as srv:
             tickets = [None] * len(queries)
             start = time.perf_counter()
@@ -285,32 +437,224 @@ def served(args):
         lat = np.array([(r["done_us"] - r["submit_us"]) * 1e-6 for r in res])
         return span, lat, [r["total"] for r in res], st
 
-    s_span, s_lat = serial_run()
-    v_span, v_lat, v_counts, st = served_run()
-    if list(v_counts) != list(ref):
-        raise SystemExit("served counts differ from the serial path")
+    points = []
+    for mult in [float(m) for m in args.rate_mults.split(",")]:
+        r = rate * mult
+        arrivals = np.array([t for t, _, _ in trace]) / trace[-1][0] * (len(queries) / r)
+        s_span, s_lat = serial_run(arrivals)
+        v_span, v_lat, v_counts, st = served_run(arrivals)
+        if list(v_counts) != list(ref):
+            raise SystemExit("served counts differ from the serial path")
+        pairs = int(sum(ref))
+        points.append({"rate_per_s": r, "rate_over_serial_capacity": mult,
+                       "served": {"pairs_per_s": pairs / v_span, "p50_ms": float(np.percentile(v_lat, 50) * 1e3),
+                                  "p99_ms": float(np.percentile(v_lat, 99) * 1e3), "batches": st["batches"],
+                                  "peak_bytes": st["peak_bytes"], "span_s": v_span},
+                       "serial": {"pairs_per_s": pairs / s_span, "p50_ms": float(np.percentile(s_lat, 50) * 1e3),
+                                  "p99_ms": float(np.percentile(s_lat, 99) * 1e3), "span_s": s_span}})
+        print(f"[bench] served x{mult}: p50 {points[-1]['served']['p50_ms']:.1f} ms p99 "
+              f"{points[-1]['served']['p99_ms']:.1f} ms vs serial p50 {points[-1]['serial']['p50_ms']:.1f} ms "
+              f"p99 {points[-1]['serial']['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
     pairs = int(sum(ref))
+    summary = {"workload": "served query stream", "queries": len(queries), "large_queries": len(queries) - n_small,
+               "large_distinct_tables": len(large_cols), "serial_capacity_per_s": rate, "serial_busy_s": serial_busy,
+               "pairs": pairs, "points": points}
+    if not emit:
+        return summary
+    first = points[0]
     out = {
-        "metric": "distinct (x,z) pairs/sec",
-        "value": pairs / v_span,
+        "metric": "distinct (x,z) pairs/sec on 1 MI355X, served vs serial; p50/p99 query latency",
+        "value": first["served"]["pairs_per_s"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 0,
-        "ms_per_step": v_span * 1000.0,
+        "ms_per_step": first["served"]["span_s"] * 1000.0,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic (seeded generator, tables resident in HBM)",
-        "config": {"workload": "served query stream", "queries": len(queries), "large_queries": len(queries) - n_small,
-                   "large_distinct_tables": len(large_cols), "arrival_rate_per_s": rate, "pairs": pairs,
-                   "served": {"pairs_per_s": pairs / v_span, "p50_ms": float(np.percentile(v_lat, 50) * 1e3),
-                              "p99_ms": float(np.percentile(v_lat, 99) * 1e3), "batches": st["batches"],
-                              "peak_bytes": st["peak_bytes"]},
-                   "serial": {"pairs_per_s": pairs / s_span, "p50_ms": float(np.percentile(s_lat, 50) * 1e3),
-                              "p99_ms": float(np.percentile(s_lat, 99) * 1e3), "busy_s": serial_busy}},
+        "config": summary,
     }
+    print(json.dumps(out), flush=True)
+
+
+def f1_sweep(args):
+    """Switch point of f1 (Sec. 2.6): uniform |R| = |S| = 1e6 over n values
+    (the paper's synthetic default, OUT_J = 1e12 / n), each query timed
+    (plan + execute + count) on the hybrid path, on the classical path and with
+    the automatic choice; identical counts required."""
+    import torch
+    import paper_2206_04995_amd as P
+    import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for n_dom in [int(v) for v in args.sweep_domains.split(",")]:
+        inst = synth.uniform_paper_default(n_tuples=args.sweep_tuples, n_domain=n_dom)
+        cols = [torch.from_numpy(c).to(dev) for c in (inst.rx, inst.ry, inst.sz, inst.sy)]
+        res = {"n_domain": n_dom}
+        for name, strat in (("hybrid", P.JP_STRATEGY_HYBRID), ("classical", P.JP_STRATEGY_CLASSICAL),
+                            ("auto", P.JP_STRATEGY_AUTO)):
+            opt = P.make_options(strategy=strat)
+            times, cnt, used = [], None, None
+            try:
+                for rep in range(1 + args.steps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    h = P.jp_plan_create(*cols, opt=opt, stream=stream)
+                    try:
+                        P.jp_execute(h, stream)
+                        c = P.jp_count(h, stream)[0]
+                        st = P.jp_plan_stats(h)
+                    finally:
+                        P.jp_plan_destroy(h)
+                    if rep:
+                        times.append((time.perf_counter() - t0) * 1e3)
+                    cnt, used = c, st["strategy"]
+            except P.JpError as e:  # the classical path refuses more than 2^30 join rows
+                res[name] = {"refused": str(e)}
+                continue
+            res[name] = {"ms": float(np.median(times)), "pairs": int(cnt), "path": "classical" if used == 2 else "hybrid"}
+            res["out_j"] = int(st["out_j"])
+        counts = {res[k]["pairs"] for k in ("hybrid", "classical", "auto") if "pairs" in res[k]}
+        if len(counts) != 1:
+            raise SystemExit(f"paths disagree at n = {n_dom}: {res}")
+        print(f"[bench] n={n_dom}: " + ", ".join(f"{k} {res[k].get('ms', float('nan')):.2f} ms"
+                                                 for k in ("hybrid", "classical", "auto")) +
+              f" (auto took {res['auto'].get('path')})", file=sys.stderr, flush=True)
+        rows.append(res)
+    out = {"metric": "f1 switch point: plan + execute + count time per path", "unit": "ms", "n_gpus": 1,
+           "steps": args.steps, "data": "synthetic uniform, |R| = |S| = %d" % args.sweep_tuples, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def aggregate_leg(args):
+    """Join-Aggregate (Sec. 4.1) G_{x,z} COUNT(*), SUM(v * u) on the power-law
+    graph self-join (2e7 edges; v = u = a seeded value in [-100, 100) per
+    tuple): plan + count pass per step (count of groups), and one full
+    materialisation timed separately ('M')."""
+    import torch
+    import paper_2206_04995_amd as P
+    import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    g = synth.config3()
+    rng = np.random.default_rng(5)
+    rv = rng.integers(-100, 100, g.n_r).astype(np.int32)
+    su = rng.integers(-100, 100, g.n_s).astype(np.int32)
+    cols = [torch.from_numpy(c).to(dev) for c in (g.rx, g.ry, rv, g.sz, g.sy, su)]
+    stream = torch.cuda.current_stream()
+
+    def step():
+        a = P.jp_agg_create(*cols, stream=stream)
+        try:
+            P.jp_agg_execute(a, stream)
+            return P.jp_agg_count(a, stream)
+        finally:
+            P.jp_agg_destroy(a)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        groups, out_j = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # 'M': materialise every group once into a reused chunk buffer
+    chunk = 1 << 26
+    bufs = [torch.empty(chunk, dtype=t, device=dev) for t in (torch.int32, torch.int32, torch.int64, torch.int64)]
+    a = P.jp_agg_create(*cols, stream=stream)
+    try:
+        P.jp_agg_execute(a, stream)
+        P.jp_agg_count(a, stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        first = 0
+        while first < groups:
+            first += P.jp_agg_materialize(a, first, chunk, *bufs, stream=stream)
+        torch.cuda.synchronize()
+        m_ms = (time.perf_counter() - t1) * 1e3
+    finally:
+        P.jp_agg_destroy(a)
+    out = {"metric": "Join-Aggregate groups/sec (COUNT, SUM(v*u)), count-only", "value": groups / (ms * 1e-3),
+           "unit": "groups/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+           "data": "synthetic (seeded generator, inputs resident in HBM)",
+           "config": {"workload": "Join-Aggregate on the power-law graph self-join", "vertices": 2_000_000,
+                      "edges": 20_000_000, "groups": int(groups), "out_j": int(out_j),
+                      "materialize_ms": m_ms, "materialize_groups_per_s": groups / (m_ms * 1e-3)}}
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build(force=False)
+        sel = (g.rx % args.cpu_sample_mod_agg) == 0
+        t0 = time.perf_counter()
+        res = oracle.aggregate(g.rx[sel], g.ry[sel], rv[sel], g.sz, g.sy, su, threads=oracle.default_threads())
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": res[0].size / dt, "unit": "groups/s", "cores": oracle.default_threads(),
+                               "kind": "oracle", "sample": f"R rows with x % {args.cpu_sample_mod_agg} == 0 "
+                                                           f"({int(sel.sum())} tuples), all of S; {res[0].size} "
+                                                           f"groups in {dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
+def composite_leg(args):
+    """Join-Project over two-attribute keys (Sec. 2.2, wider range of
+    operations): the plain 1e5-tuple query with x, y and z each split into two
+    columns (value // 100, value % 100), so x = (x1, x2), y = (y1, y2),
+    z = (z1, z2).  One step: dictionary encoding of the three key kinds, plan,
+    count pass and count (the pairs are those of the single-column query)."""
+    import torch
+    import paper_2206_04995_amd as P
+    import synth
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    inst = synth.config1() if args.composite_base == "plain" else synth.config3()
+
+    def split(c):
+        return [torch.from_numpy((c // 100).astype(np.int32)).to(dev), torch.from_numpy((c % 100).astype(np.int32)).to(dev)]
+
+    rx, ry, sz, sy = split(inst.rx), split(inst.ry), split(inst.sz), split(inst.sy)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        with P.Dict([rx], stream) as dx, P.Dict([ry, sy], stream) as dy, P.Dict([sz], stream) as dz:
+            with P.Plan(dx.ids[0], dy.ids[0], dz.ids[0], dy.ids[1], stream=stream) as p:
+                p.execute()
+                return p.count()[0]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pairs = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    out = {"metric": "distinct (x,z) pairs/sec, two-attribute keys", "value": pairs / (ms * 1e-3), "unit": "pairs/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic (seeded generator, inputs resident in HBM)",
+           "config": {"workload": f"two-attribute keys over the {args.composite_base} query", "pairs": int(pairs),
+                      "tuples": inst.n_r + inst.n_s}}
+    if not args.no_cpu_baseline:
+        import oracle
+
+        t0 = time.perf_counter()
+        ox, _ = oracle.join_project_composite([c.cpu().numpy() for c in rx], [c.cpu().numpy() for c in ry],
+                                              [c.cpu().numpy() for c in sz], [c.cpu().numpy() for c in sy])
+        dt = time.perf_counter() - t0
+        if ox[0].size != pairs:
+            raise SystemExit("composite pair count differs from the oracle's")
+        out["cpu_baseline"] = {"value": ox[0].size / dt, "unit": "pairs/s", "cores": oracle.default_threads(),
+                               "kind": "oracle", "sample": f"the whole query ({ox[0].size} pairs in {dt:.2f} s)"}
     print(json.dumps(out), flush=True)
 
 
@@ -319,12 +663,30 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="skewed",
-                    choices=["skewed", "uniform", "dense", "graph", "batched", "served"])
+    ap.add_argument("--workload", default="batched",
+                    choices=["skewed", "uniform", "dense", "graph", "batched", "served", "f1_sweep", "aggregate",
+                             "composite"])
     ap.add_argument("--queries", type=int, default=2000, help="served workload: queries in the trace")
     ap.add_argument("--p-large", type=float, default=0.01, help="served workload: share of 1e7-tuple queries")
     ap.add_argument("--large-distinct", type=int, default=2, help="served workload: distinct large tables")
     ap.add_argument("--rate", type=float, default=0.0, help="served workload: arrivals/s (0 = serial capacity)")
+    ap.add_argument("--rate-mults", default="1,2", help="served: arrival rates as multiples of --rate")
+    ap.add_argument("--served-queries", type=int, default=1000,
+                    help="batched workload: queries of the served trace reported beside it (0 = none)")
+    ap.add_argument("--plain-passes", type=int, default=1, help="batched workload: timed passes of the plain loop")
+    ap.add_argument("--stage-passes", type=int, default=2,
+                    help="batched workload: extra passes with HIP events around each stage (stage split, roofline)")
+    ap.add_argument("--direct-ids", action="store_true",
+                    help="batched workload: map dense value ranges by key histogram and scatter instead of radix sort")
+    ap.add_argument("--sweep-domains", default="1000,10000,100000,400000,1000000,4000000,10000000,100000000",
+                    help="f1_sweep: value domains n of the uniform tables")
+    ap.add_argument("--sweep-tuples", type=int, default=1_000_000, help="f1_sweep: tuples per side")
+    ap.add_argument("--cpu-sample-mod-agg", type=int, default=50, help="aggregate: oracle sample of R rows")
+    ap.add_argument("--composite-base", default="graph", choices=["plain", "graph"],
+                    help="composite: the single-column query whose columns are split in two")
+    ap.add_argument("--gen-threads", type=int, default=8, help="threads generating the seeded instances")
+    ap.add_argument("--cpu-sample-stride", type=int, default=4,
+                    help="batched workload: the CPU baseline runs the oracle on every n-th instance")
     ap.add_argument("--max-batch", type=int, default=256, help="served workload: server batch limit")
     ap.add_argument("--instances", type=int, default=4096, help="batched workload: number of instances")
     ap.add_argument("--batch-hi", type=float, default=1e6, help="batched workload: largest tuples per side")
@@ -337,7 +699,7 @@ def main():
     ap.add_argument("--k-hot-max", type=int, default=None, help="cap on hot keys per instance (default: tuned or automatic)")
     ap.add_argument("--tune-sample", type=int, default=16, help="batched workload: instances the tuner times")
     ap.add_argument("--batched-only", action="store_true",
-                    help="batched workload: skip the plain one-plan-per-instance loop (for kernel traces)")
+                    help="batched workload: skip the plain loop and the served trace (for kernel traces)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain elementwise copy over this many MiB (a reference for HBM counters)")
     args = ap.parse_args()
@@ -348,11 +710,23 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.batched_only:
+        args.plain_passes = 0
+        args.served_queries = 0
     if args.workload == "batched":
         batched(args)
         return
     if args.workload == "served":
         served(args)
+        return
+    if args.workload == "f1_sweep":
+        f1_sweep(args)
+        return
+    if args.workload == "aggregate":
+        aggregate_leg(args)
+        return
+    if args.workload == "composite":
+        composite_leg(args)
         return
 
     import torch
@@ -363,16 +737,7 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     cols = [torch.from_numpy(c).to(dev) for c in (inst.rx, inst.ry, inst.sz, inst.sy)]
-    if args.copy_ref_mib > 0:
-        # one kernel that reads and writes exactly copy_ref_mib MiB each
-        src = torch.ones(args.copy_ref_mib << 18, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        torch.bitwise_not(src, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
-        print(f"[bench] copy reference: {args.copy_ref_mib} MiB read + written by one bitwise_not kernel",
-              file=sys.stderr, flush=True)
+    copy_reference(args.copy_ref_mib, dev)
     fixed = {}
     if args.window_group is not None:
         fixed["window_group"] = args.window_group

@@ -63,11 +63,34 @@ typedef enum {
                         plan is a single query and the panels fit; the bit path otherwise */
 } jp_dense_kernel;
 
+/* Evaluation path of a plan (paper Sec. 2.6, f1, and Fig. 1): the hybrid DIM^3
+ * path (mapping, partition, SparseBMM + DenseEC) or the classical solution of
+ * Sec. 1.1 (hash join, then deduplication of the projected join rows in a
+ * device hash set; no mapping).  JP_STRATEGY_AUTO takes the classical path when
+ * f1 > 0, i.e. when the join rows it must deduplicate cost less than the
+ * mapping it avoids: OUT_J < ratio * (|R| + |S|), with OUT_J estimated from up
+ * to 4096 sampled tuples per side (exact for smaller inputs).  AUTO considers
+ * the classical path only with tau_mode AUTO, dense_kernel AUTO and no
+ * JP_FLAG_GRAPH.  The classical path takes at most 2^30 join rows (JP_EINVAL
+ * when forced beyond; AUTO then runs the hybrid path).  Its result has no dense
+ * part (every pair is in JP_PART_SPARSE) and jp_plan_work reports zeros. */
+typedef enum {
+  JP_STRATEGY_AUTO = 0,
+  JP_STRATEGY_HYBRID = 1,
+  JP_STRATEGY_CLASSICAL = 2
+} jp_strategy;
+
 /* jp_options.flags bits */
 #define JP_FLAG_TIMING 1 /* record HIP events around the kernels of jp_execute (see jp_plan_timings) */
 #define JP_FLAG_GRAPH 2  /* record the count pass of the second jp_execute into a HIP graph and
                             replay it on later calls: no allocation and one launch per call after
                             the first; results are identical; JP_FLAG_TIMING is ignored with it */
+#define JP_FLAG_DIRECT_IDS 4 /* columns whose values fill a dense range skip the sort that maps x and
+                                z to ids (Sec. 2.2, optimisation 1: values already natural numbers):
+                                ids, counts and the grouping come from a histogram over the key space,
+                                scans and a scatter with per-key cursors.  Results are identical; on
+                                gfx950 its per-element global atomics make it slower than the
+                                default radix-sort mapping, so it is opt-in */
 
 /* Options; an all-zero struct (or NULL) selects every default. */
 typedef struct {
@@ -79,7 +102,8 @@ typedef struct {
   int64_t workspace_limit_bytes; /* 0 = no limit; else the most device memory the plan or batch may hold
                                     at once, temporaries included: exceeding it returns JP_ENOMEM */
   int32_t window_group;          /* z windows per workgroup of the bit-path DenseEC count (0 = automatic, max 64) */
-  int32_t reserved;              /* must be 0 */
+  int32_t strategy;              /* a jp_strategy value, for plans: batches, servers, jp_tune and
+                                    jp_count_static run the hybrid path and reject JP_STRATEGY_CLASSICAL */
 } jp_options;
 
 /* Kernel times of the last jp_execute (filled by jp_plan_timings for a plan
@@ -114,6 +138,8 @@ typedef struct {
   int64_t dense_mfma;      /* 1 if the dense part is counted by the INT8-MFMA product, else 0 */
   int64_t peak_bytes;      /* most device memory the object held at once so far, temporaries included
                               (all instances of a batch; the quantity workspace_limit_bytes bounds) */
+  int64_t map_direct;      /* bit 0: z ids, bit 1: x ids came from the direct-range mapping (no sort) */
+  int64_t strategy;        /* JP_STRATEGY_HYBRID or JP_STRATEGY_CLASSICAL: the path the plan runs */
 } jp_stats;
 
 typedef struct jp_plan jp_plan;
@@ -354,6 +380,63 @@ jp_status jp_server_stats(jp_server* s, jp_server_summary* st);
 /* Finishes the queued queries, stops the thread, frees everything, kept
  * results included (NULL-safe). */
 void jp_server_destroy(jp_server* s);
+
+/* ---------------------------------------------------- Join-Aggregate --- */
+
+/* Join-Aggregate with group-by attributes from both tables (paper Sec. 4.1):
+ *   G_{x,z} COUNT(*), SUM(R.v * S.u)  over  R(x, y, v) JOIN_y S(z, y, u).
+ * The groups are the Join-Project result (the same (x, z) set); each carries
+ * the number of its join rows (repeated tuples count) and the sum of v * u over
+ * them as int64 (wrapping on overflow).  As the paper adapts DIM^3, the
+ * deduplicating accumulator of each x row becomes an aggregate accumulator:
+ * rows with little work aggregate in an LDS hash map, heavier rows in dense
+ * LDS accumulators over windows of z.  Columns are int32 device arrays, read
+ * only during jp_agg_create.  Errors as for jp_plan_create.  Syncs. */
+typedef struct jp_agg jp_agg;
+jp_status jp_agg_create(const int32_t* r_x, const int32_t* r_y, const int32_t* r_v, int64_t n_r,
+                        const int32_t* s_z, const int32_t* s_y, const int32_t* s_u, int64_t n_s,
+                        hipStream_t stream, jp_agg** out);
+/* Count pass (number of groups per x row); asynchronous. */
+jp_status jp_agg_execute(jp_agg* a, hipStream_t stream);
+/* Number of groups and of join rows (host outputs, nullable).  JP_ESTATE
+ * before jp_agg_execute.  Syncs. */
+jp_status jp_agg_count(jp_agg* a, int64_t* groups, int64_t* out_j, hipStream_t stream);
+/* Groups [first, first + max_groups) in (x, z) order (signed int32) into
+ * caller device buffers: x and z values, counts and sums (int64).  As
+ * jp_materialize: first == groups writes nothing, first > groups is JP_ERANGE.
+ * Syncs. */
+jp_status jp_agg_materialize(jp_agg* a, int64_t first, int64_t max_groups, int32_t* out_x, int32_t* out_z,
+                             int64_t* out_count, int64_t* out_sum, int64_t* n_written, hipStream_t stream);
+/* Frees the aggregate (NULL-safe). */
+void jp_agg_destroy(jp_agg* a);
+
+/* ---------------------------------------------------- composite keys --- */
+
+/* Dictionary encoding of multi-attribute keys (paper Sec. 2.2, "Supporting
+ * Wider Range of Join-Project Operations"): a tuple of columns is mapped to
+ * one consecutive natural number, so a Join-Project whose x, y or z is a
+ * tuple of attributes runs as the single-column operation over the ids.  The
+ * id of a tuple is its rank among the distinct tuples in lexicographic order
+ * (each column compared as signed int32): id order is tuple order, so a result
+ * sorted by ids is sorted by tuples.  Parts encoded together share one
+ * dictionary (R.y and S.y must, for their ids to join).
+ *
+ * cols[p * n_cols + c] is device column c of part p, n[p] rows (n_cols in
+ * [1, 8]); ids[p] (device, n[p] int32) receives part p's ids.  The columns are
+ * read only during the call; the dictionary keeps its own copy of the distinct
+ * tuples.  JP_EINVAL for bad counts or null pointers (checked before any device
+ * work), or more than 2^31 - 1 rows over all parts.  Syncs. */
+typedef struct jp_dict jp_dict;
+jp_status jp_dict_create(int32_t n_cols, int32_t n_parts, const int32_t* const* cols, const int64_t* n,
+                         int32_t* const* ids, hipStream_t stream, jp_dict** out);
+/* Number of distinct tuples (ids are [0, n_distinct)). */
+jp_status jp_dict_size(const jp_dict* d, int64_t* n_distinct);
+/* cols_out[c][i] = column c of the tuple with id ids[i] (device arrays of n
+ * int32).  JP_ERANGE if any id lies outside [0, n_distinct).  Syncs. */
+jp_status jp_dict_decode(const jp_dict* d, const int32_t* ids, int64_t n, int32_t* const* cols_out,
+                         hipStream_t stream);
+/* Frees the dictionary (NULL-safe). */
+void jp_dict_destroy(jp_dict* d);
 
 /* -------------------------------------------------------------- digest --- */
 

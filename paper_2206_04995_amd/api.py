@@ -119,6 +119,102 @@ def join_project(r_x, r_y, s_z, s_y, opt: Optional[B.jp_options] = None, stream=
         return p.materialize()
 
 
+class Aggregate:
+    """Join-Aggregate G_{x,z} COUNT(*), SUM(R.v * S.u) (jp_agg_* in include/jp.h)."""
+
+    def __init__(self, r_x, r_y, r_v, s_z, s_y, s_u, stream=None):
+        self.stream = stream
+        self.h = B.jp_agg_create(r_x, r_y, r_v, s_z, s_y, s_u, stream)
+
+    def execute(self):
+        B.jp_agg_execute(self.h, self.stream)
+        return self
+
+    def count(self):
+        """(number of groups, number of join rows)."""
+        return B.jp_agg_count(self.h, self.stream)
+
+    def materialize(self, first: int = 0, max_groups: Optional[int] = None):
+        """Groups [first, first + max_groups) as (x, z, count, sum) device tensors."""
+        import torch
+
+        groups = self.count()[0]
+        if max_groups is None:
+            max_groups = max(0, groups - first)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        m = max(max_groups, 1)
+        ox = torch.empty(m, dtype=torch.int32, device=dev)
+        oz = torch.empty(m, dtype=torch.int32, device=dev)
+        oc = torch.empty(m, dtype=torch.int64, device=dev)
+        osum = torch.empty(m, dtype=torch.int64, device=dev)
+        n = B.jp_agg_materialize(self.h, first, max_groups, ox, oz, oc, osum, self.stream)
+        return ox[:n], oz[:n], oc[:n], osum[:n]
+
+    def close(self):
+        if self.h:
+            B.jp_agg_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Dict:
+    """Dictionary of multi-column key tuples (jp_dict_* in include/jp.h)."""
+
+    def __init__(self, parts: Sequence[Sequence], stream=None):
+        self.stream = stream
+        self.n_cols = len(parts[0])
+        self.h, self.ids = B.jp_dict_create(parts, stream)
+
+    def size(self) -> int:
+        return B.jp_dict_size(self.h)
+
+    def decode(self, ids):
+        return B.jp_dict_decode(self.h, ids, self.n_cols, self.stream)
+
+    def close(self):
+        if self.h:
+            B.jp_dict_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def join_project_composite(r_x: Sequence, r_y: Sequence, s_z: Sequence, s_y: Sequence,
+                           opt: Optional[B.jp_options] = None, stream=None):
+    """Join-Project over multi-attribute keys: x is the tuple of the r_x columns,
+    y the tuple of the join columns (r_y and s_y, same arity), z the tuple of the
+    s_z columns (lists of int32 device tensors).  Each kind is dictionary-encoded
+    (R.y and S.y in one dictionary), the plan runs on the ids, and the id pairs
+    are decoded.  Returns (x columns, z columns) of the distinct pairs, sorted
+    lexicographically by (x tuple, z tuple)."""
+    with Dict([r_x], stream) as dx, Dict([r_y, s_y], stream) as dy, Dict([s_z], stream) as dz:
+        with Plan(dx.ids[0], dy.ids[0], dz.ids[0], dy.ids[1], opt, stream) as p:
+            p.execute()
+            ix, iz = p.materialize()
+            return dx.decode(ix), dz.decode(iz)
+
+
 class Server:
     """Continuous-batching query server, see jp_server_* in include/jp.h."""
 

@@ -22,6 +22,8 @@ JP_TAU_AUTO, JP_TAU_FIXED = 0, 1
 JP_DENSE_AUTO, JP_DENSE_BITS, JP_DENSE_MFMA = 0, 1, 2
 JP_FLAG_TIMING = 1
 JP_FLAG_GRAPH = 2
+JP_FLAG_DIRECT_IDS = 4
+JP_STRATEGY_AUTO, JP_STRATEGY_HYBRID, JP_STRATEGY_CLASSICAL = 0, 1, 2
 JP_SERVER_DIGEST = 1
 JP_SERVER_KEEP = 2
 INT64_MAX = 2 ** 63 - 1
@@ -37,6 +39,8 @@ EXPORTS = [
     "jp_server_create", "jp_server_submit", "jp_server_poll", "jp_server_wait", "jp_server_stats", "jp_server_destroy",
     "jp_server_materialize", "jp_server_release", "jp_digest_pairs",
     "jp_tune", "jp_tune_clear", "jp_count_static",
+    "jp_dict_create", "jp_dict_size", "jp_dict_decode", "jp_dict_destroy",
+    "jp_agg_create", "jp_agg_execute", "jp_agg_count", "jp_agg_materialize", "jp_agg_destroy",
 ]
 
 
@@ -55,14 +59,14 @@ class jp_options(ctypes.Structure):
         ("flags", ctypes.c_int32),
         ("workspace_limit_bytes", ctypes.c_int64),
         ("window_group", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("strategy", ctypes.c_int32),
     ]
 
 
 class jp_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("n_x", "n_y", "n_z", "n_r_kept", "out_j", "tau", "n_z_dense", "k_hot", "footprint_bytes",
-                 "pivot_cover", "dense_mfma", "peak_bytes")]
+                 "pivot_cover", "dense_mfma", "peak_bytes", "map_direct", "strategy")]
 
 
 class jp_timings(ctypes.Structure):
@@ -150,6 +154,15 @@ def _load() -> ctypes.CDLL:
         "jp_tune": (st, [vp, vp, i64, vp, vp, i64, ctypes.POINTER(jp_options), vp, ctypes.POINTER(jp_tune_result)]),
         "jp_tune_clear": (st, []),
         "jp_count_static": (st, [vp, vp, i64, vp, vp, i64, ctypes.POINTER(jp_options), vp, i64p, i64p, i64p]),
+        "jp_dict_create": (st, [i32, i32, ctypes.POINTER(vp), i64p, ctypes.POINTER(vp), vp, ctypes.POINTER(vp)]),
+        "jp_dict_size": (st, [vp, i64p]),
+        "jp_dict_decode": (st, [vp, vp, i64, ctypes.POINTER(vp), vp]),
+        "jp_dict_destroy": (None, [vp]),
+        "jp_agg_create": (st, [vp, vp, vp, i64, vp, vp, vp, i64, vp, ctypes.POINTER(vp)]),
+        "jp_agg_execute": (st, [vp, vp]),
+        "jp_agg_count": (st, [vp, i64p, i64p, vp]),
+        "jp_agg_materialize": (st, [vp, i64, i64, vp, vp, vp, vp, i64p, vp]),
+        "jp_agg_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -194,8 +207,9 @@ def _ptr(t) -> int:
 
 def make_options(tau_mode: int = JP_TAU_AUTO, dense_threshold: int = 0, dense_kernel: int = JP_DENSE_AUTO,
                  k_hot_max: int = 0, workspace_limit_bytes: int = 0, flags: int = 0,
-                 window_group: int = 0) -> jp_options:
+                 window_group: int = 0, strategy: int = JP_STRATEGY_AUTO) -> jp_options:
     o = jp_options()
+    o.strategy = strategy
     o.window_group = window_group
     o.tau_mode = tau_mode
     o.dense_kernel = dense_kernel
@@ -442,3 +456,97 @@ def jp_digest_pairs(out_x, out_z, n: int, acc, stream=None):
     if not isinstance(acc, torch.Tensor) or acc.dtype != torch.int64 or not acc.is_cuda or acc.numel() < 1:
         raise TypeError("acc must be an int64 tensor on a ROCm device")
     _check(lib.jp_digest_pairs(_ptr(out_x), _ptr(out_z), n, acc.data_ptr(), _stream(stream)))
+
+
+# ------------------------------------------------------------ dictionaries
+
+
+def jp_dict_create(parts: Sequence[Sequence], stream=None) -> Tuple[int, list]:
+    """Encode the row tuples of several parts (each a list of equal-length int32
+    device columns, the same number of columns in every part) with one
+    dictionary.  Returns (handle, [ids of each part as an int32 device tensor])."""
+    import torch
+
+    n_cols = len(parts[0])
+    if any(len(p) != n_cols for p in parts):
+        raise ValueError("every part needs the same number of columns")
+    cols = (ctypes.c_void_p * (n_cols * len(parts)))()
+    ns = (ctypes.c_int64 * len(parts))()
+    ids_t = []
+    ids = (ctypes.c_void_p * len(parts))()
+    for p, part in enumerate(parts):
+        n = int(part[0].numel())
+        ns[p] = n
+        for c, col in enumerate(part):
+            if int(col.numel()) != n:
+                raise ValueError("columns of a part differ in length")
+            cols[p * n_cols + c] = _ptr(col)
+        t = torch.empty(max(n, 1), dtype=torch.int32, device=part[0].device)
+        ids_t.append(t[:n])
+        ids[p] = _ptr(t)
+    h = ctypes.c_void_p()
+    _check(lib.jp_dict_create(n_cols, len(parts), cols, ns, ids, _stream(stream), ctypes.byref(h)))
+    return h.value, ids_t
+
+
+def jp_dict_size(d: int) -> int:
+    n = ctypes.c_int64()
+    _check(lib.jp_dict_size(d, ctypes.byref(n)))
+    return n.value
+
+
+def jp_dict_decode(d: int, ids, n_cols: int, stream=None) -> list:
+    """The tuples of the given ids as n_cols int32 device tensors."""
+    import torch
+
+    n = int(ids.numel())
+    out = [torch.empty(max(n, 1), dtype=torch.int32, device=ids.device) for _ in range(n_cols)]
+    arr = (ctypes.c_void_p * n_cols)(*[_ptr(t) for t in out])
+    _check(lib.jp_dict_decode(d, _ptr(ids) if n else None, n, arr, _stream(stream)))
+    return [t[:n] for t in out]
+
+
+def jp_dict_destroy(d: int):
+    lib.jp_dict_destroy(d)
+
+
+# ---------------------------------------------------------- Join-Aggregate
+
+
+def _ptr_any(t) -> int:
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("outputs must be contiguous tensors on a ROCm device")
+    return t.data_ptr()
+
+
+def jp_agg_create(r_x, r_y, r_v, s_z, s_y, s_u, stream=None) -> int:
+    n_r, n_s = int(r_x.numel()), int(s_z.numel())
+    if int(r_y.numel()) != n_r or int(r_v.numel()) != n_r or int(s_y.numel()) != n_s or int(s_u.numel()) != n_s:
+        raise ValueError("column lengths differ")
+    h = ctypes.c_void_p()
+    _check(lib.jp_agg_create(_ptr(r_x), _ptr(r_y), _ptr(r_v), n_r, _ptr(s_z), _ptr(s_y), _ptr(s_u), n_s,
+                             _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def jp_agg_execute(a: int, stream=None):
+    _check(lib.jp_agg_execute(a, _stream(stream)))
+
+
+def jp_agg_count(a: int, stream=None) -> Tuple[int, int]:
+    g, oj = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.jp_agg_count(a, ctypes.byref(g), ctypes.byref(oj), _stream(stream)))
+    return g.value, oj.value
+
+
+def jp_agg_materialize(a: int, first: int, max_groups: int, out_x, out_z, out_count, out_sum, stream=None) -> int:
+    n = ctypes.c_int64()
+    _check(lib.jp_agg_materialize(a, first, max_groups, _ptr(out_x), _ptr(out_z), _ptr_any(out_count),
+                                  _ptr_any(out_sum), ctypes.byref(n), _stream(stream)))
+    return n.value
+
+
+def jp_agg_destroy(a: int):
+    lib.jp_agg_destroy(a)

@@ -21,6 +21,9 @@ SOURCES = [
     "dense_ec.hip",
     "dense_mfma.hip",
     "output.hip",
+    "encode.hip",
+    "classical.hip",
+    "aggregate.hip",
     "plan.cpp",
     "server.cpp",
     "tune.cpp",

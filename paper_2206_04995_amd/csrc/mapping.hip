@@ -287,6 +287,125 @@ __global__ void k_out_j(const int32_t* __restrict__ dR, const int32_t* __restric
   }
 }
 
+
+// ------------------------------------------------- direct-range mapping
+// When the values of a column fill their range densely (the key space, the sum
+// of the instances' value ranges, is within a small multiple of the column
+// length), ids need no sort (Sec. 2.2, optimisation 1: columns that already
+// hold natural numbers skip the dictionary).  A key histogram over the key
+// space gives each value's count; the exclusive scan of the presence flags
+// gives the order-preserving id of every present key, the same ids a sort
+// assigns; the exclusive scan of the counts gives each key's first position in
+// key order, and a scatter with one atomic cursor per key places the elements
+// there (order inside a key is arbitrary).
+
+// h[key(i)] += 1 for elements whose filter entry is >= 0 (all if filter is
+// null), aggregated per block in an LDS hash table like k_histogram
+__global__ void __launch_bounds__(NT) k_key_hist(const int32_t* __restrict__ v, int64_t n,
+                                                 const int32_t* __restrict__ ebase, int n_inst,
+                                                 const int64_t* __restrict__ koff, const int32_t* __restrict__ mn,
+                                                 const int32_t* __restrict__ filter, int32_t* __restrict__ h) {
+  __shared__ uint32_t key[HG_SLOTS];
+  __shared__ int32_t cnt[HG_SLOTS];
+  for (int i = threadIdx.x; i < HG_SLOTS; i += NT) {
+    key[i] = 0xFFFFFFFFu;
+    cnt[i] = 0;
+  }
+  __syncthreads();
+  const int64_t b0 = int64_t(blockIdx.x) * HG_PER_BLOCK;
+  const int64_t b1 = b0 + HG_PER_BLOCK < n ? b0 + HG_PER_BLOCK : n;
+  SegCursor<int32_t> cur(ebase, n_inst);
+  cur.seed(int32_t(b0 < n ? b0 : 0));
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += NT) {
+    if (filter && filter[i] < 0) continue;
+    const int inst = cur(int32_t(i));
+    const uint32_t k = uint32_t(koff[inst] + (int64_t(v[i]) - int64_t(mn[inst])));
+    uint32_t s = (k * 0x9E3779B1u) >> 20;  // 12-bit slot
+    bool done = false;
+    for (int probe = 0; probe < 2 && !done; ++probe) {
+      uint32_t old = atomicCAS(&key[s], 0xFFFFFFFFu, k);
+      if (old == 0xFFFFFFFFu || old == k) {
+        atomicAdd(&cnt[s], 1);
+        done = true;
+      } else {
+        s = (s + 1) & (HG_SLOTS - 1);
+      }
+    }
+    if (!done) atomicAdd(&h[k], 1);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < HG_SLOTS; i += NT)
+    if (cnt[i]) atomicAdd(&h[key[i]], cnt[i]);
+}
+
+__global__ void k_presence(const int32_t* __restrict__ cnt, int64_t n_keys, int32_t* __restrict__ pres) {
+  GRID_STRIDE(k, n_keys) { pres[k] = cnt[k] > 0 ? 1 : 0; }
+}
+
+// for every present key: its id E[key], the id's original value, and
+// optionally its count and first position C[key]; first[n_id] = C[n_keys]
+__global__ void k_key_ids(const int32_t* __restrict__ cnt, int64_t n_keys, const int32_t* __restrict__ E,
+                          const int32_t* __restrict__ C, const int64_t* __restrict__ koff,
+                          const int32_t* __restrict__ mn, int n_inst, int32_t* __restrict__ vals,
+                          int32_t* __restrict__ m, int32_t* __restrict__ first) {
+  SegCursor<int64_t> kc(koff, n_inst);
+  GRID_STRIDE(k, n_keys) {
+    const int32_t c = cnt[k];
+    if (c > 0) {
+      const int inst = kc(k);
+      const int32_t id = E[k];
+      vals[id] = int32_t(k - koff[inst] + int64_t(mn[inst]));
+      if (m) m[id] = c;
+      if (first) first[id] = C[k];
+    }
+    if (k == n_keys - 1 && first) first[E[n_keys]] = C[n_keys];
+  }
+}
+
+// out[i] = E[koff[i]] for i in [0, n_inst]
+__global__ void k_bases_from_koff(const int32_t* __restrict__ E, const int64_t* __restrict__ koff, int n_inst,
+                                  int32_t* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n_inst) out[i] = E[koff[i]];
+}
+
+// S placed in z order: position cur[zkey]++ (cur starts as the scan of the z
+// counts) receives the y key of the tuple and its z id, ready for the stable
+// sort by y that yields the CSR of S by y with ascending z inside each row
+__global__ void k_scatter_z(const int32_t* __restrict__ sz, const int32_t* __restrict__ sy, int64_t n,
+                            const int32_t* __restrict__ ebase, int n_inst, const int64_t* __restrict__ koff_z,
+                            const int32_t* __restrict__ zmin, const int64_t* __restrict__ koff_y,
+                            const int32_t* __restrict__ ymin, const int32_t* __restrict__ Ez,
+                            int32_t* __restrict__ cur, uint32_t* __restrict__ yk, uint32_t* __restrict__ zid) {
+  SegCursor<int32_t> sc(ebase, n_inst);
+  sc.seed(int32_t(chunk_first()));
+  CHUNK_LOOP(i, n, JP_CHUNK) {
+    const int inst = sc(int32_t(i));
+    const int32_t zv = sz[i], yv = sy[i];
+    const int64_t zk = koff_z[inst] + (int64_t(zv) - int64_t(zmin[inst]));
+    const int32_t p = atomicAdd(&cur[zk], 1);
+    yk[p] = uint32_t(koff_y[inst] + (int64_t(yv) - int64_t(ymin[inst])));
+    zid[p] = uint32_t(Ez[zk]);
+  }
+}
+
+// R' grouped by x: every kept R tuple (yid >= 0) writes its y id at position
+// cur[xkey]++ (cur starts as the scan of the kept x counts)
+__global__ void k_scatter_x(const int32_t* __restrict__ rx, const int32_t* __restrict__ yid, int64_t n,
+                            const int32_t* __restrict__ ebase, int n_inst, const int64_t* __restrict__ koff_x,
+                            const int32_t* __restrict__ xmin, int32_t* __restrict__ cur, int32_t* __restrict__ rcol) {
+  SegCursor<int32_t> sc(ebase, n_inst);
+  sc.seed(int32_t(chunk_first()));
+  CHUNK_LOOP(g, n, JP_CHUNK) {
+    const int32_t y = yid[g];
+    const int inst = sc(int32_t(g));
+    if (y >= 0) {
+      const int64_t xk = koff_x[inst] + (int64_t(rx[g]) - int64_t(xmin[inst]));
+      rcol[atomicAdd(&cur[xk], 1)] = y;
+    }
+  }
+}
+
 }  // namespace
 
 void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff, const int32_t* mn,
@@ -383,6 +502,53 @@ void out_j_per_inst(const int32_t* dR, const int32_t* dS, int64_t n_y, const int
   if (n_y <= 0) return;
   hipLaunchKernelGGL(k_out_j, dim3(n_inst == 1 ? grid(n_y, 1024) : grid(n_y)), dim3(NT), 0, s, dR, dS, n_y, y_base,
                      n_inst, out_j);
+  JP_LAUNCH_CHECK();
+}
+
+void key_hist(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff, const int32_t* mn,
+              const int32_t* filter, int32_t* h, hipStream_t s) {
+  if (n <= 0) return;
+  const int blocks = int((n + HG_PER_BLOCK - 1) / HG_PER_BLOCK);
+  hipLaunchKernelGGL(k_key_hist, dim3(blocks), dim3(NT), 0, s, v, n, ebase, n_inst, koff, mn, filter, h);
+  JP_LAUNCH_CHECK();
+}
+
+void presence(const int32_t* cnt, int64_t n_keys, int32_t* pres, hipStream_t s) {
+  if (n_keys <= 0) return;
+  hipLaunchKernelGGL(k_presence, dim3(grid(n_keys)), dim3(NT), 0, s, cnt, n_keys, pres);
+  JP_LAUNCH_CHECK();
+}
+
+void key_ids(const int32_t* cnt, int64_t n_keys, const int32_t* E, const int32_t* C, const int64_t* koff,
+             const int32_t* mn, int n_inst, int32_t* vals, int32_t* m, int32_t* first, hipStream_t s) {
+  if (n_keys <= 0) {
+    if (first) fill_i32(first, 1, 0, s);
+    return;
+  }
+  hipLaunchKernelGGL(k_key_ids, dim3(grid(n_keys)), dim3(NT), 0, s, cnt, n_keys, E, C, koff, mn, n_inst, vals, m,
+                     first);
+  JP_LAUNCH_CHECK();
+}
+
+void bases_from_koff(const int32_t* E, const int64_t* koff, int n_inst, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_bases_from_koff, dim3((n_inst + 1 + NT - 1) / NT), dim3(NT), 0, s, E, koff, n_inst, out);
+  JP_LAUNCH_CHECK();
+}
+
+void scatter_z(const int32_t* sz, const int32_t* sy, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff_z,
+               const int32_t* zmin, const int64_t* koff_y, const int32_t* ymin, const int32_t* Ez, int32_t* cur,
+               uint32_t* yk, uint32_t* zid, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scatter_z, dim3(chunk_grid(n)), dim3(NT), 0, s, sz, sy, n, ebase, n_inst, koff_z, zmin, koff_y,
+                     ymin, Ez, cur, yk, zid);
+  JP_LAUNCH_CHECK();
+}
+
+void scatter_x(const int32_t* rx, const int32_t* yid, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff_x,
+               const int32_t* xmin, int32_t* cur, int32_t* rcol, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scatter_x, dim3(chunk_grid(n)), dim3(NT), 0, s, rx, yid, n, ebase, n_inst, koff_x, xmin, cur,
+                     rcol);
   JP_LAUNCH_CHECK();
 }
 

@@ -9,11 +9,13 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/jp.h"
+#include "classical.h"
 #include "common.h"
 #include "plan_impl.h"
 #include "prim.h"
@@ -214,25 +216,49 @@ void Plan::build(const jp_instance* inst, int n, const jp_options* o, hipStream_
 }
 
 // ---------------------------------------------------------------- mapping
+// With JP_FLAG_DIRECT_IDS, a key space of at most this many keys per column
+// element is mapped directly (key histogram, scans, scatter) instead of by
+// radix sort.
+constexpr int64_t DIRECT_KEYS_PER_ELEM = 2;
+constexpr int64_t DIRECT_KEYS_SLACK = 65536;
+
+// Key offsets as key_layout, without its limit: returns koff[n] (the key space).
+int64_t key_space(const std::vector<int32_t>& mn, const std::vector<int32_t>& mx, std::vector<int64_t>& koff) {
+  const int n = int(mn.size());
+  koff.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) koff[i + 1] = koff[i] + (mn[i] <= mx[i] ? int64_t(mx[i]) - int64_t(mn[i]) + 1 : 0);
+  return koff[n];
+}
+
+bool direct_ok(int64_t keys, int64_t n_elem) {
+  return keys <= DIRECT_KEYS_PER_ELEM * n_elem + DIRECT_KEYS_SLACK && keys < (int64_t(1) << 31) - 1;
+}
+
 void Plan::map(hipStream_t s) {
   const int n = n_inst;
   Arena T(&B);  // temporaries of the mapping stage
+  const bool sort_ids = (opt.flags & JP_FLAG_DIRECT_IDS) == 0;
   int32_t* mm = T.alloc<int32_t>(6 * int64_t(n), s);
   int32_t *zmin = mm, *zmax = mm + n, *ymin = mm + 2 * n, *ymax = mm + 3 * n, *xmin = mm + 4 * n, *xmax = mm + 5 * n;
   seg_minmax(sz, NS, d_sbase, n, zmin, zmax, s);
   seg_minmax(sy, NS, d_sbase, n, ymin, ymax, s);
-  std::vector<int32_t> h_mm(4 * size_t(n));
-  d2h(h_mm.data(), mm, 4 * size_t(n), s);
+  if (!sort_ids) seg_minmax(rx, NR, d_rbase, n, xmin, xmax, s);  // over all of R: the direct x mapping's range
+  std::vector<int32_t> h_mm(6 * size_t(n));
+  d2h(h_mm.data(), mm, (sort_ids ? 4 : 6) * size_t(n), s);
   sync(s);
-  std::vector<int32_t> hzmin(h_mm.begin(), h_mm.begin() + n), hzmax(h_mm.begin() + n, h_mm.begin() + 2 * n);
-  std::vector<int32_t> hymin(h_mm.begin() + 2 * n, h_mm.begin() + 3 * n), hymax(h_mm.begin() + 3 * n, h_mm.end());
+  auto part = [&](int k) { return std::vector<int32_t>(h_mm.begin() + k * n, h_mm.begin() + (k + 1) * n); };
   std::vector<int64_t> koff_z, koff_y, koff_x;
-  int zbits = key_layout(hzmin, hzmax, koff_z);
-  int ybits = key_layout(hymin, hymax, koff_y);
+  int zbits = key_layout(part(0), part(1), koff_z);
+  int ybits = key_layout(part(2), part(3), koff_y);
+  const bool direct_z = !sort_ids && direct_ok(koff_z[n], NS);
+  bool direct_x = false;
+  if (!sort_ids) direct_x = direct_ok(key_space(part(4), part(5), koff_x), NR);
   int64_t* d_koff = T.alloc<int64_t>(3 * (int64_t(n) + 1), s);
   int64_t *dkz = d_koff, *dky = d_koff + (n + 1), *dkx = d_koff + 2 * (n + 1);
   h2d(dkz, koff_z.data(), n + 1, s);
   h2d(dky, koff_y.data(), n + 1, s);
+  if (direct_x) h2d(dkx, koff_x.data(), n + 1, s);
+  map_direct = (direct_z ? 1 : 0) | (direct_x ? 2 : 0);
 
   const int64_t NSa = std::max<int64_t>(NS, 1);
   uint32_t* k1 = T.alloc<uint32_t>(NSa, s);
@@ -240,23 +266,52 @@ void Plan::map(hipStream_t s) {
   uint32_t* k2 = T.alloc<uint32_t>(NSa, s);
   uint32_t* v2 = T.alloc<uint32_t>(NSa, s);
   int32_t* flags = T.alloc<int32_t>(std::max<int64_t>(std::max(NS, NR), 1), s);
+  int32_t* d_counts = T.alloc<int32_t>(4, s);
 
-  // S sorted by (instance, z): z ids, m_z
-  make_keys(sz, NS, d_sbase, n, dkz, zmin, k1, v1, sy, s);  // S.y rides along
-  const SortSegments sseg_z{n, d_sbase, dkz, h_sbase};
-  bool alt = radix_sort_pairs(k1, v1, k2, v2, NS, n > 1 ? local_bits(koff_z) : zbits, s, T, &sseg_z);
-  uint32_t *zk = alt ? k2 : k1, *zp = alt ? v2 : v1;
-  int32_t* Ez = T.alloc<int32_t>(NS + 1, s);
-  zfirst = A.alloc<int32_t>(NS + 1, s);
+  // z ids and m_z; then S in z order with its y keys and z ids (yk, yp) ready
+  // for the stable sort by y
+  uint32_t *yk, *yp, *ok, *op;
   vals_z = A.alloc<int32_t>(NSa, s);
-  run_ids(zk, NS, dkz, zmin, n, Ez, zfirst, vals_z, s, T);
   z_base = A.alloc<int32_t>(n + 1, s);
-  gather_bases(Ez, d_sbase, n, z_base, s);
+  if (direct_z) {
+    const int64_t K = koff_z[n];
+    int32_t* cnt = T.alloc<int32_t>(K + 1, s);
+    fill_i32(cnt, K + 1, 0, s);
+    key_hist(sz, NS, d_sbase, n, dkz, zmin, nullptr, cnt, s);
+    int32_t* pres = T.alloc<int32_t>(std::max<int64_t>(K, 1), s);
+    presence(cnt, K, pres, s);
+    int32_t* Ezk = T.alloc<int32_t>(K + 1, s);
+    scan_excl_i32(pres, Ezk, K, s, T);
+    int32_t* Czk = T.alloc<int32_t>(K + 1, s);
+    scan_excl_i32(cnt, Czk, K, s, T);
+    m_z = A.alloc<int32_t>(std::max<int64_t>(std::min(K, NS), 1), s);
+    key_ids(cnt, K, Ezk, Czk, dkz, zmin, n, vals_z, m_z, nullptr, s);
+    bases_from_koff(Ezk, dkz, n, z_base, s);
+    scatter_z(sz, sy, NS, d_sbase, n, dkz, zmin, dky, ymin, Ezk, Czk, k1, v1, s);
+    JP_HIP(hipMemcpyAsync(d_counts + 0, Ezk + K, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    yk = k1;
+    yp = v1;
+    ok = k2;
+    op = v2;
+  } else {
+    // S sorted by (instance, z): z ids, m_z
+    make_keys(sz, NS, d_sbase, n, dkz, zmin, k1, v1, sy, s);  // S.y rides along
+    const SortSegments sseg_z{n, d_sbase, dkz, h_sbase};
+    bool alt = radix_sort_pairs(k1, v1, k2, v2, NS, n > 1 ? local_bits(koff_z) : zbits, s, T, &sseg_z);
+    uint32_t *zk = alt ? k2 : k1, *zp = alt ? v2 : v1;
+    int32_t* Ez = T.alloc<int32_t>(NS + 1, s);
+    zfirst = A.alloc<int32_t>(NS + 1, s);
+    run_ids(zk, NS, dkz, zmin, n, Ez, zfirst, vals_z, s, T);
+    gather_bases(Ez, d_sbase, n, z_base, s);
+    JP_HIP(hipMemcpyAsync(d_counts + 0, Ez + NS, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    yk = alt ? k1 : k2;  // the free pair
+    yp = alt ? v1 : v2;
+    make_keys_carried(zp, NS, d_sbase, n, dky, ymin, Ez, yk, yp, s);
+    ok = zk;  // reuse the z-sorted pair as scratch
+    op = zp;
+  }
 
   // S sorted by (instance, y), z ascending inside each y: CSR of S by y
-  uint32_t *yk = alt ? k1 : k2, *yp = alt ? v1 : v2;  // the free pair
-  make_keys_carried(zp, NS, d_sbase, n, dky, ymin, Ez, yk, yp, s);
-  uint32_t *ok = zk, *op = zp;  // reuse the z-sorted pair as scratch
   const SortSegments sseg_y{n, d_sbase, dky, h_sbase};
   bool alt2 = radix_sort_pairs(yk, yp, ok, op, NS, n > 1 ? local_bits(koff_y) : ybits, s, T, &sseg_y);
   uint32_t *syk = alt2 ? ok : yk, *syp = alt2 ? op : yp;
@@ -268,8 +323,9 @@ void Plan::map(hipStream_t s) {
   gather_bases(Ey, d_sbase, n, y_base, s);
   scol = A.alloc<int32_t>(NSa, s);
   if (NS) JP_HIP(hipMemcpyAsync(scol, syp, NS * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  JP_HIP(hipMemcpyAsync(d_counts + 1, Ey + NS, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
 
-  // semi-join of R on S.y (Sec. 2.2, optimisation 2), then R' sorted by (instance, x)
+  // semi-join of R on S.y (Sec. 2.2, optimisation 2), then R' grouped by (instance, x)
   const int64_t NRa = std::max<int64_t>(NR, 1);
   int32_t* yid = T.alloc<int32_t>(NRa, s);
   const int64_t y_keys = koff_y[n];
@@ -280,56 +336,85 @@ void Plan::map(hipStream_t s) {
   } else {
     semijoin(ry, NR, d_rbase, n, vals_y, y_base, flags, yid, s);
   }
-  int32_t* Ek = T.alloc<int32_t>(NR + 1, s);
-  scan_excl_i32(flags, Ek, NR, s, T);
-  int32_t* rpx = T.alloc<int32_t>(NRa, s);
-  uint32_t* rpy = T.alloc<uint32_t>(NRa, s);
-  compact_r(rx, yid, flags, Ek, NR, rpx, reinterpret_cast<int32_t*>(rpy), s);
   d_rpbase = A.alloc<int32_t>(n + 1, s);
-  gather_bases(Ek, d_rbase, n, d_rpbase, s);
-
-  int32_t counts[3];
-  int32_t* d_counts = T.alloc<int32_t>(3, s);
-  JP_HIP(hipMemcpyAsync(d_counts + 0, Ez + NS, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  JP_HIP(hipMemcpyAsync(d_counts + 1, Ey + NS, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  JP_HIP(hipMemcpyAsync(d_counts + 2, Ek + NR, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  d2h(counts, d_counts, 3, s);
   h_rpbase.resize(n + 1);
-  d2h(h_rpbase.data(), d_rpbase, n + 1, s);
-  sync(s);
-  NZ = counts[0];
-  NY = counts[1];
-  NRp = counts[2];
-
-  seg_minmax(rpx, NRp, d_rpbase, n, xmin, xmax, s);
-  std::vector<int32_t> hx(2 * size_t(n));
-  d2h(hx.data(), xmin, 2 * size_t(n), s);
-  sync(s);
-  std::vector<int32_t> hxmin(hx.begin(), hx.begin() + n), hxmax(hx.begin() + n, hx.end());
-  int xbits = key_layout(hxmin, hxmax, koff_x);
-  h2d(dkx, koff_x.data(), n + 1, s);
-
-  const int64_t NRpa = std::max<int64_t>(NRp, 1);
-  uint32_t* xk = T.alloc<uint32_t>(NRpa, s);
-  uint32_t* xk2 = T.alloc<uint32_t>(NRpa, s);
-  uint32_t* xp2 = T.alloc<uint32_t>(NRpa, s);
-  make_keys(rpx, NRp, d_rpbase, n, dkx, xmin, xk, nullptr, nullptr, s);
-  const SortSegments sseg_x{n, d_rpbase, dkx, h_rpbase};
-  bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, n > 1 ? local_bits(koff_x) : xbits, s, T, &sseg_x);
-  uint32_t *sxk = alt3 ? xk2 : xk, *sxp = alt3 ? xp2 : rpy;
-  int32_t* Ex = T.alloc<int32_t>(NRp + 1, s);
-  rptr = A.alloc<int32_t>(NRp + 1, s);
-  vals_x = A.alloc<int32_t>(NRpa, s);
-  run_ids(sxk, NRp, dkx, xmin, n, Ex, rptr, vals_x, s, T);
+  int32_t counts[4];
   x_base = A.alloc<int32_t>(n + 1, s);
-  gather_bases(Ex, d_rpbase, n, x_base, s);
-  rcol = A.alloc<int32_t>(NRpa, s);
-  if (NRp) JP_HIP(hipMemcpyAsync(rcol, sxp, NRp * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  if (direct_x) {
+    // x ids over the kept tuples' keys; R' rows by a scatter with per-key cursors
+    const int64_t K = koff_x[n];
+    int32_t* cnt = T.alloc<int32_t>(K + 1, s);
+    fill_i32(cnt, K + 1, 0, s);
+    key_hist(rx, NR, d_rbase, n, dkx, xmin, yid, cnt, s);
+    int32_t* pres = T.alloc<int32_t>(std::max<int64_t>(K, 1), s);
+    presence(cnt, K, pres, s);
+    int32_t* Exk = T.alloc<int32_t>(K + 1, s);
+    scan_excl_i32(pres, Exk, K, s, T);
+    int32_t* Cxk = T.alloc<int32_t>(K + 1, s);
+    scan_excl_i32(cnt, Cxk, K, s, T);
+    bases_from_koff(Cxk, dkx, n, d_rpbase, s);
+    bases_from_koff(Exk, dkx, n, x_base, s);
+    JP_HIP(hipMemcpyAsync(d_counts + 2, Cxk + K, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    JP_HIP(hipMemcpyAsync(d_counts + 3, Exk + K, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    d2h(counts, d_counts, 4, s);
+    d2h(h_rpbase.data(), d_rpbase, n + 1, s);
+    sync(s);
+    NZ = counts[0];
+    NY = counts[1];
+    NRp = counts[2];
+    NX = counts[3];
+    const int64_t NRpa = std::max<int64_t>(NRp, 1);
+    rptr = A.alloc<int32_t>(NX + 1, s);
+    vals_x = A.alloc<int32_t>(std::max<int64_t>(NX, 1), s);
+    key_ids(cnt, K, Exk, Cxk, dkx, xmin, n, vals_x, nullptr, rptr, s);
+    rcol = A.alloc<int32_t>(NRpa, s);
+    scatter_x(rx, yid, NR, d_rbase, n, dkx, xmin, Cxk, rcol, s);
+  } else {
+    int32_t* Ek = T.alloc<int32_t>(NR + 1, s);
+    scan_excl_i32(flags, Ek, NR, s, T);
+    int32_t* rpx = T.alloc<int32_t>(NRa, s);
+    uint32_t* rpy = T.alloc<uint32_t>(NRa, s);
+    compact_r(rx, yid, flags, Ek, NR, rpx, reinterpret_cast<int32_t*>(rpy), s);
+    gather_bases(Ek, d_rbase, n, d_rpbase, s);
+    JP_HIP(hipMemcpyAsync(d_counts + 2, Ek + NR, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    d2h(counts, d_counts, 3, s);
+    d2h(h_rpbase.data(), d_rpbase, n + 1, s);
+    sync(s);
+    NZ = counts[0];
+    NY = counts[1];
+    NRp = counts[2];
+
+    seg_minmax(rpx, NRp, d_rpbase, n, xmin, xmax, s);
+    std::vector<int32_t> hx(2 * size_t(n));
+    d2h(hx.data(), xmin, 2 * size_t(n), s);
+    sync(s);
+    std::vector<int32_t> hxmin(hx.begin(), hx.begin() + n), hxmax(hx.begin() + n, hx.end());
+    int xbits = key_layout(hxmin, hxmax, koff_x);
+    h2d(dkx, koff_x.data(), n + 1, s);
+
+    const int64_t NRpa = std::max<int64_t>(NRp, 1);
+    uint32_t* xk = T.alloc<uint32_t>(NRpa, s);
+    uint32_t* xk2 = T.alloc<uint32_t>(NRpa, s);
+    uint32_t* xp2 = T.alloc<uint32_t>(NRpa, s);
+    make_keys(rpx, NRp, d_rpbase, n, dkx, xmin, xk, nullptr, nullptr, s);
+    const SortSegments sseg_x{n, d_rpbase, dkx, h_rpbase};
+    bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, n > 1 ? local_bits(koff_x) : xbits, s, T, &sseg_x);
+    uint32_t *sxk = alt3 ? xk2 : xk, *sxp = alt3 ? xp2 : rpy;
+    int32_t* Ex = T.alloc<int32_t>(NRp + 1, s);
+    rptr = A.alloc<int32_t>(NRp + 1, s);
+    vals_x = A.alloc<int32_t>(NRpa, s);
+    run_ids(sxk, NRp, dkx, xmin, n, Ex, rptr, vals_x, s, T);
+    gather_bases(Ex, d_rpbase, n, x_base, s);
+    rcol = A.alloc<int32_t>(NRpa, s);
+    if (NRp) JP_HIP(hipMemcpyAsync(rcol, sxp, NRp * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  }
 
   // degree statistics (Sec. 2.6): m_z, d_R(y), d_S(y), OUT_J per instance
   const int64_t NYa = std::max<int64_t>(NY, 1);
-  m_z = A.alloc<int32_t>(std::max<int64_t>(NZ, 1), s);
-  run_lengths(zfirst, NZ, m_z, s);
+  if (!direct_z) {
+    m_z = A.alloc<int32_t>(std::max<int64_t>(NZ, 1), s);
+    run_lengths(zfirst, NZ, m_z, s);
+  }
   dR = A.alloc<int32_t>(NYa, s);
   dS = A.alloc<int32_t>(NYa, s);
   fill_i32(dR, NY, 0, s);
@@ -949,6 +1034,8 @@ void Plan::stats(int i, jp_stats* st) const {
   st->footprint_bytes = n_inst == 1 ? A.bytes() : A.bytes() / n_inst;
   st->dense_mfma = use_mfma ? 1 : 0;
   st->peak_bytes = B.peak;
+  st->map_direct = map_direct;
+  st->strategy = JP_STRATEGY_HYBRID;
   st->pivot_cover = (n_piv > 0 && h_piv[i] >= 0) ? int64_t(h_zdbase[i + 1] - h_zdbase[i]) -
                                                        int64_t(ds[1].h_base[i + 1] - ds[1].h_base[i])
                                                  : 0;
@@ -960,6 +1047,7 @@ void Plan::stats(int i, jp_stats* st) const {
 
 struct jp_plan {
   Plan p;
+  std::unique_ptr<ClassicalPlan> c;  // set when the plan runs the classical path
 };
 struct jp_batch {
   Plan p;
@@ -979,11 +1067,11 @@ jp_status check_opt(const jp_options* o) {
   if (o->tau_mode != JP_TAU_AUTO && o->tau_mode != JP_TAU_FIXED) return fail(JP_EINVAL, "bad tau_mode");
   if (o->dense_kernel < 0 || o->dense_kernel > 2) return fail(JP_EINVAL, "bad dense_kernel");
   if (o->k_hot_max < 0 || o->k_hot_max > 1024) return fail(JP_EINVAL, "k_hot_max must be in [0, 1024]");
-  if (o->flags & ~(JP_FLAG_TIMING | JP_FLAG_GRAPH)) return fail(JP_EINVAL, "unknown flag bits");
+  if (o->flags & ~(JP_FLAG_TIMING | JP_FLAG_GRAPH | JP_FLAG_DIRECT_IDS)) return fail(JP_EINVAL, "unknown flag bits");
   if (o->workspace_limit_bytes < 0) return fail(JP_EINVAL, "negative workspace limit");
   if (o->tau_mode == JP_TAU_FIXED && o->dense_threshold < -1) return fail(JP_EINVAL, "dense_threshold < -1");
   if (o->window_group < 0 || o->window_group > 64) return fail(JP_EINVAL, "window_group must be in [0, 64]");
-  if (o->reserved != 0) return fail(JP_EINVAL, "reserved option field must be 0");
+  if (o->strategy < JP_STRATEGY_AUTO || o->strategy > JP_STRATEGY_CLASSICAL) return fail(JP_EINVAL, "bad strategy");
   return JP_OK;
 }
 
@@ -1033,6 +1121,8 @@ jp_status jp_count_static(const int32_t* r_x, const int32_t* r_y, int64_t n_r, c
   if ((st = check_opt(opt)) != JP_OK) return st;
   if (opt && (opt->flags & (JP_FLAG_TIMING | JP_FLAG_GRAPH)))
     return fail(JP_EINVAL, "jp_count_static takes neither JP_FLAG_TIMING nor JP_FLAG_GRAPH");
+  if (opt && opt->strategy == JP_STRATEGY_CLASSICAL)
+    return fail(JP_EINVAL, "jp_count_static runs the hybrid path");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
     (void)hipGetLastError();
@@ -1068,10 +1158,30 @@ jp_status jp_plan_create(const int32_t* r_x, const int32_t* r_y, int64_t n_r, co
   if ((st = check_cols(r_x, r_y, n_r, "R")) != JP_OK) return st;
   if ((st = check_cols(s_z, s_y, n_s, "S")) != JP_OK) return st;
   if ((st = check_opt(opt)) != JP_OK) return st;
+  const int strat = opt ? opt->strategy : JP_STRATEGY_AUTO;
+  if (strat == JP_STRATEGY_CLASSICAL && (opt->flags & JP_FLAG_GRAPH))
+    return fail(JP_EINVAL, "the classical path takes no JP_FLAG_GRAPH");
   jp_plan* p = new (std::nothrow) jp_plan();
   if (!p) return fail(JP_ENOMEM, "host allocation failed");
   jp_instance in{r_x, r_y, s_z, s_y, n_r, n_s};
-  st = guarded([&] { p->p.build(&in, 1, opt, stream); });
+  st = guarded([&] {
+    // f1 (Sec. 2.6): the classical solution when its deduplication costs less than the mapping
+    bool classical = strat == JP_STRATEGY_CLASSICAL;
+    if (strat == JP_STRATEGY_AUTO && (!opt || (opt->tau_mode == JP_TAU_AUTO && opt->dense_kernel == JP_DENSE_AUTO &&
+                                               !(opt->flags & JP_FLAG_GRAPH))))
+      classical = f1_prefers_classical(estimate_out_j(r_y, n_r, s_y, n_s, stream), n_r, n_s);
+    if (classical) {
+      p->c.reset(new ClassicalPlan());
+      p->c->arena_limit(opt ? opt->workspace_limit_bytes : 0);
+      p->c->build(r_x, r_y, n_r, s_z, s_y, n_s, opt && (opt->flags & JP_FLAG_TIMING), stream);
+      if (p->c->out_j > JP_CLASSICAL_MAX_OUT_J) {
+        if (strat == JP_STRATEGY_CLASSICAL)
+          throw Error(JP_EINVAL, "the classical path takes at most 2^30 join rows");
+        p->c.reset();  // the estimate was too low: the hybrid path
+      }
+    }
+    if (!p->c) p->p.build(&in, 1, opt, stream);
+  });
   if (st != JP_OK) {
     jp_plan_destroy(p);
     return st;
@@ -1082,11 +1192,19 @@ jp_status jp_plan_create(const int32_t* r_x, const int32_t* r_y, int64_t n_r, co
 
 jp_status jp_execute(jp_plan* p, hipStream_t stream) {
   if (!p) return fail(JP_EINVAL, "plan is null");
+  if (p->c) return guarded([&] { p->c->execute(stream); });
   return guarded([&] { p->p.execute(stream); });
 }
 
 jp_status jp_count(jp_plan* p, int64_t* total, int64_t* dense, int64_t* sparse, hipStream_t stream) {
   if (!p) return fail(JP_EINVAL, "plan is null");
+  if (p->c)
+    return guarded([&] {
+      p->c->fetch_total(stream);
+      if (total) *total = p->c->total;
+      if (dense) *dense = 0;
+      if (sparse) *sparse = p->c->total;
+    });
   return guarded([&] {
     p->p.fetch_totals(stream);
     if (total) *total = p->p.h_tot[0];
@@ -1102,12 +1220,14 @@ jp_status jp_materialize(jp_plan* p, jp_part part, int64_t first, int64_t max_pa
   if (first < 0 || max_pairs < 0) return fail(JP_EINVAL, "negative first or max_pairs");
   if (max_pairs > 0 && (!out_x || !out_z)) return fail(JP_EINVAL, "null output with max_pairs > 0");
   *n_written = 0;
+  if (p->c) return guarded([&] { *n_written = p->c->materialize(int(part), first, max_pairs, out_x, out_z, stream); });
   return guarded([&] { *n_written = p->p.materialize(0, int(part), first, max_pairs, out_x, out_z, stream); });
 }
 
 jp_status jp_row_info(jp_plan* p, jp_part part, int32_t* x_values, int64_t* row_offsets, hipStream_t stream) {
   if (!p) return fail(JP_EINVAL, "plan is null");
   if (part < JP_PART_ALL || part > JP_PART_SPARSE) return fail(JP_EINVAL, "bad part");
+  if (p->c) return guarded([&] { p->c->row_info(int(part), x_values, row_offsets, stream); });
   return guarded([&] {
     Plan& q = p->p;
     if (x_values) d2h(x_values, q.vals_x, size_t(q.NX), stream);
@@ -1122,6 +1242,7 @@ jp_status jp_row_info(jp_plan* p, jp_part part, int32_t* x_values, int64_t* row_
 
 jp_status jp_dense_z(jp_plan* p, int32_t* z_values, hipStream_t stream) {
   if (!p) return fail(JP_EINVAL, "plan is null");
+  if (p->c) return JP_OK;  // the classical path has no dense z
   return guarded([&] {
     Plan& q = p->p;
     if (q.NZd > 0 && z_values) {
@@ -1137,23 +1258,31 @@ jp_status jp_dense_z(jp_plan* p, int32_t* z_values, hipStream_t stream) {
 
 jp_status jp_plan_stats(const jp_plan* p, jp_stats* s) {
   if (!p || !s) return fail(JP_EINVAL, "null argument");
-  p->p.stats(0, s);
+  if (p->c) p->c->stats(s);
+  else p->p.stats(0, s);
   return JP_OK;
 }
 
 jp_status jp_plan_timings(jp_plan* p, jp_timings* t, hipStream_t stream) {
   if (!p || !t) return fail(JP_EINVAL, "null argument");
+  if (p->c) return guarded([&] { p->c->timings(t, stream); });
   return guarded([&] { p->p.timings(t, stream); });
 }
 
 jp_status jp_plan_work(jp_plan* p, jp_timings* t, hipStream_t stream) {
   if (!p || !t) return fail(JP_EINVAL, "null argument");
+  if (p->c)
+    return guarded([&] {
+      if (!p->c->executed) throw Error(JP_ESTATE, "work counters need a jp_execute");
+      std::memset(t, 0, sizeof(*t));
+    });
   return guarded([&] { p->p.work(t, stream); });
 }
 
 void jp_plan_destroy(jp_plan* p) {
   if (!p) return;
   if (p->p.stream_used) (void)hipStreamSynchronize(p->p.stream);
+  if (p->c) (void)hipStreamSynchronize(p->c->stream);
   delete p;
 }
 
@@ -1172,6 +1301,8 @@ jp_status jp_batch_create(const jp_instance* inst, int32_t n_inst, const jp_opti
   }
   if (sr > INT32_MAX || ss > INT32_MAX) return fail(JP_EINVAL, "batch holds more than 2^31-1 tuples per side");
   if ((st = check_opt(opt)) != JP_OK) return st;
+  if (opt && opt->strategy == JP_STRATEGY_CLASSICAL)
+    return fail(JP_EINVAL, "batches run the hybrid path (JP_STRATEGY_CLASSICAL is for single plans)");
   jp_batch* b = new (std::nothrow) jp_batch();
   if (!b) return fail(JP_ENOMEM, "host allocation failed");
   st = guarded([&] { b->p.build(inst, n_inst, opt, stream); });

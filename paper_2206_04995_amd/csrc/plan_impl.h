@@ -48,6 +48,7 @@ struct Plan {
   bool executed = false;
 
   int64_t NR = 0, NS = 0, NRp = 0, NX = 0, NY = 0, NZ = 0, NZd = 0, NSp = 0;
+  int map_direct = 0;  // bit 0: z ids by the direct-range mapping, bit 1: x ids
   std::vector<int32_t> h_rbase, h_sbase, h_rpbase, h_xbase, h_ybase, h_zbase, h_zdbase;
   std::vector<int64_t> h_outj, h_tau, h_tot;
   std::vector<TuneRec> h_rec;  // per instance

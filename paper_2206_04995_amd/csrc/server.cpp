@@ -399,6 +399,8 @@ jp_status jp_server_create(const jp_server_config* cfg, jp_server** out) {
     return sfail(JP_EINVAL, "server options take neither JP_FLAG_TIMING nor JP_FLAG_GRAPH");
   jp_status st = jp::check_options(&cfg->opt);
   if (st != JP_OK) return st;
+  if (cfg->opt.strategy == JP_STRATEGY_CLASSICAL)
+    return sfail(JP_EINVAL, "the server runs the hybrid path (JP_STRATEGY_CLASSICAL is for single plans)");
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || cfg->device < 0 || cfg->device >= n)
     return sfail(JP_EINVAL, "bad device");

@@ -48,6 +48,25 @@ void semijoin_direct(const int32_t* ry, int64_t n, const int32_t* ebase, int n_i
 // stable compaction of R to the kept tuples
 void compact_r(const int32_t* rx, const int32_t* yid, const int32_t* keep, const int32_t* E, int64_t n,
                int32_t* out_x, int32_t* out_y, hipStream_t s);
+// Direct-range mapping (key space = the instances' stacked value ranges):
+// h[key(v[i])] += 1 for every i with filter[i] >= 0 (filter may be null)
+void key_hist(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff, const int32_t* mn,
+              const int32_t* filter, int32_t* h, hipStream_t s);
+// pres[k] = cnt[k] > 0
+void presence(const int32_t* cnt, int64_t n_keys, int32_t* pres, hipStream_t s);
+// for each present key k (cnt[k] > 0): id E[k], vals[id] = its value, m[id] = cnt[k] and
+// first[id] = C[k] (m, first nullable); first[E[n_keys]] = C[n_keys]
+void key_ids(const int32_t* cnt, int64_t n_keys, const int32_t* E, const int32_t* C, const int64_t* koff,
+             const int32_t* mn, int n_inst, int32_t* vals, int32_t* m, int32_t* first, hipStream_t s);
+// out[i] = E[koff[i]] for i in [0, n_inst]
+void bases_from_koff(const int32_t* E, const int64_t* koff, int n_inst, int32_t* out, hipStream_t s);
+// S into z order: position cur[zkey]++ gets the tuple's y key and z id Ez[zkey]
+void scatter_z(const int32_t* sz, const int32_t* sy, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff_z,
+               const int32_t* zmin, const int64_t* koff_y, const int32_t* ymin, const int32_t* Ez, int32_t* cur,
+               uint32_t* yk, uint32_t* zid, hipStream_t s);
+// kept R tuples (yid >= 0) grouped by x: rcol[cur[xkey]++] = yid
+void scatter_x(const int32_t* rx, const int32_t* yid, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff_x,
+               const int32_t* xmin, int32_t* cur, int32_t* rcol, hipStream_t s);
 // m[i] = first[i + 1] - first[i]
 void run_lengths(const int32_t* first, int64_t n_id, int32_t* m, hipStream_t s);
 void histogram(const uint32_t* v, int64_t n, int32_t* h, hipStream_t s);

@@ -98,12 +98,13 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
     set_last_error("bad columns");
     return JP_EINVAL;
   }
-  if (opt && (opt->flags & ~(JP_FLAG_TIMING | JP_FLAG_GRAPH))) {
+  if (opt && (opt->flags & ~(JP_FLAG_TIMING | JP_FLAG_GRAPH | JP_FLAG_DIRECT_IDS))) {
     set_last_error("unknown flag bits");
     return JP_EINVAL;
   }
   if (opt && (opt->window_group < 0 || opt->window_group > 64 || opt->k_hot_max < 0 || opt->k_hot_max > 1024 ||
-              opt->dense_kernel < 0 || opt->dense_kernel > 2 || opt->reserved != 0)) {
+              opt->dense_kernel < 0 || opt->dense_kernel > 2 || opt->strategy < 0 ||
+              opt->strategy > JP_STRATEGY_HYBRID)) {
     set_last_error("bad options");
     return JP_EINVAL;
   }

@@ -46,14 +46,14 @@ def test_invalid_arguments_rejected_before_device_work():
     assert lib.jp_plan_create(one, one, 2 ** 31, one, one, 1, None, None, ctypes.byref(h)) == B.JP_EINVAL
     # bad options
     for kw in ({"tau_mode": 7}, {"dense_kernel": 9}, {"k_hot_max": 5000}, {"workspace_limit_bytes": -1},
-               {"window_group": 65}, {"window_group": -1}, {"reserved": 1},
+               {"window_group": 65}, {"window_group": -1}, {"strategy": 3}, {"strategy": -1},
                {"tau_mode": 1, "dense_threshold": -2}):
         o = P.make_options()
         for k, v in kw.items():
             setattr(o, k, v)
         assert lib.jp_plan_create(one, one, 1, one, one, 1, ctypes.byref(o), None, ctypes.byref(h)) == B.JP_EINVAL
     o = P.make_options()
-    o.flags = 4  # not a defined JP_FLAG_* bit
+    o.flags = 8  # not a defined JP_FLAG_* bit
     assert lib.jp_plan_create(one, one, 1, one, one, 1, ctypes.byref(o), None, ctypes.byref(h)) == B.JP_EINVAL
     # null plan everywhere
     n = ctypes.c_int64()

@@ -119,3 +119,88 @@ def test_dense_1e7_mfma_equals_bits_and_rows():
         q.execute()
         assert q.stats()["dense_mfma"] == 0
         assert q.count() == total
+
+
+SKEWED_GOLD = os.path.join(os.path.dirname(__file__), "golden", "skewed_1e7.json")
+BATCHED_GOLD = os.path.join(os.path.dirname(__file__), "golden", "batched_4096.json")
+
+
+def _device_digest(ox, oz, n):
+    import torch
+    import paper_2206_04995_amd as P
+
+    acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    if n:
+        P.jp_digest_pairs(ox, oz, n, acc)
+    return int(acc.cpu().numpy().view(np.uint64)[0])
+
+
+def test_skewed_1e7_total_and_golden_rows():
+    """The skewed query's total count and OUT_J equal the oracle's, and every
+    1000th distinct x of R plus the 100 heaviest rows equal the oracle's rows in
+    count and digest (stored by tests/golden/make_fullsize.py)."""
+    import paper_2206_04995_amd as P
+
+    with open(SKEWED_GOLD) as f:
+        want = json.load(f)
+    print("[case] skewed 1e7 golden", flush=True)
+    inst = synth.config2()
+    cols = [dev(c) for c in (inst.rx, inst.ry, inst.sz, inst.sy)]
+    with P.Plan(*cols) as p:
+        p.execute()
+        total, dense, sparse = p.count()
+        assert total == want["pairs"] == dense + sparse
+        assert p.stats()["out_j"] == want["out_j"]
+        xs, offs = p.row_info(P.JP_PART_ALL)
+        for key in ("every_1000th_x", "heaviest_100"):
+            rows = want[key]
+            for x, cnt, dig in zip(rows["x"], rows["count"], rows["digest"]):
+                i = int(np.searchsorted(xs, x))
+                if i == xs.size or xs[i] != x:  # no R tuple of x survives the semi-join
+                    assert cnt == 0, x
+                    continue
+                lo, hi = int(offs[i]), int(offs[i + 1])
+                assert hi - lo == cnt, (x, hi - lo, cnt)
+                mx, mz = p.materialize(P.JP_PART_ALL, lo, hi - lo)
+                assert _device_digest(mx, mz, hi - lo) == int(dig), x
+        print(f"[case] skewed 1e7: {total} pairs, {len(want['every_1000th_x']['x'])} + 100 rows", flush=True)
+
+
+def test_batched_4096_per_instance_counts_and_digests():
+    """The 4096-instance batch in one batched plan: every instance's pair count
+    and OUT_J equal the oracle's; instances with at most 2.5e8 pairs are
+    materialised and their digests equal the oracle's."""
+    import torch
+    import paper_2206_04995_amd as P
+
+    with open(BATCHED_GOLD) as f:
+        want = json.load(f)["instances"]
+    print("[case] batched 4096 golden", flush=True)
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(8) as ex:
+        insts = list(ex.map(synth.config4_instance, range(4096)))
+    cols = [tuple(dev(c) for c in (a.rx, a.ry, a.sz, a.sy)) for a in insts]
+    for a, w in zip(insts, want):
+        assert (a.n_r, a.n_s) == (w["n_r"], w["n_s"])
+    with P.Batch(cols) as b:
+        b.execute()
+        counts = b.counts()
+        assert np.array_equal(counts, np.array([w["pairs"] for w in want], dtype=np.int64))
+        cap = 1 << 26
+        ox = torch.empty(cap, dtype=torch.int32, device="cuda")
+        oz = torch.empty(cap, dtype=torch.int32, device="cuda")
+        n_dig = 0
+        for i, w in enumerate(want):
+            assert b.stats(i)["out_j"] == w["out_j"], i
+            if w["pairs"] > 250_000_000 or w["pairs"] == 0:
+                continue
+            acc = torch.zeros(1, dtype=torch.int64, device="cuda")
+            first = 0
+            while first < w["pairs"]:
+                n = P.jp_batch_materialize(b.h, i, P.JP_PART_ALL, first, cap, ox, oz)
+                P.jp_digest_pairs(ox, oz, n, acc)
+                first += n
+            assert int(acc.cpu().numpy().view(np.uint64)[0]) == int(w["digest"]), i
+            n_dig += 1
+        print(f"[case] batched: {n_dig} instance digests", flush=True)

@@ -217,3 +217,72 @@ def test_skewed_small_exact():
     for kind in ("auto", "all_dense", "all_sparse"):
         print(f"[case] skewed small {kind}", flush=True)
         assert_parity(inst, _opts(kind), chunk=5_000_000)
+
+
+def _ids_opts(direct, kind="auto"):
+    import paper_2206_04995_amd as P
+
+    base = _opts(kind)
+    o = base if base is not None else P.make_options()
+    if direct:
+        o.flags |= P.JP_FLAG_DIRECT_IDS
+    return o
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_direct_and_sorted_ids_agree(seed):
+    """Radix-sorted ids (default) and, with JP_FLAG_DIRECT_IDS, the direct-range
+    mapping of dense value ranges (key histogram, scans, scatter): both must equal
+    the oracle."""
+    inst = synth.small_random(400 + seed, 2000 + 500 * seed, 1500 + 400 * seed, dom_x=60 + 30 * seed,
+                              dom_y=40 + 10 * seed, dom_z=80 + 20 * seed, offset=-1000 * seed,
+                              zipf_y=1.1 if seed % 2 else 0.0)
+    for direct in (False, True):
+        for kind in ("auto", "all_dense", "all_sparse"):
+            print(f"[case] ids seed={seed} direct={direct} {kind}", flush=True)
+            st, _ = assert_parity(inst, _ids_opts(direct, kind))
+            assert st["map_direct"] == (3 if direct else 0), st
+
+
+def test_sparse_value_range_takes_sorted_ids():
+    """Values spread over the int32 range are too sparse for the direct mapping,
+    which then falls back to sorted ids."""
+    rng = np.random.default_rng(7)
+    vals = rng.integers(-2 ** 31, 2 ** 31 - 1, 64, dtype=np.int64).astype(np.int32)
+    rx = vals[rng.integers(0, 64, 3000)]
+    ry = vals[rng.integers(0, 16, 3000)]
+    sz = vals[rng.integers(0, 64, 2500)]
+    sy = vals[rng.integers(0, 16, 2500)]
+    inst = synth.Instance(rx, ry, sz, sy, "wide")
+    print("[case] ids wide range", flush=True)
+    st, _ = assert_parity(inst, _ids_opts(True))
+    assert st["map_direct"] == 0, st
+
+
+@pytest.mark.parametrize("direct", [False, True])
+def test_batch_mapping_paths(direct):
+    """A batch of dense-range instances with an empty one and one without a
+    match, through both mapping paths; every instance must equal the oracle."""
+    import paper_2206_04995_amd as P
+
+    insts = [synth.small_random(600 + i, 800 + 200 * i, 700 + 150 * i, dom_x=50 + 10 * i, dom_y=25 + 5 * i,
+                                dom_z=45 + 9 * i, offset=-300 * i, zipf_y=1.2 if i % 2 else 0.0) for i in range(6)]
+    insts.insert(2, synth.Instance(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                                   np.zeros(0, np.int32), "empty"))
+    insts.insert(4, synth.Instance(np.array([7, 7, 9], np.int32), np.array([1, 2, 3], np.int32),
+                                   np.array([5], np.int32), np.array([4], np.int32), "no-match"))
+    cols = [tuple(dev(c) for c in (a.rx, a.ry, a.sz, a.sy)) for a in insts]
+    opt = P.make_options(flags=P.JP_FLAG_DIRECT_IDS if direct else 0)
+    print(f"[case] batch ids direct={direct}", flush=True)
+    with P.Batch(cols, opt=opt) as b:
+        b.execute()
+        counts = b.counts()
+        assert b.stats(0)["map_direct"] == (3 if direct else 0)
+        for i, inst in enumerate(insts):
+            ox, oz = oracle.join_project(inst.rx, inst.ry, inst.sz, inst.sy)
+            assert counts[i] == ox.size
+            st = b.stats(i)
+            assert st["out_j"] == oracle.out_j(inst.rx, inst.ry, inst.sz, inst.sy)
+            if ox.size:
+                bx, bz = b.materialize(i)
+                assert np.array_equal(bx.cpu().numpy(), ox) and np.array_equal(bz.cpu().numpy(), oz)
