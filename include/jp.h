@@ -123,6 +123,8 @@ typedef struct {
   int64_t dense_mfma_ops;     /* 2 * |X| * (dense keys) * |Z_dense| when the INT8-MFMA product ran, else 0 */
   float map_ms;               /* plan: input gather and mapping to ids with the CSR builds (Sec. 2.2) */
   float partition_ms;         /* plan: partition by z and the DenseEC tables (Sec. 2.3) */
+  int64_t dense_mfma_issued_ops; /* int8 ops the INT8-MFMA product issued (padded tiles, up to each tile's
+                                    early stop), else 0 */
 } jp_timings;
 
 typedef struct {
@@ -380,6 +382,45 @@ jp_status jp_server_stats(jp_server* s, jp_server_summary* st);
 /* Finishes the queued queries, stops the thread, frees everything, kept
  * results included (NULL-safe). */
 void jp_server_destroy(jp_server* s);
+
+/* ------------------------------------------------ partial result cache --- */
+
+/* Partial result caching (paper Sec. 3).  The result splits by z (the
+ * intersection-free partition), so the results of a subset Z_cached of the z
+ * values can be kept: a later run on the same tables omits the S tuples whose
+ * z is cached (jp_plan_create_cached), and its result together with the
+ * cached pairs (jp_cache_materialize) is the full result; the two parts are
+ * disjoint and their counts add.
+ *
+ * jp_cache_build ranks the z of an executed single-query hybrid plan by
+ * CacheScore(z) = cost(z) / space(z) and caches, in that order, those whose
+ * space fits budget_bytes (4 bytes a word):
+ *   cost(z)  = OUT_{J,z} (join rows reaching z) for a sparse z, and
+ *              (c_de / c_sp) * |X| for a dense z (the partition's cost model);
+ *   space(z) = 2 + min(k, |X| - k) words, k = number of x with (x, z) in the
+ *              result: the x list, or its complement in X when k > |X| / 2.
+ * Building reads the plan's result once (chunked, on the device).  JP_ESTATE if
+ * the plan was not executed; JP_EINVAL for a batch or a classical plan.
+ * Syncs.  The cache is valid for the tables it was built from; the caller
+ * passes the same tables to jp_plan_create_cached (whose sizes it checks). */
+typedef struct jp_cache jp_cache;
+jp_status jp_cache_build(jp_plan* p, int64_t budget_bytes, hipStream_t stream, jp_cache** out);
+/* Cached z values, cached pairs and words of storage (host outputs, nullable). */
+jp_status jp_cache_info(const jp_cache* c, int64_t* n_z, int64_t* pairs, int64_t* words);
+/* The cached z values, ascending (host array of n_z). */
+jp_status jp_cache_z(const jp_cache* c, int32_t* z_values);
+/* A plan over R and the S tuples whose z is not cached (arguments as for
+ * jp_plan_create).  Syncs. */
+jp_status jp_plan_create_cached(const int32_t* r_x, const int32_t* r_y, int64_t n_r, const int32_t* s_z,
+                                const int32_t* s_y, int64_t n_s, const jp_cache* c, const jp_options* opt,
+                                hipStream_t stream, jp_plan** out);
+/* Cached pairs [first, first + max_pairs) sorted by (z, x) as signed int32,
+ * into caller device buffers; first == pairs writes nothing, first > pairs is
+ * JP_ERANGE.  Syncs. */
+jp_status jp_cache_materialize(const jp_cache* c, int64_t first, int64_t max_pairs, int32_t* out_x, int32_t* out_z,
+                               int64_t* n_written, hipStream_t stream);
+/* Frees the cache (NULL-safe). */
+void jp_cache_destroy(jp_cache* c);
 
 /* ---------------------------------------------------- Join-Aggregate --- */
 

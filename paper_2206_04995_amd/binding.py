@@ -41,6 +41,8 @@ EXPORTS = [
     "jp_tune", "jp_tune_clear", "jp_count_static",
     "jp_dict_create", "jp_dict_size", "jp_dict_decode", "jp_dict_destroy",
     "jp_agg_create", "jp_agg_execute", "jp_agg_count", "jp_agg_materialize", "jp_agg_destroy",
+    "jp_cache_build", "jp_cache_info", "jp_cache_z", "jp_plan_create_cached", "jp_cache_materialize",
+    "jp_cache_destroy",
 ]
 
 
@@ -74,7 +76,7 @@ class jp_timings(ctypes.Structure):
                 ("pad_", ctypes.c_float)] + [
         (n, ctypes.c_int64) for n in ("sparse_join_rows", "n_r_kept", "n_x", "dense_hot_words", "dense_row_words",
                                       "dense_cold_entries", "dense_mfma_ops")] + [
-        ("map_ms", ctypes.c_float), ("partition_ms", ctypes.c_float)]
+        ("map_ms", ctypes.c_float), ("partition_ms", ctypes.c_float), ("dense_mfma_issued_ops", ctypes.c_int64)]
 
 
 class jp_tune_result(ctypes.Structure):
@@ -163,6 +165,13 @@ def _load() -> ctypes.CDLL:
         "jp_agg_count": (st, [vp, i64p, i64p, vp]),
         "jp_agg_materialize": (st, [vp, i64, i64, vp, vp, vp, vp, i64p, vp]),
         "jp_agg_destroy": (None, [vp]),
+        "jp_cache_build": (st, [vp, i64, vp, ctypes.POINTER(vp)]),
+        "jp_cache_info": (st, [vp, i64p, i64p, i64p]),
+        "jp_cache_z": (st, [vp, i32p]),
+        "jp_plan_create_cached": (st, [vp, vp, i64, vp, vp, i64, vp, ctypes.POINTER(jp_options), vp,
+                                       ctypes.POINTER(vp)]),
+        "jp_cache_materialize": (st, [vp, i64, i64, vp, vp, i64p, vp]),
+        "jp_cache_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -550,3 +559,44 @@ def jp_agg_materialize(a: int, first: int, max_groups: int, out_x, out_z, out_co
 
 def jp_agg_destroy(a: int):
     lib.jp_agg_destroy(a)
+
+
+# ------------------------------------------------------ partial result cache
+
+
+def jp_cache_build(plan: int, budget_bytes: int, stream=None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.jp_cache_build(plan, budget_bytes, _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def jp_cache_info(cache: int) -> Dict[str, int]:
+    nz, pairs, words = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.jp_cache_info(cache, ctypes.byref(nz), ctypes.byref(pairs), ctypes.byref(words)))
+    return {"n_z": nz.value, "pairs": pairs.value, "words": words.value}
+
+
+def jp_cache_z(cache: int) -> np.ndarray:
+    n = jp_cache_info(cache)["n_z"]
+    z = np.zeros(max(n, 1), dtype=np.int32)
+    _check(lib.jp_cache_z(cache, z.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return z[:n]
+
+
+def jp_plan_create_cached(r_x, r_y, s_z, s_y, cache: int, opt: Optional[jp_options] = None, stream=None) -> int:
+    h = ctypes.c_void_p()
+    _check(lib.jp_plan_create_cached(_ptr(r_x), _ptr(r_y), int(r_x.numel()), _ptr(s_z), _ptr(s_y),
+                                     int(s_z.numel()), cache, ctypes.byref(opt) if opt is not None else None,
+                                     _stream(stream), ctypes.byref(h)))
+    return h.value
+
+
+def jp_cache_materialize(cache: int, first: int, max_pairs: int, out_x, out_z, stream=None) -> int:
+    n = ctypes.c_int64()
+    _check(lib.jp_cache_materialize(cache, first, max_pairs, _ptr(out_x), _ptr(out_z), ctypes.byref(n),
+                                    _stream(stream)))
+    return n.value
+
+
+def jp_cache_destroy(cache: int):
+    lib.jp_cache_destroy(cache)

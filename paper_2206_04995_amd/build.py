@@ -24,6 +24,7 @@ SOURCES = [
     "encode.hip",
     "classical.hip",
     "aggregate.hip",
+    "cache.hip",
     "plan.cpp",
     "server.cpp",
     "tune.cpp",

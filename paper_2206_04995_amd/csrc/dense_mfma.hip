@@ -15,6 +15,13 @@
 // and keys 16 * (l / 16) .. + 15; its accumulator element r is
 // C[4 * (l / 16) + r][l % 16].  The epilogue counts C > 0 per row with ballots
 // and adds one partial count per row and tile.
+//
+// Early check (the early stop of the paper's DenseEC, Sec. 2.5): the products
+// are 0/1, so a sum only grows; once every entry of a workgroup's tile is > 0
+// the remaining keys cannot change any decision.  Every CHECK_EVERY staged
+// steps each wave votes whether all its entries (rows and columns past the
+// panel count as decided) are > 0, and the workgroup stops when all vote yes.
+// The staged steps a workgroup ran are added to *steps, for the issued work.
 #include "common.h"
 #include "prim.h"
 #include "stages.h"
@@ -35,12 +42,15 @@ constexpr int BT = 64 * WR * WC;  // threads per workgroup
 constexpr int RP = CPR + 1;       // 16-byte chunks per LDS row (one of padding)
 constexpr int SA = MT * CPR / BT;  // 16-byte staging loads per thread and step, panel A
 constexpr int SB = ZT * CPR / BT;  // the same for panel B
+constexpr int CHECK_EVERY = 4;     // staged steps between early checks
 static_assert(SA >= 1 && SB >= 1 && MT * CPR % BT == 0 && ZT * CPR % BT == 0, "staging split");
 
 __global__ void __launch_bounds__(BT, 1) k_dense_mfma(const int8_t* __restrict__ A, const int8_t* __restrict__ Bt,
-                                                      int64_t k_pad, int64_t nx, int32_t* __restrict__ cnt) {
+                                                      int64_t k_pad, int64_t nx, int64_t nz, int32_t* __restrict__ cnt,
+                                                      unsigned long long* __restrict__ steps) {
   __shared__ v4i As[2][MT * RP];
   __shared__ v4i Bs[2][ZT * RP];
+  __shared__ int s_full[2][WR * WC];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = wid / WC, wc = wid % WC;
   const int64_t x0 = int64_t(blockIdx.y) * MT, z0 = int64_t(blockIdx.x) * ZT;
@@ -66,6 +76,8 @@ __global__ void __launch_bounds__(BT, 1) k_dense_mfma(const int8_t* __restrict__
   }
   __syncthreads();
   const int nk = int(k_pad / KT);
+  const int g = lane >> 4;
+  int ran = nk;
   for (int ks = 0; ks < nk; ++ks) {
     const int cur = ks & 1;
     if (ks + 1 < nk) {
@@ -106,10 +118,36 @@ __global__ void __launch_bounds__(BT, 1) k_dense_mfma(const int8_t* __restrict__
         Bs[cur ^ 1][(c / CPR) * RP + (c % CPR)] = pb[s];
       }
     }
+    const bool check = (ks + 1) % CHECK_EVERY == 0 && ks + 1 < nk;
+    const int par = (ks / CHECK_EVERY) & 1;
+    if (check) {
+      bool full = true;
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t x = x0 + wr * 16 * TI + i * 16 + 4 * g + r;
+            const int64_t z = z0 + wc * 16 * TJ + j * 16 + (lane & 15);
+            full = full && (acc[i][j][r] > 0 || x >= nx || z >= nz);
+          }
+      const bool wave_full = ballot(!full) == 0;
+      if (lane == 0) s_full[par][wid] = wave_full ? 1 : 0;
+    }
     __syncthreads();
+    if (check) {
+      bool all = true;
+#pragma unroll
+      for (int w = 0; w < WR * WC; ++w) all = all && s_full[par][w] != 0;
+      if (all) {
+        ran = ks + 1;
+        break;
+      }
+    }
   }
+  if (tid == 0) atomicAdd(steps, (unsigned long long)ran);
 
-  const int g = lane >> 4;
 #pragma unroll
   for (int i = 0; i < TI; ++i) {
 #pragma unroll
@@ -207,13 +245,17 @@ int64_t mfma_pad_rows(int64_t n) { return (n + MT - 1) / MT * MT; }
 int64_t mfma_pad_keys(int64_t n) { return (n + KT - 1) / KT * KT; }
 int64_t mfma_pad_cols(int64_t n) { return (n + ZT - 1) / ZT * ZT; }
 
-void dense_mfma_count(const int8_t* A, const int8_t* Bt, int64_t k_pad, int64_t nx, int64_t nx_pad, int64_t nz_pad,
-                      int32_t* cnt, hipStream_t s) {
+void dense_mfma_count(const int8_t* A, const int8_t* Bt, int64_t k_pad, int64_t nx, int64_t nx_pad, int64_t nz,
+                      int64_t nz_pad, int32_t* cnt, int64_t* steps, hipStream_t s) {
   fill_i32(cnt, nx, 0, s);
+  fill_i64(steps, 1, 0, s);
   if (nx <= 0 || nz_pad <= 0 || k_pad <= 0) return;
   dim3 grid(unsigned(nz_pad / ZT), unsigned(nx_pad / MT));  // padded by mfma_pad_rows / mfma_pad_cols
-  hipLaunchKernelGGL(k_dense_mfma, grid, dim3(BT), 0, s, A, Bt, k_pad, nx, cnt);
+  hipLaunchKernelGGL(k_dense_mfma, grid, dim3(BT), 0, s, A, Bt, k_pad, nx, nz, cnt,
+                     reinterpret_cast<unsigned long long*>(steps));
   JP_LAUNCH_CHECK();
 }
+
+int64_t mfma_step_ops() { return int64_t(2) * MT * ZT * KT; }
 
 }  // namespace jp

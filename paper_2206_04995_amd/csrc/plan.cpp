@@ -563,6 +563,7 @@ void Plan::choose_dense_kernel(Arena& T, hipStream_t s) {
   if (nx_pad * k_pad > lim || nz_pad * k_pad > lim) return;
 
   use_mfma = true;
+  d_mfma_steps = A.alloc<int64_t>(1, s);
   pA = A.alloc<int8_t>(nx_pad * k_pad, s);
   pBt = A.alloc<int8_t>(nz_pad * k_pad, s);
   build_panels(rptr, rcol, NX, Ey, scol, NS, zflag, Edz, kmap, k_pad, nx_pad, nz_pad, pA, pBt, s);
@@ -916,7 +917,7 @@ void Plan::run_count_pass(hipStream_t s, bool timing) {
   else fill_i32(cnt_sp, NX, 0, s);
   if (timing) JP_HIP(hipEventRecord(ev[1], s));
   if (NZd > 0 && use_mfma) {
-    dense_mfma_count(pA, pBt, k_pad, NX, nx_pad, nz_pad, cnt_de, s);
+    dense_mfma_count(pA, pBt, k_pad, NX, nx_pad, NZd, nz_pad, cnt_de, d_mfma_steps, s);
   } else if (NZd > 0 && n_piv > 0) {
     fill_i32(cnt_de, NX, 0, s);
     dense_ec_rows(c, rows_n, NRowsN, nullptr, cnt_de, s);
@@ -969,6 +970,12 @@ void Plan::work(jp_timings* t, hipStream_t s) {
   t->dense_row_words = wk[1];
   t->dense_cold_entries = wk[2];
   t->dense_mfma_ops = use_mfma ? 2 * NX * K_panel * NZd : 0;
+  if (use_mfma) {
+    int64_t steps = 0;
+    d2h(&steps, d_mfma_steps, 1, s);
+    sync(s);
+    t->dense_mfma_issued_ops = steps * mfma_step_ops();
+  }
   if (use_mfma) t->dense_hot_words = t->dense_row_words = t->dense_cold_entries = 0;
 }
 
@@ -1045,10 +1052,6 @@ void Plan::stats(int i, jp_stats* st) const {
 
 // ================================================================== C ABI
 
-struct jp_plan {
-  Plan p;
-  std::unique_ptr<ClassicalPlan> c;  // set when the plan runs the classical path
-};
 struct jp_batch {
   Plan p;
 };

@@ -5,7 +5,10 @@
 #include <string>
 #include <vector>
 
+#include <memory>
+
 #include "../../include/jp.h"
+#include "classical.h"
 #include "pool.h"
 #include "stages.h"
 
@@ -75,6 +78,7 @@ struct Plan {
   // INT8-MFMA count of the dense part (single-instance plans with a dense panel)
   bool use_mfma = false;
   int8_t *pA = nullptr, *pBt = nullptr;
+  int64_t* d_mfma_steps = nullptr;  // staged steps the product's workgroups ran (early checks stop them)
   int64_t K_panel = 0, k_pad = 0, nx_pad = 0, nz_pad = 0, dense_keys0 = 0;
   // rows of the instances by dense width (class 0: at most NARROW_SMALL dense
   // z, 1: NARROW_MID, 2: NARROW_MAX, 3: more): per class, the first x of each
@@ -143,3 +147,9 @@ uint64_t shape_signature(int64_t nx, int64_t nz, int64_t ns, int64_t out_j);
 bool tuned_record(uint64_t sig, TuneRec* rec);
 
 }  // namespace jp
+
+// The C-ABI plan object: a hybrid plan, or the classical path when c is set.
+struct jp_plan {
+  jp::Plan p;
+  std::unique_ptr<jp::ClassicalPlan> c;
+};

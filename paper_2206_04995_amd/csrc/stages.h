@@ -222,8 +222,10 @@ void build_panels(const int32_t* rptr, const int32_t* rcol, int64_t n_x, const i
 int64_t mfma_pad_rows(int64_t n);
 int64_t mfma_pad_cols(int64_t n);
 int64_t mfma_pad_keys(int64_t n);
-void dense_mfma_count(const int8_t* A, const int8_t* Bt, int64_t k_pad, int64_t nx, int64_t nx_pad, int64_t nz_pad,
-                      int32_t* cnt, hipStream_t s);
+void dense_mfma_count(const int8_t* A, const int8_t* Bt, int64_t k_pad, int64_t nx, int64_t nx_pad, int64_t nz,
+                      int64_t nz_pad, int32_t* cnt, int64_t* steps, hipStream_t s);
+// int8 ops one workgroup issues per staged step (2 * tile rows * tile columns * keys)
+int64_t mfma_step_ops();
 // windows per workgroup of the DenseEC count kernel (JP_DENSE_WINDOW_GROUP overrides)
 int dense_window_group(int64_t max_hot, int nwin);
 

@@ -1,6 +1,7 @@
 """Parity at the full workload sizes the benchmark times, through the same
-entry points and launch configuration (one plan, jp_execute, jp_count, then
-chunked jp_materialize):
+entry points and launch configuration (one plan or one batch, execute, count,
+then chunked materialisation), against goldens the oracle wrote
+(tests/golden/make_fullsize.py):
 
 * skewed query, 1e7 tuples per side: sampled rows (random and the heaviest)
   equal the oracle's rows; the union equals dense + sparse; the count is the
@@ -10,7 +11,11 @@ chunked jp_materialize):
   streamed in 64M-pair chunks, equal the oracle's (stored by
   tests/golden/make_fullsize.py);
 * dense uniform query, 1e7 tuples over a 1e4 domain: the INT8-MFMA count
-  equals the bit path's and |X| * |Z|, and sampled rows equal the oracle's.
+  equals the bit path's and |X| * |Z|, and sampled rows equal the oracle's;
+* skewed query: total count and OUT_J, and every 1000th distinct x of R plus
+  the 100 heaviest rows in count and digest;
+* the 4096-instance batch: per-instance counts and OUT_J, and digests of the
+  instances with at most 5e7 pairs.
 """
 import json
 import os
@@ -168,8 +173,9 @@ def test_skewed_1e7_total_and_golden_rows():
 
 def test_batched_4096_per_instance_counts_and_digests():
     """The 4096-instance batch in one batched plan: every instance's pair count
-    and OUT_J equal the oracle's; instances with at most 2.5e8 pairs are
-    materialised and their digests equal the oracle's."""
+    and OUT_J equal the oracle's; the 3521 instances with at most 5e7 pairs
+    (1.4e10 pairs together) are materialised in chunks and their digests equal
+    the oracle's."""
     import torch
     import paper_2206_04995_amd as P
 
@@ -193,7 +199,7 @@ def test_batched_4096_per_instance_counts_and_digests():
         n_dig = 0
         for i, w in enumerate(want):
             assert b.stats(i)["out_j"] == w["out_j"], i
-            if w["pairs"] > 250_000_000 or w["pairs"] == 0:
+            if w["pairs"] > 50_000_000 or w["pairs"] == 0:
                 continue
             acc = torch.zeros(1, dtype=torch.int64, device="cuda")
             first = 0
