@@ -104,6 +104,14 @@ typedef struct {
   int32_t window_group;          /* z windows per workgroup of the bit-path DenseEC count (0 = automatic, max 64) */
   int32_t strategy;              /* a jp_strategy value, for plans: batches, servers, jp_tune and
                                     jp_count_static run the hybrid path and reject JP_STRATEGY_CLASSICAL */
+  int32_t sparse_light_max;      /* SparseBMM count: rows with at most this much work run one per wavefront
+                                    (0 = tuned or 1024; max 1024); heavier rows take a workgroup */
+  int32_t sparse_med_max;        /* SparseBMM count: rows up to this much work run one per workgroup with one
+                                    LDS hash set, heavier ones per z window (0 = tuned or 8192; at least
+                                    sparse_light_max, max 8192) */
+  int32_t mfma_tile;             /* tile of the INT8-MFMA product: 0 = tuned or 256 x 256, 1 = 128 x 256,
+                                    2 = 256 x 128 (rows x dense z per workgroup) */
+  int32_t reserved;              /* must be 0 */
 } jp_options;
 
 /* Kernel times of the last jp_execute (filled by jp_plan_timings for a plan
@@ -269,7 +277,9 @@ void jp_batch_destroy(jp_batch* b);
  * ratio and these choices are stored under the query's shape signature (log2
  * buckets of |X|, |Z|, |S| and OUT_J / |S|); later plans and batch instances
  * of that signature use them for every option left automatic (tau_mode
- * JP_TAU_AUTO, dense_kernel JP_DENSE_AUTO, k_hot_max 0, window_group 0).  The
+ * JP_TAU_AUTO, dense_kernel JP_DENSE_AUTO, k_hot_max 0, window_group 0,
+ * sparse_light_max 0, sparse_med_max 0, mfma_tile 0; batches take the
+ * SparseBMM bounds and the tile from their first instance's record).  The
  * store is process-wide and thread-safe.  jp_tune syncs the stream; it returns
  * JP_ESTATE if two settings disagree on the counts. */
 typedef struct {
@@ -283,6 +293,10 @@ typedef struct {
   int32_t k_hot_max;     /* chosen hot-key cap */
   int32_t window_group;  /* chosen windows per workgroup */
   uint64_t signature;  /* shape signature the choices are stored under */
+  int32_t sparse_light_max;  /* chosen SparseBMM one-wavefront-per-row bound */
+  int32_t sparse_med_max;    /* chosen SparseBMM one-workgroup-per-row bound */
+  int32_t mfma_tile;         /* chosen INT8-MFMA tile */
+  int32_t pad_;
 } jp_tune_result;
 
 jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r, const int32_t* s_z, const int32_t* s_y,

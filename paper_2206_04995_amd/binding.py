@@ -62,6 +62,10 @@ class jp_options(ctypes.Structure):
         ("workspace_limit_bytes", ctypes.c_int64),
         ("window_group", ctypes.c_int32),
         ("strategy", ctypes.c_int32),
+        ("sparse_light_max", ctypes.c_int32),
+        ("sparse_med_max", ctypes.c_int32),
+        ("mfma_tile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -83,7 +87,8 @@ class jp_tune_result(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_int64), ("model_tau", ctypes.c_int64), ("cost_ratio", ctypes.c_double),
                 ("best_ms", ctypes.c_double), ("model_ms", ctypes.c_double), ("candidates", ctypes.c_int32),
                 ("dense_kernel", ctypes.c_int32), ("k_hot_max", ctypes.c_int32), ("window_group", ctypes.c_int32),
-                ("signature", ctypes.c_uint64)]
+                ("signature", ctypes.c_uint64), ("sparse_light_max", ctypes.c_int32), ("sparse_med_max", ctypes.c_int32),
+                ("mfma_tile", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class jp_instance(ctypes.Structure):
@@ -216,9 +221,13 @@ def _ptr(t) -> int:
 
 def make_options(tau_mode: int = JP_TAU_AUTO, dense_threshold: int = 0, dense_kernel: int = JP_DENSE_AUTO,
                  k_hot_max: int = 0, workspace_limit_bytes: int = 0, flags: int = 0,
-                 window_group: int = 0, strategy: int = JP_STRATEGY_AUTO) -> jp_options:
+                 window_group: int = 0, strategy: int = JP_STRATEGY_AUTO, sparse_light_max: int = 0,
+                 sparse_med_max: int = 0, mfma_tile: int = 0) -> jp_options:
     o = jp_options()
     o.strategy = strategy
+    o.sparse_light_max = sparse_light_max
+    o.sparse_med_max = sparse_med_max
+    o.mfma_tile = mfma_tile
     o.window_group = window_group
     o.tau_mode = tau_mode
     o.dense_kernel = dense_kernel

@@ -17,6 +17,10 @@ constexpr int64_t JP_CLASSICAL_MAX_OUT_J = int64_t(1) << 30;
 
 // OUT_J estimated from up to 4096 sampled tuples per side (exact below that); syncs
 int64_t estimate_out_j(const int32_t* ry, int64_t nr, const int32_t* sy, int64_t ns, hipStream_t s);
+// the same in two halves: the sample's matching pairs into *matches (device, asynchronous), then the estimate
+void launch_out_j_sample(const int32_t* ry, int64_t nr, const int32_t* sy, int64_t ns, unsigned long long* matches,
+                         hipStream_t s);
+int64_t out_j_from_sample(unsigned long long matches, int64_t nr, int64_t ns);
 bool f1_prefers_classical(int64_t out_j_est, int64_t nr, int64_t ns);
 
 struct ClassicalPlan {

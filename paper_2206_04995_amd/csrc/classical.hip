@@ -50,57 +50,58 @@ __device__ __forceinline__ uint64_t slot_of_y(int32_t y, int shift) {
 
 // ---------------------------------------------------------------- f1 estimate
 
-// In-place ascending bitonic sort of SAMPLE ints by the block.
-__device__ void block_bitonic(int32_t* a) {
-  for (int k = 2; k <= SAMPLE; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < SAMPLE; i += SAMPLE_NT) {
-        const int l = i ^ j;
-        if (l > i) {
-          const bool up = (i & k) == 0;
-          const int32_t u = a[i], v = a[l];
-          if ((u > v) == up) {
-            a[i] = v;
-            a[l] = u;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
 // matches = number of (sampled R tuple, sampled S tuple) pairs with equal y;
-// the samples take every sr-th (ss-th) tuple, mr (ms) of them
+// the samples take every sr-th (ss-th) tuple, mr (ms) of them.  The S sample
+// goes into an LDS hash table of key counts (load <= 1/2), the R sample probes it.
+constexpr int SLOTS = 2 * SAMPLE;
 __global__ void __launch_bounds__(SAMPLE_NT) k_sample_matches(const int32_t* __restrict__ ry, int64_t sr, int mr,
                                                               const int32_t* __restrict__ sy, int64_t ss, int ms,
                                                               unsigned long long* __restrict__ matches) {
-  __shared__ int32_t a[SAMPLE], b[SAMPLE];
+  __shared__ int32_t key[SLOTS];
+  __shared__ int32_t cnt[SLOTS];
+  __shared__ int32_t min_cnt;  // the key INT32_MIN is the free marker: counted apart
   __shared__ unsigned long long tot;
-  for (int i = threadIdx.x; i < SAMPLE; i += SAMPLE_NT) {
-    a[i] = i < mr ? ry[int64_t(i) * sr] : INT32_MAX;
-    b[i] = i < ms ? sy[int64_t(i) * ss] : INT32_MAX;
+  for (int i = threadIdx.x; i < SLOTS; i += SAMPLE_NT) {
+    key[i] = INT32_MIN;
+    cnt[i] = 0;
   }
-  if (threadIdx.x == 0) tot = 0;
+  if (threadIdx.x == 0) {
+    min_cnt = 0;
+    tot = 0;
+  }
   __syncthreads();
-  block_bitonic(a);
-  block_bitonic(b);
+  for (int i = threadIdx.x; i < ms; i += SAMPLE_NT) {
+    const int32_t y = sy[int64_t(i) * ss];
+    if (y == INT32_MIN) {
+      atomicAdd(&min_cnt, 1);
+      continue;
+    }
+    uint32_t h = (uint32_t(y) * 0x9E3779B1u) >> (32 - 13);
+    while (true) {
+      const int32_t old = atomicCAS(&key[h], INT32_MIN, y);
+      if (old == INT32_MIN || old == y) break;
+      h = (h + 1) & (SLOTS - 1);
+    }
+    atomicAdd(&cnt[h], 1);
+  }
+  __syncthreads();
   unsigned long long mine = 0;
   for (int i = threadIdx.x; i < mr; i += SAMPLE_NT) {
-    const int32_t v = a[i];
-    int lo = 0, hi = ms;  // first b >= v in [0, ms)
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (b[mid] < v) lo = mid + 1;
-      else hi = mid;
+    const int32_t y = ry[int64_t(i) * sr];
+    if (y == INT32_MIN) {
+      mine += (unsigned long long)min_cnt;
+      continue;
     }
-    int lo2 = lo, hi2 = ms;  // first b > v
-    while (lo2 < hi2) {
-      const int mid = (lo2 + hi2) >> 1;
-      if (b[mid] <= v) lo2 = mid + 1;
-      else hi2 = mid;
+    uint32_t h = (uint32_t(y) * 0x9E3779B1u) >> (32 - 13);
+    while (true) {
+      const int32_t k = key[h];
+      if (k == y) {
+        mine += (unsigned long long)cnt[h];
+        break;
+      }
+      if (k == INT32_MIN) break;
+      h = (h + 1) & (SLOTS - 1);
     }
-    mine += (unsigned long long)(lo2 - lo);
   }
   atomicAdd(&tot, mine);
   __syncthreads();
@@ -294,18 +295,33 @@ void d2h_sync(void* dst, const void* src, size_t bytes, hipStream_t s) {
 
 }  // namespace
 
-int64_t estimate_out_j(const int32_t* ry, int64_t nr, const int32_t* sy, int64_t ns, hipStream_t s) {
+void launch_out_j_sample(const int32_t* ry, int64_t nr, const int32_t* sy, int64_t ns, unsigned long long* matches,
+                         hipStream_t s) {
+  if (nr == 0 || ns == 0) {
+    fill_i64(reinterpret_cast<int64_t*>(matches), 1, 0, s);
+    return;
+  }
+  const int64_t sr = (nr + SAMPLE - 1) / SAMPLE, ss = (ns + SAMPLE - 1) / SAMPLE;
+  const int mr = int((nr + sr - 1) / sr), ms = int((ns + ss - 1) / ss);
+  hipLaunchKernelGGL(k_sample_matches, dim3(1), dim3(SAMPLE_NT), 0, s, ry, sr, mr, sy, ss, ms, matches);
+  lc();
+}
+
+int64_t out_j_from_sample(unsigned long long matches, int64_t nr, int64_t ns) {
   if (nr == 0 || ns == 0) return 0;
   const int64_t sr = (nr + SAMPLE - 1) / SAMPLE, ss = (ns + SAMPLE - 1) / SAMPLE;
   const int mr = int((nr + sr - 1) / sr), ms = int((ns + ss - 1) / ss);
+  return int64_t(std::llround(double(matches) * (double(nr) / mr) * (double(ns) / ms)));
+}
+
+int64_t estimate_out_j(const int32_t* ry, int64_t nr, const int32_t* sy, int64_t ns, hipStream_t s) {
   Arena T;
   unsigned long long* d = T.alloc<unsigned long long>(1, s);
-  hipLaunchKernelGGL(k_sample_matches, dim3(1), dim3(SAMPLE_NT), 0, s, ry, sr, mr, sy, ss, ms, d);
-  lc();
+  launch_out_j_sample(ry, nr, sy, ns, d, s);
   unsigned long long m = 0;
   d2h_sync(&m, d, sizeof(m), s);
   T.release(s);
-  return int64_t(std::llround(double(m) * (double(nr) / mr) * (double(ns) / ms)));
+  return out_j_from_sample(m, nr, ns);
 }
 
 bool f1_prefers_classical(int64_t out_j_est, int64_t nr, int64_t ns) {

@@ -45,9 +45,15 @@ constexpr int SB = ZT * CPR / BT;  // the same for panel B
 constexpr int CHECK_EVERY = 4;     // staged steps between early checks
 static_assert(SA >= 1 && SB >= 1 && MT * CPR % BT == 0 && ZT * CPR % BT == 0, "staging split");
 
+template <int TI, int TJ>
 __global__ void __launch_bounds__(BT, 1) k_dense_mfma(const int8_t* __restrict__ A, const int8_t* __restrict__ Bt,
                                                       int64_t k_pad, int64_t nx, int64_t nz, int32_t* __restrict__ cnt,
                                                       unsigned long long* __restrict__ steps) {
+  constexpr int MT = WR * 16 * TI;   // x rows of this tile
+  constexpr int ZT = WC * 16 * TJ;   // dense z of this tile
+  constexpr int SA = MT * CPR / BT;  // 16-byte staging loads per thread and step, panel A
+  constexpr int SB = ZT * CPR / BT;  // the same for panel B
+  static_assert(SA >= 1 && SB >= 1 && MT * CPR % BT == 0 && ZT * CPR % BT == 0, "staging split");
   __shared__ v4i As[2][MT * RP];
   __shared__ v4i Bs[2][ZT * RP];
   __shared__ int s_full[2][WR * WC];
@@ -245,17 +251,27 @@ int64_t mfma_pad_rows(int64_t n) { return (n + MT - 1) / MT * MT; }
 int64_t mfma_pad_keys(int64_t n) { return (n + KT - 1) / KT * KT; }
 int64_t mfma_pad_cols(int64_t n) { return (n + ZT - 1) / ZT * ZT; }
 
+// tile 0: 256 x 256 (4 x 8 MFMA blocks per wave), 1: 128 x 256 (2 x 8), 2: 256 x 128 (4 x 4)
 void dense_mfma_count(const int8_t* A, const int8_t* Bt, int64_t k_pad, int64_t nx, int64_t nx_pad, int64_t nz,
-                      int64_t nz_pad, int32_t* cnt, int64_t* steps, hipStream_t s) {
+                      int64_t nz_pad, int32_t* cnt, int64_t* steps, int tile, hipStream_t s) {
   fill_i32(cnt, nx, 0, s);
   fill_i64(steps, 1, 0, s);
   if (nx <= 0 || nz_pad <= 0 || k_pad <= 0) return;
-  dim3 grid(unsigned(nz_pad / ZT), unsigned(nx_pad / MT));  // padded by mfma_pad_rows / mfma_pad_cols
-  hipLaunchKernelGGL(k_dense_mfma, grid, dim3(BT), 0, s, A, Bt, k_pad, nx, nz, cnt,
-                     reinterpret_cast<unsigned long long*>(steps));
+  const int mt = tile == 1 ? MT / 2 : MT, zt = tile == 2 ? ZT / 2 : ZT;
+  dim3 grid(unsigned(nz_pad / zt), unsigned(nx_pad / mt));  // padded by mfma_pad_rows / mfma_pad_cols
+  auto* st = reinterpret_cast<unsigned long long*>(steps);
+  if (tile == 1)
+    hipLaunchKernelGGL((k_dense_mfma<2, 8>), grid, dim3(BT), 0, s, A, Bt, k_pad, nx, nz, cnt, st);
+  else if (tile == 2)
+    hipLaunchKernelGGL((k_dense_mfma<4, 4>), grid, dim3(BT), 0, s, A, Bt, k_pad, nx, nz, cnt, st);
+  else
+    hipLaunchKernelGGL((k_dense_mfma<4, 8>), grid, dim3(BT), 0, s, A, Bt, k_pad, nx, nz, cnt, st);
   JP_LAUNCH_CHECK();
 }
 
-int64_t mfma_step_ops() { return int64_t(2) * MT * ZT * KT; }
+int64_t mfma_step_ops(int tile) {
+  const int64_t mt = tile == 1 ? MT / 2 : MT, zt = tile == 2 ? ZT / 2 : ZT;
+  return 2 * mt * zt * KT;
+}
 
 }  // namespace jp

@@ -210,6 +210,7 @@ void Plan::build(const jp_instance* inst, int n, const jp_options* o, hipStream_
     sy = csy;
   }
   map(s);
+  if (take_classical) return;  // f1 chose the classical path: the caller builds it
   if (timing) JP_HIP(hipEventRecord(evp[1], s));
   partition(s);
   if (timing) JP_HIP(hipEventRecord(evp[2], s));
@@ -245,7 +246,20 @@ void Plan::map(hipStream_t s) {
   if (!sort_ids) seg_minmax(rx, NR, d_rbase, n, xmin, xmax, s);  // over all of R: the direct x mapping's range
   std::vector<int32_t> h_mm(6 * size_t(n));
   d2h(h_mm.data(), mm, (sort_ids ? 4 : 6) * size_t(n), s);
+  // f1 (Sec. 2.6) rides on this first read-back: the classical path when the
+  // sampled OUT_J is small against the input
+  unsigned long long h_match = 0;
+  if (f1_probe) {
+    unsigned long long* dm = T.alloc<unsigned long long>(1, s);
+    launch_out_j_sample(ry, NR, sy, NS, dm, s);
+    d2h(&h_match, dm, 1, s);
+  }
   sync(s);
+  if (f1_probe && f1_prefers_classical(out_j_from_sample(h_match, NR, NS), NR, NS)) {
+    take_classical = true;
+    T.release(s);
+    return;
+  }
   auto part = [&](int k) { return std::vector<int32_t>(h_mm.begin() + k * n, h_mm.begin() + (k + 1) * n); };
   std::vector<int64_t> koff_z, koff_y, koff_x;
   int zbits = key_layout(part(0), part(1), koff_z);
@@ -458,6 +472,12 @@ void Plan::partition(hipStream_t s) {
   }
   d_tau = A.alloc<int64_t>(n, s);
   h2d(d_tau, h_tau.data(), n, s);
+  // SparseBMM class bounds and the MFMA tile: pinned by the options, else the first instance's tuned record
+  const TuneRec& r0 = h_rec[0];
+  light_max = opt.sparse_light_max > 0 ? opt.sparse_light_max : (r0.valid && r0.sparse_light_max > 0 ? r0.sparse_light_max : 1024);
+  med_max = opt.sparse_med_max > 0 ? opt.sparse_med_max : (r0.valid && r0.sparse_med_max > 0 ? r0.sparse_med_max : 8192);
+  med_max = std::max(med_max, light_max);
+  mfma_tile = opt.mfma_tile > 0 ? opt.mfma_tile : (r0.valid ? r0.mfma_tile : 0);
 
   const int64_t NZa = std::max<int64_t>(NZ, 1), NSa = std::max<int64_t>(NS, 1), NYa = std::max<int64_t>(NY, 1);
   zflag = A.alloc<int32_t>(NZa, s);
@@ -854,6 +874,8 @@ RowCtx Plan::ctx(int space) const {
   c.seglen = seglen;
   c.wgroup = opt.window_group;
   if (c.wgroup == 0 && !h_rec.empty() && h_rec[0].valid) c.wgroup = h_rec[0].window_group;  // tuned
+  c.light_max = light_max;
+  c.med_max = med_max;
   return c;
 }
 
@@ -917,7 +939,7 @@ void Plan::run_count_pass(hipStream_t s, bool timing) {
   else fill_i32(cnt_sp, NX, 0, s);
   if (timing) JP_HIP(hipEventRecord(ev[1], s));
   if (NZd > 0 && use_mfma) {
-    dense_mfma_count(pA, pBt, k_pad, NX, nx_pad, NZd, nz_pad, cnt_de, d_mfma_steps, s);
+    dense_mfma_count(pA, pBt, k_pad, NX, nx_pad, NZd, nz_pad, cnt_de, d_mfma_steps, mfma_tile, s);
   } else if (NZd > 0 && n_piv > 0) {
     fill_i32(cnt_de, NX, 0, s);
     dense_ec_rows(c, rows_n, NRowsN, nullptr, cnt_de, s);
@@ -974,7 +996,7 @@ void Plan::work(jp_timings* t, hipStream_t s) {
     int64_t steps = 0;
     d2h(&steps, d_mfma_steps, 1, s);
     sync(s);
-    t->dense_mfma_issued_ops = steps * mfma_step_ops();
+    t->dense_mfma_issued_ops = steps * mfma_step_ops(mfma_tile);
   }
   if (use_mfma) t->dense_hot_words = t->dense_row_words = t->dense_cold_entries = 0;
 }
@@ -1075,6 +1097,12 @@ jp_status check_opt(const jp_options* o) {
   if (o->tau_mode == JP_TAU_FIXED && o->dense_threshold < -1) return fail(JP_EINVAL, "dense_threshold < -1");
   if (o->window_group < 0 || o->window_group > 64) return fail(JP_EINVAL, "window_group must be in [0, 64]");
   if (o->strategy < JP_STRATEGY_AUTO || o->strategy > JP_STRATEGY_CLASSICAL) return fail(JP_EINVAL, "bad strategy");
+  if (o->sparse_light_max < 0 || o->sparse_light_max > 1024) return fail(JP_EINVAL, "sparse_light_max must be in [0, 1024]");
+  if (o->sparse_med_max < 0 || o->sparse_med_max > 8192 ||
+      (o->sparse_med_max > 0 && o->sparse_med_max < (o->sparse_light_max > 0 ? o->sparse_light_max : 1024)))
+    return fail(JP_EINVAL, "sparse_med_max must be 0 or in [sparse_light_max, 8192]");
+  if (o->mfma_tile < 0 || o->mfma_tile > 2) return fail(JP_EINVAL, "mfma_tile must be 0, 1 or 2");
+  if (o->reserved != 0) return fail(JP_EINVAL, "reserved option field must be 0");
   return JP_OK;
 }
 
@@ -1168,11 +1196,22 @@ jp_status jp_plan_create(const int32_t* r_x, const int32_t* r_y, int64_t n_r, co
   if (!p) return fail(JP_ENOMEM, "host allocation failed");
   jp_instance in{r_x, r_y, s_z, s_y, n_r, n_s};
   st = guarded([&] {
-    // f1 (Sec. 2.6): the classical solution when its deduplication costs less than the mapping
+    // f1 (Sec. 2.6): the classical solution when its deduplication costs less
+    // than the mapping; the hybrid build samples OUT_J at its first read-back
+    // and stops there if the classical path wins
     bool classical = strat == JP_STRATEGY_CLASSICAL;
-    if (strat == JP_STRATEGY_AUTO && (!opt || (opt->tau_mode == JP_TAU_AUTO && opt->dense_kernel == JP_DENSE_AUTO &&
-                                               !(opt->flags & JP_FLAG_GRAPH))))
-      classical = f1_prefers_classical(estimate_out_j(r_y, n_r, s_y, n_s, stream), n_r, n_s);
+    if (!classical) {
+      p->p.f1_probe = strat == JP_STRATEGY_AUTO &&
+                      (!opt || (opt->tau_mode == JP_TAU_AUTO && opt->dense_kernel == JP_DENSE_AUTO &&
+                                !(opt->flags & JP_FLAG_GRAPH)));
+      p->p.build(&in, 1, opt, stream);
+      if (p->p.take_classical) {
+        (void)hipStreamSynchronize(stream);
+        p->p.~Plan();  // a fresh hybrid plan object, holding nothing
+        new (&p->p) Plan();
+        classical = true;
+      }
+    }
     if (classical) {
       p->c.reset(new ClassicalPlan());
       p->c->arena_limit(opt ? opt->workspace_limit_bytes : 0);
@@ -1181,9 +1220,9 @@ jp_status jp_plan_create(const int32_t* r_x, const int32_t* r_y, int64_t n_r, co
         if (strat == JP_STRATEGY_CLASSICAL)
           throw Error(JP_EINVAL, "the classical path takes at most 2^30 join rows");
         p->c.reset();  // the estimate was too low: the hybrid path
+        p->p.build(&in, 1, opt, stream);
       }
     }
-    if (!p->c) p->p.build(&in, 1, opt, stream);
   });
   if (st != JP_OK) {
     jp_plan_destroy(p);

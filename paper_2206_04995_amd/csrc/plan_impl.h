@@ -39,6 +39,9 @@ struct TuneRec {
   int32_t dense_kernel = JP_DENSE_AUTO;
   int32_t k_hot_max = 0;
   int32_t window_group = 0;
+  int32_t sparse_light_max = 0;
+  int32_t sparse_med_max = 0;
+  int32_t mfma_tile = 0;
 };
 
 struct Plan {
@@ -52,6 +55,10 @@ struct Plan {
 
   int64_t NR = 0, NS = 0, NRp = 0, NX = 0, NY = 0, NZ = 0, NZd = 0, NSp = 0;
   int map_direct = 0;  // bit 0: z ids by the direct-range mapping, bit 1: x ids
+  bool f1_probe = false;        // build(): sample OUT_J at the first read-back and stop if f1 prefers classical
+  bool take_classical = false;  // build() stopped there
+  // SparseBMM count class bounds and the INT8-MFMA tile in effect (options, else tuned, else defaults)
+  int light_max = 1024, med_max = 8192, mfma_tile = 0;
   std::vector<int32_t> h_rbase, h_sbase, h_rpbase, h_xbase, h_ybase, h_zbase, h_zdbase;
   std::vector<int64_t> h_outj, h_tau, h_tot;
   std::vector<TuneRec> h_rec;  // per instance

@@ -126,11 +126,13 @@ __device__ __forceinline__ void heavy_window(const int32_t* __restrict__ seg0, c
 }
 
 // Sorts the rows of [x_lo, x_hi) by their work w into four lists:
-//   class 1: w in [1, SMALL_SLOTS / 2]     hdr[0], upwards from A
-//   class 2: w up to LIGHT_MAX             hdr[1], downwards from A + n
+//   class 1: w in [1, small_max]           hdr[0], upwards from A
+//   class 2: w up to light_max             hdr[1], downwards from A + n
 //   class 3: w up to med_max               hdr[2], upwards from B
 //   class 4: heavier rows                  hdr[3], downwards from B + n
-// (write mode passes med_max = LIGHT_MAX: no class 3).  A block takes
+// small_max <= SMALL_SLOTS / 2, light_max <= LIGHT_MAX and med_max <= MED_MAX
+// keep every hash set at most half full (write mode passes the defaults with
+// med_max = LIGHT_MAX: no class 3).  A block takes
 // CLS_ROWS consecutive rows (CLS_PER per thread), ranks them with one block
 // scan and reserves its places with one atomic per class, so few atomics meet
 // on the four counters.  In count mode the rows no wave or workgroup hash set
@@ -140,7 +142,8 @@ constexpr int CLS_PER = 16;
 constexpr int CLS_ROWS = NT * CLS_PER;
 
 __global__ void __launch_bounds__(NT) k_classify_rows(int64_t x_lo, int64_t x_hi, const int64_t* __restrict__ w,
-                                                      int64_t med_max, int32_t* __restrict__ cnt,
+                                                      int64_t small_max, int64_t light_max, int64_t med_max,
+                                                      int32_t* __restrict__ cnt,
                                                       int32_t* __restrict__ hdr, int32_t* __restrict__ A,
                                                       int32_t* __restrict__ B) {
   __shared__ int64_t wtot[NT / 64];
@@ -158,7 +161,7 @@ __global__ void __launch_bounds__(NT) k_classify_rows(int64_t x_lo, int64_t x_hi
     int c = 0;
     if (i < n) {
       const int64_t wx = w[i];
-      c = wx == 0 ? 0 : wx <= SMALL_SLOTS / 2 ? 1 : wx <= LIGHT_MAX ? 2 : wx <= med_max ? 3 : 4;
+      c = wx == 0 ? 0 : wx <= small_max ? 1 : wx <= light_max ? 2 : wx <= med_max ? 3 : 4;
       if (cnt && (c == 0 || c == 4)) cnt[x_lo + i] = 0;
     }
     cls |= uint64_t(c) << (3 * k);
@@ -538,9 +541,13 @@ void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
   int32_t* A = lists + 4;
   int32_t* B = A + n;
   fill_i32(hdr, 4, 0, s);
-  const int64_t med_max = out ? LIGHT_MAX : MED_MAX;
-  hipLaunchKernelGGL(k_classify_rows, dim3(int((n + CLS_ROWS - 1) / CLS_ROWS)), dim3(NT), 0, s, x_lo, x_hi, w, med_max,
-                     cnt, hdr, A, B);
+  // count mode takes the plan's class bounds (tuned or pinned), write mode the defaults
+  const int64_t light_max = out ? LIGHT_MAX : std::min<int64_t>(LIGHT_MAX, c.light_max > 0 ? c.light_max : LIGHT_MAX);
+  const int64_t small_max = std::min<int64_t>(SMALL_SLOTS / 2, light_max);
+  const int64_t med_max =
+      out ? LIGHT_MAX : std::max<int64_t>(light_max, std::min<int64_t>(MED_MAX, c.med_max > 0 ? c.med_max : MED_MAX));
+  hipLaunchKernelGGL(k_classify_rows, dim3(int((n + CLS_ROWS - 1) / CLS_ROWS)), dim3(NT), 0, s, x_lo, x_hi, w,
+                     small_max, light_max, med_max, cnt, hdr, A, B);
   JP_LAUNCH_CHECK();
   // light rows: four times as many waves as stay resident (8 blocks of 4 waves
   // per CU with 512-slot tables, 5 with 2048), each pipelining over its rows

@@ -173,6 +173,9 @@ struct RowCtx {
   // per R CSR entry j (filled by sparse_row_work): the sparse S row of its key
   const int32_t* seg0;     // first entry in spcol
   const int32_t* seglen;   // number of entries
+  // SparseBMM count: rows with work <= light_max run one per wavefront, up to med_max one per workgroup
+  int light_max;
+  int med_max;
 };
 
 // hot rank of each hot y within its instance, by decreasing d_R (rows sharing it)
@@ -223,9 +226,9 @@ int64_t mfma_pad_rows(int64_t n);
 int64_t mfma_pad_cols(int64_t n);
 int64_t mfma_pad_keys(int64_t n);
 void dense_mfma_count(const int8_t* A, const int8_t* Bt, int64_t k_pad, int64_t nx, int64_t nx_pad, int64_t nz,
-                      int64_t nz_pad, int32_t* cnt, int64_t* steps, hipStream_t s);
-// int8 ops one workgroup issues per staged step (2 * tile rows * tile columns * keys)
-int64_t mfma_step_ops();
+                      int64_t nz_pad, int32_t* cnt, int64_t* steps, int tile, hipStream_t s);
+// int8 ops one workgroup of the given tile issues per staged step (2 * tile rows * tile columns * keys)
+int64_t mfma_step_ops(int tile);
 // windows per workgroup of the DenseEC count kernel (JP_DENSE_WINDOW_GROUP overrides)
 int dense_window_group(int64_t max_hot, int nwin);
 

@@ -104,7 +104,7 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
   }
   if (opt && (opt->window_group < 0 || opt->window_group > 64 || opt->k_hot_max < 0 || opt->k_hot_max > 1024 ||
               opt->dense_kernel < 0 || opt->dense_kernel > 2 || opt->strategy < 0 ||
-              opt->strategy > JP_STRATEGY_HYBRID)) {
+              opt->strategy > JP_STRATEGY_HYBRID || check_options(opt) != JP_OK)) {
     set_last_error("bad options");
     return JP_EINVAL;
   }
@@ -184,7 +184,14 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
         o.dense_kernel = k;
         consider(o);
       }
-      if (!best.mfma) {
+      if (best.mfma) {
+        const jp_options at = best.o;
+        for (int tile : {1, 2}) {
+          jp_options o = at;
+          o.mfma_tile = tile;
+          consider(o);
+        }
+      } else {
         const jp_options at = best.o;
         for (int kh : {64, 128, 256, 512, 1024}) {
           jp_options o = at;
@@ -199,6 +206,23 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
         }
       }
     }
+    // with a sparse part: the SparseBMM bounds between one wavefront, one
+    // workgroup and z windows per row
+    if (best.o.dense_threshold != -1) {
+      const jp_options at = best.o;
+      for (int lm : {256, 512}) {
+        jp_options o = at;
+        o.sparse_light_max = lm;
+        consider(o);
+      }
+      const jp_options at2 = best.o;
+      for (int mm : {2048, 4096}) {
+        jp_options o = at2;
+        o.sparse_med_max = mm;
+        if (o.sparse_light_max > mm) continue;
+        consider(o);
+      }
+    }
     const int64_t btau = best.o.dense_threshold;
     double ratio;
     if (btau == INT64_MAX) ratio = 1e300;
@@ -210,6 +234,9 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
     rec.dense_kernel = best.mfma ? JP_DENSE_MFMA : JP_DENSE_BITS;
     rec.k_hot_max = best.o.k_hot_max;
     rec.window_group = best.o.window_group;
+    rec.sparse_light_max = best.o.sparse_light_max;
+    rec.sparse_med_max = best.o.sparse_med_max;
+    rec.mfma_tile = best.o.mfma_tile;
     {
       std::lock_guard<std::mutex> g(g_mu);
       g_rec[sig] = rec;
@@ -223,6 +250,9 @@ extern "C" jp_status jp_tune(const int32_t* r_x, const int32_t* r_y, int64_t n_r
     out->dense_kernel = rec.dense_kernel;
     out->k_hot_max = rec.k_hot_max;
     out->window_group = rec.window_group;
+    out->sparse_light_max = rec.sparse_light_max;
+    out->sparse_med_max = rec.sparse_med_max;
+    out->mfma_tile = rec.mfma_tile;
     out->signature = sig;
     return JP_OK;
   } catch (const Error& e) {

@@ -47,6 +47,8 @@ def test_invalid_arguments_rejected_before_device_work():
     # bad options
     for kw in ({"tau_mode": 7}, {"dense_kernel": 9}, {"k_hot_max": 5000}, {"workspace_limit_bytes": -1},
                {"window_group": 65}, {"window_group": -1}, {"strategy": 3}, {"strategy": -1},
+                   {"sparse_light_max": 2000}, {"sparse_med_max": 100}, {"sparse_med_max": 9000}, {"mfma_tile": 3},
+                   {"reserved": 1},
                {"tau_mode": 1, "dense_threshold": -2}):
         o = P.make_options()
         for k, v in kw.items():

@@ -75,3 +75,36 @@ def test_mfma_not_used_for_batches_or_sparse_panels():
         assert b.stats(0)["dense_mfma"] == 0
         o = oracle.count(inst.rx, inst.ry, inst.sz, inst.sy)[0]
         assert list(b.counts()) == [o, o]
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("case", [0, 3, 5])
+def test_mfma_tiles(tile, case):
+    """The 128 x 256 and 256 x 128 tiles against the oracle (ragged shapes, early
+    checks on dense panels)."""
+    import paper_2206_04995_amd as P
+
+    dims = [(130, 70, 129), (1, 1, 1), (300, 64, 128), (257, 200, 500), (77, 1000, 63), (1000, 30, 2000)][case]
+    nx, ny, nz = dims
+    n = max(200, min(60_000, nx * ny // 3))
+    inst = synth.small_random(300 + case, n, max(150, min(60_000, ny * nz // 3)), dom_x=nx, dom_y=ny, dom_z=nz,
+                              offset=(case - 3) * 1_000_000)
+    print("[case] mfma tile", tile, dims, flush=True)
+    opt = P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=-1, dense_kernel=P.JP_DENSE_MFMA, mfma_tile=tile)
+    st, _ = assert_parity(inst, opt)
+    assert st["dense_mfma"] == 1
+
+
+def test_mfma_early_check_issued_work():
+    """A dense panel: the early check stops tiles before the last key, so fewer
+    ops are issued than the full product holds, with an exact count."""
+    import paper_2206_04995_amd as P
+
+    inst = synth.uniform_paper_default(n_tuples=400_000, n_domain=2_000, seed_index=4)
+    cols = [dev(c) for c in (inst.rx, inst.ry, inst.sz, inst.sy)]
+    print("[case] mfma early check", flush=True)
+    with P.Plan(*cols, opt=_opt(P.JP_DENSE_MFMA)) as p:
+        p.execute()
+        assert p.count()[0] == oracle.count(inst.rx, inst.ry, inst.sz, inst.sy)[0]
+        wk = P.jp_plan_work(p.h)
+        assert 0 < wk["dense_mfma_issued_ops"] < wk["dense_mfma_ops"], wk

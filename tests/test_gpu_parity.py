@@ -98,6 +98,24 @@ def test_heavy_sparse_rows_many_windows():
     assert_parity(inst, _opts("all_sparse"), chunk=50_000)
 
 
+@pytest.mark.parametrize("bounds", [(256, 0), (512, 2048), (1024, 1024), (256, 4096)])
+def test_sparse_class_bounds(bounds):
+    """Every choice of the SparseBMM bounds (one wavefront, one workgroup or z
+    windows per row) gives the oracle's result."""
+    import paper_2206_04995_amd as P
+
+    light, med = bounds
+    inst = synth.config3(n_vertices=30_000, n_edges=300_000)
+    rng = np.random.default_rng(2)
+    rx = np.concatenate([inst.rx, np.repeat(np.arange(20, dtype=np.int32), 300)])
+    ry = np.concatenate([inst.ry, rng.integers(0, 30_000, 6000).astype(np.int32)])
+    inst = synth.Instance(rx, ry, inst.sz, inst.sy, "graph+heavy")
+    opt = P.make_options(tau_mode=P.JP_TAU_FIXED, dense_threshold=2 ** 63 - 1, sparse_light_max=light,
+                         sparse_med_max=med)
+    print(f"[case] sparse bounds {bounds}", flush=True)
+    assert_parity(inst, opt, chunk=1_000_000)
+
+
 def test_dense_many_windows_and_long_rows():
     # > 65536 dense z (three DenseEC windows), hot keys, cold keys, and x rows
     # with more than 64 join keys (cursor chunk 0 plus binary-searched chunks)

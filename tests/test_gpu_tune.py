@@ -46,6 +46,8 @@ def test_tune_on_graph_and_uniform():
         cols = [dev(c) for c in (inst.rx, inst.ry, inst.sz, inst.sy)]
         r = P.jp_tune(*cols)
         print("[tune]", inst.name, r, flush=True)
+        assert r["sparse_light_max"] in (0, 256, 512) and r["sparse_med_max"] in (0, 2048, 4096)
+        assert r["mfma_tile"] in (0, 1, 2)
         with P.Plan(*cols) as p:
             p.execute()
             assert p.count()[0] == oracle.count(inst.rx, inst.ry, inst.sz, inst.sy)[0]
