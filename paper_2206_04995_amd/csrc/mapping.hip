@@ -252,6 +252,25 @@ __global__ void __launch_bounds__(NT) k_histogram(const uint32_t* __restrict__ v
     if (cnt[i]) atomicAdd(&h[key[i]], cnt[i]);
 }
 
+// Histogram over a small key space (at most SMALL_BINS keys): every block bins
+// a long run of elements in LDS and adds its non-zero bins to the global counts
+// (the hash aggregation above sends most elements of a space wider than its
+// 4096 slots to global atomics, many of them on the same few thousand keys).
+constexpr int SMALL_BINS = 16384;
+
+__global__ void __launch_bounds__(NT) k_histogram_small(const uint32_t* __restrict__ v, int64_t n, int nbins,
+                                                        int64_t per_block, int32_t* __restrict__ h) {
+  __shared__ int32_t bins[SMALL_BINS];
+  for (int i = threadIdx.x; i < nbins; i += NT) bins[i] = 0;
+  __syncthreads();
+  const int64_t b0 = int64_t(blockIdx.x) * per_block;
+  const int64_t b1 = b0 + per_block < n ? b0 + per_block : n;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += NT) atomicAdd(&bins[v[i]], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nbins; i += NT)
+    if (bins[i]) atomicAdd(&h[i], bins[i]);
+}
+
 __global__ void k_out_j(const int32_t* __restrict__ dR, const int32_t* __restrict__ dS, int64_t n_y,
                         const int32_t* __restrict__ y_base, int n_inst, int64_t* __restrict__ out_j) {
   if (n_inst == 1) {  // grid-stride sum, one atomic per block
@@ -489,8 +508,16 @@ void run_lengths(const int32_t* first, int64_t n_id, int32_t* m, hipStream_t s) 
   JP_LAUNCH_CHECK();
 }
 
-void histogram(const uint32_t* v, int64_t n, int32_t* h, hipStream_t s) {
+void histogram(const uint32_t* v, int64_t n, int32_t* h, hipStream_t s, int64_t nbins) {
   if (n <= 0) return;
+  if (nbins > 0 && nbins <= SMALL_BINS) {
+    // about four blocks per CU, each over a long run so its flush of nbins is amortised
+    const int64_t per_block = std::max<int64_t>(int64_t(16) * nbins, (n + 1023) / 1024);
+    const int blocks = int((n + per_block - 1) / per_block);
+    hipLaunchKernelGGL(k_histogram_small, dim3(blocks), dim3(NT), 0, s, v, n, int(nbins), per_block, h);
+    JP_LAUNCH_CHECK();
+    return;
+  }
   const int blocks = int((n + HG_PER_BLOCK - 1) / HG_PER_BLOCK);
   hipLaunchKernelGGL(k_histogram, dim3(blocks), dim3(NT), 0, s, v, n, h);
   JP_LAUNCH_CHECK();

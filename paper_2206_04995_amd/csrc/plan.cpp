@@ -283,7 +283,13 @@ void Plan::map(hipStream_t s) {
   int32_t* d_counts = T.alloc<int32_t>(4, s);
 
   // z ids and m_z; then S in z order with its y keys and z ids (yk, yp) ready
-  // for the stable sort by y
+  // for the stable sort by y.  The sort ping-pongs between (yk, yp) and
+  // (ok, op); its pass count is known here, so the buffer its z ids end in is
+  // scol itself (no copy afterwards).
+  const int ybits_sort = n > 1 ? local_bits(koff_y) : ybits;
+  const bool y_odd = radix_passes(NS, ybits_sort) & 1;
+  scol = A.alloc<int32_t>(NSa, s);
+  uint32_t* const scol_u = reinterpret_cast<uint32_t*>(scol);
   uint32_t *yk, *yp, *ok, *op;
   vals_z = A.alloc<int32_t>(NSa, s);
   z_base = A.alloc<int32_t>(n + 1, s);
@@ -301,12 +307,12 @@ void Plan::map(hipStream_t s) {
     m_z = A.alloc<int32_t>(std::max<int64_t>(std::min(K, NS), 1), s);
     key_ids(cnt, K, Ezk, Czk, dkz, zmin, n, vals_z, m_z, nullptr, s);
     bases_from_koff(Ezk, dkz, n, z_base, s);
-    scatter_z(sz, sy, NS, d_sbase, n, dkz, zmin, dky, ymin, Ezk, Czk, k1, v1, s);
-    JP_HIP(hipMemcpyAsync(d_counts + 0, Ezk + K, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     yk = k1;
-    yp = v1;
+    yp = y_odd ? v1 : scol_u;
     ok = k2;
-    op = v2;
+    op = y_odd ? scol_u : v2;
+    scatter_z(sz, sy, NS, d_sbase, n, dkz, zmin, dky, ymin, Ezk, Czk, yk, yp, s);
+    JP_HIP(hipMemcpyAsync(d_counts + 0, Ezk + K, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   } else {
     // S sorted by (instance, z): z ids, m_z
     make_keys(sz, NS, d_sbase, n, dkz, zmin, k1, v1, sy, s);  // S.y rides along
@@ -319,24 +325,23 @@ void Plan::map(hipStream_t s) {
     gather_bases(Ez, d_sbase, n, z_base, s);
     JP_HIP(hipMemcpyAsync(d_counts + 0, Ez + NS, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     yk = alt ? k1 : k2;  // the free pair
-    yp = alt ? v1 : v2;
+    yp = y_odd ? (alt ? v1 : v2) : scol_u;
     make_keys_carried(zp, NS, d_sbase, n, dky, ymin, Ez, yk, yp, s);
     ok = zk;  // reuse the z-sorted pair as scratch
-    op = zp;
+    op = y_odd ? scol_u : zp;
   }
 
   // S sorted by (instance, y), z ascending inside each y: CSR of S by y
   const SortSegments sseg_y{n, d_sbase, dky, h_sbase};
-  bool alt2 = radix_sort_pairs(yk, yp, ok, op, NS, n > 1 ? local_bits(koff_y) : ybits, s, T, &sseg_y);
-  uint32_t *syk = alt2 ? ok : yk, *syp = alt2 ? op : yp;
+  bool alt2 = radix_sort_pairs(yk, yp, ok, op, NS, ybits_sort, s, T, &sseg_y);
+  uint32_t* syk = alt2 ? ok : yk;
+  if ((alt2 ? op : yp) != scol_u) throw Error(JP_EHIP, "radix sort pass count differs from its plan");
   Ey = A.alloc<int32_t>(NS + 1, s);
   sptr = A.alloc<int32_t>(NS + 1, s);
   vals_y = A.alloc<int32_t>(NSa, s);
   run_ids(syk, NS, dky, ymin, n, Ey, sptr, vals_y, s, T);
   y_base = A.alloc<int32_t>(n + 1, s);
   gather_bases(Ey, d_sbase, n, y_base, s);
-  scol = A.alloc<int32_t>(NSa, s);
-  if (NS) JP_HIP(hipMemcpyAsync(scol, syp, NS * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   JP_HIP(hipMemcpyAsync(d_counts + 1, Ey + NS, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
 
   // semi-join of R on S.y (Sec. 2.2, optimisation 2), then R' grouped by (instance, x)
@@ -409,18 +414,22 @@ void Plan::map(hipStream_t s) {
     const int64_t NRpa = std::max<int64_t>(NRp, 1);
     uint32_t* xk = T.alloc<uint32_t>(NRpa, s);
     uint32_t* xk2 = T.alloc<uint32_t>(NRpa, s);
-    uint32_t* xp2 = T.alloc<uint32_t>(NRpa, s);
+    // with an odd pass count the sorted y ids end in the alternate buffer: rcol itself
+    const int xbits_sort = n > 1 ? local_bits(koff_x) : xbits;
+    const bool x_odd = radix_passes(NRp, xbits_sort) & 1;
+    rcol = A.alloc<int32_t>(NRpa, s);
+    uint32_t* xp2 = x_odd ? reinterpret_cast<uint32_t*>(rcol) : T.alloc<uint32_t>(NRpa, s);
     make_keys(rpx, NRp, d_rpbase, n, dkx, xmin, xk, nullptr, nullptr, s);
     const SortSegments sseg_x{n, d_rpbase, dkx, h_rpbase};
-    bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, n > 1 ? local_bits(koff_x) : xbits, s, T, &sseg_x);
+    bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, xbits_sort, s, T, &sseg_x);
     uint32_t *sxk = alt3 ? xk2 : xk, *sxp = alt3 ? xp2 : rpy;
     int32_t* Ex = T.alloc<int32_t>(NRp + 1, s);
     rptr = A.alloc<int32_t>(NRp + 1, s);
     vals_x = A.alloc<int32_t>(NRpa, s);
     run_ids(sxk, NRp, dkx, xmin, n, Ex, rptr, vals_x, s, T);
     gather_bases(Ex, d_rpbase, n, x_base, s);
-    rcol = A.alloc<int32_t>(NRpa, s);
-    if (NRp) JP_HIP(hipMemcpyAsync(rcol, sxp, NRp * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (NRp && sxp != reinterpret_cast<uint32_t*>(rcol))
+      JP_HIP(hipMemcpyAsync(rcol, sxp, NRp * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   }
 
   // degree statistics (Sec. 2.6): m_z, d_R(y), d_S(y), OUT_J per instance
@@ -432,7 +441,7 @@ void Plan::map(hipStream_t s) {
   dR = A.alloc<int32_t>(NYa, s);
   dS = A.alloc<int32_t>(NYa, s);
   fill_i32(dR, NY, 0, s);
-  histogram(reinterpret_cast<const uint32_t*>(rcol), NRp, dR, s);
+  histogram(reinterpret_cast<const uint32_t*>(rcol), NRp, dR, s, NY);
   run_lengths(sptr, NY, dS, s);
   d_outj = A.alloc<int64_t>(n, s);
   out_j_per_inst(dR, dS, NY, y_base, n, d_outj, s);

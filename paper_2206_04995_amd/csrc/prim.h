@@ -28,6 +28,8 @@ struct SortSegments {
 // (keys only).
 bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int64_t n, int bits,
                       hipStream_t s, Arena& a, const SortSegments* seg = nullptr);
+// passes radix_sort_pairs makes (an odd count leaves the data in (kt, vt))
+int radix_passes(int64_t n, int bits);
 
 // Per-segment min and max of int32 values; segment i is [base[i], base[i+1]).
 // mn/mx (n_seg entries) are overwritten; empty segments give mn > mx.

@@ -389,10 +389,12 @@ void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s, Ar
   scan_impl<int64_t, int64_t>(in, out, n, s, a);
 }
 
+int radix_passes(int64_t n, int bits) { return (n <= 1 || bits <= 0) ? 0 : (bits + 7) / 8; }
+
 bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int64_t n, int bits,
                       hipStream_t s, Arena& a, const SortSegments* seg) {
   if (n <= 1 || bits <= 0) return false;
-  int passes = (bits + 7) / 8;
+  int passes = radix_passes(n, bits);
   int width = (bits + passes - 1) / passes;
   TileMap m{nullptr, nullptr, nullptr, 0};
   int nblocks = int((n + RS_TILE - 1) / RS_TILE);

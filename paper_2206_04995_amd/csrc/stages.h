@@ -69,7 +69,8 @@ void scatter_x(const int32_t* rx, const int32_t* yid, int64_t n, const int32_t* 
                const int32_t* xmin, int32_t* cur, int32_t* rcol, hipStream_t s);
 // m[i] = first[i + 1] - first[i]
 void run_lengths(const int32_t* first, int64_t n_id, int32_t* m, hipStream_t s);
-void histogram(const uint32_t* v, int64_t n, int32_t* h, hipStream_t s);
+// h[v[i]] += 1; nbins > 0 (the key space, when known) picks direct LDS bins for a small space
+void histogram(const uint32_t* v, int64_t n, int32_t* h, hipStream_t s, int64_t nbins = 0);
 // out_j[inst] += sum over y of dR[y] * dS[y]
 void out_j_per_inst(const int32_t* dR, const int32_t* dS, int64_t n_y, const int32_t* y_base, int n_inst,
                     int64_t* out_j, hipStream_t s);
