@@ -60,97 +60,140 @@ __global__ void k_make_keys(const int32_t* __restrict__ v, int64_t n, const int3
   }
 }
 
-__global__ void k_make_keys_carried(const uint32_t* __restrict__ v, int64_t n, const int32_t* __restrict__ ebase,
-                                    int n_inst, const int64_t* __restrict__ koff, const int32_t* __restrict__ mn,
-                                    const int32_t* __restrict__ E, uint32_t* __restrict__ keys,
-                                    uint32_t* __restrict__ payload) {
-  SegCursor<int32_t> cur(ebase, n_inst);
-  cur.seed(int32_t(chunk_first()));
-  CHUNK_LOOP(p, n, JP_CHUNK) {
-    const int inst = cur(int32_t(p));  // sorted by instance first: the instance of position p
-    keys[p] = uint32_t(koff[inst] + (int64_t(int32_t(v[p])) - int64_t(mn[inst])));
-    payload[p] = uint32_t(E[p + 1] - 1);
-  }
-}
-
 // Run ids of sorted keys in two passes over the keys (a head starts a run of
-// equal keys): k_run_heads counts the heads of each tile, and k_run_ids scans
-// the head flags of its tile (offset by the scanned tile counts), writes
-// E[i] = heads before i, and for every head its position first[id] and its
-// original value vals[id] = key - koff[inst] + mn[inst].
+// equal keys): k_run_heads counts the heads of each tile, and k_run_ids ranks
+// the heads of its tile (offset by the scanned tile counts) and writes, for
+// every head, its position first[id] and its original value
+// vals[id] = key - koff[inst] + mn[inst].  A wave owns 64 * RUN_IT consecutive
+// keys and takes them 64 at a time, so loads and stores are coalesced and the
+// head ranks are ballot bit counts.  Per position it writes, by mode:
+//   RUN_E      E[i] = runs started before position i (E[n] = the run count);
+//   RUN_NONE   nothing (ids of segment starts come from first[], ids_at_bases);
+//   RUN_CARRY  the id of position i as payload[i], and the key of the carried
+//              value c.v[i] under a second layout (c.koff, c.mn) as c.keys[i],
+//              ready for the next sort.
 constexpr int RUN_NT = 256;
 constexpr int RUN_IT = 8;
 constexpr int RUN_TILE = RUN_NT * RUN_IT;
+constexpr int RUN_WAVES = RUN_NT / 64;
+constexpr int RUN_WTILE = 64 * RUN_IT;
+enum RunMode { RUN_E = 0, RUN_NONE = 1, RUN_CARRY = 2 };
+
+__device__ __forceinline__ uint64_t run_head_bits(const uint32_t* __restrict__ keys, int64_t n, int64_t w0,
+                                                  const uint32_t (&k)[RUN_IT], uint64_t (&hb)[RUN_IT]) {
+  const int lane = lane_id();
+  uint32_t before = (w0 > 0 && w0 - 1 < n) ? keys[w0 - 1] : 0u;  // key in front of the wave's first
+  uint64_t cnt = 0;
+#pragma unroll
+  for (int j = 0; j < RUN_IT; ++j) {
+    const int64_t i = w0 + j * 64 + lane;
+    uint32_t prev = __shfl_up(k[j], 1, 64);
+    if (lane == 0) prev = before;
+    const bool head = i < n && (i == 0 || prev != k[j]);
+    hb[j] = ballot(head);
+    cnt += uint64_t(__popcll(hb[j]));
+    before = __builtin_amdgcn_readlane(k[j], 63);
+  }
+  return cnt;
+}
 
 __global__ void __launch_bounds__(RUN_NT) k_run_heads(const uint32_t* __restrict__ keys, int64_t n,
                                                       int32_t* __restrict__ sums) {
-  __shared__ int32_t part[RUN_NT / 64];
-  const int64_t b0 = int64_t(blockIdx.x) * RUN_TILE;
-  int c = 0;
+  __shared__ int32_t part[RUN_WAVES];
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  const int64_t w0 = int64_t(blockIdx.x) * RUN_TILE + int64_t(wid) * RUN_WTILE;
+  uint32_t k[RUN_IT];
+  uint64_t hb[RUN_IT];
 #pragma unroll
   for (int j = 0; j < RUN_IT; ++j) {
-    const int64_t i = b0 + j * RUN_NT + threadIdx.x;
-    if (i < n) c += (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+    const int64_t i = w0 + j * 64 + lane;
+    k[j] = i < n ? keys[i] : 0u;
   }
-  c = wave_sum(c);
-  if (lane_id() == 0) part[threadIdx.x >> 6] = c;
+  const int c = int(run_head_bits(keys, n, w0, k, hb));
+  if (lane == 0) part[wid] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
     int t = 0;
-    for (int w = 0; w < RUN_NT / 64; ++w) t += part[w];
+#pragma unroll
+    for (int w = 0; w < RUN_WAVES; ++w) t += part[w];
     sums[blockIdx.x] = t;
   }
 }
 
+
+template <int MODE>
 __global__ void __launch_bounds__(RUN_NT) k_run_ids(const uint32_t* __restrict__ keys, int64_t n,
                                                     const int32_t* __restrict__ offs, const int64_t* __restrict__ koff,
                                                     const int32_t* __restrict__ mn, int n_inst, int32_t* __restrict__ E,
-                                                    int32_t* __restrict__ first, int32_t* __restrict__ vals) {
-  __shared__ int32_t part[RUN_NT / 64];
+                                                    int32_t* __restrict__ first, int32_t* __restrict__ vals,
+                                                    int32_t* __restrict__ total, RunCarry c) {
+  __shared__ int32_t part[RUN_WAVES];
   const int lane = lane_id(), wid = threadIdx.x >> 6;
-  const int64_t b0 = int64_t(blockIdx.x) * RUN_TILE;  // < n: the grid covers n
-  const int64_t base = b0 + int64_t(threadIdx.x) * RUN_IT;
-  SegCursor<int64_t> kcur(koff, n_inst);
-  kcur.seed(int64_t(keys[b0]));  // the tile's smallest key
+  const int64_t w0 = int64_t(blockIdx.x) * RUN_TILE + int64_t(wid) * RUN_WTILE;
+  const uint64_t ltm = lanemask_lt();
   uint32_t k[RUN_IT];
-  int h[RUN_IT];
-  int loc = 0;
+  int32_t cv[RUN_IT];
+  uint64_t hb[RUN_IT];
 #pragma unroll
   for (int j = 0; j < RUN_IT; ++j) {
-    const int64_t i = base + j;
-    k[j] = 0u;
-    h[j] = 0;
-    if (i < n) {
-      k[j] = keys[i];
-      const bool head = i == 0 || (j > 0 ? k[j - 1] : keys[i - 1]) != k[j];
-      h[j] = head ? 1 : 0;
-    }
-    loc += h[j];
+    const int64_t i = w0 + j * 64 + lane;
+    k[j] = i < n ? keys[i] : 0u;
+    if (MODE == RUN_CARRY) cv[j] = i < n ? c.v[i] : 0;
   }
-  const int inc = wave_incl_scan(loc);
-  if (lane == 63) part[wid] = inc;
+  const int cnt = int(run_head_bits(keys, n, w0, k, hb));
+  if (lane == 0) part[wid] = cnt;
   __syncthreads();
-  int pre = 0;
-  for (int w = 0; w < wid; ++w) pre += part[w];
-  int run = (offs ? offs[blockIdx.x] : 0) + pre + inc - loc;
+  int run = offs ? offs[blockIdx.x] : 0, btot = 0;
+#pragma unroll
+  for (int w = 0; w < RUN_WAVES; ++w) {
+    if (w < wid) run += part[w];
+    btot += part[w];
+  }
+  SegCursor<int64_t> kcur(koff, n_inst);
+  if (w0 < n) kcur.seed(int64_t(__builtin_amdgcn_readlane(k[0], 0)));  // the wave's smallest key
 #pragma unroll
   for (int j = 0; j < RUN_IT; ++j) {
-    const int64_t i = base + j;
+    const int64_t i = w0 + j * 64 + lane;
+    const int h = int((hb[j] >> lane) & 1u);
+    const int r = run + __popcll(hb[j] & ltm);  // runs started before i
     if (i < n) {
-      E[i] = run;
-      if (h[j]) {
+      if (MODE == RUN_E) E[i] = r;
+      if (h || MODE == RUN_CARRY) {
         const int inst = kcur(int64_t(k[j]));
-        first[run] = int32_t(i);
-        vals[run] = int32_t(int64_t(k[j]) - koff[inst] + int64_t(mn[inst]));
+        if (h) {
+          first[r] = int32_t(i);
+          vals[r] = int32_t(int64_t(k[j]) - koff[inst] + int64_t(mn[inst]));
+        }
+        if (MODE == RUN_CARRY) {
+          c.keys[i] = uint32_t(c.koff[inst] + (int64_t(cv[j]) - int64_t(c.mn[inst])));
+          c.payload[i] = uint32_t(r + h - 1);
+        }
       }
     }
-    run += h[j];
+    run += __popcll(hb[j]);
   }
-  // the last thread of the grid holds the total: E[n] and first[total] = n
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == RUN_NT - 1) {
-    E[n] = run;
-    first[run] = int32_t(n);
+  // the grid's last block holds the total: E[n], first[total] = n
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const int t = (offs ? offs[blockIdx.x] : 0) + btot;
+    if (MODE == RUN_E) E[n] = t;
+    first[t] = int32_t(n);
+    if (total) *total = t;
   }
+}
+
+// out[i] = runs started before ebase[i] = lower bound of ebase[i] in first[0, *total)
+__global__ void k_ids_at_bases(const int32_t* __restrict__ first, const int32_t* __restrict__ total,
+                               const int32_t* __restrict__ ebase, int n_inst, int32_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n_inst) return;
+  const int32_t p = ebase[i];
+  int64_t lo = 0, hi = *total;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (first[mid] < p) lo = mid + 1;
+    else hi = mid;
+  }
+  out[i] = int32_t(lo);
 }
 
 __global__ void k_gather_bases(const int32_t* __restrict__ E, const int32_t* __restrict__ ebase, int n_inst,
@@ -176,12 +219,12 @@ __global__ void k_semijoin(const int32_t* __restrict__ ry, int64_t n, const int3
 }
 
 // direct-address table of the y keys (used when the key space is small, as
-// for naturally dense domains): table[key] = id for every run head
-__global__ void k_fill_direct(const uint32_t* __restrict__ keys, int64_t n, const int32_t* __restrict__ E,
-                              int32_t* __restrict__ table) {
-  GRID_STRIDE(p, n) {
-    if (E[p + 1] != E[p]) table[keys[p]] = E[p];
-  }
+// for naturally dense domains): table[key] = id, one thread per run of the
+// y-sorted keys (first[id] is the run's first position)
+__global__ void k_fill_direct(const uint32_t* __restrict__ keys, const int32_t* __restrict__ first,
+                              const int32_t* __restrict__ total, int32_t* __restrict__ table) {
+  const int64_t runs = *total;
+  GRID_STRIDE(r, runs) table[keys[first[r]]] = int32_t(r);
 }
 
 __global__ void k_semijoin_direct(const int32_t* __restrict__ ry, int64_t n, const int32_t* __restrict__ ebase,
@@ -435,19 +478,12 @@ void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, co
   JP_LAUNCH_CHECK();
 }
 
-void make_keys_carried(const uint32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff,
-                       const int32_t* mn, const int32_t* E, uint32_t* keys, uint32_t* payload, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_make_keys_carried, dim3(chunk_grid(n)), dim3(NT), 0, s, v, n, ebase, n_inst, koff, mn, E, keys,
-                     payload);
-  JP_LAUNCH_CHECK();
-}
-
 void run_ids(const uint32_t* keys, int64_t n, const int64_t* koff, const int32_t* mn, int n_inst, int32_t* E,
-             int32_t* first, int32_t* vals, hipStream_t s, Arena& a) {
+             int32_t* first, int32_t* vals, hipStream_t s, Arena& a, int32_t* total, const RunCarry* carry) {
   if (n <= 0) {
-    fill_i32(E, 1, 0, s);
+    if (E) fill_i32(E, 1, 0, s);
     fill_i32(first, 1, 0, s);
+    if (total) fill_i32(total, 1, 0, s);
     return;
   }
   const int64_t nb = (n + RUN_TILE - 1) / RUN_TILE;
@@ -460,13 +496,28 @@ void run_ids(const uint32_t* keys, int64_t n, const int64_t* koff, const int32_t
     JP_LAUNCH_CHECK();
     scan_excl_i32(sums, offs, nb, s, a);
   }
-  hipLaunchKernelGGL(k_run_ids, dim3(int(nb)), dim3(RUN_NT), 0, s, keys, n, (const int32_t*)offs, koff, mn, n_inst, E,
-                     first, vals);
+  const RunCarry c = carry ? *carry : RunCarry{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (carry)
+    hipLaunchKernelGGL(k_run_ids<RUN_CARRY>, dim3(int(nb)), dim3(RUN_NT), 0, s, keys, n, (const int32_t*)offs, koff,
+                       mn, n_inst, E, first, vals, total, c);
+  else if (E)
+    hipLaunchKernelGGL(k_run_ids<RUN_E>, dim3(int(nb)), dim3(RUN_NT), 0, s, keys, n, (const int32_t*)offs, koff, mn,
+                       n_inst, E, first, vals, total, c);
+  else
+    hipLaunchKernelGGL(k_run_ids<RUN_NONE>, dim3(int(nb)), dim3(RUN_NT), 0, s, keys, n, (const int32_t*)offs, koff,
+                       mn, n_inst, E, first, vals, total, c);
   JP_LAUNCH_CHECK();
   if (nb > 1) {
     a.give_back(offs, s);
     a.give_back(sums, s);
   }
+}
+
+void ids_at_bases(const int32_t* first, const int32_t* total, const int32_t* ebase, int n_inst, int32_t* out,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_ids_at_bases, dim3((n_inst + 1 + NT - 1) / NT), dim3(NT), 0, s, first, total, ebase, n_inst,
+                     out);
+  JP_LAUNCH_CHECK();
 }
 
 void gather_bases(const int32_t* E, const int32_t* ebase, int n_inst, int32_t* out, hipStream_t s) {
@@ -482,11 +533,11 @@ void semijoin(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, co
 }
 
 void semijoin_direct(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, const uint32_t* ykeys, int64_t ns,
-                     const int32_t* Ey, const int64_t* koff, int64_t key_space, const int32_t* mn, int32_t* table,
-                     int32_t* keep, int32_t* yid, hipStream_t s) {
+                     const int32_t* first, const int32_t* total, const int64_t* koff, int64_t key_space,
+                     const int32_t* mn, int32_t* table, int32_t* keep, int32_t* yid, hipStream_t s) {
   fill_i32(table, key_space, -1, s);
   if (ns > 0) {
-    hipLaunchKernelGGL(k_fill_direct, dim3(grid(ns)), dim3(NT), 0, s, ykeys, ns, Ey, table);
+    hipLaunchKernelGGL(k_fill_direct, dim3(grid(ns, 8192)), dim3(NT), 0, s, ykeys, first, total, table);
     JP_LAUNCH_CHECK();
   }
   if (n <= 0) return;

@@ -319,14 +319,14 @@ void Plan::map(hipStream_t s) {
     const SortSegments sseg_z{n, d_sbase, dkz, h_sbase};
     bool alt = radix_sort_pairs(k1, v1, k2, v2, NS, n > 1 ? local_bits(koff_z) : zbits, s, T, &sseg_z);
     uint32_t *zk = alt ? k2 : k1, *zp = alt ? v2 : v1;
-    int32_t* Ez = T.alloc<int32_t>(NS + 1, s);
+    // z ids of the sorted positions go straight into the y sort's input, with
+    // the carried S.y as its keys
     zfirst = A.alloc<int32_t>(NS + 1, s);
-    run_ids(zk, NS, dkz, zmin, n, Ez, zfirst, vals_z, s, T);
-    gather_bases(Ez, d_sbase, n, z_base, s);
-    JP_HIP(hipMemcpyAsync(d_counts + 0, Ez + NS, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     yk = alt ? k1 : k2;  // the free pair
     yp = y_odd ? (alt ? v1 : v2) : scol_u;
-    make_keys_carried(zp, NS, d_sbase, n, dky, ymin, Ez, yk, yp, s);
+    const RunCarry carry{reinterpret_cast<const int32_t*>(zp), dky, ymin, yk, yp};
+    run_ids(zk, NS, dkz, zmin, n, nullptr, zfirst, vals_z, s, T, d_counts + 0, &carry);
+    ids_at_bases(zfirst, d_counts + 0, d_sbase, n, z_base, s);
     ok = zk;  // reuse the z-sorted pair as scratch
     op = y_odd ? scol_u : zp;
   }
@@ -339,10 +339,9 @@ void Plan::map(hipStream_t s) {
   Ey = A.alloc<int32_t>(NS + 1, s);
   sptr = A.alloc<int32_t>(NS + 1, s);
   vals_y = A.alloc<int32_t>(NSa, s);
-  run_ids(syk, NS, dky, ymin, n, Ey, sptr, vals_y, s, T);
+  run_ids(syk, NS, dky, ymin, n, Ey, sptr, vals_y, s, T, d_counts + 1);
   y_base = A.alloc<int32_t>(n + 1, s);
   gather_bases(Ey, d_sbase, n, y_base, s);
-  JP_HIP(hipMemcpyAsync(d_counts + 1, Ey + NS, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
 
   // semi-join of R on S.y (Sec. 2.2, optimisation 2), then R' grouped by (instance, x)
   const int64_t NRa = std::max<int64_t>(NR, 1);
@@ -351,7 +350,7 @@ void Plan::map(hipStream_t s) {
   if (y_keys <= 2 * NS + 65536) {
     // dense key domain: one table lookup per R tuple instead of a binary search
     int32_t* table = T.alloc<int32_t>(std::max<int64_t>(y_keys, 1), s);
-    semijoin_direct(ry, NR, d_rbase, n, syk, NS, Ey, dky, y_keys, ymin, table, flags, yid, s);
+    semijoin_direct(ry, NR, d_rbase, n, syk, NS, sptr, d_counts + 1, dky, y_keys, ymin, table, flags, yid, s);
   } else {
     semijoin(ry, NR, d_rbase, n, vals_y, y_base, flags, yid, s);
   }
@@ -423,11 +422,11 @@ void Plan::map(hipStream_t s) {
     const SortSegments sseg_x{n, d_rpbase, dkx, h_rpbase};
     bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, xbits_sort, s, T, &sseg_x);
     uint32_t *sxk = alt3 ? xk2 : xk, *sxp = alt3 ? xp2 : rpy;
-    int32_t* Ex = T.alloc<int32_t>(NRp + 1, s);
     rptr = A.alloc<int32_t>(NRp + 1, s);
     vals_x = A.alloc<int32_t>(NRpa, s);
-    run_ids(sxk, NRp, dkx, xmin, n, Ex, rptr, vals_x, s, T);
-    gather_bases(Ex, d_rpbase, n, x_base, s);
+    int32_t* d_nx = T.alloc<int32_t>(1, s);
+    run_ids(sxk, NRp, dkx, xmin, n, nullptr, rptr, vals_x, s, T, d_nx);
+    ids_at_bases(rptr, d_nx, d_rpbase, n, x_base, s);
     if (NRp && sxp != reinterpret_cast<uint32_t*>(rcol))
       JP_HIP(hipMemcpyAsync(rcol, sxp, NRp * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   }

@@ -26,25 +26,37 @@ constexpr int T_STAGE = 3;
 // payload[i] = pay_src[i] (a column carried through the sort) or i
 void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff,
                const int32_t* mn, uint32_t* keys, uint32_t* payload, const int32_t* pay_src, hipStream_t s);
-// keys[p] = key of the value v[p] carried through an earlier sort (position p
-// keeps its instance); payload[p] = E[p + 1] - 1 (the id of sorted position p)
-void make_keys_carried(const uint32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff,
-                       const int32_t* mn, const int32_t* E, uint32_t* keys, uint32_t* payload, hipStream_t s);
-// ids of the runs of equal sorted keys: E[p] = runs started before position p
-// (E[n] = number of runs), and for each run id: first[id] = its first position,
-// vals[id] = the original value of its key; first[E[n]] = n
+// A column carried through a sort by run keys: with it, run_ids writes the id of
+// each sorted position (payload) and the key of the carried value under the
+// layout (koff, mn) of the next sort (keys), instead of E.
+struct RunCarry {
+  const int32_t* v;
+  const int64_t* koff;
+  const int32_t* mn;
+  uint32_t* keys;
+  uint32_t* payload;
+};
+// ids of the runs of equal sorted keys: for each run id, first[id] = its first
+// position and vals[id] = the original value of its key; first[runs] = n, and
+// *total = runs if total is non-null.  If E is non-null, E[p] = runs started
+// before position p (E[n] = runs); with carry, E is not written.
 void run_ids(const uint32_t* keys, int64_t n, const int64_t* koff, const int32_t* mn, int n_inst, int32_t* E,
-             int32_t* first, int32_t* vals, hipStream_t s, Arena& a);
+             int32_t* first, int32_t* vals, hipStream_t s, Arena& a, int32_t* total = nullptr,
+             const RunCarry* carry = nullptr);
+// out[i] = runs started before ebase[i] (i in [0, n_inst]), from first[] and the run count
+void ids_at_bases(const int32_t* first, const int32_t* total, const int32_t* ebase, int n_inst, int32_t* out,
+                  hipStream_t s);
 // out[i] = E[ebase[i]] for i in [0, n_inst]
 void gather_bases(const int32_t* E, const int32_t* ebase, int n_inst, int32_t* out, hipStream_t s);
 // semi-join of R on S.y: keep[g] = 1 and yid[g] = id iff ry[g] occurs among the y values of its instance
 void semijoin(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, const int32_t* vals_y,
               const int32_t* y_base, int32_t* keep, int32_t* yid, hipStream_t s);
 // same result through a direct-address table over the key space of S.y
-// (table has key_space entries; ykeys/Ey are the y-sorted S keys and their scan)
+// (table has key_space entries; ykeys are the y-sorted S keys, first[] their
+// run starts and *total the run count)
 void semijoin_direct(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, const uint32_t* ykeys, int64_t ns,
-                     const int32_t* Ey, const int64_t* koff, int64_t key_space, const int32_t* mn, int32_t* table,
-                     int32_t* keep, int32_t* yid, hipStream_t s);
+                     const int32_t* first, const int32_t* total, const int64_t* koff, int64_t key_space,
+                     const int32_t* mn, int32_t* table, int32_t* keep, int32_t* yid, hipStream_t s);
 // stable compaction of R to the kept tuples
 void compact_r(const int32_t* rx, const int32_t* yid, const int32_t* keep, const int32_t* E, int64_t n,
                int32_t* out_x, int32_t* out_y, hipStream_t s);
