@@ -1,4 +1,4 @@
-// Device primitives for gfx950: reduce-then-scan, LSD radix sort with
+// Device primitives for gfx950: single-pass scan with decoupled look-back, LSD radix sort with
 // wave-ballot ranking and LDS-staged scatter, segmented min/max, fills.
 #include <climits>
 
@@ -30,22 +30,6 @@ __device__ T block_excl_scan(T v, T* lds, T& total) {
   return pre + inc - v;
 }
 
-template <class Ti, class To>
-__global__ void __launch_bounds__(SCAN_NT) k_scan_reduce(const Ti* __restrict__ in, int64_t n,
-                                                         To* __restrict__ sums) {
-  __shared__ To lds[SCAN_NT / 64];
-  int64_t base = int64_t(blockIdx.x) * SCAN_TILE;
-  To acc = 0;
-#pragma unroll
-  for (int j = 0; j < SCAN_IT; ++j) {
-    int64_t i = base + j * SCAN_NT + threadIdx.x;
-    if (i < n) acc += To(in[i]);
-  }
-  To tot;
-  block_excl_scan<To>(acc, lds, tot);
-  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
-}
-
 // exclusive scan of `in` with an added per-block offset; out[n] written by the last block
 template <class Ti, class To>
 __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const Ti* __restrict__ in, To* __restrict__ out,
@@ -74,6 +58,113 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const Ti* __restrict__ i
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + tot;
 }
 
+// Single-pass exclusive scan with decoupled look-back (Merrill and Garland,
+// "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016): a tile
+// takes its index from a counter in the order tiles start, publishes its sum,
+// finds the sum of everything before it from its predecessors' published
+// words, and publishes its inclusive prefix.  The input is read once.  A
+// status word holds a flag in its top two bits (1: tile sum, 2: inclusive
+// prefix, 0: not yet published) and the value as a 62-bit two's complement
+// integer, so one 64-bit store publishes both.  The statuses and the counter
+// start at zero.  A tile only waits on tiles that took their index before it,
+// which are running or done, so every wait ends.
+constexpr int LB_NT = 256;
+constexpr int LB_IT = 16;
+constexpr int LB_WTILE = 64 * LB_IT;    // consecutive elements per wave
+constexpr int LB_TILE = LB_NT * LB_IT;  // 4096 elements per tile
+constexpr uint64_t LB_VAL = (uint64_t(1) << 62) - 1;
+constexpr int LB_SPIN_MAX = 1 << 16;  // polls of one window before the wait gives up and flags status[ntiles + 1]
+
+__device__ __forceinline__ uint64_t lb_pack(uint64_t flag, int64_t v) { return (flag << 62) | (uint64_t(v) & LB_VAL); }
+__device__ __forceinline__ int64_t lb_value(uint64_t w) { return int64_t(w << 2) >> 2; }
+
+template <class T>
+__device__ __forceinline__ T lb_wave_incl(T v) {
+  if constexpr (sizeof(T) == 4) return T(wave_scan_add_dpp(int(v)));
+  else return wave_incl_scan(v);
+}
+
+template <class Ti, class To>
+__global__ void __launch_bounds__(LB_NT) k_scan_lookback(const Ti* __restrict__ in, To* __restrict__ out, int64_t n,
+                                                         uint64_t* __restrict__ status, int64_t ntiles) {
+  __shared__ int64_t s_tile;
+  __shared__ To s_wsum[LB_NT / 64];
+  __shared__ To s_excl;
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_tile = int64_t(atomicAdd(reinterpret_cast<unsigned long long*>(status + ntiles), 1ull));
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t w0 = tile * LB_TILE + int64_t(wid) * LB_WTILE;
+  To v[LB_IT];
+#pragma unroll
+  for (int j = 0; j < LB_IT; ++j) {
+    const int64_t i = w0 + j * 64 + lane;
+    v[j] = i < n ? To(in[i]) : To(0);
+  }
+  To run = 0;  // wave-uniform
+#pragma unroll
+  for (int j = 0; j < LB_IT; ++j) {
+    const To inc = lb_wave_incl<To>(v[j]);
+    const To ex = run + inc - v[j];
+    run += __shfl(inc, 63, 64);
+    v[j] = ex;
+  }
+  if (lane == 0) s_wsum[wid] = run;
+  __syncthreads();
+  To woff = 0, btot = 0;
+#pragma unroll
+  for (int w = 0; w < LB_NT / 64; ++w) {
+    if (w < wid) woff += s_wsum[w];
+    btot += s_wsum[w];
+  }
+  if (wid == 0) {
+    To excl = 0;
+    if (tile == 0) {
+      if (lane == 0) __hip_atomic_store(status, lb_pack(2, int64_t(btot)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      if (lane == 0)
+        __hip_atomic_store(status + tile, lb_pack(1, int64_t(btot)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // lane l reads tile t - l; the window moves back 64 tiles until it holds an inclusive prefix
+      for (int64_t t = tile - 1;; t -= 64) {
+        const int64_t idx = t - lane;
+        uint64_t w;
+        for (int spin = 0;; ++spin) {
+          w = idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       : lb_pack(2, 0);
+          if (ballot((w >> 62) == 0) == 0) break;
+          if (spin == LB_SPIN_MAX) {  // not reached when every tile runs (see above); a bound all the same
+            if (lane == 0) atomicOr(reinterpret_cast<unsigned long long*>(status + ntiles + 1), 1ull);
+            w = lb_pack(2, 0);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        const uint64_t incm = ballot((w >> 62) == 2);
+        const int stop = incm ? __ffsll((unsigned long long)incm) - 1 : 63;
+        excl += wave_sum(lane <= stop ? To(lb_value(w)) : To(0));
+        if (incm) break;
+      }
+      if (lane == 0)
+        __hip_atomic_store(status + tile, lb_pack(2, int64_t(excl + btot)), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (lane == 0) s_excl = excl;
+  }
+  __syncthreads();
+  const To base = s_excl + woff;
+#pragma unroll
+  for (int j = 0; j < LB_IT; ++j) {
+    const int64_t i = w0 + j * 64 + lane;
+    if (i < n) out[i] = base + v[j];
+  }
+  if (tile == ntiles - 1 && threadIdx.x == 0) out[n] = s_excl + btot;
+}
+
+__global__ void k_zero_u64(uint64_t* p, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = 0;
+}
+
 template <class Ti, class To>
 void scan_impl(const Ti* in, To* out, int64_t n, hipStream_t s, Arena& a) {
   if (n <= 0) {
@@ -82,23 +173,19 @@ void scan_impl(const Ti* in, To* out, int64_t n, hipStream_t s, Arena& a) {
     JP_LAUNCH_CHECK();
     return;
   }
-  int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-  if (nb == 1) {
+  if (n <= SCAN_TILE) {
     hipLaunchKernelGGL((k_scan_apply<Ti, To>), dim3(1), dim3(SCAN_NT), 0, s, in, out, n,
                        (const To*)nullptr, 1);
     JP_LAUNCH_CHECK();
     return;
   }
-  To* sums = a.alloc<To>(nb, s);
-  To* offs = a.alloc<To>(nb + 1, s);
-  hipLaunchKernelGGL((k_scan_reduce<Ti, To>), dim3(nb), dim3(SCAN_NT), 0, s, in, n, sums);
+  const int64_t nt = (n + LB_TILE - 1) / LB_TILE;
+  uint64_t* status = a.alloc<uint64_t>(nt + 2, s);  // tile words, the tile counter, a give-up flag
+  hipLaunchKernelGGL(k_zero_u64, dim3(int(std::min<int64_t>((nt + 257) / 256, 1024))), dim3(256), 0, s, status,
+                     nt + 2);
+  hipLaunchKernelGGL((k_scan_lookback<Ti, To>), dim3(int(nt)), dim3(LB_NT), 0, s, in, out, n, status, nt);
   JP_LAUNCH_CHECK();
-  scan_impl<To, To>(sums, offs, nb, s, a);
-  hipLaunchKernelGGL((k_scan_apply<Ti, To>), dim3(nb), dim3(SCAN_NT), 0, s, in, out, n,
-                     (const To*)offs, 0);
-  JP_LAUNCH_CHECK();
-  a.give_back(offs, s);
-  a.give_back(sums, s);
+  a.give_back(status, s);
 }
 
 // ------------------------------------------------------------ radix sort
