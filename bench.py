@@ -220,8 +220,11 @@ def batched(args):
     plain_opt = P.make_options(flags=base_flags)
     timing_opt = P.make_options(flags=P.JP_FLAG_TIMING | base_flags)
 
+    # the C ABI's instance table, built once per batch like the columns it points to
+    table = P.Instances(cols)
+
     def batch(timing=False, want_work=False):
-        b = P.jp_batch_create(cols, opt=timing_opt if timing else plain_opt, stream=stream)
+        b = P.jp_batch_create(table, opt=timing_opt if timing else plain_opt, stream=stream)
         try:
             P.jp_batch_execute(b, stream)
             counts = P.jp_batch_counts(b, len(cols), stream)

@@ -351,8 +351,22 @@ def _instances(cols: Sequence[Tuple]) -> "ctypes.Array":
     return arr
 
 
-def jp_batch_create(cols: Sequence[Tuple], opt: Optional[jp_options] = None, stream=None) -> int:
-    arr = _instances(cols)
+class Instances:
+    """A batch's instance table (the jp_instance array of the C ABI), built once
+    from (r_x, r_y, s_z, s_y) column tensors and reusable for every jp_batch_create
+    over the same columns; it keeps the tensors referenced."""
+
+    def __init__(self, cols: Sequence[Tuple]):
+        self.cols = list(cols)
+        self.arr = _instances(self.cols)
+
+    def __len__(self) -> int:
+        return len(self.cols)
+
+
+def jp_batch_create(cols, opt: Optional[jp_options] = None, stream=None) -> int:
+    """cols: a sequence of (r_x, r_y, s_z, s_y) tensors, or an Instances table."""
+    arr = cols.arr if isinstance(cols, Instances) else _instances(cols)
     h = ctypes.c_void_p()
     _check(lib.jp_batch_create(arr, len(cols), ctypes.byref(opt) if opt is not None else None, _stream(stream),
                                ctypes.byref(h)))

@@ -208,4 +208,64 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 
 inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
+
+// ------------------------------------------------- decoupled look-back
+// Single-pass prefix over tiles (Merrill and Garland, "Single-pass Parallel
+// Prefix Scan with Decoupled Look-back", 2016).  A tile takes its index from a
+// counter (status[ntiles]) in the order tiles start, publishes its own total,
+// sums what its predecessors published until it meets an inclusive prefix,
+// and publishes its own inclusive prefix.  A status word holds a flag in its
+// top two bits (1: tile total, 2: inclusive prefix, 0: not yet published) and
+// the value as a 62-bit two's complement integer, so one 64-bit store
+// publishes both.  status[0, ntiles + 2) starts at zero.  A tile only waits on
+// tiles that took their index before it, which are running or done, so every
+// wait ends; the wait is bounded all the same (status[ntiles + 1] records a
+// wait that gave up).
+constexpr uint64_t LB_VALUE_MASK = (uint64_t(1) << 62) - 1;
+constexpr int LB_SPIN_MAX = 1 << 16;
+
+__device__ __forceinline__ uint64_t lb_pack(uint64_t flag, int64_t v) {
+  return (flag << 62) | (uint64_t(v) & LB_VALUE_MASK);
+}
+__device__ __forceinline__ int64_t lb_value(uint64_t w) { return int64_t(w << 2) >> 2; }
+
+// thread 0 of the block: the tile index, in start order
+__device__ __forceinline__ int64_t lookback_ticket(uint64_t* status, int64_t ntiles) {
+  return int64_t(atomicAdd(reinterpret_cast<unsigned long long*>(status + ntiles), 1ull));
+}
+
+// one whole wave: returns the sum of the totals of tiles [0, tile) and
+// publishes this tile's inclusive prefix
+__device__ __forceinline__ int64_t lookback_exclusive(uint64_t* status, int64_t tile, int64_t ntiles, int64_t total) {
+  const int lane = lane_id();
+  int64_t excl = 0;
+  if (tile == 0) {
+    if (lane == 0) __hip_atomic_store(status, lb_pack(2, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return 0;
+  }
+  if (lane == 0) __hip_atomic_store(status + tile, lb_pack(1, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // lane l reads tile t - l; the window moves back 64 tiles until it holds an inclusive prefix
+  for (int64_t t = tile - 1;; t -= 64) {
+    const int64_t idx = t - lane;
+    uint64_t w;
+    for (int spin = 0;; ++spin) {
+      w = idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : lb_pack(2, 0);
+      if (ballot((w >> 62) == 0) == 0) break;
+      if (spin == LB_SPIN_MAX) {
+        if (lane == 0) atomicOr(reinterpret_cast<unsigned long long*>(status + ntiles + 1), 1ull);
+        w = lb_pack(2, 0);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    const uint64_t incm = ballot((w >> 62) == 2);
+    const int stop = incm ? __ffsll((unsigned long long)incm) - 1 : 63;
+    excl += wave_sum(lane <= stop ? lb_value(w) : int64_t(0));
+    if (incm) break;
+  }
+  if (lane == 0)
+    __hip_atomic_store(status + tile, lb_pack(2, excl + total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return excl;
+}
+
 }  // namespace jp

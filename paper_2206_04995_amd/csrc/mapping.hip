@@ -243,15 +243,104 @@ __global__ void k_semijoin_direct(const int32_t* __restrict__ ry, int64_t n, con
   }
 }
 
-__global__ void k_compact_r(const int32_t* __restrict__ rx, const int32_t* __restrict__ yid,
-                            const int32_t* __restrict__ keep, const int32_t* __restrict__ E, int64_t n,
-                            int32_t* __restrict__ ox, int32_t* __restrict__ oy) {
-  GRID_STRIDE(g, n) {
-    if (keep[g]) {
-      int32_t p = E[g];
-      ox[p] = rx[g];
-      oy[p] = yid[g];
+// Semi-join, compaction and x keys in one pass (Sec. 2.2, optimisation 2):
+// per R tuple its y id (direct table or binary search among the instance's y
+// values), and for the kept tuples, in order, the key of x under the layout
+// (koff_x, xmin) and the y id.  A tile places its kept tuples at the
+// look-back prefix of the kept counts (lookback_exclusive), and writes
+// rpbase[i] = kept tuples before ebase[i] for the instances starting in it.
+constexpr int SJ_NT = 256;
+constexpr int SJ_IT = 16;
+constexpr int SJ_WTILE = 64 * SJ_IT;
+constexpr int SJ_TILE = SJ_NT * SJ_IT;
+
+template <bool DIRECT>
+__global__ void __launch_bounds__(SJ_NT) k_semijoin_compact(SemiJoinIn in, uint32_t* __restrict__ xk,
+                                                            uint32_t* __restrict__ oy, int32_t* __restrict__ rpbase,
+                                                            int32_t* __restrict__ total, uint64_t* __restrict__ status,
+                                                            int64_t ntiles) {
+  __shared__ int64_t s_tile;
+  __shared__ int32_t s_wsum[SJ_NT / 64];
+  __shared__ int64_t s_excl;
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  const uint64_t ltm = lanemask_lt();
+  if (threadIdx.x == 0) s_tile = lookback_ticket(status, ntiles);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t w0 = tile * SJ_TILE + int64_t(wid) * SJ_WTILE;
+  SegCursor<int32_t> cur(in.ebase, in.n_inst);
+  if (w0 < in.n) cur.seed(int32_t(w0));
+  // columns and instances of all rows first (loads at clamped, valid indices), then the y lookups
+  int32_t xr[SJ_IT], yr[SJ_IT], ins[SJ_IT];
+  uint32_t starts = 0;  // bit j: this lane's position of row j starts an instance
+#pragma unroll
+  for (int j = 0; j < SJ_IT; ++j) {
+    const int64_t i = w0 + j * 64 + lane;
+    const int64_t ic = i < in.n ? i : in.n - 1;
+    xr[j] = in.rx[ic];
+    yr[j] = in.ry[ic];
+    ins[j] = 0;
+    if (i < in.n) {
+      ins[j] = cur(int32_t(i));
+      if (i == cur.lo) starts |= 1u << j;
     }
+  }
+  uint32_t xv[SJ_IT];
+  int32_t yid[SJ_IT];
+  int cnt = 0;
+#pragma unroll
+  for (int j = 0; j < SJ_IT; ++j) {
+    const int inst = ins[j];
+    int32_t id = -1;
+    if (DIRECT) {
+      const int64_t rel = int64_t(yr[j]) - int64_t(in.ymin[inst]);
+      const int64_t k0 = in.koff_y[inst];
+      const bool ok = rel >= 0 && rel < in.koff_y[inst + 1] - k0;
+      const int32_t t = in.table[ok ? k0 + rel : 0];
+      id = ok ? t : -1;
+    } else {
+      const int64_t lo = in.y_base[inst], hi = in.y_base[inst + 1];
+      const int64_t pos = lower_bound_dev<int32_t>(in.vals_y, lo, hi, yr[j]);
+      if (pos < hi && in.vals_y[pos] == yr[j]) id = int32_t(pos);
+    }
+    yid[j] = w0 + j * 64 + lane < in.n ? id : -1;
+    xv[j] = uint32_t(in.koff_x[inst] + (int64_t(xr[j]) - int64_t(in.xmin[inst])));
+    cnt += __popcll(ballot(yid[j] >= 0));
+  }
+  if (lane == 0) s_wsum[wid] = cnt;
+  __syncthreads();
+  int32_t woff = 0, btot = 0;
+#pragma unroll
+  for (int w = 0; w < SJ_NT / 64; ++w) {
+    if (w < wid) woff += s_wsum[w];
+    btot += s_wsum[w];
+  }
+  if (wid == 0) {
+    const int64_t excl = lookback_exclusive(status, tile, ntiles, btot);
+    if (lane == 0) s_excl = excl;
+  }
+  __syncthreads();
+  int64_t run = s_excl + woff;  // wave-uniform
+#pragma unroll
+  for (int j = 0; j < SJ_IT; ++j) {
+    const uint64_t b = ballot(yid[j] >= 0);
+    const int64_t before = run + __popcll(b & ltm);
+    if (yid[j] >= 0) {
+      xk[before] = xv[j];
+      oy[before] = uint32_t(yid[j]);
+    }
+    if ((starts >> j) & 1u) {
+      // the instance holding this position and any empty ones starting here
+      const int32_t i = int32_t(w0 + j * 64 + lane);
+      for (int k = find_inst<int32_t>(in.ebase, in.n_inst, i); k >= 0 && in.ebase[k] == i; --k)
+        rpbase[k] = int32_t(before);
+    }
+    run += __popcll(b);
+  }
+  if (tile == ntiles - 1 && threadIdx.x == 0) {
+    const int32_t t = int32_t(s_excl + btot);
+    *total = t;
+    for (int k = in.n_inst; k >= 0 && in.ebase[k] == in.n; --k) rpbase[k] = t;
   }
 }
 
@@ -546,11 +635,33 @@ void semijoin_direct(const int32_t* ry, int64_t n, const int32_t* ebase, int n_i
   JP_LAUNCH_CHECK();
 }
 
-void compact_r(const int32_t* rx, const int32_t* yid, const int32_t* keep, const int32_t* E, int64_t n, int32_t* ox,
-               int32_t* oy, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_compact_r, dim3(grid(n)), dim3(NT), 0, s, rx, yid, keep, E, n, ox, oy);
+void fill_direct_table(const uint32_t* ykeys, int64_t ns, const int32_t* first, const int32_t* total,
+                       int64_t key_space, int32_t* table, hipStream_t s) {
+  fill_i32(table, key_space, -1, s);
+  if (ns > 0) {
+    hipLaunchKernelGGL(k_fill_direct, dim3(grid(ns, 8192)), dim3(NT), 0, s, ykeys, first, total, table);
+    JP_LAUNCH_CHECK();
+  }
+}
+
+void semijoin_compact(const SemiJoinIn& in, uint32_t* xk, uint32_t* oy, int32_t* rpbase, int32_t* total,
+                      hipStream_t s, Arena& a) {
+  if (in.n <= 0) {
+    fill_i32(rpbase, int64_t(in.n_inst) + 1, 0, s);
+    fill_i32(total, 1, 0, s);
+    return;
+  }
+  const int64_t nt = (in.n + SJ_TILE - 1) / SJ_TILE;
+  uint64_t* status = a.alloc<uint64_t>(nt + 2, s);
+  fill_i64(reinterpret_cast<int64_t*>(status), nt + 2, 0, s);
+  if (in.table)
+    hipLaunchKernelGGL(k_semijoin_compact<true>, dim3(int(nt)), dim3(SJ_NT), 0, s, in, xk, oy, rpbase, total, status,
+                       nt);
+  else
+    hipLaunchKernelGGL(k_semijoin_compact<false>, dim3(int(nt)), dim3(SJ_NT), 0, s, in, xk, oy, rpbase, total,
+                       status, nt);
   JP_LAUNCH_CHECK();
+  a.give_back(status, s);
 }
 
 void run_lengths(const int32_t* first, int64_t n_id, int32_t* m, hipStream_t s) {

@@ -40,40 +40,9 @@ __global__ void k_dense_index(const int32_t* __restrict__ flag, const int32_t* _
   }
 }
 
-// one thread per S entry; the row (y id) of entry p is Ey[p + 1] - 1
-__global__ void k_entry_flags(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol, int64_t n,
-                              const int32_t* __restrict__ zflag, const int32_t* __restrict__ hot,
-                              int32_t* __restrict__ sp_flag, int32_t* __restrict__ cold_flag) {
-  GRID_STRIDE(p, n) {
-    int d = zflag[scol[p]];
-    if (sp_flag) sp_flag[p] = d ? 0 : 1;
-    if (cold_flag) {
-      int h = hot[Ey[p + 1] - 1];
-      cold_flag[p] = (d && !h) ? 1 : 0;
-    }
-  }
-}
-
 __global__ void k_remap_rowptr(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ E, int64_t n_y,
                                int32_t* __restrict__ out) {
   GRID_STRIDE(y, n_y + 1) { out[y] = E[rowptr[y]]; }
-}
-
-__global__ void k_compact_entries(const int32_t* __restrict__ scol, const int32_t* __restrict__ flag,
-                                  const int32_t* __restrict__ E, int64_t n, const int32_t* __restrict__ Edz,
-                                  const int32_t* __restrict__ z_base, const int32_t* __restrict__ zd_base,
-                                  int n_inst, int to_local_dense, int32_t* __restrict__ out) {
-  GRID_STRIDE(p, n) {
-    if (flag[p]) {
-      int32_t z = scol[p];
-      int32_t v = z;
-      if (to_local_dense) {
-        int inst = n_inst == 1 ? 0 : find_inst<int32_t>(z_base, n_inst, z);
-        v = Edz[z] - zd_base[inst];
-      }
-      out[E[p]] = v;
-    }
-  }
 }
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
@@ -161,25 +130,97 @@ __global__ void k_build_hot_bits(const int32_t* __restrict__ Ey, const int32_t* 
   }
 }
 
-// per S entry: 1 iff its z lies in the space and its key is not hot (cold entry)
-__global__ void k_cold_flags(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol, int64_t n,
-                             const int32_t* __restrict__ zmap, const int32_t* __restrict__ hot,
-                             int32_t* __restrict__ flag) {
-  GRID_STRIDE(p, n) flag[p] = (zmap[scol[p]] >= 0 && !hot[Ey[p + 1] - 1]) ? 1 : 0;
-}
-
 // per S entry: 1 iff its z lies in the space
 __global__ void k_space_flags(const int32_t* __restrict__ scol, int64_t n, const int32_t* __restrict__ zmap,
                               int32_t* __restrict__ flag) {
   GRID_STRIDE(p, n) flag[p] = zmap[scol[p]] >= 0 ? 1 : 0;
 }
 
-// compaction of flagged S entries to their local index in the space
-__global__ void k_compact_mapped(const int32_t* __restrict__ scol, const int32_t* __restrict__ flag,
-                                 const int32_t* __restrict__ E, int64_t n, const int32_t* __restrict__ zmap,
-                                 int32_t* __restrict__ out) {
-  GRID_STRIDE(p, n) {
-    if (flag[p]) out[E[p]] = zmap[scol[p]];
+// S entries (CSR by y, the row of entry p is Ey[p + 1] - 1) filtered into a
+// CSR over the same rows in one pass: the kept entries in order (out), the
+// row pointers (rowptr[row] at each row's first entry, rowptr[n_rows] = kept)
+// and the kept count.  A tile places its kept entries at the look-back
+// prefix of the kept counts (lookback_exclusive).  Every row has an entry.
+//   FILTER_SPARSE  keep z with zsel[z] == 0 (z not dense), out = z;
+//   FILTER_COLD    keep z with zsel[z] >= 0 (z in the space) whose row is not
+//                  hot, out = zsel[z] (the local index in the space).
+constexpr int FR_NT = 256;
+constexpr int FR_IT = 16;
+constexpr int FR_WTILE = 64 * FR_IT;
+constexpr int FR_TILE = FR_NT * FR_IT;
+enum FilterMode { FILTER_SPARSE = 0, FILTER_COLD = 1 };
+
+template <int MODE>
+__global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol,
+                                                       int64_t n, const int32_t* __restrict__ zsel,
+                                                       const int32_t* __restrict__ hot, int32_t* __restrict__ out,
+                                                       int32_t* __restrict__ rowptr, int64_t n_rows,
+                                                       int32_t* __restrict__ total, uint64_t* __restrict__ status,
+                                                       int64_t ntiles) {
+  __shared__ int64_t s_tile;
+  __shared__ int32_t s_wsum[FR_NT / 64];
+  __shared__ int64_t s_excl;
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  const uint64_t ltm = lanemask_lt();
+  if (threadIdx.x == 0) s_tile = lookback_ticket(status, ntiles);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t w0 = tile * FR_TILE + int64_t(wid) * FR_WTILE;
+  // every load first, at clamped (valid) indices, so the gathers of all rows are in flight together
+  int32_t val[FR_IT], row1[FR_IT];  // row1: row + 1 of a row's first entry, else 0
+  int32_t z[FR_IT], e1[FR_IT], e0[FR_IT];
+#pragma unroll
+  for (int j = 0; j < FR_IT; ++j) {
+    int64_t i = w0 + j * 64 + lane;
+    i = i < n ? i : n - 1;
+    e1[j] = Ey[i + 1];
+    e0[j] = Ey[i];
+    z[j] = scol[i];
+  }
+  int32_t sel[FR_IT], h[FR_IT];
+#pragma unroll
+  for (int j = 0; j < FR_IT; ++j) {
+    sel[j] = zsel[z[j]];
+    h[j] = MODE == FILTER_COLD ? hot[e1[j] - 1] : 0;
+  }
+  uint32_t keep = 0;
+  int cnt = 0;
+#pragma unroll
+  for (int j = 0; j < FR_IT; ++j) {
+    const bool in = w0 + j * 64 + lane < n;
+    const bool k = in && (MODE == FILTER_SPARSE ? sel[j] == 0 : (sel[j] >= 0 && !h[j]));
+    val[j] = MODE == FILTER_SPARSE ? z[j] : sel[j];
+    row1[j] = (in && e1[j] != e0[j]) ? e1[j] : 0;
+    if (k) keep |= 1u << j;
+    cnt += __popcll(ballot(k));
+  }
+  if (lane == 0) s_wsum[wid] = cnt;
+  __syncthreads();
+  int32_t woff = 0, btot = 0;
+#pragma unroll
+  for (int w = 0; w < FR_NT / 64; ++w) {
+    if (w < wid) woff += s_wsum[w];
+    btot += s_wsum[w];
+  }
+  if (wid == 0) {
+    const int64_t excl = lookback_exclusive(status, tile, ntiles, btot);
+    if (lane == 0) s_excl = excl;
+  }
+  __syncthreads();
+  int64_t run = s_excl + woff;  // wave-uniform
+#pragma unroll
+  for (int j = 0; j < FR_IT; ++j) {
+    const bool k = (keep >> j) & 1u;
+    const uint64_t b = ballot(k);
+    const int64_t before = run + __popcll(b & ltm);
+    if (k) out[before] = val[j];
+    if (row1[j]) rowptr[row1[j] - 1] = int32_t(before);
+    run += __popcll(b);
+  }
+  if (tile == ntiles - 1 && threadIdx.x == 0) {
+    const int32_t t = int32_t(s_excl + btot);
+    rowptr[n_rows] = t;
+    *total = t;
   }
 }
 
@@ -436,24 +477,29 @@ void dense_index(const int32_t* flag, const int32_t* Edz, int64_t n_z, int32_t* 
   JP_LAUNCH_CHECK();
 }
 
-void entry_flags(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zflag, const int32_t* hot,
-                 int32_t* sp_flag, int32_t* cold_flag, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_entry_flags, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, zflag, hot, sp_flag, cold_flag);
+void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zsel,
+                 const int32_t* hot, int32_t* out, int32_t* rowptr, int64_t n_rows, int32_t* total, hipStream_t s,
+                 Arena& a) {
+  if (n <= 0) {
+    fill_i32(rowptr, n_rows + 1, 0, s);
+    fill_i32(total, 1, 0, s);
+    return;
+  }
+  const int64_t nt = (n + FR_TILE - 1) / FR_TILE;
+  uint64_t* status = a.alloc<uint64_t>(nt + 2, s);
+  fill_i64(reinterpret_cast<int64_t*>(status), nt + 2, 0, s);
+  if (cold)
+    hipLaunchKernelGGL(k_filter_rows<FILTER_COLD>, dim3(int(nt)), dim3(FR_NT), 0, s, Ey, scol, n, zsel, hot, out, rowptr,
+                       n_rows, total, status, nt);
+  else
+    hipLaunchKernelGGL(k_filter_rows<FILTER_SPARSE>, dim3(int(nt)), dim3(FR_NT), 0, s, Ey, scol, n, zsel, hot, out,
+                       rowptr, n_rows, total, status, nt);
   JP_LAUNCH_CHECK();
+  a.give_back(status, s);
 }
 
 void remap_rowptr(const int32_t* rowptr, const int32_t* E, int64_t n_y, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_remap_rowptr, dim3(grid(n_y + 1)), dim3(NT), 0, s, rowptr, E, n_y, out);
-  JP_LAUNCH_CHECK();
-}
-
-void compact_entries(const int32_t* scol, const int32_t* flag, const int32_t* E, int64_t n, const int32_t* Edz,
-                     const int32_t* z_base, const int32_t* zd_base, int n_inst, bool to_local_dense, int32_t* out,
-                     hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_compact_entries, dim3(grid(n)), dim3(NT), 0, s, scol, flag, E, n, Edz, z_base, zd_base, n_inst,
-                     to_local_dense ? 1 : 0, out);
   JP_LAUNCH_CHECK();
 }
 
@@ -481,23 +527,9 @@ void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int
   JP_LAUNCH_CHECK();
 }
 
-void cold_flags(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zmap, const int32_t* hot,
-                int32_t* flag, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_cold_flags, dim3(grid(n)), dim3(NT), 0, s, Ey, scol, n, zmap, hot, flag);
-  JP_LAUNCH_CHECK();
-}
-
 void space_flags(const int32_t* scol, int64_t n, const int32_t* zmap, int32_t* flag, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_space_flags, dim3(grid(n)), dim3(NT), 0, s, scol, n, zmap, flag);
-  JP_LAUNCH_CHECK();
-}
-
-void compact_mapped(const int32_t* scol, const int32_t* flag, const int32_t* E, int64_t n, const int32_t* zmap,
-                    int32_t* out, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_compact_mapped, dim3(grid(n)), dim3(NT), 0, s, scol, flag, E, n, zmap, out);
   JP_LAUNCH_CHECK();
 }
 

@@ -83,23 +83,51 @@ int local_bits(const std::vector<int64_t>& koff) {
   return bits_for(uint64_t(w));
 }
 
-// gather of per-instance device columns into one concatenated buffer
+// gather of per-instance device columns into one concatenated buffer; with
+// mn/mx non-null also each instance's minimum and maximum (the key layout of
+// the mapping), so the column is read once for both
+__device__ __forceinline__ void flush_minmax(int inst, int32_t lo, int32_t hi, int32_t* mn, int32_t* mx) {
+  // whole wave: one atomic pair when every lane holds the same instance
+  const int i0 = __builtin_amdgcn_readfirstlane(inst);
+  if (ballot(inst != i0) == 0) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int32_t a = __shfl_xor(lo, o, 64), b = __shfl_xor(hi, o, 64);
+      lo = a < lo ? a : lo;
+      hi = b > hi ? b : hi;
+    }
+    if (lane_id() == 0 && inst >= 0) {
+      atomicMin(&mn[inst], lo);
+      atomicMax(&mx[inst], hi);
+    }
+  } else if (inst >= 0) {
+    atomicMin(&mn[inst], lo);
+    atomicMax(&mx[inst], hi);
+  }
+}
+
 __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int32_t* __restrict__ base, int n_inst,
-                              int64_t n, int32_t* __restrict__ dst) {
+                              int64_t n, int32_t* __restrict__ dst, int32_t* __restrict__ mn,
+                              int32_t* __restrict__ mx) {
   SegCursor<int32_t> cur(base, n_inst);
   cur.seed(int32_t(chunk_first()));
   const int64_t c1 = chunk_first() + JP_CHUNK < n ? chunk_first() + JP_CHUNK : n;
   const int64_t step = blockDim.x;
   const int32_t* col = nullptr;
-  int last = -1;
+  int last = -1;                           // instance of `col`
+  int acc = -1;                            // instance whose values lo and hi hold
+  int32_t lo = INT32_MAX, hi = INT32_MIN;
   // four elements per thread and step: their source addresses first, then the
-  // four loads in flight together, then the stores
+  // four loads in flight together, then the stores (and the min and max, in
+  // element order, so a lane's values move to the next instance's at its bound)
   for (int64_t g0 = chunk_first() + threadIdx.x; g0 < c1; g0 += 4 * step) {
     const int32_t* at[4];
+    int iu[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t g = g0 + u * step;
       at[u] = nullptr;
+      iu[u] = -1;
       if (g < c1) {
         const int inst = cur(int32_t(g));
         if (inst != last) {
@@ -107,6 +135,7 @@ __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int3
           col = src[inst];
         }
         at[u] = col + (g - cur.lo);
+        iu[u] = inst;
       }
     }
     int32_t vv[4];
@@ -114,8 +143,30 @@ __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int3
     for (int u = 0; u < 4; ++u) vv[u] = at[u] ? *at[u] : 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (g0 + u * step < c1) dst[g0 + u * step] = vv[u];
+      if (iu[u] >= 0) {
+        dst[g0 + u * step] = vv[u];
+        if (mn) {
+          if (iu[u] != acc) {  // rare: at instance bounds
+            if (acc >= 0) {
+              atomicMin(&mn[acc], lo);
+              atomicMax(&mx[acc], hi);
+            }
+            acc = iu[u];
+            lo = INT32_MAX;
+            hi = INT32_MIN;
+          }
+          lo = vv[u] < lo ? vv[u] : lo;
+          hi = vv[u] > hi ? vv[u] : hi;
+        }
+      }
   }
+  if (mn) flush_minmax(acc, lo, hi, mn, mx);
+}
+
+// minima (rows 0, 2, 4 of n) start at INT32_MAX, maxima (rows 1, 3, 5) at INT32_MIN
+__global__ void k_fill_minmax(int32_t* mm, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 6 * n) mm[i] = ((i / n) & 1) ? INT32_MIN : INT32_MAX;
 }
 
 __global__ void k_slice_info(const int64_t* __restrict__ off_de, const int64_t* __restrict__ off_sp,
@@ -195,13 +246,22 @@ void Plan::build(const jp_instance* inst, int n, const jp_options* o, hipStream_
     h2d(d_ptrs, ptrs.data(), ptrs.size(), s);
     int32_t* cat = A.alloc<int32_t>(2 * NR + 2 * NS, s);
     int32_t *crx = cat, *cry = cat + NR, *csz = cat + 2 * NR, *csy = cat + 2 * NR + NS;
+    // per-instance min and max of z, y (S) and x (R) come with the gather: the mapping's key layouts
+    d_minmax = A.alloc<int32_t>(6 * int64_t(n), s);
+    int32_t *zmin = d_minmax, *zmax = d_minmax + n, *ymin = d_minmax + 2 * n, *ymax = d_minmax + 3 * n;
+    int32_t *xmin = d_minmax + 4 * n, *xmax = d_minmax + 5 * n;
+    hipLaunchKernelGGL(k_fill_minmax, dim3((6 * n + 255) / 256), dim3(256), 0, s, d_minmax, n);
+    int32_t* none = nullptr;
     if (NR) {
-      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NR)), dim3(256), 0, s, d_ptrs, d_rbase, n, NR, crx);
-      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NR)), dim3(256), 0, s, d_ptrs + n, d_rbase, n, NR, cry);
+      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NR)), dim3(256), 0, s, d_ptrs, d_rbase, n, NR, crx, xmin, xmax);
+      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NR)), dim3(256), 0, s, d_ptrs + n, d_rbase, n, NR, cry, none,
+                         none);
     }
     if (NS) {
-      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NS)), dim3(256), 0, s, d_ptrs + 2 * n, d_sbase, n, NS, csz);
-      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NS)), dim3(256), 0, s, d_ptrs + 3 * n, d_sbase, n, NS, csy);
+      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NS)), dim3(256), 0, s, d_ptrs + 2 * n, d_sbase, n, NS, csz,
+                         zmin, zmax);
+      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NS)), dim3(256), 0, s, d_ptrs + 3 * n, d_sbase, n, NS, csy,
+                         ymin, ymax);
     }
     JP_LAUNCH_CHECK();
     rx = crx;
@@ -239,13 +299,16 @@ void Plan::map(hipStream_t s) {
   const int n = n_inst;
   Arena T(&B);  // temporaries of the mapping stage
   const bool sort_ids = (opt.flags & JP_FLAG_DIRECT_IDS) == 0;
-  int32_t* mm = T.alloc<int32_t>(6 * int64_t(n), s);
+  // per-instance min and max of S.z, S.y and R.x (all of R: the x keys' layout); a batch's gather took them
+  int32_t* mm = d_minmax ? d_minmax : T.alloc<int32_t>(6 * int64_t(n), s);
   int32_t *zmin = mm, *zmax = mm + n, *ymin = mm + 2 * n, *ymax = mm + 3 * n, *xmin = mm + 4 * n, *xmax = mm + 5 * n;
-  seg_minmax(sz, NS, d_sbase, n, zmin, zmax, s);
-  seg_minmax(sy, NS, d_sbase, n, ymin, ymax, s);
-  if (!sort_ids) seg_minmax(rx, NR, d_rbase, n, xmin, xmax, s);  // over all of R: the direct x mapping's range
+  if (!d_minmax) {
+    seg_minmax(sz, NS, d_sbase, n, zmin, zmax, s);
+    seg_minmax(sy, NS, d_sbase, n, ymin, ymax, s);
+    seg_minmax(rx, NR, d_rbase, n, xmin, xmax, s);
+  }
   std::vector<int32_t> h_mm(6 * size_t(n));
-  d2h(h_mm.data(), mm, (sort_ids ? 4 : 6) * size_t(n), s);
+  d2h(h_mm.data(), mm, 6 * size_t(n), s);
   // f1 (Sec. 2.6) rides on this first read-back: the classical path when the
   // sampled OUT_J is small against the input
   unsigned long long h_match = 0;
@@ -267,11 +330,12 @@ void Plan::map(hipStream_t s) {
   const bool direct_z = !sort_ids && direct_ok(koff_z[n], NS);
   bool direct_x = false;
   if (!sort_ids) direct_x = direct_ok(key_space(part(4), part(5), koff_x), NR);
+  const int xbits = direct_x ? 0 : key_layout(part(4), part(5), koff_x);
   int64_t* d_koff = T.alloc<int64_t>(3 * (int64_t(n) + 1), s);
   int64_t *dkz = d_koff, *dky = d_koff + (n + 1), *dkx = d_koff + 2 * (n + 1);
   h2d(dkz, koff_z.data(), n + 1, s);
   h2d(dky, koff_y.data(), n + 1, s);
-  if (direct_x) h2d(dkx, koff_x.data(), n + 1, s);
+  h2d(dkx, koff_x.data(), n + 1, s);
   map_direct = (direct_z ? 1 : 0) | (direct_x ? 2 : 0);
 
   const int64_t NSa = std::max<int64_t>(NS, 1);
@@ -279,7 +343,6 @@ void Plan::map(hipStream_t s) {
   uint32_t* v1 = T.alloc<uint32_t>(NSa, s);
   uint32_t* k2 = T.alloc<uint32_t>(NSa, s);
   uint32_t* v2 = T.alloc<uint32_t>(NSa, s);
-  int32_t* flags = T.alloc<int32_t>(std::max<int64_t>(std::max(NS, NR), 1), s);
   int32_t* d_counts = T.alloc<int32_t>(4, s);
 
   // z ids and m_z; then S in z order with its y keys and z ids (yk, yp) ready
@@ -345,20 +408,20 @@ void Plan::map(hipStream_t s) {
 
   // semi-join of R on S.y (Sec. 2.2, optimisation 2), then R' grouped by (instance, x)
   const int64_t NRa = std::max<int64_t>(NR, 1);
-  int32_t* yid = T.alloc<int32_t>(NRa, s);
   const int64_t y_keys = koff_y[n];
-  if (y_keys <= 2 * NS + 65536) {
-    // dense key domain: one table lookup per R tuple instead of a binary search
-    int32_t* table = T.alloc<int32_t>(std::max<int64_t>(y_keys, 1), s);
-    semijoin_direct(ry, NR, d_rbase, n, syk, NS, sptr, d_counts + 1, dky, y_keys, ymin, table, flags, yid, s);
-  } else {
-    semijoin(ry, NR, d_rbase, n, vals_y, y_base, flags, yid, s);
-  }
+  const bool y_table = y_keys <= 2 * NS + 65536;  // dense key domain: a table lookup instead of a binary search
+  int32_t* table = y_table ? T.alloc<int32_t>(std::max<int64_t>(y_keys, 1), s) : nullptr;
   d_rpbase = A.alloc<int32_t>(n + 1, s);
   h_rpbase.resize(n + 1);
   int32_t counts[4];
   x_base = A.alloc<int32_t>(n + 1, s);
   if (direct_x) {
+    int32_t* yid = T.alloc<int32_t>(NRa, s);
+    int32_t* flags = T.alloc<int32_t>(NRa, s);
+    if (y_table)
+      semijoin_direct(ry, NR, d_rbase, n, syk, NS, sptr, d_counts + 1, dky, y_keys, ymin, table, flags, yid, s);
+    else
+      semijoin(ry, NR, d_rbase, n, vals_y, y_base, flags, yid, s);
     // x ids over the kept tuples' keys; R' rows by a scatter with per-key cursors
     const int64_t K = koff_x[n];
     int32_t* cnt = T.alloc<int32_t>(K + 1, s);
@@ -388,13 +451,12 @@ void Plan::map(hipStream_t s) {
     rcol = A.alloc<int32_t>(NRpa, s);
     scatter_x(rx, yid, NR, d_rbase, n, dkx, xmin, Cxk, rcol, s);
   } else {
-    int32_t* Ek = T.alloc<int32_t>(NR + 1, s);
-    scan_excl_i32(flags, Ek, NR, s, T);
-    int32_t* rpx = T.alloc<int32_t>(NRa, s);
+    // kept tuples in order with their x keys and y ids, in one pass
+    if (y_table) fill_direct_table(syk, NS, sptr, d_counts + 1, y_keys, table, s);
+    uint32_t* xk = T.alloc<uint32_t>(NRa, s);
     uint32_t* rpy = T.alloc<uint32_t>(NRa, s);
-    compact_r(rx, yid, flags, Ek, NR, rpx, reinterpret_cast<int32_t*>(rpy), s);
-    gather_bases(Ek, d_rbase, n, d_rpbase, s);
-    JP_HIP(hipMemcpyAsync(d_counts + 2, Ek + NR, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    const SemiJoinIn sj{rx, ry, NR, d_rbase, n, dky, ymin, table, vals_y, y_base, dkx, xmin};
+    semijoin_compact(sj, xk, rpy, d_rpbase, d_counts + 2, s, T);
     d2h(counts, d_counts, 3, s);
     d2h(h_rpbase.data(), d_rpbase, n + 1, s);
     sync(s);
@@ -402,23 +464,13 @@ void Plan::map(hipStream_t s) {
     NY = counts[1];
     NRp = counts[2];
 
-    seg_minmax(rpx, NRp, d_rpbase, n, xmin, xmax, s);
-    std::vector<int32_t> hx(2 * size_t(n));
-    d2h(hx.data(), xmin, 2 * size_t(n), s);
-    sync(s);
-    std::vector<int32_t> hxmin(hx.begin(), hx.begin() + n), hxmax(hx.begin() + n, hx.end());
-    int xbits = key_layout(hxmin, hxmax, koff_x);
-    h2d(dkx, koff_x.data(), n + 1, s);
-
     const int64_t NRpa = std::max<int64_t>(NRp, 1);
-    uint32_t* xk = T.alloc<uint32_t>(NRpa, s);
     uint32_t* xk2 = T.alloc<uint32_t>(NRpa, s);
     // with an odd pass count the sorted y ids end in the alternate buffer: rcol itself
     const int xbits_sort = n > 1 ? local_bits(koff_x) : xbits;
     const bool x_odd = radix_passes(NRp, xbits_sort) & 1;
     rcol = A.alloc<int32_t>(NRpa, s);
     uint32_t* xp2 = x_odd ? reinterpret_cast<uint32_t*>(rcol) : T.alloc<uint32_t>(NRpa, s);
-    make_keys(rpx, NRp, d_rpbase, n, dkx, xmin, xk, nullptr, nullptr, s);
     const SortSegments sseg_x{n, d_rpbase, dkx, h_rpbase};
     bool alt3 = radix_sort_pairs(xk, rpy, xk2, xp2, NRp, xbits_sort, s, T, &sseg_x);
     uint32_t *sxk = alt3 ? xk2 : xk, *sxp = alt3 ? xp2 : rpy;
@@ -498,14 +550,12 @@ void Plan::partition(hipStream_t s) {
   gather_bases(Edz, z_base, n, zd_base, s);
 
   // S_sparse: CSR by y of the entries whose z is sparse
-  int32_t* fl = T.alloc<int32_t>(NSa, s);
-  entry_flags(Ey, scol, NS, zflag, nullptr, fl, nullptr, s);
-  int32_t* Esp = T.alloc<int32_t>(NS + 1, s);
-  scan_excl_i32(fl, Esp, NS, s, T);
+  spcol = A.alloc<int32_t>(NSa, s);  // sized before the count is known: one pass fills it
   spptr = A.alloc<int32_t>(NY + 1, s);
-  remap_rowptr(sptr, Esp, NY, spptr, s);
+  int32_t* d_nsp = T.alloc<int32_t>(1, s);
+  filter_rows(false, Ey, scol, NS, zflag, nullptr, spcol, spptr, NY, d_nsp, s, T);
   int32_t nsp = 0;
-  d2h(&nsp, Esp + NS, 1, s);
+  d2h(&nsp, d_nsp, 1, s);
   int32_t* hist = T.alloc<int32_t>(int64_t(n) * 32, s);
   hot_histogram(sptr, spptr, dR, NY, y_base, n, hist, s);
   std::vector<int32_t> h_hist(size_t(n) * 32);
@@ -515,8 +565,6 @@ void Plan::partition(hipStream_t s) {
   sync(s);
   NSp = nsp;
   NZd = h_zdbase[n];
-  spcol = A.alloc<int32_t>(std::max<int64_t>(NSp, 1), s);
-  compact_entries(scol, fl, Esp, NS, Edz, z_base, zd_base, n, false, spcol, s);
 
   DenseSpace& d0 = ds[0];
   d0.h_base = h_zdbase;
@@ -703,18 +751,14 @@ void Plan::build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a,
   build_hot_bits(Ey, scol, NS, hot, d.hotrow, y_base, zmap, d.d_hboff, d.d_roww, n, d.hb, s);
 
   // cold entries: CSR by y over the space's local index (ascending in each row)
-  int32_t* fl = T.alloc<int32_t>(NSa, s);
-  cold_flags(Ey, scol, NS, zmap, hot, fl, s);
-  int32_t* Ec = T.alloc<int32_t>(NS + 1, s);
-  scan_excl_i32(fl, Ec, NS, s, T);
+  int32_t* ccol_y = T.alloc<int32_t>(NSa, s);
   d.cptr = A.alloc<int32_t>(NY + 1, s);
-  remap_rowptr(sptr, Ec, NY, d.cptr, s);
+  int32_t* d_ncold = T.alloc<int32_t>(1, s);
+  filter_rows(true, Ey, scol, NS, zmap, hot, ccol_y, d.cptr, NY, d_ncold, s, T);
   int32_t ncold = 0;
-  d2h(&ncold, Ec + NS, 1, s);
+  d2h(&ncold, d_ncold, 1, s);
   sync(s);
   d.NCold = ncold;
-  int32_t* ccol_y = T.alloc<int32_t>(std::max<int64_t>(d.NCold, 1), s);
-  compact_mapped(scol, fl, Ec, NS, zmap, ccol_y, s);
 
   // cold entries in window-major order with per-(window, key) segment bounds
   std::vector<int64_t> h_cwoff(n, 0), h_cwmoff(n, 0);

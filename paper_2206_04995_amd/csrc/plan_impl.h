@@ -66,6 +66,7 @@ struct Plan {
   // inputs (concatenated over instances)
   const int32_t *rx = nullptr, *ry = nullptr, *sz = nullptr, *sy = nullptr;
   int32_t *d_rbase = nullptr, *d_sbase = nullptr, *d_rpbase = nullptr;
+  int32_t* d_minmax = nullptr;  // a batch: per-instance min and max of z, y, x (6 rows of n), from the gather
   // mapping
   int32_t *vals_x = nullptr, *vals_y = nullptr, *vals_z = nullptr;
   int32_t *x_base = nullptr, *y_base = nullptr, *z_base = nullptr;

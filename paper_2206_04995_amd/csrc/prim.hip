@@ -58,25 +58,12 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const Ti* __restrict__ i
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = off + tot;
 }
 
-// Single-pass exclusive scan with decoupled look-back (Merrill and Garland,
-// "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016): a tile
-// takes its index from a counter in the order tiles start, publishes its sum,
-// finds the sum of everything before it from its predecessors' published
-// words, and publishes its inclusive prefix.  The input is read once.  A
-// status word holds a flag in its top two bits (1: tile sum, 2: inclusive
-// prefix, 0: not yet published) and the value as a 62-bit two's complement
-// integer, so one 64-bit store publishes both.  The statuses and the counter
-// start at zero.  A tile only waits on tiles that took their index before it,
-// which are running or done, so every wait ends.
+// Single-pass exclusive scan with decoupled look-back (lookback_exclusive in
+// common.h): the input is read once.
 constexpr int LB_NT = 256;
 constexpr int LB_IT = 16;
 constexpr int LB_WTILE = 64 * LB_IT;    // consecutive elements per wave
 constexpr int LB_TILE = LB_NT * LB_IT;  // 4096 elements per tile
-constexpr uint64_t LB_VAL = (uint64_t(1) << 62) - 1;
-constexpr int LB_SPIN_MAX = 1 << 16;  // polls of one window before the wait gives up and flags status[ntiles + 1]
-
-__device__ __forceinline__ uint64_t lb_pack(uint64_t flag, int64_t v) { return (flag << 62) | (uint64_t(v) & LB_VAL); }
-__device__ __forceinline__ int64_t lb_value(uint64_t w) { return int64_t(w << 2) >> 2; }
 
 template <class T>
 __device__ __forceinline__ T lb_wave_incl(T v) {
@@ -91,7 +78,7 @@ __global__ void __launch_bounds__(LB_NT) k_scan_lookback(const Ti* __restrict__ 
   __shared__ To s_wsum[LB_NT / 64];
   __shared__ To s_excl;
   const int lane = lane_id(), wid = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_tile = int64_t(atomicAdd(reinterpret_cast<unsigned long long*>(status + ntiles), 1ull));
+  if (threadIdx.x == 0) s_tile = lookback_ticket(status, ntiles);
   __syncthreads();
   const int64_t tile = s_tile;
   const int64_t w0 = tile * LB_TILE + int64_t(wid) * LB_WTILE;
@@ -118,36 +105,7 @@ __global__ void __launch_bounds__(LB_NT) k_scan_lookback(const Ti* __restrict__ 
     btot += s_wsum[w];
   }
   if (wid == 0) {
-    To excl = 0;
-    if (tile == 0) {
-      if (lane == 0) __hip_atomic_store(status, lb_pack(2, int64_t(btot)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      if (lane == 0)
-        __hip_atomic_store(status + tile, lb_pack(1, int64_t(btot)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      // lane l reads tile t - l; the window moves back 64 tiles until it holds an inclusive prefix
-      for (int64_t t = tile - 1;; t -= 64) {
-        const int64_t idx = t - lane;
-        uint64_t w;
-        for (int spin = 0;; ++spin) {
-          w = idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                       : lb_pack(2, 0);
-          if (ballot((w >> 62) == 0) == 0) break;
-          if (spin == LB_SPIN_MAX) {  // not reached when every tile runs (see above); a bound all the same
-            if (lane == 0) atomicOr(reinterpret_cast<unsigned long long*>(status + ntiles + 1), 1ull);
-            w = lb_pack(2, 0);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-        const uint64_t incm = ballot((w >> 62) == 2);
-        const int stop = incm ? __ffsll((unsigned long long)incm) - 1 : 63;
-        excl += wave_sum(lane <= stop ? To(lb_value(w)) : To(0));
-        if (incm) break;
-      }
-      if (lane == 0)
-        __hip_atomic_store(status + tile, lb_pack(2, int64_t(excl + btot)), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
+    const To excl = To(lookback_exclusive(status, tile, ntiles, int64_t(btot)));
     if (lane == 0) s_excl = excl;
   }
   __syncthreads();
@@ -158,11 +116,6 @@ __global__ void __launch_bounds__(LB_NT) k_scan_lookback(const Ti* __restrict__ 
     if (i < n) out[i] = base + v[j];
   }
   if (tile == ntiles - 1 && threadIdx.x == 0) out[n] = s_excl + btot;
-}
-
-__global__ void k_zero_u64(uint64_t* p, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    p[i] = 0;
 }
 
 template <class Ti, class To>
@@ -181,8 +134,7 @@ void scan_impl(const Ti* in, To* out, int64_t n, hipStream_t s, Arena& a) {
   }
   const int64_t nt = (n + LB_TILE - 1) / LB_TILE;
   uint64_t* status = a.alloc<uint64_t>(nt + 2, s);  // tile words, the tile counter, a give-up flag
-  hipLaunchKernelGGL(k_zero_u64, dim3(int(std::min<int64_t>((nt + 257) / 256, 1024))), dim3(256), 0, s, status,
-                     nt + 2);
+  fill_i64(reinterpret_cast<int64_t*>(status), nt + 2, 0, s);
   hipLaunchKernelGGL((k_scan_lookback<Ti, To>), dim3(int(nt)), dim3(LB_NT), 0, s, in, out, n, status, nt);
   JP_LAUNCH_CHECK();
   a.give_back(status, s);
@@ -243,6 +195,18 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t k, const Tile& t, int shif
   return (uint32_t(int64_t(k) - t.koff) >> shift) & mask;
 }
 
+// Lanes of one wave row whose keys share digit d: the ballots of d's bits
+// (a lane's own mask, lowest lane = the group's leader).
+__device__ __forceinline__ uint64_t digit_match(uint32_t d, bool valid, int nbits) {
+  uint64_t m = ballot(valid);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
 __global__ void __launch_bounds__(RS_NT) k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
                                                        int shift, int nbits, int* __restrict__ hist,
                                                        TileMap m) {
@@ -297,32 +261,32 @@ __global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restr
 
   const int64_t wbase = tl.lo + int64_t(wid) * RS_WTILE;
   uint32_t key[RS_IT], val[RS_IT];
-  int lrank[RS_IT];
 #pragma unroll
   for (int j = 0; j < RS_IT; ++j) {
-    int64_t i = wbase + j * 64 + lane;
-    bool valid = i < tl.hi;
-    uint32_t k = valid ? kin[i] : 0u;
-    uint32_t d = digit_of(k, tl, shift, mask);
-    key[j] = k;
+    const int64_t i = wbase + j * 64 + lane;
+    const bool valid = i < tl.hi;
+    key[j] = valid ? kin[i] : 0u;
     if (HAS_V) val[j] = valid ? vin[i] : 0u;
-    uint64_t m = ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
-      bool bit = (d >> b) & 1u;
-      uint64_t bb = ballot(bit);
-      m &= bit ? bb : ~bb;
-    }
-    int r = -1;
-    if (valid) {
-      int rank = __popcll(m & ltm);
-      int leader = __ffsll((unsigned long long)m) - 1;
-      int c = __popcll(m);
-      int before = wcnt[wid][d];
-      if (lane == leader) wcnt[wid][d] = before + c;
-      r = before + rank;
-    }
-    lrank[j] = r;
-    __builtin_amdgcn_wave_barrier();
+  }
+  // Stable ranks inside the wave: per row, the group leader of each digit adds
+  // the group's size to the wave's counter and gets the count before it.  The
+  // adds of all rows are issued back to back; LDS executes one wave's
+  // operations in order, so row j sees the counts of rows before it.
+  int before[RS_IT], lead[RS_IT], lrank[RS_IT];
+#pragma unroll
+  for (int j = 0; j < RS_IT; ++j) {
+    const bool valid = wbase + j * 64 + lane < tl.hi;
+    const uint32_t d = digit_of(key[j], tl, shift, mask);
+    const uint64_t mm = digit_match(d, valid, nbits);
+    lead[j] = valid ? __ffsll((unsigned long long)mm) - 1 : lane;
+    lrank[j] = valid ? __popcll(mm & ltm) : -1;
+    before[j] = 0;
+    if (valid && lane == lead[j]) before[j] = atomicAdd(&wcnt[wid][d], __popcll(mm));
+  }
+#pragma unroll
+  for (int j = 0; j < RS_IT; ++j) {
+    const int b = __shfl(before[j], lead[j], 64);  // every lane takes part
+    if (lrank[j] >= 0) lrank[j] += b;
   }
   __syncthreads();
   // per digit: prefix across waves, block total, block-local start

@@ -57,9 +57,32 @@ void semijoin(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, co
 void semijoin_direct(const int32_t* ry, int64_t n, const int32_t* ebase, int n_inst, const uint32_t* ykeys, int64_t ns,
                      const int32_t* first, const int32_t* total, const int64_t* koff, int64_t key_space,
                      const int32_t* mn, int32_t* table, int32_t* keep, int32_t* yid, hipStream_t s);
-// stable compaction of R to the kept tuples
-void compact_r(const int32_t* rx, const int32_t* yid, const int32_t* keep, const int32_t* E, int64_t n,
-               int32_t* out_x, int32_t* out_y, hipStream_t s);
+// Inputs of the fused semi-join of R: R's columns and instance bases, the y
+// lookup (table over the S.y key space when table is non-null, else binary
+// search in vals_y within y_base), and the layout of the x keys.
+struct SemiJoinIn {
+  const int32_t* rx;
+  const int32_t* ry;
+  int64_t n;
+  const int32_t* ebase;
+  int n_inst;
+  const int64_t* koff_y;
+  const int32_t* ymin;
+  const int32_t* table;
+  const int32_t* vals_y;
+  const int32_t* y_base;
+  const int64_t* koff_x;
+  const int32_t* xmin;
+};
+// table[key] = y id for every key of S.y, -1 elsewhere (key_space entries;
+// ykeys are the y-sorted S keys, first[] their run starts, *total the run count)
+void fill_direct_table(const uint32_t* ykeys, int64_t ns, const int32_t* first, const int32_t* total,
+                       int64_t key_space, int32_t* table, hipStream_t s);
+// semi-join of R on S.y with the kept tuples compacted in order: xk = their x
+// keys, oy = their y ids, rpbase[i] = kept tuples before instance i (i in
+// [0, n_inst]), *total = kept tuples
+void semijoin_compact(const SemiJoinIn& in, uint32_t* xk, uint32_t* oy, int32_t* rpbase, int32_t* total,
+                      hipStream_t s, Arena& a);
 // Direct-range mapping (key space = the instances' stacked value ranges):
 // h[key(v[i])] += 1 for every i with filter[i] >= 0 (filter may be null)
 void key_hist(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff, const int32_t* mn,
@@ -93,15 +116,15 @@ void dense_flags(const int32_t* m_z, int64_t n_z, const int32_t* z_base, int n_i
                  int32_t* flag, hipStream_t s);
 // dz2z[Edz[z]] = z for dense z
 void dense_index(const int32_t* flag, const int32_t* Edz, int64_t n_z, int32_t* dz2z, hipStream_t s);
-// per S entry p (row Ey[p+1]-1): sparse flag (z not dense) and cold flag (z dense, y not hot)
-void entry_flags(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zflag,
-                 const int32_t* hot, int32_t* sp_flag, int32_t* cold_flag, hipStream_t s);
+// S entries filtered into a CSR over the rows of S in one pass: the entries
+// whose z is sparse (cold = false: zsel = zflag, out = z), or the cold
+// entries of a space (cold = true: zsel = zmap, hot = hot rows, out = local
+// index); rowptr gets n_rows + 1 entries, *total the kept count
+void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zsel,
+                 const int32_t* hot, int32_t* out, int32_t* rowptr, int64_t n_rows, int32_t* total, hipStream_t s,
+                 Arena& a);
 // rowptr_out[y] = E[rowptr[y]] for y in [0, n_y]
 void remap_rowptr(const int32_t* rowptr, const int32_t* E, int64_t n_y, int32_t* out, hipStream_t s);
-// compaction of S entries with flag set; values z (sparse) or local dense index (cold)
-void compact_entries(const int32_t* scol, const int32_t* flag, const int32_t* E, int64_t n, const int32_t* Edz,
-                     const int32_t* z_base, const int32_t* zd_base, int n_inst, bool to_local_dense,
-                     int32_t* out, hipStream_t s);
 // The tables of DenseEC are built over a "space" of z: a map zmap[z] = local
 // index of z in its instance's part of the space, or -1 if z is not in it.
 // The count of key y in the space is cnt_a[y+1] - cnt_a[y] - (cnt_b ? cnt_b[y+1] - cnt_b[y] : 0).
@@ -116,14 +139,8 @@ void hot_flags(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR, in
 void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* hotrow,
                     const int32_t* y_base, const int32_t* zmap, const int64_t* hb_off, const int32_t* row_words,
                     int n_inst, uint32_t* hb, hipStream_t s);
-// per S entry: in the space and not of a hot key
-void cold_flags(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zmap, const int32_t* hot,
-                int32_t* flag, hipStream_t s);
 // per S entry: in the space
 void space_flags(const int32_t* scol, int64_t n, const int32_t* zmap, int32_t* flag, hipStream_t s);
-// out[E[p]] = zmap[scol[p]] for flagged entries
-void compact_mapped(const int32_t* scol, const int32_t* flag, const int32_t* E, int64_t n, const int32_t* zmap,
-                    int32_t* out, hipStream_t s);
 // space 0: all dense z
 void zmap_dense(const int32_t* zflag, const int32_t* Edz, int64_t n_z, const int32_t* z_base, const int32_t* zd_base,
                 int n_inst, int32_t* zmap, hipStream_t s);
