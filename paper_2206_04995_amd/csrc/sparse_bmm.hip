@@ -35,88 +35,24 @@ __device__ __forceinline__ void lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Per R CSR entry j in [j_lo, j_hi) (the entries of rows [x_lo, x_hi)): the
-// sparse S row of its join key as (seg0, len), and in the same pass the row
-// work w[x] = the sum of its entries' lengths.  The lengths' prefix over the
-// entries comes from a look-back over tiles (lookback_exclusive); only its
-// value at each row's first entry is kept (Erow[x - x_lo]; Erow[rows] = the
-// total), and w is the difference of consecutive ones.  Every row has an entry.
-constexpr int ES_NT = 256;
-constexpr int ES_IT = 16;
-constexpr int ES_WTILE = 64 * ES_IT;
-constexpr int ES_TILE = ES_NT * ES_IT;
-
-__global__ void __launch_bounds__(ES_NT) k_entry_seg(const int32_t* __restrict__ rcol, const int32_t* __restrict__ spptr,
-                                                     const int32_t* __restrict__ rptr, int64_t j_lo, int64_t j_hi,
-                                                     int64_t x_lo, int64_t n_rows, int32_t* __restrict__ seg0,
-                                                     int32_t* __restrict__ len, int64_t* __restrict__ Erow,
-                                                     uint64_t* __restrict__ status, int64_t ntiles) {
-  __shared__ int64_t s_tile;
-  __shared__ int64_t s_wsum[ES_NT / 64];
-  __shared__ int64_t s_excl;
-  const int lane = lane_id(), wid = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_tile = lookback_ticket(status, ntiles);
-  __syncthreads();
-  const int64_t tile = s_tile;
-  const int64_t w0 = j_lo + tile * ES_TILE + int64_t(wid) * ES_WTILE;
-  // every load first, at clamped (valid) indices, so the gathers of all rows are in flight together
-  int32_t y[ES_IT], l[ES_IT];
-#pragma unroll
-  for (int j = 0; j < ES_IT; ++j) {
-    const int64_t i = w0 + j * 64 + lane;
-    y[j] = rcol[i < j_hi ? i : j_hi - 1];
+// per R CSR entry j: the sparse S row of its join key, as (start, length)
+__global__ void k_entry_seg(const int32_t* __restrict__ rcol, const int32_t* __restrict__ spptr, int64_t j_lo,
+                            int64_t j_hi, int32_t* __restrict__ seg0, int32_t* __restrict__ len) {
+  for (int64_t j = j_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < j_hi;
+       j += int64_t(gridDim.x) * blockDim.x) {
+    const int y = rcol[j];
+    const int a = spptr[y];
+    seg0[j] = a;
+    len[j] = spptr[y + 1] - a;
   }
-  int32_t a[ES_IT];
-#pragma unroll
-  for (int j = 0; j < ES_IT; ++j) {
-    a[j] = spptr[y[j]];
-    l[j] = spptr[y[j] + 1];
-  }
-  int64_t mine = 0;  // this lane's lengths
-#pragma unroll
-  for (int j = 0; j < ES_IT; ++j) {
-    const int64_t i = w0 + j * 64 + lane;
-    l[j] = i < j_hi ? l[j] - a[j] : 0;
-    if (i < j_hi) {
-      seg0[i] = a[j];
-      len[i] = l[j];
-    }
-    mine += l[j];
-  }
-  const int64_t wtot = wave_sum(mine);
-  if (lane == 0) s_wsum[wid] = wtot;
-  __syncthreads();
-  int64_t woff = 0, btot = 0;
-#pragma unroll
-  for (int w = 0; w < ES_NT / 64; ++w) {
-    if (w < wid) woff += s_wsum[w];
-    btot += s_wsum[w];
-  }
-  if (wid == 0) {
-    const int64_t e = lookback_exclusive(status, tile, ntiles, btot);
-    if (lane == 0) s_excl = e;
-  }
-  __syncthreads();
-  int64_t run = s_excl + woff;  // wave-uniform: prefix before the wave's row j
-  SegCursor<int32_t> cur(rptr + x_lo, int(n_rows));
-  if (w0 < j_hi) cur.seed(int32_t(w0));
-#pragma unroll
-  for (int j = 0; j < ES_IT; ++j) {
-    const int64_t i = w0 + j * 64 + lane;
-    const int64_t inc = wave_incl_scan<int64_t>(int64_t(l[j]));
-    if (i < j_hi) {
-      const int r = cur(int32_t(i));
-      if (i == cur.lo) Erow[r] = run + inc - l[j];
-    }
-    run += __shfl(inc, 63, 64);
-  }
-  if (tile == ntiles - 1 && threadIdx.x == 0) Erow[n_rows] = s_excl + btot;
 }
 
-// w[r] = Erow[r + 1] - Erow[r]
-__global__ void k_row_diff(const int64_t* __restrict__ Erow, int64_t n_rows, int64_t* __restrict__ w) {
-  for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n_rows; r += int64_t(gridDim.x) * blockDim.x)
-    w[r] = Erow[r + 1] - Erow[r];
+// w[x] = sum of the entry lengths of row x (difference of the entries' prefix sums)
+__global__ void k_row_diff(const int32_t* __restrict__ rptr, const int64_t* __restrict__ E, int64_t j_lo, int64_t x_lo,
+                           int64_t x_hi, int64_t* __restrict__ w) {
+  for (int64_t x = x_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < x_hi;
+       x += int64_t(gridDim.x) * blockDim.x)
+    w[x - x_lo] = E[rptr[x + 1] - j_lo] - E[rptr[x] - j_lo];
 }
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t z, int log2t) {
@@ -577,25 +513,20 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_write(const int32_t* __rest
 
 void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, int64_t j_hi, int64_t* w,
                      int32_t* seg0, int32_t* seglen, hipStream_t s, Arena& a) {
-  const int64_t n = x_hi - x_lo;
+  int64_t n = x_hi - x_lo;
   if (n <= 0) return;
   const int64_t ne = j_hi - j_lo;
-  if (ne <= 0) {
-    fill_i64(w, n, 0, s);
-    return;
+  int64_t* E = a.alloc<int64_t>(ne + 1, s);
+  if (ne > 0) {
+    int g = int(std::min<int64_t>((ne + NT - 1) / NT, 1 << 16));
+    hipLaunchKernelGGL(k_entry_seg, dim3(g), dim3(NT), 0, s, c.rcol, c.spptr, j_lo, j_hi, seg0, seglen);
+    JP_LAUNCH_CHECK();
   }
-  int64_t* Erow = a.alloc<int64_t>(n + 1, s);
-  const int64_t nt = (ne + ES_TILE - 1) / ES_TILE;
-  uint64_t* status = a.alloc<uint64_t>(nt + 2, s);
-  fill_i64(reinterpret_cast<int64_t*>(status), nt + 2, 0, s);
-  hipLaunchKernelGGL(k_entry_seg, dim3(int(nt)), dim3(ES_NT), 0, s, c.rcol, c.spptr, c.rptr, j_lo, j_hi, x_lo, n, seg0,
-                     seglen, Erow, status, nt);
+  scan_excl_i32_to_i64(seglen + j_lo, E, ne, s, a);
+  int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
+  hipLaunchKernelGGL(k_row_diff, dim3(g), dim3(NT), 0, s, c.rptr, E, j_lo, x_lo, x_hi, w);
   JP_LAUNCH_CHECK();
-  const int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
-  hipLaunchKernelGGL(k_row_diff, dim3(g), dim3(NT), 0, s, (const int64_t*)Erow, n, w);
-  JP_LAUNCH_CHECK();
-  a.give_back(status, s);
-  a.give_back(Erow, s);
+  a.give_back(E, s);
 }
 
 int64_t sparse_list_ints(int64_t n_rows) { return 2 * n_rows + 4; }
