@@ -109,10 +109,36 @@ __device__ __forceinline__ void flush_minmax(int inst, int32_t lo, int32_t hi, i
 __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int32_t* __restrict__ base, int n_inst,
                               int64_t n, int32_t* __restrict__ dst, int32_t* __restrict__ mn,
                               int32_t* __restrict__ mx) {
-  SegCursor<int32_t> cur(base, n_inst);
-  cur.seed(int32_t(chunk_first()));
-  const int64_t c1 = chunk_first() + JP_CHUNK < n ? chunk_first() + JP_CHUNK : n;
+  const int64_t c0 = chunk_first();
+  const int64_t c1 = c0 + JP_CHUNK < n ? c0 + JP_CHUNK : n;
   const int64_t step = blockDim.x;
+  const int i0 = wave_find_inst<int32_t>(base, n_inst, int32_t(c0));
+  if (int64_t(base[i0 + 1]) >= c1) {
+    // the chunk lies in one instance (all but the chunks at instance bounds): no per-element lookups
+    const int32_t* col = src[i0] + (c0 - base[i0]);
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
+    for (int64_t g0 = c0 + threadIdx.x; g0 < c1; g0 += 4 * step) {
+      int32_t vv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t g = g0 + u * step;
+        vv[u] = g < c1 ? col[g - c0] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t g = g0 + u * step;
+        if (g < c1) {
+          dst[g] = vv[u];
+          lo = vv[u] < lo ? vv[u] : lo;
+          hi = vv[u] > hi ? vv[u] : hi;
+        }
+      }
+    }
+    if (mn) flush_minmax(i0, lo, hi, mn, mx);
+    return;
+  }
+  SegCursor<int32_t> cur(base, n_inst);
+  cur.seed(int32_t(c0));
   const int32_t* col = nullptr;
   int last = -1;                           // instance of `col`
   int acc = -1;                            // instance whose values lo and hi hold
