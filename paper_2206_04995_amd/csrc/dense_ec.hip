@@ -296,9 +296,11 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
   }
 }
 
-// Count mode for rows of instances with few dense z (0 < Z_d <= 32 * LANES):
+// Count mode for rows of instances with few dense z (0 < Z_d <= 32 * LANES * WPL):
 // the whole dense range is one short bit row, so a group of LANES lanes owns
 // a row, WPL 32-z words per lane, and a wave counts 64 / LANES rows at once
+// (each row is a chain of dependent loads, so more rows per wave keep more
+// loads in flight)
 // (the window kernel would spend a 32768-z window, 1024 words, on each).  The
 // groups walk their rows' join keys LANES at a time: hot keys are ORed one
 // per group per step (each group loads its own key's words), cold keys are
@@ -308,10 +310,10 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
 template <int LANES, int WPL>
 __global__ void __launch_bounds__(256) k_dense_narrow(RowCtx c, int64_t n_slots, const int32_t* __restrict__ rows,
                                                    int accumulate, int32_t* __restrict__ cnt) {
-  static_assert(WPL == 1 || WPL == 4, "one word or one uint4 per lane");
-  constexpr int CLS = LANES == 16 ? 0 : WPL == 1 ? 1 : 2;
+  static_assert(WPL == 1 || WPL == 2 || WPL == 4 || WPL == 8, "a word, a uint2, a uint4 or two uint4 per lane");
   constexpr int GROUPS = 64 / LANES;
   constexpr int ZMAX = 32 * LANES * WPL;
+  constexpr int CLS = ZMAX == NARROW_SMALL ? 0 : ZMAX == NARROW_MID ? 1 : 2;
   constexpr int ZMIN = CLS == 0 ? 1 : CLS == 1 ? NARROW_SMALL + 1 : NARROW_MID + 1;
   static_assert(ZMAX == (CLS == 0 ? NARROW_SMALL : CLS == 1 ? NARROW_MID : NARROW_MAX), "class bounds");
   __shared__ uint32_t buf_all[4][64 * WPL];
@@ -380,12 +382,20 @@ __global__ void __launch_bounds__(256) k_dense_narrow(RowCtx c, int64_t n_slots,
         for (int e = 0; e < WPL; ++e) v[u][e] = 0u;
         if (has && mine) {
           const uint32_t* src = hrow + int64_t(k) * rw + gl * WPL;  // rows are whole windows: WPL words in bounds
-          if (WPL == 4) {
+          if constexpr (WPL == 8) {
+            const uint4 q0 = reinterpret_cast<const uint4*>(src)[0], q1 = reinterpret_cast<const uint4*>(src)[1];
+            const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+            for (int e = 0; e < WPL; ++e) v[u][e] = w[e % 8];
+          } else if constexpr (WPL == 4) {
             const uint4 q = *reinterpret_cast<const uint4*>(src);
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int e = 0; e < WPL; ++e) v[u][e] = w[e % 4];
+          } else if constexpr (WPL == 2) {
+            const uint2 q = *reinterpret_cast<const uint2*>(src);
             v[u][0] = q.x;
-            v[u][WPL > 1 ? 1 : 0] = q.y;
-            v[u][WPL > 2 ? 2 : 0] = q.z;
-            v[u][WPL > 3 ? 3 : 0] = q.w;
+            v[u][WPL - 1] = q.y;
           } else {
             v[u][0] = src[0];
           }
@@ -552,18 +562,18 @@ static void dense_narrow(const RowCtx& c, int64_t n_rows, const int32_t* rows, i
                          hipStream_t s) {
   if (c.narrow & 1) {
     const int64_t n = rows ? n_rows : c.nar_rows[0];
-    hipLaunchKernelGGL((k_dense_narrow<16, 1>), dim3(int((n + 15) / 16)), dim3(256), 0, s, c, n, rows, accumulate,
-                       cnt);
+    hipLaunchKernelGGL((k_dense_narrow<8, 2>), dim3(int((n + 31) / 32)), dim3(256), 0, s, c, n, rows, accumulate, cnt);
     JP_LAUNCH_CHECK();
   }
   if (c.narrow & 2) {
     const int64_t n = rows ? n_rows : c.nar_rows[1];
-    hipLaunchKernelGGL((k_dense_narrow<64, 1>), dim3(int((n + 3) / 4)), dim3(256), 0, s, c, n, rows, accumulate, cnt);
+    hipLaunchKernelGGL((k_dense_narrow<16, 4>), dim3(int((n + 15) / 16)), dim3(256), 0, s, c, n, rows, accumulate,
+                       cnt);
     JP_LAUNCH_CHECK();
   }
   if (c.narrow & 4) {
     const int64_t n = rows ? n_rows : c.nar_rows[2];
-    hipLaunchKernelGGL((k_dense_narrow<64, 4>), dim3(int((n + 3) / 4)), dim3(256), 0, s, c, n, rows, accumulate, cnt);
+    hipLaunchKernelGGL((k_dense_narrow<32, 8>), dim3(int((n + 7) / 8)), dim3(256), 0, s, c, n, rows, accumulate, cnt);
     JP_LAUNCH_CHECK();
   }
 }

@@ -119,6 +119,7 @@ __global__ void k_build_hot_bits(const int32_t* __restrict__ Ey, const int32_t* 
         }
       }
     }
+    if (ballot(addr != NONE) == 0) continue;  // no hot entry among these 64 (wave-uniform)
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const uint64_t a2 = __shfl_down(addr, o, 64);
@@ -169,13 +170,19 @@ __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict
   // every load first, at clamped (valid) indices, so the gathers of all rows are in flight together
   int32_t val[FR_IT], row1[FR_IT];  // row1: row + 1 of a row's first entry, else 0
   int32_t z[FR_IT], e1[FR_IT], e0[FR_IT];
+  const int32_t ew = Ey[w0 < n ? w0 : n - 1];  // the row count before the wave's first entry
 #pragma unroll
   for (int j = 0; j < FR_IT; ++j) {
     int64_t i = w0 + j * 64 + lane;
     i = i < n ? i : n - 1;
     e1[j] = Ey[i + 1];
-    e0[j] = Ey[i];
     z[j] = scol[i];
+  }
+  // Ey[i] of each entry is Ey[i + 1] of the one before it (a lane shift)
+#pragma unroll
+  for (int j = 0; j < FR_IT; ++j) {
+    const int32_t up = __shfl_up(e1[j], 1, 64);
+    e0[j] = lane > 0 ? up : (j > 0 ? __builtin_amdgcn_readlane(e1[j > 0 ? j - 1 : 0], 63) : ew);
   }
   int32_t sel[FR_IT], h[FR_IT];
 #pragma unroll
