@@ -52,25 +52,29 @@ __device__ __forceinline__ int space_count(const int32_t* __restrict__ a, const 
   return (a[y + 1] - a[y]) - (b ? b[y + 1] - b[y] : 0);
 }
 
+// Per-instance histogram of floor(log2(count in the space)) over y with dR > 0.
+// A block takes a chunk of y ids (CHUNK_LOOP); counts of the chunk's first
+// instance gather in LDS (one atomic per bucket and block at the end), the
+// rare ids of later instances in the chunk go straight to global memory.
 __global__ void k_hot_histogram(const int32_t* __restrict__ cnt_a, const int32_t* __restrict__ cnt_b,
                                 const int32_t* __restrict__ dR, int64_t n_y, const int32_t* __restrict__ y_base,
                                 int n_inst, int32_t* __restrict__ hist) {
-  __shared__ int32_t loc[32];  // one instance: block-local buckets
+  __shared__ int32_t loc[32];
   if (threadIdx.x < 32) loc[threadIdx.x] = 0;
+  SegCursor<int32_t> ycur(y_base, n_inst);
+  ycur.seed(int32_t(chunk_first() < n_y ? chunk_first() : 0));
+  const int i0 = ycur.cur;
   __syncthreads();
-  GRID_STRIDE(y, n_y) {
+  CHUNK_LOOP(y, n_y, JP_CHUNK) {
     const int dd = space_count(cnt_a, cnt_b, y);
     if (dd > 0 && dR[y] > 0) {
-      if (n_inst == 1) {
-        atomicAdd(&loc[ilog2(dd)], 1);
-      } else {
-        int inst = find_inst<int32_t>(y_base, n_inst, int32_t(y));
-        atomicAdd(&hist[inst * 32 + ilog2(dd)], 1);
-      }
+      const int inst = ycur(int32_t(y));
+      if (inst == i0) atomicAdd(&loc[ilog2(dd)], 1);
+      else atomicAdd(&hist[inst * 32 + ilog2(dd)], 1);
     }
   }
   __syncthreads();
-  if (n_inst == 1 && threadIdx.x < 32 && loc[threadIdx.x]) atomicAdd(&hist[threadIdx.x], loc[threadIdx.x]);
+  if (threadIdx.x < 32 && loc[threadIdx.x]) atomicAdd(&hist[(i0 > 0 ? i0 : 0) * 32 + threadIdx.x], loc[threadIdx.x]);
 }
 
 __global__ void k_hot_flags(const int32_t* __restrict__ cnt_a, const int32_t* __restrict__ cnt_b,
@@ -151,9 +155,24 @@ constexpr int FR_WTILE = 64 * FR_IT;
 constexpr int FR_TILE = FR_NT * FR_IT;
 enum FilterMode { FILTER_SPARSE = 0, FILTER_COLD = 1 };
 
+// One bit per z of the filter's z test (kept iff set): bit z of zbit[z / 64].
+// In bits the test of a random z reads a table 32 times smaller than the
+// int32 one, which mostly stays in cache.
+template <int MODE>
+__global__ void k_filter_bits(const int32_t* __restrict__ zsel, int64_t n_z, uint64_t* __restrict__ zbit) {
+  for (int64_t base = (int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63)); base < n_z;
+       base += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t z = base + lane_id();
+    const bool k = z < n_z && (MODE == FILTER_SPARSE ? zsel[z] == 0 : zsel[z] >= 0);
+    const uint64_t b = ballot(k);
+    if (lane_id() == 0) zbit[base >> 6] = b;
+  }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol,
                                                        int64_t n, const int32_t* __restrict__ zsel,
+                                                       const uint64_t* __restrict__ zbit,
                                                        const int32_t* __restrict__ hot, int32_t* __restrict__ out,
                                                        int32_t* __restrict__ rowptr, int64_t n_rows,
                                                        int32_t* __restrict__ total, uint64_t* __restrict__ status,
@@ -184,10 +203,11 @@ __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict
     const int32_t up = __shfl_up(e1[j], 1, 64);
     e0[j] = lane > 0 ? up : (j > 0 ? __builtin_amdgcn_readlane(e1[j > 0 ? j - 1 : 0], 63) : ew);
   }
-  int32_t sel[FR_IT], h[FR_IT];
+  uint64_t zb[FR_IT];
+  int32_t h[FR_IT];
 #pragma unroll
   for (int j = 0; j < FR_IT; ++j) {
-    sel[j] = zsel[z[j]];
+    zb[j] = zbit[z[j] >> 6];
     h[j] = MODE == FILTER_COLD ? hot[e1[j] - 1] : 0;
   }
   uint32_t keep = 0;
@@ -195,12 +215,14 @@ __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict
 #pragma unroll
   for (int j = 0; j < FR_IT; ++j) {
     const bool in = w0 + j * 64 + lane < n;
-    const bool k = in && (MODE == FILTER_SPARSE ? sel[j] == 0 : (sel[j] >= 0 && !h[j]));
-    val[j] = MODE == FILTER_SPARSE ? z[j] : sel[j];
+    const bool k = in && ((zb[j] >> (z[j] & 63)) & 1u) && !h[j];
     row1[j] = (in && e1[j] != e0[j]) ? e1[j] : 0;
     if (k) keep |= 1u << j;
     cnt += __popcll(ballot(k));
   }
+  // values of the kept entries: z itself, or its local index (a gather for kept entries only)
+#pragma unroll
+  for (int j = 0; j < FR_IT; ++j) val[j] = MODE == FILTER_SPARSE ? z[j] : (((keep >> j) & 1u) ? zsel[z[j]] : 0);
   if (lane == 0) s_wsum[wid] = cnt;
   __syncthreads();
   int32_t woff = 0, btot = 0;
@@ -484,7 +506,7 @@ void dense_index(const int32_t* flag, const int32_t* Edz, int64_t n_z, int32_t* 
   JP_LAUNCH_CHECK();
 }
 
-void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zsel,
+void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zsel, int64_t n_z,
                  const int32_t* hot, int32_t* out, int32_t* rowptr, int64_t n_rows, int32_t* total, hipStream_t s,
                  Arena& a) {
   if (n <= 0) {
@@ -492,17 +514,23 @@ void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, c
     fill_i32(total, 1, 0, s);
     return;
   }
+  const int64_t nw = (n_z + 63) / 64;
+  uint64_t* zbit = a.alloc<uint64_t>(std::max<int64_t>(nw, 1), s);
+  const int gb = int(std::min<int64_t>((n_z + NT - 1) / NT, 1 << 16));
+  if (cold) hipLaunchKernelGGL(k_filter_bits<FILTER_COLD>, dim3(gb > 0 ? gb : 1), dim3(NT), 0, s, zsel, n_z, zbit);
+  else hipLaunchKernelGGL(k_filter_bits<FILTER_SPARSE>, dim3(gb > 0 ? gb : 1), dim3(NT), 0, s, zsel, n_z, zbit);
   const int64_t nt = (n + FR_TILE - 1) / FR_TILE;
   uint64_t* status = a.alloc<uint64_t>(nt + 2, s);
   fill_i64(reinterpret_cast<int64_t*>(status), nt + 2, 0, s);
   if (cold)
-    hipLaunchKernelGGL(k_filter_rows<FILTER_COLD>, dim3(int(nt)), dim3(FR_NT), 0, s, Ey, scol, n, zsel, hot, out, rowptr,
-                       n_rows, total, status, nt);
+    hipLaunchKernelGGL(k_filter_rows<FILTER_COLD>, dim3(int(nt)), dim3(FR_NT), 0, s, Ey, scol, n, zsel,
+                       (const uint64_t*)zbit, hot, out, rowptr, n_rows, total, status, nt);
   else
-    hipLaunchKernelGGL(k_filter_rows<FILTER_SPARSE>, dim3(int(nt)), dim3(FR_NT), 0, s, Ey, scol, n, zsel, hot, out,
-                       rowptr, n_rows, total, status, nt);
+    hipLaunchKernelGGL(k_filter_rows<FILTER_SPARSE>, dim3(int(nt)), dim3(FR_NT), 0, s, Ey, scol, n, zsel,
+                       (const uint64_t*)zbit, hot, out, rowptr, n_rows, total, status, nt);
   JP_LAUNCH_CHECK();
   a.give_back(status, s);
+  a.give_back(zbit, s);
 }
 
 void remap_rowptr(const int32_t* rowptr, const int32_t* E, int64_t n_y, int32_t* out, hipStream_t s) {
@@ -514,7 +542,8 @@ void hot_histogram(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR
                    const int32_t* y_base, int n_inst, int32_t* hist, hipStream_t s) {
   fill_i32(hist, int64_t(n_inst) * 32, 0, s);
   if (n_y <= 0) return;
-  hipLaunchKernelGGL(k_hot_histogram, dim3(grid(n_y)), dim3(NT), 0, s, cnt_a, cnt_b, dR, n_y, y_base, n_inst, hist);
+  hipLaunchKernelGGL(k_hot_histogram, dim3(chunk_grid(n_y)), dim3(NT), 0, s, cnt_a, cnt_b, dR, n_y, y_base, n_inst,
+                     hist);
   JP_LAUNCH_CHECK();
 }
 

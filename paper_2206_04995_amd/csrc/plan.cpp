@@ -579,7 +579,7 @@ void Plan::partition(hipStream_t s) {
   spcol = A.alloc<int32_t>(NSa, s);  // sized before the count is known: one pass fills it
   spptr = A.alloc<int32_t>(NY + 1, s);
   int32_t* d_nsp = T.alloc<int32_t>(1, s);
-  filter_rows(false, Ey, scol, NS, zflag, nullptr, spcol, spptr, NY, d_nsp, s, T);
+  filter_rows(false, Ey, scol, NS, zflag, NZ, nullptr, spcol, spptr, NY, d_nsp, s, T);
   int32_t nsp = 0;
   d2h(&nsp, d_nsp, 1, s);
   int32_t* hist = T.alloc<int32_t>(int64_t(n) * 32, s);
@@ -780,7 +780,7 @@ void Plan::build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a,
   int32_t* ccol_y = T.alloc<int32_t>(NSa, s);
   d.cptr = A.alloc<int32_t>(NY + 1, s);
   int32_t* d_ncold = T.alloc<int32_t>(1, s);
-  filter_rows(true, Ey, scol, NS, zmap, hot, ccol_y, d.cptr, NY, d_ncold, s, T);
+  filter_rows(true, Ey, scol, NS, zmap, NZ, hot, ccol_y, d.cptr, NY, d_ncold, s, T);
   int32_t ncold = 0;
   d2h(&ncold, d_ncold, 1, s);
   sync(s);

@@ -119,8 +119,8 @@ void dense_index(const int32_t* flag, const int32_t* Edz, int64_t n_z, int32_t* 
 // S entries filtered into a CSR over the rows of S in one pass: the entries
 // whose z is sparse (cold = false: zsel = zflag, out = z), or the cold
 // entries of a space (cold = true: zsel = zmap, hot = hot rows, out = local
-// index); rowptr gets n_rows + 1 entries, *total the kept count
-void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zsel,
+// index); zsel has n_z entries; rowptr gets n_rows + 1 entries, *total the kept count
+void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zsel, int64_t n_z,
                  const int32_t* hot, int32_t* out, int32_t* rowptr, int64_t n_rows, int32_t* total, hipStream_t s,
                  Arena& a);
 // rowptr_out[y] = E[rowptr[y]] for y in [0, n_y]
