@@ -203,11 +203,13 @@ __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict
     const int32_t up = __shfl_up(e1[j], 1, 64);
     e0[j] = lane > 0 ? up : (j > 0 ? __builtin_amdgcn_readlane(e1[j > 0 ? j - 1 : 0], 63) : ew);
   }
-  uint64_t zb[FR_IT];
+  // the bitmap read as 32-bit words (little-endian: word z / 32 holds bit z % 32)
+  const uint32_t* zb32 = reinterpret_cast<const uint32_t*>(zbit);
+  uint32_t zb[FR_IT];
   int32_t h[FR_IT];
 #pragma unroll
   for (int j = 0; j < FR_IT; ++j) {
-    zb[j] = zbit[z[j] >> 6];
+    zb[j] = zb32[z[j] >> 5];
     h[j] = MODE == FILTER_COLD ? hot[e1[j] - 1] : 0;
   }
   uint32_t keep = 0;
@@ -215,7 +217,7 @@ __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict
 #pragma unroll
   for (int j = 0; j < FR_IT; ++j) {
     const bool in = w0 + j * 64 + lane < n;
-    const bool k = in && ((zb[j] >> (z[j] & 63)) & 1u) && !h[j];
+    const bool k = in && ((zb[j] >> (z[j] & 31)) & 1u) && !h[j];
     row1[j] = (in && e1[j] != e0[j]) ? e1[j] : 0;
     if (k) keep |= 1u << j;
     cnt += __popcll(ballot(k));
