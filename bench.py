@@ -64,10 +64,12 @@ MEASURED_TRAFFIC = {
                           "stages.h": "19c030a1670b519a14c35bf3e9f052e634aca0be7ac1bd4d72947b679aac04fc",
                           "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
     # the mapping stage of one batched pass (every kernel from k_gather_cols to k_out_j), 4096 instances
-    "batched_map": {"kernels": "mapping and CSR builds of the batched pass", "fetch_kib": 60563260.9,
-                    "write_kib": 86790138.1,
-                    "sources": {"mapping.hip": "31b65335cbf460d339bda12e7bd785caee6554211547af901dfbfc74aba3ac6f",
-                                "prim.hip": "357a597bf671428e992d90c55058e3ad4a1e381eb3669035c44e9d121fbb67c6"}},
+    "batched_map": {"kernels": "mapping and CSR builds of the batched pass", "fetch_kib": 46785041.6,
+                    "write_kib": 69226141.4,
+                    "sources": {"mapping.hip": "616d5e34d78aa075ad056945dc90158b6c75255209e765ecf684be86f7495f16",
+                                "prim.hip": "a4ebfd219de22a68a710ce6025099963f69d518620a9db0f5fd0967dd74297b5",
+                                "plan.cpp": "0a49376f163b06aa79da6036deb98f97122c38503e04951caaf8ac510e26299c",
+                                "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
     "dense": {"kernels": "k_dense_mfma", "fetch_kib": 809038.4, "write_kib": 12343.8,
               "sources": {"dense_mfma.hip": "c4103f00b68fb47500e9e25f66d0e6c7b0317e25200728f600fa7ef5ed3c3ed4",
                           "stages.h": "19c030a1670b519a14c35bf3e9f052e634aca0be7ac1bd4d72947b679aac04fc",
