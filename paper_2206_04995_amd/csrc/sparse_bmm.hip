@@ -47,12 +47,47 @@ __global__ void k_entry_seg(const int32_t* __restrict__ rcol, const int32_t* __r
   }
 }
 
-// w[x] = sum of the entry lengths of row x (difference of the entries' prefix sums)
-__global__ void k_row_diff(const int32_t* __restrict__ rptr, const int64_t* __restrict__ E, int64_t j_lo, int64_t x_lo,
-                           int64_t x_hi, int64_t* __restrict__ w) {
+// w[x] = sum of the entry lengths of row x: one thread per row (rows are a
+// few entries long on average and their lengths lie together); a row of more
+// than ROW_LONG entries goes to a list that whole workgroups sum
+constexpr int ROW_LONG = 512;
+
+__global__ void k_row_work(const int32_t* __restrict__ rptr, const int32_t* __restrict__ len, int64_t x_lo,
+                           int64_t x_hi, int64_t* __restrict__ w, int32_t* __restrict__ long_rows,
+                           int32_t* __restrict__ n_long) {
   for (int64_t x = x_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < x_hi;
-       x += int64_t(gridDim.x) * blockDim.x)
-    w[x - x_lo] = E[rptr[x + 1] - j_lo] - E[rptr[x] - j_lo];
+       x += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t a = rptr[x], b = rptr[x + 1];
+    if (b - a > ROW_LONG) {
+      long_rows[atomicAdd(n_long, 1)] = int32_t(x);
+      continue;
+    }
+    int64_t sum = 0;
+    for (int32_t j = a; j < b; ++j) sum += len[j];
+    w[x - x_lo] = sum;
+  }
+}
+
+__global__ void __launch_bounds__(NT) k_row_work_long(const int32_t* __restrict__ rptr, const int32_t* __restrict__ len,
+                                                      int64_t x_lo, int64_t* __restrict__ w,
+                                                      const int32_t* __restrict__ long_rows,
+                                                      const int32_t* __restrict__ n_long) {
+  __shared__ int64_t part[NT / 64];
+  const int nl = *n_long;
+  for (int i = blockIdx.x; i < nl; i += gridDim.x) {  // block-uniform
+    const int32_t x = long_rows[i];
+    int64_t sum = 0;
+    for (int32_t j = rptr[x] + threadIdx.x; j < rptr[x + 1]; j += NT) sum += len[j];
+    sum = wave_sum(sum);
+    if (lane_id() == 0) part[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t t = 0;
+      for (int q = 0; q < NT / 64; ++q) t += part[q];
+      w[x - x_lo] = t;
+    }
+    __syncthreads();
+  }
 }
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t z, int log2t) {
@@ -513,20 +548,24 @@ __global__ void __launch_bounds__(NT) k_sparse_heavy_write(const int32_t* __rest
 
 void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, int64_t j_hi, int64_t* w,
                      int32_t* seg0, int32_t* seglen, hipStream_t s, Arena& a) {
-  int64_t n = x_hi - x_lo;
+  const int64_t n = x_hi - x_lo;
   if (n <= 0) return;
   const int64_t ne = j_hi - j_lo;
-  int64_t* E = a.alloc<int64_t>(ne + 1, s);
   if (ne > 0) {
     int g = int(std::min<int64_t>((ne + NT - 1) / NT, 1 << 16));
     hipLaunchKernelGGL(k_entry_seg, dim3(g), dim3(NT), 0, s, c.rcol, c.spptr, j_lo, j_hi, seg0, seglen);
     JP_LAUNCH_CHECK();
   }
-  scan_excl_i32_to_i64(seglen + j_lo, E, ne, s, a);
-  int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
-  hipLaunchKernelGGL(k_row_diff, dim3(g), dim3(NT), 0, s, c.rptr, E, j_lo, x_lo, x_hi, w);
+  int32_t* n_long = a.alloc<int32_t>(1, s);
+  int32_t* long_rows = a.alloc<int32_t>(std::max<int64_t>(std::min<int64_t>(n, ne / ROW_LONG + 1), 1), s);
+  fill_i32(n_long, 1, 0, s);
+  const int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
+  hipLaunchKernelGGL(k_row_work, dim3(g), dim3(NT), 0, s, c.rptr, seglen, x_lo, x_hi, w, long_rows, n_long);
+  hipLaunchKernelGGL(k_row_work_long, dim3(int(std::min<int64_t>(n, 1024))), dim3(NT), 0, s, c.rptr, seglen, x_lo, w,
+                     (const int32_t*)long_rows, (const int32_t*)n_long);
   JP_LAUNCH_CHECK();
-  a.give_back(E, s);
+  a.give_back(long_rows, s);
+  a.give_back(n_long, s);
 }
 
 int64_t sparse_list_ints(int64_t n_rows) { return 2 * n_rows + 4; }
