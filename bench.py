@@ -51,18 +51,18 @@ FETCH_FACTOR = 1048576 / 524308.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
     # two count launches per step: rows without and with the pivot key (2 windows per workgroup, as tuned)
-    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 663647.8 + 275965.1, "write_kib": 80210.6 + 39764.1,
-               "sources": {"dense_ec.hip": "9abaf47b14713dc235ed9bb4d25b280a95c0f2e143ff38b509303eb9123bc0ad",
-                           "stages.h": "19c030a1670b519a14c35bf3e9f052e634aca0be7ac1bd4d72947b679aac04fc",
-                           "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
-    # the whole timed SparseBMM count region: per-entry segments and their scan,
-    # row work, row lists, the light/medium/heavy count kernels
+    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 706836.1 + 271579.4, "write_kib": 80210.6 + 39764.1,
+               "sources": {"dense_ec.hip": "3a4ea9f17479945a1200432af77316d554213d3c1778f78e91fdf20f898c90ff",
+                           "stages.h": "9f1d17ce26dd03bb4ead68b177f5469ad14d4b3a281ad23ece576481e3261635",
+                           "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
+    # the whole timed SparseBMM count region: per-entry segments, row work, row
+    # lists, the light/medium/heavy count kernels
     "graph": {"kernels": "SparseBMM count pass (k_entry_seg ... k_sparse_heavy_count)",
-              "fetch_kib": 2757289.5, "write_kib": 372779.5,
-              "sources": {"sparse_bmm.hip": "0563945fb2abfe85c00b9423b0102642ee95735227e00dc29ac7eb30a2a15044",
-                          "prim.hip": "357a597bf671428e992d90c55058e3ad4a1e381eb3669035c44e9d121fbb67c6",
-                          "stages.h": "19c030a1670b519a14c35bf3e9f052e634aca0be7ac1bd4d72947b679aac04fc",
-                          "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
+              "fetch_kib": 2650799.2, "write_kib": 216310.6,
+              "sources": {"sparse_bmm.hip": "7925383867891d063a91fd656adc43e24dba1dcfee4e9cc927bbca11da5affe0",
+                          "prim.hip": "a4ebfd219de22a68a710ce6025099963f69d518620a9db0f5fd0967dd74297b5",
+                          "stages.h": "9f1d17ce26dd03bb4ead68b177f5469ad14d4b3a281ad23ece576481e3261635",
+                          "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
     # the mapping stage of one batched pass (every kernel from k_gather_cols to k_out_j), 4096 instances
     "batched_map": {"kernels": "mapping and CSR builds of the batched pass", "fetch_kib": 46785041.6,
                     "write_kib": 69226141.4,
@@ -70,10 +70,10 @@ MEASURED_TRAFFIC = {
                                 "prim.hip": "a4ebfd219de22a68a710ce6025099963f69d518620a9db0f5fd0967dd74297b5",
                                 "plan.cpp": "0a49376f163b06aa79da6036deb98f97122c38503e04951caaf8ac510e26299c",
                                 "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
-    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 809038.4, "write_kib": 12343.8,
-              "sources": {"dense_mfma.hip": "c4103f00b68fb47500e9e25f66d0e6c7b0317e25200728f600fa7ef5ed3c3ed4",
-                          "stages.h": "19c030a1670b519a14c35bf3e9f052e634aca0be7ac1bd4d72947b679aac04fc",
-                          "common.h": "1e62888273711daaffd80f57584a98f295562b616c4d66eaa3fffa0c1186baa5"}},
+    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 127735.5, "write_kib": 25185.5,
+              "sources": {"dense_mfma.hip": "e01d5a7827ea364242f9cdbc823f069d02d4dc8d34fb036d2fc3687d726d1998",
+                          "stages.h": "9f1d17ce26dd03bb4ead68b177f5469ad14d4b3a281ad23ece576481e3261635",
+                          "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
 }
 
 

@@ -557,6 +557,118 @@ __global__ void k_scatter_x(const int32_t* __restrict__ rx, const int32_t* __res
   }
 }
 
+// gather of per-instance device columns into one concatenated buffer; with
+// mn/mx non-null also each instance's minimum and maximum (the key layout of
+// the mapping), so the column is read once for both
+__device__ __forceinline__ void flush_minmax(int inst, int32_t lo, int32_t hi, int32_t* mn, int32_t* mx) {
+  // whole wave: one atomic pair when every lane holds the same instance
+  const int i0 = __builtin_amdgcn_readfirstlane(inst);
+  if (ballot(inst != i0) == 0) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const int32_t a = __shfl_xor(lo, o, 64), b = __shfl_xor(hi, o, 64);
+      lo = a < lo ? a : lo;
+      hi = b > hi ? b : hi;
+    }
+    if (lane_id() == 0 && inst >= 0) {
+      atomicMin(&mn[inst], lo);
+      atomicMax(&mx[inst], hi);
+    }
+  } else if (inst >= 0) {
+    atomicMin(&mn[inst], lo);
+    atomicMax(&mx[inst], hi);
+  }
+}
+
+__global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int32_t* __restrict__ base, int n_inst,
+                              int64_t n, int32_t* __restrict__ dst, int32_t* __restrict__ mn,
+                              int32_t* __restrict__ mx) {
+  const int64_t c0 = chunk_first();
+  const int64_t c1 = c0 + JP_CHUNK < n ? c0 + JP_CHUNK : n;
+  const int64_t step = blockDim.x;
+  const int i0 = wave_find_inst<int32_t>(base, n_inst, int32_t(c0));
+  if (int64_t(base[i0 + 1]) >= c1) {
+    // the chunk lies in one instance (all but the chunks at instance bounds): no per-element lookups
+    const int32_t* col = src[i0] + (c0 - base[i0]);
+    int32_t lo = INT32_MAX, hi = INT32_MIN;
+    for (int64_t g0 = c0 + threadIdx.x; g0 < c1; g0 += 4 * step) {
+      int32_t vv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t g = g0 + u * step;
+        vv[u] = g < c1 ? col[g - c0] : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t g = g0 + u * step;
+        if (g < c1) {
+          dst[g] = vv[u];
+          lo = vv[u] < lo ? vv[u] : lo;
+          hi = vv[u] > hi ? vv[u] : hi;
+        }
+      }
+    }
+    if (mn) flush_minmax(i0, lo, hi, mn, mx);
+    return;
+  }
+  SegCursor<int32_t> cur(base, n_inst);
+  cur.seed(int32_t(c0));
+  const int32_t* col = nullptr;
+  int last = -1;                           // instance of `col`
+  int acc = -1;                            // instance whose values lo and hi hold
+  int32_t lo = INT32_MAX, hi = INT32_MIN;
+  // four elements per thread and step: their source addresses first, then the
+  // four loads in flight together, then the stores (and the min and max, in
+  // element order, so a lane's values move to the next instance's at its bound)
+  for (int64_t g0 = chunk_first() + threadIdx.x; g0 < c1; g0 += 4 * step) {
+    const int32_t* at[4];
+    int iu[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t g = g0 + u * step;
+      at[u] = nullptr;
+      iu[u] = -1;
+      if (g < c1) {
+        const int inst = cur(int32_t(g));
+        if (inst != last) {
+          last = inst;
+          col = src[inst];
+        }
+        at[u] = col + (g - cur.lo);
+        iu[u] = inst;
+      }
+    }
+    int32_t vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) vv[u] = at[u] ? *at[u] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (iu[u] >= 0) {
+        dst[g0 + u * step] = vv[u];
+        if (mn) {
+          if (iu[u] != acc) {  // rare: at instance bounds
+            if (acc >= 0) {
+              atomicMin(&mn[acc], lo);
+              atomicMax(&mx[acc], hi);
+            }
+            acc = iu[u];
+            lo = INT32_MAX;
+            hi = INT32_MIN;
+          }
+          lo = vv[u] < lo ? vv[u] : lo;
+          hi = vv[u] > hi ? vv[u] : hi;
+        }
+      }
+  }
+  if (mn) flush_minmax(acc, lo, hi, mn, mx);
+}
+
+// minima (rows 0, 2, 4 of n) start at INT32_MAX, maxima (rows 1, 3, 5) at INT32_MIN
+__global__ void k_fill_minmax(int32_t* mm, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 6 * n) mm[i] = ((i / n) & 1) ? INT32_MIN : INT32_MAX;
+}
+
 }  // namespace
 
 void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff, const int32_t* mn,
@@ -738,6 +850,18 @@ void scatter_x(const int32_t* rx, const int32_t* yid, int64_t n, const int32_t* 
   if (n <= 0) return;
   hipLaunchKernelGGL(k_scatter_x, dim3(chunk_grid(n)), dim3(NT), 0, s, rx, yid, n, ebase, n_inst, koff_x, xmin, cur,
                      rcol);
+  JP_LAUNCH_CHECK();
+}
+
+void fill_minmax(int32_t* mm, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_minmax, dim3((6 * n_inst + 255) / 256), dim3(256), 0, s, mm, n_inst);
+  JP_LAUNCH_CHECK();
+}
+
+void gather_cols(const int32_t* const* src, const int32_t* base, int n_inst, int64_t n, int32_t* dst, int32_t* mn,
+                 int32_t* mx, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(n)), dim3(256), 0, s, src, base, n_inst, n, dst, mn, mx);
   JP_LAUNCH_CHECK();
 }
 

@@ -28,6 +28,44 @@ __global__ void k_inst_totals(const int64_t* __restrict__ oa, const int64_t* __r
   }
 }
 
+// per-instance totals straight from the per-row counts (no offsets):
+// tot[3i] += dense + sparse, tot[3i + 1] += dense, tot[3i + 2] += sparse over
+// the rows of instance i (tot zeroed before).  A thread sums its rows of one
+// instance at a time; at the end a wave whose lanes all hold the same
+// instance adds once.
+__device__ __forceinline__ void add_tot(int64_t* tot, int inst, int64_t de, int64_t sp) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(&tot[3 * inst + 0]), (unsigned long long)(de + sp));
+  atomicAdd(reinterpret_cast<unsigned long long*>(&tot[3 * inst + 1]), (unsigned long long)de);
+  atomicAdd(reinterpret_cast<unsigned long long*>(&tot[3 * inst + 2]), (unsigned long long)sp);
+}
+
+__global__ void k_inst_sums(const int32_t* __restrict__ cnt_sp, const int32_t* __restrict__ cnt_de,
+                            const int32_t* __restrict__ x_base, int n_inst, int64_t n_x, int64_t* __restrict__ tot) {
+  SegCursor<int32_t> cur(x_base, n_inst);
+  cur.seed(int32_t(chunk_first() < n_x ? chunk_first() : 0));
+  int acc = -1;
+  int64_t de = 0, sp = 0;
+  CHUNK_LOOP(x, n_x, JP_CHUNK) {
+    const int inst = cur(int32_t(x));
+    if (inst != acc) {
+      if (acc >= 0) add_tot(tot, acc, de, sp);
+      acc = inst;
+      de = 0;
+      sp = 0;
+    }
+    de += cnt_de[x];
+    sp += cnt_sp[x];
+  }
+  const int i0 = __builtin_amdgcn_readfirstlane(acc);
+  if (ballot(acc != i0) == 0) {
+    de = wave_sum(de);
+    sp = wave_sum(sp);
+    if (lane_id() == 0 && acc >= 0) add_tot(tot, acc, de, sp);
+  } else if (acc >= 0) {
+    add_tot(tot, acc, de, sp);
+  }
+}
+
 // out2[0] = row holding pair g0, out2[1] = first row starting at or after g1
 __global__ void k_find_rows(const int64_t* __restrict__ off, int64_t xb, int64_t xe, int64_t g0, int64_t g1,
                             int64_t* __restrict__ out2) {
@@ -134,6 +172,14 @@ void add_counts(const int32_t* a, const int32_t* b, int64_t n, int32_t* out, hip
   if (n <= 0) return;
   int g = int(std::min<int64_t>((n + NT - 1) / NT, 1 << 16));
   hipLaunchKernelGGL(k_add_counts, dim3(g), dim3(NT), 0, s, a, b, n, out);
+  JP_LAUNCH_CHECK();
+}
+
+void inst_sums(const int32_t* cnt_sp, const int32_t* cnt_de, const int32_t* x_base, int n_inst, int64_t n_x,
+               int64_t* tot, hipStream_t s) {
+  fill_i64(tot, 3 * int64_t(n_inst), 0, s);
+  if (n_x <= 0) return;
+  hipLaunchKernelGGL(k_inst_sums, dim3(chunk_grid(n_x)), dim3(NT), 0, s, cnt_sp, cnt_de, x_base, n_inst, n_x, tot);
   JP_LAUNCH_CHECK();
 }
 

@@ -83,118 +83,6 @@ int local_bits(const std::vector<int64_t>& koff) {
   return bits_for(uint64_t(w));
 }
 
-// gather of per-instance device columns into one concatenated buffer; with
-// mn/mx non-null also each instance's minimum and maximum (the key layout of
-// the mapping), so the column is read once for both
-__device__ __forceinline__ void flush_minmax(int inst, int32_t lo, int32_t hi, int32_t* mn, int32_t* mx) {
-  // whole wave: one atomic pair when every lane holds the same instance
-  const int i0 = __builtin_amdgcn_readfirstlane(inst);
-  if (ballot(inst != i0) == 0) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const int32_t a = __shfl_xor(lo, o, 64), b = __shfl_xor(hi, o, 64);
-      lo = a < lo ? a : lo;
-      hi = b > hi ? b : hi;
-    }
-    if (lane_id() == 0 && inst >= 0) {
-      atomicMin(&mn[inst], lo);
-      atomicMax(&mx[inst], hi);
-    }
-  } else if (inst >= 0) {
-    atomicMin(&mn[inst], lo);
-    atomicMax(&mx[inst], hi);
-  }
-}
-
-__global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int32_t* __restrict__ base, int n_inst,
-                              int64_t n, int32_t* __restrict__ dst, int32_t* __restrict__ mn,
-                              int32_t* __restrict__ mx) {
-  const int64_t c0 = chunk_first();
-  const int64_t c1 = c0 + JP_CHUNK < n ? c0 + JP_CHUNK : n;
-  const int64_t step = blockDim.x;
-  const int i0 = wave_find_inst<int32_t>(base, n_inst, int32_t(c0));
-  if (int64_t(base[i0 + 1]) >= c1) {
-    // the chunk lies in one instance (all but the chunks at instance bounds): no per-element lookups
-    const int32_t* col = src[i0] + (c0 - base[i0]);
-    int32_t lo = INT32_MAX, hi = INT32_MIN;
-    for (int64_t g0 = c0 + threadIdx.x; g0 < c1; g0 += 4 * step) {
-      int32_t vv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t g = g0 + u * step;
-        vv[u] = g < c1 ? col[g - c0] : 0;
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t g = g0 + u * step;
-        if (g < c1) {
-          dst[g] = vv[u];
-          lo = vv[u] < lo ? vv[u] : lo;
-          hi = vv[u] > hi ? vv[u] : hi;
-        }
-      }
-    }
-    if (mn) flush_minmax(i0, lo, hi, mn, mx);
-    return;
-  }
-  SegCursor<int32_t> cur(base, n_inst);
-  cur.seed(int32_t(c0));
-  const int32_t* col = nullptr;
-  int last = -1;                           // instance of `col`
-  int acc = -1;                            // instance whose values lo and hi hold
-  int32_t lo = INT32_MAX, hi = INT32_MIN;
-  // four elements per thread and step: their source addresses first, then the
-  // four loads in flight together, then the stores (and the min and max, in
-  // element order, so a lane's values move to the next instance's at its bound)
-  for (int64_t g0 = chunk_first() + threadIdx.x; g0 < c1; g0 += 4 * step) {
-    const int32_t* at[4];
-    int iu[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t g = g0 + u * step;
-      at[u] = nullptr;
-      iu[u] = -1;
-      if (g < c1) {
-        const int inst = cur(int32_t(g));
-        if (inst != last) {
-          last = inst;
-          col = src[inst];
-        }
-        at[u] = col + (g - cur.lo);
-        iu[u] = inst;
-      }
-    }
-    int32_t vv[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) vv[u] = at[u] ? *at[u] : 0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (iu[u] >= 0) {
-        dst[g0 + u * step] = vv[u];
-        if (mn) {
-          if (iu[u] != acc) {  // rare: at instance bounds
-            if (acc >= 0) {
-              atomicMin(&mn[acc], lo);
-              atomicMax(&mx[acc], hi);
-            }
-            acc = iu[u];
-            lo = INT32_MAX;
-            hi = INT32_MIN;
-          }
-          lo = vv[u] < lo ? vv[u] : lo;
-          hi = vv[u] > hi ? vv[u] : hi;
-        }
-      }
-  }
-  if (mn) flush_minmax(acc, lo, hi, mn, mx);
-}
-
-// minima (rows 0, 2, 4 of n) start at INT32_MAX, maxima (rows 1, 3, 5) at INT32_MIN
-__global__ void k_fill_minmax(int32_t* mm, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 6 * n) mm[i] = ((i / n) & 1) ? INT32_MIN : INT32_MAX;
-}
-
 __global__ void k_slice_info(const int64_t* __restrict__ off_de, const int64_t* __restrict__ off_sp,
                              const int64_t* __restrict__ rows, int64_t* __restrict__ info) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -276,20 +164,12 @@ void Plan::build(const jp_instance* inst, int n, const jp_options* o, hipStream_
     d_minmax = A.alloc<int32_t>(6 * int64_t(n), s);
     int32_t *zmin = d_minmax, *zmax = d_minmax + n, *ymin = d_minmax + 2 * n, *ymax = d_minmax + 3 * n;
     int32_t *xmin = d_minmax + 4 * n, *xmax = d_minmax + 5 * n;
-    hipLaunchKernelGGL(k_fill_minmax, dim3((6 * n + 255) / 256), dim3(256), 0, s, d_minmax, n);
-    int32_t* none = nullptr;
-    if (NR) {
-      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NR)), dim3(256), 0, s, d_ptrs, d_rbase, n, NR, crx, xmin, xmax);
-      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NR)), dim3(256), 0, s, d_ptrs + n, d_rbase, n, NR, cry, none,
-                         none);
-    }
-    if (NS) {
-      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NS)), dim3(256), 0, s, d_ptrs + 2 * n, d_sbase, n, NS, csz,
-                         zmin, zmax);
-      hipLaunchKernelGGL(k_gather_cols, dim3(chunk_grid(NS)), dim3(256), 0, s, d_ptrs + 3 * n, d_sbase, n, NS, csy,
-                         ymin, ymax);
-    }
-    JP_LAUNCH_CHECK();
+    fill_minmax(d_minmax, n, s);
+    const int32_t* const* src = d_ptrs;
+    gather_cols(src, d_rbase, n, NR, crx, xmin, xmax, s);
+    gather_cols(src + n, d_rbase, n, NR, cry, nullptr, nullptr, s);
+    gather_cols(src + 2 * n, d_sbase, n, NS, csz, zmin, zmax, s);
+    gather_cols(src + 3 * n, d_sbase, n, NS, csy, ymin, ymax, s);
     rx = crx;
     ry = cry;
     sz = csz;
@@ -1005,6 +885,7 @@ void Plan::execute(hipStream_t s) {
   }
   warm = true;
   executed = true;
+  offsets_ready = false;
   h_tot.clear();
 }
 
@@ -1028,12 +909,22 @@ void Plan::run_count_pass(hipStream_t s, bool timing) {
     fill_i32(cnt_de, NX, 0, s);
   }
   if (timing) JP_HIP(hipEventRecord(ev[2], s));
-  add_counts(cnt_sp, cnt_de, NX, cnt_all, s);
-  scan_excl_i32_to_i64(cnt_all, off_all, NX, s, XA);
-  scan_excl_i32_to_i64(cnt_de, off_de, NX, s, XA);
-  scan_excl_i32_to_i64(cnt_sp, off_sp, NX, s, XA);
-  inst_totals(off_all, off_de, off_sp, x_base, n_inst, tot, s);
+  // per-instance totals now; the row offsets only when a list or the offsets are asked for (ensure_offsets)
+  inst_sums(cnt_sp, cnt_de, x_base, n_inst, NX, tot, s);
   if (timing) JP_HIP(hipEventRecord(ev[3], s));
+}
+
+// Row offsets of the last count pass (prefix sums of the per-row counts of
+// each part), computed at the first call that needs them.
+void Plan::ensure_offsets(hipStream_t s) {
+  if (offsets_ready) return;
+  Arena T(&B);
+  add_counts(cnt_sp, cnt_de, NX, cnt_all, s);
+  scan_excl_i32_to_i64(cnt_all, off_all, NX, s, T);
+  scan_excl_i32_to_i64(cnt_de, off_de, NX, s, T);
+  scan_excl_i32_to_i64(cnt_sp, off_sp, NX, s, T);
+  T.release(s);
+  offsets_ready = true;
 }
 
 void Plan::timings(jp_timings* t, hipStream_t s) {
@@ -1096,6 +987,7 @@ int64_t Plan::materialize(int inst, int part, int64_t first, int64_t maxp, int32
   const int64_t nw = std::min(maxp, count - first);
   if (nw <= 0) return 0;
   const int64_t xb = h_xbase[inst], xe = h_xbase[inst + 1];
+  ensure_offsets(s);
   const int64_t* off = part == JP_PART_ALL ? off_all : (part == JP_PART_DENSE ? off_de : off_sp);
   int64_t base = 0;
   d2h(&base, off + xb, 1, s);
@@ -1353,6 +1245,7 @@ jp_status jp_row_info(jp_plan* p, jp_part part, int32_t* x_values, int64_t* row_
     if (x_values) d2h(x_values, q.vals_x, size_t(q.NX), stream);
     if (row_offsets) {
       if (!q.executed) throw Error(JP_ESTATE, "row offsets before execute");
+      q.ensure_offsets(stream);
       const int64_t* off = part == JP_PART_ALL ? q.off_all : (part == JP_PART_DENSE ? q.off_de : q.off_sp);
       d2h(row_offsets, off, size_t(q.NX) + 1, stream);
     }

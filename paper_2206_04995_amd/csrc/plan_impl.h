@@ -108,6 +108,7 @@ struct Plan {
   int32_t *seg0 = nullptr, *seglen = nullptr;  // per R entry: sparse S row of its key
   int32_t *cnt_sp = nullptr, *cnt_de = nullptr, *cnt_all = nullptr;
   int64_t *off_all = nullptr, *off_de = nullptr, *off_sp = nullptr, *tot = nullptr;
+  bool offsets_ready = false;  // off_* hold the last count pass's row offsets
 
   // JP_FLAG_TIMING: events around the execute kernels and work counters
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -122,6 +123,7 @@ struct Plan {
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;
   void run_count_pass(hipStream_t s, bool timing);
+  void ensure_offsets(hipStream_t s);  // row offsets of the last count pass, computed on first use
 
   ~Plan() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);

@@ -22,6 +22,13 @@ constexpr int N_WIDTH_CLASSES = 4;  // the three narrow classes and the window k
 constexpr int T_STAGE = 3;
 
 // ------------------------------------------------------------ mapping
+// a batch's columns, one device pointer per instance (src[i], base[i + 1] -
+// base[i] values), into one buffer dst; with mn/mx non-null also each
+// instance's minimum and maximum (atomically merged into mn/mx, which
+// fill_minmax prepares: 6 rows of n_inst, minima at rows 0, 2, 4)
+void fill_minmax(int32_t* mm, int n_inst, hipStream_t s);
+void gather_cols(const int32_t* const* src, const int32_t* base, int n_inst, int64_t n, int32_t* dst, int32_t* mn,
+                 int32_t* mx, hipStream_t s);
 // keys[i] = koff[inst(i)] + (v[i] - mn[inst(i)]); if payload is non-null,
 // payload[i] = pay_src[i] (a column carried through the sort) or i
 void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, const int64_t* koff,
@@ -273,6 +280,9 @@ void work_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const int64
 void digest_pairs(const int32_t* x, const int32_t* z, int64_t n, uint64_t* acc, hipStream_t s);
 void add_counts(const int32_t* a, const int32_t* b, int64_t n, int32_t* out, hipStream_t s);
 // tot[3*i + {0,1,2}] = all, dense, sparse pairs of instance i
+// tot[3i + {0, 1, 2}] = all, dense, sparse pairs of instance i, summed from the per-row counts
+void inst_sums(const int32_t* cnt_sp, const int32_t* cnt_de, const int32_t* x_base, int n_inst, int64_t n_x,
+               int64_t* tot, hipStream_t s);
 void inst_totals(const int64_t* off_all, const int64_t* off_de, const int64_t* off_sp, const int32_t* x_base,
                  int n_inst, int64_t* tot, hipStream_t s);
 // rows [lo, hi) covering global pair range [g0, g1) of an offset array
