@@ -364,20 +364,32 @@ __global__ void __launch_bounds__(NT) k_histogram(const uint32_t* __restrict__ v
   __syncthreads();
   const int64_t b0 = int64_t(blockIdx.x) * HG_PER_BLOCK;
   const int64_t b1 = b0 + HG_PER_BLOCK < n ? b0 + HG_PER_BLOCK : n;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += NT) {
-    const uint32_t k = v[i];
-    uint32_t s = (k * 0x9E3779B1u) >> 20;  // 12-bit slot
-    bool done = false;
-    for (int probe = 0; probe < 2 && !done; ++probe) {
-      uint32_t old = atomicCAS(&key[s], 0xFFFFFFFFu, k);
-      if (old == 0xFFFFFFFFu || old == k) {
-        atomicAdd(&cnt[s], 1);
-        done = true;
-      } else {
-        s = (s + 1) & (HG_SLOTS - 1);
-      }
+  // eight values' loads in flight (clamped indices), then their table updates
+  constexpr int HG_U = 8;
+  for (int64_t i0 = b0 + threadIdx.x; i0 < b1; i0 += HG_U * NT) {
+    uint32_t kk[HG_U];
+#pragma unroll
+    for (int u = 0; u < HG_U; ++u) {
+      const int64_t i = i0 + u * NT;
+      kk[u] = v[i < b1 ? i : b1 - 1];
     }
-    if (!done) atomicAdd(&h[k], 1);
+#pragma unroll
+    for (int u = 0; u < HG_U; ++u) {
+      if (i0 + u * NT >= b1) break;
+      const uint32_t k = kk[u];
+      uint32_t s = (k * 0x9E3779B1u) >> 20;  // 12-bit slot
+      bool done = false;
+      for (int probe = 0; probe < 2 && !done; ++probe) {
+        uint32_t old = atomicCAS(&key[s], 0xFFFFFFFFu, k);
+        if (old == 0xFFFFFFFFu || old == k) {
+          atomicAdd(&cnt[s], 1);
+          done = true;
+        } else {
+          s = (s + 1) & (HG_SLOTS - 1);
+        }
+      }
+      if (!done) atomicAdd(&h[k], 1);
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < HG_SLOTS; i += NT)

@@ -217,11 +217,16 @@ __global__ void __launch_bounds__(RS_NT) k_radix_hist(const uint32_t* __restrict
   const Tile tl = tile_of(m, n, nd);
   for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&cnt[0][0])[i] = 0;
   __syncthreads();
-#pragma unroll 4
+  // all of a thread's loads first (clamped, so they need no branch), then the LDS counts
+  uint32_t kk[RS_IT];
+#pragma unroll
   for (int j = 0; j < RS_IT; ++j) {
-    int64_t i = tl.lo + j * RS_NT + threadIdx.x;
-    if (i < tl.hi) atomicAdd(&cnt[wid][digit_of(keys[i], tl, shift, mask)], 1);
+    const int64_t i = tl.lo + j * RS_NT + threadIdx.x;
+    kk[j] = keys[i < tl.hi ? i : tl.hi - 1];
   }
+#pragma unroll
+  for (int j = 0; j < RS_IT; ++j)
+    if (tl.lo + j * RS_NT + threadIdx.x < tl.hi) atomicAdd(&cnt[wid][digit_of(kk[j], tl, shift, mask)], 1);
   __syncthreads();
   for (int d = threadIdx.x; d < nd; d += RS_NT) {
     int c = 0;
