@@ -16,18 +16,6 @@ __global__ void k_add_counts(const int32_t* __restrict__ a, const int32_t* __res
     out[i] = a[i] + b[i];
 }
 
-__global__ void k_inst_totals(const int64_t* __restrict__ oa, const int64_t* __restrict__ od,
-                              const int64_t* __restrict__ os, const int32_t* __restrict__ x_base, int n_inst,
-                              int64_t* __restrict__ tot) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_inst) {
-    int lo = x_base[i], hi = x_base[i + 1];
-    tot[3 * i + 0] = oa[hi] - oa[lo];
-    tot[3 * i + 1] = od[hi] - od[lo];
-    tot[3 * i + 2] = os[hi] - os[lo];
-  }
-}
-
 // per-instance totals straight from the per-row counts (no offsets):
 // tot[3i] += dense + sparse, tot[3i + 1] += dense, tot[3i + 2] += sparse over
 // the rows of instance i (tot zeroed before).  A thread sums its rows of one
@@ -180,13 +168,6 @@ void inst_sums(const int32_t* cnt_sp, const int32_t* cnt_de, const int32_t* x_ba
   fill_i64(tot, 3 * int64_t(n_inst), 0, s);
   if (n_x <= 0) return;
   hipLaunchKernelGGL(k_inst_sums, dim3(chunk_grid(n_x)), dim3(NT), 0, s, cnt_sp, cnt_de, x_base, n_inst, n_x, tot);
-  JP_LAUNCH_CHECK();
-}
-
-void inst_totals(const int64_t* off_all, const int64_t* off_de, const int64_t* off_sp, const int32_t* x_base, int n_inst,
-                 int64_t* tot, hipStream_t s) {
-  hipLaunchKernelGGL(k_inst_totals, dim3((n_inst + NT - 1) / NT), dim3(NT), 0, s, off_all, off_de, off_sp, x_base,
-                     n_inst, tot);
   JP_LAUNCH_CHECK();
 }
 

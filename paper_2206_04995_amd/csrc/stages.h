@@ -279,12 +279,9 @@ void work_rows(const RowCtx& c, const int32_t* rows, int64_t n_rows, const int64
 // the order-independent digest of a pair list
 void digest_pairs(const int32_t* x, const int32_t* z, int64_t n, uint64_t* acc, hipStream_t s);
 void add_counts(const int32_t* a, const int32_t* b, int64_t n, int32_t* out, hipStream_t s);
-// tot[3*i + {0,1,2}] = all, dense, sparse pairs of instance i
 // tot[3i + {0, 1, 2}] = all, dense, sparse pairs of instance i, summed from the per-row counts
 void inst_sums(const int32_t* cnt_sp, const int32_t* cnt_de, const int32_t* x_base, int n_inst, int64_t n_x,
                int64_t* tot, hipStream_t s);
-void inst_totals(const int64_t* off_all, const int64_t* off_de, const int64_t* off_sp, const int32_t* x_base,
-                 int n_inst, int64_t* tot, hipStream_t s);
 // rows [lo, hi) covering global pair range [g0, g1) of an offset array
 void find_rows(const int64_t* off, int64_t x_begin, int64_t x_end, int64_t g0, int64_t g1, int64_t* out2,
                hipStream_t s);
