@@ -174,14 +174,15 @@ __device__ __forceinline__ void heavy_window(const int32_t* __restrict__ seg0, c
 // writes (empty and heavy ones) get count 0 here, before the heavy kernel adds
 // to it.
 constexpr int CLS_PER = 16;
-constexpr int CLS_ROWS = NT * CLS_PER;
+constexpr int CLS_NT = 1024;  // large blocks: each block reserves list space with one atomic per class
+constexpr int CLS_ROWS = CLS_NT * CLS_PER;  // per-class counts of a block fit the 16-bit packed fields
 
-__global__ void __launch_bounds__(NT) k_classify_rows(int64_t x_lo, int64_t x_hi, const int64_t* __restrict__ w,
+__global__ void __launch_bounds__(CLS_NT) k_classify_rows(int64_t x_lo, int64_t x_hi, const int64_t* __restrict__ w,
                                                       int64_t small_max, int64_t light_max, int64_t med_max,
                                                       int32_t* __restrict__ cnt,
                                                       int32_t* __restrict__ hdr, int32_t* __restrict__ A,
                                                       int32_t* __restrict__ B) {
-  __shared__ int64_t wtot[NT / 64];
+  __shared__ int64_t wtot[CLS_NT / 64];
   __shared__ int32_t bases[4];
   const int lane = lane_id();
   const int wid = threadIdx.x >> 6;
@@ -206,7 +207,7 @@ __global__ void __launch_bounds__(NT) k_classify_rows(int64_t x_lo, int64_t x_hi
   if (lane == 63) wtot[wid] = incl;
   __syncthreads();
   int64_t pre = 0, all = 0;
-  for (int q = 0; q < NT / 64; ++q) {
+  for (int q = 0; q < CLS_NT / 64; ++q) {
     const int64_t v = wtot[q];
     if (q < wid) pre += v;
     all += v;
@@ -585,7 +586,7 @@ void sparse_bmm(const RowCtx& c, int64_t x_lo, int64_t x_hi, const int64_t* w, i
   const int64_t small_max = std::min<int64_t>(SMALL_SLOTS / 2, light_max);
   const int64_t med_max =
       out ? LIGHT_MAX : std::max<int64_t>(light_max, std::min<int64_t>(MED_MAX, c.med_max > 0 ? c.med_max : MED_MAX));
-  hipLaunchKernelGGL(k_classify_rows, dim3(int((n + CLS_ROWS - 1) / CLS_ROWS)), dim3(NT), 0, s, x_lo, x_hi, w,
+  hipLaunchKernelGGL(k_classify_rows, dim3(int((n + CLS_ROWS - 1) / CLS_ROWS)), dim3(CLS_NT), 0, s, x_lo, x_hi, w,
                      small_max, light_max, med_max, cnt, hdr, A, B);
   JP_LAUNCH_CHECK();
   // light rows: four times as many waves as stay resident (8 blocks of 4 waves
