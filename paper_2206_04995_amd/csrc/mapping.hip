@@ -620,7 +620,30 @@ __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int3
         }
       }
     }
-    if (mn) flush_minmax(i0, lo, hi, mn, mx);
+    if (mn) {
+      // the block's min and max (one instance): one atomic pair per block
+      __shared__ int32_t s_lo[JP_CHUNK / 64], s_hi[JP_CHUNK / 64];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const int32_t a = __shfl_xor(lo, o, 64), b = __shfl_xor(hi, o, 64);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+      }
+      const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+      if (lane_id() == 0) {
+        s_lo[wid] = lo;
+        s_hi[wid] = hi;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; ++w) {
+          lo = s_lo[w] < lo ? s_lo[w] : lo;
+          hi = s_hi[w] > hi ? s_hi[w] : hi;
+        }
+        atomicMin(&mn[i0], lo);
+        atomicMax(&mx[i0], hi);
+      }
+    }
     return;
   }
   SegCursor<int32_t> cur(base, n_inst);

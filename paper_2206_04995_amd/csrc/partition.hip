@@ -1,5 +1,5 @@
-// Intersection-free partition of S by z (paper Sec. 2.3, Alg. 1 line
-// "partition S by S.z"): every S tuple of a z goes to the dense part iff
+// Intersection-free partition of S by z (paper Sec. 2.3, Alg. 1): every S
+// tuple of a z goes to the dense part iff
 // m_z > tau for that z's instance, so the results of the two parts are
 // disjoint.  Also builds the structures of the dense part: the hot join keys
 // (y with many dense S entries) as bit rows over the dense z index, and the
@@ -89,49 +89,90 @@ __global__ void k_hot_flags(const int32_t* __restrict__ cnt_a, const int32_t* __
   }
 }
 
-// one lane per S entry: set the bit of every z of a hot row that lies in the
-// space (zmap[z] = local index in the space, or -1).  A hot row's entries
-// ascend in z, so neighbouring lanes often target the same word: the wave ORs
-// the bits of lanes with equal word addresses (shuffle-down doubling; every
-// bit a lane takes belongs to its own address) and only the first lane of each
-// run issues the atomic.  The wave walks its chunk in uniform steps so the
-// shuffles never read an inactive lane.
-__global__ void k_build_hot_bits(const int32_t* __restrict__ Ey, const int32_t* __restrict__ scol, int64_t n,
-                                 const int32_t* __restrict__ hot, const int32_t* __restrict__ hotrow,
-                                 const int32_t* __restrict__ y_base, const int32_t* __restrict__ zmap,
-                                 const int64_t* __restrict__ hb_off, const int32_t* __restrict__ row_words,
-                                 int n_inst, uint32_t* __restrict__ hb) {
-  const int lane = lane_id();
-  SegCursor<int32_t> ycur(y_base, n_inst);
-  const int64_t c0 = chunk_first();
-  if (c0 >= n) return;  // whole block
-  ycur.seed(Ey[c0 + 1] - 1);
-  const int64_t c1 = c0 + JP_CHUNK < n ? c0 + JP_CHUNK : n;
+// Bit rows of the hot keys: one lane per entry of a hot row (the rows of the
+// hot list, in list order, concatenated; hoff = their scanned lengths), which
+// sets the bit of the entry's z if it lies in the space (zmap[z] = local index
+// in the space, or -1).  Only hot rows are read, not every S entry.  Per hot
+// key, k_hot_row_info first stores what its entries share: the distance from
+// a position in the concatenation to the entry's position in S (pdel) and the
+// key's first bitmap word (rbase), so an entry costs two dependent loads
+// (scol, zmap).  A lane takes HU entries per step with every load issued
+// before any is used.  A row's entries ascend in z, so neighbouring lanes
+// often target the same word: the wave ORs the bits of lanes with equal word
+// addresses (shuffle-down doubling; every bit a lane takes belongs to its own
+// address) and only the first lane of each run issues the atomic.  Blocks
+// stride over chunks of the concatenation (its length is known only on the
+// device) and walk each chunk in wave-uniform steps, so the shuffles never
+// read an inactive lane.
+__global__ void k_hot_row_lengths(const int32_t* __restrict__ hotlist, int64_t n_hot,
+                                  const int32_t* __restrict__ sptr, int32_t* __restrict__ len) {
+  GRID_STRIDE(i, n_hot) {
+    const int32_t y = hotlist[i];
+    len[i] = sptr[y + 1] - sptr[y];
+  }
+}
+
+__global__ void k_hot_row_info(const int32_t* __restrict__ hotlist, int64_t n_hot, const int32_t* __restrict__ hoff,
+                               const int32_t* __restrict__ sptr, const int32_t* __restrict__ hotrow,
+                               const int32_t* __restrict__ y_base, int n_inst, const int64_t* __restrict__ hb_off,
+                               const int32_t* __restrict__ row_words, int32_t* __restrict__ pdel,
+                               int64_t* __restrict__ rbase) {
+  GRID_STRIDE(i, n_hot) {
+    const int32_t y = hotlist[i];
+    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, y);
+    pdel[i] = sptr[y] - hoff[i];
+    rbase[i] = hb_off[inst] + int64_t(hotrow[y]) * row_words[inst];
+  }
+}
+
+constexpr int HU = 4;  // entries per lane and step
+
+__global__ void k_build_hot_bits(const int32_t* __restrict__ hoff, int n_hot, const int32_t* __restrict__ pdel,
+                                 const int64_t* __restrict__ rbase, const int32_t* __restrict__ scol,
+                                 const int32_t* __restrict__ zmap, uint32_t* __restrict__ hb) {
+  const int lane = lane_id(), wid = threadIdx.x >> 6;
+  const int64_t total = hoff[n_hot];
   constexpr uint64_t NONE = ~uint64_t(0);
-  for (int64_t base = c0 + (threadIdx.x & ~63); base < c1; base += blockDim.x) {
-    const int64_t p = base + lane;
-    uint64_t addr = NONE;
-    uint32_t bits = 0u;
-    if (p < c1) {
-      const int32_t y = Ey[p + 1] - 1;
-      if (hot[y]) {
-        const int32_t dl = zmap[scol[p]];
-        if (dl >= 0) {
-          const int inst = ycur(y);
-          addr = uint64_t(hb_off[inst] + int64_t(hotrow[y]) * row_words[inst] + (dl >> 5));
-          bits = 1u << (dl & 31);
+  for (int64_t c0 = int64_t(blockIdx.x) * JP_CHUNK; c0 < total; c0 += int64_t(gridDim.x) * JP_CHUNK) {
+    const int64_t c1 = c0 + JP_CHUNK < total ? c0 + JP_CHUNK : total;
+    SegCursor<int32_t> hcur(hoff, n_hot);
+    hcur.seed(int32_t(c0));
+    for (int64_t base = c0 + int64_t(wid) * 64 * HU; base < c1; base += int64_t(blockDim.x) * HU) {
+      // positions past the chunk end are clamped to its last one (valid loads) and dropped below
+      int32_t ii[HU], p[HU], dl[HU];
+      int64_t rb[HU];
+#pragma unroll
+      for (int u = 0; u < HU; ++u) {
+        const int64_t q = base + u * 64 + lane;
+        const int32_t qc = int32_t(q < c1 ? q : c1 - 1);
+        ii[u] = hcur(qc);
+        p[u] = qc;
+      }
+#pragma unroll
+      for (int u = 0; u < HU; ++u) {
+        p[u] += pdel[ii[u]];
+        rb[u] = rbase[ii[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < HU; ++u) dl[u] = scol[p[u]];
+#pragma unroll
+      for (int u = 0; u < HU; ++u) dl[u] = zmap[dl[u]];
+#pragma unroll
+      for (int u = 0; u < HU; ++u) {
+        const bool in = base + u * 64 + lane < c1 && dl[u] >= 0;
+        if (ballot(in) == 0) continue;  // nothing in the space among these 64 (wave-uniform)
+        uint64_t addr = in ? uint64_t(rb[u] + (dl[u] >> 5)) : NONE;
+        uint32_t bits = in ? 1u << (dl[u] & 31) : 0u;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint64_t a2 = __shfl_down(addr, o, 64);
+          const uint32_t b2 = __shfl_down(bits, o, 64);
+          if (lane + o < 64 && a2 == addr) bits |= b2;
         }
+        const uint64_t ap = __shfl_up(addr, 1, 64);
+        if (addr != NONE && (lane == 0 || ap != addr)) atomicOr(&hb[addr], bits);
       }
     }
-    if (ballot(addr != NONE) == 0) continue;  // no hot entry among these 64 (wave-uniform)
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint64_t a2 = __shfl_down(addr, o, 64);
-      const uint32_t b2 = __shfl_down(bits, o, 64);
-      if (lane + o < 64 && a2 == addr) bits |= b2;
-    }
-    const uint64_t ap = __shfl_up(addr, 1, 64);
-    if (addr != NONE && (lane == 0 || ap != addr)) atomicOr(&hb[addr], bits);
   }
 }
 
@@ -155,17 +196,39 @@ constexpr int FR_WTILE = 64 * FR_IT;
 constexpr int FR_TILE = FR_NT * FR_IT;
 enum FilterMode { FILTER_SPARSE = 0, FILTER_COLD = 1 };
 
-// One bit per z of the filter's z test (kept iff set): bit z of zbit[z / 64].
-// In bits the test of a random z reads a table 32 times smaller than the
-// int32 one, which mostly stays in cache.
+// One bit per z of the filter's z test (kept iff set).  In bits the test of a
+// random z reads a table 32 times smaller than the int32 one, which mostly
+// stays in cache.
+//   FILTER_SPARSE  bit z of the 64-bit word zbit[z / 64];
+//   FILTER_COLD    bit z % 32 of the low half of zbit[z / 32], whose high half
+//                  holds the word's rank base r: every z of the word in the
+//                  space has zsel[z] = r + (bits of the word below z), or r is
+//                  -1 (the local indices restart inside the word, at an
+//                  instance boundary) and zsel[z] is read instead.  A kept
+//                  entry's local index then costs no gather from zsel.
 template <int MODE>
 __global__ void k_filter_bits(const int32_t* __restrict__ zsel, int64_t n_z, uint64_t* __restrict__ zbit) {
+  const int lane = lane_id();
   for (int64_t base = (int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63)); base < n_z;
        base += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t z = base + lane_id();
-    const bool k = z < n_z && (MODE == FILTER_SPARSE ? zsel[z] == 0 : zsel[z] >= 0);
+    const int64_t z = base + lane;
+    const int32_t v = z < n_z ? zsel[z] : -1;
+    const bool k = z < n_z && (MODE == FILTER_SPARSE ? v == 0 : v >= 0);
     const uint64_t b = ballot(k);
-    if (lane_id() == 0) zbit[base >> 6] = b;
+    if (MODE == FILTER_SPARSE) {
+      if (lane == 0) zbit[base >> 6] = b;
+    } else {
+      const int half = lane >> 5;
+      const uint32_t bits = uint32_t(b >> (32 * half));
+      const int32_t pred = v - __popc(bits & ((1u << (lane & 31)) - 1u));  // the base this z implies
+      const int first = bits ? 32 * half + __ffs(bits) - 1 : lane;
+      const int32_t p0 = __shfl(pred, first, 64);
+      const uint64_t bad = ballot(k && pred != p0);
+      const bool ok = uint32_t(bad >> (32 * half)) == 0u;
+      const int32_t r = bits == 0u ? 0 : (ok ? p0 : -1);
+      if ((lane & 31) == 0 && base + 32 * half < n_z)  // the word exists ((n_z + 31) / 32 words)
+        zbit[(base >> 5) + half] = uint64_t(bits) | (uint64_t(uint32_t(r)) << 32);
+    }
   }
 }
 
@@ -187,8 +250,7 @@ __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict
   const int64_t tile = s_tile;
   const int64_t w0 = tile * FR_TILE + int64_t(wid) * FR_WTILE;
   // every load first, at clamped (valid) indices, so the gathers of all rows are in flight together
-  int32_t val[FR_IT], row1[FR_IT];  // row1: row + 1 of a row's first entry, else 0
-  int32_t z[FR_IT], e1[FR_IT], e0[FR_IT];
+  int32_t z[FR_IT], e1[FR_IT];
   const int32_t ew = Ey[w0 < n ? w0 : n - 1];  // the row count before the wave's first entry
 #pragma unroll
   for (int j = 0; j < FR_IT; ++j) {
@@ -197,34 +259,55 @@ __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict
     e1[j] = Ey[i + 1];
     z[j] = scol[i];
   }
-  // Ey[i] of each entry is Ey[i + 1] of the one before it (a lane shift)
+  // Ey[i] of each entry is Ey[i + 1] of the one before it (a lane shift); bit
+  // j of `first`: entry j of this lane starts its row (row Ey[i + 1] - 1)
+  uint32_t first = 0;
 #pragma unroll
   for (int j = 0; j < FR_IT; ++j) {
     const int32_t up = __shfl_up(e1[j], 1, 64);
-    e0[j] = lane > 0 ? up : (j > 0 ? __builtin_amdgcn_readlane(e1[j > 0 ? j - 1 : 0], 63) : ew);
+    const int32_t e0 = lane > 0 ? up : (j > 0 ? __builtin_amdgcn_readlane(e1[j > 0 ? j - 1 : 0], 63) : ew);
+    if (w0 + j * 64 + lane < n && e1[j] != e0) first |= 1u << j;
   }
-  // the bitmap read as 32-bit words (little-endian: word z / 32 holds bit z % 32)
+  // the bitmap words as 32-bit words (sparse: the 64-bit words read
+  // little-endian, word z / 32 holds bit z % 32; cold: the low halves of the
+  // packed words) and the hot flags of the rows
   const uint32_t* zb32 = reinterpret_cast<const uint32_t*>(zbit);
+  constexpr int ZW = MODE == FILTER_COLD ? 2 : 1;  // 32-bit words per 32 z
   uint32_t zb[FR_IT];
   int32_t h[FR_IT];
 #pragma unroll
   for (int j = 0; j < FR_IT; ++j) {
-    zb[j] = zb32[z[j] >> 5];
+    zb[j] = zb32[ZW * (z[j] >> 5)];
     h[j] = MODE == FILTER_COLD ? hot[e1[j] - 1] : 0;
   }
   uint32_t keep = 0;
   int cnt = 0;
 #pragma unroll
   for (int j = 0; j < FR_IT; ++j) {
-    const bool in = w0 + j * 64 + lane < n;
-    const bool k = in && ((zb[j] >> (z[j] & 31)) & 1u) && !h[j];
-    row1[j] = (in && e1[j] != e0[j]) ? e1[j] : 0;
+    const bool k = w0 + j * 64 + lane < n && ((zb[j] >> (z[j] & 31)) & 1u) && !h[j];
     if (k) keep |= 1u << j;
     cnt += __popcll(ballot(k));
   }
-  // values of the kept entries: z itself, or its local index (a gather for kept entries only)
+  // values of the kept entries: z itself, or its local index in the space from
+  // the word's rank base (the high half, in the same cache line; a gather from
+  // zsel only where the word has none)
+  int32_t val[FR_IT];
 #pragma unroll
-  for (int j = 0; j < FR_IT; ++j) val[j] = MODE == FILTER_SPARSE ? z[j] : (((keep >> j) & 1u) ? zsel[z[j]] : 0);
+  for (int j = 0; j < FR_IT; ++j) {
+    if (MODE == FILTER_SPARSE) {
+      val[j] = z[j];
+    } else {
+      val[j] = ((keep >> j) & 1u) ? int32_t(zb32[2 * (z[j] >> 5) + 1]) : 0;
+    }
+  }
+  if (MODE == FILTER_COLD) {
+#pragma unroll
+    for (int j = 0; j < FR_IT; ++j) {
+      if ((keep >> j) & 1u) {
+        val[j] = val[j] >= 0 ? val[j] + __popc(zb[j] & ((1u << (z[j] & 31)) - 1u)) : zsel[z[j]];
+      }
+    }
+  }
   if (lane == 0) s_wsum[wid] = cnt;
   __syncthreads();
   int32_t woff = 0, btot = 0;
@@ -245,7 +328,7 @@ __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict
     const uint64_t b = ballot(k);
     const int64_t before = run + __popcll(b & ltm);
     if (k) out[before] = val[j];
-    if (row1[j]) rowptr[row1[j] - 1] = int32_t(before);
+    if ((first >> j) & 1u) rowptr[e1[j] - 1] = int32_t(before);
     run += __popcll(b);
   }
   if (tile == ntiles - 1 && threadIdx.x == 0) {
@@ -516,7 +599,7 @@ void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, c
     fill_i32(total, 1, 0, s);
     return;
   }
-  const int64_t nw = (n_z + 63) / 64;
+  const int64_t nw = cold ? (n_z + 31) / 32 : (n_z + 63) / 64;  // cold: packed 32-bit words with rank bases
   uint64_t* zbit = a.alloc<uint64_t>(std::max<int64_t>(nw, 1), s);
   const int gb = int(std::min<int64_t>((n_z + NT - 1) / NT, 1 << 16));
   if (cold) hipLaunchKernelGGL(k_filter_bits<FILTER_COLD>, dim3(gb > 0 ? gb : 1), dim3(NT), 0, s, zsel, n_z, zbit);
@@ -556,13 +639,29 @@ void hot_flags(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR, in
   JP_LAUNCH_CHECK();
 }
 
-void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* hotrow,
-                    const int32_t* y_base, const int32_t* zmap, const int64_t* hb_off, const int32_t* row_words,
-                    int n_inst, uint32_t* hb, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_build_hot_bits, dim3(chunk_grid(n)), dim3(NT), 0, s, Ey, scol, n, hot, hotrow, y_base, zmap, hb_off,
-                     row_words, n_inst, hb);
+void build_hot_bits(const int32_t* hotlist, int64_t n_hot, const int32_t* sptr, const int32_t* scol, int64_t n_s,
+                    const int32_t* hotrow, const int32_t* y_base, const int32_t* zmap, const int64_t* hb_off,
+                    const int32_t* row_words, int n_inst, uint32_t* hb, hipStream_t s, Arena& a) {
+  if (n_hot <= 0 || n_s <= 0) return;
+  int32_t* len = a.alloc<int32_t>(n_hot, s);
+  int32_t* hoff = a.alloc<int32_t>(n_hot + 1, s);
+  int32_t* pdel = a.alloc<int32_t>(n_hot, s);
+  int64_t* rbase = a.alloc<int64_t>(n_hot, s);
+  hipLaunchKernelGGL(k_hot_row_lengths, dim3(grid(n_hot)), dim3(NT), 0, s, hotlist, n_hot, sptr, len);
   JP_LAUNCH_CHECK();
+  scan_excl_i32(len, hoff, n_hot, s, a);
+  hipLaunchKernelGGL(k_hot_row_info, dim3(grid(n_hot)), dim3(NT), 0, s, hotlist, n_hot, hoff, sptr, hotrow, y_base,
+                     n_inst, hb_off, row_words, pdel, rbase);
+  JP_LAUNCH_CHECK();
+  // the hot rows hold at most all n_s entries; enough blocks to fill the chip,
+  // each striding over chunks of the concatenated rows
+  const int blocks = std::min(chunk_grid(n_s), 2048);
+  hipLaunchKernelGGL(k_build_hot_bits, dim3(blocks), dim3(NT), 0, s, hoff, int(n_hot), pdel, rbase, scol, zmap, hb);
+  JP_LAUNCH_CHECK();
+  a.give_back(rbase, s);
+  a.give_back(pdel, s);
+  a.give_back(hoff, s);
+  a.give_back(len, s);
 }
 
 void space_flags(const int32_t* scol, int64_t n, const int32_t* zmap, int32_t* flag, hipStream_t s) {

@@ -283,10 +283,16 @@ void Plan::map(hipStream_t s) {
     scatter_z(sz, sy, NS, d_sbase, n, dkz, zmin, dky, ymin, Ezk, Czk, yk, yp, s);
     JP_HIP(hipMemcpyAsync(d_counts + 0, Ezk + K, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   } else {
-    // S sorted by (instance, z): z ids, m_z
-    make_keys(sz, NS, d_sbase, n, dkz, zmin, k1, v1, sy, s);  // S.y rides along
+    // S sorted by (instance, z): z ids, m_z.  The sort's first pass makes the
+    // z keys as it reads S.z; S.y rides along.
     const SortSegments sseg_z{n, d_sbase, dkz, h_sbase};
-    bool alt = radix_sort_pairs(k1, v1, k2, v2, NS, n > 1 ? local_bits(koff_z) : zbits, s, T, &sseg_z);
+    const int zbits_sort = n > 1 ? local_bits(koff_z) : zbits;
+    bool alt = false;
+    if (radix_passes(NS, zbits_sort) > 0) {
+      alt = radix_sort_raw(sz, sy, zmin, k1, v1, k2, v2, NS, zbits_sort, s, T, sseg_z);
+    } else {
+      make_keys(sz, NS, d_sbase, n, dkz, zmin, k1, v1, sy, s);
+    }
     uint32_t *zk = alt ? k2 : k1, *zp = alt ? v2 : v1;
     // z ids of the sorted positions go straight into the y sort's input, with
     // the carried S.y as its keys
@@ -654,7 +660,7 @@ void Plan::build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a,
   d.NHb = hb_words;
   d.hb = A.alloc<uint32_t>(std::max<int64_t>(hb_words, 4), s);
   fill_u32(d.hb, hb_words, 0u, s);
-  build_hot_bits(Ey, scol, NS, hot, d.hotrow, y_base, zmap, d.d_hboff, d.d_roww, n, d.hb, s);
+  build_hot_bits(hotlist, n_hot, sptr, scol, NS, d.hotrow, y_base, zmap, d.d_hboff, d.d_roww, n, d.hb, s, T);
 
   // cold entries: CSR by y over the space's local index (ascending in each row)
   int32_t* ccol_y = T.alloc<int32_t>(NSa, s);

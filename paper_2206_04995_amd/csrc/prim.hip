@@ -2,6 +2,7 @@
 // wave-ballot ranking and LDS-staged scatter, segmented min/max, fills.
 #include <climits>
 
+#include "../../include/jp.h"
 #include "common.h"
 #include "prim.h"
 
@@ -147,6 +148,11 @@ constexpr int RS_IT = 16;
 constexpr int RS_TILE = RS_NT * RS_IT;  // 4096 keys per block
 constexpr int RS_WAVES = RS_NT / 64;
 constexpr int RS_WTILE = RS_TILE / RS_WAVES;  // 1024 keys per wave
+// Digits are at most 8 bits wide.  (9-bit digits, two passes instead of
+// three for a 17-bit range, were slower: with 4096-key tiles a 512-way
+// scatter writes runs of about 8 keys.)
+constexpr int RS_MAXBITS = 8;
+constexpr int RS_MAXD = 1 << RS_MAXBITS;
 
 // Tiles of a segmented sort: segment i (elements [ebase[i], ebase[i+1]), keys
 // in [koff[i], koff[i] + 2^bits)) owns tiles [toff[i], toff[i+1]), so no tile
@@ -159,6 +165,7 @@ struct TileMap {
   const int32_t* ebase;  // [n_seg + 1]
   const int64_t* koff;   // [n_seg] (null: 0)
   int n_seg;             // 0: one segment [0, n)
+  const int32_t* mn;     // raw input (first pass only): key = koff + value - mn of the segment
 };
 
 struct Tile {
@@ -166,6 +173,7 @@ struct Tile {
   int64_t hbase;    // histogram index of digit 0
   int stride;       // histogram distance of consecutive digits (tiles of the segment)
   int64_t koff;     // subtracted from the keys
+  int64_t radd;     // raw input: added to a value to give its key
 };
 
 // whole wave, uniform control flow
@@ -178,6 +186,7 @@ __device__ __forceinline__ Tile tile_of(const TileMap& m, int64_t n, int nd) {
     t.hbase = b;
     t.stride = int(gridDim.x);
     t.koff = 0;
+    t.radd = m.mn ? (m.koff ? m.koff[0] : 0) - int64_t(m.mn[0]) : 0;
     return t;
   }
   const int sg = wave_find_inst<int32_t>(m.toff, m.n_seg, b);
@@ -188,7 +197,14 @@ __device__ __forceinline__ Tile tile_of(const TileMap& m, int64_t n, int nd) {
   t.hbase = int64_t(t0) * nd + (b - t0);
   t.stride = nt;
   t.koff = m.koff ? m.koff[sg] : 0;
+  t.radd = m.mn ? t.koff - int64_t(m.mn[sg]) : 0;
   return t;
+}
+
+// a loaded element's key: raw values are moved into the segment's key range
+template <bool RAW>
+__device__ __forceinline__ uint32_t key_in(uint32_t k, const Tile& t) {
+  return RAW ? uint32_t(int64_t(int32_t(k)) + t.radd) : k;
 }
 
 __device__ __forceinline__ uint32_t digit_of(uint32_t k, const Tile& t, int shift, uint32_t mask) {
@@ -207,22 +223,23 @@ __device__ __forceinline__ uint64_t digit_match(uint32_t d, bool valid, int nbit
   return m;
 }
 
+template <bool RAW>
 __global__ void __launch_bounds__(RS_NT) k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
                                                        int shift, int nbits, int* __restrict__ hist,
                                                        TileMap m) {
-  __shared__ int cnt[RS_WAVES][256];
+  __shared__ int cnt[RS_WAVES][RS_MAXD];
   const int wid = threadIdx.x >> 6;
   const int nd = 1 << nbits;
   const uint32_t mask = uint32_t(nd - 1);
   const Tile tl = tile_of(m, n, nd);
-  for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&cnt[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < RS_WAVES * RS_MAXD; i += RS_NT) (&cnt[0][0])[i] = 0;
   __syncthreads();
   // all of a thread's loads first (clamped, so they need no branch), then the LDS counts
   uint32_t kk[RS_IT];
 #pragma unroll
   for (int j = 0; j < RS_IT; ++j) {
     const int64_t i = tl.lo + j * RS_NT + threadIdx.x;
-    kk[j] = keys[i < tl.hi ? i : tl.hi - 1];
+    kk[j] = key_in<RAW>(keys[i < tl.hi ? i : tl.hi - 1], tl);
   }
 #pragma unroll
   for (int j = 0; j < RS_IT; ++j)
@@ -242,7 +259,7 @@ __global__ void k_tile_counts(const int32_t* __restrict__ ebase, int n_seg, int3
   if (i < n_seg) cnt[i] = int32_t((int64_t(ebase[i + 1]) - ebase[i] + RS_TILE - 1) / RS_TILE);
 }
 
-template <bool HAS_V>
+template <bool HAS_V, bool RAW>
 __global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restrict__ kin,
                                                           const uint32_t* __restrict__ vin,
                                                           uint32_t* __restrict__ kout,
@@ -251,17 +268,18 @@ __global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restr
                                                           const int* __restrict__ offs, TileMap m) {
   __shared__ uint32_t s_k[RS_TILE];
   __shared__ uint32_t s_v[HAS_V ? RS_TILE : 1];
-  __shared__ int wcnt[RS_WAVES][256];
-  __shared__ int dstart[256];
-  __shared__ int goff[256];
+  __shared__ int wcnt[RS_WAVES][RS_MAXD];
+  __shared__ int dstart[RS_MAXD];
+  __shared__ int goff[RS_MAXD];
   __shared__ int scan_lds[RS_NT / 64];
+  static_assert(RS_MAXD <= RS_NT, "one thread per digit in the digit scan");
 
   const int lane = lane_id(), wid = threadIdx.x >> 6;
   const int nd = 1 << nbits;
   const uint32_t mask = uint32_t(nd - 1);
   const uint64_t ltm = lanemask_lt();
   const Tile tl = tile_of(m, n, nd);
-  for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < RS_WAVES * RS_MAXD; i += RS_NT) (&wcnt[0][0])[i] = 0;
   __syncthreads();
 
   const int64_t wbase = tl.lo + int64_t(wid) * RS_WTILE;
@@ -272,6 +290,13 @@ __global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restr
     const bool valid = i < tl.hi;
     key[j] = valid ? kin[i] : 0u;
     if (HAS_V) val[j] = valid ? vin[i] : 0u;
+  }
+  // raw values become keys only once every load is in flight (converting each
+  // as it arrives would make the loads wait for one another); lanes past the
+  // tile end are never ranked, whatever their key
+  if (RAW) {
+#pragma unroll
+    for (int j = 0; j < RS_IT; ++j) key[j] = key_in<RAW>(key[j], tl);
   }
   // Stable ranks inside the wave: per row, the group leader of each digit adds
   // the group's size to the wave's counter and gets the count before it.  The
@@ -445,14 +470,51 @@ void scan_excl_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s, Ar
   scan_impl<int64_t, int64_t>(in, out, n, s, a);
 }
 
-int radix_passes(int64_t n, int bits) { return (n <= 1 || bits <= 0) ? 0 : (bits + 7) / 8; }
+int radix_passes(int64_t n, int bits) {
+  return (n <= 1 || bits <= 0) ? 0 : (bits + RS_MAXBITS - 1) / RS_MAXBITS;
+}
 
-bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int64_t n, int bits,
-                      hipStream_t s, Arena& a, const SortSegments* seg) {
+namespace {
+
+void launch_hist(bool raw, int nblocks, const uint32_t* ki, int64_t n, int shift, int w, int* hist,
+                 const TileMap& m, hipStream_t s) {
+  if (raw)
+    hipLaunchKernelGGL((k_radix_hist<true>), dim3(nblocks), dim3(RS_NT), 0, s, ki, n, shift, w, hist, m);
+  else
+    hipLaunchKernelGGL((k_radix_hist<false>), dim3(nblocks), dim3(RS_NT), 0, s, ki, n, shift, w, hist, m);
+  JP_LAUNCH_CHECK();
+}
+
+void launch_scatter(bool raw, bool has_v, int nblocks, const uint32_t* ki, const uint32_t* vi, uint32_t* ko,
+                    uint32_t* vo, int64_t n, int shift, int w, const int* offs, const TileMap& m, hipStream_t s) {
+  if (!has_v) {
+    vi = nullptr;
+    vo = nullptr;
+  }
+  if (raw && has_v)
+    hipLaunchKernelGGL((k_radix_scatter<true, true>), dim3(nblocks), dim3(RS_NT), 0, s, ki, vi, ko, vo, n,
+                       shift, w, offs, m);
+  else if (raw)
+    hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(nblocks), dim3(RS_NT), 0, s, ki, vi, ko, vo, n,
+                       shift, w, offs, m);
+  else if (has_v)
+    hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3(nblocks), dim3(RS_NT), 0, s, ki, vi, ko, vo, n,
+                       shift, w, offs, m);
+  else
+    hipLaunchKernelGGL((k_radix_scatter<false, false>), dim3(nblocks), dim3(RS_NT), 0, s, ki, vi, ko, vo, n,
+                       shift, w, offs, m);
+  JP_LAUNCH_CHECK();
+}
+
+// The passes of a sort whose first pass reads (k0, v0): (k, v) itself, or raw
+// values moved into their segments' key ranges by raw_mn.
+bool radix_impl(const uint32_t* k0, const uint32_t* v0, const int32_t* raw_mn, uint32_t* k, uint32_t* v,
+                uint32_t* kt, uint32_t* vt, int64_t n, int bits, hipStream_t s, Arena& a,
+                const SortSegments* seg) {
   if (n <= 1 || bits <= 0) return false;
   int passes = radix_passes(n, bits);
   int width = (bits + passes - 1) / passes;
-  TileMap m{nullptr, nullptr, nullptr, 0};
+  TileMap m{nullptr, nullptr, raw_mn && seg ? seg->d_koff : nullptr, 0, raw_mn};
   int nblocks = int((n + RS_TILE - 1) / RS_TILE);
   int32_t* toff = nullptr;
   if (seg && seg->n_seg > 1) {
@@ -466,35 +528,51 @@ bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int6
     JP_LAUNCH_CHECK();
     scan_excl_i32(tc, toff, ns, s, a);
     a.give_back(tc, s);
-    m = TileMap{toff, seg->d_ebase, seg->d_koff, ns};
+    m = TileMap{toff, seg->d_ebase, seg->d_koff, ns, raw_mn};
   }
   if (nblocks == 0) return false;
   int64_t hsz = int64_t(1 << width) * nblocks;
   int* hist = a.alloc<int>(hsz, s);
   int* offs = a.alloc<int>(hsz + 1, s);
-  uint32_t *ki = k, *vi = v, *ko = kt, *vo = vt;
+  const uint32_t *ki = k0, *vi = v0;
+  uint32_t *ko = kt, *vo = vt;
   int shift = 0;
   for (int p = 0; p < passes; ++p) {
     int w = width;
     if (shift + w > bits) w = bits - shift;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(RS_NT), 0, s, (const uint32_t*)ki, n, shift, w, hist, m);
-    JP_LAUNCH_CHECK();
+    const bool raw = m.mn != nullptr;
+    launch_hist(raw, nblocks, ki, n, shift, w, hist, m, s);
     scan_impl<int, int>(hist, offs, int64_t(1 << w) * nblocks, s, a);
-    if (v)
-      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(nblocks), dim3(RS_NT), 0, s, (const uint32_t*)ki,
-                         (const uint32_t*)vi, ko, vo, n, shift, w, (const int*)offs, m);
-    else
-      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblocks), dim3(RS_NT), 0, s, (const uint32_t*)ki,
-                         (const uint32_t*)nullptr, ko, (uint32_t*)nullptr, n, shift, w, (const int*)offs, m);
-    JP_LAUNCH_CHECK();
-    std::swap(ki, ko);
-    std::swap(vi, vo);
+    launch_scatter(raw, v != nullptr, nblocks, ki, vi, ko, vo, n, shift, w, offs, m, s);
+    m.mn = nullptr;
+    // the pass wrote (ko, vo); the next one writes the other pair
+    uint32_t* nk = ko == kt ? k : kt;
+    uint32_t* nv = ko == kt ? v : vt;
+    ki = ko;
+    vi = vo;
+    ko = nk;
+    vo = nv;
     shift += w;
   }
   a.give_back(offs, s);
   a.give_back(hist, s);
   if (toff) a.give_back(toff, s);
   return ki == kt;
+}
+
+}  // namespace
+
+bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int64_t n, int bits,
+                      hipStream_t s, Arena& a, const SortSegments* seg) {
+  return radix_impl(k, v, nullptr, k, v, kt, vt, n, bits, s, a, seg);
+}
+
+bool radix_sort_raw(const int32_t* raw, const int32_t* raw_v, const int32_t* mn, uint32_t* k, uint32_t* v,
+                    uint32_t* kt, uint32_t* vt, int64_t n, int bits, hipStream_t s, Arena& a,
+                    const SortSegments& seg) {
+  if (radix_passes(n, bits) == 0) throw Error(JP_EINVAL, "radix_sort_raw needs at least one pass");
+  return radix_impl(reinterpret_cast<const uint32_t*>(raw), reinterpret_cast<const uint32_t*>(raw_v), mn, k, v, kt,
+                    vt, n, bits, s, a, &seg);
 }
 
 void seg_minmax(const int32_t* v, int64_t n, const int32_t* base, int n_seg, int32_t* mn, int32_t* mx,

@@ -142,10 +142,11 @@ void hot_histogram(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR
 // hot[y] = 1 iff dR[y] > 0 and the count of y in the space >= theta[inst(y)]
 void hot_flags(const int32_t* cnt_a, const int32_t* cnt_b, const int32_t* dR, int64_t n_y, const int32_t* y_base,
                int n_inst, const int64_t* theta, int32_t* hot, hipStream_t s);
-// hot row bit sets over the space's local index (one thread per S entry)
-void build_hot_bits(const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* hot, const int32_t* hotrow,
-                    const int32_t* y_base, const int32_t* zmap, const int64_t* hb_off, const int32_t* row_words,
-                    int n_inst, uint32_t* hb, hipStream_t s);
+// hot row bit sets over the space's local index (one lane per entry of a hot row;
+// hotlist holds the n_hot hot keys, sptr is the CSR of S by y)
+void build_hot_bits(const int32_t* hotlist, int64_t n_hot, const int32_t* sptr, const int32_t* scol, int64_t n_s,
+                    const int32_t* hotrow, const int32_t* y_base, const int32_t* zmap, const int64_t* hb_off,
+                    const int32_t* row_words, int n_inst, uint32_t* hb, hipStream_t s, Arena& a);
 // per S entry: in the space
 void space_flags(const int32_t* scol, int64_t n, const int32_t* zmap, int32_t* flag, hipStream_t s);
 // space 0: all dense z
