@@ -268,44 +268,79 @@ __global__ void __launch_bounds__(SJ_NT) k_semijoin_compact(SemiJoinIn in, uint3
   __syncthreads();
   const int64_t tile = s_tile;
   const int64_t w0 = tile * SJ_TILE + int64_t(wid) * SJ_WTILE;
-  SegCursor<int32_t> cur(in.ebase, in.n_inst);
-  if (w0 < in.n) cur.seed(int32_t(w0));
-  // columns and instances of all rows first (loads at clamped, valid indices), then the y lookups
-  int32_t xr[SJ_IT], yr[SJ_IT], ins[SJ_IT];
-  uint32_t starts = 0;  // bit j: this lane's position of row j starts an instance
-#pragma unroll
-  for (int j = 0; j < SJ_IT; ++j) {
-    const int64_t i = w0 + j * 64 + lane;
-    const int64_t ic = i < in.n ? i : in.n - 1;
-    xr[j] = in.rx[ic];
-    yr[j] = in.ry[ic];
-    ins[j] = 0;
-    if (i < in.n) {
-      ins[j] = cur(int32_t(i));
-      if (i == cur.lo) starts |= 1u << j;
-    }
-  }
+  const int64_t wend = w0 + SJ_WTILE < in.n ? w0 + SJ_WTILE : in.n;
+  int32_t xr[SJ_IT], yr[SJ_IT];
   uint32_t xv[SJ_IT];
   int32_t yid[SJ_IT];
+  uint32_t starts = 0;  // bit j: this lane's position of row j starts an instance
   int cnt = 0;
+  // the instance of the wave's first position (wave-uniform)
+  const int i0 = DIRECT && w0 < in.n ? wave_find_inst<int32_t>(in.ebase, in.n_inst, int32_t(w0)) : 0;
+  if (DIRECT && w0 < in.n && int64_t(in.ebase[i0 + 1]) >= wend) {
+    // the wave's positions lie in one instance (all but the waves at instance
+    // bounds): its layout constants are wave-uniform, and every load (columns,
+    // then the y lookups) is issued before any is used
+    const int64_t k0 = in.koff_y[i0], range = in.koff_y[i0 + 1] - k0;
+    const int64_t ymn = in.ymin[i0], xoff = in.koff_x[i0] - int64_t(in.xmin[i0]);
+    const int64_t st = in.ebase[i0];
 #pragma unroll
-  for (int j = 0; j < SJ_IT; ++j) {
-    const int inst = ins[j];
-    int32_t id = -1;
-    if (DIRECT) {
-      const int64_t rel = int64_t(yr[j]) - int64_t(in.ymin[inst]);
-      const int64_t k0 = in.koff_y[inst];
-      const bool ok = rel >= 0 && rel < in.koff_y[inst + 1] - k0;
-      const int32_t t = in.table[ok ? k0 + rel : 0];
-      id = ok ? t : -1;
-    } else {
-      const int64_t lo = in.y_base[inst], hi = in.y_base[inst + 1];
-      const int64_t pos = lower_bound_dev<int32_t>(in.vals_y, lo, hi, yr[j]);
-      if (pos < hi && in.vals_y[pos] == yr[j]) id = int32_t(pos);
+    for (int j = 0; j < SJ_IT; ++j) {
+      const int64_t i = w0 + j * 64 + lane;
+      const int64_t ic = i < wend ? i : wend - 1;
+      xr[j] = in.rx[ic];
+      yr[j] = in.ry[ic];
+      if (i == st) starts |= 1u << j;
     }
-    yid[j] = w0 + j * 64 + lane < in.n ? id : -1;
-    xv[j] = uint32_t(in.koff_x[inst] + (int64_t(xr[j]) - int64_t(in.xmin[inst])));
-    cnt += __popcll(ballot(yid[j] >= 0));
+    int32_t t[SJ_IT];
+#pragma unroll
+    for (int j = 0; j < SJ_IT; ++j) {
+      const int64_t rel = int64_t(yr[j]) - ymn;
+      t[j] = in.table[rel >= 0 && rel < range ? k0 + rel : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < SJ_IT; ++j) {
+      const int64_t rel = int64_t(yr[j]) - ymn;
+      const bool ok = rel >= 0 && rel < range && w0 + j * 64 + lane < wend;
+      yid[j] = ok ? t[j] : -1;
+      xv[j] = uint32_t(xoff + int64_t(xr[j]));
+      cnt += __popcll(ballot(yid[j] >= 0));
+    }
+  } else {
+    SegCursor<int32_t> cur(in.ebase, in.n_inst);
+    if (w0 < in.n) cur.seed(int32_t(w0));
+    // columns and instances of all rows first (loads at clamped, valid indices), then the y lookups
+    int32_t ins[SJ_IT];
+#pragma unroll
+    for (int j = 0; j < SJ_IT; ++j) {
+      const int64_t i = w0 + j * 64 + lane;
+      const int64_t ic = i < in.n ? i : in.n - 1;
+      xr[j] = in.rx[ic];
+      yr[j] = in.ry[ic];
+      ins[j] = 0;
+      if (i < in.n) {
+        ins[j] = cur(int32_t(i));
+        if (i == cur.lo) starts |= 1u << j;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SJ_IT; ++j) {
+      const int inst = ins[j];
+      int32_t id = -1;
+      if (DIRECT) {
+        const int64_t rel = int64_t(yr[j]) - int64_t(in.ymin[inst]);
+        const int64_t k0 = in.koff_y[inst];
+        const bool ok = rel >= 0 && rel < in.koff_y[inst + 1] - k0;
+        const int32_t t = in.table[ok ? k0 + rel : 0];
+        id = ok ? t : -1;
+      } else {
+        const int64_t lo = in.y_base[inst], hi = in.y_base[inst + 1];
+        const int64_t pos = lower_bound_dev<int32_t>(in.vals_y, lo, hi, yr[j]);
+        if (pos < hi && in.vals_y[pos] == yr[j]) id = int32_t(pos);
+      }
+      yid[j] = w0 + j * 64 + lane < in.n ? id : -1;
+      xv[j] = uint32_t(in.koff_x[inst] + (int64_t(xr[j]) - int64_t(in.xmin[inst])));
+      cnt += __popcll(ballot(yid[j] >= 0));
+    }
   }
   if (lane == 0) s_wsum[wid] = cnt;
   __syncthreads();
