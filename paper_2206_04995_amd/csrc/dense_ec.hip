@@ -43,6 +43,13 @@ constexpr int QW = DW_WORDS / 4;          // uint4 per window slice
 // compiler not to move them past each other.
 __device__ __forceinline__ void lds_fence() { __builtin_amdgcn_wave_barrier(); }
 
+// uint4 columns (64 lanes x 4 words = 256 words each) of the window starting
+// at z index wstart that hold dense z of a range of zd dense z (wstart < zd)
+__device__ __forceinline__ int win_cols(int zd, int32_t wstart) {
+  const int words = min(DW_WORDS, (zd - wstart + 31) / 32);
+  return (words + 255) / 256;
+}
+
 __device__ __forceinline__ int popc4(uint4 v) { return __popc(v.x) + __popc(v.y) + __popc(v.z) + __popc(v.w); }
 
 __device__ __forceinline__ void or4(uint4& a, const uint4 b) {
@@ -77,6 +84,35 @@ __device__ __forceinline__ void hot_or(uint4 (&acc)[QN], int code, bool staged, 
     const uint4* s0 = reinterpret_cast<const uint4*>(hbase + int64_t(k0) * rw);
 #pragma unroll
     for (int q = 0; q < QN; ++q) or4(acc[q], s0[q * 64 + lane]);
+  }
+}
+
+// hot_or over the first qa of the QN uint4 columns only (a window that the
+// dense range ends inside: the other columns hold padding words)
+template <int QN>
+__device__ __forceinline__ void hot_or_part(uint4 (&acc)[QN], int code, bool staged, int t_eff,
+                                            const uint4 (*stage)[QW], const uint32_t* hbase, int64_t rw, int qa) {
+  const int lane = lane_id();
+  uint64_t hm = ballot(code >= 0);
+  const uint64_t sm = ballot(code >= 0 && staged && code < t_eff);
+  uint64_t m = sm;
+  while (m) {
+    const int l = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const int k = __builtin_amdgcn_readlane(code, l);
+#pragma unroll
+    for (int q = 0; q < QN; ++q)
+      if (q < qa) or4(acc[q], stage[k][q * 64 + lane]);
+  }
+  m = hm & ~sm;
+  while (m) {
+    const int l0 = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    const int k0 = __builtin_amdgcn_readlane(code, l0);
+    const uint4* s0 = reinterpret_cast<const uint4*>(hbase + int64_t(k0) * rw);
+#pragma unroll
+    for (int q = 0; q < QN; ++q)
+      if (q < qa) or4(acc[q], s0[q * 64 + lane]);
   }
 }
 
@@ -186,8 +222,10 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
     const int32_t wstart = w * DW_BITS;
     __syncthreads();
     if (w < nwin0) {
-      for (int i = threadIdx.x; i < t_eff * QW; i += NT) {
-        const int k = i / QW, q = i - k * QW;
+      // only the uint4 columns that hold dense z of the first instance
+      const int qw0 = win_cols(zd0, wstart) * 64;
+      for (int i = threadIdx.x; i < t_eff * qw0; i += NT) {
+        const int k = i / qw0, q = i - k * qw0;
         stage[k][q] = reinterpret_cast<const uint4*>(hb0 + int64_t(k) * rw0 + int64_t(w) * DW_WORDS)[q];
       }
     }
@@ -213,6 +251,8 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
       const int yb = c.y_base[inst];
       const int ny = c.y_base[inst + 1] - yb;
       const int32_t* wp = c.wptr + c.cwm_off[inst] + int64_t(w) * ny;
+      // uint4 columns of this window that hold dense z of the row's instance
+      const int qa = win_cols(c.zd_base[inst + 1] - c.zd_base[inst], wstart);
 
       // bounds of this window's cold segments: issued first, used after the hot ORs
       const int cd = cd_r;
@@ -227,16 +267,28 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
       uint4 acc[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) acc[q] = make_uint4(0, 0, 0, 0);
-      hot_or<Q>(acc, cd, staged, t_eff, stage, hbase, rw);
-      for (int c0 = a + 64; c0 < b; c0 += 64) {  // rows with more than 64 join keys
-        const int j = c0 + lane;
-        const int cx = j < b ? c.rcode[j] : -1;
-        any_cold |= ballot(cx <= -2) != 0;
-        hot_or<Q>(acc, cx, staged, t_eff, stage, hbase, rw);
+      if (qa == Q) {
+        hot_or<Q>(acc, cd, staged, t_eff, stage, hbase, rw);
+        for (int c0 = a + 64; c0 < b; c0 += 64) {  // rows with more than 64 join keys
+          const int j = c0 + lane;
+          const int cx = j < b ? c.rcode[j] : -1;
+          any_cold |= ballot(cx <= -2) != 0;
+          hot_or<Q>(acc, cx, staged, t_eff, stage, hbase, rw);
+        }
+      } else {
+        hot_or_part<Q>(acc, cd, staged, t_eff, stage, hbase, rw, qa);
+        for (int c0 = a + 64; c0 < b; c0 += 64) {
+          const int j = c0 + lane;
+          const int cx = j < b ? c.rcode[j] : -1;
+          any_cold |= ballot(cx <= -2) != 0;
+          hot_or_part<Q>(acc, cx, staged, t_eff, stage, hbase, rw, qa);
+        }
       }
       if (any_cold) {
+        // columns past qa stay zero in acc (cold z lie in the dense range)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) rowbuf4[q * 64 + lane] = acc[q];
+        for (int q = 0; q < Q; ++q)
+          if (q < qa) rowbuf4[q * 64 + lane] = acc[q];
         lds_fence();
         cold_scatter(s0, len, c.ccol, wstart, rowbuf);
         for (int c0 = a + 64; c0 < b; c0 += 64) {
@@ -252,7 +304,8 @@ __global__ void __launch_bounds__(NT, 8) k_dense_bits(RowCtx c, int64_t x_lo, in
         }
         lds_fence();
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc[q] = rowbuf4[q * 64 + lane];
+        for (int q = 0; q < Q; ++q)
+          if (q < qa) acc[q] = rowbuf4[q * 64 + lane];
         lds_fence();
       }
 

@@ -237,7 +237,8 @@ __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict
                                                        int64_t n, const int32_t* __restrict__ zsel,
                                                        const uint64_t* __restrict__ zbit,
                                                        const int32_t* __restrict__ hot, int32_t* __restrict__ out,
-                                                       int32_t* __restrict__ rowptr, int64_t n_rows,
+                                                       int32_t* __restrict__ orow, int32_t* __restrict__ rowptr,
+                                                       int64_t n_rows,
                                                        int32_t* __restrict__ total, uint64_t* __restrict__ status,
                                                        int64_t ntiles) {
   __shared__ int64_t s_tile;
@@ -327,7 +328,10 @@ __global__ void __launch_bounds__(FR_NT) k_filter_rows(const int32_t* __restrict
     const bool k = (keep >> j) & 1u;
     const uint64_t b = ballot(k);
     const int64_t before = run + __popcll(b & ltm);
-    if (k) out[before] = val[j];
+    if (k) {
+      out[before] = val[j];
+      if (orow) orow[before] = e1[j] - 1;
+    }
     if ((first >> j) & 1u) rowptr[e1[j] - 1] = int32_t(before);
     run += __popcll(b);
   }
@@ -481,35 +485,65 @@ __global__ void k_key_codes(const int32_t* __restrict__ hotrow, const int32_t* _
 
 __global__ void k_row_codes(const int32_t* __restrict__ rcol, int64_t n, const int32_t* __restrict__ ycode,
                             int32_t* __restrict__ rcode) {
-  GRID_STRIDE(j, n) rcode[j] = ycode[rcol[j]];
+  // four entries per thread and step: their column loads, then their code gathers, then the stores
+  const int64_t c1 = chunk_first() + JP_CHUNK < n ? chunk_first() + JP_CHUNK : n;
+  const int64_t step = blockDim.x;
+  for (int64_t j0 = chunk_first() + threadIdx.x; j0 < c1; j0 += 4 * step) {
+    int32_t y[4], v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) y[u] = rcol[j0 + u * step < c1 ? j0 + u * step : c1 - 1];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = ycode[y[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j0 + u * step < c1) rcode[j0 + u * step] = v[u];
+  }
 }
 
 // every table slot is written exactly once: by the first entry of y at or
 // after the window start (entries), or by the row end (tail)
-__global__ void k_cold_win_entries(const int32_t* __restrict__ cptr, const int32_t* __restrict__ ccol, int64_t n_y,
-                                   int64_t n_cold, const int32_t* __restrict__ y_base, int n_inst,
-                                   const int64_t* __restrict__ cw_off, int32_t* __restrict__ cw) {
-  // row of entry p: largest y with cptr[y] <= p
-  SegCursor<int32_t> rowcur(cptr, int(n_y)), ycur(y_base, n_inst);
-  rowcur.seed(int32_t(chunk_first()));
-  ycur.seed(int32_t(rowcur.cur));
-  CHUNK_LOOP(p, n_cold, JP_CHUNK) {
-    const int32_t y = rowcur(int32_t(p));
-    const int inst = ycur(y);
-    const int ny = y_base[inst + 1] - y_base[inst];
-    const int yl = y - y_base[inst];
-    const int wp = ccol[p] / DW_BITS;
-    const int wprev = p == cptr[y] ? -1 : ccol[p - 1] / DW_BITS;
-    int32_t* t = cw + cw_off[inst] + yl;
-    for (int w = wprev + 1; w <= wp; ++w) t[int64_t(w) * ny] = int32_t(p);
+__global__ void k_cold_win_entries(const int32_t* __restrict__ cptr, const int32_t* __restrict__ ccol,
+                                   const int32_t* __restrict__ crow, int64_t n_cold,
+                                   const int32_t* __restrict__ y_base, int n_inst, const int64_t* __restrict__ cw_off,
+                                   int32_t* __restrict__ cw) {
+  // crow[p] = row of entry p; four entries per thread and step, loads first
+  SegCursor<int32_t> ycur(y_base, n_inst);
+  ycur.seed(crow[chunk_first() < n_cold ? chunk_first() : n_cold - 1]);
+  const int64_t c1 = chunk_first() + JP_CHUNK < n_cold ? chunk_first() + JP_CHUNK : n_cold;
+  const int64_t step = blockDim.x;
+  for (int64_t p0 = chunk_first() + threadIdx.x; p0 < c1; p0 += 4 * step) {
+    int32_t y[4], d[4], dp[4], a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t p = p0 + u * step < c1 ? p0 + u * step : c1 - 1;
+      y[u] = crow[p];
+      d[u] = ccol[p];
+      dp[u] = ccol[p > 0 ? p - 1 : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = cptr[y[u]];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t p = p0 + u * step;
+      if (p >= c1) break;
+      const int inst = ycur(y[u]);
+      const int ny = y_base[inst + 1] - y_base[inst];
+      const int yl = y[u] - y_base[inst];
+      const int wp = d[u] / DW_BITS;
+      const int wprev = p == a[u] ? -1 : dp[u] / DW_BITS;
+      int32_t* t = cw + cw_off[inst] + yl;
+      for (int w = wprev + 1; w <= wp; ++w) t[int64_t(w) * ny] = int32_t(p);
+    }
   }
 }
 
 __global__ void k_cold_win_tail(const int32_t* __restrict__ cptr, const int32_t* __restrict__ ccol, int64_t n_y,
                                 const int32_t* __restrict__ y_base, const int32_t* __restrict__ zd_base, int n_inst,
                                 const int64_t* __restrict__ cw_off, int32_t* __restrict__ cw) {
-  GRID_STRIDE(y, n_y) {
-    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+  SegCursor<int32_t> ycur(y_base, n_inst);
+  ycur.seed(int32_t(chunk_first()));
+  CHUNK_LOOP(y, n_y, JP_CHUNK) {
+    const int inst = ycur(int32_t(y));
     const int zd = zd_base[inst + 1] - zd_base[inst];
     if (zd <= 0) continue;
     const int nwin = (zd + DW_BITS - 1) / DW_BITS;
@@ -527,8 +561,10 @@ __global__ void k_cold_win_counts(const int32_t* __restrict__ cw, const int64_t*
                                   const int64_t* __restrict__ cwm_off, const int32_t* __restrict__ y_base,
                                   const int32_t* __restrict__ zd_base, int n_inst, int64_t n_y,
                                   int32_t* __restrict__ cnt) {
-  GRID_STRIDE(y, n_y) {
-    const int inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+  SegCursor<int32_t> ycur(y_base, n_inst);
+  ycur.seed(int32_t(chunk_first()));
+  CHUNK_LOOP(y, n_y, JP_CHUNK) {
+    const int inst = ycur(int32_t(y));
     const int zd = zd_base[inst + 1] - zd_base[inst];
     if (zd <= 0) continue;
     const int nwin = (zd + DW_BITS - 1) / DW_BITS;
@@ -540,40 +576,59 @@ __global__ void k_cold_win_counts(const int32_t* __restrict__ cw, const int64_t*
   }
 }
 
-__global__ void k_cold_win_scatter(const int32_t* __restrict__ cptr, const int32_t* __restrict__ ccol, int64_t n_y,
+__global__ void k_cold_win_scatter(const int32_t* __restrict__ ccol, const int32_t* __restrict__ crow,
                                    int64_t n_cold, const int32_t* __restrict__ y_base, int n_inst,
                                    const int32_t* __restrict__ cw, const int64_t* __restrict__ cw_off,
                                    const int32_t* __restrict__ wptr, const int64_t* __restrict__ cwm_off,
                                    int32_t* __restrict__ ccol_w) {
-  SegCursor<int32_t> rowcur(cptr, int(n_y)), ycur(y_base, n_inst);
-  rowcur.seed(int32_t(chunk_first()));
-  ycur.seed(int32_t(rowcur.cur));
-  CHUNK_LOOP(p, n_cold, JP_CHUNK) {
-    const int32_t y = rowcur(int32_t(p));
-    const int inst = ycur(y);
-    const int ny = y_base[inst + 1] - y_base[inst];
-    const int yl = y - y_base[inst];
-    const int32_t d = ccol[p];
-    const int64_t slot = int64_t(d / DW_BITS) * ny + yl;
-    ccol_w[wptr[cwm_off[inst] + slot] + (p - cw[cw_off[inst] + slot])] = d;
+  // crow[p] = row of entry p; four entries per thread and step, loads first
+  SegCursor<int32_t> ycur(y_base, n_inst);
+  ycur.seed(crow[chunk_first() < n_cold ? chunk_first() : n_cold - 1]);
+  const int64_t c1 = chunk_first() + JP_CHUNK < n_cold ? chunk_first() + JP_CHUNK : n_cold;
+  const int64_t step = blockDim.x;
+  for (int64_t p0 = chunk_first() + threadIdx.x; p0 < c1; p0 += 4 * step) {
+    int32_t y[4], d[4], inst[4], b0[4], e0[4];
+    int64_t slot[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t p = p0 + u * step < c1 ? p0 + u * step : c1 - 1;
+      y[u] = crow[p];
+      d[u] = ccol[p];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      inst[u] = ycur(y[u]);
+      const int ny = y_base[inst[u] + 1] - y_base[inst[u]];
+      slot[u] = int64_t(d[u] / DW_BITS) * ny + (y[u] - y_base[inst[u]]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      b0[u] = wptr[cwm_off[inst[u]] + slot[u]];
+      e0[u] = cw[cw_off[inst[u]] + slot[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t p = p0 + u * step;
+      if (p < c1) ccol_w[b0[u] + (p - e0[u])] = d[u];
+    }
   }
 }
 
 }  // namespace
 
-void cold_window_major(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t n_cold, const int32_t* y_base,
+void cold_window_major(const int32_t* ccol, const int32_t* crow, int64_t n_y, int64_t n_cold, const int32_t* y_base,
                        const int32_t* zd_base, int n_inst, const int32_t* cw, const int64_t* cw_off,
                        const int64_t* cwm_off, int64_t cwm_total, int32_t* wptr, int32_t* ccol_w, hipStream_t s,
                        Arena& a) {
   int32_t* cnt = a.alloc<int32_t>(std::max<int64_t>(cwm_total, 1), s);
   if (n_y > 0)
-    hipLaunchKernelGGL(k_cold_win_counts, dim3(grid(n_y)), dim3(NT), 0, s, cw, cw_off, cwm_off, y_base, zd_base, n_inst,
-                       n_y, cnt);
+    hipLaunchKernelGGL(k_cold_win_counts, dim3(chunk_grid(n_y)), dim3(NT), 0, s, cw, cw_off, cwm_off, y_base, zd_base,
+                       n_inst, n_y, cnt);
   JP_LAUNCH_CHECK();
   scan_excl_i32(cnt, wptr, cwm_total, s, a);
   if (n_cold > 0)
-    hipLaunchKernelGGL(k_cold_win_scatter, dim3(chunk_grid(n_cold)), dim3(NT), 0, s, cptr, ccol, n_y, n_cold, y_base, n_inst,
-                       cw, cw_off, wptr, cwm_off, ccol_w);
+    hipLaunchKernelGGL(k_cold_win_scatter, dim3(chunk_grid(n_cold)), dim3(NT), 0, s, ccol, crow, n_cold, y_base,
+                       n_inst, cw, cw_off, wptr, cwm_off, ccol_w);
   JP_LAUNCH_CHECK();
   a.give_back(cnt, s);
 }
@@ -592,8 +647,8 @@ void dense_index(const int32_t* flag, const int32_t* Edz, int64_t n_z, int32_t* 
 }
 
 void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zsel, int64_t n_z,
-                 const int32_t* hot, int32_t* out, int32_t* rowptr, int64_t n_rows, int32_t* total, hipStream_t s,
-                 Arena& a) {
+                 const int32_t* hot, int32_t* out, int32_t* out_row, int32_t* rowptr, int64_t n_rows, int32_t* total,
+                 hipStream_t s, Arena& a) {
   if (n <= 0) {
     fill_i32(rowptr, n_rows + 1, 0, s);
     fill_i32(total, 1, 0, s);
@@ -609,10 +664,10 @@ void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, c
   fill_i64(reinterpret_cast<int64_t*>(status), nt + 2, 0, s);
   if (cold)
     hipLaunchKernelGGL(k_filter_rows<FILTER_COLD>, dim3(int(nt)), dim3(FR_NT), 0, s, Ey, scol, n, zsel,
-                       (const uint64_t*)zbit, hot, out, rowptr, n_rows, total, status, nt);
+                       (const uint64_t*)zbit, hot, out, out_row, rowptr, n_rows, total, status, nt);
   else
     hipLaunchKernelGGL(k_filter_rows<FILTER_SPARSE>, dim3(int(nt)), dim3(FR_NT), 0, s, Ey, scol, n, zsel,
-                       (const uint64_t*)zbit, hot, out, rowptr, n_rows, total, status, nt);
+                       (const uint64_t*)zbit, hot, out, out_row, rowptr, n_rows, total, status, nt);
   JP_LAUNCH_CHECK();
   a.give_back(status, s);
   a.give_back(zbit, s);
@@ -739,20 +794,21 @@ void row_codes(const int32_t* rcol, int64_t n, const int32_t* hotrow, const int3
   if (n <= 0 || n_y <= 0) return;
   hipLaunchKernelGGL(k_key_codes, dim3(grid(n_y)), dim3(NT), 0, s, hotrow, cptr, n_y, ycode);
   JP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_row_codes, dim3(grid(n)), dim3(NT), 0, s, rcol, n, ycode, rcode);
+  hipLaunchKernelGGL(k_row_codes, dim3(chunk_grid(n)), dim3(NT), 0, s, rcol, n, ycode, rcode);
   JP_LAUNCH_CHECK();
 }
 
-void cold_windows(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t n_cold, const int32_t* y_base,
-                  const int32_t* zd_base, int n_inst, const int64_t* cw_off, int32_t* cw, hipStream_t s) {
+void cold_windows(const int32_t* cptr, const int32_t* ccol, const int32_t* crow, int64_t n_y, int64_t n_cold,
+                  const int32_t* y_base, const int32_t* zd_base, int n_inst, const int64_t* cw_off, int32_t* cw,
+                  hipStream_t s) {
   if (n_y <= 0) return;
   if (n_cold > 0) {
-    hipLaunchKernelGGL(k_cold_win_entries, dim3(chunk_grid(n_cold)), dim3(NT), 0, s, cptr, ccol, n_y, n_cold, y_base, n_inst,
-                       cw_off, cw);
+    hipLaunchKernelGGL(k_cold_win_entries, dim3(chunk_grid(n_cold)), dim3(NT), 0, s, cptr, ccol, crow, n_cold, y_base,
+                       n_inst, cw_off, cw);
     JP_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_cold_win_tail, dim3(grid(n_y)), dim3(NT), 0, s, cptr, ccol, n_y, y_base, zd_base, n_inst, cw_off,
-                     cw);
+  hipLaunchKernelGGL(k_cold_win_tail, dim3(chunk_grid(n_y)), dim3(NT), 0, s, cptr, ccol, n_y, y_base, zd_base, n_inst,
+                     cw_off, cw);
   JP_LAUNCH_CHECK();
 }
 

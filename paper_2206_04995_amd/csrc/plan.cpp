@@ -465,7 +465,7 @@ void Plan::partition(hipStream_t s) {
   spcol = A.alloc<int32_t>(NSa, s);  // sized before the count is known: one pass fills it
   spptr = A.alloc<int32_t>(NY + 1, s);
   int32_t* d_nsp = T.alloc<int32_t>(1, s);
-  filter_rows(false, Ey, scol, NS, zflag, NZ, nullptr, spcol, spptr, NY, d_nsp, s, T);
+  filter_rows(false, Ey, scol, NS, zflag, NZ, nullptr, spcol, nullptr, spptr, NY, d_nsp, s, T);
   int32_t nsp = 0;
   d2h(&nsp, d_nsp, 1, s);
   int32_t* hist = T.alloc<int32_t>(int64_t(n) * 32, s);
@@ -666,7 +666,8 @@ void Plan::build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a,
   int32_t* ccol_y = T.alloc<int32_t>(NSa, s);
   d.cptr = A.alloc<int32_t>(NY + 1, s);
   int32_t* d_ncold = T.alloc<int32_t>(1, s);
-  filter_rows(true, Ey, scol, NS, zmap, NZ, hot, ccol_y, d.cptr, NY, d_ncold, s, T);
+  int32_t* crow = T.alloc<int32_t>(NSa, s);  // row of each cold entry
+  filter_rows(true, Ey, scol, NS, zmap, NZ, hot, ccol_y, crow, d.cptr, NY, d_ncold, s, T);
   int32_t ncold = 0;
   d2h(&ncold, d_ncold, 1, s);
   sync(s);
@@ -694,8 +695,8 @@ void Plan::build_space(DenseSpace& d, const int32_t* zmap, const int32_t* cnt_a,
   d.wptr = A.alloc<int32_t>(cwm_total + 1, s);
   d.ccol = A.alloc<int32_t>(std::max<int64_t>(d.NCold, 1), s);
   if (cw_total > 0) {
-    cold_windows(d.cptr, ccol_y, NY, d.NCold, y_base, d.base, n, d_offs, cw, s);
-    cold_window_major(d.cptr, ccol_y, NY, d.NCold, y_base, d.base, n, cw, d_offs, d.d_cwmoff, cwm_total, d.wptr, d.ccol,
+    cold_windows(d.cptr, ccol_y, crow, NY, d.NCold, y_base, d.base, n, d_offs, cw, s);
+    cold_window_major(ccol_y, crow, NY, d.NCold, y_base, d.base, n, cw, d_offs, d.d_cwmoff, cwm_total, d.wptr, d.ccol,
                       s, T);
   } else {
     fill_i32(d.wptr, 1, 0, s);

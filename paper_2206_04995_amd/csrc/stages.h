@@ -126,10 +126,11 @@ void dense_index(const int32_t* flag, const int32_t* Edz, int64_t n_z, int32_t* 
 // S entries filtered into a CSR over the rows of S in one pass: the entries
 // whose z is sparse (cold = false: zsel = zflag, out = z), or the cold
 // entries of a space (cold = true: zsel = zmap, hot = hot rows, out = local
-// index); zsel has n_z entries; rowptr gets n_rows + 1 entries, *total the kept count
+// index); zsel has n_z entries; rowptr gets n_rows + 1 entries, *total the kept count;
+// out_row (if not null) gets the row of each kept entry
 void filter_rows(bool cold, const int32_t* Ey, const int32_t* scol, int64_t n, const int32_t* zsel, int64_t n_z,
-                 const int32_t* hot, int32_t* out, int32_t* rowptr, int64_t n_rows, int32_t* total, hipStream_t s,
-                 Arena& a);
+                 const int32_t* hot, int32_t* out, int32_t* out_row, int32_t* rowptr, int64_t n_rows, int32_t* total,
+                 hipStream_t s, Arena& a);
 // rowptr_out[y] = E[rowptr[y]] for y in [0, n_y]
 void remap_rowptr(const int32_t* rowptr, const int32_t* E, int64_t n_y, int32_t* out, hipStream_t s);
 // The tables of DenseEC are built over a "space" of z: a map zmap[z] = local
@@ -223,13 +224,14 @@ void hot_rank(const int32_t* hot, const int32_t* Ehot, int64_t n_y, int64_t n_ho
 void row_codes(const int32_t* rcol, int64_t n, const int32_t* hotrow, const int32_t* cptr, int64_t n_y,
                int32_t* ycode, int32_t* rcode, hipStream_t s);
 // cold segment table: cw[cw_off[i] + w * Y_i + (y - y_base[i])] = first cold entry of y with local dense
-// index >= w * DW_BITS, for w in [0, nwin_i]
-void cold_windows(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t n_cold, const int32_t* y_base,
-                  const int32_t* zd_base, int n_inst, const int64_t* cw_off, int32_t* cw, hipStream_t s);
+// index >= w * DW_BITS, for w in [0, nwin_i]; crow[p] = row of cold entry p
+void cold_windows(const int32_t* cptr, const int32_t* ccol, const int32_t* crow, int64_t n_y, int64_t n_cold,
+                  const int32_t* y_base, const int32_t* zd_base, int n_inst, const int64_t* cw_off, int32_t* cw,
+                  hipStream_t s);
 // Window-major copy of the cold entries: the entries of (window w, key y) of
 // instance i are ccol_w[wptr[k], wptr[k + 1]) with k = cwm_off[i] + w * Y_i + (y - y_base[i]);
 // wptr has cwm_total + 1 entries.
-void cold_window_major(const int32_t* cptr, const int32_t* ccol, int64_t n_y, int64_t n_cold, const int32_t* y_base,
+void cold_window_major(const int32_t* ccol, const int32_t* crow, int64_t n_y, int64_t n_cold, const int32_t* y_base,
                        const int32_t* zd_base, int n_inst, const int32_t* cw, const int64_t* cw_off,
                        const int64_t* cwm_off, int64_t cwm_total, int32_t* wptr, int32_t* ccol_w, hipStream_t s,
                        Arena& a);
