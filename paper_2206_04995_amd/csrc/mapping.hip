@@ -126,7 +126,8 @@ __global__ void __launch_bounds__(RUN_NT) k_run_ids(const uint32_t* __restrict__
                                                     const int32_t* __restrict__ offs, const int64_t* __restrict__ koff,
                                                     const int32_t* __restrict__ mn, int n_inst, int32_t* __restrict__ E,
                                                     int32_t* __restrict__ first, int32_t* __restrict__ vals,
-                                                    int32_t* __restrict__ total, RunCarry c) {
+                                                    int32_t* __restrict__ total, RunCarry c,
+                                                    int32_t* __restrict__ table) {
   __shared__ int32_t part[RUN_WAVES];
   const int lane = lane_id(), wid = threadIdx.x >> 6;
   const int64_t w0 = int64_t(blockIdx.x) * RUN_TILE + int64_t(wid) * RUN_WTILE;
@@ -163,6 +164,7 @@ __global__ void __launch_bounds__(RUN_NT) k_run_ids(const uint32_t* __restrict__
         if (h) {
           first[r] = int32_t(i);
           vals[r] = int32_t(int64_t(k[j]) - koff[inst] + int64_t(mn[inst]));
+          if (table) table[k[j]] = r;
         }
         if (MODE == RUN_CARRY) {
           c.keys[i] = uint32_t(c.koff[inst] + (int64_t(cv[j]) - int64_t(c.mn[inst])));
@@ -467,16 +469,20 @@ __global__ void k_out_j(const int32_t* __restrict__ dR, const int32_t* __restric
     }
     return;
   }
-  for (int64_t b = int64_t(blockIdx.x) * blockDim.x; b < n_y; b += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t y = b + threadIdx.x;
+  // a block per chunk of JP_CHUNK keys, walked in wave-uniform steps with an instance cursor
+  SegCursor<int32_t> ycur(y_base, n_inst);
+  ycur.seed(int32_t(chunk_first()));
+  const int64_t c1 = chunk_first() + JP_CHUNK < n_y ? chunk_first() + JP_CHUNK : n_y;
+  for (int64_t b = chunk_first() + (threadIdx.x & ~63); b < c1; b += blockDim.x) {
+    const int64_t y = b + lane_id();
     int64_t prod = 0;
     int inst = 0;
-    if (y < n_y) {
+    if (y < c1) {
       prod = int64_t(dR[y]) * int64_t(dS[y]);
-      inst = n_inst == 1 ? 0 : find_inst<int32_t>(y_base, n_inst, int32_t(y));
+      inst = ycur(int32_t(y));
     }
     const int i0 = __shfl(inst, 0, 64);
-    if (ballot(y < n_y && inst != i0) == 0) {
+    if (ballot(y < c1 && inst != i0) == 0) {
       const int64_t s = wave_sum(prod);
       if (lane_id() == 0 && s) atomicAdd((unsigned long long*)&out_j[i0], (unsigned long long)s);
     } else if (prod) {
@@ -750,7 +756,8 @@ void make_keys(const int32_t* v, int64_t n, const int32_t* ebase, int n_inst, co
 }
 
 void run_ids(const uint32_t* keys, int64_t n, const int64_t* koff, const int32_t* mn, int n_inst, int32_t* E,
-             int32_t* first, int32_t* vals, hipStream_t s, Arena& a, int32_t* total, const RunCarry* carry) {
+             int32_t* first, int32_t* vals, hipStream_t s, Arena& a, int32_t* total, const RunCarry* carry,
+             int32_t* table) {
   if (n <= 0) {
     if (E) fill_i32(E, 1, 0, s);
     fill_i32(first, 1, 0, s);
@@ -770,13 +777,13 @@ void run_ids(const uint32_t* keys, int64_t n, const int64_t* koff, const int32_t
   const RunCarry c = carry ? *carry : RunCarry{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (carry)
     hipLaunchKernelGGL(k_run_ids<RUN_CARRY>, dim3(int(nb)), dim3(RUN_NT), 0, s, keys, n, (const int32_t*)offs, koff,
-                       mn, n_inst, E, first, vals, total, c);
+                       mn, n_inst, E, first, vals, total, c, table);
   else if (E)
     hipLaunchKernelGGL(k_run_ids<RUN_E>, dim3(int(nb)), dim3(RUN_NT), 0, s, keys, n, (const int32_t*)offs, koff, mn,
-                       n_inst, E, first, vals, total, c);
+                       n_inst, E, first, vals, total, c, table);
   else
     hipLaunchKernelGGL(k_run_ids<RUN_NONE>, dim3(int(nb)), dim3(RUN_NT), 0, s, keys, n, (const int32_t*)offs, koff,
-                       mn, n_inst, E, first, vals, total, c);
+                       mn, n_inst, E, first, vals, total, c, table);
   JP_LAUNCH_CHECK();
   if (nb > 1) {
     a.give_back(offs, s);
@@ -815,15 +822,6 @@ void semijoin_direct(const int32_t* ry, int64_t n, const int32_t* ebase, int n_i
   hipLaunchKernelGGL(k_semijoin_direct, dim3(chunk_grid(n)), dim3(NT), 0, s, ry, n, ebase, n_inst, koff, mn, table, keep,
                      yid);
   JP_LAUNCH_CHECK();
-}
-
-void fill_direct_table(const uint32_t* ykeys, int64_t ns, const int32_t* first, const int32_t* total,
-                       int64_t key_space, int32_t* table, hipStream_t s) {
-  fill_i32(table, key_space, -1, s);
-  if (ns > 0) {
-    hipLaunchKernelGGL(k_fill_direct, dim3(grid(ns, 8192)), dim3(NT), 0, s, ykeys, first, total, table);
-    JP_LAUNCH_CHECK();
-  }
 }
 
 void semijoin_compact(const SemiJoinIn& in, uint32_t* xk, uint32_t* oy, int32_t* rpbase, int32_t* total,
@@ -871,8 +869,8 @@ void out_j_per_inst(const int32_t* dR, const int32_t* dS, int64_t n_y, const int
                     int64_t* out_j, hipStream_t s) {
   fill_i64(out_j, n_inst, 0, s);
   if (n_y <= 0) return;
-  hipLaunchKernelGGL(k_out_j, dim3(n_inst == 1 ? grid(n_y, 1024) : grid(n_y)), dim3(NT), 0, s, dR, dS, n_y, y_base,
-                     n_inst, out_j);
+  hipLaunchKernelGGL(k_out_j, dim3(n_inst == 1 ? grid(n_y, 1024) : chunk_grid(n_y)), dim3(NT), 0, s, dR, dS, n_y,
+                     y_base, n_inst, out_j);
   JP_LAUNCH_CHECK();
 }
 

@@ -314,15 +314,19 @@ void Plan::map(hipStream_t s) {
   Ey = A.alloc<int32_t>(NS + 1, s);
   sptr = A.alloc<int32_t>(NS + 1, s);
   vals_y = A.alloc<int32_t>(NSa, s);
-  run_ids(syk, NS, dky, ymin, n, Ey, sptr, vals_y, s, T, d_counts + 1);
+  // the semi-join's y table (dense key domain: a table lookup instead of a
+  // binary search); on the sort path the y run ids fill it at their run heads
+  const int64_t y_keys = koff_y[n];
+  const bool y_table = y_keys <= 2 * NS + 65536;
+  int32_t* table = y_table ? T.alloc<int32_t>(std::max<int64_t>(y_keys, 1), s) : nullptr;
+  const bool table_by_runs = y_table && !direct_x;
+  if (table_by_runs) fill_i32(table, y_keys, -1, s);
+  run_ids(syk, NS, dky, ymin, n, Ey, sptr, vals_y, s, T, d_counts + 1, nullptr, table_by_runs ? table : nullptr);
   y_base = A.alloc<int32_t>(n + 1, s);
   gather_bases(Ey, d_sbase, n, y_base, s);
 
   // semi-join of R on S.y (Sec. 2.2, optimisation 2), then R' grouped by (instance, x)
   const int64_t NRa = std::max<int64_t>(NR, 1);
-  const int64_t y_keys = koff_y[n];
-  const bool y_table = y_keys <= 2 * NS + 65536;  // dense key domain: a table lookup instead of a binary search
-  int32_t* table = y_table ? T.alloc<int32_t>(std::max<int64_t>(y_keys, 1), s) : nullptr;
   d_rpbase = A.alloc<int32_t>(n + 1, s);
   h_rpbase.resize(n + 1);
   int32_t counts[4];
@@ -364,7 +368,6 @@ void Plan::map(hipStream_t s) {
     scatter_x(rx, yid, NR, d_rbase, n, dkx, xmin, Cxk, rcol, s);
   } else {
     // kept tuples in order with their x keys and y ids, in one pass
-    if (y_table) fill_direct_table(syk, NS, sptr, d_counts + 1, y_keys, table, s);
     uint32_t* xk = T.alloc<uint32_t>(NRa, s);
     uint32_t* rpy = T.alloc<uint32_t>(NRa, s);
     const SemiJoinIn sj{rx, ry, NR, d_rbase, n, dky, ymin, table, vals_y, y_base, dkx, xmin};

@@ -38,12 +38,28 @@ __device__ __forceinline__ void lds_fence() {
 // per R CSR entry j: the sparse S row of its join key, as (start, length)
 __global__ void k_entry_seg(const int32_t* __restrict__ rcol, const int32_t* __restrict__ spptr, int64_t j_lo,
                             int64_t j_hi, int32_t* __restrict__ seg0, int32_t* __restrict__ len) {
-  for (int64_t j = j_lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < j_hi;
-       j += int64_t(gridDim.x) * blockDim.x) {
-    const int y = rcol[j];
-    const int a = spptr[y];
-    seg0[j] = a;
-    len[j] = spptr[y + 1] - a;
+  // a block per chunk of JP_CHUNK entries, four entries per thread and step:
+  // their column loads, then their row-pointer gathers, then the stores
+  const int64_t c0 = j_lo + int64_t(blockIdx.x) * JP_CHUNK;
+  const int64_t c1 = c0 + JP_CHUNK < j_hi ? c0 + JP_CHUNK : j_hi;
+  const int64_t step = blockDim.x;
+  for (int64_t j0 = c0 + threadIdx.x; j0 < c1; j0 += 4 * step) {
+    int32_t y[4], a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) y[u] = rcol[j0 + u * step < c1 ? j0 + u * step : c1 - 1];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = spptr[y[u]];
+      b[u] = spptr[y[u] + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t j = j0 + u * step;
+      if (j < c1) {
+        seg0[j] = a[u];
+        len[j] = b[u] - a[u];
+      }
+    }
   }
 }
 
@@ -553,8 +569,7 @@ void sparse_row_work(const RowCtx& c, int64_t x_lo, int64_t x_hi, int64_t j_lo, 
   if (n <= 0) return;
   const int64_t ne = j_hi - j_lo;
   if (ne > 0) {
-    int g = int(std::min<int64_t>((ne + NT - 1) / NT, 1 << 16));
-    hipLaunchKernelGGL(k_entry_seg, dim3(g), dim3(NT), 0, s, c.rcol, c.spptr, j_lo, j_hi, seg0, seglen);
+    hipLaunchKernelGGL(k_entry_seg, dim3(chunk_grid(ne)), dim3(NT), 0, s, c.rcol, c.spptr, j_lo, j_hi, seg0, seglen);
     JP_LAUNCH_CHECK();
   }
   int32_t* n_long = a.alloc<int32_t>(1, s);

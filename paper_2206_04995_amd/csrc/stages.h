@@ -46,10 +46,12 @@ struct RunCarry {
 // ids of the runs of equal sorted keys: for each run id, first[id] = its first
 // position and vals[id] = the original value of its key; first[runs] = n, and
 // *total = runs if total is non-null.  If E is non-null, E[p] = runs started
-// before position p (E[n] = runs); with carry, E is not written.
+// before position p (E[n] = runs); with carry, E is not written.  With table,
+// table[key] = id for the key of every run (the entries of other keys are
+// left as they are).
 void run_ids(const uint32_t* keys, int64_t n, const int64_t* koff, const int32_t* mn, int n_inst, int32_t* E,
              int32_t* first, int32_t* vals, hipStream_t s, Arena& a, int32_t* total = nullptr,
-             const RunCarry* carry = nullptr);
+             const RunCarry* carry = nullptr, int32_t* table = nullptr);
 // out[i] = runs started before ebase[i] (i in [0, n_inst]), from first[] and the run count
 void ids_at_bases(const int32_t* first, const int32_t* total, const int32_t* ebase, int n_inst, int32_t* out,
                   hipStream_t s);
@@ -81,10 +83,6 @@ struct SemiJoinIn {
   const int64_t* koff_x;
   const int32_t* xmin;
 };
-// table[key] = y id for every key of S.y, -1 elsewhere (key_space entries;
-// ykeys are the y-sorted S keys, first[] their run starts, *total the run count)
-void fill_direct_table(const uint32_t* ykeys, int64_t ns, const int32_t* first, const int32_t* total,
-                       int64_t key_space, int32_t* table, hipStream_t s);
 // semi-join of R on S.y with the kept tuples compacted in order: xk = their x
 // keys, oy = their y ids, rpbase[i] = kept tuples before instance i (i in
 // [0, n_inst]), *total = kept tuples
