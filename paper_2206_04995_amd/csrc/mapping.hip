@@ -285,12 +285,15 @@ __global__ void __launch_bounds__(SJ_NT) k_semijoin_compact(SemiJoinIn in, uint3
     const int64_t k0 = in.koff_y[i0], range = in.koff_y[i0 + 1] - k0;
     const int64_t ymn = in.ymin[i0], xoff = in.koff_x[i0] - int64_t(in.xmin[i0]);
     const int64_t st = in.ebase[i0];
+    // element i at px[i - st] (the instance's own buffers, or the concatenation)
+    const int32_t* px = in.cx ? in.cx[i0] : in.rx + st;
+    const int32_t* py = in.cy ? in.cy[i0] : in.ry + st;
 #pragma unroll
     for (int j = 0; j < SJ_IT; ++j) {
       const int64_t i = w0 + j * 64 + lane;
       const int64_t ic = i < wend ? i : wend - 1;
-      xr[j] = in.rx[ic];
-      yr[j] = in.ry[ic];
+      xr[j] = px[ic - st];
+      yr[j] = py[ic - st];
       if (i == st) starts |= 1u << j;
     }
     int32_t t[SJ_IT];
@@ -316,12 +319,23 @@ __global__ void __launch_bounds__(SJ_NT) k_semijoin_compact(SemiJoinIn in, uint3
     for (int j = 0; j < SJ_IT; ++j) {
       const int64_t i = w0 + j * 64 + lane;
       const int64_t ic = i < in.n ? i : in.n - 1;
-      xr[j] = in.rx[ic];
-      yr[j] = in.ry[ic];
       ins[j] = 0;
-      if (i < in.n) {
-        ins[j] = cur(int32_t(i));
-        if (i == cur.lo) starts |= 1u << j;
+      if (in.cx) {
+        // per-instance buffers: the instance first (the clamped position's, for lanes past the end)
+        const int k = cur(int32_t(ic));
+        xr[j] = in.cx[k][ic - cur.lo];
+        yr[j] = in.cy[k][ic - cur.lo];
+        if (i < in.n) {
+          ins[j] = k;
+          if (i == cur.lo) starts |= 1u << j;
+        }
+      } else {
+        xr[j] = in.rx[ic];
+        yr[j] = in.ry[ic];
+        if (i < in.n) {
+          ins[j] = cur(int32_t(i));
+          if (i == cur.lo) starts |= 1u << j;
+        }
       }
     }
 #pragma unroll
@@ -655,7 +669,7 @@ __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int3
       for (int u = 0; u < 4; ++u) {
         const int64_t g = g0 + u * step;
         if (g < c1) {
-          dst[g] = vv[u];
+          if (dst) dst[g] = vv[u];
           lo = vv[u] < lo ? vv[u] : lo;
           hi = vv[u] > hi ? vv[u] : hi;
         }
@@ -720,7 +734,7 @@ __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int3
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (iu[u] >= 0) {
-        dst[g0 + u * step] = vv[u];
+        if (dst) dst[g0 + u * step] = vv[u];
         if (mn) {
           if (iu[u] != acc) {  // rare: at instance bounds
             if (acc >= 0) {

@@ -190,7 +190,7 @@ __global__ void k_space_flags(const int32_t* __restrict__ scol, int64_t n, const
 //   FILTER_SPARSE  keep z with zsel[z] == 0 (z not dense), out = z;
 //   FILTER_COLD    keep z with zsel[z] >= 0 (z in the space) whose row is not
 //                  hot, out = zsel[z] (the local index in the space).
-constexpr int FR_NT = 256;
+constexpr int FR_NT = 512;  // 8192-entry tiles: half the look-backs of 4096
 constexpr int FR_IT = 16;
 constexpr int FR_WTILE = 64 * FR_IT;
 constexpr int FR_TILE = FR_NT * FR_IT;

@@ -158,22 +158,34 @@ void Plan::build(const jp_instance* inst, int n, const jp_options* o, hipStream_
     }
     const int32_t** d_ptrs = A.alloc<const int32_t*>(4 * int64_t(n), s);
     h2d(d_ptrs, ptrs.data(), ptrs.size(), s);
-    int32_t* cat = A.alloc<int32_t>(2 * NR + 2 * NS, s);
-    int32_t *crx = cat, *cry = cat + NR, *csz = cat + 2 * NR, *csy = cat + 2 * NR + NS;
-    // per-instance min and max of z, y (S) and x (R) come with the gather: the mapping's key layouts
+    // per-instance min and max of z, y (S) and x (R): the mapping's key layouts
     d_minmax = A.alloc<int32_t>(6 * int64_t(n), s);
     int32_t *zmin = d_minmax, *zmax = d_minmax + n, *ymin = d_minmax + 2 * n, *ymax = d_minmax + 3 * n;
     int32_t *xmin = d_minmax + 4 * n, *xmax = d_minmax + 5 * n;
     fill_minmax(d_minmax, n, s);
     const int32_t* const* src = d_ptrs;
-    gather_cols(src, d_rbase, n, NR, crx, xmin, xmax, s);
-    gather_cols(src + n, d_rbase, n, NR, cry, nullptr, nullptr, s);
-    gather_cols(src + 2 * n, d_sbase, n, NS, csz, zmin, zmax, s);
-    gather_cols(src + 3 * n, d_sbase, n, NS, csy, ymin, ymax, s);
-    rx = crx;
-    ry = cry;
-    sz = csz;
-    sy = csy;
+    // The sort path reads the instances' columns in place (the z sort's first
+    // pass and the semi-join take one buffer per instance), so only the min and
+    // max are taken here.  The direct-range mapping and the f1 sample read one
+    // concatenated buffer per column, which the same pass fills.
+    const bool in_place = (opt.flags & JP_FLAG_DIRECT_IDS) == 0 && !f1_probe;
+    if (in_place) {
+      d_cols = src;
+      gather_cols(src, d_rbase, n, NR, nullptr, xmin, xmax, s);
+      gather_cols(src + 2 * n, d_sbase, n, NS, nullptr, zmin, zmax, s);
+      gather_cols(src + 3 * n, d_sbase, n, NS, nullptr, ymin, ymax, s);
+    } else {
+      int32_t* cat = A.alloc<int32_t>(2 * NR + 2 * NS, s);
+      int32_t *crx = cat, *cry = cat + NR, *csz = cat + 2 * NR, *csy = cat + 2 * NR + NS;
+      gather_cols(src, d_rbase, n, NR, crx, xmin, xmax, s);
+      gather_cols(src + n, d_rbase, n, NR, cry, nullptr, nullptr, s);
+      gather_cols(src + 2 * n, d_sbase, n, NS, csz, zmin, zmax, s);
+      gather_cols(src + 3 * n, d_sbase, n, NS, csy, ymin, ymax, s);
+      rx = crx;
+      ry = cry;
+      sz = csz;
+      sy = csy;
+    }
   }
   map(s);
   if (take_classical) return;  // f1 chose the classical path: the caller builds it
@@ -289,9 +301,19 @@ void Plan::map(hipStream_t s) {
     const int zbits_sort = n > 1 ? local_bits(koff_z) : zbits;
     bool alt = false;
     if (radix_passes(NS, zbits_sort) > 0) {
-      alt = radix_sort_raw(sz, sy, zmin, k1, v1, k2, v2, NS, zbits_sort, s, T, sseg_z);
+      alt = radix_sort_raw(sz, sy, d_cols ? d_cols + 2 * n : nullptr, d_cols ? d_cols + 3 * n : nullptr, zmin, k1, v1,
+                           k2, v2, NS, zbits_sort, s, T, sseg_z);
     } else {
-      make_keys(sz, NS, d_sbase, n, dkz, zmin, k1, v1, sy, s);
+      const int32_t *zc = sz, *yc = sy;
+      if (d_cols) {  // no sort pass to read the instances' buffers: concatenate them for the key pass
+        int32_t* tz = T.alloc<int32_t>(NSa, s);
+        int32_t* ty = T.alloc<int32_t>(NSa, s);
+        gather_cols(d_cols + 2 * n, d_sbase, n, NS, tz, nullptr, nullptr, s);
+        gather_cols(d_cols + 3 * n, d_sbase, n, NS, ty, nullptr, nullptr, s);
+        zc = tz;
+        yc = ty;
+      }
+      make_keys(zc, NS, d_sbase, n, dkz, zmin, k1, v1, yc, s);
     }
     uint32_t *zk = alt ? k2 : k1, *zp = alt ? v2 : v1;
     // z ids of the sorted positions go straight into the y sort's input, with
@@ -370,7 +392,8 @@ void Plan::map(hipStream_t s) {
     // kept tuples in order with their x keys and y ids, in one pass
     uint32_t* xk = T.alloc<uint32_t>(NRa, s);
     uint32_t* rpy = T.alloc<uint32_t>(NRa, s);
-    const SemiJoinIn sj{rx, ry, NR, d_rbase, n, dky, ymin, table, vals_y, y_base, dkx, xmin};
+    const SemiJoinIn sj{rx, ry, d_cols, d_cols ? d_cols + n : nullptr, NR, d_rbase, n, dky, ymin, table, vals_y,
+                        y_base, dkx, xmin};
     semijoin_compact(sj, xk, rpy, d_rpbase, d_counts + 2, s, T);
     d2h(counts, d_counts, 3, s);
     d2h(h_rpbase.data(), d_rpbase, n + 1, s);

@@ -67,6 +67,9 @@ struct Plan {
   const int32_t *rx = nullptr, *ry = nullptr, *sz = nullptr, *sy = nullptr;
   int32_t *d_rbase = nullptr, *d_sbase = nullptr, *d_rpbase = nullptr;
   int32_t* d_minmax = nullptr;  // a batch: per-instance min and max of z, y, x (6 rows of n), from the gather
+  // a batch read in place: device table of the instances' column pointers
+  // (R.x, R.y, S.z, S.y; n each), used by the mapping instead of rx, ry, sz, sy
+  const int32_t* const* d_cols = nullptr;
   // mapping
   int32_t *vals_x = nullptr, *vals_y = nullptr, *vals_z = nullptr;
   int32_t *x_base = nullptr, *y_base = nullptr, *z_base = nullptr;

@@ -34,11 +34,13 @@ int radix_passes(int64_t n, int bits);
 // grouped by segment, with raw_v (or nothing, if null) as their values: the
 // first pass reads (raw, raw_v) and makes the keys as it loads them, the rest
 // ping-pong between (kt, vt) and (k, v) as radix_sort_pairs does, so the
-// result lies where radix_sort_pairs would leave it.  Needs at least one pass
-// (radix_passes(n, bits) > 0).
-bool radix_sort_raw(const int32_t* raw, const int32_t* raw_v, const int32_t* mn, uint32_t* k, uint32_t* v,
-                    uint32_t* kt, uint32_t* vt, int64_t n, int bits, hipStream_t s, Arena& a,
-                    const SortSegments& seg);
+// result lies where radix_sort_pairs would leave it.  With seg_raw (device
+// array of n_seg pointers, more than one segment), the raw values of segment
+// i are read from their own buffer seg_raw[i] (values seg_raw_v[i]) and raw,
+// raw_v are not used.  Needs at least one pass (radix_passes(n, bits) > 0).
+bool radix_sort_raw(const int32_t* raw, const int32_t* raw_v, const int32_t* const* seg_raw,
+                    const int32_t* const* seg_raw_v, const int32_t* mn, uint32_t* k, uint32_t* v, uint32_t* kt,
+                    uint32_t* vt, int64_t n, int bits, hipStream_t s, Arena& a, const SortSegments& seg);
 
 // Per-segment min and max of int32 values; segment i is [base[i], base[i+1]).
 // mn/mx (n_seg entries) are overwritten; empty segments give mn > mx.

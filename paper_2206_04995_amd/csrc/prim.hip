@@ -166,6 +166,11 @@ struct TileMap {
   const int64_t* koff;   // [n_seg] (null: 0)
   int n_seg;             // 0: one segment [0, n)
   const int32_t* mn;     // raw input (first pass only): key = koff + value - mn of the segment
+  // raw input in one buffer per segment (first pass only, n_seg > 0): element
+  // i of segment s is rk[s][i - ebase[s]] (values rv[s][...]); null: the
+  // pass's input arrays
+  const int32_t* const* rk;
+  const int32_t* const* rv;
 };
 
 struct Tile {
@@ -174,6 +179,9 @@ struct Tile {
   int stride;       // histogram distance of consecutive digits (tiles of the segment)
   int64_t koff;     // subtracted from the keys
   int64_t radd;     // raw input: added to a value to give its key
+  const uint32_t* kp;  // raw input in the segment's own buffer (null: the pass's input array)
+  const uint32_t* vp;
+  int64_t e0;          // the segment's first element (index 0 of kp, vp)
 };
 
 // whole wave, uniform control flow
@@ -187,6 +195,9 @@ __device__ __forceinline__ Tile tile_of(const TileMap& m, int64_t n, int nd) {
     t.stride = int(gridDim.x);
     t.koff = 0;
     t.radd = m.mn ? (m.koff ? m.koff[0] : 0) - int64_t(m.mn[0]) : 0;
+    t.kp = nullptr;
+    t.vp = nullptr;
+    t.e0 = 0;
     return t;
   }
   const int sg = wave_find_inst<int32_t>(m.toff, m.n_seg, b);
@@ -198,6 +209,9 @@ __device__ __forceinline__ Tile tile_of(const TileMap& m, int64_t n, int nd) {
   t.stride = nt;
   t.koff = m.koff ? m.koff[sg] : 0;
   t.radd = m.mn ? t.koff - int64_t(m.mn[sg]) : 0;
+  t.kp = m.rk ? reinterpret_cast<const uint32_t*>(m.rk[sg]) : nullptr;
+  t.vp = m.rv ? reinterpret_cast<const uint32_t*>(m.rv[sg]) : nullptr;
+  t.e0 = m.ebase[sg];
   return t;
 }
 
@@ -235,11 +249,14 @@ __global__ void __launch_bounds__(RS_NT) k_radix_hist(const uint32_t* __restrict
   for (int i = threadIdx.x; i < RS_WAVES * RS_MAXD; i += RS_NT) (&cnt[0][0])[i] = 0;
   __syncthreads();
   // all of a thread's loads first (clamped, so they need no branch), then the LDS counts
+  const bool own = RAW && tl.kp;  // raw input in the segment's own buffer
+  const uint32_t* kb = own ? tl.kp : keys;
+  const int64_t ko = own ? tl.e0 : 0;
   uint32_t kk[RS_IT];
 #pragma unroll
   for (int j = 0; j < RS_IT; ++j) {
     const int64_t i = tl.lo + j * RS_NT + threadIdx.x;
-    kk[j] = key_in<RAW>(keys[i < tl.hi ? i : tl.hi - 1], tl);
+    kk[j] = key_in<RAW>(kb[(i < tl.hi ? i : tl.hi - 1) - ko], tl);
   }
 #pragma unroll
   for (int j = 0; j < RS_IT; ++j)
@@ -283,13 +300,17 @@ __global__ void __launch_bounds__(RS_NT) k_radix_scatter(const uint32_t* __restr
   __syncthreads();
 
   const int64_t wbase = tl.lo + int64_t(wid) * RS_WTILE;
+  const bool own = RAW && tl.kp;  // raw input in the segment's own buffers
+  const uint32_t* kb = own ? tl.kp : kin;
+  const uint32_t* vb = own ? tl.vp : vin;
+  const int64_t ko = own ? tl.e0 : 0;
   uint32_t key[RS_IT], val[RS_IT];
 #pragma unroll
   for (int j = 0; j < RS_IT; ++j) {
     const int64_t i = wbase + j * 64 + lane;
     const bool valid = i < tl.hi;
-    key[j] = valid ? kin[i] : 0u;
-    if (HAS_V) val[j] = valid ? vin[i] : 0u;
+    key[j] = valid ? kb[i - ko] : 0u;
+    if (HAS_V) val[j] = valid ? vb[i - ko] : 0u;
   }
   // raw values become keys only once every load is in flight (converting each
   // as it arrives would make the loads wait for one another); lanes past the
@@ -508,13 +529,13 @@ void launch_scatter(bool raw, bool has_v, int nblocks, const uint32_t* ki, const
 
 // The passes of a sort whose first pass reads (k0, v0): (k, v) itself, or raw
 // values moved into their segments' key ranges by raw_mn.
-bool radix_impl(const uint32_t* k0, const uint32_t* v0, const int32_t* raw_mn, uint32_t* k, uint32_t* v,
-                uint32_t* kt, uint32_t* vt, int64_t n, int bits, hipStream_t s, Arena& a,
-                const SortSegments* seg) {
+bool radix_impl(const uint32_t* k0, const uint32_t* v0, const int32_t* raw_mn, const int32_t* const* seg_k,
+                const int32_t* const* seg_v, uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int64_t n,
+                int bits, hipStream_t s, Arena& a, const SortSegments* seg) {
   if (n <= 1 || bits <= 0) return false;
   int passes = radix_passes(n, bits);
   int width = (bits + passes - 1) / passes;
-  TileMap m{nullptr, nullptr, raw_mn && seg ? seg->d_koff : nullptr, 0, raw_mn};
+  TileMap m{nullptr, nullptr, raw_mn && seg ? seg->d_koff : nullptr, 0, raw_mn, nullptr, nullptr};
   int nblocks = int((n + RS_TILE - 1) / RS_TILE);
   int32_t* toff = nullptr;
   if (seg && seg->n_seg > 1) {
@@ -528,7 +549,9 @@ bool radix_impl(const uint32_t* k0, const uint32_t* v0, const int32_t* raw_mn, u
     JP_LAUNCH_CHECK();
     scan_excl_i32(tc, toff, ns, s, a);
     a.give_back(tc, s);
-    m = TileMap{toff, seg->d_ebase, seg->d_koff, ns, raw_mn};
+    m = TileMap{toff, seg->d_ebase, seg->d_koff, ns, raw_mn, seg_k, seg_v};
+  } else if (seg_k) {
+    throw Error(JP_EINVAL, "per-segment input needs more than one segment");
   }
   if (nblocks == 0) return false;
   int64_t hsz = int64_t(1 << width) * nblocks;
@@ -545,6 +568,8 @@ bool radix_impl(const uint32_t* k0, const uint32_t* v0, const int32_t* raw_mn, u
     scan_impl<int, int>(hist, offs, int64_t(1 << w) * nblocks, s, a);
     launch_scatter(raw, v != nullptr, nblocks, ki, vi, ko, vo, n, shift, w, offs, m, s);
     m.mn = nullptr;
+    m.rk = nullptr;
+    m.rv = nullptr;
     // the pass wrote (ko, vo); the next one writes the other pair
     uint32_t* nk = ko == kt ? k : kt;
     uint32_t* nv = ko == kt ? v : vt;
@@ -564,15 +589,16 @@ bool radix_impl(const uint32_t* k0, const uint32_t* v0, const int32_t* raw_mn, u
 
 bool radix_sort_pairs(uint32_t* k, uint32_t* v, uint32_t* kt, uint32_t* vt, int64_t n, int bits,
                       hipStream_t s, Arena& a, const SortSegments* seg) {
-  return radix_impl(k, v, nullptr, k, v, kt, vt, n, bits, s, a, seg);
+  return radix_impl(k, v, nullptr, nullptr, nullptr, k, v, kt, vt, n, bits, s, a, seg);
 }
 
-bool radix_sort_raw(const int32_t* raw, const int32_t* raw_v, const int32_t* mn, uint32_t* k, uint32_t* v,
-                    uint32_t* kt, uint32_t* vt, int64_t n, int bits, hipStream_t s, Arena& a,
-                    const SortSegments& seg) {
+bool radix_sort_raw(const int32_t* raw, const int32_t* raw_v, const int32_t* const* seg_raw,
+                    const int32_t* const* seg_raw_v, const int32_t* mn, uint32_t* k, uint32_t* v, uint32_t* kt,
+                    uint32_t* vt, int64_t n, int bits, hipStream_t s, Arena& a, const SortSegments& seg) {
   if (radix_passes(n, bits) == 0) throw Error(JP_EINVAL, "radix_sort_raw needs at least one pass");
-  return radix_impl(reinterpret_cast<const uint32_t*>(raw), reinterpret_cast<const uint32_t*>(raw_v), mn, k, v, kt,
-                    vt, n, bits, s, a, &seg);
+  if (seg_raw && v && !seg_raw_v) throw Error(JP_EINVAL, "radix_sort_raw: keys per segment need values per segment");
+  return radix_impl(reinterpret_cast<const uint32_t*>(raw), reinterpret_cast<const uint32_t*>(raw_v), mn, seg_raw,
+                    seg_raw_v, k, v, kt, vt, n, bits, s, a, &seg);
 }
 
 void seg_minmax(const int32_t* v, int64_t n, const int32_t* base, int n_seg, int32_t* mn, int32_t* mx,

@@ -78,8 +78,14 @@ __global__ void k_row_work(const int32_t* __restrict__ rptr, const int32_t* __re
       long_rows[atomicAdd(n_long, 1)] = int32_t(x);
       continue;
     }
+    // four lengths' loads in flight per step
     int64_t sum = 0;
-    for (int32_t j = a; j < b; ++j) sum += len[j];
+    int32_t j = a;
+    for (; j + 4 <= b; j += 4) {
+      const int32_t l0 = len[j], l1 = len[j + 1], l2 = len[j + 2], l3 = len[j + 3];
+      sum += int64_t(l0) + l1 + l2 + l3;
+    }
+    for (; j < b; ++j) sum += len[j];
     w[x - x_lo] = sum;
   }
 }

@@ -23,9 +23,9 @@ constexpr int T_STAGE = 3;
 
 // ------------------------------------------------------------ mapping
 // a batch's columns, one device pointer per instance (src[i], base[i + 1] -
-// base[i] values), into one buffer dst; with mn/mx non-null also each
-// instance's minimum and maximum (atomically merged into mn/mx, which
-// fill_minmax prepares: 6 rows of n_inst, minima at rows 0, 2, 4)
+// base[i] values), into one buffer dst (or nowhere, if dst is null); with
+// mn/mx non-null also each instance's minimum and maximum (atomically merged
+// into mn/mx, which fill_minmax prepares: 6 rows of n_inst, minima at rows 0, 2, 4)
 void fill_minmax(int32_t* mm, int n_inst, hipStream_t s);
 void gather_cols(const int32_t* const* src, const int32_t* base, int n_inst, int64_t n, int32_t* dst, int32_t* mn,
                  int32_t* mx, hipStream_t s);
@@ -72,6 +72,9 @@ void semijoin_direct(const int32_t* ry, int64_t n, const int32_t* ebase, int n_i
 struct SemiJoinIn {
   const int32_t* rx;
   const int32_t* ry;
+  // or, if non-null, one buffer per instance: element i of instance k is cx[k][i - ebase[k]]
+  const int32_t* const* cx;
+  const int32_t* const* cy;
   int64_t n;
   const int32_t* ebase;
   int n_inst;
