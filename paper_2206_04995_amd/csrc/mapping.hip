@@ -251,7 +251,7 @@ __global__ void k_semijoin_direct(const int32_t* __restrict__ ry, int64_t n, con
 // (koff_x, xmin) and the y id.  A tile places its kept tuples at the
 // look-back prefix of the kept counts (lookback_exclusive), and writes
 // rpbase[i] = kept tuples before ebase[i] for the instances starting in it.
-constexpr int SJ_NT = 256;
+constexpr int SJ_NT = 512;  // 8192-tuple tiles (faster with one buffer per instance)
 constexpr int SJ_IT = 16;
 constexpr int SJ_WTILE = 64 * SJ_IT;
 constexpr int SJ_TILE = SJ_NT * SJ_IT;
@@ -656,23 +656,23 @@ __global__ void k_gather_cols(const int32_t* const* __restrict__ src, const int3
   const int i0 = wave_find_inst<int32_t>(base, n_inst, int32_t(c0));
   if (int64_t(base[i0 + 1]) >= c1) {
     // the chunk lies in one instance (all but the chunks at instance bounds): no per-element lookups
+    // all of a thread's JP_CHUNK / 256 loads in flight at once (clamped indices, no branches), then the stores
     const int32_t* col = src[i0] + (c0 - base[i0]);
     int32_t lo = INT32_MAX, hi = INT32_MIN;
-    for (int64_t g0 = c0 + threadIdx.x; g0 < c1; g0 += 4 * step) {
-      int32_t vv[4];
+    constexpr int GU = JP_CHUNK / 256;  // elements per thread (the launch uses 256 threads)
+    int32_t vv[GU];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t g = g0 + u * step;
-        vv[u] = g < c1 ? col[g - c0] : 0;
-      }
+    for (int u = 0; u < GU; ++u) {
+      const int64_t g = c0 + threadIdx.x + u * step;
+      vv[u] = col[(g < c1 ? g : c1 - 1) - c0];
+    }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t g = g0 + u * step;
-        if (g < c1) {
-          if (dst) dst[g] = vv[u];
-          lo = vv[u] < lo ? vv[u] : lo;
-          hi = vv[u] > hi ? vv[u] : hi;
-        }
+    for (int u = 0; u < GU; ++u) {
+      const int64_t g = c0 + threadIdx.x + u * step;
+      if (g < c1) {
+        if (dst) dst[g] = vv[u];
+        lo = vv[u] < lo ? vv[u] : lo;
+        hi = vv[u] > hi ? vv[u] : hi;
       }
     }
     if (mn) {

@@ -153,6 +153,7 @@ constexpr int RS_WTILE = RS_TILE / RS_WAVES;  // 1024 keys per wave
 // scatter writes runs of about 8 keys.)
 constexpr int RS_MAXBITS = 8;
 constexpr int RS_MAXD = 1 << RS_MAXBITS;
+constexpr int RS_SUB = 4;  // digit counter sets per wave in the histogram pass
 
 // Tiles of a segmented sort: segment i (elements [ebase[i], ebase[i+1]), keys
 // in [koff[i], koff[i] + 2^bits)) owns tiles [toff[i], toff[i+1]), so no tile
@@ -241,12 +242,12 @@ template <bool RAW>
 __global__ void __launch_bounds__(RS_NT) k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
                                                        int shift, int nbits, int* __restrict__ hist,
                                                        TileMap m) {
-  __shared__ int cnt[RS_WAVES][RS_MAXD];
+  __shared__ int cnt[RS_WAVES * RS_SUB][RS_MAXD];
   const int wid = threadIdx.x >> 6;
   const int nd = 1 << nbits;
   const uint32_t mask = uint32_t(nd - 1);
   const Tile tl = tile_of(m, n, nd);
-  for (int i = threadIdx.x; i < RS_WAVES * RS_MAXD; i += RS_NT) (&cnt[0][0])[i] = 0;
+  for (int i = threadIdx.x; i < RS_WAVES * RS_SUB * RS_MAXD; i += RS_NT) (&cnt[0][0])[i] = 0;
   __syncthreads();
   // all of a thread's loads first (clamped, so they need no branch), then the LDS counts
   const bool own = RAW && tl.kp;  // raw input in the segment's own buffer
@@ -258,14 +259,17 @@ __global__ void __launch_bounds__(RS_NT) k_radix_hist(const uint32_t* __restrict
     const int64_t i = tl.lo + j * RS_NT + threadIdx.x;
     kk[j] = key_in<RAW>(kb[(i < tl.hi ? i : tl.hi - 1) - ko], tl);
   }
+  // four counter sets per wave (by lane mod 4): concentrated digits (the high
+  // digits of clustered keys) put at most 16 lanes of a row on one counter
+  const int sub = wid * RS_SUB + (lane_id() & (RS_SUB - 1));
 #pragma unroll
   for (int j = 0; j < RS_IT; ++j)
-    if (tl.lo + j * RS_NT + threadIdx.x < tl.hi) atomicAdd(&cnt[wid][digit_of(kk[j], tl, shift, mask)], 1);
+    if (tl.lo + j * RS_NT + threadIdx.x < tl.hi) atomicAdd(&cnt[sub][digit_of(kk[j], tl, shift, mask)], 1);
   __syncthreads();
   for (int d = threadIdx.x; d < nd; d += RS_NT) {
     int c = 0;
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; ++w) c += cnt[w][d];
+    for (int w = 0; w < RS_WAVES * RS_SUB; ++w) c += cnt[w][d];
     hist[tl.hbase + int64_t(d) * tl.stride] = c;
   }
 }
