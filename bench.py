@@ -64,11 +64,11 @@ MEASURED_TRAFFIC = {
                           "stages.h": "9f1d17ce26dd03bb4ead68b177f5469ad14d4b3a281ad23ece576481e3261635",
                           "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
     # the mapping stage of one batched pass (every kernel from k_gather_cols to k_out_j), 4096 instances
-    "batched_map": {"kernels": "mapping and CSR builds of the batched pass", "fetch_kib": 46785041.6,
-                    "write_kib": 69226141.4,
-                    "sources": {"mapping.hip": "616d5e34d78aa075ad056945dc90158b6c75255209e765ecf684be86f7495f16",
-                                "prim.hip": "a4ebfd219de22a68a710ce6025099963f69d518620a9db0f5fd0967dd74297b5",
-                                "plan.cpp": "0a49376f163b06aa79da6036deb98f97122c38503e04951caaf8ac510e26299c",
+    "batched_map": {"kernels": "mapping and CSR builds of the batched pass", "fetch_kib": 42410883.1,
+                    "write_kib": 55208109.9,
+                    "sources": {"mapping.hip": "e66bb2eee4467ccb033e8c0a47ddb3316a178a2a3a2f9ba9b2e656ea021d054b",
+                                "prim.hip": "aa91d31fd34175ce1892346820986f5724ded929dcb54c118cbca1f0000a6392",
+                                "plan.cpp": "367e463c5029c0b61b2bc7a31e8e0c147a5a72e1b1cea3cde499f9f12167dab9",
                                 "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
     "dense": {"kernels": "k_dense_mfma", "fetch_kib": 127735.5, "write_kib": 25185.5,
               "sources": {"dense_mfma.hip": "e01d5a7827ea364242f9cdbc823f069d02d4dc8d34fb036d2fc3687d726d1998",
