@@ -51,17 +51,17 @@ FETCH_FACTOR = 1048576 / 524308.0
 WRITE_FACTOR = 1.0
 MEASURED_TRAFFIC = {
     # two count launches per step: rows without and with the pivot key (2 windows per workgroup, as tuned)
-    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 706836.1 + 271579.4, "write_kib": 80210.6 + 39764.1,
-               "sources": {"dense_ec.hip": "3a4ea9f17479945a1200432af77316d554213d3c1778f78e91fdf20f898c90ff",
-                           "stages.h": "9f1d17ce26dd03bb4ead68b177f5469ad14d4b3a281ad23ece576481e3261635",
+    "skewed": {"kernels": "k_dense_bits<false> x 2", "fetch_kib": 706865.6 + 273163.8, "write_kib": 80210.6 + 39764.1,
+               "sources": {"dense_ec.hip": "a2c2ca011abf4bc11f190ba76a0dd4fe59a0c710c70864a664745a32e639c628",
+                           "stages.h": "af5828bcd4afad9ebfd854f63779ccd66f242169b2a52c51395aa1b755824fdb",
                            "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
     # the whole timed SparseBMM count region: per-entry segments, row work, row
     # lists, the light/medium/heavy count kernels
     "graph": {"kernels": "SparseBMM count pass (k_entry_seg ... k_sparse_heavy_count)",
-              "fetch_kib": 2650799.2, "write_kib": 216310.6,
-              "sources": {"sparse_bmm.hip": "7925383867891d063a91fd656adc43e24dba1dcfee4e9cc927bbca11da5affe0",
-                          "prim.hip": "a4ebfd219de22a68a710ce6025099963f69d518620a9db0f5fd0967dd74297b5",
-                          "stages.h": "9f1d17ce26dd03bb4ead68b177f5469ad14d4b3a281ad23ece576481e3261635",
+              "fetch_kib": 2652154.2, "write_kib": 216415.2,
+              "sources": {"sparse_bmm.hip": "1db89b3848ff78a56483dd559396584af5d058fbcff3b30daa4e28d3f5ab3cf8",
+                          "prim.hip": "aa91d31fd34175ce1892346820986f5724ded929dcb54c118cbca1f0000a6392",
+                          "stages.h": "af5828bcd4afad9ebfd854f63779ccd66f242169b2a52c51395aa1b755824fdb",
                           "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
     # the mapping stage of one batched pass (every kernel from k_gather_cols to k_out_j), 4096 instances
     "batched_map": {"kernels": "mapping and CSR builds of the batched pass", "fetch_kib": 42410883.1,
@@ -70,9 +70,9 @@ MEASURED_TRAFFIC = {
                                 "prim.hip": "aa91d31fd34175ce1892346820986f5724ded929dcb54c118cbca1f0000a6392",
                                 "plan.cpp": "367e463c5029c0b61b2bc7a31e8e0c147a5a72e1b1cea3cde499f9f12167dab9",
                                 "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
-    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 127735.5, "write_kib": 25185.5,
+    "dense": {"kernels": "k_dense_mfma", "fetch_kib": 127546.7, "write_kib": 25186.2,
               "sources": {"dense_mfma.hip": "e01d5a7827ea364242f9cdbc823f069d02d4dc8d34fb036d2fc3687d726d1998",
-                          "stages.h": "9f1d17ce26dd03bb4ead68b177f5469ad14d4b3a281ad23ece576481e3261635",
+                          "stages.h": "af5828bcd4afad9ebfd854f63779ccd66f242169b2a52c51395aa1b755824fdb",
                           "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
 }
 
