@@ -304,3 +304,33 @@ def test_batch_mapping_paths(direct):
             if ox.size:
                 bx, bz = b.materialize(i)
                 assert np.array_equal(bx.cpu().numpy(), ox) and np.array_equal(bz.cpu().numpy(), oz)
+
+
+@pytest.mark.parametrize("direct", [False, True])
+def test_batch_without_z_sort_pass(direct):
+    """Batches whose z keys need no sort pass (every instance holds one S.z
+    value; a batch with a single S tuple), so the key pass makes the keys from
+    the instances' columns; both mapping paths, every instance equal to the oracle."""
+    import paper_2206_04995_amd as P
+
+    batches = [
+        [synth.small_random(900 + i, 300 + 50 * i, 200 + 40 * i, dom_x=30, dom_y=15, dom_z=1, offset=17 * i)
+         for i in range(5)],
+        [synth.Instance(np.array([1, 2, 2], np.int32), np.array([3, 3, 4], np.int32), np.array([7], np.int32),
+                        np.array([3], np.int32), "one-s"),
+         synth.Instance(np.array([5], np.int32), np.array([3], np.int32), np.zeros(0, np.int32),
+                        np.zeros(0, np.int32), "empty-s")],
+    ]
+    opt = P.make_options(flags=P.JP_FLAG_DIRECT_IDS if direct else 0)
+    for k, insts in enumerate(batches):
+        cols = [tuple(dev(c) for c in (a.rx, a.ry, a.sz, a.sy)) for a in insts]
+        print(f"[case] batch without z sort pass {k} direct={direct}", flush=True)
+        with P.Batch(cols, opt=opt) as b:
+            b.execute()
+            counts = b.counts()
+            for i, inst in enumerate(insts):
+                ox, oz = oracle.join_project(inst.rx, inst.ry, inst.sz, inst.sy)
+                assert counts[i] == ox.size
+                if ox.size:
+                    bx, bz = b.materialize(i)
+                    assert np.array_equal(bx.cpu().numpy(), ox) and np.array_equal(bz.cpu().numpy(), oz)
