@@ -540,12 +540,15 @@ __global__ void k_cold_win_entries(const int32_t* __restrict__ cptr, const int32
 __global__ void k_cold_win_tail(const int32_t* __restrict__ cptr, const int32_t* __restrict__ ccol, int64_t n_y,
                                 const int32_t* __restrict__ y_base, const int32_t* __restrict__ zd_base, int n_inst,
                                 const int64_t* __restrict__ cw_off, int32_t* __restrict__ cw) {
+  // one row per thread; the instance cursor is seeded once per wave
   SegCursor<int32_t> ycur(y_base, n_inst);
-  ycur.seed(int32_t(chunk_first()));
-  CHUNK_LOOP(y, n_y, JP_CHUNK) {
+  const int64_t y = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t y0 = y - lane_id();  // the wave's first row
+  ycur.seed(int32_t(y0 < n_y ? y0 : 0));
+  if (y < n_y) {
     const int inst = ycur(int32_t(y));
     const int zd = zd_base[inst + 1] - zd_base[inst];
-    if (zd <= 0) continue;
+    if (zd <= 0) return;
     const int nwin = (zd + DW_BITS - 1) / DW_BITS;
     const int ny = y_base[inst + 1] - y_base[inst];
     const int yl = int(y) - y_base[inst];
@@ -561,12 +564,16 @@ __global__ void k_cold_win_counts(const int32_t* __restrict__ cw, const int64_t*
                                   const int64_t* __restrict__ cwm_off, const int32_t* __restrict__ y_base,
                                   const int32_t* __restrict__ zd_base, int n_inst, int64_t n_y,
                                   int32_t* __restrict__ cnt) {
+  // one row per thread (a row walks all windows of its instance); the
+  // instance cursor is seeded once per wave instead of a search per row
   SegCursor<int32_t> ycur(y_base, n_inst);
-  ycur.seed(int32_t(chunk_first()));
-  CHUNK_LOOP(y, n_y, JP_CHUNK) {
+  const int64_t y = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t y0 = y - lane_id();  // the wave's first row
+  ycur.seed(int32_t(y0 < n_y ? y0 : 0));
+  if (y < n_y) {
     const int inst = ycur(int32_t(y));
     const int zd = zd_base[inst + 1] - zd_base[inst];
-    if (zd <= 0) continue;
+    if (zd <= 0) return;
     const int nwin = (zd + DW_BITS - 1) / DW_BITS;
     const int ny = y_base[inst + 1] - y_base[inst];
     const int yl = int(y) - y_base[inst];
@@ -622,8 +629,8 @@ void cold_window_major(const int32_t* ccol, const int32_t* crow, int64_t n_y, in
                        Arena& a) {
   int32_t* cnt = a.alloc<int32_t>(std::max<int64_t>(cwm_total, 1), s);
   if (n_y > 0)
-    hipLaunchKernelGGL(k_cold_win_counts, dim3(chunk_grid(n_y)), dim3(NT), 0, s, cw, cw_off, cwm_off, y_base, zd_base,
-                       n_inst, n_y, cnt);
+    hipLaunchKernelGGL(k_cold_win_counts, dim3(chunk_grid(n_y, NT)), dim3(NT), 0, s, cw, cw_off, cwm_off, y_base,
+                       zd_base, n_inst, n_y, cnt);
   JP_LAUNCH_CHECK();
   scan_excl_i32(cnt, wptr, cwm_total, s, a);
   if (n_cold > 0)
@@ -807,8 +814,8 @@ void cold_windows(const int32_t* cptr, const int32_t* ccol, const int32_t* crow,
                        n_inst, cw_off, cw);
     JP_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_cold_win_tail, dim3(chunk_grid(n_y)), dim3(NT), 0, s, cptr, ccol, n_y, y_base, zd_base, n_inst,
-                     cw_off, cw);
+  hipLaunchKernelGGL(k_cold_win_tail, dim3(chunk_grid(n_y, NT)), dim3(NT), 0, s, cptr, ccol, n_y, y_base, zd_base,
+                     n_inst, cw_off, cw);
   JP_LAUNCH_CHECK();
 }
 
