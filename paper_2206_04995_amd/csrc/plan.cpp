@@ -903,7 +903,7 @@ void Plan::execute(hipStream_t s) {
     if (!cap_stream) JP_HIP(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
     JP_HIP(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
     try {
-      run_count_pass(cap_stream, false);
+      run_count_pass(cap_stream, false, false);
     } catch (...) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(cap_stream, &g);
@@ -914,7 +914,7 @@ void Plan::execute(hipStream_t s) {
     JP_HIP(hipGraphInstantiate(&graph_exec, graph_, nullptr, nullptr, 0));
     JP_HIP(hipGraphLaunch(graph_exec, s));
   } else {
-    run_count_pass(s, timing);
+    run_count_pass(s, timing, allow_aux && !timing && !graph);
   }
   warm = true;
   executed = true;
@@ -922,24 +922,48 @@ void Plan::execute(hipStream_t s) {
   h_tot.clear();
 }
 
-void Plan::run_count_pass(hipStream_t s, bool timing) {
+void Plan::run_count_pass(hipStream_t s, bool timing, bool aux_ok) {
   XA.rewind();
   RowCtx c = ctx();
   if (timing) JP_HIP(hipEventRecord(ev[0], s));
+  // The sparse and dense parts read the plan's tables and write disjoint
+  // outputs; with work in both, the dense part runs on the auxiliary stream
+  // (it allocates nothing from the pass's arena) so the two overlap.
+  static const bool one_stream = env_double("JP_COUNT_ONE_STREAM", 0.0) != 0.0;  // for comparisons
+  const bool split = aux_ok && !one_stream && NSp > 0 && NZd > 0;
+  hipStream_t sd = s;
+  if (split) {
+    if (!aux_stream) {
+      JP_HIP(hipStreamCreateWithFlags(&aux_stream, hipStreamNonBlocking));
+      JP_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+      JP_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    }
+    JP_HIP(hipEventRecord(ev_fork, s));
+    JP_HIP(hipStreamWaitEvent(aux_stream, ev_fork, 0));
+    sd = aux_stream;
+  }
+  auto dense_part = [&](hipStream_t st) {
+    if (NZd > 0 && use_mfma) {
+      dense_mfma_count(pA, pBt, k_pad, NX, nx_pad, NZd, nz_pad, cnt_de, d_mfma_steps, mfma_tile, st);
+    } else if (NZd > 0 && n_piv > 0) {
+      fill_i32(cnt_de, NX, 0, st);
+      dense_ec_rows(c, rows_n, NRowsN, nullptr, cnt_de, st);
+      dense_ec_rows(ctx(1), rows_p, NRowsP, d_pivcnt, cnt_de, st);
+    } else if (NZd > 0) {
+      dense_ec(c, 0, NX, cnt_de, nullptr, nullptr, 0, st);
+    } else {
+      fill_i32(cnt_de, NX, 0, st);
+    }
+  };
+  if (split) dense_part(sd);
   sparse_row_work(c, 0, NX, 0, NRp, w, seg0, seglen, s, XA);
   if (NSp > 0) sparse_bmm(c, 0, NX, w, cnt_sp, nullptr, nullptr, heavy_list, s);
   else fill_i32(cnt_sp, NX, 0, s);
   if (timing) JP_HIP(hipEventRecord(ev[1], s));
-  if (NZd > 0 && use_mfma) {
-    dense_mfma_count(pA, pBt, k_pad, NX, nx_pad, NZd, nz_pad, cnt_de, d_mfma_steps, mfma_tile, s);
-  } else if (NZd > 0 && n_piv > 0) {
-    fill_i32(cnt_de, NX, 0, s);
-    dense_ec_rows(c, rows_n, NRowsN, nullptr, cnt_de, s);
-    dense_ec_rows(ctx(1), rows_p, NRowsP, d_pivcnt, cnt_de, s);
-  } else if (NZd > 0) {
-    dense_ec(c, 0, NX, cnt_de, nullptr, nullptr, 0, s);
-  } else {
-    fill_i32(cnt_de, NX, 0, s);
+  if (!split) dense_part(s);
+  if (split) {
+    JP_HIP(hipEventRecord(ev_join, sd));
+    JP_HIP(hipStreamWaitEvent(s, ev_join, 0));
   }
   if (timing) JP_HIP(hipEventRecord(ev[2], s));
   // per-instance totals now; the row offsets only when a list or the offsets are asked for (ensure_offsets)
@@ -1169,6 +1193,7 @@ jp_status jp_count_static(const int32_t* r_x, const int32_t* r_y, int64_t n_r, c
     region.size = STATIC_SCRATCH_BYTES;
     RegionScope scope(&region);  // every arena below carves from the scratch
     Plan p;
+    p.allow_aux = false;  // no stream or event creation on this path
     jp_instance in{r_x, r_y, s_z, s_y, n_r, n_s};
     try {
       p.build(&in, 1, opt, stream);

@@ -125,13 +125,22 @@ struct Plan {
   hipGraph_t graph_ = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;
-  void run_count_pass(hipStream_t s, bool timing);
+  // the dense part of a count pass runs on aux_stream beside the sparse part
+  // (they share no data), forked from and joined back to the caller's stream
+  // by events; off for captured, timed and static passes
+  bool allow_aux = true;
+  hipStream_t aux_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  void run_count_pass(hipStream_t s, bool timing, bool aux_ok);
   void ensure_offsets(hipStream_t s);  // row offsets of the last count pass, computed on first use
 
   ~Plan() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph_) (void)hipGraphDestroy(graph_);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (aux_stream) (void)hipStreamDestroy(aux_stream);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     for (auto& e : evp)
