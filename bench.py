@@ -64,11 +64,11 @@ MEASURED_TRAFFIC = {
                           "stages.h": "af5828bcd4afad9ebfd854f63779ccd66f242169b2a52c51395aa1b755824fdb",
                           "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
     # the mapping stage of one batched pass (every kernel from k_gather_cols to k_out_j), 4096 instances
-    "batched_map": {"kernels": "mapping and CSR builds of the batched pass", "fetch_kib": 42410883.1,
-                    "write_kib": 55208109.9,
+    "batched_map": {"kernels": "mapping and CSR builds of the batched pass", "fetch_kib": 42407149.9,
+                    "write_kib": 55199994.8,
                     "sources": {"mapping.hip": "e66bb2eee4467ccb033e8c0a47ddb3316a178a2a3a2f9ba9b2e656ea021d054b",
                                 "prim.hip": "aa91d31fd34175ce1892346820986f5724ded929dcb54c118cbca1f0000a6392",
-                                "plan.cpp": "367e463c5029c0b61b2bc7a31e8e0c147a5a72e1b1cea3cde499f9f12167dab9",
+                                "plan.cpp": "2d6047ec0b817632bfbaa19a43b79d69703ec9c7ca07254f9d4bcc1189fbd93f",
                                 "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
     "dense": {"kernels": "k_dense_mfma", "fetch_kib": 127546.7, "write_kib": 25186.2,
               "sources": {"dense_mfma.hip": "e01d5a7827ea364242f9cdbc823f069d02d4dc8d34fb036d2fc3687d726d1998",
