@@ -125,7 +125,7 @@ __global__ void k_hot_row_info(const int32_t* __restrict__ hotlist, int64_t n_ho
   }
 }
 
-constexpr int HU = 4;  // entries per lane and step
+constexpr int HU = 8;  // entries per lane and step
 
 __global__ void k_build_hot_bits(const int32_t* __restrict__ hoff, int n_hot, const int32_t* __restrict__ pdel,
                                  const int64_t* __restrict__ rbase, const int32_t* __restrict__ scol,
@@ -485,17 +485,18 @@ __global__ void k_key_codes(const int32_t* __restrict__ hotrow, const int32_t* _
 
 __global__ void k_row_codes(const int32_t* __restrict__ rcol, int64_t n, const int32_t* __restrict__ ycode,
                             int32_t* __restrict__ rcode) {
-  // four entries per thread and step: their column loads, then their code gathers, then the stores
+  // eight entries per thread and step: their column loads, then their code gathers, then the stores
+  constexpr int U = 8;
   const int64_t c1 = chunk_first() + JP_CHUNK < n ? chunk_first() + JP_CHUNK : n;
   const int64_t step = blockDim.x;
-  for (int64_t j0 = chunk_first() + threadIdx.x; j0 < c1; j0 += 4 * step) {
-    int32_t y[4], v[4];
+  for (int64_t j0 = chunk_first() + threadIdx.x; j0 < c1; j0 += U * step) {
+    int32_t y[U], v[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) y[u] = rcol[j0 + u * step < c1 ? j0 + u * step : c1 - 1];
+    for (int u = 0; u < U; ++u) y[u] = rcol[j0 + u * step < c1 ? j0 + u * step : c1 - 1];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = ycode[y[u]];
+    for (int u = 0; u < U; ++u) v[u] = ycode[y[u]];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < U; ++u)
       if (j0 + u * step < c1) rcode[j0 + u * step] = v[u];
   }
 }

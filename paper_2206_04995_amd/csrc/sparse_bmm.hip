@@ -38,22 +38,23 @@ __device__ __forceinline__ void lds_fence() {
 // per R CSR entry j: the sparse S row of its join key, as (start, length)
 __global__ void k_entry_seg(const int32_t* __restrict__ rcol, const int32_t* __restrict__ spptr, int64_t j_lo,
                             int64_t j_hi, int32_t* __restrict__ seg0, int32_t* __restrict__ len) {
-  // a block per chunk of JP_CHUNK entries, four entries per thread and step:
+  // a block per chunk of JP_CHUNK entries, eight entries per thread and step:
   // their column loads, then their row-pointer gathers, then the stores
+  constexpr int U = 8;
   const int64_t c0 = j_lo + int64_t(blockIdx.x) * JP_CHUNK;
   const int64_t c1 = c0 + JP_CHUNK < j_hi ? c0 + JP_CHUNK : j_hi;
   const int64_t step = blockDim.x;
-  for (int64_t j0 = c0 + threadIdx.x; j0 < c1; j0 += 4 * step) {
-    int32_t y[4], a[4], b[4];
+  for (int64_t j0 = c0 + threadIdx.x; j0 < c1; j0 += U * step) {
+    int32_t y[U], a[U], b[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) y[u] = rcol[j0 + u * step < c1 ? j0 + u * step : c1 - 1];
+    for (int u = 0; u < U; ++u) y[u] = rcol[j0 + u * step < c1 ? j0 + u * step : c1 - 1];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       a[u] = spptr[y[u]];
       b[u] = spptr[y[u] + 1];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int64_t j = j0 + u * step;
       if (j < c1) {
         seg0[j] = a[u];
