@@ -58,8 +58,8 @@ MEASURED_TRAFFIC = {
     # the whole timed SparseBMM count region: per-entry segments, row work, row
     # lists, the light/medium/heavy count kernels
     "graph": {"kernels": "SparseBMM count pass (k_entry_seg ... k_sparse_heavy_count)",
-              "fetch_kib": 2652154.2, "write_kib": 216415.2,
-              "sources": {"sparse_bmm.hip": "1db89b3848ff78a56483dd559396584af5d058fbcff3b30daa4e28d3f5ab3cf8",
+              "fetch_kib": 2649981.2, "write_kib": 216505.0,
+              "sources": {"sparse_bmm.hip": "addfe73224abb63593a34713c3e93f4be48b03619e0aff71fc668e8756aec8a8",
                           "prim.hip": "aa91d31fd34175ce1892346820986f5724ded929dcb54c118cbca1f0000a6392",
                           "stages.h": "af5828bcd4afad9ebfd854f63779ccd66f242169b2a52c51395aa1b755824fdb",
                           "common.h": "413b5e9d8f8940a4323be50fae6774429ed9e3bd0848ceec14892d2cfec2c7a5"}},
